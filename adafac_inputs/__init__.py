@@ -1,0 +1,56 @@
+"""Seeded synthetic inputs shared by the oracle tests, the GPU tests and the benchmark.
+
+This module only draws random numbers and lays them out; it holds none of
+the method's arithmetic.  Every array is produced with numpy's PCG64
+generator (``numpy.random.default_rng(seed)``) in C order with x on the last
+axis, on the vertex lattice of the finest level ((3^L + 1)^d entries; the
+boundary entries are drawn too and ignored) or on a block grid of the
+coefficient ((3^k)^d entries).
+
+The workloads mirror the paper's setting: -div(eps grad u) = f on the unit
+square/cube, zero Dirichlet boundary, uniform spacetree levels, eps piecewise
+constant on aligned blocks with log10(eps) uniform.
+"""
+import numpy as np
+
+
+def rhs(d, L, seed=0, dist="uniform"):
+    """Vertex samples of f: U(-1, 1) or N(0, 1) on the (3^L+1)^d lattice."""
+    rng = np.random.default_rng(seed)
+    shape = (3 ** L + 1,) * d
+    if dist == "uniform":
+        return rng.uniform(-1.0, 1.0, shape)
+    if dist == "normal":
+        return rng.standard_normal(shape)
+    raise ValueError(dist)
+
+
+def eps_blocks(d, k, log10_max, seed=0):
+    """Coefficient blocks 10**U(0, log10_max) on the (3^k)^d cells of level k."""
+    rng = np.random.default_rng(seed)
+    return 10.0 ** rng.uniform(0.0, log10_max, (3 ** k,) * d)
+
+
+def poisson_blocks(d):
+    """eps = 1 everywhere: a single block."""
+    return np.ones((1,) * d)
+
+
+# Named workloads ------------------------------------------------------------
+
+def workload_2d_poisson_l4(seed=0):
+    """2D Poisson, 81 x 81 finest cells (L = 4), f ~ U(-1, 1), 20 cycles."""
+    return dict(d=2, L=4, lmin=1, eps=poisson_blocks(2), f=rhs(2, 4, seed, "uniform"), cycles=20)
+
+
+def workload_3d_poisson_l5(seed=0):
+    """3D Poisson, 243^3 finest cells (L = 5), f ~ N(0, 1)."""
+    return dict(d=3, L=5, lmin=1, eps=poisson_blocks(3), f=rhs(3, 5, seed, "normal"))
+
+
+def workload_jump(d, L, seed=0):
+    """Jump-coefficient solve of the request stream: 9x9 blocks log10 U(0,3) in 2D,
+    27^3 blocks log10 U(0,4) in 3D, f ~ U(-1, 1)."""
+    k, p = (2, 3.0) if d == 2 else (3, 4.0)
+    k = min(k, L)
+    return dict(d=d, L=L, lmin=1, eps=eps_blocks(d, k, p, seed), f=rhs(d, L, seed + 1, "uniform"))
