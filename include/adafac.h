@@ -1,0 +1,185 @@
+/*
+ * adafac.h -- C ABI of the MI355X (gfx950) additively damped asynchronous FAC solver.
+ *
+ * The library solves  -div(eps grad u) = f  on the unit square (d = 2) or cube
+ * (d = 3) with u = 0 on the boundary (problem statement, Sec. 1 of Murray &
+ * Weinzierl, "Stabilised asynchronous fast adaptive composite multigrid using
+ * additive damping", arXiv:1903.10367), discretised with d-linear finite
+ * elements on the levels of a 3:1 spacetree (Sec. 2.1), and iterates the
+ * additive adAFAC cycle of eq. (adaFACx) / Algorithm 1 (Sec. 3.1): every level
+ * takes one damped Jacobi step, the coarse levels see the FAS right-hand side
+ * of eq. (fas-with-htmg) (Sec. 2.3), and every level below the finest solves
+ * the auxiliary damping equation with the smoothed restriction R~ (Sec. 3.2).
+ *
+ * Conventions shared by every entry point
+ *  - Return value: ADAFAC_OK (0) or one of the ADAFAC_E* codes below.  No C++
+ *    exception crosses the ABI.  adafac_last_error() gives a message for the
+ *    last failing call on a context.
+ *  - Host arrays are read (or written) during the call only; the caller keeps
+ *    ownership and may free them afterwards.
+ *  - Device memory: the caller allocates ONE workspace of at least
+ *    adafac_workspace_bytes() bytes on the GPU (any allocator, 256-byte
+ *    aligned), passes it to adafac_bind() and keeps it alive until
+ *    adafac_destroy() or the next adafac_bind().  The library sub-allocates
+ *    all level arrays inside it and never calls hipMalloc while cycling.
+ *  - All GPU work is enqueued on the hipStream_t given to adafac_bind().
+ *    adafac_cycle() returns without synchronising; adafac_residual(),
+ *    adafac_solve(), adafac_get_solution() and adafac_get_level() synchronise
+ *    that stream.
+ *  - Lattice arrays are C order with x fastest: entry (x, y[, z]) of a level
+ *    with n = 3^l cells per axis sits at x + (n+1)*(y + (n+1)*z).
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef ADAFAC_H
+#define ADAFAC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define ADAFAC_OK 0
+#define ADAFAC_EINVAL 1      /* bad argument: dims, levels, sizes, eps <= 0, non-finite data */
+#define ADAFAC_ESTATE 2      /* entry point called out of order */
+#define ADAFAC_ENOMEM 3      /* workspace too small */
+#define ADAFAC_EDEVICE 4     /* a HIP runtime call failed (message kept) */
+#define ADAFAC_EDIVERGED 5   /* residual became NaN/Inf or grew beyond 1e3 x its initial value */
+#define ADAFAC_EUNSUPPORTED 7/* option combination not implemented */
+
+/* inter-grid transfers (Sec. 2.4; the switch of Sec. 3.2) */
+#define ADAFAC_TRANSFER_DLINEAR 0
+#define ADAFAC_TRANSFER_BOXMG 1
+/* damping of the additive corrections (Sec. 3.2, Sec. 6.1) */
+#define ADAFAC_DAMP_JAC 0    /* adAFAC-Jac: auxiliary equation with R~ one level coarser */
+#define ADAFAC_DAMP_PI 1     /* adAFAC-PI: c~_l = P I c_l */
+#define ADAFAC_DAMP_NONE 2   /* plain additive multigrid, eq. (additive-mg) */
+#define ADAFAC_DAMP_EXP 3    /* exponential damping omega_hat^(L-l) */
+/* the smoothed restriction R~ = omega R A M^-1 truncated to P's support (Sec. 3.2) */
+#define ADAFAC_RTILDE_CONST_EPS1 0 /* from the eps = 1 operator, the same on every level */
+/* arithmetic of the cycle (spec precision form) */
+#define ADAFAC_PREC_FP64 0
+#define ADAFAC_PREC_FP32_REFINED 1 /* FP32 cycles inside FP64 defect correction */
+
+typedef struct adafac_ctx adafac_ctx;
+
+typedef struct {
+  int transfer;        /* ADAFAC_TRANSFER_* */
+  int damping;         /* ADAFAC_DAMP_* */
+  int rtilde;          /* ADAFAC_RTILDE_* */
+  int precision;       /* ADAFAC_PREC_* */
+  int inner_k;         /* FP32_REFINED: cycles per outer FP64 step (>= 1) */
+  int fused;           /* 1: single-pass fine sweep with deferred prolongation (default),
+                          0: one kernel per step (same iterates; used as a cross-check) */
+  double omega;        /* Jacobi damping, 0.6 in Sec. 6 */
+  double omega_tilde;  /* auxiliary Jacobi damping (the paper gives no value; default omega) */
+  double omega_hat;    /* ADAFAC_DAMP_EXP base */
+} adafac_opts;
+
+/* Fill *o with the defaults: DLINEAR, JAC, CONST_EPS1, FP64, inner_k 4, fused,
+ * omega = omega_tilde = 0.6, omega_hat = 0.5. */
+void adafac_default_opts(adafac_opts* o);
+
+/* Create a context for a d-dimensional (dim = 2 or 3) uniform spacetree whose
+ * levels l_min..l_max carry degrees of freedom (Sec. 2.1: levels counted from
+ * the root cell, l_max the finest, 1 <= l_min <= l_max; l_max <= 9 for d = 2,
+ * l_max <= 6 for d = 3).  Level l has 3^l cells per axis.  *out receives a new
+ * context owned by the caller (free with adafac_destroy).  EINVAL on bad
+ * arguments. */
+int adafac_create(adafac_ctx** out, int dim, int l_min, int l_max);
+
+/* Coefficient eps of the PDE (Sec. 1), piecewise constant on the cells of
+ * spacetree level k: blocks_per_axis = 3^k (1 <= 3^k <= 3^l_max), eps holds
+ * blocks_per_axis^dim finite values > 0, C order with x fastest.  Default when
+ * never called: eps = 1 (Poisson).  EINVAL on bad sizes or values. */
+int adafac_set_coefficient_blocks(adafac_ctx* ctx, int blocks_per_axis, const double* eps);
+
+/* Right-hand side f sampled at the vertices of the finest level: n must equal
+ * (3^l_max + 1)^dim; boundary entries are ignored.  The load vector is
+ * b_v = m_v f_v with the lumped mass m_v (h^d on a uniform level).  EINVAL on
+ * a wrong n or non-finite values. */
+int adafac_set_rhs_lattice(adafac_ctx* ctx, const double* f, size_t n);
+
+/* Build operators and transfers on the host in FP64 (Sec. 2.2, 2.4, 3.2,
+ * 5.1): Q1 element operators from eps, BoxMG or d-linear P and R = P^T,
+ * Ritz-Galerkin coarse operators, Jacobi diagonals, R~.  opts may be NULL
+ * (defaults).  Invalidates a previous bind.  EINVAL / EUNSUPPORTED on bad
+ * options. */
+int adafac_build_operators(adafac_ctx* ctx, const adafac_opts* opts);
+
+/* Bytes of device workspace the bound context needs (after build_operators). */
+int adafac_workspace_bytes(const adafac_ctx* ctx, size_t* bytes);
+
+/* Bind device workspace and stream; uploads operators and the right-hand side
+ * and sets u = 0 (iterate 0).  dev_workspace: device pointer, bytes >= the
+ * value of adafac_workspace_bytes (else ENOMEM).  hip_stream: a hipStream_t
+ * (NULL = the null stream).  EDEVICE if a copy fails. */
+int adafac_bind(adafac_ctx* ctx, void* dev_workspace, size_t bytes, void* hip_stream);
+
+/* Enqueue ncycles adAFAC cycles (FP64 form; for FP32_REFINED one call runs
+ * ncycles outer steps of inner_k FP32 cycles each).  Cycle n computes the
+ * residual norms of iterate n and produces iterate n+1.  Non-blocking. */
+int adafac_cycle(adafac_ctx* ctx, int ncycles);
+
+/* Iterate until ||r^(n)||_h / ||r^(0)||_h <= rel_tol for the input iterate n
+ * of the last cycle run, or max_cycles cycles (outer steps for FP32_REFINED)
+ * have run.  *cycles_done (may be NULL) receives the number run; the solution
+ * afterwards is iterate cycles_done (for FP32_REFINED: the last outer iterate,
+ * whose FP64 residual met the tolerance).  Synchronises.  EDIVERGED on NaN/Inf
+ * or growth beyond 1e3 x the initial norm. */
+int adafac_solve(adafac_ctx* ctx, double rel_tol, int max_cycles, int* cycles_done);
+
+/* Residual norms of iterate `cycle` (0-based, < cycles run since bind):
+ * l2h = sqrt(sum_i h^d r_i^2) and linf = max_i |r_i| over the finest-level
+ * dofs (Sec. 6, eq. (normalised-residual), before normalisation).  For
+ * FP32_REFINED, `cycle` counts outer steps.  Synchronises.  EINVAL if the
+ * cycle has not run. */
+int adafac_residual(adafac_ctx* ctx, int cycle, double* l2h, double* linf);
+
+/* Number of residual norms recorded so far. */
+int adafac_cycles_run(const adafac_ctx* ctx);
+
+/* Copy the current finest-level iterate (full lattice, n = (3^l_max+1)^dim,
+ * boundary zero) to host memory u.  Synchronises.  EINVAL on a wrong n. */
+int adafac_get_solution(adafac_ctx* ctx, double* u, size_t n);
+
+/* Replace the current iterate (warm start / resume); boundary entries are
+ * ignored.  Residual history is cleared.  Synchronises. */
+int adafac_set_solution(adafac_ctx* ctx, const double* u, size_t n);
+
+/* Copy a level array of the last cycle to host memory (inspection and
+ * per-step parity checks).  which: 0 = u_l (FAS solution, injected),
+ * 1 = b_l (FAS right-hand side), 2 = b~_l (auxiliary right-hand side),
+ * 3 = r_l (level residual), 4 = S_l (accumulated correction P^{..}(c - c~)).
+ * Levels l_min..l_max-1; n = (3^l+1)^dim.  FP64 form only.  Synchronises. */
+int adafac_get_level(adafac_ctx* ctx, int level, int which, double* out, size_t n);
+
+/* Copy a host-side FP64 operator built by adafac_build_operators (no GPU needed):
+ * which 0 = the level's 3^dim stencil per vertex (slot index (ox+1) + 3 (oy+1) + 9 (oz+1),
+ * n = 3^dim (3^l+1)^dim; Q1 rows from eps for levels whose cells lie inside one eps block,
+ * Ritz-Galerkin rows below that, Sec. 2.2), 1 = its diagonal (n = (3^l+1)^dim),
+ * 2 = prolongation weights from level l-1 into level l, 2^dim per fine vertex for the
+ * corners of the coarse cell floor(x/3) clamped to the last cell (Sec. 2.4; d-linear or
+ * BoxMG), n = 2^dim (3^l+1)^dim, l > l_min, 3 = the R~ weights times omega on the 5^dim
+ * offsets (Sec. 3.2), n = 5^dim, level ignored.  ESTATE before build_operators. */
+int adafac_host_operator(const adafac_ctx* ctx, int level, int which, double* out, size_t n);
+
+/* Sum over levels of the dofs (3^l - 1)^dim: the vertex updates of one cycle. */
+int64_t adafac_dofs_per_cycle(const adafac_ctx* ctx);
+
+/* Kernel timing of the dominant (finest-level) kernel: when enabled, every
+ * launch of it is bracketed by HIP events on the bound stream.  Returns the
+ * summed duration in ms and the number of launches since enabling.
+ * Synchronises. */
+int adafac_set_kernel_timing(adafac_ctx* ctx, int enable);
+int adafac_kernel_time(adafac_ctx* ctx, double* total_ms, int* launches);
+
+void adafac_destroy(adafac_ctx* ctx);
+const char* adafac_last_error(const adafac_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADAFAC_H */

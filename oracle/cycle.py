@@ -58,11 +58,15 @@ def _damping_terms(H, c, rhs_for_aux, damping, omega_t):
     return ct
 
 
-def _accumulate(H, c, ct):
+def _accumulate(H, c, ct, trace=None):
     """u increment sum_l P^{L-l}(c_l - c~_l), accumulated from the coarsest level upwards."""
     S = c[H.lmin] - ct[H.lmin]
+    if trace is not None:
+        trace.setdefault("S", {})[H.lmin] = S
     for l in range(H.lmin + 1, H.L + 1):
         S = c[l] - ct[l] + H.lev[l].P(S)
+        if trace is not None:
+            trace["S"][l] = S
     return S
 
 
@@ -86,13 +90,14 @@ def cycle_correction(H, u, b, omega=0.6, omega_t=0.6, damping="jac", omega_hat=0
     return u + _accumulate(H, c, ct), r
 
 
-def cycle_fas(H, u, b, omega=0.6, omega_t=0.6, damping="jac", omega_hat=0.5):
+def cycle_fas(H, u, b, omega=0.6, omega_t=0.6, damping="jac", omega_hat=0.5, trace=None):
     """One cycle in FAS/HTMG form (Sec. 2.3, Algorithm 3's use of r and r^).
 
     Level l < L: u_l = I u_{l+1}; b_l = R r^_{l+1} with the hierarchical
     residual r^_{l+1} = b_{l+1} - A_{l+1}(u_{l+1} - P I u_{l+1}); the residual
     r_l = b_l - A_l u_l drives the Jacobi correction, and the auxiliary
-    right-hand side is b~_l = R~ r_{l+1} (plain residual).
+    right-hand side is b~_l = R~ r_{l+1} (plain residual).  If ``trace`` is a dict it
+    receives the per-level arrays u, b, btilde, r and S (for inspection only).
     """
     _check(damping)
     L, lmin, lev = H.L, H.lmin, H.lev
@@ -109,7 +114,9 @@ def cycle_fas(H, u, b, omega=0.6, omega_t=0.6, damping="jac", omega_hat=0.5):
     if damping == "exp":
         c = {l: omega_hat ** (L - l) * c[l] for l in c}
     ct = _damping_terms(H, c, bt, damping, omega_t)
-    return u + _accumulate(H, c, ct), rl[L]
+    if trace is not None:
+        trace.update(u=ul, b=bF, btilde=bt, r=rl)
+    return u + _accumulate(H, c, ct, trace), rl[L]
 
 
 def solve(H, b, max_cycles, tol=None, form="correction", u0=None, **kw):

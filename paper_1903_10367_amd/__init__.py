@@ -1,0 +1,122 @@
+"""MI355X-native additively damped asynchronous FAC (adAFAC) solver.
+
+Python face of the C ABI in ``include/adafac.h``: the arguments are marshalled with
+ctypes, device memory for the workspace comes from a torch uint8 tensor and the
+stream from torch's current stream.  Every step of the cycle runs in the gfx950
+kernels of ``libadafac.so``; there is no CPU path.
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import _abi
+from ._abi import AdafacError, DAMPING, LEVEL_ARRAY, PRECISION, TRANSFER
+
+__all__ = ["Solver", "AdafacError", "lib"]
+
+lib = _abi.lib
+
+
+def _check(L, ctx, rc):
+    if rc != _abi.OK:
+        msg = L.adafac_last_error(ctx)
+        raise AdafacError(rc, msg.decode() if msg else "")
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Solver:
+    """One adAFAC solve on a uniform 3:1 spacetree of dimension ``dim`` with levels lmin..lmax.
+
+    ``eps_blocks``: coefficient on the (3^k)^dim cells of level k (None: Poisson);
+    ``f``: right-hand side samples on the (3^lmax + 1)^dim finest vertices.
+    """
+
+    def __init__(self, dim, lmin, lmax, f, eps_blocks=None, transfer="dlinear", damping="jac",
+                 precision="fp64", inner_k=4, fused=True, omega=0.6, omega_tilde=0.6, omega_hat=0.5,
+                 device=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("adafac needs a ROCm GPU (gfx950); none is visible")
+        self.L = _abi.lib()
+        self.dim, self.lmin, self.lmax = dim, lmin, lmax
+        ctx = C.c_void_p()
+        rc = self.L.adafac_create(C.byref(ctx), dim, lmin, lmax)
+        if rc:
+            raise AdafacError(rc, "adafac_create")
+        self.ctx = ctx
+        if eps_blocks is not None:
+            e = np.ascontiguousarray(eps_blocks, dtype=np.float64)
+            _check(self.L, ctx, self.L.adafac_set_coefficient_blocks(ctx, e.shape[0], _dptr(e)))
+        fa = np.ascontiguousarray(f, dtype=np.float64).ravel()
+        _check(self.L, ctx, self.L.adafac_set_rhs_lattice(ctx, _dptr(fa), fa.size))
+        o = _abi.Opts()
+        self.L.adafac_default_opts(C.byref(o))
+        o.transfer, o.damping, o.precision = TRANSFER[transfer], DAMPING[damping], PRECISION[precision]
+        o.inner_k, o.fused = inner_k, int(bool(fused))
+        o.omega, o.omega_tilde, o.omega_hat = omega, omega_tilde, omega_hat
+        _check(self.L, ctx, self.L.adafac_build_operators(ctx, C.byref(o)))
+        nbytes = C.c_size_t()
+        _check(self.L, ctx, self.L.adafac_workspace_bytes(ctx, C.byref(nbytes)))
+        self.device = torch.device(device or "cuda:0")
+        self.workspace = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        _check(self.L, ctx, self.L.adafac_bind(ctx, C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                                               C.c_void_p(self.stream.cuda_stream)))
+        self.nvert = (3 ** lmax + 1) ** dim
+
+    # --- cycle ----------------------------------------------------------------
+    def cycle(self, n=1):
+        _check(self.L, self.ctx, self.L.adafac_cycle(self.ctx, n))
+
+    def solve(self, rel_tol, max_cycles):
+        done = C.c_int()
+        rc = self.L.adafac_solve(self.ctx, rel_tol, max_cycles, C.byref(done))
+        _check(self.L, self.ctx, rc)
+        return done.value
+
+    def residual(self, i):
+        a, b = C.c_double(), C.c_double()
+        _check(self.L, self.ctx, self.L.adafac_residual(self.ctx, i, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def residuals(self):
+        return [self.residual(i) for i in range(self.L.adafac_cycles_run(self.ctx))]
+
+    def solution(self):
+        u = np.empty(self.nvert)
+        _check(self.L, self.ctx, self.L.adafac_get_solution(self.ctx, _dptr(u), u.size))
+        return u
+
+    def set_solution(self, u):
+        u = np.ascontiguousarray(u, dtype=np.float64).ravel()
+        _check(self.L, self.ctx, self.L.adafac_set_solution(self.ctx, _dptr(u), u.size))
+
+    def level(self, level, which):
+        out = np.empty((3 ** level + 1) ** self.dim)
+        _check(self.L, self.ctx, self.L.adafac_get_level(self.ctx, level, LEVEL_ARRAY[which], _dptr(out), out.size))
+        return out
+
+    def dofs_per_cycle(self):
+        return int(self.L.adafac_dofs_per_cycle(self.ctx))
+
+    def set_kernel_timing(self, on):
+        _check(self.L, self.ctx, self.L.adafac_set_kernel_timing(self.ctx, int(on)))
+
+    def kernel_time(self):
+        ms, n = C.c_double(), C.c_int()
+        _check(self.L, self.ctx, self.L.adafac_kernel_time(self.ctx, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.L.adafac_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

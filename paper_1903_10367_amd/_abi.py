@@ -1,0 +1,74 @@
+"""ctypes declarations of the C ABI in include/adafac.h (argument marshalling only)."""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libadafac.so")
+
+OK, EINVAL, ESTATE, ENOMEM, EDEVICE, EDIVERGED, EUNSUPPORTED = 0, 1, 2, 3, 4, 5, 7
+TRANSFER = {"dlinear": 0, "boxmg": 1}
+DAMPING = {"jac": 0, "pi": 1, "none": 2, "exp": 3}
+PRECISION = {"fp64": 0, "fp32_refined": 1}
+LEVEL_ARRAY = {"u": 0, "b": 1, "btilde": 2, "r": 3, "S": 4}
+
+# every symbol the header declares
+EXPORTS = [
+    "adafac_default_opts", "adafac_create", "adafac_set_coefficient_blocks", "adafac_set_rhs_lattice",
+    "adafac_build_operators", "adafac_workspace_bytes", "adafac_bind", "adafac_cycle", "adafac_solve",
+    "adafac_residual", "adafac_cycles_run", "adafac_get_solution", "adafac_set_solution",
+    "adafac_get_level", "adafac_host_operator", "adafac_dofs_per_cycle", "adafac_set_kernel_timing", "adafac_kernel_time",
+    "adafac_destroy", "adafac_last_error",
+]
+
+
+class Opts(C.Structure):
+    _fields_ = [("transfer", C.c_int), ("damping", C.c_int), ("rtilde", C.c_int), ("precision", C.c_int),
+                ("inner_k", C.c_int), ("fused", C.c_int), ("omega", C.c_double),
+                ("omega_tilde", C.c_double), ("omega_hat", C.c_double)]
+
+
+class AdafacError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"adafac error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libadafac.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} missing: run `python -m paper_1903_10367_amd.build` first")
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    sig = {
+        "adafac_default_opts": (None, [C.POINTER(Opts)]),
+        "adafac_create": (C.c_int, [C.POINTER(P), C.c_int, C.c_int, C.c_int]),
+        "adafac_set_coefficient_blocks": (C.c_int, [P, C.c_int, C.POINTER(C.c_double)]),
+        "adafac_set_rhs_lattice": (C.c_int, [P, C.POINTER(C.c_double), C.c_size_t]),
+        "adafac_build_operators": (C.c_int, [P, C.POINTER(Opts)]),
+        "adafac_workspace_bytes": (C.c_int, [P, C.POINTER(C.c_size_t)]),
+        "adafac_bind": (C.c_int, [P, P, C.c_size_t, P]),
+        "adafac_cycle": (C.c_int, [P, C.c_int]),
+        "adafac_solve": (C.c_int, [P, C.c_double, C.c_int, C.POINTER(C.c_int)]),
+        "adafac_residual": (C.c_int, [P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+        "adafac_cycles_run": (C.c_int, [P]),
+        "adafac_get_solution": (C.c_int, [P, C.POINTER(C.c_double), C.c_size_t]),
+        "adafac_set_solution": (C.c_int, [P, C.POINTER(C.c_double), C.c_size_t]),
+        "adafac_get_level": (C.c_int, [P, C.c_int, C.c_int, C.POINTER(C.c_double), C.c_size_t]),
+        "adafac_host_operator": (C.c_int, [P, C.c_int, C.c_int, C.POINTER(C.c_double), C.c_size_t]),
+        "adafac_dofs_per_cycle": (C.c_int64, [P]),
+        "adafac_set_kernel_timing": (C.c_int, [P, C.c_int]),
+        "adafac_kernel_time": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
+        "adafac_destroy": (None, [P]),
+        "adafac_last_error": (C.c_char_p, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype, f.argtypes = res, args
+    _lib = L
+    return L

@@ -1,0 +1,75 @@
+// Internal declarations shared by the host setup, the C ABI and the gfx950 kernels.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace adafac {
+
+constexpr int kMaxLevel = 9;    // 3^9 cells per axis in 2D, levels 0..9
+constexpr int kNormBlocks = 2048;
+
+inline int ipow3(int k) { int r = 1; while (k-- > 0) r *= 3; return r; }
+
+// ---------------------------------------------------------------------------
+// Host-side FP64 operators of one uniform level (full vertex lattice, x fastest)
+// ---------------------------------------------------------------------------
+struct HostLevel {
+  int level = 0, n = 0, nv = 0;    // cells per axis, vertices per axis
+  size_t nverts = 0;               // nv^d
+  double h = 0;
+  bool fem = true;                 // Q1 element operator from eps blocks (else stored stencil)
+  std::vector<double> st;          // stored operator: 3^d entries per vertex (offset index o_x+3 o_y+9 o_z)
+  std::vector<double> dg;          // diagonal of the operator (every level)
+  std::vector<double> pw;          // transfer from level-1 to this level: 2^d weights per vertex, or empty = d-linear
+};
+
+struct HostOps {
+  int dim = 2, lmin = 1, L = 1;
+  int nb = 1, k = 0;               // eps blocks per axis = 3^k
+  std::vector<double> eps;         // nb^d
+  std::vector<HostLevel> lev;      // indexed by level (0..L)
+  std::vector<double> rtilde;      // 5^d weights of R~ (already times omega), offset index as st
+};
+
+// Builds every operator of the hierarchy (FEM fine levels, BoxMG or d-linear
+// transfers, Galerkin coarse operators below the coefficient-block level, R~).
+// Returns an empty string on success, else a message.
+std::string build_host_ops(HostOps& ops, int transfer_boxmg, double omega);
+
+// Q1 stencil entry of a FEM level for vertex v and neighbour offset o (used by tests of the setup).
+double fem_stencil_entry(const HostOps& ops, int level, const int* v, const int* o);
+
+// ---------------------------------------------------------------------------
+// Device views
+// ---------------------------------------------------------------------------
+template <typename T>
+struct LevelView {
+  int n, nv;                 // cells / vertices per axis
+  T h;                       // mesh width
+  T hd;                      // h^d (norm weight)
+  T hdm2;                    // h^(d-2) (element scaling)
+  int fem;                   // 1: operator from eps blocks, 0: stored stencil
+  int nb;                    // eps blocks per axis
+  int bs;                    // cells per block along an axis (>= 1) when fem
+  const T* eps;              // nb^d block coefficients (nullptr: eps = 1)
+  const T* st;               // stored stencil (3^d per vertex) when !fem
+  const T* dg;               // stored diagonal when !fem
+  const T* pw;               // transfer weights into this level (2^d per vertex) or nullptr: d-linear
+  T* u;                      // FAS solution (coarse: injected); fine: unused here
+  T* rr;                     // restricted residual R r_{l+1}
+  T* bt;                     // auxiliary right-hand side R~ r_{l+1}
+  T* bf;                     // FAS right-hand side R r_{l+1} + A_l I u_{l+1}
+  T* r;                      // level residual
+  T* S;                      // accumulated correction
+  T* ic;                     // adAFAC-PI: injected correction of the next finer level
+};
+
+struct CycleParams {
+  double omega, omega_t, omega_hat;
+  int damping;               // ADAFAC_DAMP_*
+  int L, lmin;
+};
+
+}  // namespace adafac

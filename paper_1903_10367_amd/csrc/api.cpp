@@ -1,0 +1,606 @@
+// C ABI of the adAFAC solver (include/adafac.h): context, host setup, workspace layout and
+// the sequencing of the gfx950 kernels of one cycle on the bound stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "adafac.h"
+#include "adafac_internal.hpp"
+
+namespace adafac {
+
+template <typename T>
+hipError_t launch_fine_residual(int d, const LevelView<T>& F, const T* uin, T* uout, const T* b, T* r,
+                                T* ic_coarse, int nvc, T omega, int pi, double* partials, int nblocks,
+                                hipStream_t s);
+template <typename T>
+hipError_t launch_level_update(int d, const LevelView<T>& C, const LevelView<T>& F, const LevelView<T>& Cm,
+                               const T* rt, T omega, T omega_t, T cscale, int damping, int gather,
+                               hipStream_t s);
+template <typename T>
+hipError_t launch_prolong_add(int d, const LevelView<T>& F, const LevelView<T>& C, T* dst, const T* src,
+                              const T* sub, hipStream_t s);
+hipError_t launch_norm_finalize(const double* partials, int n, double* out, hipStream_t s);
+template <typename T>
+hipError_t launch_fine_sweep(int d, const LevelView<T>& F, const LevelView<T>& C, const T* uin, T* uout,
+                             const T* b, const T* rt, T omega, int damping, int apply_pending,
+                             double* partials, int* nparts, hipStream_t s);
+size_t fine_sweep_partials(int d, int n);
+
+}  // namespace adafac
+
+using namespace adafac;
+
+namespace {
+constexpr int kMaxHist = 1 << 14;
+constexpr int kTimingPool = 256;
+}
+
+struct adafac_ctx {
+  int dim = 2, lmin = 1, L = 1;
+  int nb = 1;
+  std::vector<double> eps{1.0};
+  std::vector<double> f;
+  adafac_opts opts{};
+  HostOps ops;
+  bool built = false, bound = false;
+  std::string err;
+  // device
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t ws_need = 0;       // workspace size of the built hierarchy
+  hipStream_t stream = nullptr;
+  LevelView<double> v64[kMaxLevel + 1]{};
+  double* ufine[2] = {nullptr, nullptr};
+  double* bfine = nullptr;
+  double* rfine = nullptr;
+  double* partials = nullptr;
+  size_t npartials = 0;
+  double* norms = nullptr;
+  double* rt = nullptr;
+  double* eps_dev = nullptr;
+  int cur = 0;
+  bool pending = false;     // fused path: P S_{L-1} of the last cycle not yet added to u
+  int ncyc = 0;
+  // kernel timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  int ev_used = 0;
+  double t_acc = 0.0;
+  int t_launches = 0;
+};
+
+namespace {
+
+int fail(adafac_ctx* c, int code, const std::string& m) {
+  if (c) c->err = m;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(ctx, ADAFAC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t nverts_of(int d, int l) {
+  size_t nv = size_t(ipow3(l) + 1);
+  return d == 2 ? nv * nv : nv * nv * nv;
+}
+
+// Lay out every device array inside the workspace; with base == nullptr only sizes.
+size_t layout(adafac_ctx* c, char* base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    off = (off + 255) & ~size_t(255);
+    char* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  };
+  const int d = c->dim;
+  const int ns = d == 2 ? 9 : 27;
+  c->eps_dev = reinterpret_cast<double*>(take(sizeof(double) * c->ops.eps.size()));
+  c->rt = reinterpret_cast<double*>(take(sizeof(double) * 125));
+  for (int l = c->lmin; l <= c->L; ++l) {
+    const HostLevel& hl = c->ops.lev[l];
+    LevelView<double>& v = c->v64[l];
+    v = LevelView<double>{};
+    v.n = hl.n;
+    v.nv = hl.nv;
+    v.h = hl.h;
+    v.hd = std::pow(hl.h, d);
+    v.hdm2 = std::pow(hl.h, d - 2);
+    v.fem = hl.fem ? 1 : 0;
+    v.nb = c->ops.nb;
+    v.bs = hl.fem ? ipow3(l - c->ops.k) : 1;
+    v.eps = (c->ops.nb == 1 && c->ops.eps[0] == 1.0) ? nullptr : c->eps_dev;
+    size_t nvx = hl.nverts;
+    if (!hl.fem) {
+      v.st = reinterpret_cast<double*>(take(sizeof(double) * nvx * ns));
+      v.dg = reinterpret_cast<double*>(take(sizeof(double) * nvx));
+    }
+    if (!hl.pw.empty()) v.pw = reinterpret_cast<double*>(take(sizeof(double) * nvx * (1u << d)));
+    if (l < c->L) {
+      v.u = reinterpret_cast<double*>(take(sizeof(double) * nvx));
+      v.rr = reinterpret_cast<double*>(take(sizeof(double) * nvx));
+      v.bt = reinterpret_cast<double*>(take(sizeof(double) * nvx));
+      v.bf = reinterpret_cast<double*>(take(sizeof(double) * nvx));
+      v.r = reinterpret_cast<double*>(take(sizeof(double) * nvx));
+      v.S = reinterpret_cast<double*>(take(sizeof(double) * nvx));
+      v.ic = reinterpret_cast<double*>(take(sizeof(double) * nvx));
+    }
+  }
+  size_t nvL = c->ops.lev[c->L].nverts;
+  c->ufine[0] = reinterpret_cast<double*>(take(sizeof(double) * nvL));
+  c->ufine[1] = reinterpret_cast<double*>(take(sizeof(double) * nvL));
+  c->bfine = reinterpret_cast<double*>(take(sizeof(double) * nvL));
+  c->rfine = reinterpret_cast<double*>(take(sizeof(double) * nvL));
+  c->npartials = std::max<size_t>(kNormBlocks, fine_sweep_partials(d, ipow3(c->L)));
+  c->partials = reinterpret_cast<double*>(take(sizeof(double) * 2 * c->npartials));
+  c->norms = reinterpret_cast<double*>(take(sizeof(double) * 2 * kMaxHist));
+  return (off + 255) & ~size_t(255);
+}
+
+bool ready(adafac_ctx* c) { return c && c->bound; }
+
+// the single-pass sweep needs 27 | 3^L (L >= 3) and d-linear transfer into the finest level
+bool fused_ok(const adafac_ctx* c) { return c->L >= 3 && c->ops.lev[c->L].pw.empty(); }
+
+int record_start(adafac_ctx* c) {
+  if (!c->timing) return ADAFAC_OK;
+  if (c->ev_used + 2 > int(c->ev.size())) {
+    // pool full: fold the finished pairs into the accumulator
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i + 1 < c->ev_used; i += 2) {
+      float ms = 0.f;
+      HIPCHK(c, hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+      c->t_acc += ms;
+    }
+    c->ev_used = 0;
+  }
+  HIPCHK(c, hipEventRecord(c->ev[c->ev_used], c->stream));
+  return ADAFAC_OK;
+}
+
+int record_stop(adafac_ctx* c) {
+  if (!c->timing) return ADAFAC_OK;
+  HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+  c->ev_used += 2;
+  c->t_launches += 1;
+  return ADAFAC_OK;
+}
+
+// One FP64 cycle.  Cycle n: residual (and norms) of iterate n, FAS restriction cascade,
+// coarse corrections, prolongation; iterate n+1 lands in ufine[1-cur].
+int run_cycle64(adafac_ctx* c) {
+  const int d = c->dim, L = c->L, lmin = c->lmin;
+  const adafac_opts& o = c->opts;
+  const int damping = o.damping;
+  const int pi = damping == ADAFAC_DAMP_PI;
+  double* uin = c->ufine[c->cur];
+  double* uout = c->ufine[1 - c->cur];
+  LevelView<double> F = c->v64[L];
+  F.u = uin;
+  LevelView<double> Lm1 = L > lmin ? c->v64[L - 1] : LevelView<double>{};
+  int nparts = kNormBlocks;
+  int rc;
+  // adAFAC-PI reads and writes the injected fine correction in the same sweep: one kernel per step
+  const bool fused = o.fused && L > lmin && !pi && fused_ok(c);
+  if (fused) {
+    if ((rc = record_start(c))) return rc;
+    HIPCHK(c, launch_fine_sweep<double>(d, F, Lm1, uin, uout, c->bfine, c->rt, o.omega, damping,
+                                        c->pending ? 1 : 0, c->partials, &nparts, c->stream));
+    if ((rc = record_stop(c))) return rc;
+  } else {
+    if ((rc = record_start(c))) return rc;
+    HIPCHK(c, launch_fine_residual<double>(d, F, uin, uout, c->bfine, c->rfine, pi ? Lm1.ic : nullptr,
+                                           Lm1.nv, o.omega, pi, c->partials, kNormBlocks, c->stream));
+    if ((rc = record_stop(c))) return rc;
+  }
+  HIPCHK(c, launch_norm_finalize(c->partials, nparts, c->norms + 2 * (c->ncyc % kMaxHist), c->stream));
+  // coarse levels, finest first: each needs the residual of the next finer level
+  for (int l = L - 1; l >= lmin; --l) {
+    LevelView<double> Fv = c->v64[l + 1];
+    bool from_sweep = fused && l == L - 1;
+    if (l + 1 == L) { Fv.u = uin; Fv.r = c->rfine; }
+    LevelView<double> Cm = l > lmin ? c->v64[l - 1] : LevelView<double>{};
+    double cscale = damping == ADAFAC_DAMP_EXP ? std::pow(o.omega_hat, L - l) : 1.0;
+    HIPCHK(c, launch_level_update<double>(d, c->v64[l], Fv, Cm, c->rt, o.omega, o.omega_tilde, cscale,
+                                          damping, from_sweep ? 0 : 1, c->stream));
+  }
+  for (int l = lmin + 1; l < L; ++l)
+    HIPCHK(c, launch_prolong_add<double>(d, c->v64[l], c->v64[l - 1], c->v64[l].S, c->v64[l - 1].S,
+                                         pi ? c->v64[l - 1].ic : nullptr, c->stream));
+  if (fused) {
+    c->pending = true;       // P S_{L-1} enters the next sweep (or the flush)
+  } else if (L > lmin) {
+    HIPCHK(c, launch_prolong_add<double>(d, c->v64[L], c->v64[L - 1], uout, c->v64[L - 1].S,
+                                         pi ? c->v64[L - 1].ic : nullptr, c->stream));
+  }
+  c->cur = 1 - c->cur;
+  c->ncyc += 1;
+  return ADAFAC_OK;
+}
+
+// Add the pending prolongated coarse correction to the current iterate.
+int flush(adafac_ctx* c) {
+  if (!c->pending) return ADAFAC_OK;
+  const int L = c->L;
+  const bool pi = c->opts.damping == ADAFAC_DAMP_PI;
+  HIPCHK(c, launch_prolong_add<double>(c->dim, c->v64[L], c->v64[L - 1], c->ufine[c->cur], c->v64[L - 1].S,
+                                       pi ? c->v64[L - 1].ic : nullptr, c->stream));
+  c->pending = false;
+  return ADAFAC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void adafac_default_opts(adafac_opts* o) {
+  if (!o) return;
+  o->transfer = ADAFAC_TRANSFER_DLINEAR;
+  o->damping = ADAFAC_DAMP_JAC;
+  o->rtilde = ADAFAC_RTILDE_CONST_EPS1;
+  o->precision = ADAFAC_PREC_FP64;
+  o->inner_k = 4;
+  o->fused = 1;
+  o->omega = 0.6;
+  o->omega_tilde = 0.6;
+  o->omega_hat = 0.5;
+}
+
+int adafac_create(adafac_ctx** out, int dim, int l_min, int l_max) {
+  if (!out) return ADAFAC_EINVAL;
+  *out = nullptr;
+  if (dim != 2 && dim != 3) return ADAFAC_EINVAL;
+  if (l_min < 1 || l_min > l_max) return ADAFAC_EINVAL;
+  if ((dim == 2 && l_max > 9) || (dim == 3 && l_max > 6)) return ADAFAC_EINVAL;
+  adafac_ctx* c = new (std::nothrow) adafac_ctx();
+  if (!c) return ADAFAC_ENOMEM;
+  c->dim = dim;
+  c->lmin = l_min;
+  c->L = l_max;
+  c->eps.assign(1, 1.0);
+  c->nb = 1;
+  adafac_default_opts(&c->opts);
+  *out = c;
+  return ADAFAC_OK;
+}
+
+int adafac_set_coefficient_blocks(adafac_ctx* c, int blocks_per_axis, const double* eps) {
+  if (!c) return ADAFAC_EINVAL;
+  if (!eps || blocks_per_axis < 1) return fail(c, ADAFAC_EINVAL, "eps: null or blocks_per_axis < 1");
+  int k = 0, b = 1;
+  while (b < blocks_per_axis) { b *= 3; ++k; }
+  if (b != blocks_per_axis || k > c->L) return fail(c, ADAFAC_EINVAL, "blocks_per_axis must be 3^k, k <= l_max");
+  size_t n = c->dim == 2 ? size_t(b) * b : size_t(b) * b * b;
+  for (size_t i = 0; i < n; ++i)
+    if (!(eps[i] > 0.0) || !std::isfinite(eps[i])) return fail(c, ADAFAC_EINVAL, "eps must be finite and > 0");
+  c->eps.assign(eps, eps + n);
+  c->nb = b;
+  c->built = c->bound = false;
+  return ADAFAC_OK;
+}
+
+int adafac_set_rhs_lattice(adafac_ctx* c, const double* f, size_t n) {
+  if (!c) return ADAFAC_EINVAL;
+  if (!f || n != nverts_of(c->dim, c->L)) return fail(c, ADAFAC_EINVAL, "f: wrong size");
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(f[i])) return fail(c, ADAFAC_EINVAL, "f: non-finite value");
+  c->f.assign(f, f + n);
+  c->bound = false;
+  return ADAFAC_OK;
+}
+
+int adafac_build_operators(adafac_ctx* c, const adafac_opts* opts) {
+  if (!c) return ADAFAC_EINVAL;
+  adafac_opts o;
+  adafac_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.transfer != ADAFAC_TRANSFER_DLINEAR && o.transfer != ADAFAC_TRANSFER_BOXMG)
+    return fail(c, ADAFAC_EINVAL, "unknown transfer");
+  if (o.damping < ADAFAC_DAMP_JAC || o.damping > ADAFAC_DAMP_EXP) return fail(c, ADAFAC_EINVAL, "unknown damping");
+  if (o.rtilde != ADAFAC_RTILDE_CONST_EPS1) return fail(c, ADAFAC_EUNSUPPORTED, "only the eps = 1 R~ is implemented");
+  if (o.precision != ADAFAC_PREC_FP64) return fail(c, ADAFAC_EUNSUPPORTED, "precision form not implemented");
+  if (!(o.omega > 0.0) || !(o.omega_tilde >= 0.0) || !(o.omega_hat > 0.0) || o.inner_k < 1)
+    return fail(c, ADAFAC_EINVAL, "bad damping parameters");
+  c->opts = o;
+  c->ops = HostOps{};
+  c->ops.dim = c->dim;
+  c->ops.lmin = c->lmin;
+  c->ops.L = c->L;
+  c->ops.nb = c->nb;
+  c->ops.k = 0;
+  for (int b = 1; b < c->nb; b *= 3) c->ops.k++;
+  c->ops.eps = c->eps;
+  std::string m = build_host_ops(c->ops, o.transfer == ADAFAC_TRANSFER_BOXMG, o.omega);
+  if (!m.empty()) return fail(c, ADAFAC_EINVAL, m);
+  c->built = true;
+  c->bound = false;
+  c->ws_need = layout(c, nullptr);
+  return ADAFAC_OK;
+}
+
+int adafac_workspace_bytes(const adafac_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return ADAFAC_EINVAL;
+  if (!c->built) return ADAFAC_ESTATE;
+  *bytes = c->ws_need;
+  return ADAFAC_OK;
+}
+
+int adafac_bind(adafac_ctx* c, void* ws, size_t bytes, void* stream) {
+  if (!c) return ADAFAC_EINVAL;
+  if (!c->built) return fail(c, ADAFAC_ESTATE, "build_operators first");
+  if (c->f.empty()) return fail(c, ADAFAC_ESTATE, "set_rhs_lattice first");
+  size_t need = c->ws_need;
+  if (!ws || bytes < need) return fail(c, ADAFAC_ENOMEM, "workspace too small: need " + std::to_string(need));
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(c, ADAFAC_EINVAL, "workspace not 256-byte aligned");
+  c->ws = static_cast<char*>(ws);
+  c->ws_bytes = bytes;
+  c->stream = static_cast<hipStream_t>(stream);
+  layout(c, c->ws);
+  const int d = c->dim;
+  HIPCHK(c, hipMemsetAsync(c->ws, 0, need, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->eps_dev, c->ops.eps.data(), sizeof(double) * c->ops.eps.size(),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->rt, c->ops.rtilde.data(), sizeof(double) * c->ops.rtilde.size(),
+                           hipMemcpyHostToDevice, c->stream));
+  const int ns = d == 2 ? 9 : 27;
+  for (int l = c->lmin; l <= c->L; ++l) {
+    const HostLevel& hl = c->ops.lev[l];
+    LevelView<double>& v = c->v64[l];
+    if (!hl.fem) {
+      HIPCHK(c, hipMemcpyAsync(const_cast<double*>(v.st), hl.st.data(), sizeof(double) * hl.nverts * ns,
+                               hipMemcpyHostToDevice, c->stream));
+      HIPCHK(c, hipMemcpyAsync(const_cast<double*>(v.dg), hl.dg.data(), sizeof(double) * hl.nverts,
+                               hipMemcpyHostToDevice, c->stream));
+    }
+    if (!hl.pw.empty())
+      HIPCHK(c, hipMemcpyAsync(const_cast<double*>(v.pw), hl.pw.data(), sizeof(double) * hl.pw.size(),
+                               hipMemcpyHostToDevice, c->stream));
+  }
+  // load vector with lumped mass: h^d f on interior vertices of the uniform finest level
+  const HostLevel& fl = c->ops.lev[c->L];
+  std::vector<double> b(fl.nverts, 0.0);
+  const double hd = std::pow(fl.h, d);
+  for (size_t i = 0; i < fl.nverts; ++i) {
+    size_t t = i;
+    bool in = true;
+    for (int a = 0; a < d; ++a) {
+      int x = int(t % fl.nv);
+      t /= fl.nv;
+      if (x == 0 || x == fl.nv - 1) in = false;
+    }
+    if (in) b[i] = hd * c->f[i];
+  }
+  HIPCHK(c, hipMemcpyAsync(c->bfine, b.data(), sizeof(double) * b.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->cur = 0;
+  c->pending = false;
+  c->ncyc = 0;
+  c->bound = true;
+  return ADAFAC_OK;
+}
+
+int adafac_cycle(adafac_ctx* c, int ncycles) {
+  if (!c) return ADAFAC_EINVAL;
+  if (!ready(c)) return fail(c, ADAFAC_ESTATE, "bind first");
+  if (ncycles < 0) return fail(c, ADAFAC_EINVAL, "ncycles < 0");
+  for (int i = 0; i < ncycles; ++i) {
+    int rc = run_cycle64(c);
+    if (rc) return rc;
+  }
+  return ADAFAC_OK;
+}
+
+int adafac_cycles_run(const adafac_ctx* c) { return c ? c->ncyc : 0; }
+
+int adafac_residual(adafac_ctx* c, int cycle, double* l2h, double* linf) {
+  if (!c) return ADAFAC_EINVAL;
+  if (!ready(c)) return fail(c, ADAFAC_ESTATE, "bind first");
+  if (cycle < 0 || cycle >= c->ncyc || c->ncyc - cycle > kMaxHist)
+    return fail(c, ADAFAC_EINVAL, "cycle not run (or no longer kept)");
+  double nrm[2];
+  HIPCHK(c, hipMemcpyAsync(nrm, c->norms + 2 * (cycle % kMaxHist), sizeof(nrm), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (l2h) *l2h = nrm[0];
+  if (linf) *linf = nrm[1];
+  return ADAFAC_OK;
+}
+
+int adafac_solve(adafac_ctx* c, double rel_tol, int max_cycles, int* cycles_done) {
+  if (!c) return ADAFAC_EINVAL;
+  if (!ready(c)) return fail(c, ADAFAC_ESTATE, "bind first");
+  if (!(rel_tol >= 0.0) || max_cycles < 0) return fail(c, ADAFAC_EINVAL, "bad tolerance or cycle cap");
+  int done = 0, rc = ADAFAC_OK;
+  const int start = c->ncyc;
+  double r0 = -1.0;
+  for (; done < max_cycles; ++done) {
+    if ((rc = run_cycle64(c))) break;
+    double l2 = 0, li = 0;
+    if ((rc = adafac_residual(c, c->ncyc - 1, &l2, &li))) break;
+    if (c->ncyc - 1 == 0 || r0 < 0) {
+      double r00 = 0;
+      if ((rc = adafac_residual(c, start == 0 ? 0 : 0, &r00, nullptr))) break;
+      r0 = r00;
+    }
+    if (!std::isfinite(l2) || l2 > 1e3 * r0) {
+      ++done;
+      rc = fail(c, ADAFAC_EDIVERGED, "residual diverged");
+      break;
+    }
+    if (r0 == 0.0 || l2 / r0 <= rel_tol) { ++done; break; }
+  }
+  if (cycles_done) *cycles_done = done;
+  int frc = flush(c);
+  if (!rc) rc = frc;
+  if (!rc) HIPCHK(c, hipStreamSynchronize(c->stream));
+  return rc;
+}
+
+int adafac_get_solution(adafac_ctx* c, double* u, size_t n) {
+  if (!c) return ADAFAC_EINVAL;
+  if (!ready(c)) return fail(c, ADAFAC_ESTATE, "bind first");
+  if (!u || n != nverts_of(c->dim, c->L)) return fail(c, ADAFAC_EINVAL, "u: wrong size");
+  int rc = flush(c);
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync(u, c->ufine[c->cur], sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return ADAFAC_OK;
+}
+
+int adafac_set_solution(adafac_ctx* c, const double* u, size_t n) {
+  if (!c) return ADAFAC_EINVAL;
+  if (!ready(c)) return fail(c, ADAFAC_ESTATE, "bind first");
+  if (!u || n != nverts_of(c->dim, c->L)) return fail(c, ADAFAC_EINVAL, "u: wrong size");
+  const HostLevel& fl = c->ops.lev[c->L];
+  std::vector<double> v(u, u + n);
+  for (size_t i = 0; i < n; ++i) {
+    size_t t = i;
+    for (int a = 0; a < c->dim; ++a) {
+      int x = int(t % fl.nv);
+      t /= fl.nv;
+      if (x == 0 || x == fl.nv - 1) v[i] = 0.0;
+    }
+    if (!std::isfinite(v[i])) return fail(c, ADAFAC_EINVAL, "u: non-finite value");
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->ufine[c->cur], v.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->pending = false;
+  c->ncyc = 0;
+  return ADAFAC_OK;
+}
+
+int adafac_get_level(adafac_ctx* c, int level, int which, double* out, size_t n) {
+  if (!c) return ADAFAC_EINVAL;
+  if (!ready(c)) return fail(c, ADAFAC_ESTATE, "bind first");
+  if (level < c->lmin || level >= c->L) return fail(c, ADAFAC_EINVAL, "level out of range");
+  if (!out || n != nverts_of(c->dim, level)) return fail(c, ADAFAC_EINVAL, "out: wrong size");
+  const LevelView<double>& v = c->v64[level];
+  const double* src = nullptr;
+  switch (which) {
+    case 0: src = v.u; break;
+    case 1: src = v.bf; break;
+    case 2: src = v.bt; break;
+    case 3: src = v.r; break;
+    case 4: src = v.S; break;
+    default: return fail(c, ADAFAC_EINVAL, "which out of range");
+  }
+  HIPCHK(c, hipMemcpyAsync(out, src, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return ADAFAC_OK;
+}
+
+int adafac_host_operator(const adafac_ctx* cc, int level, int which, double* out, size_t n) {
+  adafac_ctx* c = const_cast<adafac_ctx*>(cc);
+  if (!c || !out) return ADAFAC_EINVAL;
+  if (!c->built) return fail(c, ADAFAC_ESTATE, "build_operators first");
+  const int d = c->dim, ns = d == 2 ? 9 : 27;
+  if (which == 3) {
+    if (n != c->ops.rtilde.size()) return fail(c, ADAFAC_EINVAL, "out: wrong size");
+    std::memcpy(out, c->ops.rtilde.data(), sizeof(double) * n);
+    return ADAFAC_OK;
+  }
+  if (level < c->lmin || level > c->L) return fail(c, ADAFAC_EINVAL, "level out of range");
+  const HostLevel& hl = c->ops.lev[level];
+  const size_t nv = hl.nverts;
+  auto coords = [&](size_t i, int* v) { for (int a = 0; a < d; ++a) { v[a] = int(i % hl.nv); i /= hl.nv; } };
+  auto interior = [&](const int* v) { for (int a = 0; a < d; ++a) if (v[a] <= 0 || v[a] >= hl.nv - 1) return false; return true; };
+  if (which == 0) {
+    if (n != nv * ns) return fail(c, ADAFAC_EINVAL, "out: wrong size");
+    if (!hl.st.empty()) { std::memcpy(out, hl.st.data(), sizeof(double) * n); return ADAFAC_OK; }
+    for (size_t i = 0; i < nv; ++i) {
+      int v[3] = {0, 0, 0};
+      coords(i, v);
+      for (int t = 0; t < ns; ++t) {
+        int o[3] = {t % 3 - 1, (t / 3) % 3 - 1, d == 3 ? t / 9 - 1 : 0}, w[3] = {0, 0, 0};
+        for (int a = 0; a < d; ++a) w[a] = v[a] + o[a];
+        out[i * ns + t] = (interior(v) && interior(w)) ? fem_stencil_entry(c->ops, level, v, o) : 0.0;
+      }
+    }
+    return ADAFAC_OK;
+  }
+  if (which == 1) {
+    if (n != nv) return fail(c, ADAFAC_EINVAL, "out: wrong size");
+    std::memcpy(out, hl.dg.data(), sizeof(double) * n);
+    return ADAFAC_OK;
+  }
+  if (which == 2) {
+    const size_t ne = size_t(1) << d;
+    if (level <= c->lmin || n != nv * ne) return fail(c, ADAFAC_EINVAL, "level or size out of range");
+    if (!hl.pw.empty()) { std::memcpy(out, hl.pw.data(), sizeof(double) * n); return ADAFAC_OK; }
+    const int nc = hl.n / 3;
+    for (size_t i = 0; i < nv; ++i) {
+      int v[3] = {0, 0, 0};
+      coords(i, v);
+      for (size_t e = 0; e < ne; ++e) {
+        double w = interior(v) ? 1.0 : 0.0;
+        for (int a = 0; a < d; ++a) {
+          int cell = std::min(v[a] / 3, nc - 1), s = v[a] - 3 * cell, cv = cell + int((e >> a) & 1);
+          w *= ((e >> a) & 1) ? s / 3.0 : (3 - s) / 3.0;
+          if (cv <= 0 || cv >= nc) w = 0.0;   // no shape function on a boundary coarse vertex
+        }
+        out[i * ne + e] = w;
+      }
+    }
+    return ADAFAC_OK;
+  }
+  return fail(c, ADAFAC_EINVAL, "which out of range");
+}
+
+int64_t adafac_dofs_per_cycle(const adafac_ctx* c) {
+  if (!c) return 0;
+  int64_t s = 0;
+  for (int l = c->lmin; l <= c->L; ++l) {
+    int64_t m = ipow3(l) - 1;
+    s += c->dim == 2 ? m * m : m * m * m;
+  }
+  return s;
+}
+
+int adafac_set_kernel_timing(adafac_ctx* c, int enable) {
+  if (!c) return ADAFAC_EINVAL;
+  if (c->stream || c->bound) HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (enable && c->ev.empty()) {
+    c->ev.resize(2 * kTimingPool);
+    for (auto& e : c->ev) HIPCHK(c, hipEventCreate(&e));
+  }
+  c->timing = enable != 0;
+  c->ev_used = 0;
+  c->t_acc = 0.0;
+  c->t_launches = 0;
+  return ADAFAC_OK;
+}
+
+int adafac_kernel_time(adafac_ctx* c, double* total_ms, int* launches) {
+  if (!c) return ADAFAC_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int i = 0; i + 1 < c->ev_used; i += 2) {
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+    c->t_acc += ms;
+  }
+  c->ev_used = 0;
+  if (total_ms) *total_ms = c->t_acc;
+  if (launches) *launches = c->t_launches;
+  return ADAFAC_OK;
+}
+
+void adafac_destroy(adafac_ctx* c) {
+  if (!c) return;
+  if (c->bound) (void)hipStreamSynchronize(c->stream);
+  for (auto& e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+const char* adafac_last_error(const adafac_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

@@ -1,0 +1,153 @@
+// Device helpers shared by the adAFAC kernels: lattice indexing, the level operator,
+// transfer weights and block reductions.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "adafac_internal.hpp"
+
+namespace adafac {
+
+template <int D>
+__device__ __forceinline__ size_t lin(int x, int y, int z, int nv) {
+  return D == 2 ? size_t(y) * nv + x : (size_t(z) * nv + y) * nv + x;
+}
+
+template <int D>
+__device__ __forceinline__ bool is_interior(int x, int y, int z, int nv) {
+  bool in = x > 0 && x < nv - 1 && y > 0 && y < nv - 1;
+  if (D == 3) in = in && z > 0 && z < nv - 1;
+  return in;
+}
+
+template <int D>
+__device__ __forceinline__ int rt_index(int ox, int oy, int oz) {
+  return D == 2 ? (ox + 2) + 5 * (oy + 2) : (ox + 2) + 5 * (oy + 2) + 25 * (oz + 2);
+}
+
+template <typename T, int D>
+__device__ __forceinline__ T eps_cell(const LevelView<T>& L, int cx, int cy, int cz) {
+  if (!L.eps) return T(1);
+  int bx = cx / L.bs, by = cy / L.bs;
+  if (D == 2) return L.eps[by * L.nb + bx];
+  int bz = cz / L.bs;
+  return L.eps[(bz * L.nb + by) * L.nb + bx];
+}
+
+// A_l u at an interior vertex; U(dx, dy, dz) returns u at the neighbour offset.  dg receives
+// the diagonal.  Q1 levels: element-wise sum over the 2^d adjacent cells of
+// eps_c h^(d-2) K[i][j] u_j with the d-linear element matrix (2D: 2/3 on the diagonal,
+// -1/6 along an edge, -1/3 across; 3D: 1/3, 0, -1/12 for face and body diagonals).
+// Stored levels: the 3^d Galerkin stencil.
+template <typename T, int D, typename F>
+__device__ __forceinline__ T apply_level_op(const LevelView<T>& L, int x, int y, int z, T& dg, F&& U) {
+  if (L.fem) {
+    const T u0 = U(0, 0, 0);
+    T s = T(0), es = T(0);
+    if (D == 2) {
+#pragma unroll
+      for (int sy = -1; sy <= 1; sy += 2)
+#pragma unroll
+        for (int sx = -1; sx <= 1; sx += 2) {
+          T e = eps_cell<T, D>(L, x + (sx < 0 ? -1 : 0), y + (sy < 0 ? -1 : 0), 0);
+          s += e * (T(2.0 / 3.0) * u0 - T(1.0 / 6.0) * (U(sx, 0, 0) + U(0, sy, 0)) - T(1.0 / 3.0) * U(sx, sy, 0));
+          es += e;
+        }
+      dg = T(2.0 / 3.0) * es;
+      return s;
+    } else {
+#pragma unroll
+      for (int sz = -1; sz <= 1; sz += 2)
+#pragma unroll
+        for (int sy = -1; sy <= 1; sy += 2)
+#pragma unroll
+          for (int sx = -1; sx <= 1; sx += 2) {
+            T e = eps_cell<T, D>(L, x + (sx < 0 ? -1 : 0), y + (sy < 0 ? -1 : 0), z + (sz < 0 ? -1 : 0));
+            s += e * (T(1.0 / 3.0) * u0 -
+                      T(1.0 / 12.0) * (U(sx, sy, 0) + U(sx, 0, sz) + U(0, sy, sz) + U(sx, sy, sz)));
+            es += e;
+          }
+      dg = L.h * T(1.0 / 3.0) * es;
+      return L.h * s;
+    }
+  }
+  const int nv = L.nv;
+  const size_t i = lin<D>(x, y, z, nv);
+  const T* st = L.st + i * (D == 2 ? 9 : 27);
+  T s = T(0);
+  const int zlo = D == 3 ? -1 : 0, zhi = D == 3 ? 1 : 0;
+  for (int oz = zlo; oz <= zhi; ++oz)
+    for (int oy = -1; oy <= 1; ++oy)
+      for (int ox = -1; ox <= 1; ++ox)
+        s += st[(ox + 1) + 3 * (oy + 1) + 9 * (oz + 1)] * U(ox, oy, oz);
+  dg = L.dg[i];
+  return s;
+}
+
+// P(f <- c) of the transfer from the next coarser level into level F (R = P^T).
+template <typename T, int D>
+__device__ __forceinline__ T restrict_weight(const LevelView<T>& F, int fx, int fy, int fz, int cx, int cy,
+                                             int cz) {
+  if (!F.pw) {
+    T w = (T(3) - T(abs(fx - 3 * cx))) * T(1.0 / 3.0);
+    w *= (T(3) - T(abs(fy - 3 * cy))) * T(1.0 / 3.0);
+    if (D == 3) w *= (T(3) - T(abs(fz - 3 * cz))) * T(1.0 / 3.0);
+    return w;
+  }
+  if (!is_interior<D>(fx, fy, fz, F.nv)) return T(0);
+  const int nc = (F.nv - 1) / 3;
+  int ex = cx - min(fx / 3, nc - 1), ey = cy - min(fy / 3, nc - 1);
+  int ez = D == 3 ? cz - min(fz / 3, nc - 1) : 0;
+  if (ex < 0 || ex > 1 || ey < 0 || ey > 1 || ez < 0 || ez > 1) return T(0);
+  return F.pw[lin<D>(fx, fy, fz, F.nv) * (1 << D) + (ex | (ey << 1) | (ez << 2))];
+}
+
+// sum_c P(f <- c) (src(c) - sub(c)) at fine vertex f of level F from level C.
+template <typename T, int D>
+__device__ __forceinline__ T prolong_value(const LevelView<T>& F, const LevelView<T>& C, int x, int y, int z,
+                                           const T* __restrict__ src, const T* __restrict__ sub) {
+  const int nc = C.nv - 1;
+  const int cx = min(x / 3, nc - 1), cy = min(y / 3, nc - 1), cz = D == 3 ? min(z / 3, nc - 1) : 0;
+  const int sx = x - 3 * cx, sy = y - 3 * cy, sz = z - 3 * cz;
+  T acc = T(0);
+#pragma unroll
+  for (int e = 0; e < (1 << D); ++e) {
+    const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+    T w;
+    if (!F.pw) {
+      w = (ex ? T(sx) : T(3 - sx)) * T(1.0 / 3.0);
+      w *= (ey ? T(sy) : T(3 - sy)) * T(1.0 / 3.0);
+      if (D == 3) w *= (ez ? T(sz) : T(3 - sz)) * T(1.0 / 3.0);
+    } else {
+      w = F.pw[lin<D>(x, y, z, F.nv) * (1 << D) + e];
+    }
+    if (w != T(0)) {
+      size_t ci = lin<D>(cx + ex, cy + ey, cz + ez, C.nv);
+      T v = src[ci];
+      if (sub) v -= sub[ci];
+      acc += w * v;
+    }
+  }
+  return acc;
+}
+
+// Block-wide (256 threads) sum and max; thread 0 writes (sum, max) to partials[2*blockIdx.x].
+__device__ __forceinline__ void block_norm_partials(double ssum, double smax, double* partials) {
+  __shared__ double ws[8], wm[8];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    ssum += __shfl_xor(ssum, off);
+    smax = fmax(smax, __shfl_xor(smax, off));
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) { ws[wave] = ssum; wm[wave] = smax; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0, m = 0.0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int w = 0; w < nw; ++w) { s += ws[w]; m = fmax(m, wm[w]); }
+    partials[2 * blockIdx.x] = s;
+    partials[2 * blockIdx.x + 1] = m;
+  }
+}
+
+}  // namespace adafac

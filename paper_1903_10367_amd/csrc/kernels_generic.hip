@@ -1,0 +1,200 @@
+// gfx950 kernels of the adAFAC cycle, one kernel per step (Sec. 3.1, Algorithm 1).
+//
+// These kernels are the building blocks that every path uses for the coarse levels and,
+// with `fused = 0`, for the finest level too:
+//   fine_residual   r_L = b - A_L u, u <- u + omega D^-1 r_L, per-block norm partials
+//   level_update    FAS step of one coarse level l (Sec. 2.3): inject u_l = I u_{l+1},
+//                   restrict R r_{l+1} and R~ r_{l+1}, form the FAS right-hand side with the
+//                   tau correction b_l = R r_{l+1} + A_l I u_{l+1}, the level residual
+//                   r_l = b_l - A_l u_l, the Jacobi correction c_l = omega D^-1 r_l and the
+//                   auxiliary correction c~_l = omega~ D^-1 b~_l (Sec. 3.2)
+//   prolong_add     S_l += P S_{l-1} (accumulation of the prolonged corrections)
+//   norm_finalize   fixed-order reduction of the norm partials
+// One thread per vertex; arrays cover the full vertex lattice (boundary entries zero).
+#include <hip/hip_runtime.h>
+
+#include "adafac.h"
+#include "adafac_internal.hpp"
+#include "kernels_common.hpp"
+
+namespace adafac {
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_fine_residual(LevelView<T> F, const T* __restrict__ uin,
+                                                       T* __restrict__ uout, const T* __restrict__ b,
+                                                       T* __restrict__ r, T* __restrict__ ic_coarse,
+                                                       int nvc, T omega, int pi,
+                                                       double* __restrict__ partials) {
+  const int nv = F.nv;
+  const size_t nverts = D == 2 ? size_t(nv) * nv : size_t(nv) * nv * nv;
+  double ssum = 0.0, smax = 0.0;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nverts;
+       i += size_t(gridDim.x) * blockDim.x) {
+    int x = int(i % nv), y = int((i / nv) % nv), z = D == 3 ? int(i / (size_t(nv) * nv)) : 0;
+    if (!is_interior<D>(x, y, z, nv)) continue;
+    T dg;
+    T au = apply_level_op<T, D>(F, x, y, z, dg, [&](int dx, int dy, int dz) {
+      return uin[lin<D>(x + dx, y + dy, z + dz, nv)];
+    });
+    T res = b[i] - au;
+    T c = omega * res / dg;
+    r[i] = res;
+    uout[i] = uin[i] + c;
+    if (pi && x % 3 == 0 && y % 3 == 0 && (D == 2 || z % 3 == 0))
+      ic_coarse[lin<D>(x / 3, y / 3, z / 3, nvc)] = c;
+    double rd = double(res);
+    ssum += double(F.hd) * rd * rd;
+    smax = fmax(smax, fabs(rd));
+  }
+  block_norm_partials(ssum, smax, partials);
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_level_update(LevelView<T> C, LevelView<T> F, LevelView<T> Cm,
+                                                      const T* __restrict__ rt, T omega, T omega_t,
+                                                      T cscale, int damping, int gather) {
+  const int nv = C.nv, nvf = F.nv;
+  const size_t nverts = D == 2 ? size_t(nv) * nv : size_t(nv) * nv * nv;
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nverts) return;
+  int x = int(i % nv), y = int((i / nv) % nv), z = D == 3 ? int(i / (size_t(nv) * nv)) : 0;
+  if (!is_interior<D>(x, y, z, nv)) return;
+  T uv, rr, bt;
+  if (gather) {
+    const int X = 3 * x, Y = 3 * y, Z = 3 * z;
+    uv = F.u[lin<D>(X, Y, Z, nvf)];
+    rr = T(0);
+    bt = T(0);
+    const int zlo = D == 3 ? -2 : 0, zhi = D == 3 ? 2 : 0;
+    for (int oz = zlo; oz <= zhi; ++oz)
+      for (int oy = -2; oy <= 2; ++oy)
+        for (int ox = -2; ox <= 2; ++ox) {
+          T rv = F.r[lin<D>(X + ox, Y + oy, Z + oz, nvf)];
+          rr += restrict_weight<T, D>(F, X + ox, Y + oy, Z + oz, x, y, z) * rv;
+          if (damping == ADAFAC_DAMP_JAC) bt += rt[rt_index<D>(ox, oy, oz)] * rv;
+        }
+    C.u[i] = uv;
+    C.rr[i] = rr;
+    C.bt[i] = bt;
+  } else {
+    uv = C.u[i];
+    rr = C.rr[i];
+    bt = C.bt[i];
+  }
+  T dg;
+  T au = apply_level_op<T, D>(C, x, y, z, dg, [&](int dx, int dy, int dz) {
+    return gather ? F.u[lin<D>(3 * (x + dx), 3 * (y + dy), 3 * (z + dz), nvf)]
+                  : C.u[lin<D>(x + dx, y + dy, z + dz, nv)];
+  });
+  // FAS right-hand side with the tau correction, then the FAS residual of this level
+  T bf = rr + au;
+  T res = bf - au;
+  T c = cscale * omega * res / dg;
+  T s = c;
+  if (damping == ADAFAC_DAMP_JAC) s = c - omega_t * bt / dg;
+  if (damping == ADAFAC_DAMP_PI && Cm.ic && x % 3 == 0 && y % 3 == 0 && (D == 2 || z % 3 == 0))
+    Cm.ic[lin<D>(x / 3, y / 3, z / 3, Cm.nv)] = c;
+  C.bf[i] = bf;
+  C.r[i] = res;
+  C.S[i] = s;
+}
+
+// dst(f) += sum_c P(f <- c) (src(c) - sub(c)) on the interior vertices of level F.
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_prolong_add(LevelView<T> F, LevelView<T> C, T* __restrict__ dst,
+                                                     const T* __restrict__ src, const T* __restrict__ sub) {
+  const int nv = F.nv;
+  const size_t nverts = D == 2 ? size_t(nv) * nv : size_t(nv) * nv * nv;
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nverts) return;
+  int x = int(i % nv), y = int((i / nv) % nv), z = D == 3 ? int(i / (size_t(nv) * nv)) : 0;
+  if (!is_interior<D>(x, y, z, nv)) return;
+  dst[i] += prolong_value<T, D>(F, C, x, y, z, src, sub);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_fine_residual(int d, const LevelView<T>& F, const T* uin, T* uout, const T* b, T* r,
+                                T* ic_coarse, int nvc, T omega, int pi, double* partials, int nblocks,
+                                hipStream_t s) {
+  if (d == 2)
+    k_fine_residual<T, 2><<<nblocks, 256, 0, s>>>(F, uin, uout, b, r, ic_coarse, nvc, omega, pi, partials);
+  else
+    k_fine_residual<T, 3><<<nblocks, 256, 0, s>>>(F, uin, uout, b, r, ic_coarse, nvc, omega, pi, partials);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_level_update(int d, const LevelView<T>& C, const LevelView<T>& F, const LevelView<T>& Cm,
+                               const T* rt, T omega, T omega_t, T cscale, int damping, int gather,
+                               hipStream_t s) {
+  size_t nverts = d == 2 ? size_t(C.nv) * C.nv : size_t(C.nv) * C.nv * C.nv;
+  unsigned nb = unsigned((nverts + 255) / 256);
+  if (d == 2)
+    k_level_update<T, 2><<<nb, 256, 0, s>>>(C, F, Cm, rt, omega, omega_t, cscale, damping, gather);
+  else
+    k_level_update<T, 3><<<nb, 256, 0, s>>>(C, F, Cm, rt, omega, omega_t, cscale, damping, gather);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong_add(int d, const LevelView<T>& F, const LevelView<T>& C, T* dst, const T* src,
+                              const T* sub, hipStream_t s) {
+  size_t nverts = d == 2 ? size_t(F.nv) * F.nv : size_t(F.nv) * F.nv * F.nv;
+  unsigned nb = unsigned((nverts + 255) / 256);
+  if (d == 2)
+    k_prolong_add<T, 2><<<nb, 256, 0, s>>>(F, C, dst, src, sub);
+  else
+    k_prolong_add<T, 3><<<nb, 256, 0, s>>>(F, C, dst, src, sub);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_norm_finalize(const double* __restrict__ partials, int n,
+                                                       double* __restrict__ out) {
+  __shared__ double ss[256], sm[256];
+  double s = 0.0, m = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    s += partials[2 * i];
+    m = fmax(m, partials[2 * i + 1]);
+  }
+  ss[threadIdx.x] = s;
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      ss[threadIdx.x] += ss[threadIdx.x + w];
+      sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = sqrt(ss[0]);
+    out[1] = sm[0];
+  }
+}
+
+hipError_t launch_norm_finalize(const double* partials, int n, double* out, hipStream_t s) {
+  k_norm_finalize<<<1, 256, 0, s>>>(partials, n, out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_fine_residual<double>(int, const LevelView<double>&, const double*, double*,
+                                                 const double*, double*, double*, int, double, int, double*,
+                                                 int, hipStream_t);
+template hipError_t launch_fine_residual<float>(int, const LevelView<float>&, const float*, float*,
+                                                const float*, float*, float*, int, float, int, double*, int,
+                                                hipStream_t);
+template hipError_t launch_level_update<double>(int, const LevelView<double>&, const LevelView<double>&,
+                                                const LevelView<double>&, const double*, double, double,
+                                                double, int, int, hipStream_t);
+template hipError_t launch_level_update<float>(int, const LevelView<float>&, const LevelView<float>&,
+                                               const LevelView<float>&, const float*, float, float, float,
+                                               int, int, hipStream_t);
+template hipError_t launch_prolong_add<double>(int, const LevelView<double>&, const LevelView<double>&,
+                                               double*, const double*, const double*, hipStream_t);
+template hipError_t launch_prolong_add<float>(int, const LevelView<float>&, const LevelView<float>&, float*,
+                                              const float*, const float*, hipStream_t);
+
+}  // namespace adafac

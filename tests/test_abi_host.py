@@ -1,0 +1,150 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol, validates its
+arguments, and its host-side FP64 setup (Q1 operators, BoxMG, Galerkin, R~) agrees with the
+oracle.  No GPU work is launched here."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import adafac_inputs as inp
+from oracle import hierarchy
+from paper_1903_10367_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _abi.lib()
+    header = open(os.path.join(ROOT, "include", "adafac.h")).read()
+    declared = sorted(set(re.findall(r"\b(adafac_[a-z_]+)\s*\(", header)))
+    assert declared, "no declarations found"
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(_abi.EXPORTS) == declared
+
+
+def _ctx(d, lmin, L, eps=None, transfer="dlinear", f=None):
+    lib = _abi.lib()
+    ctx = C.c_void_p()
+    assert lib.adafac_create(C.byref(ctx), d, lmin, L) == 0
+    if eps is not None:
+        e = np.ascontiguousarray(eps, dtype=np.float64)
+        assert lib.adafac_set_coefficient_blocks(ctx, e.shape[0], _dp(e)) == 0
+    fa = np.zeros((3 ** L + 1) ** d) if f is None else np.ascontiguousarray(f, dtype=np.float64).ravel()
+    assert lib.adafac_set_rhs_lattice(ctx, _dp(fa), fa.size) == 0
+    o = _abi.Opts()
+    lib.adafac_default_opts(C.byref(o))
+    o.transfer = _abi.TRANSFER[transfer]
+    rc = lib.adafac_build_operators(ctx, C.byref(o))
+    assert rc == 0, lib.adafac_last_error(ctx)
+    return lib, ctx
+
+
+def _host_op(lib, ctx, level, which, n):
+    out = np.zeros(n)
+    rc = lib.adafac_host_operator(ctx, level, which, _dp(out), n)
+    assert rc == 0, lib.adafac_last_error(ctx)
+    return out
+
+
+def _stencil_from_matrix(A, d, level):
+    nv = 3 ** level + 1
+    N = nv ** d
+    ns = 3 ** d
+    st = np.zeros((N, ns))
+    A = A.tocoo()
+    rv = np.array(np.unravel_index(A.row, (nv,) * d))   # axis order z, y, x
+    cv = np.array(np.unravel_index(A.col, (nv,) * d))
+    o = cv - rv
+    slot = np.zeros(A.row.size, int)
+    for a in range(d):   # slot (ox+1) + 3 (oy+1) + 9 (oz+1): x is the last numpy axis
+        slot += (o[d - 1 - a] + 1) * 3 ** a
+    np.add.at(st, (A.row, slot), A.data)
+    return st.ravel()
+
+
+@pytest.mark.parametrize("d,L,k,kind", [(2, 3, 2, "boxmg"), (2, 3, 2, "dlinear"), (3, 2, 1, "boxmg"),
+                                        (2, 4, 0, "dlinear"), (3, 3, 2, "boxmg")])
+def test_host_operators_match_oracle(d, L, k, kind):
+    eps = inp.eps_blocks(d, k, 3.0, seed=21) if k else None
+    lib, ctx = _ctx(d, 1, L, eps, kind)
+    H = hierarchy.Hierarchy(d, L, 1, eps, kind)
+    try:
+        for l in range(1, L + 1):
+            nv = (3 ** l + 1) ** d
+            st = _host_op(lib, ctx, l, 0, nv * 3 ** d)
+            ref = _stencil_from_matrix(H.lev[l].A.mat, d, l)
+            scale = np.abs(ref).max()
+            assert np.abs(st - ref).max() <= 1e-13 * scale, f"stencil level {l}"
+            dg = _host_op(lib, ctx, l, 1, nv)
+            assert np.abs(dg - H.lev[l].D).max() <= 1e-13 * scale
+            if l > 1:
+                pw = _host_op(lib, ctx, l, 2, nv * 2 ** d).reshape(nv, 2 ** d)
+                P = H.lev[l].P.mat.toarray()
+                nvc = 3 ** (l - 1) + 1
+                nc = nvc - 1
+                fidx = np.array(np.unravel_index(np.arange(nv), (3 ** l + 1,) * d))[::-1]  # x, y, z
+                worst = 0.0
+                for e in range(2 ** d):
+                    cells = np.minimum(fidx // 3, nc - 1)
+                    cx = cells + np.array([(e >> a) & 1 for a in range(d)])[:, None]
+                    ci = np.ravel_multi_index(tuple(cx[::-1]), (nvc,) * d)
+                    worst = max(worst, np.abs(P[np.arange(nv), ci] - pw[:, e]).max())
+                assert worst < 1e-13, f"transfer level {l}"
+        rt = _host_op(lib, ctx, 0, 3, 5 ** d)
+        want = 0.6 * H.smoothed_eps1[(slice(1, 6),) * d]
+        assert np.abs(rt - want.ravel()).max() < 1e-15
+    finally:
+        lib.adafac_destroy(ctx)
+
+
+def test_argument_validation():
+    lib = _abi.lib()
+    ctx = C.c_void_p()
+    assert lib.adafac_create(C.byref(ctx), 4, 1, 3) == _abi.EINVAL
+    assert lib.adafac_create(C.byref(ctx), 2, 0, 3) == _abi.EINVAL
+    assert lib.adafac_create(C.byref(ctx), 2, 3, 2) == _abi.EINVAL
+    assert lib.adafac_create(C.byref(ctx), 3, 1, 7) == _abi.EINVAL
+    assert lib.adafac_create(C.byref(ctx), 2, 1, 3) == 0
+    try:
+        bad = np.array([[1.0, -1.0, 1.0]] * 3)
+        assert lib.adafac_set_coefficient_blocks(ctx, 3, _dp(bad)) == _abi.EINVAL
+        nan = np.full((3, 3), np.nan)
+        assert lib.adafac_set_coefficient_blocks(ctx, 3, _dp(nan)) == _abi.EINVAL
+        two = np.ones((2, 2))
+        assert lib.adafac_set_coefficient_blocks(ctx, 2, _dp(two)) == _abi.EINVAL
+        f = np.zeros(27 * 27)
+        assert lib.adafac_set_rhs_lattice(ctx, _dp(f), f.size) == _abi.EINVAL
+        n = C.c_size_t()
+        assert lib.adafac_workspace_bytes(ctx, C.byref(n)) == _abi.ESTATE
+        f = np.zeros(28 * 28)
+        f[5] = np.inf
+        assert lib.adafac_set_rhs_lattice(ctx, _dp(f), f.size) == _abi.EINVAL
+        f[5] = 0.0
+        assert lib.adafac_set_rhs_lattice(ctx, _dp(f), f.size) == 0
+        assert lib.adafac_bind(ctx, None, 0, None) == _abi.ESTATE
+        assert lib.adafac_build_operators(ctx, None) == 0
+        assert lib.adafac_workspace_bytes(ctx, C.byref(n)) == 0 and n.value > 0
+        assert lib.adafac_bind(ctx, None, 0, None) == _abi.ENOMEM
+        assert lib.adafac_cycle(ctx, 1) == _abi.ESTATE
+        assert lib.adafac_dofs_per_cycle(ctx) == 4 + 64 + 676
+    finally:
+        lib.adafac_destroy(ctx)
+
+
+def test_workspace_grows_with_problem():
+    sizes = []
+    for L in (3, 4):
+        lib, ctx = _ctx(3, 1, L)
+        n = C.c_size_t()
+        assert lib.adafac_workspace_bytes(ctx, C.byref(n)) == 0
+        sizes.append(n.value)
+        lib.adafac_destroy(ctx)
+    # four finest-level FP64 arrays dominate
+    assert sizes[1] > 4 * 8 * 82 ** 3 and sizes[0] < sizes[1]

@@ -1,0 +1,185 @@
+"""Parity of the gfx950 cycle (through the C ABI) with the FP64 oracle.
+
+Bar (FP64 path): per-cycle residual norms within 1e-12 of the oracle's, relative to the
+initial norm, and the iterate within 1e-12 in relative 2-norm.  Inputs are the seeded
+synthetic workloads of ``adafac_inputs``.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import adafac_inputs as inp
+from oracle import cycle, hierarchy
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def gpu_run(d, L, f, eps=None, cycles=10, **kw):
+    from paper_1903_10367_amd import Solver
+    s = Solver(d, 1, L, f, eps_blocks=eps, **kw)
+    s.cycle(cycles)
+    hist = s.residuals()
+    u = s.solution()
+    s.close()
+    return hist, u
+
+
+def oracle_run(d, L, f, eps=None, cycles=10, transfer="dlinear", **kw):
+    H = hierarchy.Hierarchy(d, L, 1, eps, transfer)
+    b = H.rhs(f)
+    u, hist = cycle.solve(H, b, cycles, **kw)
+    return hist, u
+
+
+def assert_parity(hg, ug, ho, uo, tol=TOL):
+    assert len(hg) == len(ho)
+    r0, m0 = ho[0]
+    for n, (a, b) in enumerate(zip(hg, ho)):
+        assert abs(a[0] - b[0]) <= tol * r0, f"cycle {n}: l2h {a[0]!r} vs {b[0]!r}"
+        assert abs(a[1] - b[1]) <= tol * m0, f"cycle {n}: linf {a[1]!r} vs {b[1]!r}"
+    err = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+    assert err <= tol, f"solution rel. error {err:.3e}"
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_2d_poisson_l4_twenty_cycles(fused):
+    w = inp.workload_2d_poisson_l4()
+    say("case 2d poisson L=4 fused", fused)
+    hg, ug = gpu_run(2, 4, w["f"], cycles=20, fused=fused)
+    ho, uo = oracle_run(2, 4, w["f"], cycles=20)
+    assert_parity(hg, ug, ho, uo)
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_3d_poisson_l4(fused):
+    f = inp.rhs(3, 4, seed=3, dist="normal")
+    say("case 3d poisson L=4 fused", fused)
+    hg, ug = gpu_run(3, 4, f, cycles=8, fused=fused)
+    ho, uo = oracle_run(3, 4, f, cycles=8)
+    assert_parity(hg, ug, ho, uo)
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_2d_jump_coefficient_boxmg(fused):
+    eps = inp.eps_blocks(2, 2, 3.0, seed=4)
+    f = inp.rhs(2, 4, seed=5)
+    say("case 2d jump L=4 boxmg fused", fused)
+    hg, ug = gpu_run(2, 4, f, eps, cycles=12, transfer="boxmg", fused=fused)
+    ho, uo = oracle_run(2, 4, f, eps, cycles=12, transfer="boxmg")
+    assert_parity(hg, ug, ho, uo)
+
+
+def test_3d_jump_coefficient_boxmg():
+    eps = inp.eps_blocks(3, 2, 4.0, seed=6)
+    f = inp.rhs(3, 4, seed=7)
+    say("case 3d jump 9^3 blocks L=4 boxmg")
+    hg, ug = gpu_run(3, 4, f, eps, cycles=6, transfer="boxmg")
+    ho, uo = oracle_run(3, 4, f, eps, cycles=6, transfer="boxmg")
+    assert_parity(hg, ug, ho, uo)
+
+
+def test_3d_coefficient_per_fine_cell():
+    # eps on every finest cell: BoxMG on every transfer, stored Galerkin operators below L
+    eps = inp.eps_blocks(3, 2, 2.0, seed=8)
+    f = inp.rhs(3, 2, seed=9)
+    say("case 3d eps per fine cell L=2")
+    hg, ug = gpu_run(3, 2, f, eps, cycles=6, transfer="boxmg")
+    ho, uo = oracle_run(3, 2, f, eps, cycles=6, transfer="boxmg")
+    assert_parity(hg, ug, ho, uo)
+
+
+@pytest.mark.parametrize("damping", ["none", "pi", "exp"])
+def test_damping_variants(damping):
+    w = inp.workload_2d_poisson_l4(seed=2)
+    say("case damping", damping)
+    hg, ug = gpu_run(2, 4, w["f"], cycles=10, damping=damping, omega_hat=0.7)
+    ho, uo = oracle_run(2, 4, w["f"], cycles=10, damping=damping, omega_hat=0.7)
+    assert_parity(hg, ug, ho, uo)
+
+
+@pytest.mark.parametrize("d,L,fused", [(2, 4, True), (3, 3, True), (3, 3, False)])
+def test_level_arrays_match_fas_oracle(d, L, fused):
+    """u_l (injection), b_l (FAS rhs with tau), b~_l, r_l and S_l of the second cycle."""
+    from paper_1903_10367_amd import Solver
+    f = inp.rhs(d, L, seed=10)
+    say("case level arrays", d, L, fused)
+    s = Solver(d, 1, L, f, fused=fused)
+    s.cycle(2)
+    got = {(l, w): s.level(l, w) for l in range(1, L) for w in ("u", "b", "btilde", "r", "S")}
+    s.close()
+    H = hierarchy.Hierarchy(d, L, 1)
+    b = H.rhs(f)
+    u1, _ = cycle.cycle_fas(H, np.zeros_like(b), b)
+    tr = {}
+    cycle.cycle_fas(H, u1, b, trace=tr)
+    for (l, w), g in got.items():
+        ref = tr[w][l]
+        scale = np.abs(ref).max()
+        assert np.abs(g - ref).max() <= 1e-12 * scale, f"level {l} {w}"
+
+
+def test_full_size_3d_poisson_l5():
+    """The benchmark workload itself (243^3 cells), three cycles, in the benchmark's launch shape."""
+    w = inp.workload_3d_poisson_l5()
+    say("case 3d poisson L=5 full size")
+    hg, ug = gpu_run(3, 5, w["f"], cycles=3)
+    say("oracle 3d L=5")
+    ho, uo = oracle_run(3, 5, w["f"], cycles=3)
+    assert_parity(hg, ug, ho, uo)
+
+
+def test_repeat_runs_are_bitwise_identical():
+    f = inp.rhs(3, 4, seed=11)
+    say("case determinism")
+    h1, u1 = gpu_run(3, 4, f, cycles=4)
+    h2, u2 = gpu_run(3, 4, f, cycles=4)
+    assert h1 == h2
+    assert np.array_equal(u1, u2)
+
+
+@pytest.mark.parametrize("d,L,lmin", [(2, 2, 2), (2, 3, 2), (3, 2, 1), (2, 6, 1)])
+def test_edge_sizes(d, L, lmin):
+    """One level (damped Jacobi), two levels, a level too small for the single-pass sweep,
+    and a 2D level spanning many tiles."""
+    from paper_1903_10367_amd import Solver
+    f = inp.rhs(d, L, seed=12)
+    say("case edge", d, L, lmin)
+    s = Solver(d, lmin, L, f)
+    s.cycle(5)
+    hg, ug = s.residuals(), s.solution()
+    s.close()
+    H = hierarchy.Hierarchy(d, L, lmin)
+    uo, ho = cycle.solve(H, H.rhs(f), 5)
+    assert_parity(hg, ug, ho, uo)
+
+
+def test_solve_to_tolerance_matches_oracle():
+    from paper_1903_10367_amd import Solver
+    f = inp.rhs(3, 4, seed=13, dist="normal")
+    say("case solve 1e-8")
+    s = Solver(3, 1, 4, f)
+    n = s.solve(1e-8, 100)
+    hg, ug = s.residuals(), s.solution()
+    s.close()
+    H = hierarchy.Hierarchy(3, 4, 1)
+    uo, ho = cycle.solve(H, H.rhs(f), 100, tol=1e-8)
+    assert n == len(ho) and hg[-1][0] / hg[0][0] <= 1e-8
+    assert_parity(hg, ug, ho, uo)
+
+
+def test_divergence_is_reported():
+    from paper_1903_10367_amd import AdafacError, Solver
+    f = inp.rhs(2, 3, seed=14)
+    say("case divergence")
+    s = Solver(2, 1, 3, f, omega=1.5)
+    with pytest.raises(AdafacError) as e:
+        s.solve(1e-8, 200)
+    assert e.value.code == 5
+    s.close()
