@@ -1,0 +1,130 @@
+"""Benchmark of the adAFAC-Jac cycle on one MI355X.
+
+Workload: 3D Poisson on the unit cube, uniform spacetree with 243^3 finest cells (levels
+1..5, 14,702,584 dofs per cycle over all levels), f ~ N(0, 1) from seed 0, FP64, d-linear
+transfers, adAFAC-Jac with omega = omega~ = 0.6.  One step = one additive cycle over all
+levels (fine sweep, coarse FAS levels, prolongation, residual norms).  The value is
+vertex-updates/s = dofs per cycle x cycles / wall time, inputs resident in HBM.
+
+Prints one JSON line.  With --gpus N > 1 it exits: this build runs on one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "fine_sweep3d_poisson_l5_traffic.json")
+
+
+def fine_sweep_bytes(d, L):
+    """Algorithmic bytes of one fused fine sweep: per fine dof u read + u write + b read
+    (24 B); per dof of level L-1 S read and u, R r, R~ r written (32 B)."""
+    nf = (3 ** L - 1) ** d
+    nc = (3 ** (L - 1) - 1) ** d
+    return 24 * nf + 32 * nc
+
+
+def cpu_baseline(d, L, f, cycles, dofs):
+    """The FP64 oracle (numpy/scipy, single-threaded ops) on the same workload, `cycles` cycles."""
+    import numpy as np
+    from oracle import cycle, hierarchy
+    H = hierarchy.Hierarchy(d, L, 1)
+    b = H.rhs(f)
+    u = np.zeros_like(b)
+    t0 = time.perf_counter()
+    for _ in range(cycles):
+        u, _ = cycle.cycle_correction(H, u, b)
+    dt = time.perf_counter() - t0
+    return {"value": dofs * cycles / dt, "unit": "vertex-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{cycles} full cycles of the same 243^3 workload (operator setup excluded), "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-cycles", type=int, default=2)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU sharding is a design note, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import adafac_inputs as inp
+    from paper_1903_10367_amd import Solver
+
+    w = inp.workload_3d_poisson_l5(seed=0)
+    d, L = w["d"], w["L"]
+    s = Solver(d, 1, L, w["f"], device="cuda:0")
+    dofs = s.dofs_per_cycle()
+    s.cycle(args.warmup)
+    torch.cuda.synchronize()
+    s.set_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.cycle(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ksum_ms, nlaunch = s.kernel_time()
+    s.set_kernel_timing(False)
+    hist = s.residuals()
+    s.close()
+
+    value = dofs * args.steps / dt
+    kavg_s = ksum_ms / 1e3 / max(nlaunch, 1)
+    kbytes = fine_sweep_bytes(d, L)
+    achieved = kbytes / kavg_s / 1e9
+    traffic = None
+    if os.path.exists(PROFILE_TRAFFIC):
+        with open(PROFILE_TRAFFIC) as fh:
+            traffic = json.load(fh).get("bytes_per_launch")
+
+    # solve to 1e-8 in FP64 (context: cycles and time to the paper's stopping criterion)
+    s = Solver(d, 1, L, w["f"], device="cuda:0")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ncyc = s.solve(1e-8, 200)
+    torch.cuda.synchronize()
+    tsolve = time.perf_counter() - t1
+    hs = s.residuals()
+    s.close()
+
+    out = {
+        "metric": "vertex-updates/s & %HBM peak per cycle",
+        "value": value,
+        "unit": "vertex-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3d-poisson-243^3-adafac-jac-fp64", "levels": "1..5",
+                   "dofs_per_cycle": dofs, "omega": 0.6, "omega_tilde": 0.6, "transfer": "d-linear",
+                   "rhs": "N(0,1) seed 0"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_fine_sweep3d", "kernel_avg_us": kavg_s * 1e6,
+                     "algorithmic_bytes_per_launch": kbytes, "launches": nlaunch},
+        "solve_fp64_to_1e-8": {"cycles": ncyc, "ms": tsolve * 1e3,
+                               "last_checked_rel_residual": hs[-1][0] / hs[0][0]},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(d, L, w["f"], args.cpu_cycles, dofs)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -152,7 +152,10 @@ class Hierarchy:
     """All operators of an adAFAC solve on a uniform grid, levels lmin..L."""
 
     def __init__(self, d, L, lmin=1, eps_blocks=None, transfer_kind="dlinear",
-                 rtilde="const", omega=0.6, assemble_limit=2_000_000):
+                 rtilde="const", omega=0.6, assemble_limit=2_000_000, boxmg_inside_blocks=True):
+        """``boxmg_inside_blocks=False`` takes the d-linear transfer for BoxMG wherever every
+        coarse cell lies inside one coefficient block, where the two coincide (pinned by
+        the tests); it only saves the slow per-cell solves on large levels."""
         assert d in (2, 3) and 1 <= lmin <= L
         assert transfer_kind in ("dlinear", "boxmg") and rtilde in ("const", "operator")
         if eps_blocks is None:
@@ -200,7 +203,7 @@ class Hierarchy:
                 lv.P = Op(fn=Pf, fnT=PTf)
                 Ac = fem.assemble(fem.cell_eps_from_blocks(eps_blocks, l - 1))
             else:
-                if transfer_kind == "dlinear":
+                if transfer_kind == "dlinear" or (not boxmg_inside_blocks and l - 1 >= k):
                     P = transfer.dlinear_prolongation(d, l)
                 else:
                     P = transfer.boxmg_prolongation(lv.A.mat, d, l)

@@ -31,6 +31,11 @@ struct HostOps {
   std::vector<double> eps;         // nb^d
   std::vector<HostLevel> lev;      // indexed by level (0..L)
   std::vector<double> rtilde;      // 5^d weights of R~ (already times omega), offset index as st
+  // R~ = scale * sum_a delta(o_a) prod_{b != a} m(o_b): the eps = 1 operator is a sum of tensor
+  // products (1D stiffness x 1D masses) and the 1D stiffness annihilates the 1D hat except at
+  // its centre, so R~ splits into d planar tensor-product stencils (checked against rtilde).
+  double rt_m[5] = {0, 0, 0, 0, 0};
+  double rt_scale = 0;
 };
 
 // Builds every operator of the hierarchy (FEM fine levels, BoxMG or d-linear
@@ -64,6 +69,13 @@ struct LevelView {
   T* r;                      // level residual
   T* S;                      // accumulated correction
   T* ic;                     // adAFAC-PI: injected correction of the next finer level
+};
+
+// Tensor-product factors of R~ handed to the kernels.
+template <typename T>
+struct RtSep {
+  T m[5];
+  T scale;
 };
 
 struct CycleParams {

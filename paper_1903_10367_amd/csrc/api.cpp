@@ -20,7 +20,7 @@ hipError_t launch_fine_residual(int d, const LevelView<T>& F, const T* uin, T* u
                                 hipStream_t s);
 template <typename T>
 hipError_t launch_level_update(int d, const LevelView<T>& C, const LevelView<T>& F, const LevelView<T>& Cm,
-                               const T* rt, T omega, T omega_t, T cscale, int damping, int gather,
+                               const RtSep<T>& rt, T omega, T omega_t, T cscale, int damping, int gather,
                                hipStream_t s);
 template <typename T>
 hipError_t launch_prolong_add(int d, const LevelView<T>& F, const LevelView<T>& C, T* dst, const T* src,
@@ -28,7 +28,7 @@ hipError_t launch_prolong_add(int d, const LevelView<T>& F, const LevelView<T>& 
 hipError_t launch_norm_finalize(const double* partials, int n, double* out, hipStream_t s);
 template <typename T>
 hipError_t launch_fine_sweep(int d, const LevelView<T>& F, const LevelView<T>& C, const T* uin, T* uout,
-                             const T* b, const T* rt, T omega, int damping, int apply_pending,
+                             const T* b, const RtSep<T>& rt, T omega, int damping, int apply_pending,
                              double* partials, int* nparts, hipStream_t s);
 size_t fine_sweep_partials(int d, int n);
 
@@ -63,6 +63,7 @@ struct adafac_ctx {
   size_t npartials = 0;
   double* norms = nullptr;
   double* rt = nullptr;
+  RtSep<double> rts64{};
   double* eps_dev = nullptr;
   int cur = 0;
   bool pending = false;     // fused path: P S_{L-1} of the last cycle not yet added to u
@@ -194,7 +195,7 @@ int run_cycle64(adafac_ctx* c) {
   const bool fused = o.fused && L > lmin && !pi && fused_ok(c);
   if (fused) {
     if ((rc = record_start(c))) return rc;
-    HIPCHK(c, launch_fine_sweep<double>(d, F, Lm1, uin, uout, c->bfine, c->rt, o.omega, damping,
+    HIPCHK(c, launch_fine_sweep<double>(d, F, Lm1, uin, uout, c->bfine, c->rts64, o.omega, damping,
                                         c->pending ? 1 : 0, c->partials, &nparts, c->stream));
     if ((rc = record_stop(c))) return rc;
   } else {
@@ -211,7 +212,7 @@ int run_cycle64(adafac_ctx* c) {
     if (l + 1 == L) { Fv.u = uin; Fv.r = c->rfine; }
     LevelView<double> Cm = l > lmin ? c->v64[l - 1] : LevelView<double>{};
     double cscale = damping == ADAFAC_DAMP_EXP ? std::pow(o.omega_hat, L - l) : 1.0;
-    HIPCHK(c, launch_level_update<double>(d, c->v64[l], Fv, Cm, c->rt, o.omega, o.omega_tilde, cscale,
+    HIPCHK(c, launch_level_update<double>(d, c->v64[l], Fv, Cm, c->rts64, o.omega, o.omega_tilde, cscale,
                                           damping, from_sweep ? 0 : 1, c->stream));
   }
   for (int l = lmin + 1; l < L; ++l)
@@ -322,6 +323,8 @@ int adafac_build_operators(adafac_ctx* c, const adafac_opts* opts) {
   c->ops.eps = c->eps;
   std::string m = build_host_ops(c->ops, o.transfer == ADAFAC_TRANSFER_BOXMG, o.omega);
   if (!m.empty()) return fail(c, ADAFAC_EINVAL, m);
+  for (int i = 0; i < 5; ++i) c->rts64.m[i] = c->ops.rt_m[i];
+  c->rts64.scale = c->ops.rt_scale;
   c->built = true;
   c->bound = false;
   c->ws_need = layout(c, nullptr);

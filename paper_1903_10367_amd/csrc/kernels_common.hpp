@@ -83,6 +83,48 @@ __device__ __forceinline__ T apply_level_op(const LevelView<T>& L, int x, int y,
   return s;
 }
 
+// A_l u at an interior vertex from its 3^d neighbourhood nb[(ox+1) + 3 (oy+1) + 9 (oz+1)]
+// (already in registers); same arithmetic as apply_level_op.
+template <typename T, int D>
+__device__ __forceinline__ T apply_level_op_nb(const LevelView<T>& L, int x, int y, int z, const T* nb, T& dg) {
+  auto U = [&](int dx, int dy, int dz) { return nb[(dx + 1) + 3 * (dy + 1) + (D == 3 ? 9 * (dz + 1) : 0)]; };
+  if (L.fem) {
+    const T u0 = U(0, 0, 0);
+    T s = T(0), es = T(0);
+    if (D == 2) {
+#pragma unroll
+      for (int sy = -1; sy <= 1; sy += 2)
+#pragma unroll
+        for (int sx = -1; sx <= 1; sx += 2) {
+          T e = eps_cell<T, D>(L, x + (sx < 0 ? -1 : 0), y + (sy < 0 ? -1 : 0), 0);
+          s += e * (T(2.0 / 3.0) * u0 - T(1.0 / 6.0) * (U(sx, 0, 0) + U(0, sy, 0)) - T(1.0 / 3.0) * U(sx, sy, 0));
+          es += e;
+        }
+      dg = T(2.0 / 3.0) * es;
+      return s;
+    }
+#pragma unroll
+    for (int sz = -1; sz <= 1; sz += 2)
+#pragma unroll
+      for (int sy = -1; sy <= 1; sy += 2)
+#pragma unroll
+        for (int sx = -1; sx <= 1; sx += 2) {
+          T e = eps_cell<T, D>(L, x + (sx < 0 ? -1 : 0), y + (sy < 0 ? -1 : 0), z + (sz < 0 ? -1 : 0));
+          s += e * (T(1.0 / 3.0) * u0 - T(1.0 / 12.0) * (U(sx, sy, 0) + U(sx, 0, sz) + U(0, sy, sz) + U(sx, sy, sz)));
+          es += e;
+        }
+    dg = L.h * T(1.0 / 3.0) * es;
+    return L.h * s;
+  }
+  const size_t i = lin<D>(x, y, z, L.nv);
+  const T* st = L.st + i * (D == 2 ? 9 : 27);
+  T s = T(0);
+#pragma unroll
+  for (int t = 0; t < (D == 2 ? 9 : 27); ++t) s += st[t] * nb[t];
+  dg = L.dg[i];
+  return s;
+}
+
 // P(f <- c) of the transfer from the next coarser level into level F (R = P^T).
 template <typename T, int D>
 __device__ __forceinline__ T restrict_weight(const LevelView<T>& F, int fx, int fy, int fz, int cx, int cy,
@@ -130,9 +172,9 @@ __device__ __forceinline__ T prolong_value(const LevelView<T>& F, const LevelVie
   return acc;
 }
 
-// Block-wide (256 threads) sum and max; thread 0 writes (sum, max) to partials[2*blockIdx.x].
+// Block-wide (up to 1024 threads) sum and max; thread 0 writes (sum, max) to partials[2*blockIdx.x].
 __device__ __forceinline__ void block_norm_partials(double ssum, double smax, double* partials) {
-  __shared__ double ws[8], wm[8];
+  __shared__ double ws[16], wm[16];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     ssum += __shfl_xor(ssum, off);

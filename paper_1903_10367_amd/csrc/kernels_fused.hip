@@ -17,9 +17,13 @@
 // u on a 31-wide ring: every coarse value is written by exactly one workgroup, without atomics,
 // and the result does not depend on scheduling.  3D tiles march through z with the current
 // u plane and the current residual plane in LDS; the 27-point stencil is split into the two
-// cell layers below and above a vertex, whose partial sums are carried in registers.
-// Workgroup ids are remapped so that consecutive tiles (which share halo planes) run on the
-// same XCD and hit the same L2.
+// cell layers below and above a vertex, whose partial sums are carried in registers, and the
+// global loads of the next plane are issued before the current plane is processed.  Both
+// restrictions are tensor products (R = P^T of d-linear P; R~ a sum of d planar products,
+// see the host setup) and are evaluated by an x pass over all rows and a y pass per coarse
+// column.  Workgroup ids are remapped so that consecutive tiles (which share halo planes)
+// run on the same XCD and hit the same L2.  adAFAC-PI reads and writes the injected fine
+// correction in the same pass and therefore runs on the one-kernel-per-step path.
 #include <hip/hip_runtime.h>
 
 #include "adafac.h"
@@ -34,8 +38,24 @@ constexpr int UW = TX + 4;        // u ring: x0-3 .. x0+27
 constexpr int RW = TX + 2;        // residual ring: x0-2 .. x0+26
 constexpr int CW = TX / 3 + 3;    // coarse S block: x0/3-1 .. x0/3+10
 constexpr int NCO = TX / 3;       // owned coarse vertices per axis
-constexpr int MAXTZ = 27;
-constexpr int NSLOT = (RW * RW + 255) / 256;
+constexpr int MAXTZ = 81;
+constexpr int NU = UW * UW;
+constexpr int NR = RW * RW;
+// workgroup size of the 3D sweep and the occupancy it is compiled for (waves per SIMD)
+#ifndef ADAFAC_SWEEP3D_THREADS
+#define ADAFAC_SWEEP3D_THREADS 1024
+#endif
+#ifndef ADAFAC_SWEEP3D_MINWAVES
+#define ADAFAC_SWEEP3D_MINWAVES 4
+#endif
+#ifndef ADAFAC_SWEEP3D_TZ
+#define ADAFAC_SWEEP3D_TZ 0      // 0: choose per level
+#endif
+constexpr int NT3 = ADAFAC_SWEEP3D_THREADS;
+constexpr int NUSLOT = (NU + 255) / 256;
+constexpr int NSLOT = (NR + 255) / 256;
+constexpr int NUSLOT3 = (NU + NT3 - 1) / NT3;
+constexpr int NSLOT3 = (NR + NT3 - 1) / NT3;
 
 __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
   // blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous range of tiles
@@ -59,180 +79,161 @@ __device__ __forceinline__ T eps_fine(const LevelView<T>& F, int cx, int cy, int
   return eps_cell<T, D>(F, cx, cy, cz);
 }
 
+// x pass of both tensor-product restrictions over the residual ring: for every row y and
+// owned coarse column, the d-linear weighted and the R~ mass-weighted sums along x.
+template <typename T, int NTH = 256>
+__device__ __forceinline__ void restrict_x_pass(const T* Rb, T* Xw, T* Xm, const RtSep<T>& rts, int tid) {
+  for (int t = tid; t < RW * NCO; t += NTH) {
+    const int y = t / NCO, ccx = t % NCO;
+    const T* rp = &Rb[y * RW + 3 * ccx + 2];
+    T sw = T(0), sm = T(0);
+#pragma unroll
+    for (int o = -2; o <= 2; ++o) {
+      sw += wlin<T>(o) * rp[o];
+      sm += rts.m[o + 2] * rp[o];
+    }
+    Xw[t] = sw;
+    Xm[t] = sm;
+  }
+}
+
 }  // namespace
 
-template <typename T, bool VAREPS>
-__global__ void __launch_bounds__(256) k_fine_sweep3d(LevelView<T> F, LevelView<T> C,
-                                                      const T* __restrict__ uin, T* __restrict__ uout,
-                                                      const T* __restrict__ b, const T* __restrict__ rt,
-                                                      T omega, int damping, int apply_pending, int tz,
-                                                      int ntx, int ntz, double* __restrict__ partials) {
-  __shared__ T Ub[UW * UW];
-  __shared__ T Rb[RW * RW];
-  __shared__ T Sb[(MAXTZ / 3 + 3) * CW * CW];
+// Arguments of the 3D sweep (only what it reads; passed in kernarg memory).
+template <typename T>
+struct Sweep3dArgs {
+  const T* uin;
+  T* uout;
+  const T* b;
+  const T* S;        // S_{L-1}
+  T* cu;             // u_{L-1} (injection)
+  T* crr;            // R r
+  T* cbt;            // R~ r
+  const T* eps;      // eps blocks (VAREPS)
+  double* partials;
+  T h, omega, hd;
+  RtSep<T> rts;
+  int n, nv, nc, nvc, nb, bs;
+  int tz, ntx, ntz, damping, apply_pending;
+};
 
-  const int nv = F.nv, n = F.n, nvc = C.nv, nc = C.n;
-  const int nblk = ntx * ntx * ntz;
+template <typename T, bool VAREPS>
+__global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_fine_sweep3d(Sweep3dArgs<T> a) {
+  static_assert(NT3 >= NU, "one thread per ring column");
+  // one barrier per plane: every per-plane buffer written in a step is read in the next one
+  __shared__ T Ub[2][NU];                // u planes, by plane parity
+  __shared__ T Rb[3][NR];                // residual planes, by plane index mod 3
+  __shared__ T Xw[2][RW * NCO];          // x passes, by plane parity
+  __shared__ T Xm[2][RW * NCO];
+  __shared__ T Sb[(MAXTZ / 3 + 3) * CW * CW];
+  __shared__ T Sz[2][CW * CW];           // S blended to a fine plane, by plane parity
+
+  const int n = a.n, nv = a.nv, nc = a.nc, nvc = a.nvc;
+  const int plane = nv * nv;
+  const int nblk = a.ntx * a.ntx * a.ntz;
   const int t = xcd_remap(blockIdx.x, nblk);
-  const int tzi = t % ntz, tyi = (t / ntz) % ntx, txi = t / (ntz * ntx);
+  // x/y tiles fastest: the tiles of one XCD share their x/y halos in its L2 at the same time
+  const int txi = t % a.ntx, tyi = (t / a.ntx) % a.ntx, tzi = t / (a.ntx * a.ntx);
+  const int tz = a.tz;
   const int x0 = TX * txi, y0 = TX * tyi, z0 = tz * tzi;
   const int cbx = x0 / 3 - 1, cby = y0 / 3 - 1, cbz = z0 / 3 - 1;
   const int nsz = tz / 3 + 3;
   const int tid = threadIdx.x;
-  const int pi = damping == ADAFAC_DAMP_PI;
-  const T h = F.h;
+  const bool jac = a.damping == ADAFAC_DAMP_JAC;
+  const bool pend = a.apply_pending != 0;
+  const T h = a.h;
 
-  // (a) coarse correction block S (minus the injected fine correction for adAFAC-PI)
-  if (apply_pending) {
-    for (int i = tid; i < nsz * CW * CW; i += 256) {
+  // (a) coarse correction block S
+  if (pend) {
+    for (int i = tid; i < nsz * CW * CW; i += NT3) {
       const int lx = i % CW, ly = (i / CW) % CW, lz = i / (CW * CW);
       const int cx = cbx + lx, cy = cby + ly, cz = cbz + lz;
       T v = T(0);
-      if (cx >= 0 && cx <= nc && cy >= 0 && cy <= nc && cz >= 0 && cz <= nc) {
-        const size_t ci = lin<3>(cx, cy, cz, nvc);
-        v = C.S[ci];
-        if (pi) v -= C.ic[ci];
-      }
+      if (cx >= 0 && cx <= nc && cy >= 0 && cy <= nc && cz >= 0 && cz <= nc) v = a.S[lin<3>(cx, cy, cz, nvc)];
       Sb[i] = v;
     }
   }
 
-  // per residual column: running sums of the two cell layers (see header)
-  T own[NSLOT], dsum[NSLOT], esum[NSLOT], tprev[NSLOT], dq[NSLOT][4], eq[NSLOT][4], epsprev[NSLOT];
-#pragma unroll
-  for (int s = 0; s < NSLOT; ++s) {
-    own[s] = dsum[s] = esum[s] = tprev[s] = epsprev[s] = T(0);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) dq[s][q] = eq[s][q] = T(0);
-  }
+  // this thread's u-ring column (loads are clamped into the lattice: values off the lattice
+  // only feed residuals of non-dof vertices, which are discarded)
+  const bool uact = tid < NU;
+  const int ui = uact ? tid : 0;
+  const int ux = x0 - 3 + ui % UW, uy = y0 - 3 + ui / UW;
+  const int uoff = min(max(ux, 0), n) + nv * min(max(uy, 0), n);
+  const int ucx = min(max(ux, 0), n) / 3, ucy = min(max(uy, 0), n) / 3;
+  const int usi = (ucy - cby) * CW + ucx - cbx;
+  const int usx = min(max(ux, 0), n) - 3 * ucx, usy = min(max(uy, 0), n) - 3 * ucy;
+  const T wx0 = T(3 - usx) * T(1.0 / 3.0), wx1 = T(usx) * T(1.0 / 3.0);
+  const T wy0 = T(3 - usy) * T(1.0 / 3.0), wy1 = T(usy) * T(1.0 / 3.0);
+  // this thread's residual column
+  const bool ract = tid < NR;
+  const int rj = ract ? tid : 0;
+  const int rx = rj % RW, ry = rj / RW;
+  const int x = x0 - 2 + rx, y = y0 - 2 + ry;
+  const bool rint = ract && x > 0 && x < n && y > 0 && y < n;
+  const bool rown = rint && rx >= 2 && ry >= 2 && x < x0 + TX && y < y0 + TX;
+  const bool rcc = x % 3 == 0 && y % 3 == 0;
+  const int roff = min(max(x, 0), n) + nv * min(max(y, 0), n);
+
+  // Carried per residual column (see header).  Poisson: u(z), D4(z) = sum of the four in-plane
+  // diagonal neighbours, F(z-1) and F(z) with F = 2 A4 + D4 (A4: the four in-plane axis
+  // neighbours); then A u(z) = h [8/3 u(z) - (2 D4(z) + F(z-1) + F(z+1)) / 12].  Variable eps:
+  // the contribution of the cell layer below, eps of that layer, and per quadrant the values the
+  // layer above needs.
+  T own = T(0), c1 = T(0), c2 = T(0), c3 = T(0), epsprev = T(0);
+  T dq[4] = {T(0), T(0), T(0), T(0)}, eq[4] = {T(0), T(0), T(0), T(0)};
+  // prefetch ring, three planes deep: slot k serves the steps p with (p - zs) % 3 == k
+  constexpr int PD = 3;
+  T pu[PD], pb[PD];
   T accR[2] = {T(0), T(0)}, accT[2] = {T(0), T(0)};
   double ssum = 0.0, smax = 0.0;
+  const T wdiag = a.omega / (h * T(8.0 / 3.0));     // omega / D for eps = 1
+
+  auto uload = [&](int p) { return a.uin[min(max(p, 0), n) * plane + uoff]; };
+  auto bload = [&](int z) { return a.b[min(max(z, 0), n) * plane + roff]; };
+  auto blend_s = [&](int p) {   // Sz = S interpolated along z to fine plane p
+    if (pend && tid < CW * CW && p >= 0 && p <= n) {
+      const int cz = p / 3, sz = p - 3 * cz;
+      const T* s0 = &Sb[(cz - cbz) * CW * CW + tid];
+      Sz[p & 1][tid] = T(3 - sz) * T(1.0 / 3.0) * s0[0] + T(sz) * T(1.0 / 3.0) * s0[CW * CW];
+    }
+  };
+  auto mod3 = [](int v) { return (v % 3 + 3) % 3; };
 
   const int zs = z0 - 3, ze = z0 + tz;
-  for (int p = zs; p <= ze; ++p) {
-    __syncthreads();  // previous plane fully consumed (Ub) and restricted (Rb), Sb ready
-    // load u plane p on the 31 x 31 ring, adding the pending prolongated correction
-    for (int i = tid; i < UW * UW; i += 256) {
-      const int ux = i % UW, uy = i / UW;
-      const int x = x0 - 3 + ux, y = y0 - 3 + uy;
-      T v = T(0);
-      if (x >= 0 && x <= n && y >= 0 && y <= n && p >= 0 && p <= n) {
-        v = uin[lin<3>(x, y, p, nv)];
-        if (apply_pending) {
-          const int cx = x / 3, cy = y / 3, cz = p / 3;
-          const int sx = x - 3 * cx, sy = y - 3 * cy, sz = p - 3 * cz;
-          const T wx[2] = {T(3 - sx) * T(1.0 / 3.0), T(sx) * T(1.0 / 3.0)};
-          const T wy[2] = {T(3 - sy) * T(1.0 / 3.0), T(sy) * T(1.0 / 3.0)};
-          const T wz[2] = {T(3 - sz) * T(1.0 / 3.0), T(sz) * T(1.0 / 3.0)};
-          const int lx = cx - cbx, ly = cy - cby, lz = cz - cbz;
-          T acc = T(0);
 #pragma unroll
-          for (int ez = 0; ez < 2; ++ez)
-#pragma unroll
-            for (int ey = 0; ey < 2; ++ey)
-#pragma unroll
-              for (int ex = 0; ex < 2; ++ex)
-                acc += wz[ez] * wy[ey] * wx[ex] * Sb[((lz + ez) * CW + ly + ey) * CW + lx + ex];
-          v += acc;
-        }
-      }
-      Ub[i] = v;
-    }
-    __syncthreads();
-    // residual of plane z = p - 1 on the 29 x 29 ring
-    const int z = p - 1;
-    const bool zres = p >= zs + 2;
-#pragma unroll
-    for (int s = 0; s < NSLOT; ++s) {
-      const int j = tid + 256 * s;
-      if (j >= RW * RW) continue;
-      const int rx = j % RW, ry = j / RW;
-      const int x = x0 - 2 + rx, y = y0 - 2 + ry;
-      const T* up = &Ub[(ry + 1) * UW + rx + 1];
-      const T o_n = up[0];
-      // quadrants q = (sx, sy): 0 = (-,-), 1 = (+,-), 2 = (-,+), 3 = (+,+)
-      const T ax_m = up[-1], ax_p = up[1], ay_m = up[-UW], ay_p = up[UW];
-      const T d_n[4] = {up[-UW - 1], up[-UW + 1], up[UW - 1], up[UW + 1]};
-      const T e_n[4] = {ax_m + ay_m + d_n[0], ax_p + ay_m + d_n[1], ax_m + ay_p + d_n[2], ax_p + ay_p + d_n[3]};
-      T bc, tn, esl;
-      if (!VAREPS) {
-        const T ds_n = (d_n[0] + d_n[1]) + (d_n[2] + d_n[3]);
-        const T es_n = (e_n[0] + e_n[1]) + (e_n[2] + e_n[3]);
-        bc = T(4.0 / 3.0) * own[s] - T(1.0 / 12.0) * (dsum[s] + es_n);
-        tn = T(4.0 / 3.0) * o_n - T(1.0 / 12.0) * (ds_n + esum[s]);
-        esl = T(4);
-        dsum[s] = ds_n;
-        esum[s] = es_n;
-      } else {
-        // eps of the four cells of layer z (between planes z and z+1) around column (x, y)
-        const T e4[4] = {eps_fine<T, 3>(F, x - 1, y - 1, z), eps_fine<T, 3>(F, x, y - 1, z),
-                         eps_fine<T, 3>(F, x - 1, y, z), eps_fine<T, 3>(F, x, y, z)};
-        bc = T(0);
-        tn = T(0);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          bc += e4[q] * (T(1.0 / 3.0) * own[s] - T(1.0 / 12.0) * (dq[s][q] + e_n[q]));
-          tn += e4[q] * (T(1.0 / 3.0) * o_n - T(1.0 / 12.0) * (d_n[q] + eq[s][q]));
-        }
-        esl = (e4[0] + e4[1]) + (e4[2] + e4[3]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          dq[s][q] = d_n[q];
-          eq[s][q] = e_n[q];
-        }
-      }
-      T res = T(0);
-      if (zres && x > 0 && x < n && y > 0 && y < n && z > 0 && z < n) {
-        const T au = h * (bc + tprev[s]);
-        const T dg = h * T(1.0 / 3.0) * (esl + epsprev[s]);
-        const T uz = own[s];
-        res = b[lin<3>(x, y, z, nv)] - au;
-        const bool owned = rx >= 2 && ry >= 2 && x < x0 + TX && y < y0 + TX && z >= z0 && z < z0 + tz;
-        if (owned) {
-          const T c = omega * res / dg;
-          uout[lin<3>(x, y, z, nv)] = uz + c;
-          const double rd = double(res);
-          ssum += double(F.hd) * rd * rd;
-          smax = fmax(smax, fabs(rd));
-          if (x % 3 == 0 && y % 3 == 0 && z % 3 == 0) {
-            const size_t ci = lin<3>(x / 3, y / 3, z / 3, nvc);
-            C.u[ci] = uz;                    // FAS injection of iterate n
-            if (pi) C.ic[ci] = c;            // adAFAC-PI: injected fine correction
-          }
-        }
-      }
-      Rb[j] = res;
-      tprev[s] = tn;
-      epsprev[s] = esl;
-      own[s] = o_n;
-    }
-    __syncthreads();
-    if (!zres) continue;
-    // restriction of plane z to the owned coarse columns: R r and R~ r (5 x 5 in-plane gathers)
+  for (int q = 0; q < PD; ++q) {
+    pu[q] = uload(zs + q);
+    pb[q] = bload(zs + q - 1);
+  }
+  __syncthreads();  // Sb ready
+  blend_s(zs);
+  __syncthreads();  // Sz[zs & 1] ready
+
+  // y pass of residual plane zr (its x pass done): R r and R~ r accumulated per coarse plane
+  auto y_pass = [&](int zr) {
     if (tid < NCO * NCO) {
+      const T* xw = Xw[zr & 1];
+      const T* xm = Xm[zr & 1];
+      const T* rz = Rb[mod3(zr)];
       const int ccx = tid % NCO, ccy = tid / NCO;
-      const T* rc = &Rb[(3 * ccy + 2) * RW + 3 * ccx + 2];
-      const int lo = z >= 0 ? z / 3 : -1;   // z >= z0 - 2 >= -2; only z < 0 at the lower boundary
-      const int m = z - 3 * lo;             // 0, 1, 2 (offset from coarse plane lo)
-      T sR = T(0), sT0 = T(0), sT1 = T(0);
-      // R~ in-plane pattern for |oz| = m (coarse plane lo) and |oz| = 3 - m (plane lo + 1)
-      const int pa = 2 + m, pb = 2 + (3 - m);   // index into rt's z offset (+|oz| side)
+      T W = T(0), Q = T(0), Y = T(0);
 #pragma unroll
-      for (int oy = -2; oy <= 2; ++oy)
-#pragma unroll
-        for (int ox = -2; ox <= 2; ++ox) {
-          const T rv = rc[oy * RW + ox];
-          sR += wlin<T>(ox) * wlin<T>(oy) * rv;
-          if (damping == ADAFAC_DAMP_JAC) {
-            sT0 += rt[(ox + 2) + 5 * (oy + 2) + 25 * pa] * rv;
-            if (m) sT1 += rt[(ox + 2) + 5 * (oy + 2) + 25 * (pb < 5 ? pb : 0)] * rv;
-          }
-        }
-      accR[0] += wlin<T>(m) * sR;
-      accT[0] += sT0;
+      for (int o = -2; o <= 2; ++o) {
+        const int row = 3 * ccy + 2 + o;
+        W += wlin<T>(o) * xw[row * NCO + ccx];
+        Q += a.rts.m[o + 2] * xm[row * NCO + ccx];
+        Y += a.rts.m[o + 2] * rz[row * RW + 3 * ccx + 2];
+      }
+      const T X = xm[(3 * ccy + 2) * NCO + ccx];
+      const int lo = zr >= 0 ? zr / 3 : -1;   // coarse plane at or below zr (zr >= -2)
+      const int m = zr - 3 * lo;              // 0, 1, 2
+      // R~: planar tensor products; the plane through the coarse vertex also carries Q
+      accR[0] += wlin<T>(m) * W;
+      if (jac) accT[0] += a.rts.scale * (a.rts.m[2 + m] * (X + Y) + (m == 0 ? Q : T(0)));
       if (m) {
-        accR[1] += wlin<T>(3 - m) * sR;
-        accT[1] += sT1;
+        accR[1] += wlin<T>(3 - m) * W;
+        if (jac) accT[1] += a.rts.scale * a.rts.m[2 + 3 - m] * (X + Y);
       }
       if (m == 2) {
         const int cz = lo;
@@ -240,26 +241,121 @@ __global__ void __launch_bounds__(256) k_fine_sweep3d(LevelView<T> F, LevelView<
         if (cz >= z0 / 3 && cz < (z0 + tz) / 3 && cx > 0 && cx < nc && cy > 0 && cy < nc && cz > 0 &&
             cz < nc) {
           const size_t ci = lin<3>(cx, cy, cz, nvc);
-          C.rr[ci] = accR[0];
-          C.bt[ci] = accT[0];
+          a.crr[ci] = accR[0];
+          a.cbt[ci] = accT[0];
         }
         accR[0] = accR[1];
         accT[0] = accT[1];
         accR[1] = accT[1] = T(0);
       }
     }
+  };
+
+  // the residual of plane p-1 needs u planes p-2, p-1, p (the carried sums hold p-2 and p-1)
+  auto residual = [&](int p, int k) {
+    const int z = p - 1;
+    const T* up = &Ub[p & 1][(ry + 1) * UW + rx + 1];
+    const T o_n = up[0];
+    const T ax_m = up[-1], ax_p = up[1], ay_m = up[-UW], ay_p = up[UW];
+    const T d_0 = up[-UW - 1], d_1 = up[-UW + 1], d_2 = up[UW - 1], d_3 = up[UW + 1];
+    T au, dinv;
+    const T uz = own;
+    if constexpr (!VAREPS) {
+      const T d4 = (d_0 + d_1) + (d_2 + d_3);
+      const T f = T(2) * ((ax_m + ax_p) + (ay_m + ay_p)) + d4;
+      // c1 = D4(z), c2 = F(z-1), c3 = F(z) for z = p-1; the new plane p brings F(z+1) = f
+      au = h * (T(8.0 / 3.0) * uz - T(1.0 / 12.0) * ((T(2) * c1 + c2) + f));
+      dinv = wdiag;
+      c1 = d4;
+      c2 = c3;
+      c3 = f;
+    } else {
+      // quadrants q = (sx, sy): 0 = (-,-), 1 = (+,-), 2 = (-,+), 3 = (+,+)
+      const T d_n[4] = {d_0, d_1, d_2, d_3};
+      const T e_n[4] = {ax_m + ay_m + d_0, ax_p + ay_m + d_1, ax_m + ay_p + d_2, ax_p + ay_p + d_3};
+      // eps of the four cells of layer z (between planes z and z+1) around the column
+      const int bx0 = min(max(x - 1, 0), n - 1) / a.bs, bx1 = min(max(x, 0), n - 1) / a.bs;
+      const int by0 = min(max(y - 1, 0), n - 1) / a.bs, by1 = min(max(y, 0), n - 1) / a.bs;
+      const int bz = min(max(z, 0), n - 1) / a.bs;
+      const T* eb = a.eps + size_t(bz) * a.nb * a.nb;
+      const T e4[4] = {eb[by0 * a.nb + bx0], eb[by0 * a.nb + bx1], eb[by1 * a.nb + bx0], eb[by1 * a.nb + bx1]};
+      T bc = T(0), tn = T(0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        bc += e4[q] * (T(1.0 / 3.0) * uz - T(1.0 / 12.0) * (dq[q] + e_n[q]));
+        tn += e4[q] * (T(1.0 / 3.0) * o_n - T(1.0 / 12.0) * (d_n[q] + eq[q]));
+      }
+      const T esl = (e4[0] + e4[1]) + (e4[2] + e4[3]);
+      au = h * (bc + c1);
+      dinv = a.omega / (h * T(1.0 / 3.0) * (esl + epsprev));
+      c1 = tn;
+      epsprev = esl;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        dq[q] = d_n[q];
+        eq[q] = e_n[q];
+      }
+    }
+    own = o_n;
+    T res = T(0);
+    if (p >= zs + 2 && rint && z > 0 && z < n) {
+      res = pb[k] - au;
+      if (rown && z >= z0 && z < z0 + tz) {
+        __builtin_nontemporal_store(uz + dinv * res, &a.uout[z * plane + roff]);
+        const double rd = double(res);
+        ssum += rd * rd;
+        smax = fabs(rd) > smax ? fabs(rd) : smax;
+        if (rcc && z % 3 == 0) a.cu[lin<3>(x / 3, y / 3, z / 3, nvc)] = uz;   // FAS injection of iterate n
+      }
+    }
+    if (ract) Rb[mod3(z)][tid] = res;
+  };
+
+  auto ubuild = [&](int p, int k) {   // u plane p (ring slot k) plus the pending correction
+    T v = pu[k];
+    if (pend) {
+      const T* s0 = &Sz[p & 1][usi];
+      v += wy0 * (wx0 * s0[0] + wx1 * s0[1]) + wy1 * (wx0 * s0[CW] + wx1 * s0[CW + 1]);
+    }
+    if (uact) Ub[p & 1][tid] = v;
+  };
+
+  // Step p (one barrier): u plane p into LDS; residual of plane p-2 (u planes p-3..p-1 are in
+  // LDS or registers); x pass of plane p-3; y pass of plane p-4; S blended for plane p+1.
+  // Ring slot k = (p - zs) mod PD holds u(p) and b(p-2) and is refilled with u(p+PD), b(p+PD-2).
+  auto step = [&](int p, int k) {
+    // the refills are unconditional (planes clamped to the chunk) so that the compiler can
+    // count the loads in flight and wait only for the oldest one
+    if (p <= ze) ubuild(p, k);
+    pu[k] = uload(min(p + PD, ze));
+    const int kr = (k + PD - 1) % PD;          // slot that held u(p-1): it carries b(p-2)
+    if (p - 1 >= zs && p - 1 <= ze) residual(p - 1, kr);
+    pb[kr] = bload(min(p - 1 + PD - 1, ze));
+    if (p - 3 >= zs + 1 && p - 3 <= ze - 1) restrict_x_pass<T, NT3>(Rb[mod3(p - 3)], Xw[(p - 3) & 1], Xm[(p - 3) & 1], a.rts, tid);
+    if (p - 4 >= zs + 1 && p - 4 <= ze - 1) y_pass(p - 4);
+    if (p + 1 <= ze) blend_s(p + 1);
+    __syncthreads();
+  };
+
+  // steps zs .. ze+4 drain the pipeline (residuals end at plane ze-1, restriction two steps later)
+  for (int p = zs; p <= ze + 3; p += PD) {
+    step(p, 0);
+    step(p + 1, 1);
+    step(p + 2, 2);
   }
-  block_norm_partials(ssum, smax, partials);
+  block_norm_partials(double(a.hd) * ssum, smax, a.partials);
 }
 
 template <typename T, bool VAREPS>
 __global__ void __launch_bounds__(256) k_fine_sweep2d(LevelView<T> F, LevelView<T> C,
                                                       const T* __restrict__ uin, T* __restrict__ uout,
-                                                      const T* __restrict__ b, const T* __restrict__ rt,
-                                                      T omega, int damping, int apply_pending, int ntx,
+                                                      const T* __restrict__ b, RtSep<T> rts, T omega,
+                                                      int damping, int apply_pending, int ntx,
                                                       double* __restrict__ partials) {
-  __shared__ T Ub[UW * UW];
-  __shared__ T Rb[RW * RW];
+  __shared__ T Ub[NU];
+  __shared__ T Rb[NR];
+  __shared__ T Xw[RW * NCO];
+  __shared__ T Xm[RW * NCO];
   __shared__ T Sb[CW * CW];
   const int nv = F.nv, n = F.n, nvc = C.nv, nc = C.n;
   const int t = xcd_remap(blockIdx.x, ntx * ntx);
@@ -267,39 +363,47 @@ __global__ void __launch_bounds__(256) k_fine_sweep2d(LevelView<T> F, LevelView<
   const int x0 = TX * txi, y0 = TX * tyi;
   const int cbx = x0 / 3 - 1, cby = y0 / 3 - 1;
   const int tid = threadIdx.x;
-  const int pi = damping == ADAFAC_DAMP_PI;
+  const bool jac = damping == ADAFAC_DAMP_JAC;
+  // global loads first; the coarse block and the ring values are combined after one barrier
+  T pu[NUSLOT];
+#pragma unroll
+  for (int k = 0; k < NUSLOT; ++k) {
+    const int i = tid + 256 * k;
+    const int x = x0 - 3 + i % UW, y = y0 - 3 + i / UW;
+    pu[k] = (i < NU && x >= 0 && x <= n && y >= 0 && y <= n) ? uin[lin<2>(x, y, 0, nv)] : T(0);
+  }
   if (apply_pending) {
     for (int i = tid; i < CW * CW; i += 256) {
       const int cx = cbx + i % CW, cy = cby + i / CW;
       T v = T(0);
       if (cx >= 0 && cx <= nc && cy >= 0 && cy <= nc) {
-        const size_t ci = lin<2>(cx, cy, 0, nvc);
-        v = C.S[ci];
-        if (pi) v -= C.ic[ci];
+        v = C.S[lin<2>(cx, cy, 0, nvc)];
       }
       Sb[i] = v;
     }
     __syncthreads();
   }
-  for (int i = tid; i < UW * UW; i += 256) {
+#pragma unroll
+  for (int k = 0; k < NUSLOT; ++k) {
+    const int i = tid + 256 * k;
+    if (i >= NU) continue;
     const int x = x0 - 3 + i % UW, y = y0 - 3 + i / UW;
-    T v = T(0);
-    if (x >= 0 && x <= n && y >= 0 && y <= n) {
-      v = uin[lin<2>(x, y, 0, nv)];
-      if (apply_pending) {
-        const int cx = x / 3, cy = y / 3, sx = x - 3 * cx, sy = y - 3 * cy;
-        const int lx = cx - cbx, ly = cy - cby;
-        const T wx0 = T(3 - sx) * T(1.0 / 3.0), wx1 = T(sx) * T(1.0 / 3.0);
-        const T wy0 = T(3 - sy) * T(1.0 / 3.0), wy1 = T(sy) * T(1.0 / 3.0);
-        v += wy0 * (wx0 * Sb[ly * CW + lx] + wx1 * Sb[ly * CW + lx + 1]) +
-             wy1 * (wx0 * Sb[(ly + 1) * CW + lx] + wx1 * Sb[(ly + 1) * CW + lx + 1]);
-      }
+    T v = pu[k];
+    if (apply_pending && x >= 0 && x <= n && y >= 0 && y <= n) {
+      const int cx = x / 3, cy = y / 3, sx = x - 3 * cx, sy = y - 3 * cy;
+      const T* s0 = &Sb[(cy - cby) * CW + cx - cbx];
+      const T wx0 = T(3 - sx) * T(1.0 / 3.0), wx1 = T(sx) * T(1.0 / 3.0);
+      const T wy0 = T(3 - sy) * T(1.0 / 3.0), wy1 = T(sy) * T(1.0 / 3.0);
+      v += wy0 * (wx0 * s0[0] + wx1 * s0[1]) + wy1 * (wx0 * s0[CW] + wx1 * s0[CW + 1]);
     }
     Ub[i] = v;
   }
   __syncthreads();
   double ssum = 0.0, smax = 0.0;
-  for (int j = tid; j < RW * RW; j += 256) {
+#pragma unroll
+  for (int s = 0; s < NSLOT; ++s) {
+    const int j = tid + 256 * s;
+    if (j >= NR) continue;
     const int rx = j % RW, ry = j / RW;
     const int x = x0 - 2 + rx, y = y0 - 2 + ry;
     T res = T(0);
@@ -331,32 +435,30 @@ __global__ void __launch_bounds__(256) k_fine_sweep2d(LevelView<T> F, LevelView<
         ssum += double(F.hd) * rd * rd;
         smax = fmax(smax, fabs(rd));
         if (x % 3 == 0 && y % 3 == 0) {
-          const size_t ci = lin<2>(x / 3, y / 3, 0, nvc);
-          C.u[ci] = u0;
-          if (pi) C.ic[ci] = c;
+          C.u[lin<2>(x / 3, y / 3, 0, nvc)] = u0;
         }
       }
     }
     Rb[j] = res;
   }
   __syncthreads();
+  restrict_x_pass<T>(Rb, Xw, Xm, rts, tid);
+  __syncthreads();
   if (tid < NCO * NCO) {
     const int ccx = tid % NCO, ccy = tid / NCO;
     const int cx = x0 / 3 + ccx, cy = y0 / 3 + ccy;
     if (cx > 0 && cx < nc && cy > 0 && cy < nc) {
-      const T* rc = &Rb[(3 * ccy + 2) * RW + 3 * ccx + 2];
-      T sR = T(0), sT = T(0);
+      T W = T(0), Y = T(0);
 #pragma unroll
-      for (int oy = -2; oy <= 2; ++oy)
-#pragma unroll
-        for (int ox = -2; ox <= 2; ++ox) {
-          const T rv = rc[oy * RW + ox];
-          sR += wlin<T>(ox) * wlin<T>(oy) * rv;
-          if (damping == ADAFAC_DAMP_JAC) sT += rt[(ox + 2) + 5 * (oy + 2)] * rv;
-        }
+      for (int o = -2; o <= 2; ++o) {
+        const int row = 3 * ccy + 2 + o;
+        W += wlin<T>(o) * Xw[row * NCO + ccx];
+        Y += rts.m[o + 2] * Rb[row * RW + 3 * ccx + 2];
+      }
+      const T X = Xm[(3 * ccy + 2) * NCO + ccx];
       const size_t ci = lin<2>(cx, cy, 0, nvc);
-      C.rr[ci] = sR;
-      C.bt[ci] = sT;
+      C.rr[ci] = W;
+      C.bt[ci] = jac ? rts.scale * (X + Y) : T(0);
     }
   }
   block_norm_partials(ssum, smax, partials);
@@ -371,17 +473,19 @@ size_t fine_sweep_partials(int d, int n) {
 }
 
 static int pick_tz(int n) {
-  // longest z chunk (multiple of 3, <= 27, dividing n) that still gives >= 512 workgroups
+  // longest z chunk (multiple of 3 dividing n, <= MAXTZ) that still gives one workgroup per CU
+  // of the 256 (fewer, longer chunks re-read fewer halo planes)
   const int ntx = n / TX;
+  if (ADAFAC_SWEEP3D_TZ > 0 && n % ADAFAC_SWEEP3D_TZ == 0) return ADAFAC_SWEEP3D_TZ;
   int best = 3;
   for (int tz = 3; tz <= MAXTZ; tz *= 3)
-    if (n % tz == 0 && size_t(ntx) * ntx * (n / tz) >= 512) best = tz;
+    if (n % tz == 0 && size_t(ntx) * ntx * (n / tz) >= 240) best = tz;
   return best;
 }
 
 template <typename T>
 hipError_t launch_fine_sweep(int d, const LevelView<T>& F, const LevelView<T>& C, const T* uin, T* uout,
-                             const T* b, const T* rt, T omega, int damping, int apply_pending,
+                             const T* b, const RtSep<T>& rts, T omega, int damping, int apply_pending,
                              double* partials, int* nparts, hipStream_t s) {
   const int n = F.n;
   if (n % TX || F.pw) return hipErrorInvalidValue;   // needs 27 | n and d-linear transfer into L
@@ -390,27 +494,29 @@ hipError_t launch_fine_sweep(int d, const LevelView<T>& F, const LevelView<T>& C
   if (d == 2) {
     const unsigned nb = unsigned(ntx * ntx);
     if (var)
-      k_fine_sweep2d<T, true><<<nb, 256, 0, s>>>(F, C, uin, uout, b, rt, omega, damping, apply_pending, ntx, partials);
+      k_fine_sweep2d<T, true><<<nb, 256, 0, s>>>(F, C, uin, uout, b, rts, omega, damping, apply_pending, ntx, partials);
     else
-      k_fine_sweep2d<T, false><<<nb, 256, 0, s>>>(F, C, uin, uout, b, rt, omega, damping, apply_pending, ntx, partials);
+      k_fine_sweep2d<T, false><<<nb, 256, 0, s>>>(F, C, uin, uout, b, rts, omega, damping, apply_pending, ntx, partials);
     *nparts = int(nb);
   } else {
     const int tz = pick_tz(n), ntz = n / tz;
     const unsigned nb = unsigned(ntx * ntx * ntz);
+    Sweep3dArgs<T> a{uin, uout, b, C.S, C.u, C.rr, C.bt, F.eps, partials, F.h, omega, F.hd, rts,
+                     n, F.nv, C.n, C.nv, F.nb, F.bs, tz, ntx, ntz, damping, apply_pending};
     if (var)
-      k_fine_sweep3d<T, true><<<nb, 256, 0, s>>>(F, C, uin, uout, b, rt, omega, damping, apply_pending, tz, ntx, ntz, partials);
+      k_fine_sweep3d<T, true><<<nb, NT3, 0, s>>>(a);
     else
-      k_fine_sweep3d<T, false><<<nb, 256, 0, s>>>(F, C, uin, uout, b, rt, omega, damping, apply_pending, tz, ntx, ntz, partials);
+      k_fine_sweep3d<T, false><<<nb, NT3, 0, s>>>(a);
     *nparts = int(nb);
   }
   return hipGetLastError();
 }
 
 template hipError_t launch_fine_sweep<double>(int, const LevelView<double>&, const LevelView<double>&,
-                                              const double*, double*, const double*, const double*, double,
-                                              int, int, double*, int*, hipStream_t);
+                                              const double*, double*, const double*, const RtSep<double>&,
+                                              double, int, int, double*, int*, hipStream_t);
 template hipError_t launch_fine_sweep<float>(int, const LevelView<float>&, const LevelView<float>&,
-                                             const float*, float*, const float*, const float*, float, int,
-                                             int, double*, int*, hipStream_t);
+                                             const float*, float*, const float*, const RtSep<float>&, float,
+                                             int, int, double*, int*, hipStream_t);
 
 }  // namespace adafac

@@ -408,6 +408,30 @@ std::string build_host_ops(HostOps& ops, int transfer_boxmg, double omega) {
       }
       ops.rtilde[t] = omega * s / diag;
     }
+    // tensor-product factors: m = (1D mass stencil) * (1D hat), kc = (1D stiffness * hat)(0)
+    double mass1[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0}, stiff1[3] = {-1.0, 2.0, -1.0};
+    auto hat1 = [](int q) { q = std::abs(q); return q >= 3 ? 0.0 : 1.0 - q / 3.0; };
+    for (int o = -2; o <= 2; ++o) {
+      double mm = 0.0;
+      for (int j = -1; j <= 1; ++j) mm += mass1[j + 1] * hat1(o + j);
+      ops.rt_m[o + 2] = mm;
+    }
+    double kc = 0.0;
+    for (int j = -1; j <= 1; ++j) kc += stiff1[j + 1] * hat1(j);
+    ops.rt_scale = omega * kc / diag;
+    for (int t = 0; t < n5; ++t) {
+      int p[3] = {0, 0, 0}, tt = t;
+      for (int a = 0; a < d; ++a) { p[a] = tt % 5 - 2; tt /= 5; }
+      double sep = 0.0;
+      for (int a = 0; a < d; ++a) {
+        if (p[a] != 0) continue;
+        double w = 1.0;
+        for (int b = 0; b < d; ++b) if (b != a) w *= ops.rt_m[p[b] + 2];
+        sep += w;
+      }
+      sep *= ops.rt_scale;
+      if (std::fabs(sep - ops.rtilde[t]) > 1e-14 * omega) return "R~ is not the expected tensor-product sum";
+    }
   }
   return "";
 }

@@ -106,6 +106,15 @@ def test_boxmg_constant_eps_is_dlinear(d, l):
     assert abs(Pb - Pd).max() < 1e-14
 
 
+@pytest.mark.parametrize("d,l,k", [(2, 4, 2), (2, 3, 2), (3, 3, 2)])
+def test_boxmg_is_dlinear_where_coarse_cells_lie_in_one_block(d, l, k):
+    # eps constant on every coarse cell and along every coarse face: the collapsed 1D/2D problems
+    # and the cell-interior problem have the d-linear interpolant as their solution
+    eps = fem.cell_eps_from_blocks(inp.eps_blocks(d, k, 4.0, seed=17), l)
+    Pb = transfer.boxmg_prolongation(fem.assemble(eps), d, l)
+    assert abs(Pb - transfer.dlinear_prolongation(d, l)).max() < 1e-13
+
+
 def _boxmg_equations_hold(d, l, eps_cells):
     """Check the defining equations of Sec. 2.4 on every column of P."""
     A = fem.assemble(eps_cells).tocsr()
