@@ -8,7 +8,7 @@
  * elements on the levels of a 3:1 spacetree (Sec. 2.1), and iterates the
  * additive adAFAC cycle of eq. (adaFACx) / Algorithm 1 (Sec. 3.1): every level
  * takes one damped Jacobi step, the coarse levels see the FAS right-hand side
- * of eq. (fas-with-htmg) (Sec. 2.3), and every level below the finest solves
+ * of eq. (fas-with-htmg) (Sec. 2.4), and every level below the finest solves
  * the auxiliary damping equation with the smoothed restriction R~ (Sec. 3.2).
  *
  * Conventions shared by every entry point
@@ -49,10 +49,10 @@ extern "C" {
 #define ADAFAC_EDIVERGED 5   /* residual became NaN/Inf or grew beyond 1e3 x its initial value */
 #define ADAFAC_EUNSUPPORTED 7/* option combination not implemented */
 
-/* inter-grid transfers (Sec. 2.4; the switch of Sec. 3.2) */
+/* inter-grid transfers (Sec. 2.5; the switch of Sec. 3.2) */
 #define ADAFAC_TRANSFER_DLINEAR 0
 #define ADAFAC_TRANSFER_BOXMG 1
-/* damping of the additive corrections (Sec. 3.2, Sec. 6.1) */
+/* damping of the additive corrections (Sec. 3.2, Sec. 5.1) */
 #define ADAFAC_DAMP_JAC 0    /* adAFAC-Jac: auxiliary equation with R~ one level coarser */
 #define ADAFAC_DAMP_PI 1     /* adAFAC-PI: c~_l = P I c_l */
 #define ADAFAC_DAMP_NONE 2   /* plain additive multigrid, eq. (additive-mg) */
@@ -73,7 +73,7 @@ typedef struct {
   int inner_k;         /* FP32_REFINED: cycles per outer FP64 step (>= 1) */
   int fused;           /* 1: single-pass fine sweep with deferred prolongation (default),
                           0: one kernel per step (same iterates; used as a cross-check) */
-  double omega;        /* Jacobi damping, 0.6 in Sec. 6 */
+  double omega;        /* Jacobi damping, 0.6 in Sec. 5 */
   double omega_tilde;  /* auxiliary Jacobi damping (the paper gives no value; default omega) */
   double omega_hat;    /* ADAFAC_DAMP_EXP base */
 } adafac_opts;
@@ -102,8 +102,8 @@ int adafac_set_coefficient_blocks(adafac_ctx* ctx, int blocks_per_axis, const do
  * a wrong n or non-finite values. */
 int adafac_set_rhs_lattice(adafac_ctx* ctx, const double* f, size_t n);
 
-/* Build operators and transfers on the host in FP64 (Sec. 2.2, 2.4, 3.2,
- * 5.1): Q1 element operators from eps, BoxMG or d-linear P and R = P^T,
+/* Build operators and transfers on the host in FP64 (Sec. 2.2, 2.5, 3.2,
+ * 4.1): Q1 element operators from eps, BoxMG or d-linear P and R = P^T,
  * Ritz-Galerkin coarse operators, Jacobi diagonals, R~.  opts may be NULL
  * (defaults).  Invalidates a previous bind.  EINVAL / EUNSUPPORTED on bad
  * options. */
@@ -133,7 +133,7 @@ int adafac_solve(adafac_ctx* ctx, double rel_tol, int max_cycles, int* cycles_do
 
 /* Residual norms of iterate `cycle` (0-based, < cycles run since bind):
  * l2h = sqrt(sum_i h^d r_i^2) and linf = max_i |r_i| over the finest-level
- * dofs (Sec. 6, eq. (normalised-residual), before normalisation).  For
+ * dofs (Sec. 5, eq. (normalised-residual), before normalisation).  For
  * FP32_REFINED, `cycle` counts outer steps.  Synchronises.  EINVAL if the
  * cycle has not run. */
 int adafac_residual(adafac_ctx* ctx, int cycle, double* l2h, double* linf);
@@ -161,7 +161,7 @@ int adafac_get_level(adafac_ctx* ctx, int level, int which, double* out, size_t 
  * n = 3^dim (3^l+1)^dim; Q1 rows from eps for levels whose cells lie inside one eps block,
  * Ritz-Galerkin rows below that, Sec. 2.2), 1 = its diagonal (n = (3^l+1)^dim),
  * 2 = prolongation weights from level l-1 into level l, 2^dim per fine vertex for the
- * corners of the coarse cell floor(x/3) clamped to the last cell (Sec. 2.4; d-linear or
+ * corners of the coarse cell floor(x/3) clamped to the last cell (Sec. 2.5; d-linear or
  * BoxMG), n = 2^dim (3^l+1)^dim, l > l_min, 3 = the R~ weights times omega on the 5^dim
  * offsets (Sec. 3.2), n = 5^dim, level ignored.  ESTATE before build_operators. */
 int adafac_host_operator(const adafac_ctx* ctx, int level, int which, double* out, size_t n);

@@ -10,14 +10,14 @@ It restates, in slow and obvious form, what the method of Murray & Weinzierl,
 damping" (Numer. Linear Algebra Appl., arXiv:1903.10367) computes:
 
 * ``fem``        Q1 finite elements on a level of the 3:1 spacetree (Sec. 2.1),
-                 element-wise assembly (Sec. 5.2), lumped right-hand side.
-* ``transfer``   d-linear and BoxMG prolongation (Sec. 2.4), injection (Sec. 2.3).
+                 element-wise assembly (Sec. 4.2), lumped right-hand side.
+* ``transfer``   d-linear and BoxMG prolongation (Sec. 2.5), injection (Sec. 2.4).
 * ``hierarchy``  Ritz-Galerkin coarse operators (Sec. 2.2), Jacobi diagonals,
                  the smoothed auxiliary restriction R~ (Sec. 3.2).
 * ``cycle``      one adAFAC-Jac cycle (eq. (adaFACx), Algorithm 1) in the
                  correction form and in the FAS/HTMG form (eq. (fas-with-htmg)),
                  plus the adAFAC-PI, plain additive and exponentially damped
-                 variants, residual norms (Sec. 6) and FP32 defect correction.
+                 variants, residual norms (Sec. 5) and FP32 defect correction.
 * ``dense``      tiny-grid dense tools: direct solve, iteration matrix.
 
 All vectors live on the full vertex lattice of a level, shape ``(n+1,)*d`` in C

@@ -13,18 +13,18 @@ correction.  The coarsest level gets no damping term (the garbled
 "M_{lmax-1}^{-1} = 0" is read as: no level below lmin, Sec. 3.1).
 
 Readings taken where the paper is silent (listed with the rest in the design
-notes of the repository): omega = 0.6 (Sec. 6), omega~ = omega, omega_add = 1
+notes of the repository): omega = 0.6 (Sec. 5), omega~ = omega, omega_add = 1
 with the Jacobi damping inside M^{-1} = omega D^{-1}, u^0 = 0.
 
 ``cycle_correction`` evaluates the corrections level by level from restricted
 residuals (the AFAC correction form).  ``cycle_fas`` carries the full
-approximation storage of Sec. 2.3: coarse levels hold the injected solution,
+approximation storage of Sec. 2.4: coarse levels hold the injected solution,
 their right-hand side is the restricted hierarchical residual
 R (b - A (u - P I u)) (eq. (fas-with-htmg)), and their residual is
 b_l - A_l u_l.  Under Ritz-Galerkin operators both forms give the same
 iterates in exact arithmetic.
 
-Variants (Sec. 3.2, Sec. 6.1): damping "jac" (adAFAC-Jac, auxiliary equation
+Variants (Sec. 3.2, Sec. 5.1): damping "jac" (adAFAC-Jac, auxiliary equation
 with R~), "pi" (adAFAC-PI, c~_l = P I c_l on the level itself, Algorithm 2),
 "none" (plain additive multigrid, eq. (additive-mg)) and "exp" (exponential
 damping omega_add(l) = omega_hat^(L-l)).
@@ -33,7 +33,7 @@ import numpy as np
 
 
 def norms(H, r):
-    """h-weighted l2 norm sqrt(sum_i h^d r_i^2) and max |r_i| over dofs (Sec. 6, normalised residual)."""
+    """h-weighted l2 norm sqrt(sum_i h^d r_i^2) and max |r_i| over dofs (Sec. 5, normalised residual)."""
     lv = H.lev[H.L]
     ri = np.asarray(r, dtype=np.float64)[lv.mask.ravel()]
     if ri.size == 0:
@@ -91,7 +91,7 @@ def cycle_correction(H, u, b, omega=0.6, omega_t=0.6, damping="jac", omega_hat=0
 
 
 def cycle_fas(H, u, b, omega=0.6, omega_t=0.6, damping="jac", omega_hat=0.5, trace=None):
-    """One cycle in FAS/HTMG form (Sec. 2.3, Algorithm 3's use of r and r^).
+    """One cycle in FAS/HTMG form (Sec. 2.4, Algorithm 3's use of r and r^).
 
     Level l < L: u_l = I u_{l+1}; b_l = R r^_{l+1} with the hierarchical
     residual r^_{l+1} = b_{l+1} - A_{l+1}(u_{l+1} - P I u_{l+1}); the residual

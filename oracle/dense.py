@@ -1,7 +1,7 @@
 """Tiny-grid tools: direct solve of the discrete system and the cycle's iteration matrix.
 
 The paper states that all stable variants are real solvers that converge to
-the same solution (Sec. 6.1); the direct solve is that solution.  The
+the same solution (Sec. 5.1); the direct solve is that solution.  The
 iteration matrix E (the cycle applied to unit vectors with b = 0) gives the
 asymptotic convergence factor rho(E) of a linear stationary iteration.
 """

@@ -2,7 +2,7 @@
 
 Follows Sec. 2.1 of the paper (spacetree levels, d-linear shape functions,
 boundary vertices carry no test function) and the element-wise mat-vec of
-Sec. 5.2 (each cell contributes its element matrix to its 2^d vertices).
+Sec. 4.2 (each cell contributes its element matrix to its 2^d vertices).
 
 Level ``l`` of the unit square/cube has ``n = 3**l`` cells per axis and mesh
 width ``h = 3**-l``.  Arrays over vertices have shape ``(n+1,)*d`` and arrays
@@ -87,7 +87,7 @@ def assemble(eps_cells):
 
     Element matrix of cell c: eps_c * h^(d-2) * K_ref (gradients scale with 1/h,
     the volume with h^d).  Entries are summed over all cells sharing the two
-    vertices (element-wise assembly, Sec. 5.2).  Boundary vertices carry no
+    vertices (element-wise assembly, Sec. 4.2).  Boundary vertices carry no
     test function (Sec. 2.1), so their rows and columns are dropped; their
     value is zero for the homogeneous Dirichlet problems treated here.
     """

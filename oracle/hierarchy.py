@@ -1,7 +1,7 @@
 """Multilevel operators of a uniform 3:1 spacetree.
 
-* A_L from the Q1 discretisation of -div(eps grad u) = f (Sec. 2.1, Sec. 5.2);
-* P_l from d-linear or BoxMG transfers (Sec. 2.4), R_l = P_l^T;
+* A_L from the Q1 discretisation of -div(eps grad u) = f (Sec. 2.1, Sec. 4.2);
+* P_l from d-linear or BoxMG transfers (Sec. 2.5), R_l = P_l^T;
 * Ritz-Galerkin coarse operators A_{l-1} = R A_l P (Sec. 2.2);
 * Jacobi diagonals D_l = diag(A_l) (Sec. 2.2: Jacobi on every level);
 * the smoothed auxiliary restriction R~ = omega R A M^{-1}, truncated to the

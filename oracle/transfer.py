@@ -1,8 +1,8 @@
 """Inter-grid transfers between two uniform levels of the 3:1 spacetree.
 
-* d-linear prolongation (Sec. 2.4 "geometric" choice; Sec. 3.2 switch),
-* BoxMG operator-dependent prolongation for 3-partitioning (Sec. 2.4),
-* injection of a fine vertex value into the coinciding coarse vertex (Sec. 2.3).
+* d-linear prolongation (Sec. 2.5 "geometric" choice; Sec. 3.2 switch),
+* BoxMG operator-dependent prolongation for 3-partitioning (Sec. 2.5),
+* injection of a fine vertex value into the coinciding coarse vertex (Sec. 2.4).
 
 Restriction is the transpose of prolongation, R = P^T (the Ritz-Galerkin
 setting of Sec. 2.2; the paper does not state a scaling, this is the unscaled
@@ -46,7 +46,7 @@ def dlinear_prolongation(d, level_f):
 
 
 def injection(d, level_f):
-    """I: coarse vertex v takes the value of the fine vertex at 3v (Sec. 2.3)."""
+    """I: coarse vertex v takes the value of the fine vertex at 3v (Sec. 2.4)."""
     nc = 3 ** (level_f - 1)
     cshape = (nc + 1,) * d
     fshape = (3 * nc + 1,) * d
@@ -58,7 +58,7 @@ def injection(d, level_f):
 
 
 def boxmg_prolongation(A_f, d, level_f):
-    """BoxMG prolongation for 3-partitioning (Sec. 2.4), built from the fine operator.
+    """BoxMG prolongation for 3-partitioning (Sec. 2.5), built from the fine operator.
 
     For every coarse cell and every one of its corners e, the column of P for e
     restricted to the closed cell is determined by

@@ -78,6 +78,24 @@ struct RtSep {
   T scale;
 };
 
+// The smallest levels lo..hi handled by one workgroup (see k_small_levels).  lv[j] is the
+// view of level lo-1+j (lv[0]: level lo-1, empty when lo is the coarsest; lv[hi-lo+2]: the
+// next finer level hi+1).
+constexpr int kMaxSmall = 4;
+template <typename T>
+struct SmallLevelsArgs {
+  LevelView<T> lv[kMaxSmall + 2];
+  int lo, hi;
+  int gather[kMaxSmall];
+  T cscale[kMaxSmall];
+  RtSep<T> rts;
+  T omega, omega_t;
+  int damping;
+  const double* partials;
+  int nparts;
+  double* norm_out;        // nullptr: no norms in this launch
+};
+
 struct CycleParams {
   double omega, omega_t, omega_hat;
   int damping;               // ADAFAC_DAMP_*

@@ -31,6 +31,13 @@ hipError_t launch_fine_sweep(int d, const LevelView<T>& F, const LevelView<T>& C
                              const T* b, const RtSep<T>& rt, T omega, int damping, int apply_pending,
                              double* partials, int* nparts, hipStream_t s);
 size_t fine_sweep_partials(int d, int n);
+template <typename T>
+hipError_t launch_coarse_sweep(int d, const LevelView<T>& L, const LevelView<T>& C, const RtSep<T>& rts,
+                               T omega, T omega_t, T cscale, int damping, hipStream_t s);
+bool sweep_level_ok(int d, const LevelView<double>& L);
+template <typename T>
+hipError_t launch_small_levels(int d, const SmallLevelsArgs<T>& a, size_t lds_bytes, hipStream_t s);
+
 
 }  // namespace adafac
 
@@ -38,6 +45,11 @@ using namespace adafac;
 
 namespace {
 constexpr int kMaxHist = 1 << 14;
+// Levels with at most this many vertices are updated together by one workgroup.
+#ifndef ADAFAC_SMALL_VERTS
+#define ADAFAC_SMALL_VERTS 256
+#endif
+constexpr size_t kSmallVerts = ADAFAC_SMALL_VERTS;
 constexpr int kTimingPool = 256;
 }
 
@@ -177,8 +189,22 @@ int record_stop(adafac_ctx* c) {
   return ADAFAC_OK;
 }
 
+// Coarse levels are swept with the tiled kernel when they have at least this many cells per
+// axis (fewer tiles than CUs otherwise, and the short z march is latency bound).
+#ifndef ADAFAC_COARSE_SWEEP_MIN_N
+#define ADAFAC_COARSE_SWEEP_MIN_N 81
+#endif
+constexpr int kCoarseSweepMinN = ADAFAC_COARSE_SWEEP_MIN_N;
+
 // One FP64 cycle.  Cycle n: residual (and norms) of iterate n, FAS restriction cascade,
 // coarse corrections, prolongation; iterate n+1 lands in ufine[1-cur].
+//   finest level   single-pass sweep (deferred prolongation of the previous cycle's coarse
+//                  corrections, residual, Jacobi, injection, R and R~), or one kernel per step;
+//   coarse levels  the same tiled sweep in FAS mode where the level allows it (3D, 27 | 3^l,
+//                  Q1 operator, d-linear transfer), else one thread per vertex gathering from
+//                  the finer level; the smallest levels together in one workgroup;
+//   prolongation   S_l += P S_{l-1} upwards; the finest level's share is added by the next
+//                  sweep (or the flush).
 int run_cycle64(adafac_ctx* c) {
   const int d = c->dim, L = c->L, lmin = c->lmin;
   const adafac_opts& o = c->opts;
@@ -188,34 +214,66 @@ int run_cycle64(adafac_ctx* c) {
   double* uout = c->ufine[1 - c->cur];
   LevelView<double> F = c->v64[L];
   F.u = uin;
+  F.r = c->rfine;
   LevelView<double> Lm1 = L > lmin ? c->v64[L - 1] : LevelView<double>{};
   int nparts = kNormBlocks;
   int rc;
   // adAFAC-PI reads and writes the injected fine correction in the same sweep: one kernel per step
   const bool fused = o.fused && L > lmin && !pi && fused_ok(c);
+  if ((rc = record_start(c))) return rc;
   if (fused) {
-    if ((rc = record_start(c))) return rc;
     HIPCHK(c, launch_fine_sweep<double>(d, F, Lm1, uin, uout, c->bfine, c->rts64, o.omega, damping,
                                         c->pending ? 1 : 0, c->partials, &nparts, c->stream));
-    if ((rc = record_stop(c))) return rc;
   } else {
-    if ((rc = record_start(c))) return rc;
     HIPCHK(c, launch_fine_residual<double>(d, F, uin, uout, c->bfine, c->rfine, pi ? Lm1.ic : nullptr,
                                            Lm1.nv, o.omega, pi, c->partials, kNormBlocks, c->stream));
-    if ((rc = record_stop(c))) return rc;
   }
-  HIPCHK(c, launch_norm_finalize(c->partials, nparts, c->norms + 2 * (c->ncyc % kMaxHist), c->stream));
-  // coarse levels, finest first: each needs the residual of the next finer level
-  for (int l = L - 1; l >= lmin; --l) {
-    LevelView<double> Fv = c->v64[l + 1];
-    bool from_sweep = fused && l == L - 1;
-    if (l + 1 == L) { Fv.u = uin; Fv.r = c->rfine; }
-    LevelView<double> Cm = l > lmin ? c->v64[l - 1] : LevelView<double>{};
-    double cscale = damping == ADAFAC_DAMP_EXP ? std::pow(o.omega_hat, L - l) : 1.0;
-    HIPCHK(c, launch_level_update<double>(d, c->v64[l], Fv, Cm, c->rts64, o.omega, o.omega_tilde, cscale,
-                                          damping, from_sweep ? 0 : 1, c->stream));
+  if ((rc = record_stop(c))) return rc;
+  double* norm_out = c->norms + 2 * (c->ncyc % kMaxHist);
+  auto cscale_of = [&](int l) { return damping == ADAFAC_DAMP_EXP ? std::pow(o.omega_hat, L - l) : 1.0; };
+  // smallest levels lo..hi for the single-workgroup kernel
+  int hi = lmin - 1;
+  for (int l = lmin; l < L && l - lmin < kMaxSmall && nverts_of(d, l) <= kSmallVerts; ++l) hi = l;
+  bool fed = fused;               // level l's u, R r and R~ r already written by the finer level
+  for (int l = L - 1; l > hi; --l) {
+    const bool sweep = !pi && fed && l > lmin && c->v64[l].n >= kCoarseSweepMinN && sweep_level_ok(d, c->v64[l]);
+    if (sweep) {
+      HIPCHK(c, launch_coarse_sweep<double>(d, c->v64[l], c->v64[l - 1], c->rts64, o.omega, o.omega_tilde,
+                                            cscale_of(l), damping, c->stream));
+    } else {
+      LevelView<double> Fv = c->v64[l + 1];
+      if (l + 1 == L) { Fv.u = uin; Fv.r = c->rfine; }
+      LevelView<double> Cm = l > lmin ? c->v64[l - 1] : LevelView<double>{};
+      HIPCHK(c, launch_level_update<double>(d, c->v64[l], Fv, Cm, c->rts64, o.omega, o.omega_tilde,
+                                            cscale_of(l), damping, fed ? 0 : 1, c->stream));
+    }
+    fed = sweep;
   }
-  for (int l = lmin + 1; l < L; ++l)
+  if (hi >= lmin) {
+    SmallLevelsArgs<double> a{};
+    a.lo = lmin;
+    a.hi = hi;
+    for (int l = lmin - 1; l <= hi + 1; ++l) {
+      LevelView<double> v = (l >= lmin) ? c->v64[l] : LevelView<double>{};
+      if (l == L) { v.u = uin; v.r = c->rfine; }
+      a.lv[l - lmin + 1] = v;
+    }
+    for (int l = lmin; l <= hi; ++l) {
+      a.gather[l - lmin] = (l == hi && fed) ? 0 : 1;
+      a.cscale[l - lmin] = cscale_of(l);
+    }
+    a.rts = c->rts64;
+    a.omega = o.omega;
+    a.omega_t = o.omega_tilde;
+    a.damping = damping;
+    a.partials = c->partials;
+    a.nparts = nparts;
+    a.norm_out = norm_out;
+    HIPCHK(c, launch_small_levels<double>(d, a, 0, c->stream));
+  } else {
+    HIPCHK(c, launch_norm_finalize(c->partials, nparts, norm_out, c->stream));
+  }
+  for (int l = std::max(hi + 1, lmin + 1); l < L; ++l)
     HIPCHK(c, launch_prolong_add<double>(d, c->v64[l], c->v64[l - 1], c->v64[l].S, c->v64[l - 1].S,
                                          pi ? c->v64[l - 1].ic : nullptr, c->stream));
   if (fused) {

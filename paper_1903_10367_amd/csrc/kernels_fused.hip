@@ -2,17 +2,17 @@
 //
 // One launch touches every finest-level vertex once per cycle and does, per vertex:
 //   (a) u <- u + P S_{L-1}: the coarse corrections of the previous cycle, applied one sweep
-//       late (the iterate shift of Sec. 5.3; the iterates equal those of the unshifted cycle),
-//   (b) r = b - A u with the Q1 operator of -div(eps grad u) (element-wise, Sec. 5.2),
+//       late (the iterate shift of Sec. 4.3; the iterates equal those of the unshifted cycle),
+//   (b) r = b - A u with the Q1 operator of -div(eps grad u) (element-wise, Sec. 4.2),
 //   (c) u <- u + omega D^-1 r (damped Jacobi, Algorithm 1),
 //   (d) the FAS injection u_{L-1} = I u, the restriction R r (the coarse level adds the tau
-//       correction, Sec. 2.3) and the auxiliary right-hand side R~ r (Sec. 3.2) for every
+//       correction, Sec. 2.4) and the auxiliary right-hand side R~ r (Sec. 3.2) for every
 //       coarse vertex the tile owns,
-//   (e) per-block partial sums of h^d r^2 and max |r| (Sec. 6 residual norms).
+//   (e) per-block partial sums of h^d r^2 and max |r| (Sec. 5 residual norms).
 //
-// Tiling.  A workgroup (256 lanes, four wave64) owns a 27 x 27 x tz block of fine vertices
-// (tz a multiple of 3), i.e. whole coarse cells, and every coarse vertex at a multiple of 3
-// inside it.  The 5^d-point restriction of an owned coarse vertex reaches two fine vertices
+// Tiling.  A workgroup owns a 27 x 27 (x tz in 3D, tz a multiple of 3) block of fine vertices,
+// i.e. whole coarse cells, and every coarse vertex at a multiple of 3 inside it; the 3D sweep
+// runs 1024 lanes (sixteen wave64), one per x/y column of the rings below, the 2D sweep 256.  The 5^d-point restriction of an owned coarse vertex reaches two fine vertices
 // into the lower neighbour, so the tile recomputes the residual on a 29-wide ring and reads
 // u on a 31-wide ring: every coarse value is written by exactly one workgroup, without atomics,
 // and the result does not depend on scheduling.  3D tiles march through z with the current
@@ -115,6 +115,15 @@ struct Sweep3dArgs {
   RtSep<T> rts;
   int n, nv, nc, nvc, nb, bs;
   int tz, ntx, ntz, damping, apply_pending;
+  // coarse FAS level (coarse = 1): b holds R r of the finer level; the kernel forms the FAS
+  // right-hand side bf = R r + A u (tau correction), the residual r = bf - A u, and writes
+  // S = cscale omega D^-1 r - omega~ D^-1 b~ instead of updating u
+  int coarse;
+  const T* bt_in;
+  T* sout;
+  T* bfout;
+  T* rout;
+  T omega_t, cscale;
 };
 
 template <typename T, bool VAREPS>
@@ -299,14 +308,28 @@ __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_fine_sweep3d(S
     own = o_n;
     T res = T(0);
     if (p >= zs + 2 && rint && z > 0 && z < n) {
-      res = pb[k] - au;
-      if (rown && z >= z0 && z < z0 + tz) {
-        __builtin_nontemporal_store(uz + dinv * res, &a.uout[z * plane + roff]);
-        const double rd = double(res);
-        ssum += rd * rd;
-        smax = fabs(rd) > smax ? fabs(rd) : smax;
-        if (rcc && z % 3 == 0) a.cu[lin<3>(x / 3, y / 3, z / 3, nvc)] = uz;   // FAS injection of iterate n
+      const bool own_pt = rown && z >= z0 && z < z0 + tz;
+      if (!a.coarse) {
+        res = pb[k] - au;
+        if (own_pt) {
+          __builtin_nontemporal_store(uz + dinv * res, &a.uout[z * plane + roff]);
+          const double rd = double(res);
+          ssum += rd * rd;
+          smax = fabs(rd) > smax ? fabs(rd) : smax;
+        }
+      } else {
+        const T bf = pb[k] + au;       // FAS right-hand side with the tau correction
+        res = bf - au;
+        if (own_pt) {
+          const int gi = z * plane + roff;
+          T sv = a.cscale * dinv * res;
+          if (jac) sv -= (a.omega_t / a.omega) * dinv * a.bt_in[gi];
+          a.sout[gi] = sv;
+          a.bfout[gi] = bf;
+          a.rout[gi] = res;
+        }
       }
+      if (own_pt && rcc && z % 3 == 0) a.cu[lin<3>(x / 3, y / 3, z / 3, nvc)] = uz;   // FAS injection
     }
     if (ract) Rb[mod3(z)][tid] = res;
   };
@@ -343,7 +366,7 @@ __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_fine_sweep3d(S
     step(p + 1, 1);
     step(p + 2, 2);
   }
-  block_norm_partials(double(a.hd) * ssum, smax, a.partials);
+  if (!a.coarse) block_norm_partials(double(a.hd) * ssum, smax, a.partials);
 }
 
 template <typename T, bool VAREPS>
@@ -484,6 +507,33 @@ static int pick_tz(int n) {
 }
 
 template <typename T>
+static hipError_t launch_sweep3d(const Sweep3dArgs<T>& a, bool var, hipStream_t s) {
+  const unsigned nb = unsigned(a.ntx * a.ntx * a.ntz);
+  if (var)
+    k_fine_sweep3d<T, true><<<nb, NT3, 0, s>>>(a);
+  else
+    k_fine_sweep3d<T, false><<<nb, NT3, 0, s>>>(a);
+  return hipGetLastError();
+}
+
+bool sweep_level_ok(int d, const LevelView<double>& L) {
+  return d == 3 && L.fem && L.n % TX == 0 && !L.pw;
+}
+
+// FAS update of a coarse level L (3^l >= 27 cells per axis, Q1 operator, d-linear transfer
+// into it) in one tiled pass that also restricts into the next coarser level C.
+template <typename T>
+hipError_t launch_coarse_sweep(int d, const LevelView<T>& L, const LevelView<T>& C, const RtSep<T>& rts,
+                               T omega, T omega_t, T cscale, int damping, hipStream_t s) {
+  if (d != 3 || L.n % TX || L.pw || !L.fem) return hipErrorInvalidValue;
+  const int n = L.n, ntx = n / TX, tz = pick_tz(n), ntz = n / tz;
+  Sweep3dArgs<T> a{L.u, nullptr, L.rr, C.S, C.u, C.rr, C.bt, L.eps, nullptr, L.h, omega, L.hd, rts,
+                   n, L.nv, C.n, C.nv, L.nb, L.bs, tz, ntx, ntz, damping, 0,
+                   1, L.bt, L.S, L.bf, L.r, omega_t, cscale};
+  return launch_sweep3d<T>(a, L.eps != nullptr, s);
+}
+
+template <typename T>
 hipError_t launch_fine_sweep(int d, const LevelView<T>& F, const LevelView<T>& C, const T* uin, T* uout,
                              const T* b, const RtSep<T>& rts, T omega, int damping, int apply_pending,
                              double* partials, int* nparts, hipStream_t s) {
@@ -502,16 +552,18 @@ hipError_t launch_fine_sweep(int d, const LevelView<T>& F, const LevelView<T>& C
     const int tz = pick_tz(n), ntz = n / tz;
     const unsigned nb = unsigned(ntx * ntx * ntz);
     Sweep3dArgs<T> a{uin, uout, b, C.S, C.u, C.rr, C.bt, F.eps, partials, F.h, omega, F.hd, rts,
-                     n, F.nv, C.n, C.nv, F.nb, F.bs, tz, ntx, ntz, damping, apply_pending};
-    if (var)
-      k_fine_sweep3d<T, true><<<nb, NT3, 0, s>>>(a);
-    else
-      k_fine_sweep3d<T, false><<<nb, NT3, 0, s>>>(a);
+                     n, F.nv, C.n, C.nv, F.nb, F.bs, tz, ntx, ntz, damping, apply_pending,
+                     0, nullptr, nullptr, nullptr, nullptr, T(0), T(1)};
+    (void)launch_sweep3d<T>(a, var, s);
     *nparts = int(nb);
   }
   return hipGetLastError();
 }
 
+template hipError_t launch_coarse_sweep<double>(int, const LevelView<double>&, const LevelView<double>&,
+                                                const RtSep<double>&, double, double, double, int, hipStream_t);
+template hipError_t launch_coarse_sweep<float>(int, const LevelView<float>&, const LevelView<float>&,
+                                               const RtSep<float>&, float, float, float, int, hipStream_t);
 template hipError_t launch_fine_sweep<double>(int, const LevelView<double>&, const LevelView<double>&,
                                               const double*, double*, const double*, const RtSep<double>&,
                                               double, int, int, double*, int*, hipStream_t);

@@ -3,7 +3,7 @@
 // These kernels are the building blocks that every path uses for the coarse levels and,
 // with `fused = 0`, for the finest level too:
 //   fine_residual   r_L = b - A_L u, u <- u + omega D^-1 r_L, per-block norm partials
-//   level_update    FAS step of one coarse level l (Sec. 2.3): inject u_l = I u_{l+1},
+//   level_update    FAS step of one coarse level l (Sec. 2.4): inject u_l = I u_{l+1},
 //                   restrict R r_{l+1} and R~ r_{l+1}, form the FAS right-hand side with the
 //                   tau correction b_l = R r_{l+1} + A_l I u_{l+1}, the level residual
 //                   r_l = b_l - A_l u_l, the Jacobi correction c_l = omega D^-1 r_l and the
@@ -49,14 +49,12 @@ __global__ void __launch_bounds__(256) k_fine_residual(LevelView<T> F, const T* 
   block_norm_partials(ssum, smax, partials);
 }
 
+// FAS update of vertex i of coarse level C (next finer level F, next coarser level Cm).
 template <typename T, int D>
-__global__ void __launch_bounds__(256) k_level_update(LevelView<T> C, LevelView<T> F, LevelView<T> Cm,
-                                                      RtSep<T> rts, T omega, T omega_t, T cscale,
-                                                      int damping, int gather) {
+__device__ __forceinline__ void level_update_vertex(const LevelView<T>& C, const LevelView<T>& F,
+                                                    const LevelView<T>& Cm, const RtSep<T>& rts, T omega,
+                                                    T omega_t, T cscale, int damping, int gather, size_t i) {
   const int nv = C.nv, nvf = F.nv;
-  const size_t nverts = D == 2 ? size_t(nv) * nv : size_t(nv) * nv * nv;
-  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= nverts) return;
   int x = int(i % nv), y = int((i / nv) % nv), z = D == 3 ? int(i / (size_t(nv) * nv)) : 0;
   if (!is_interior<D>(x, y, z, nv)) return;
   const bool jac = damping == ADAFAC_DAMP_JAC;
@@ -126,6 +124,77 @@ __global__ void __launch_bounds__(256) k_level_update(LevelView<T> C, LevelView<
   C.S[i] = s;
 }
 
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_level_update(LevelView<T> C, LevelView<T> F, LevelView<T> Cm,
+                                                      RtSep<T> rts, T omega, T omega_t, T cscale,
+                                                      int damping, int gather) {
+  const size_t nverts = D == 2 ? size_t(C.nv) * C.nv : size_t(C.nv) * C.nv * C.nv;
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nverts) return;
+  level_update_vertex<T, D>(C, F, Cm, rts, omega, omega_t, cscale, damping, gather, i);
+}
+
+// The smallest levels in one workgroup: the residual norms of the cycle (fixed-order reduction
+// of the finest-level partials), the FAS updates of levels hi .. lo (finest first), then the
+// prolongation S_l += P S_{l-1} for l = lo+1 .. hi, with a workgroup barrier between levels.
+template <typename T, int D>
+__global__ void __launch_bounds__(1024) k_small_levels(SmallLevelsArgs<T> a) {
+  const int tid = threadIdx.x;
+  const int lo = a.lo, hi = a.hi;
+  auto nverts_of = [](const LevelView<T>& v) {
+    return D == 2 ? size_t(v.nv) * v.nv : size_t(v.nv) * v.nv * v.nv;
+  };
+  if (a.norm_out) {
+    // fixed order: each lane sums a strided subset, then a fixed butterfly and wave order
+    __shared__ double ws[16], wm[16];
+    double s = 0.0, m = 0.0;
+    for (int i = tid; i < a.nparts; i += 1024) {
+      s += a.partials[2 * i];
+      m = fmax(m, a.partials[2 * i + 1]);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      s += __shfl_xor(s, off);
+      m = fmax(m, __shfl_xor(m, off));
+    }
+    if ((tid & 63) == 0) {
+      ws[tid >> 6] = s;
+      wm[tid >> 6] = m;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double st = 0.0, mt = 0.0;
+      for (int w = 0; w < 16; ++w) {
+        st += ws[w];
+        mt = fmax(mt, wm[w]);
+      }
+      a.norm_out[0] = sqrt(st);
+      a.norm_out[1] = mt;
+    }
+  }
+  for (int l = hi; l >= lo; --l) {
+    const LevelView<T>& C = a.lv[l - lo + 1];
+    const size_t nverts = nverts_of(C);
+    for (size_t i = tid; i < nverts; i += 1024)
+      level_update_vertex<T, D>(C, a.lv[l - lo + 2], a.lv[l - lo], a.rts, a.omega, a.omega_t,
+                                a.cscale[l - lo], a.damping, a.gather[l - lo], i);
+    __syncthreads();
+  }
+  const bool pi = a.damping == ADAFAC_DAMP_PI;
+  for (int l = lo + 1; l <= hi; ++l) {
+    const LevelView<T>& F = a.lv[l - lo + 1];
+    const LevelView<T>& C = a.lv[l - lo];
+    const int nv = F.nv;
+    const size_t nverts = nverts_of(F);
+    for (size_t i = tid; i < nverts; i += 1024) {
+      int x = int(i % nv), y = int((i / nv) % nv), z = D == 3 ? int(i / (size_t(nv) * nv)) : 0;
+      if (!is_interior<D>(x, y, z, nv)) continue;
+      F.S[i] += prolong_value<T, D>(F, C, x, y, z, C.S, pi ? C.ic : nullptr);
+    }
+    __syncthreads();
+  }
+}
+
 // dst(f) += sum_c P(f <- c) (src(c) - sub(c)) on the interior vertices of level F.
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_prolong_add(LevelView<T> F, LevelView<T> C, T* __restrict__ dst,
@@ -177,6 +246,17 @@ hipError_t launch_prolong_add(int d, const LevelView<T>& F, const LevelView<T>& 
     k_prolong_add<T, 3><<<nb, 256, 0, s>>>(F, C, dst, src, sub);
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_small_levels(int d, const SmallLevelsArgs<T>& a, size_t lds_bytes, hipStream_t s) {
+  if (d == 2)
+    k_small_levels<T, 2><<<1, 1024, lds_bytes, s>>>(a);
+  else
+    k_small_levels<T, 3><<<1, 1024, lds_bytes, s>>>(a);
+  return hipGetLastError();
+}
+template hipError_t launch_small_levels<double>(int, const SmallLevelsArgs<double>&, size_t, hipStream_t);
+template hipError_t launch_small_levels<float>(int, const SmallLevelsArgs<float>&, size_t, hipStream_t);
 
 __global__ void __launch_bounds__(256) k_norm_finalize(const double* __restrict__ partials, int n,
                                                        double* __restrict__ out) {

@@ -1,7 +1,7 @@
 // Host-side FP64 construction of the multilevel operators of a uniform 3:1 spacetree.
 //
-//  * Q1 element operator from the coefficient (Sec. 2.1, element-wise form of Sec. 5.2),
-//  * BoxMG prolongation for 3-partitioning (Sec. 2.4) or d-linear interpolation,
+//  * Q1 element operator from the coefficient (Sec. 2.1, element-wise form of Sec. 4.2),
+//  * BoxMG prolongation for 3-partitioning (Sec. 2.5) or d-linear interpolation,
 //  * Ritz-Galerkin coarse operators A_{l-1} = P^T A_l P (Sec. 2.2),
 //  * the smoothed restriction R~ = omega R A M^-1 of the eps = 1 operator, truncated to the
 //    support of P (Sec. 3.2).
@@ -166,7 +166,7 @@ bool solve_dense(int m, double* M, double* x) {  // Gaussian elimination, partia
   return true;
 }
 
-// BoxMG weights (Sec. 2.4) of the transfer into level l, from the stencil of level l.
+// BoxMG weights (Sec. 2.5) of the transfer into level l, from the stencil of level l.
 // For every coarse cell and each of its corners e: identity at c-points; on every coarse
 // edge, then face, the stencil is summed along the normal directions and the collapsed
 // homogeneous equations are solved for the points inside it; inside the cell A P e = 0.

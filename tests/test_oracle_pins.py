@@ -81,7 +81,7 @@ def test_lumped_rhs_uniform():
     assert np.all(b[~m] == 0)
 
 
-# --- transfers (Sec. 2.4) ----------------------------------------------------
+# --- transfers (Sec. 2.5) ----------------------------------------------------
 
 @pytest.mark.parametrize("d,l", [(2, 3), (3, 2)])
 def test_dlinear_reproduces_multilinear(d, l):
@@ -99,7 +99,7 @@ def test_dlinear_reproduces_multilinear(d, l):
 
 @pytest.mark.parametrize("d,l", [(2, 3), (3, 2)])
 def test_boxmg_constant_eps_is_dlinear(d, l):
-    # Sec. 6.1: BoxMG gives bilinear transfers for Poisson
+    # Sec. 5.1: BoxMG gives bilinear transfers for Poisson
     A = fem.assemble(np.full((3 ** l,) * d, 4.0))
     Pb = transfer.boxmg_prolongation(A, d, l)
     Pd = transfer.dlinear_prolongation(d, l)
@@ -116,7 +116,7 @@ def test_boxmg_is_dlinear_where_coarse_cells_lie_in_one_block(d, l, k):
 
 
 def _boxmg_equations_hold(d, l, eps_cells):
-    """Check the defining equations of Sec. 2.4 on every column of P."""
+    """Check the defining equations of Sec. 2.5 on every column of P."""
     A = fem.assemble(eps_cells).tocsr()
     P = transfer.boxmg_prolongation(A, d, l).toarray()
     nf = 3 ** l
@@ -178,7 +178,7 @@ def test_boxmg_rows_sum_to_one_away_from_boundary():
 
 @pytest.mark.parametrize("d,lf", [(2, 3), (3, 2)])
 def test_galerkin_of_constant_eps_is_rediscretisation(d, lf):
-    # Sec. 6.1: Ritz-Galerkin gives the rediscretised operator for Poisson (3D: proportional to h)
+    # Sec. 5.1: Ritz-Galerkin gives the rediscretised operator for Poisson (3D: proportional to h)
     A = fem.assemble(np.ones((3 ** lf,) * d))
     P = transfer.dlinear_prolongation(d, lf)
     Ac = (P.T @ A @ P).toarray()
@@ -371,7 +371,7 @@ def test_fas_form_equals_correction_form(d, L, kind, k):
 
 @pytest.mark.parametrize("damping", ["jac", "pi"])
 def test_fixed_point_is_direct_solve(damping):
-    # Sec. 6.1: the stable variants are real solvers and converge to the same solution
+    # Sec. 5.1: the stable variants are real solvers and converge to the same solution
     H = hierarchy.Hierarchy(2, 3, 1, inp.eps_blocks(2, 2, 2.0, 9), "boxmg")
     b = H.rhs(inp.rhs(2, 3, 9))
     us = dense.direct_solve(H, b)
@@ -430,7 +430,7 @@ def test_defect_correction_fp32_reaches_fp64_tolerance():
 
 
 def test_plain_additive_degrades_with_depth_while_adafac_does_not():
-    # Sec. 6.1 (qualitative): plain additive overshoots more as levels are added; adAFAC stays stable
+    # Sec. 5.1 (qualitative): plain additive overshoots more as levels are added; adAFAC stays stable
     rates = {}
     for L in (2, 3):
         H = hierarchy.Hierarchy(2, L, 1)
