@@ -118,17 +118,24 @@ int adafac_workspace_bytes(const adafac_ctx* ctx, size_t* bytes);
  * (NULL = the null stream).  EDEVICE if a copy fails. */
 int adafac_bind(adafac_ctx* ctx, void* dev_workspace, size_t bytes, void* hip_stream);
 
-/* Enqueue ncycles adAFAC cycles (FP64 form; for FP32_REFINED one call runs
- * ncycles outer steps of inner_k FP32 cycles each).  Cycle n computes the
- * residual norms of iterate n and produces iterate n+1.  Non-blocking. */
+/* Enqueue ncycles adAFAC cycles.  Cycle n computes the residual norms of
+ * iterate n and produces iterate n+1.  FP32_REFINED: ncycles outer steps of
+ * FP64 defect correction, each the FP64 defect r = b - A u of the outer
+ * iterate (its norms are recorded), inner_k FP32 cycles on A e = r from e = 0,
+ * and u <- u + e in FP64 (applied at the start of the next step or when the
+ * solution is read).  Non-blocking. */
 int adafac_cycle(adafac_ctx* ctx, int ncycles);
 
 /* Iterate until ||r^(n)||_h / ||r^(0)||_h <= rel_tol for the input iterate n
  * of the last cycle run, or max_cycles cycles (outer steps for FP32_REFINED)
- * have run.  *cycles_done (may be NULL) receives the number run; the solution
- * afterwards is iterate cycles_done (for FP32_REFINED: the last outer iterate,
- * whose FP64 residual met the tolerance).  Synchronises.  EDIVERGED on NaN/Inf
- * or growth beyond 1e3 x the initial norm. */
+ * have run; r^(0) is the residual of the iterate at bind / set_solution.
+ * *cycles_done (may be NULL) receives the number of residual evaluations.  FP64
+ * form: the cycle that measured iterate n also produced n+1, and the solution
+ * afterwards is that iterate.  FP32_REFINED: an outer step measures the FP64
+ * defect of its iterate and, unless it met the tolerance, runs inner_k FP32
+ * cycles on A e = r; the solution afterwards is the last outer iterate (the one
+ * whose FP64 residual met the tolerance when the solve converged).
+ * Synchronises.  EDIVERGED on NaN/Inf or growth beyond 1e3 x the initial norm. */
 int adafac_solve(adafac_ctx* ctx, double rel_tol, int max_cycles, int* cycles_done);
 
 /* Residual norms of iterate `cycle` (0-based, < cycles run since bind):

@@ -138,7 +138,8 @@ def solve(H, b, max_cycles, tol=None, form="correction", u0=None, **kw):
     return u, hist
 
 
-def defect_correction(H, b, k_inner, tol, max_outer, inner_dtype=np.float32, form="correction", **kw):
+def defect_correction(H, b, k_inner, tol, max_outer, inner_dtype=np.float32, form="correction",
+                      iterates=None, **kw):
     """FP64 defect correction around k inner adAFAC cycles in ``inner_dtype``.
 
     Outer step: r = b - A u in FP64; stop if ||r||_h/||r^0||_h <= tol;
@@ -146,7 +147,7 @@ def defect_correction(H, b, k_inner, tol, max_outer, inner_dtype=np.float32, for
     entirely in ``inner_dtype`` (operators, smoothing, transfers, damping),
     then u <- u + e in FP64.  The cycle is linear, so in exact arithmetic k
     inner cycles equal k outer cycles.  Returns (u, outer residual history,
-    total inner cycles).
+    total inner cycles); ``iterates`` (a list) receives every outer iterate.
     """
     L = H.L
     Hs = H.astype(inner_dtype)
@@ -156,6 +157,8 @@ def defect_correction(H, b, k_inner, tol, max_outer, inner_dtype=np.float32, for
     for _ in range(max_outer + 1):
         r = b - H.lev[L].A(u)
         hist.append(norms(H, r))
+        if iterates is not None:
+            iterates.append(u.copy())
         if hist[0][0] == 0 or hist[-1][0] / hist[0][0] <= tol or len(hist) > max_outer:
             break
         rs = r.astype(inner_dtype)

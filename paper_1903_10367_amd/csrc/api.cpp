@@ -26,6 +26,10 @@ template <typename T>
 hipError_t launch_prolong_add(int d, const LevelView<T>& F, const LevelView<T>& C, T* dst, const T* src,
                               const T* sub, hipStream_t s);
 hipError_t launch_norm_finalize(const double* partials, int n, double* out, hipStream_t s);
+hipError_t launch_accumulate(int d, const LevelView<float>& F, const LevelView<float>& C, double* u,
+                             const float* e, const float* S, hipStream_t s);
+hipError_t launch_defect(int d, const LevelView<double>& F, const double* u, const double* b, float* r32,
+                         double* partials, int nblocks, hipStream_t s);
 template <typename T>
 hipError_t launch_fine_sweep(int d, const LevelView<T>& F, const LevelView<T>& C, const T* uin, T* uout,
                              const T* b, const RtSep<T>& rt, T omega, int damping, int apply_pending,
@@ -34,10 +38,9 @@ size_t fine_sweep_partials(int d, int n);
 template <typename T>
 hipError_t launch_coarse_sweep(int d, const LevelView<T>& L, const LevelView<T>& C, const RtSep<T>& rts,
                                T omega, T omega_t, T cscale, int damping, hipStream_t s);
-bool sweep_level_ok(int d, const LevelView<double>& L);
+bool sweep_level_ok(int d, int n, int fem, bool has_pw);
 template <typename T>
 hipError_t launch_small_levels(int d, const SmallLevelsArgs<T>& a, size_t lds_bytes, hipStream_t s);
-
 
 }  // namespace adafac
 
@@ -51,7 +54,21 @@ constexpr int kMaxHist = 1 << 14;
 #endif
 constexpr size_t kSmallVerts = ADAFAC_SMALL_VERTS;
 constexpr int kTimingPool = 256;
-}
+
+// The device hierarchy of one arithmetic precision: level views, the finest-level iterate
+// (ping-pong, the Jacobi step reads the old neighbours), its right-hand side and residual.
+template <typename T>
+struct Hier {
+  LevelView<T> v[kMaxLevel + 1]{};
+  T* ufine[2] = {nullptr, nullptr};
+  T* bfine = nullptr;
+  T* rfine = nullptr;
+  T* eps = nullptr;
+  RtSep<T> rts{};
+  int cur = 0;
+  bool pending = false;     // fused path: P S_{L-1} of the last cycle not yet added to the iterate
+};
+}  // namespace
 
 struct adafac_ctx {
   int dim = 2, lmin = 1, L = 1;
@@ -67,18 +84,16 @@ struct adafac_ctx {
   size_t ws_bytes = 0;
   size_t ws_need = 0;       // workspace size of the built hierarchy
   hipStream_t stream = nullptr;
-  LevelView<double> v64[kMaxLevel + 1]{};
-  double* ufine[2] = {nullptr, nullptr};
-  double* bfine = nullptr;
-  double* rfine = nullptr;
+  Hier<double> h64;         // FP64 form; for FP32_REFINED only the finest level (u, b, operator)
+  Hier<float> h32;          // FP32_REFINED: inner cycles on A e = r, ufine = e, bfine = r
+  float* ezero = nullptr;   // FP32_REFINED: e = 0, the iterate every inner solve starts from
+  bool e_pending = false;   // FP32_REFINED: inner correction not yet added to the FP64 solution
   double* partials = nullptr;
   size_t npartials = 0;
-  double* norms = nullptr;
-  double* rt = nullptr;
-  RtSep<double> rts64{};
-  double* eps_dev = nullptr;
-  int cur = 0;
-  bool pending = false;     // fused path: P S_{L-1} of the last cycle not yet added to u
+  double* norms = nullptr;  // (l2h, linf) per cycle or outer step, ring of kMaxHist
+  double* scratch_norm = nullptr;
+  double* norm0 = nullptr;  // (l2h, linf) of iterate 0, kept beyond the ring
+  double r0 = -1.0;         // l2h of iterate 0 (host copy, set by solve)
   int ncyc = 0;
   // kernel timing
   bool timing = false;
@@ -107,6 +122,8 @@ size_t nverts_of(int d, int l) {
   return d == 2 ? nv * nv : nv * nv * nv;
 }
 
+bool mixed(const adafac_ctx* c) { return c->opts.precision == ADAFAC_PREC_FP32_REFINED; }
+
 // Lay out every device array inside the workspace; with base == nullptr only sizes.
 size_t layout(adafac_ctx* c, char* base) {
   size_t off = 0;
@@ -118,45 +135,61 @@ size_t layout(adafac_ctx* c, char* base) {
   };
   const int d = c->dim;
   const int ns = d == 2 ? 9 : 27;
-  c->eps_dev = reinterpret_cast<double*>(take(sizeof(double) * c->ops.eps.size()));
-  c->rt = reinterpret_cast<double*>(take(sizeof(double) * 125));
-  for (int l = c->lmin; l <= c->L; ++l) {
-    const HostLevel& hl = c->ops.lev[l];
-    LevelView<double>& v = c->v64[l];
-    v = LevelView<double>{};
-    v.n = hl.n;
-    v.nv = hl.nv;
-    v.h = hl.h;
-    v.hd = std::pow(hl.h, d);
-    v.hdm2 = std::pow(hl.h, d - 2);
-    v.fem = hl.fem ? 1 : 0;
-    v.nb = c->ops.nb;
-    v.bs = hl.fem ? ipow3(l - c->ops.k) : 1;
-    v.eps = (c->ops.nb == 1 && c->ops.eps[0] == 1.0) ? nullptr : c->eps_dev;
-    size_t nvx = hl.nverts;
-    if (!hl.fem) {
-      v.st = reinterpret_cast<double*>(take(sizeof(double) * nvx * ns));
-      v.dg = reinterpret_cast<double*>(take(sizeof(double) * nvx));
+  const bool mp = mixed(c);
+  auto views = [&](auto& H, auto tag, bool coarse_arrays) {
+    using T = decltype(tag);
+    const bool unit = c->ops.nb == 1 && c->ops.eps[0] == 1.0;
+    H.eps = reinterpret_cast<T*>(take(sizeof(T) * c->ops.eps.size()));
+    for (int l = c->lmin; l <= c->L; ++l) {
+      const HostLevel& hl = c->ops.lev[l];
+      LevelView<T>& v = H.v[l];
+      v = LevelView<T>{};
+      v.n = hl.n;
+      v.nv = hl.nv;
+      v.h = T(hl.h);
+      v.hd = T(std::pow(hl.h, d));
+      v.hdm2 = T(std::pow(hl.h, d - 2));
+      v.fem = hl.fem ? 1 : 0;
+      v.nb = c->ops.nb;
+      v.bs = hl.fem ? ipow3(l - c->ops.k) : 1;
+      v.eps = unit ? nullptr : H.eps;
+      if (!coarse_arrays && l < c->L) continue;
+      const size_t nvx = hl.nverts;
+      if (!hl.fem) {
+        v.st = reinterpret_cast<T*>(take(sizeof(T) * nvx * ns));
+        v.dg = reinterpret_cast<T*>(take(sizeof(T) * nvx));
+      }
+      if (!hl.pw.empty()) v.pw = reinterpret_cast<T*>(take(sizeof(T) * nvx * (1u << d)));
+      if (l < c->L) {
+        v.u = reinterpret_cast<T*>(take(sizeof(T) * nvx));
+        v.rr = reinterpret_cast<T*>(take(sizeof(T) * nvx));
+        v.bt = reinterpret_cast<T*>(take(sizeof(T) * nvx));
+        v.bf = reinterpret_cast<T*>(take(sizeof(T) * nvx));
+        v.r = reinterpret_cast<T*>(take(sizeof(T) * nvx));
+        v.S = reinterpret_cast<T*>(take(sizeof(T) * nvx));
+        v.ic = reinterpret_cast<T*>(take(sizeof(T) * nvx));
+      }
     }
-    if (!hl.pw.empty()) v.pw = reinterpret_cast<double*>(take(sizeof(double) * nvx * (1u << d)));
-    if (l < c->L) {
-      v.u = reinterpret_cast<double*>(take(sizeof(double) * nvx));
-      v.rr = reinterpret_cast<double*>(take(sizeof(double) * nvx));
-      v.bt = reinterpret_cast<double*>(take(sizeof(double) * nvx));
-      v.bf = reinterpret_cast<double*>(take(sizeof(double) * nvx));
-      v.r = reinterpret_cast<double*>(take(sizeof(double) * nvx));
-      v.S = reinterpret_cast<double*>(take(sizeof(double) * nvx));
-      v.ic = reinterpret_cast<double*>(take(sizeof(double) * nvx));
-    }
+    const size_t nvL = c->ops.lev[c->L].nverts;
+    H.ufine[0] = reinterpret_cast<T*>(take(sizeof(T) * nvL));
+    H.ufine[1] = reinterpret_cast<T*>(take(sizeof(T) * nvL));
+    H.bfine = reinterpret_cast<T*>(take(sizeof(T) * nvL));
+  };
+  views(c->h64, double{}, !mp);
+  c->h64.rfine = mp ? nullptr : reinterpret_cast<double*>(take(sizeof(double) * c->ops.lev[c->L].nverts));
+  if (mp) {
+    views(c->h32, float{}, true);
+    c->h32.rfine = reinterpret_cast<float*>(take(sizeof(float) * c->ops.lev[c->L].nverts));
+    c->ezero = reinterpret_cast<float*>(take(sizeof(float) * c->ops.lev[c->L].nverts));
+  } else {
+    c->h32 = Hier<float>{};
+    c->ezero = nullptr;
   }
-  size_t nvL = c->ops.lev[c->L].nverts;
-  c->ufine[0] = reinterpret_cast<double*>(take(sizeof(double) * nvL));
-  c->ufine[1] = reinterpret_cast<double*>(take(sizeof(double) * nvL));
-  c->bfine = reinterpret_cast<double*>(take(sizeof(double) * nvL));
-  c->rfine = reinterpret_cast<double*>(take(sizeof(double) * nvL));
   c->npartials = std::max<size_t>(kNormBlocks, fine_sweep_partials(d, ipow3(c->L)));
   c->partials = reinterpret_cast<double*>(take(sizeof(double) * 2 * c->npartials));
   c->norms = reinterpret_cast<double*>(take(sizeof(double) * 2 * kMaxHist));
+  c->scratch_norm = reinterpret_cast<double*>(take(sizeof(double) * 2));
+  c->norm0 = reinterpret_cast<double*>(take(sizeof(double) * 2));
   return (off + 255) & ~size_t(255);
 }
 
@@ -196,105 +229,187 @@ int record_stop(adafac_ctx* c) {
 #endif
 constexpr int kCoarseSweepMinN = ADAFAC_COARSE_SWEEP_MIN_N;
 
-// One FP64 cycle.  Cycle n: residual (and norms) of iterate n, FAS restriction cascade,
-// coarse corrections, prolongation; iterate n+1 lands in ufine[1-cur].
-//   finest level   single-pass sweep (deferred prolongation of the previous cycle's coarse
-//                  corrections, residual, Jacobi, injection, R and R~), or one kernel per step;
-//   coarse levels  the same tiled sweep in FAS mode where the level allows it (3D, 27 | 3^l,
-//                  Q1 operator, d-linear transfer), else one thread per vertex gathering from
-//                  the finer level; the smallest levels together in one workgroup;
-//   prolongation   S_l += P S_{l-1} upwards; the finest level's share is added by the next
-//                  sweep (or the flush).
-int run_cycle64(adafac_ctx* c) {
+// One adAFAC cycle in the arithmetic of T on hierarchy H: residual (and norms into norm_out)
+// of the current finest iterate, FAS restriction cascade, coarse corrections, prolongation; the
+// next iterate lands in H.ufine[1 - H.cur].  uin_zero (may be nullptr) replaces the current
+// iterate by a zero lattice (first inner cycle of a defect-correction step).
+template <typename T>
+int run_cycle(adafac_ctx* c, Hier<T>& H, double* norm_out, const T* uin_zero) {
   const int d = c->dim, L = c->L, lmin = c->lmin;
   const adafac_opts& o = c->opts;
   const int damping = o.damping;
   const int pi = damping == ADAFAC_DAMP_PI;
-  double* uin = c->ufine[c->cur];
-  double* uout = c->ufine[1 - c->cur];
-  LevelView<double> F = c->v64[L];
-  F.u = uin;
-  F.r = c->rfine;
-  LevelView<double> Lm1 = L > lmin ? c->v64[L - 1] : LevelView<double>{};
+  const T omega = T(o.omega), omega_t = T(o.omega_tilde);
+  const T* uin = uin_zero ? uin_zero : H.ufine[H.cur];
+  T* uout = H.ufine[1 - H.cur];
+  LevelView<T> F = H.v[L];
+  F.u = const_cast<T*>(uin);
+  F.r = H.rfine;
+  LevelView<T> Lm1 = L > lmin ? H.v[L - 1] : LevelView<T>{};
   int nparts = kNormBlocks;
   int rc;
   // adAFAC-PI reads and writes the injected fine correction in the same sweep: one kernel per step
   const bool fused = o.fused && L > lmin && !pi && fused_ok(c);
+  const bool pend = H.pending && !uin_zero;
   if ((rc = record_start(c))) return rc;
   if (fused) {
-    HIPCHK(c, launch_fine_sweep<double>(d, F, Lm1, uin, uout, c->bfine, c->rts64, o.omega, damping,
-                                        c->pending ? 1 : 0, c->partials, &nparts, c->stream));
+    HIPCHK(c, launch_fine_sweep<T>(d, F, Lm1, uin, uout, H.bfine, H.rts, omega, damping, pend ? 1 : 0,
+                                   c->partials, &nparts, c->stream));
   } else {
-    HIPCHK(c, launch_fine_residual<double>(d, F, uin, uout, c->bfine, c->rfine, pi ? Lm1.ic : nullptr,
-                                           Lm1.nv, o.omega, pi, c->partials, kNormBlocks, c->stream));
+    HIPCHK(c, launch_fine_residual<T>(d, F, uin, uout, H.bfine, H.rfine, pi ? Lm1.ic : nullptr, Lm1.nv, omega,
+                                      pi, c->partials, kNormBlocks, c->stream));
   }
   if ((rc = record_stop(c))) return rc;
-  double* norm_out = c->norms + 2 * (c->ncyc % kMaxHist);
-  auto cscale_of = [&](int l) { return damping == ADAFAC_DAMP_EXP ? std::pow(o.omega_hat, L - l) : 1.0; };
+  auto cscale_of = [&](int l) { return T(damping == ADAFAC_DAMP_EXP ? std::pow(o.omega_hat, L - l) : 1.0); };
   // smallest levels lo..hi for the single-workgroup kernel
   int hi = lmin - 1;
   for (int l = lmin; l < L && l - lmin < kMaxSmall && nverts_of(d, l) <= kSmallVerts; ++l) hi = l;
   bool fed = fused;               // level l's u, R r and R~ r already written by the finer level
   for (int l = L - 1; l > hi; --l) {
-    const bool sweep = !pi && fed && l > lmin && c->v64[l].n >= kCoarseSweepMinN && sweep_level_ok(d, c->v64[l]);
+    const bool sweep = !pi && fed && l > lmin && H.v[l].n >= kCoarseSweepMinN &&
+                       sweep_level_ok(d, H.v[l].n, H.v[l].fem, H.v[l].pw != nullptr);
     if (sweep) {
-      HIPCHK(c, launch_coarse_sweep<double>(d, c->v64[l], c->v64[l - 1], c->rts64, o.omega, o.omega_tilde,
-                                            cscale_of(l), damping, c->stream));
+      HIPCHK(c, launch_coarse_sweep<T>(d, H.v[l], H.v[l - 1], H.rts, omega, omega_t, cscale_of(l), damping,
+                                       c->stream));
     } else {
-      LevelView<double> Fv = c->v64[l + 1];
-      if (l + 1 == L) { Fv.u = uin; Fv.r = c->rfine; }
-      LevelView<double> Cm = l > lmin ? c->v64[l - 1] : LevelView<double>{};
-      HIPCHK(c, launch_level_update<double>(d, c->v64[l], Fv, Cm, c->rts64, o.omega, o.omega_tilde,
-                                            cscale_of(l), damping, fed ? 0 : 1, c->stream));
+      LevelView<T> Fv = H.v[l + 1];
+      if (l + 1 == L) { Fv.u = const_cast<T*>(uin); Fv.r = H.rfine; }
+      LevelView<T> Cm = l > lmin ? H.v[l - 1] : LevelView<T>{};
+      HIPCHK(c, launch_level_update<T>(d, H.v[l], Fv, Cm, H.rts, omega, omega_t, cscale_of(l), damping,
+                                       fed ? 0 : 1, c->stream));
     }
     fed = sweep;
   }
   if (hi >= lmin) {
-    SmallLevelsArgs<double> a{};
+    SmallLevelsArgs<T> a{};
     a.lo = lmin;
     a.hi = hi;
     for (int l = lmin - 1; l <= hi + 1; ++l) {
-      LevelView<double> v = (l >= lmin) ? c->v64[l] : LevelView<double>{};
-      if (l == L) { v.u = uin; v.r = c->rfine; }
+      LevelView<T> v = (l >= lmin) ? H.v[l] : LevelView<T>{};
+      if (l == L) { v.u = const_cast<T*>(uin); v.r = H.rfine; }
       a.lv[l - lmin + 1] = v;
     }
     for (int l = lmin; l <= hi; ++l) {
       a.gather[l - lmin] = (l == hi && fed) ? 0 : 1;
       a.cscale[l - lmin] = cscale_of(l);
     }
-    a.rts = c->rts64;
-    a.omega = o.omega;
-    a.omega_t = o.omega_tilde;
+    a.rts = H.rts;
+    a.omega = omega;
+    a.omega_t = omega_t;
     a.damping = damping;
     a.partials = c->partials;
     a.nparts = nparts;
     a.norm_out = norm_out;
-    HIPCHK(c, launch_small_levels<double>(d, a, 0, c->stream));
+    HIPCHK(c, launch_small_levels<T>(d, a, 0, c->stream));
   } else {
     HIPCHK(c, launch_norm_finalize(c->partials, nparts, norm_out, c->stream));
   }
   for (int l = std::max(hi + 1, lmin + 1); l < L; ++l)
-    HIPCHK(c, launch_prolong_add<double>(d, c->v64[l], c->v64[l - 1], c->v64[l].S, c->v64[l - 1].S,
-                                         pi ? c->v64[l - 1].ic : nullptr, c->stream));
+    HIPCHK(c, launch_prolong_add<T>(d, H.v[l], H.v[l - 1], H.v[l].S, H.v[l - 1].S,
+                                    pi ? H.v[l - 1].ic : nullptr, c->stream));
   if (fused) {
-    c->pending = true;       // P S_{L-1} enters the next sweep (or the flush)
-  } else if (L > lmin) {
-    HIPCHK(c, launch_prolong_add<double>(d, c->v64[L], c->v64[L - 1], uout, c->v64[L - 1].S,
-                                         pi ? c->v64[L - 1].ic : nullptr, c->stream));
+    H.pending = true;        // P S_{L-1} enters the next sweep (or the flush)
+  } else {
+    H.pending = false;
+    if (L > lmin)
+      HIPCHK(c, launch_prolong_add<T>(d, H.v[L], H.v[L - 1], uout, H.v[L - 1].S,
+                                      pi ? H.v[L - 1].ic : nullptr, c->stream));
   }
-  c->cur = 1 - c->cur;
+  H.cur = 1 - H.cur;
+  return ADAFAC_OK;
+}
+
+// Add the pending prolongated coarse correction to the current FP64 iterate (FP64 form), or
+// the pending inner correction e + P S_{L-1} to the FP64 solution (FP32_REFINED).
+int flush(adafac_ctx* c) {
+  const int L = c->L;
+  if (mixed(c)) {
+    if (!c->e_pending) return ADAFAC_OK;
+    Hier<float>& H = c->h32;
+    const float* S = (H.pending && L > c->lmin) ? H.v[L - 1].S : nullptr;
+    LevelView<float> C = L > c->lmin ? H.v[L - 1] : LevelView<float>{};
+    HIPCHK(c, launch_accumulate(c->dim, H.v[L], C, c->h64.ufine[c->h64.cur], H.ufine[H.cur], S, c->stream));
+    H.pending = false;
+    c->e_pending = false;
+    return ADAFAC_OK;
+  }
+  Hier<double>& H = c->h64;
+  if (!H.pending) return ADAFAC_OK;
+  const bool pi = c->opts.damping == ADAFAC_DAMP_PI;
+  HIPCHK(c, launch_prolong_add<double>(c->dim, H.v[L], H.v[L - 1], H.ufine[H.cur], H.v[L - 1].S,
+                                       pi ? H.v[L - 1].ic : nullptr, c->stream));
+  H.pending = false;
+  return ADAFAC_OK;
+}
+
+// FP64 form: one cycle.  FP32_REFINED: the FP64 part of an outer step, i.e. the pending inner
+// correction added to u and the FP64 defect r = b - A u with its norms (the norms of the outer
+// iterate), stored in FP32 as the right-hand side of the next inner solve.
+int run_outer(adafac_ctx* c) {
+  double* norm_out = c->norms + 2 * (c->ncyc % kMaxHist);
+  if (!mixed(c)) {
+    int rc = run_cycle<double>(c, c->h64, norm_out, nullptr);
+    if (rc) return rc;
+  } else {
+    int rc = flush(c);
+    if (rc) return rc;
+    HIPCHK(c, launch_defect(c->dim, c->h64.v[c->L], c->h64.ufine[c->h64.cur], c->h64.bfine, c->h32.bfine,
+                            c->partials, kNormBlocks, c->stream));
+    HIPCHK(c, launch_norm_finalize(c->partials, kNormBlocks, norm_out, c->stream));
+  }
+  if (c->ncyc == 0)
+    HIPCHK(c, hipMemcpyAsync(c->norm0, norm_out, 2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   c->ncyc += 1;
   return ADAFAC_OK;
 }
 
-// Add the pending prolongated coarse correction to the current iterate.
-int flush(adafac_ctx* c) {
-  if (!c->pending) return ADAFAC_OK;
-  const int L = c->L;
-  const bool pi = c->opts.damping == ADAFAC_DAMP_PI;
-  HIPCHK(c, launch_prolong_add<double>(c->dim, c->v64[L], c->v64[L - 1], c->ufine[c->cur], c->v64[L - 1].S,
-                                       pi ? c->v64[L - 1].ic : nullptr, c->stream));
-  c->pending = false;
+// FP32_REFINED: inner_k FP32 cycles on A e = r from e = 0; the correction stays pending.
+int run_inner(adafac_ctx* c) {
+  Hier<float>& H = c->h32;
+  H.pending = false;
+  for (int j = 0; j < c->opts.inner_k; ++j) {
+    int rc = run_cycle<float>(c, H, c->scratch_norm, j == 0 ? c->ezero : nullptr);
+    if (rc) return rc;
+  }
+  c->e_pending = true;
+  return ADAFAC_OK;
+}
+
+// One step as adafac_cycle defines it: a cycle, or an outer step with its inner solve.
+int run_step(adafac_ctx* c) {
+  int rc = run_outer(c);
+  if (rc || !mixed(c)) return rc;
+  return run_inner(c);
+}
+
+template <typename T>
+int upload_ops(adafac_ctx* c, Hier<T>& H, bool coarse) {
+  const int ns = c->dim == 2 ? 9 : 27;
+  auto put = [&](T* dst, const std::vector<double>& src) -> int {
+    if (std::is_same<T, double>::value) {
+      HIPCHK(c, hipMemcpyAsync(dst, src.data(), sizeof(double) * src.size(), hipMemcpyHostToDevice, c->stream));
+    } else {
+      std::vector<T> tmp(src.begin(), src.end());
+      HIPCHK(c, hipMemcpyAsync(dst, tmp.data(), sizeof(T) * tmp.size(), hipMemcpyHostToDevice, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));   // tmp goes out of scope
+    }
+    return ADAFAC_OK;
+  };
+  int rc;
+  if ((rc = put(H.eps, c->ops.eps))) return rc;
+  for (int l = c->lmin; l <= c->L; ++l) {
+    if (!coarse && l < c->L) continue;
+    const HostLevel& hl = c->ops.lev[l];
+    LevelView<T>& v = H.v[l];
+    if (!hl.fem) {
+      if ((rc = put(const_cast<T*>(v.st), hl.st))) return rc;
+      if ((rc = put(const_cast<T*>(v.dg), hl.dg))) return rc;
+    }
+    if (!hl.pw.empty() && (rc = put(const_cast<T*>(v.pw), hl.pw))) return rc;
+    (void)ns;
+  }
+  for (int i = 0; i < 5; ++i) H.rts.m[i] = T(c->ops.rt_m[i]);
+  H.rts.scale = T(c->ops.rt_scale);
   return ADAFAC_OK;
 }
 
@@ -367,7 +482,8 @@ int adafac_build_operators(adafac_ctx* c, const adafac_opts* opts) {
     return fail(c, ADAFAC_EINVAL, "unknown transfer");
   if (o.damping < ADAFAC_DAMP_JAC || o.damping > ADAFAC_DAMP_EXP) return fail(c, ADAFAC_EINVAL, "unknown damping");
   if (o.rtilde != ADAFAC_RTILDE_CONST_EPS1) return fail(c, ADAFAC_EUNSUPPORTED, "only the eps = 1 R~ is implemented");
-  if (o.precision != ADAFAC_PREC_FP64) return fail(c, ADAFAC_EUNSUPPORTED, "precision form not implemented");
+  if (o.precision != ADAFAC_PREC_FP64 && o.precision != ADAFAC_PREC_FP32_REFINED)
+    return fail(c, ADAFAC_EINVAL, "unknown precision form");
   if (!(o.omega > 0.0) || !(o.omega_tilde >= 0.0) || !(o.omega_hat > 0.0) || o.inner_k < 1)
     return fail(c, ADAFAC_EINVAL, "bad damping parameters");
   c->opts = o;
@@ -381,8 +497,6 @@ int adafac_build_operators(adafac_ctx* c, const adafac_opts* opts) {
   c->ops.eps = c->eps;
   std::string m = build_host_ops(c->ops, o.transfer == ADAFAC_TRANSFER_BOXMG, o.omega);
   if (!m.empty()) return fail(c, ADAFAC_EINVAL, m);
-  for (int i = 0; i < 5; ++i) c->rts64.m[i] = c->ops.rt_m[i];
-  c->rts64.scale = c->ops.rt_scale;
   c->built = true;
   c->bound = false;
   c->ws_need = layout(c, nullptr);
@@ -409,24 +523,9 @@ int adafac_bind(adafac_ctx* c, void* ws, size_t bytes, void* stream) {
   layout(c, c->ws);
   const int d = c->dim;
   HIPCHK(c, hipMemsetAsync(c->ws, 0, need, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->eps_dev, c->ops.eps.data(), sizeof(double) * c->ops.eps.size(),
-                           hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->rt, c->ops.rtilde.data(), sizeof(double) * c->ops.rtilde.size(),
-                           hipMemcpyHostToDevice, c->stream));
-  const int ns = d == 2 ? 9 : 27;
-  for (int l = c->lmin; l <= c->L; ++l) {
-    const HostLevel& hl = c->ops.lev[l];
-    LevelView<double>& v = c->v64[l];
-    if (!hl.fem) {
-      HIPCHK(c, hipMemcpyAsync(const_cast<double*>(v.st), hl.st.data(), sizeof(double) * hl.nverts * ns,
-                               hipMemcpyHostToDevice, c->stream));
-      HIPCHK(c, hipMemcpyAsync(const_cast<double*>(v.dg), hl.dg.data(), sizeof(double) * hl.nverts,
-                               hipMemcpyHostToDevice, c->stream));
-    }
-    if (!hl.pw.empty())
-      HIPCHK(c, hipMemcpyAsync(const_cast<double*>(v.pw), hl.pw.data(), sizeof(double) * hl.pw.size(),
-                               hipMemcpyHostToDevice, c->stream));
-  }
+  int rc = upload_ops<double>(c, c->h64, !mixed(c));
+  if (!rc && mixed(c)) rc = upload_ops<float>(c, c->h32, true);
+  if (rc) return rc;
   // load vector with lumped mass: h^d f on interior vertices of the uniform finest level
   const HostLevel& fl = c->ops.lev[c->L];
   std::vector<double> b(fl.nverts, 0.0);
@@ -441,11 +540,12 @@ int adafac_bind(adafac_ctx* c, void* ws, size_t bytes, void* stream) {
     }
     if (in) b[i] = hd * c->f[i];
   }
-  HIPCHK(c, hipMemcpyAsync(c->bfine, b.data(), sizeof(double) * b.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->h64.bfine, b.data(), sizeof(double) * b.size(), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  c->cur = 0;
-  c->pending = false;
+  c->h64.cur = c->h32.cur = 0;
+  c->h64.pending = c->h32.pending = c->e_pending = false;
   c->ncyc = 0;
+  c->r0 = -1.0;
   c->bound = true;
   return ADAFAC_OK;
 }
@@ -455,7 +555,7 @@ int adafac_cycle(adafac_ctx* c, int ncycles) {
   if (!ready(c)) return fail(c, ADAFAC_ESTATE, "bind first");
   if (ncycles < 0) return fail(c, ADAFAC_EINVAL, "ncycles < 0");
   for (int i = 0; i < ncycles; ++i) {
-    int rc = run_cycle64(c);
+    int rc = run_step(c);
     if (rc) return rc;
   }
   return ADAFAC_OK;
@@ -481,23 +581,27 @@ int adafac_solve(adafac_ctx* c, double rel_tol, int max_cycles, int* cycles_done
   if (!ready(c)) return fail(c, ADAFAC_ESTATE, "bind first");
   if (!(rel_tol >= 0.0) || max_cycles < 0) return fail(c, ADAFAC_EINVAL, "bad tolerance or cycle cap");
   int done = 0, rc = ADAFAC_OK;
-  const int start = c->ncyc;
-  double r0 = -1.0;
   for (; done < max_cycles; ++done) {
-    if ((rc = run_cycle64(c))) break;
+    // norms of iterate ncyc (FP64 cycle or FP64 defect of the outer iterate)
+    if ((rc = run_outer(c))) break;
     double l2 = 0, li = 0;
     if ((rc = adafac_residual(c, c->ncyc - 1, &l2, &li))) break;
-    if (c->ncyc - 1 == 0 || r0 < 0) {
-      double r00 = 0;
-      if ((rc = adafac_residual(c, start == 0 ? 0 : 0, &r00, nullptr))) break;
-      r0 = r00;
+    if (c->r0 < 0) {
+      HIPCHK(c, hipMemcpyAsync(&c->r0, c->norm0, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
     }
-    if (!std::isfinite(l2) || l2 > 1e3 * r0) {
+    if (!std::isfinite(l2) || l2 > 1e3 * c->r0) {
       ++done;
       rc = fail(c, ADAFAC_EDIVERGED, "residual diverged");
       break;
     }
-    if (r0 == 0.0 || l2 / r0 <= rel_tol) { ++done; break; }
+    if (c->r0 == 0.0 || l2 / c->r0 <= rel_tol) {
+      // FP64: the cycle that measured iterate n also produced n+1; FP32_REFINED: the outer
+      // iterate itself met the tolerance and no inner solve follows
+      ++done;
+      break;
+    }
+    if (mixed(c) && (rc = run_inner(c))) break;
   }
   if (cycles_done) *cycles_done = done;
   int frc = flush(c);
@@ -512,7 +616,7 @@ int adafac_get_solution(adafac_ctx* c, double* u, size_t n) {
   if (!u || n != nverts_of(c->dim, c->L)) return fail(c, ADAFAC_EINVAL, "u: wrong size");
   int rc = flush(c);
   if (rc) return rc;
-  HIPCHK(c, hipMemcpyAsync(u, c->ufine[c->cur], sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(u, c->h64.ufine[c->h64.cur], sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return ADAFAC_OK;
 }
@@ -533,10 +637,11 @@ int adafac_set_solution(adafac_ctx* c, const double* u, size_t n) {
     if (!std::isfinite(v[i])) return fail(c, ADAFAC_EINVAL, "u: non-finite value");
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->ufine[c->cur], v.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->h64.ufine[c->h64.cur], v.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  c->pending = false;
+  c->h64.pending = c->h32.pending = c->e_pending = false;
   c->ncyc = 0;
+  c->r0 = -1.0;
   return ADAFAC_OK;
 }
 
@@ -545,7 +650,8 @@ int adafac_get_level(adafac_ctx* c, int level, int which, double* out, size_t n)
   if (!ready(c)) return fail(c, ADAFAC_ESTATE, "bind first");
   if (level < c->lmin || level >= c->L) return fail(c, ADAFAC_EINVAL, "level out of range");
   if (!out || n != nverts_of(c->dim, level)) return fail(c, ADAFAC_EINVAL, "out: wrong size");
-  const LevelView<double>& v = c->v64[level];
+  if (mixed(c)) return fail(c, ADAFAC_ESTATE, "level arrays are kept in the FP64 form only");
+  const LevelView<double>& v = c->h64.v[level];
   const double* src = nullptr;
   switch (which) {
     case 0: src = v.u; break;

@@ -26,6 +26,8 @@
 // correction in the same pass and therefore runs on the one-kernel-per-step path.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "adafac.h"
 #include "adafac_internal.hpp"
 #include "kernels_common.hpp"
@@ -126,19 +128,69 @@ struct Sweep3dArgs {
   T omega_t, cscale;
 };
 
-template <typename T, bool VAREPS>
+// Lattice loads and stores of the 3D sweep through a buffer resource: the per-lane column
+// offset stays in one VGPR and the plane offset is a scalar, so no 64-bit address arithmetic
+// is spent per plane.
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+template <typename T>
+struct Lattice;
+template <>
+struct Lattice<double> {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ Lattice(const double* p, unsigned bytes)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), 0, int(bytes), 0x00020000)) {}
+  __device__ __forceinline__ double ld(unsigned voff, unsigned soff) const {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  }
+  __device__ __forceinline__ void st_stream(double v, unsigned voff, unsigned soff) const {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, voff, soff, 2 /* nt */);
+  }
+};
+template <>
+struct Lattice<float> {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ Lattice(const float* p, unsigned bytes)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), 0, int(bytes), 0x00020000)) {}
+  __device__ __forceinline__ float ld(unsigned voff, unsigned soff) const {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  }
+  __device__ __forceinline__ void st_stream(float v, unsigned voff, unsigned soff) const {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 2 /* nt */);
+  }
+};
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// Lanes that run the per-plane restriction and interpolation passes: disjoint wavefronts, so
+// that no wavefront carries more than one of them on top of its column.
+constexpr int XP0 = 0;      // x pass: RW * NCO = 261 lanes, wavefronts 0-4
+constexpr int YP0 = 320;    // y pass: NCO^2 = 81 lanes, wavefronts 5-6
+constexpr int BL0 = 448;    // S interpolation: CW^2 = 144 lanes, wavefronts 7-9
+static_assert(RW * NCO <= YP0 && YP0 + NCO * NCO <= BL0 && BL0 + CW * CW <= NT3, "pass lanes overlap");
+
+// The sweep marches z in steps of one fine plane; three steps make one coarse layer.  Step p
+// (ring slot K = (p - zs) mod 3, a compile-time constant because zs is a multiple of 3):
+//   build u plane p in LDS (plus the pending S interpolated to it),
+//   residual of plane p-2 (u planes p-3..p-1), Jacobi update, norm partials,
+//   x pass of plane p-3, y pass of plane p-4 (coarse plane accumulation),
+//   S interpolated to plane p+1,
+// then one barrier.  Every per-plane LDS buffer is indexed by its plane's slot.  Steps of the
+// pipeline's fill and drain carry the range checks (CK); the steady state carries none.
+template <typename T, bool VAREPS, bool COARSE, bool PEND>
 __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_fine_sweep3d(Sweep3dArgs<T> a) {
-  static_assert(NT3 >= NU, "one thread per ring column");
-  // one barrier per plane: every per-plane buffer written in a step is read in the next one
-  __shared__ T Ub[2][NU];                // u planes, by plane parity
-  __shared__ T Rb[3][NR];                // residual planes, by plane index mod 3
-  __shared__ T Xw[2][RW * NCO];          // x passes, by plane parity
-  __shared__ T Xm[2][RW * NCO];
-  __shared__ T Sb[(MAXTZ / 3 + 3) * CW * CW];
-  __shared__ T Sz[2][CW * CW];           // S blended to a fine plane, by plane parity
+  static_assert(NT3 >= NU, "one lane per ring column");
+  __shared__ T Ub[3][NT3];               // u planes (padded: every lane writes its slot)
+  __shared__ T Rb[3][NT3];               // residual planes
+  __shared__ T Xw[3][RW * NCO];          // x passes
+  __shared__ T Xm[3][RW * NCO];
+  __shared__ T Sb[PEND ? (MAXTZ / 3 + 3) * CW * CW : 1];
+  __shared__ T Sz[3][CW * CW];           // S interpolated to a fine plane
 
   const int n = a.n, nv = a.nv, nc = a.nc, nvc = a.nvc;
   const int plane = nv * nv;
+  const unsigned planeb = unsigned(plane * sizeof(T));
+  const unsigned latb = unsigned(size_t(plane) * nv * sizeof(T));
   const int nblk = a.ntx * a.ntx * a.ntz;
   const int t = xcd_remap(blockIdx.x, nblk);
   // x/y tiles fastest: the tiles of one XCD share their x/y halos in its L2 at the same time
@@ -149,11 +201,10 @@ __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_fine_sweep3d(S
   const int nsz = tz / 3 + 3;
   const int tid = threadIdx.x;
   const bool jac = a.damping == ADAFAC_DAMP_JAC;
-  const bool pend = a.apply_pending != 0;
   const T h = a.h;
+  const Lattice<T> U(a.uin, latb), B(a.b, latb), UO(a.uout, latb);
 
-  // (a) coarse correction block S
-  if (pend) {
+  if constexpr (PEND) {
     for (int i = tid; i < nsz * CW * CW; i += NT3) {
       const int lx = i % CW, ly = (i / CW) % CW, lz = i / (CW * CW);
       const int cx = cbx + lx, cy = cby + ly, cz = cbz + lz;
@@ -163,210 +214,246 @@ __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_fine_sweep3d(S
     }
   }
 
-  // this thread's u-ring column (loads are clamped into the lattice: values off the lattice
-  // only feed residuals of non-dof vertices, which are discarded)
-  const bool uact = tid < NU;
-  const int ui = uact ? tid : 0;
+  // this lane's u-ring column (loads are clamped into the lattice: values off the lattice only
+  // feed residuals of non-dof vertices, which are discarded)
+  const int ui = tid < NU ? tid : 0;
   const int ux = x0 - 3 + ui % UW, uy = y0 - 3 + ui / UW;
-  const int uoff = min(max(ux, 0), n) + nv * min(max(uy, 0), n);
-  const int ucx = min(max(ux, 0), n) / 3, ucy = min(max(uy, 0), n) / 3;
+  const int uxc = min(max(ux, 0), n), uyc = min(max(uy, 0), n);
+  const unsigned uoffb = unsigned((uxc + nv * uyc) * sizeof(T));
+  const int ucx = uxc / 3, ucy = uyc / 3;
   const int usi = (ucy - cby) * CW + ucx - cbx;
-  const int usx = min(max(ux, 0), n) - 3 * ucx, usy = min(max(uy, 0), n) - 3 * ucy;
+  const int usx = uxc - 3 * ucx, usy = uyc - 3 * ucy;
   const T wx0 = T(3 - usx) * T(1.0 / 3.0), wx1 = T(usx) * T(1.0 / 3.0);
   const T wy0 = T(3 - usy) * T(1.0 / 3.0), wy1 = T(usy) * T(1.0 / 3.0);
-  // this thread's residual column
+  // this lane's residual column
   const bool ract = tid < NR;
   const int rj = ract ? tid : 0;
   const int rx = rj % RW, ry = rj / RW;
   const int x = x0 - 2 + rx, y = y0 - 2 + ry;
   const bool rint = ract && x > 0 && x < n && y > 0 && y < n;
   const bool rown = rint && rx >= 2 && ry >= 2 && x < x0 + TX && y < y0 + TX;
-  const bool rcc = x % 3 == 0 && y % 3 == 0;
+  const bool rinj = rown && x % 3 == 0 && y % 3 == 0;
   const int roff = min(max(x, 0), n) + nv * min(max(y, 0), n);
+  const unsigned roffb = unsigned(roff * sizeof(T));
+  const int upos = (ry + 1) * UW + rx + 1;
 
-  // Carried per residual column (see header).  Poisson: u(z), D4(z) = sum of the four in-plane
-  // diagonal neighbours, F(z-1) and F(z) with F = 2 A4 + D4 (A4: the four in-plane axis
-  // neighbours); then A u(z) = h [8/3 u(z) - (2 D4(z) + F(z-1) + F(z+1)) / 12].  Variable eps:
-  // the contribution of the cell layer below, eps of that layer, and per quadrant the values the
+  // Carried per residual column.  Poisson: u(z), D4(z) = sum of the four in-plane diagonal
+  // neighbours, F(z-1) and F(z) with F = 2 A4 + D4 (A4: the four in-plane axis neighbours);
+  // then A u(z) = h [8/3 u(z) - (2 D4(z) + F(z-1) + F(z+1)) / 12].  Variable eps: the
+  // contribution of the cell layer below, eps of that layer, and per quadrant the values the
   // layer above needs.
   T own = T(0), c1 = T(0), c2 = T(0), c3 = T(0), epsprev = T(0);
   T dq[4] = {T(0), T(0), T(0), T(0)}, eq[4] = {T(0), T(0), T(0), T(0)};
-  // prefetch ring, three planes deep: slot k serves the steps p with (p - zs) % 3 == k
-  constexpr int PD = 3;
-  T pu[PD], pb[PD];
+  // prefetch ring: slot K holds u(p) and b(p-2) for the steps p of slot K
+  T pu[3], pb[3];
   T accR[2] = {T(0), T(0)}, accT[2] = {T(0), T(0)};
   double ssum = 0.0, smax = 0.0;
   const T wdiag = a.omega / (h * T(8.0 / 3.0));     // omega / D for eps = 1
 
-  auto uload = [&](int p) { return a.uin[min(max(p, 0), n) * plane + uoff]; };
-  auto bload = [&](int z) { return a.b[min(max(z, 0), n) * plane + roff]; };
-  auto blend_s = [&](int p) {   // Sz = S interpolated along z to fine plane p
-    if (pend && tid < CW * CW && p >= 0 && p <= n) {
-      const int cz = p / 3, sz = p - 3 * cz;
-      const T* s0 = &Sb[(cz - cbz) * CW * CW + tid];
-      Sz[p & 1][tid] = T(3 - sz) * T(1.0 / 3.0) * s0[0] + T(sz) * T(1.0 / 3.0) * s0[CW * CW];
-    }
-  };
-  auto mod3 = [](int v) { return (v % 3 + 3) % 3; };
-
   const int zs = z0 - 3, ze = z0 + tz;
+  auto uload = [&](int p) { return U.ld(uoffb, unsigned(min(max(p, 0), n)) * planeb); };
+  auto bload = [&](int p) { return B.ld(roffb, unsigned(min(max(p, 0), n)) * planeb); };
 #pragma unroll
-  for (int q = 0; q < PD; ++q) {
+  for (int q = 0; q < 3; ++q) {
     pu[q] = uload(zs + q);
     pb[q] = bload(zs + q - 1);
   }
-  __syncthreads();  // Sb ready
-  blend_s(zs);
-  __syncthreads();  // Sz[zs & 1] ready
 
-  // y pass of residual plane zr (its x pass done): R r and R~ r accumulated per coarse plane
-  auto y_pass = [&](int zr) {
-    if (tid < NCO * NCO) {
-      const T* xw = Xw[zr & 1];
-      const T* xm = Xm[zr & 1];
-      const T* rz = Rb[mod3(zr)];
-      const int ccx = tid % NCO, ccy = tid / NCO;
-      T W = T(0), Q = T(0), Y = T(0);
-#pragma unroll
-      for (int o = -2; o <= 2; ++o) {
-        const int row = 3 * ccy + 2 + o;
-        W += wlin<T>(o) * xw[row * NCO + ccx];
-        Q += a.rts.m[o + 2] * xm[row * NCO + ccx];
-        Y += a.rts.m[o + 2] * rz[row * RW + 3 * ccx + 2];
-      }
-      const T X = xm[(3 * ccy + 2) * NCO + ccx];
-      const int lo = zr >= 0 ? zr / 3 : -1;   // coarse plane at or below zr (zr >= -2)
-      const int m = zr - 3 * lo;              // 0, 1, 2
-      // R~: planar tensor products; the plane through the coarse vertex also carries Q
-      accR[0] += wlin<T>(m) * W;
-      if (jac) accT[0] += a.rts.scale * (a.rts.m[2 + m] * (X + Y) + (m == 0 ? Q : T(0)));
-      if (m) {
-        accR[1] += wlin<T>(3 - m) * W;
-        if (jac) accT[1] += a.rts.scale * a.rts.m[2 + 3 - m] * (X + Y);
-      }
-      if (m == 2) {
-        const int cz = lo;
-        const int cx = x0 / 3 + ccx, cy = y0 / 3 + ccy;
-        if (cz >= z0 / 3 && cz < (z0 + tz) / 3 && cx > 0 && cx < nc && cy > 0 && cy < nc && cz > 0 &&
-            cz < nc) {
-          const size_t ci = lin<3>(cx, cy, cz, nvc);
-          a.crr[ci] = accR[0];
-          a.cbt[ci] = accT[0];
+  // S interpolated along z to fine plane p, into slot KS (zero off the lattice)
+  auto blend_s = [&](int p, auto ks) {
+    constexpr int KS = decltype(ks)::value;
+    if constexpr (PEND) {
+      const int bt = tid - BL0;
+      if (bt >= 0 && bt < CW * CW) {
+        T v = T(0);
+        if (p >= 0 && p <= n) {
+          const int cz = p / 3, sz = p - 3 * cz;
+          const T* s0 = &Sb[(cz - cbz) * CW * CW + bt];
+          v = T(3 - sz) * T(1.0 / 3.0) * s0[0] + T(sz) * T(1.0 / 3.0) * s0[CW * CW];
         }
-        accR[0] = accR[1];
-        accT[0] = accT[1];
-        accR[1] = accT[1] = T(0);
+        Sz[KS][bt] = v;
       }
     }
   };
+  if constexpr (PEND) __syncthreads();  // Sb ready
+  blend_s(zs, IC<0>{});
+  __syncthreads();                       // Sz[0] ready
 
-  // the residual of plane p-1 needs u planes p-2, p-1, p (the carried sums hold p-2 and p-1)
-  auto residual = [&](int p, int k) {
-    const int z = p - 1;
-    const T* up = &Ub[p & 1][(ry + 1) * UW + rx + 1];
-    const T o_n = up[0];
-    const T ax_m = up[-1], ax_p = up[1], ay_m = up[-UW], ay_p = up[UW];
-    const T d_0 = up[-UW - 1], d_1 = up[-UW + 1], d_2 = up[UW - 1], d_3 = up[UW + 1];
-    T au, dinv;
-    const T uz = own;
-    if constexpr (!VAREPS) {
-      const T d4 = (d_0 + d_1) + (d_2 + d_3);
-      const T f = T(2) * ((ax_m + ax_p) + (ay_m + ay_p)) + d4;
-      // c1 = D4(z), c2 = F(z-1), c3 = F(z) for z = p-1; the new plane p brings F(z+1) = f
-      au = h * (T(8.0 / 3.0) * uz - T(1.0 / 12.0) * ((T(2) * c1 + c2) + f));
-      dinv = wdiag;
-      c1 = d4;
-      c2 = c3;
-      c3 = f;
-    } else {
-      // quadrants q = (sx, sy): 0 = (-,-), 1 = (+,-), 2 = (-,+), 3 = (+,+)
-      const T d_n[4] = {d_0, d_1, d_2, d_3};
-      const T e_n[4] = {ax_m + ay_m + d_0, ax_p + ay_m + d_1, ax_m + ay_p + d_2, ax_p + ay_p + d_3};
-      // eps of the four cells of layer z (between planes z and z+1) around the column
-      const int bx0 = min(max(x - 1, 0), n - 1) / a.bs, bx1 = min(max(x, 0), n - 1) / a.bs;
-      const int by0 = min(max(y - 1, 0), n - 1) / a.bs, by1 = min(max(y, 0), n - 1) / a.bs;
-      const int bz = min(max(z, 0), n - 1) / a.bs;
-      const T* eb = a.eps + size_t(bz) * a.nb * a.nb;
-      const T e4[4] = {eb[by0 * a.nb + bx0], eb[by0 * a.nb + bx1], eb[by1 * a.nb + bx0], eb[by1 * a.nb + bx1]};
-      T bc = T(0), tn = T(0);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        bc += e4[q] * (T(1.0 / 3.0) * uz - T(1.0 / 12.0) * (dq[q] + e_n[q]));
-        tn += e4[q] * (T(1.0 / 3.0) * o_n - T(1.0 / 12.0) * (d_n[q] + eq[q]));
+  auto step = [&](int p, auto ck, auto kk) {
+    constexpr bool CK = decltype(ck)::value != 0;
+    constexpr int K = decltype(kk)::value;
+    constexpr int K1 = (K + 1) % 3, K2 = (K + 2) % 3;
+    // (1) u plane p into slot K, plus the pending correction
+    if (!CK || p <= ze) {
+      T v = pu[K];
+      if constexpr (PEND) {
+        const T* s0 = &Sz[K][usi];
+        v += wy0 * (wx0 * s0[0] + wx1 * s0[1]) + wy1 * (wx0 * s0[CW] + wx1 * s0[CW + 1]);
       }
-      const T esl = (e4[0] + e4[1]) + (e4[2] + e4[3]);
-      au = h * (bc + c1);
-      dinv = a.omega / (h * T(1.0 / 3.0) * (esl + epsprev));
-      c1 = tn;
-      epsprev = esl;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        dq[q] = d_n[q];
-        eq[q] = e_n[q];
-      }
+      Ub[K][tid] = v;
     }
-    own = o_n;
-    T res = T(0);
-    if (p >= zs + 2 && rint && z > 0 && z < n) {
-      const bool own_pt = rown && z >= z0 && z < z0 + tz;
-      if (!a.coarse) {
-        res = pb[k] - au;
-        if (own_pt) {
-          __builtin_nontemporal_store(uz + dinv * res, &a.uout[z * plane + roff]);
-          const double rd = double(res);
-          ssum += rd * rd;
-          smax = fabs(rd) > smax ? fabs(rd) : smax;
-        }
+    pu[K] = CK ? uload(min(p + 3, ze)) : U.ld(uoffb, unsigned(p + 3) * planeb);
+    // (2) residual of plane z = p-2 from u planes p-3 (registers), p-2 (registers) and p-1 (slot K2)
+    if (!CK || (p - 1 >= zs && p - 1 <= ze)) {
+      const int z = p - 2;
+      const T* up = &Ub[K2][upos];
+      const T o_n = up[0];
+      const T ax_m = up[-1], ax_p = up[1], ay_m = up[-UW], ay_p = up[UW];
+      const T d_0 = up[-UW - 1], d_1 = up[-UW + 1], d_2 = up[UW - 1], d_3 = up[UW + 1];
+      T au, dinv;
+      const T uz = own;
+      if constexpr (!VAREPS) {
+        const T d4 = (d_0 + d_1) + (d_2 + d_3);
+        const T f = T(2) * ((ax_m + ax_p) + (ay_m + ay_p)) + d4;
+        au = h * (T(8.0 / 3.0) * uz - T(1.0 / 12.0) * ((T(2) * c1 + c2) + f));
+        dinv = wdiag;
+        c1 = d4;
+        c2 = c3;
+        c3 = f;
       } else {
-        const T bf = pb[k] + au;       // FAS right-hand side with the tau correction
-        res = bf - au;
-        if (own_pt) {
-          const int gi = z * plane + roff;
-          T sv = a.cscale * dinv * res;
-          if (jac) sv -= (a.omega_t / a.omega) * dinv * a.bt_in[gi];
-          a.sout[gi] = sv;
-          a.bfout[gi] = bf;
-          a.rout[gi] = res;
+        // quadrants q = (sx, sy): 0 = (-,-), 1 = (+,-), 2 = (-,+), 3 = (+,+)
+        const T d_n[4] = {d_0, d_1, d_2, d_3};
+        const T e_n[4] = {ax_m + ay_m + d_0, ax_p + ay_m + d_1, ax_m + ay_p + d_2, ax_p + ay_p + d_3};
+        // eps of the four cells of layer z (between planes z and z+1) around the column
+        const int bx0 = min(max(x - 1, 0), n - 1) / a.bs, bx1 = min(max(x, 0), n - 1) / a.bs;
+        const int by0 = min(max(y - 1, 0), n - 1) / a.bs, by1 = min(max(y, 0), n - 1) / a.bs;
+        const int bz = min(max(z, 0), n - 1) / a.bs;
+        const T* eb = a.eps + size_t(bz) * a.nb * a.nb;
+        const T e4[4] = {eb[by0 * a.nb + bx0], eb[by0 * a.nb + bx1], eb[by1 * a.nb + bx0], eb[by1 * a.nb + bx1]};
+        T bc = T(0), tn = T(0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          bc += e4[q] * (T(1.0 / 3.0) * uz - T(1.0 / 12.0) * (dq[q] + e_n[q]));
+          tn += e4[q] * (T(1.0 / 3.0) * o_n - T(1.0 / 12.0) * (d_n[q] + eq[q]));
+        }
+        const T esl = (e4[0] + e4[1]) + (e4[2] + e4[3]);
+        au = h * (bc + c1);
+        dinv = a.omega / (h * T(1.0 / 3.0) * (esl + epsprev));
+        c1 = tn;
+        epsprev = esl;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          dq[q] = d_n[q];
+          eq[q] = e_n[q];
         }
       }
-      if (own_pt && rcc && z % 3 == 0) a.cu[lin<3>(x / 3, y / 3, z / 3, nvc)] = uz;   // FAS injection
+      own = o_n;
+      T res = T(0);
+      const bool zin = !CK || (p - 1 >= zs + 2 && z > 0 && z < n);
+      if (zin && rint) {
+        const bool own_pt = rown && (!CK || (z >= z0 && z < z0 + tz));
+        if constexpr (!COARSE) {
+          res = pb[K2] - au;
+          if (own_pt) {
+            UO.st_stream(uz + dinv * res, roffb, unsigned(z) * planeb);
+            const double rd = double(res);
+            ssum += rd * rd;
+            smax = fabs(rd) > smax ? fabs(rd) : smax;
+          }
+        } else {
+          const T bf = pb[K2] + au;       // FAS right-hand side with the tau correction
+          res = bf - au;
+          if (own_pt) {
+            const int gi = z * plane + roff;
+            T sv = a.cscale * dinv * res;
+            if (jac) sv -= (a.omega_t / a.omega) * dinv * a.bt_in[gi];
+            a.sout[gi] = sv;
+            a.bfout[gi] = bf;
+            a.rout[gi] = res;
+          }
+        }
+        // FAS injection u_{L-1} = I u: planes z = p-2 with z = 0 mod 3 are the steps K = 2
+        if (K == 2 && own_pt && rinj) a.cu[lin<3>(x / 3, y / 3, z / 3, nvc)] = uz;
+      }
+      Rb[K1][tid] = res;
     }
-    if (ract) Rb[mod3(z)][tid] = res;
-  };
-
-  auto ubuild = [&](int p, int k) {   // u plane p (ring slot k) plus the pending correction
-    T v = pu[k];
-    if (pend) {
-      const T* s0 = &Sz[p & 1][usi];
-      v += wy0 * (wx0 * s0[0] + wx1 * s0[1]) + wy1 * (wx0 * s0[CW] + wx1 * s0[CW + 1]);
+    pb[K2] = CK ? bload(min(p + 1, ze)) : B.ld(roffb, unsigned(p + 1) * planeb);
+    // (3) x pass of residual plane p-3 (slot K)
+    if (!CK || (p - 3 >= zs + 1 && p - 3 <= ze - 1)) {
+      const int xt = tid - XP0;
+      if (xt >= 0 && xt < RW * NCO) {
+        const int yy = xt / NCO, ccx = xt % NCO;
+        const T* rp = &Rb[K][yy * RW + 3 * ccx + 2];
+        T sw = T(0), sm = T(0);
+#pragma unroll
+        for (int o = -2; o <= 2; ++o) {
+          sw += wlin<T>(o) * rp[o];
+          sm += a.rts.m[o + 2] * rp[o];
+        }
+        Xw[K][xt] = sw;
+        Xm[K][xt] = sm;
+      }
     }
-    if (uact) Ub[p & 1][tid] = v;
-  };
-
-  // Step p (one barrier): u plane p into LDS; residual of plane p-2 (u planes p-3..p-1 are in
-  // LDS or registers); x pass of plane p-3; y pass of plane p-4; S blended for plane p+1.
-  // Ring slot k = (p - zs) mod PD holds u(p) and b(p-2) and is refilled with u(p+PD), b(p+PD-2).
-  auto step = [&](int p, int k) {
-    // the refills are unconditional (planes clamped to the chunk) so that the compiler can
-    // count the loads in flight and wait only for the oldest one
-    if (p <= ze) ubuild(p, k);
-    pu[k] = uload(min(p + PD, ze));
-    const int kr = (k + PD - 1) % PD;          // slot that held u(p-1): it carries b(p-2)
-    if (p - 1 >= zs && p - 1 <= ze) residual(p - 1, kr);
-    pb[kr] = bload(min(p - 1 + PD - 1, ze));
-    if (p - 3 >= zs + 1 && p - 3 <= ze - 1) restrict_x_pass<T, NT3>(Rb[mod3(p - 3)], Xw[(p - 3) & 1], Xm[(p - 3) & 1], a.rts, tid);
-    if (p - 4 >= zs + 1 && p - 4 <= ze - 1) y_pass(p - 4);
-    if (p + 1 <= ze) blend_s(p + 1);
+    // (4) y pass of residual plane zr = p-4 (slot K2), accumulated into the coarse planes at
+    // or below and above it; m = zr - 3 floor(zr / 3) = K2 because zs = 0 mod 3
+    if (!CK || (p - 4 >= zs + 1 && p - 4 <= ze - 1)) {
+      const int yt = tid - YP0;
+      if (yt >= 0 && yt < NCO * NCO) {
+        constexpr int m = K2;
+        const int zr = p - 4;
+        const T* xw = Xw[K2];
+        const T* xm = Xm[K2];
+        const T* rz = Rb[K2];
+        const int ccx = yt % NCO, ccy = yt / NCO;
+        T W = T(0), Q = T(0), Y = T(0);
+#pragma unroll
+        for (int o = -2; o <= 2; ++o) {
+          const int row = 3 * ccy + 2 + o;
+          W += wlin<T>(o) * xw[row * NCO + ccx];
+          Q += a.rts.m[o + 2] * xm[row * NCO + ccx];
+          Y += a.rts.m[o + 2] * rz[row * RW + 3 * ccx + 2];
+        }
+        const T X = xm[(3 * ccy + 2) * NCO + ccx];
+        // R~: planar tensor products; the plane through the coarse vertex also carries Q
+        accR[0] += wlin<T>(m) * W;
+        if (jac) accT[0] += a.rts.scale * (a.rts.m[2 + m] * (X + Y) + (m == 0 ? Q : T(0)));
+        if constexpr (m != 0) {
+          accR[1] += wlin<T>(3 - m) * W;
+          if (jac) accT[1] += a.rts.scale * a.rts.m[2 + 3 - m] * (X + Y);
+        }
+        if constexpr (m == 2) {
+          const int cz = (zr - 2) / 3;        // coarse plane below zr (zr >= z0 - 1 >= -1)
+          const int cx = x0 / 3 + ccx, cy = y0 / 3 + ccy;
+          if (cz >= z0 / 3 && cz < (z0 + tz) / 3 && cx > 0 && cx < nc && cy > 0 && cy < nc &&
+              cz > 0 && cz < nc) {
+            const size_t ci = lin<3>(cx, cy, cz, nvc);
+            a.crr[ci] = accR[0];
+            a.cbt[ci] = accT[0];
+          }
+          accR[0] = accR[1];
+          accT[0] = accT[1];
+          accR[1] = accT[1] = T(0);
+        }
+      }
+    }
+    // (5) S interpolated to plane p+1 (slot K1)
+    if (!CK || p + 1 <= ze) blend_s(p + 1, IC<K1>{});
     __syncthreads();
   };
 
-  // steps zs .. ze+4 drain the pipeline (residuals end at plane ze-1, restriction two steps later)
-  for (int p = zs; p <= ze + 3; p += PD) {
-    step(p, 0);
-    step(p + 1, 1);
-    step(p + 2, 2);
+  // steps zs .. ze+3 drain the pipeline (residuals end at plane ze-1, restriction two steps later)
+  const int nit = (tz + 7 + 2) / 3;
+  const int ihi = (tz - 2) / 3;          // iterations 2..ihi need no range checks
+  int it = 0;
+  for (; it < min(2, nit); ++it) {
+    const int p = zs + 3 * it;
+    step(p, IC<1>{}, IC<0>{});
+    step(p + 1, IC<1>{}, IC<1>{});
+    step(p + 2, IC<1>{}, IC<2>{});
   }
-  if (!a.coarse) block_norm_partials(double(a.hd) * ssum, smax, a.partials);
+  for (; it <= ihi; ++it) {
+    const int p = zs + 3 * it;
+    step(p, IC<0>{}, IC<0>{});
+    step(p + 1, IC<0>{}, IC<1>{});
+    step(p + 2, IC<0>{}, IC<2>{});
+  }
+  for (; it < nit; ++it) {
+    const int p = zs + 3 * it;
+    step(p, IC<1>{}, IC<0>{});
+    step(p + 1, IC<1>{}, IC<1>{});
+    step(p + 2, IC<1>{}, IC<2>{});
+  }
+  if constexpr (!COARSE) block_norm_partials(double(a.hd) * ssum, smax, a.partials);
 }
 
 template <typename T, bool VAREPS>
@@ -509,15 +596,28 @@ static int pick_tz(int n) {
 template <typename T>
 static hipError_t launch_sweep3d(const Sweep3dArgs<T>& a, bool var, hipStream_t s) {
   const unsigned nb = unsigned(a.ntx * a.ntx * a.ntz);
-  if (var)
-    k_fine_sweep3d<T, true><<<nb, NT3, 0, s>>>(a);
-  else
-    k_fine_sweep3d<T, false><<<nb, NT3, 0, s>>>(a);
+  const bool pend = a.apply_pending != 0;
+  if (a.coarse) {
+    if (var)
+      k_fine_sweep3d<T, true, true, false><<<nb, NT3, 0, s>>>(a);
+    else
+      k_fine_sweep3d<T, false, true, false><<<nb, NT3, 0, s>>>(a);
+  } else if (var) {
+    if (pend)
+      k_fine_sweep3d<T, true, false, true><<<nb, NT3, 0, s>>>(a);
+    else
+      k_fine_sweep3d<T, true, false, false><<<nb, NT3, 0, s>>>(a);
+  } else {
+    if (pend)
+      k_fine_sweep3d<T, false, false, true><<<nb, NT3, 0, s>>>(a);
+    else
+      k_fine_sweep3d<T, false, false, false><<<nb, NT3, 0, s>>>(a);
+  }
   return hipGetLastError();
 }
 
-bool sweep_level_ok(int d, const LevelView<double>& L) {
-  return d == 3 && L.fem && L.n % TX == 0 && !L.pw;
+bool sweep_level_ok(int d, int n, int fem, bool has_pw) {
+  return d == 3 && fem && n % TX == 0 && !has_pw;
 }
 
 // FAS update of a coarse level L (3^l >= 27 cells per axis, Q1 operator, d-linear transfer

@@ -137,8 +137,15 @@ __global__ void __launch_bounds__(256) k_level_update(LevelView<T> C, LevelView<
 // The smallest levels in one workgroup: the residual norms of the cycle (fixed-order reduction
 // of the finest-level partials), the FAS updates of levels hi .. lo (finest first), then the
 // prolongation S_l += P S_{l-1} for l = lo+1 .. hi, with a workgroup barrier between levels.
+// Lanes of the small-level workgroup: few enough that the 5^d gathers stay in registers.
+#ifndef ADAFAC_SMALL_THREADS
+#define ADAFAC_SMALL_THREADS 256
+#endif
+constexpr int kSmallThreads = ADAFAC_SMALL_THREADS;
+static_assert(kSmallThreads % 64 == 0 && kSmallThreads <= 1024, "whole wavefronts, at most 16");
+
 template <typename T, int D>
-__global__ void __launch_bounds__(1024) k_small_levels(SmallLevelsArgs<T> a) {
+__global__ void __launch_bounds__(kSmallThreads) k_small_levels(SmallLevelsArgs<T> a) {
   const int tid = threadIdx.x;
   const int lo = a.lo, hi = a.hi;
   auto nverts_of = [](const LevelView<T>& v) {
@@ -148,7 +155,7 @@ __global__ void __launch_bounds__(1024) k_small_levels(SmallLevelsArgs<T> a) {
     // fixed order: each lane sums a strided subset, then a fixed butterfly and wave order
     __shared__ double ws[16], wm[16];
     double s = 0.0, m = 0.0;
-    for (int i = tid; i < a.nparts; i += 1024) {
+    for (int i = tid; i < a.nparts; i += kSmallThreads) {
       s += a.partials[2 * i];
       m = fmax(m, a.partials[2 * i + 1]);
     }
@@ -164,7 +171,7 @@ __global__ void __launch_bounds__(1024) k_small_levels(SmallLevelsArgs<T> a) {
     __syncthreads();
     if (tid == 0) {
       double st = 0.0, mt = 0.0;
-      for (int w = 0; w < 16; ++w) {
+      for (int w = 0; w < kSmallThreads / 64; ++w) {
         st += ws[w];
         mt = fmax(mt, wm[w]);
       }
@@ -175,7 +182,7 @@ __global__ void __launch_bounds__(1024) k_small_levels(SmallLevelsArgs<T> a) {
   for (int l = hi; l >= lo; --l) {
     const LevelView<T>& C = a.lv[l - lo + 1];
     const size_t nverts = nverts_of(C);
-    for (size_t i = tid; i < nverts; i += 1024)
+    for (size_t i = tid; i < nverts; i += kSmallThreads)
       level_update_vertex<T, D>(C, a.lv[l - lo + 2], a.lv[l - lo], a.rts, a.omega, a.omega_t,
                                 a.cscale[l - lo], a.damping, a.gather[l - lo], i);
     __syncthreads();
@@ -186,7 +193,7 @@ __global__ void __launch_bounds__(1024) k_small_levels(SmallLevelsArgs<T> a) {
     const LevelView<T>& C = a.lv[l - lo];
     const int nv = F.nv;
     const size_t nverts = nverts_of(F);
-    for (size_t i = tid; i < nverts; i += 1024) {
+    for (size_t i = tid; i < nverts; i += kSmallThreads) {
       int x = int(i % nv), y = int((i / nv) % nv), z = D == 3 ? int(i / (size_t(nv) * nv)) : 0;
       if (!is_interior<D>(x, y, z, nv)) continue;
       F.S[i] += prolong_value<T, D>(F, C, x, y, z, C.S, pi ? C.ic : nullptr);
@@ -208,9 +215,70 @@ __global__ void __launch_bounds__(256) k_prolong_add(LevelView<T> F, LevelView<T
   dst[i] += prolong_value<T, D>(F, C, x, y, z, src, sub);
 }
 
+// FP32 cycles inside FP64 defect correction: the two FP64 steps of an outer iteration.
+//   accumulate  u <- u + (e + P S_{L-1}): the FP32 correction of the inner cycles (with the
+//               prolongation the fused sweep leaves pending) added to the FP64 solution
+//   defect      r = b - A_L u in FP64, stored rounded to FP32 as the inner right-hand side,
+//               with the FP64 norm partials of r
+template <int D>
+__global__ void __launch_bounds__(256) k_accumulate(LevelView<float> F, LevelView<float> C, double* __restrict__ u,
+                                                    const float* __restrict__ e, const float* __restrict__ S) {
+  const int nv = F.nv;
+  const size_t nverts = D == 2 ? size_t(nv) * nv : size_t(nv) * nv * nv;
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nverts) return;
+  int x = int(i % nv), y = int((i / nv) % nv), z = D == 3 ? int(i / (size_t(nv) * nv)) : 0;
+  if (!is_interior<D>(x, y, z, nv)) return;
+  float c = e[i];
+  if (S) c += prolong_value<float, D>(F, C, x, y, z, S, nullptr);
+  u[i] += double(c);
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_defect(LevelView<double> F, const double* __restrict__ u,
+                                                const double* __restrict__ b, float* __restrict__ r32,
+                                                double* __restrict__ partials) {
+  const int nv = F.nv;
+  const size_t nverts = D == 2 ? size_t(nv) * nv : size_t(nv) * nv * nv;
+  double ssum = 0.0, smax = 0.0;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nverts;
+       i += size_t(gridDim.x) * blockDim.x) {
+    int x = int(i % nv), y = int((i / nv) % nv), z = D == 3 ? int(i / (size_t(nv) * nv)) : 0;
+    if (!is_interior<D>(x, y, z, nv)) continue;
+    double dg;
+    const double au = apply_level_op<double, D>(F, x, y, z, dg, [&](int dx, int dy, int dz) {
+      return u[lin<D>(x + dx, y + dy, z + dz, nv)];
+    });
+    const double res = b[i] - au;
+    r32[i] = float(res);
+    ssum += F.hd * res * res;
+    smax = fmax(smax, fabs(res));
+  }
+  block_norm_partials(ssum, smax, partials);
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+hipError_t launch_accumulate(int d, const LevelView<float>& F, const LevelView<float>& C, double* u,
+                             const float* e, const float* S, hipStream_t s) {
+  size_t nverts = d == 2 ? size_t(F.nv) * F.nv : size_t(F.nv) * F.nv * F.nv;
+  unsigned nb = unsigned((nverts + 255) / 256);
+  if (d == 2)
+    k_accumulate<2><<<nb, 256, 0, s>>>(F, C, u, e, S);
+  else
+    k_accumulate<3><<<nb, 256, 0, s>>>(F, C, u, e, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_defect(int d, const LevelView<double>& F, const double* u, const double* b, float* r32,
+                         double* partials, int nblocks, hipStream_t s) {
+  if (d == 2)
+    k_defect<2><<<nblocks, 256, 0, s>>>(F, u, b, r32, partials);
+  else
+    k_defect<3><<<nblocks, 256, 0, s>>>(F, u, b, r32, partials);
+  return hipGetLastError();
+}
 template <typename T>
 hipError_t launch_fine_residual(int d, const LevelView<T>& F, const T* uin, T* uout, const T* b, T* r,
                                 T* ic_coarse, int nvc, T omega, int pi, double* partials, int nblocks,
@@ -250,9 +318,9 @@ hipError_t launch_prolong_add(int d, const LevelView<T>& F, const LevelView<T>& 
 template <typename T>
 hipError_t launch_small_levels(int d, const SmallLevelsArgs<T>& a, size_t lds_bytes, hipStream_t s) {
   if (d == 2)
-    k_small_levels<T, 2><<<1, 1024, lds_bytes, s>>>(a);
+    k_small_levels<T, 2><<<1, kSmallThreads, lds_bytes, s>>>(a);
   else
-    k_small_levels<T, 3><<<1, 1024, lds_bytes, s>>>(a);
+    k_small_levels<T, 3><<<1, kSmallThreads, lds_bytes, s>>>(a);
   return hipGetLastError();
 }
 template hipError_t launch_small_levels<double>(int, const SmallLevelsArgs<double>&, size_t, hipStream_t);

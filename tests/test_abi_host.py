@@ -148,3 +148,29 @@ def test_workspace_grows_with_problem():
         lib.adafac_destroy(ctx)
     # four finest-level FP64 arrays dominate
     assert sizes[1] > 4 * 8 * 82 ** 3 and sizes[0] < sizes[1]
+
+
+def test_precision_forms_are_accepted_and_sized():
+    lib = _abi.lib()
+    sizes = {}
+    for prec in (0, 1, 7):
+        ctx = C.c_void_p()
+        assert lib.adafac_create(C.byref(ctx), 3, 1, 4) == 0
+        fa = np.zeros(82 ** 3)
+        assert lib.adafac_set_rhs_lattice(ctx, _dp(fa), fa.size) == 0
+        o = _abi.Opts()
+        lib.adafac_default_opts(C.byref(o))
+        o.precision = prec
+        rc = lib.adafac_build_operators(ctx, C.byref(o))
+        if prec == 7:
+            assert rc == _abi.EINVAL
+        else:
+            assert rc == 0, lib.adafac_last_error(ctx)
+            n = C.c_size_t()
+            assert lib.adafac_workspace_bytes(ctx, C.byref(n)) == 0
+            sizes[prec] = n.value
+        lib.adafac_destroy(ctx)
+    # FP32_REFINED keeps the FP64 solution and load (3 arrays) and the FP32 inner hierarchy
+    nv = 82 ** 3
+    assert sizes[1] > 3 * 8 * nv + 4 * 4 * nv
+    assert sizes[0] > 4 * 8 * nv
