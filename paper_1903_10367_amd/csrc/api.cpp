@@ -39,6 +39,9 @@ template <typename T>
 hipError_t launch_coarse_sweep(int d, const LevelView<T>& L, const LevelView<T>& C, const RtSep<T>& rts,
                                T omega, T omega_t, T cscale, int damping, hipStream_t s);
 bool sweep_level_ok(int d, int n, int fem, bool has_pw);
+hipError_t launch_defect3d(const LevelView<double>& F, int nc, int nvc, const double* uin, double* uout,
+                           const float* e, const float* S, const double* b, float* r32, double* partials,
+                           int mode, int* nparts, hipStream_t s);
 template <typename T>
 hipError_t launch_small_levels(int d, const SmallLevelsArgs<T>& a, size_t lds_bytes, hipStream_t s);
 
@@ -350,6 +353,20 @@ int run_outer(adafac_ctx* c) {
   if (!mixed(c)) {
     int rc = run_cycle<double>(c, c->h64, norm_out, nullptr);
     if (rc) return rc;
+  } else if (c->dim == 3 && c->opts.fused && fused_ok(c)) {
+    // one pass: u' = u + e + P S into the other FP64 buffer, and the FP64 defect of u'
+    Hier<double>& D = c->h64;
+    Hier<float>& H = c->h32;
+    const int L = c->L;
+    const int mode = !c->e_pending ? 0 : (H.pending ? 2 : 1);
+    const LevelView<float> C = L > c->lmin ? H.v[L - 1] : LevelView<float>{};
+    int nparts = 0;
+    HIPCHK(c, launch_defect3d(D.v[L], C.n, C.nv, D.ufine[D.cur], D.ufine[1 - D.cur], H.ufine[H.cur],
+                              mode == 2 ? C.S : nullptr, D.bfine, H.bfine, c->partials, mode, &nparts, c->stream));
+    HIPCHK(c, launch_norm_finalize(c->partials, nparts, norm_out, c->stream));
+    D.cur = 1 - D.cur;
+    H.pending = false;
+    c->e_pending = false;
   } else {
     int rc = flush(c);
     if (rc) return rc;

@@ -99,6 +99,67 @@ __device__ __forceinline__ void restrict_x_pass(const T* Rb, T* Xw, T* Xm, const
   }
 }
 
+// The 27-point Q1 operator on one z column, one plane at a time.  push() takes the 3 x 3
+// neighbourhood of the column in the newest u plane (centre at up, row pitch W) and returns
+// A u at the plane below it, z, with the diagonal D there; uz receives u(z).  Carried:
+// Poisson (eps = 1): u(z), D4(z) = sum of the four in-plane diagonal neighbours, F(z-1) and
+// F(z) with F = 2 A4 + D4 (A4: the four in-plane axis neighbours), and then
+// A u(z) = h [8/3 u(z) - (2 D4(z) + F(z-1) + F(z+1)) / 12].  Variable eps: the contribution
+// of the cell layer below z, the eps sum of that layer, and per quadrant the values the layer
+// above needs; the eps of the four cells of layer z around the column come from the blocks.
+template <typename T, bool VAREPS>
+struct ColumnOp {
+  T own = T(0), c1 = T(0), c2 = T(0), c3 = T(0), epsprev = T(0);
+  T dq[4] = {T(0), T(0), T(0), T(0)}, eq[4] = {T(0), T(0), T(0), T(0)};
+
+  template <int W>
+  __device__ __forceinline__ T push(const T* up, T h, int x, int y, int z, int n, const T* eps, int nb, int bs,
+                                    T& diag, T& uz) {
+    const T o_n = up[0];
+    const T ax_m = up[-1], ax_p = up[1], ay_m = up[-W], ay_p = up[W];
+    const T d_0 = up[-W - 1], d_1 = up[-W + 1], d_2 = up[W - 1], d_3 = up[W + 1];
+    T au;
+    uz = own;
+    if constexpr (!VAREPS) {
+      const T d4 = (d_0 + d_1) + (d_2 + d_3);
+      const T f = T(2) * ((ax_m + ax_p) + (ay_m + ay_p)) + d4;
+      au = h * (T(8.0 / 3.0) * uz - T(1.0 / 12.0) * ((T(2) * c1 + c2) + f));
+      diag = h * T(8.0 / 3.0);
+      c1 = d4;
+      c2 = c3;
+      c3 = f;
+    } else {
+      // quadrants q = (sx, sy): 0 = (-,-), 1 = (+,-), 2 = (-,+), 3 = (+,+)
+      const T d_n[4] = {d_0, d_1, d_2, d_3};
+      const T e_n[4] = {ax_m + ay_m + d_0, ax_p + ay_m + d_1, ax_m + ay_p + d_2, ax_p + ay_p + d_3};
+      // eps of the four cells of layer z (between planes z and z+1) around the column
+      const int bx0 = min(max(x - 1, 0), n - 1) / bs, bx1 = min(max(x, 0), n - 1) / bs;
+      const int by0 = min(max(y - 1, 0), n - 1) / bs, by1 = min(max(y, 0), n - 1) / bs;
+      const int bz = min(max(z, 0), n - 1) / bs;
+      const T* eb = eps + size_t(bz) * nb * nb;
+      const T e4[4] = {eb[by0 * nb + bx0], eb[by0 * nb + bx1], eb[by1 * nb + bx0], eb[by1 * nb + bx1]};
+      T bc = T(0), tn = T(0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        bc += e4[q] * (T(1.0 / 3.0) * uz - T(1.0 / 12.0) * (dq[q] + e_n[q]));
+        tn += e4[q] * (T(1.0 / 3.0) * o_n - T(1.0 / 12.0) * (d_n[q] + eq[q]));
+      }
+      const T esl = (e4[0] + e4[1]) + (e4[2] + e4[3]);
+      au = h * (bc + c1);
+      diag = h * T(1.0 / 3.0) * (esl + epsprev);
+      c1 = tn;
+      epsprev = esl;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        dq[q] = d_n[q];
+        eq[q] = e_n[q];
+      }
+    }
+    own = o_n;
+    return au;
+  }
+};
+
 }  // namespace
 
 // Arguments of the 3D sweep (only what it reads; passed in kernarg memory).
@@ -237,13 +298,7 @@ __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_fine_sweep3d(S
   const unsigned roffb = unsigned(roff * sizeof(T));
   const int upos = (ry + 1) * UW + rx + 1;
 
-  // Carried per residual column.  Poisson: u(z), D4(z) = sum of the four in-plane diagonal
-  // neighbours, F(z-1) and F(z) with F = 2 A4 + D4 (A4: the four in-plane axis neighbours);
-  // then A u(z) = h [8/3 u(z) - (2 D4(z) + F(z-1) + F(z+1)) / 12].  Variable eps: the
-  // contribution of the cell layer below, eps of that layer, and per quadrant the values the
-  // layer above needs.
-  T own = T(0), c1 = T(0), c2 = T(0), c3 = T(0), epsprev = T(0);
-  T dq[4] = {T(0), T(0), T(0), T(0)}, eq[4] = {T(0), T(0), T(0), T(0)};
+  ColumnOp<T, VAREPS> col;
   // prefetch ring: slot K holds u(p) and b(p-2) for the steps p of slot K
   T pu[3], pb[3];
   T accR[2] = {T(0), T(0)}, accT[2] = {T(0), T(0)};
@@ -296,48 +351,9 @@ __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_fine_sweep3d(S
     // (2) residual of plane z = p-2 from u planes p-3 (registers), p-2 (registers) and p-1 (slot K2)
     if (!CK || (p - 1 >= zs && p - 1 <= ze)) {
       const int z = p - 2;
-      const T* up = &Ub[K2][upos];
-      const T o_n = up[0];
-      const T ax_m = up[-1], ax_p = up[1], ay_m = up[-UW], ay_p = up[UW];
-      const T d_0 = up[-UW - 1], d_1 = up[-UW + 1], d_2 = up[UW - 1], d_3 = up[UW + 1];
-      T au, dinv;
-      const T uz = own;
-      if constexpr (!VAREPS) {
-        const T d4 = (d_0 + d_1) + (d_2 + d_3);
-        const T f = T(2) * ((ax_m + ax_p) + (ay_m + ay_p)) + d4;
-        au = h * (T(8.0 / 3.0) * uz - T(1.0 / 12.0) * ((T(2) * c1 + c2) + f));
-        dinv = wdiag;
-        c1 = d4;
-        c2 = c3;
-        c3 = f;
-      } else {
-        // quadrants q = (sx, sy): 0 = (-,-), 1 = (+,-), 2 = (-,+), 3 = (+,+)
-        const T d_n[4] = {d_0, d_1, d_2, d_3};
-        const T e_n[4] = {ax_m + ay_m + d_0, ax_p + ay_m + d_1, ax_m + ay_p + d_2, ax_p + ay_p + d_3};
-        // eps of the four cells of layer z (between planes z and z+1) around the column
-        const int bx0 = min(max(x - 1, 0), n - 1) / a.bs, bx1 = min(max(x, 0), n - 1) / a.bs;
-        const int by0 = min(max(y - 1, 0), n - 1) / a.bs, by1 = min(max(y, 0), n - 1) / a.bs;
-        const int bz = min(max(z, 0), n - 1) / a.bs;
-        const T* eb = a.eps + size_t(bz) * a.nb * a.nb;
-        const T e4[4] = {eb[by0 * a.nb + bx0], eb[by0 * a.nb + bx1], eb[by1 * a.nb + bx0], eb[by1 * a.nb + bx1]};
-        T bc = T(0), tn = T(0);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          bc += e4[q] * (T(1.0 / 3.0) * uz - T(1.0 / 12.0) * (dq[q] + e_n[q]));
-          tn += e4[q] * (T(1.0 / 3.0) * o_n - T(1.0 / 12.0) * (d_n[q] + eq[q]));
-        }
-        const T esl = (e4[0] + e4[1]) + (e4[2] + e4[3]);
-        au = h * (bc + c1);
-        dinv = a.omega / (h * T(1.0 / 3.0) * (esl + epsprev));
-        c1 = tn;
-        epsprev = esl;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          dq[q] = d_n[q];
-          eq[q] = e_n[q];
-        }
-      }
-      own = o_n;
+      T diag, uz;
+      const T au = col.template push<UW>(&Ub[K2][upos], h, x, y, z, n, a.eps, a.nb, a.bs, diag, uz);
+      const T dinv = VAREPS ? a.omega / diag : wdiag;
       T res = T(0);
       const bool zin = !CK || (p - 1 >= zs + 2 && z > 0 && z < n);
       if (zin && rint) {
@@ -454,6 +470,186 @@ __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_fine_sweep3d(S
     step(p + 2, IC<1>{}, IC<2>{});
   }
   if constexpr (!COARSE) block_norm_partials(double(a.hd) * ssum, smax, a.partials);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 step of defect correction on a 3D level (FP32 cycles inside FP64 defect correction):
+//   u' = u + (e + P S_{L-1})     the FP32 inner correction with its pending prolongation
+//                                (MODE 2), the correction alone (MODE 1) or nothing (MODE 0)
+//   r  = b - A u'                in FP64, stored in FP32 as the next inner right-hand side,
+//                                with the FP64 norm partials
+// in one z march over 27 x 27 column tiles (u' on a 29 x 29 ring in LDS), u' into the other
+// FP64 buffer.  Per dof: u, b read and u' written in FP64, e read and r written in FP32.
+// ---------------------------------------------------------------------------
+struct Defect3dArgs {
+  const double* uin;
+  double* uout;
+  const float* e;
+  const float* S;
+  const double* b;
+  float* r32;
+  const double* eps;
+  double* partials;
+  double h, hd;
+  int n, nv, nc, nvc, nb, bs, tz, ntx, ntz;
+};
+
+namespace {
+constexpr int DW = TX + 2;          // u' ring: x0-1 .. x0+27
+constexpr int ND = DW * DW;
+constexpr int NTD = 1024;
+}  // namespace
+
+// One 1024-lane workgroup per CU: at 64 VGPRs (two per CU) the Poisson variant spills.
+#ifndef ADAFAC_DEFECT3D_MINWAVES
+#define ADAFAC_DEFECT3D_MINWAVES 4
+#endif
+template <bool VAREPS, int MODE>
+__global__ void __launch_bounds__(NTD, VAREPS ? 4 : ADAFAC_DEFECT3D_MINWAVES) k_defect3d(Defect3dArgs a) {
+  static_assert(NTD >= ND && NTD >= TX * TX, "one lane per ring column");
+  __shared__ double Ub[3][NTD];
+  __shared__ float Sb[MODE == 2 ? (MAXTZ / 3 + 3) * CW * CW : 1];
+  __shared__ float Sz[3][CW * CW];
+
+  const int n = a.n, nv = a.nv, nc = a.nc, nvc = a.nvc;
+  const int plane = nv * nv;
+  const unsigned latb = unsigned(size_t(plane) * nv * sizeof(double));
+  const unsigned latf = unsigned(size_t(plane) * nv * sizeof(float));
+  const unsigned planeb = unsigned(plane * sizeof(double)), planef = unsigned(plane * sizeof(float));
+  const int nblk = a.ntx * a.ntx * a.ntz;
+  const int t = xcd_remap(blockIdx.x, nblk);
+  const int txi = t % a.ntx, tyi = (t / a.ntx) % a.ntx, tzi = t / (a.ntx * a.ntx);
+  const int tz = a.tz;
+  const int x0 = TX * txi, y0 = TX * tyi, z0 = tz * tzi;
+  const int cbx = x0 / 3 - 1, cby = y0 / 3 - 1, cbz = z0 / 3 - 1;
+  const int nsz = tz / 3 + 3;
+  const int tid = threadIdx.x;
+  const double h = a.h;
+  const Lattice<double> U(a.uin, latb), UO(a.uout, latb), B(a.b, latb);
+  const Lattice<float> E(a.e, latf), R(a.r32, latf);
+
+  if constexpr (MODE == 2) {
+    for (int i = tid; i < nsz * CW * CW; i += NTD) {
+      const int lx = i % CW, ly = (i / CW) % CW, lz = i / (CW * CW);
+      const int cx = cbx + lx, cy = cby + ly, cz = cbz + lz;
+      float v = 0.f;
+      if (cx >= 0 && cx <= nc && cy >= 0 && cy <= nc && cz >= 0 && cz <= nc) v = a.S[lin<3>(cx, cy, cz, nvc)];
+      Sb[i] = v;
+    }
+  }
+  // u' ring column of this lane (clamped into the lattice)
+  const int ui = tid < ND ? tid : 0;
+  const int ux = x0 - 1 + ui % DW, uy = y0 - 1 + ui / DW;
+  const int uxc = min(max(ux, 0), n), uyc = min(max(uy, 0), n);
+  const unsigned uoffd = unsigned(uxc + nv * uyc);
+  const bool uown = tid < ND && ux == uxc && uy == uyc && ux > 0 && ux < n && uy > 0 && uy < n &&
+                    ux >= x0 && ux < x0 + TX && uy >= y0 && uy < y0 + TX;
+  const int ucx = uxc / 3, ucy = uyc / 3;
+  const int usi = (ucy - cby) * CW + ucx - cbx;
+  const int usx = uxc - 3 * ucx, usy = uyc - 3 * ucy;
+  const float wx0 = float(3 - usx) * (1.f / 3.f), wx1 = float(usx) * (1.f / 3.f);
+  const float wy0 = float(3 - usy) * (1.f / 3.f), wy1 = float(usy) * (1.f / 3.f);
+  // residual column of this lane: the owned 27 x 27
+  const bool ract = tid < TX * TX;
+  const int rj = ract ? tid : 0;
+  const int x = x0 + rj % TX, y = y0 + rj / TX;
+  const bool rint = ract && x < n && y < n && x > 0 && y > 0;
+  const int xc = min(x, n), yc = min(y, n);
+  const unsigned roffd = unsigned(xc + nv * yc);
+  const int upos = (rj / TX + 1) * DW + rj % TX + 1;
+
+  ColumnOp<double, VAREPS> col;
+  double pu[3], pb[3];
+  float pe[3];
+  double ssum = 0.0, smax = 0.0;
+  const int zs = z0 - 1, ze = min(z0 + tz, n);
+  auto pl = [&](int p) { return unsigned(min(max(p, 0), n)); };
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    pu[q] = U.ld(uoffd * 8u, pl(zs + q) * planeb);
+    pe[q] = MODE ? E.ld(uoffd * 4u, pl(zs + q) * planef) : 0.f;
+    pb[q] = B.ld(roffd * 8u, pl(zs + q - 1) * planeb);
+  }
+  auto blend_s = [&](int p, auto ks) {
+    constexpr int KS = decltype(ks)::value;
+    if constexpr (MODE == 2) {
+      const int bt = tid - BL0;
+      if (bt >= 0 && bt < CW * CW) {
+        float v = 0.f;
+        if (p >= 0 && p <= n) {
+          const int cz = p / 3, sz = p - 3 * cz;
+          const float* s0 = &Sb[(cz - cbz) * CW * CW + bt];
+          v = float(3 - sz) * (1.f / 3.f) * s0[0] + float(sz) * (1.f / 3.f) * s0[CW * CW];
+        }
+        Sz[KS][bt] = v;
+      }
+    }
+  };
+  if constexpr (MODE == 2) __syncthreads();
+  blend_s(zs, IC<0>{});
+  __syncthreads();
+
+  auto step = [&](int p, auto ck, auto kk) {
+    constexpr bool CK = decltype(ck)::value != 0;
+    constexpr int K = decltype(kk)::value;
+    constexpr int K1 = (K + 1) % 3, K2 = (K + 2) % 3;
+    // (1) u' plane p into slot K; owned interior values are the new FP64 solution
+    if (!CK || p <= ze) {
+      double v = pu[K];
+      if constexpr (MODE >= 1) {
+        float c = pe[K];
+        if constexpr (MODE == 2) {
+          const float* s0 = &Sz[K][usi];
+          c += wy0 * (wx0 * s0[0] + wx1 * s0[1]) + wy1 * (wx0 * s0[CW] + wx1 * s0[CW + 1]);
+        }
+        v += double(c);
+      }
+      Ub[K][tid] = v;
+      if (uown && (!CK || (p >= z0 && p < z0 + tz && p > 0 && p < n))) UO.st_stream(v, uoffd * 8u, unsigned(p) * planeb);
+    }
+    const unsigned nxt = (CK ? pl(min(p + 3, ze)) : unsigned(p + 3));
+    pu[K] = U.ld(uoffd * 8u, nxt * planeb);
+    if constexpr (MODE >= 1) pe[K] = E.ld(uoffd * 4u, nxt * planef);
+    // (2) residual of plane z = p-2 from u' planes p-3, p-2 (registers) and p-1 (slot K2)
+    if (!CK || (p - 1 >= zs && p - 1 <= ze)) {
+      const int z = p - 2;
+      double diag, uz;
+      const double au = col.template push<DW>(&Ub[K2][upos], h, x, y, z, n, a.eps, a.nb, a.bs, diag, uz);
+      if (rint && (!CK || (z >= z0 && z < z0 + tz && z > 0 && z < n))) {
+        const double res = pb[K2] - au;
+        R.st_stream(float(res), roffd * 4u, unsigned(z) * planef);
+        ssum += res * res;
+        smax = fabs(res) > smax ? fabs(res) : smax;
+      }
+    }
+    pb[K2] = B.ld(roffd * 8u, (CK ? pl(min(p + 1, ze)) : unsigned(p + 1)) * planeb);
+    if (!CK || p + 1 <= ze) blend_s(p + 1, IC<K1>{});
+    __syncthreads();
+  };
+
+  // steps zs .. ze+1: u' planes z0-1 .. z0+tz, residual planes z0 .. z0+tz-1
+  const int nit = (tz + 3 + 2) / 3;
+  const int ihi = (tz - 4) / 3;          // iterations 2..ihi need no range checks
+  int it = 0;
+  for (; it < min(2, nit); ++it) {
+    const int p = zs + 3 * it;
+    step(p, IC<1>{}, IC<0>{});
+    step(p + 1, IC<1>{}, IC<1>{});
+    step(p + 2, IC<1>{}, IC<2>{});
+  }
+  for (; it <= ihi; ++it) {
+    const int p = zs + 3 * it;
+    step(p, IC<0>{}, IC<0>{});
+    step(p + 1, IC<0>{}, IC<1>{});
+    step(p + 2, IC<0>{}, IC<2>{});
+  }
+  for (; it < nit; ++it) {
+    const int p = zs + 3 * it;
+    step(p, IC<1>{}, IC<0>{});
+    step(p + 1, IC<1>{}, IC<1>{});
+    step(p + 2, IC<1>{}, IC<2>{});
+  }
+  block_norm_partials(a.hd * ssum, smax, a.partials);
 }
 
 template <typename T, bool VAREPS>
@@ -657,6 +853,31 @@ hipError_t launch_fine_sweep(int d, const LevelView<T>& F, const LevelView<T>& C
     (void)launch_sweep3d<T>(a, var, s);
     *nparts = int(nb);
   }
+  return hipGetLastError();
+}
+
+// FP64 defect step of a 3D level with 27 | n (see k_defect3d).  mode: 0 u' = u, 1 u' = u + e,
+// 2 u' = u + e + P S (d-linear P into the level).  *nparts receives the partial count.
+hipError_t launch_defect3d(const LevelView<double>& F, int nc, int nvc, const double* uin, double* uout,
+                           const float* e, const float* S, const double* b, float* r32, double* partials,
+                           int mode, int* nparts, hipStream_t s) {
+  const int n = F.n;
+  if (n % TX) return hipErrorInvalidValue;
+  const int ntx = n / TX, tz = pick_tz(n), ntz = n / tz;
+  Defect3dArgs a{uin, uout, e, S, b, r32, F.eps, partials, F.h, F.hd, n, F.nv, nc, nvc, F.nb, F.bs, tz, ntx, ntz};
+  const unsigned nb = unsigned(ntx * ntx * ntz);
+  const bool var = F.eps != nullptr;
+  if (mode == 2) {
+    if (var) k_defect3d<true, 2><<<nb, NTD, 0, s>>>(a);
+    else k_defect3d<false, 2><<<nb, NTD, 0, s>>>(a);
+  } else if (mode == 1) {
+    if (var) k_defect3d<true, 1><<<nb, NTD, 0, s>>>(a);
+    else k_defect3d<false, 1><<<nb, NTD, 0, s>>>(a);
+  } else {
+    if (var) k_defect3d<true, 0><<<nb, NTD, 0, s>>>(a);
+    else k_defect3d<false, 0><<<nb, NTD, 0, s>>>(a);
+  }
+  *nparts = int(nb);
   return hipGetLastError();
 }
 
