@@ -186,6 +186,102 @@ int adafac_kernel_time(adafac_ctx* ctx, double* total_ms, int* launches);
 void adafac_destroy(adafac_ctx* ctx);
 const char* adafac_last_error(const adafac_ctx* ctx);
 
+/* ------------------------------------------------------------------------
+ * Request server: continuous batching of independent solves (the cycle of
+ * Sec. 3.1 run to the stopping criterion of Sec. 5, one hierarchy per request).
+ *
+ * The caller hands over one device workspace.  A small header of it holds the
+ * batched kernel's request table; the rest is a pool that holds the hierarchies
+ * of the admitted requests.  Requests wait in a FIFO queue.  A request is
+ * admitted, in arrival order (a later request may pass one that does not fit
+ * yet), when an active slot is free and its exact device footprint (the
+ * adafac_workspace_bytes of its hierarchy) fits in the free pool.  Each
+ * scheduling round (adafac_server_step) does three things:
+ *  - harvests the previous round;
+ *  - admits;
+ *  - advances every active request by up to cycles_per_round cycles (outer
+ *    steps for FP32_REFINED).
+ * Requests whose finest level has at most batch_max_vertices vertices advance
+ * together in ONE launch of a work-queue kernel: one workgroup per request, all
+ * levels in sequence, stopping exactly at the first iterate that meets the
+ * tolerance.  Larger requests advance on their own streams.  Their work
+ * overlaps with the batched launch, and they stop at the end of the round in
+ * which their residual met the tolerance, so up to cycles_per_round - 1 extra
+ * cycles run.  A finished request's solution is copied to host memory and its
+ * device memory and slot are freed.  A request's arithmetic does not depend on
+ * the other requests, so results are the same served alone or in a mix.
+ * A server is driven by one host thread.
+ * ------------------------------------------------------------------------ */
+typedef struct adafac_server adafac_server;
+
+typedef struct {
+  int max_active;             /* requests on the device at once, 1..4096 */
+  int max_queued;             /* requests waiting for admission (EAGAIN beyond), >= 1 */
+  int cycles_per_round;       /* cycles a request advances per round, >= 1 */
+  int max_streams;            /* large requests advancing concurrently, 1..16 */
+  size_t batch_max_vertices;  /* finest-level vertex count up to which a request is batched */
+} adafac_server_cfg;
+
+typedef struct {
+  int dim, l_min, l_max;      /* as adafac_create */
+  int blocks_per_axis;        /* eps blocks per axis (3^k), 0: eps = 1 */
+  const double* eps;          /* blocks_per_axis^dim values, copied by submit */
+  const double* f;            /* (3^l_max + 1)^dim right-hand side samples, copied by submit */
+  adafac_opts opts;           /* as adafac_build_operators */
+  double rel_tol;             /* stop when ||r||_h / ||r^0||_h <= rel_tol */
+  int max_cycles;             /* cycle (outer step) cap, >= 1 */
+} adafac_request;
+
+#define ADAFAC_REQ_QUEUED 0
+#define ADAFAC_REQ_RUNNING 1
+#define ADAFAC_REQ_CONVERGED 2
+#define ADAFAC_REQ_DIVERGED 3
+#define ADAFAC_REQ_CAPPED 4       /* max_cycles reached first */
+#define ADAFAC_REQ_FAILED 5       /* set-up failed or the request can never fit */
+#define ADAFAC_EAGAIN 6           /* queue full: submit again after a round */
+
+typedef struct {
+  int status;                 /* ADAFAC_REQ_* */
+  int cycles;                 /* cycles (outer steps) run */
+  int batched;                /* 1: served by the batched kernel */
+  int error;                  /* ADAFAC_E* of a failed set-up, else 0 */
+  double l2h0, l2h, linf;     /* ||r^0||_h, and ||r||_h, max |r| of the last measured iterate */
+  double t_submit, t_admit, t_done;  /* seconds since adafac_server_create (host clock) */
+  size_t footprint;           /* device bytes held while active */
+} adafac_result;
+
+/* Defaults: max_active 256, max_queued 4096, cycles_per_round 4, max_streams 4,
+ * batch_max_vertices 65536. */
+void adafac_server_default_cfg(adafac_server_cfg* cfg);
+
+/* Create a server over the device workspace [dev_workspace, +bytes) (256-byte
+ * aligned), with all work on hip_stream (and max_streams streams of its own for
+ * large requests).  cfg may be NULL (defaults).  EINVAL on bad values, ENOMEM
+ * when the workspace cannot hold the request table. */
+int adafac_server_create(const adafac_server_cfg* cfg, void* dev_workspace, size_t bytes, void* hip_stream,
+                         adafac_server** out);
+
+/* Queue a request; inputs are copied.  *ticket identifies it.  EINVAL on bad
+ * arguments (as adafac_create / set_* / build_operators would report),
+ * ADAFAC_EAGAIN when max_queued requests wait already. */
+int adafac_server_submit(adafac_server* srv, const adafac_request* req, uint64_t* ticket);
+
+/* One scheduling round: wait for the previous round, harvest finished
+ * requests, admit, launch.  *active (may be NULL) receives the number of
+ * requests on the device after admission, *queued (may be NULL) the number
+ * waiting.  Returns after enqueuing the round. */
+int adafac_server_step(adafac_server* srv, int* active, int* queued);
+
+/* State of a ticket (no GPU synchronisation).  EINVAL for an unknown ticket. */
+int adafac_server_poll(const adafac_server* srv, uint64_t ticket, adafac_result* out);
+
+/* Copy the solution of a finished request (full finest lattice, n = (3^l_max +
+ * 1)^dim) and forget the ticket.  ESTATE while it is queued or running. */
+int adafac_server_fetch(adafac_server* srv, uint64_t ticket, double* u, size_t n);
+
+void adafac_server_destroy(adafac_server* srv);
+const char* adafac_server_last_error(const adafac_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,7 +12,7 @@ import numpy as np
 from . import _abi
 from ._abi import AdafacError, DAMPING, LEVEL_ARRAY, PRECISION, TRANSFER
 
-__all__ = ["Solver", "AdafacError", "lib"]
+__all__ = ["Solver", "Server", "AdafacError", "lib"]
 
 lib = _abi.lib
 
@@ -114,6 +114,102 @@ class Solver:
         if getattr(self, "ctx", None):
             self.L.adafac_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Request server of the C ABI (continuous batching of independent solves).
+
+    The pool for the request hierarchies is a torch uint8 tensor of ``budget_bytes`` on
+    ``device``; all work runs on torch's current stream there (plus the server's own streams
+    for large requests).
+    """
+
+    def __init__(self, budget_bytes, max_active=256, max_queued=4096, cycles_per_round=4, max_streams=4,
+                 batch_max_vertices=65536, device=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("adafac needs a ROCm GPU (gfx950); none is visible")
+        self.L = _abi.lib()
+        cfg = _abi.ServerCfg()
+        self.L.adafac_server_default_cfg(C.byref(cfg))
+        cfg.max_active, cfg.max_queued, cfg.cycles_per_round = max_active, max_queued, cycles_per_round
+        cfg.max_streams, cfg.batch_max_vertices = max_streams, batch_max_vertices
+        self.device = torch.device(device or "cuda:0")
+        self.workspace = torch.empty(int(budget_bytes), dtype=torch.uint8, device=self.device)
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        srv = C.c_void_p()
+        rc = self.L.adafac_server_create(C.byref(cfg), C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
+                                         C.c_void_p(self.stream.cuda_stream), C.byref(srv))
+        if rc:
+            raise AdafacError(rc, "adafac_server_create")
+        self.srv = srv
+        self._sizes = {}
+
+    def _err(self, rc, what):
+        if rc != _abi.OK:
+            msg = self.L.adafac_server_last_error(self.srv)
+            raise AdafacError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def submit(self, dim, lmin, lmax, f, eps_blocks=None, rel_tol=1e-8, max_cycles=200, transfer="dlinear",
+               damping="jac", precision="fp64", inner_k=4, fused=True, omega=0.6, omega_tilde=0.6,
+               omega_hat=0.5):
+        """Queue a solve; returns its ticket, or None when the queue is full (submit again later)."""
+        q = _abi.Request()
+        q.dim, q.l_min, q.l_max = dim, lmin, lmax
+        fa = np.ascontiguousarray(f, dtype=np.float64).ravel()
+        q.f = _dptr(fa)
+        if eps_blocks is not None:
+            e = np.ascontiguousarray(eps_blocks, dtype=np.float64)
+            q.blocks_per_axis, q.eps = e.shape[0], _dptr(e)
+        else:
+            q.blocks_per_axis = 0
+        self.L.adafac_default_opts(C.byref(q.opts))
+        q.opts.transfer, q.opts.damping, q.opts.precision = TRANSFER[transfer], DAMPING[damping], PRECISION[precision]
+        q.opts.inner_k, q.opts.fused = inner_k, int(bool(fused))
+        q.opts.omega, q.opts.omega_tilde, q.opts.omega_hat = omega, omega_tilde, omega_hat
+        q.rel_tol, q.max_cycles = rel_tol, max_cycles
+        t = C.c_uint64()
+        rc = self.L.adafac_server_submit(self.srv, C.byref(q), C.byref(t))
+        if rc == _abi.EAGAIN:
+            return None
+        self._err(rc, "submit")
+        self._sizes[t.value] = fa.size
+        return t.value
+
+    def step(self):
+        """One scheduling round; returns (active, queued)."""
+        a, q = C.c_int(), C.c_int()
+        self._err(self.L.adafac_server_step(self.srv, C.byref(a), C.byref(q)), "step")
+        return a.value, q.value
+
+    def poll(self, ticket):
+        r = _abi.Result()
+        self._err(self.L.adafac_server_poll(self.srv, ticket, C.byref(r)), "poll")
+        return {name: getattr(r, name) for name, _ in r._fields_} | {"state": _abi.REQ_STATUS[r.status]}
+
+    def fetch(self, ticket):
+        n = self._sizes.pop(ticket)
+        u = np.empty(n)
+        self._err(self.L.adafac_server_fetch(self.srv, ticket, _dptr(u), n), "fetch")
+        return u
+
+    def run_until_idle(self, max_rounds=100000):
+        for _ in range(max_rounds):
+            a, q = self.step()
+            if a == 0 and q == 0:
+                return
+        raise RuntimeError("server did not drain")
+
+    def close(self):
+        if getattr(self, "srv", None):
+            self.L.adafac_server_destroy(self.srv)
+            self.srv = None
 
     def __del__(self):
         try:

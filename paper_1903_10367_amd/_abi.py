@@ -5,7 +5,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libadafac.so")
 
-OK, EINVAL, ESTATE, ENOMEM, EDEVICE, EDIVERGED, EUNSUPPORTED = 0, 1, 2, 3, 4, 5, 7
+OK, EINVAL, ESTATE, ENOMEM, EDEVICE, EDIVERGED, EAGAIN, EUNSUPPORTED = 0, 1, 2, 3, 4, 5, 6, 7
+REQ_STATUS = {0: "queued", 1: "running", 2: "converged", 3: "diverged", 4: "capped", 5: "failed"}
 TRANSFER = {"dlinear": 0, "boxmg": 1}
 DAMPING = {"jac": 0, "pi": 1, "none": 2, "exp": 3}
 PRECISION = {"fp64": 0, "fp32_refined": 1}
@@ -18,6 +19,8 @@ EXPORTS = [
     "adafac_residual", "adafac_cycles_run", "adafac_get_solution", "adafac_set_solution",
     "adafac_get_level", "adafac_host_operator", "adafac_dofs_per_cycle", "adafac_set_kernel_timing", "adafac_kernel_time",
     "adafac_destroy", "adafac_last_error",
+    "adafac_server_default_cfg", "adafac_server_create", "adafac_server_submit", "adafac_server_step",
+    "adafac_server_poll", "adafac_server_fetch", "adafac_server_destroy", "adafac_server_last_error",
 ]
 
 
@@ -25,6 +28,24 @@ class Opts(C.Structure):
     _fields_ = [("transfer", C.c_int), ("damping", C.c_int), ("rtilde", C.c_int), ("precision", C.c_int),
                 ("inner_k", C.c_int), ("fused", C.c_int), ("omega", C.c_double),
                 ("omega_tilde", C.c_double), ("omega_hat", C.c_double)]
+
+
+class ServerCfg(C.Structure):
+    _fields_ = [("max_active", C.c_int), ("max_queued", C.c_int), ("cycles_per_round", C.c_int),
+                ("max_streams", C.c_int), ("batch_max_vertices", C.c_size_t)]
+
+
+class Request(C.Structure):
+    _fields_ = [("dim", C.c_int), ("l_min", C.c_int), ("l_max", C.c_int), ("blocks_per_axis", C.c_int),
+                ("eps", C.POINTER(C.c_double)), ("f", C.POINTER(C.c_double)), ("opts", Opts),
+                ("rel_tol", C.c_double), ("max_cycles", C.c_int)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int), ("cycles", C.c_int), ("batched", C.c_int), ("error", C.c_int),
+                ("l2h0", C.c_double), ("l2h", C.c_double), ("linf", C.c_double),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double),
+                ("footprint", C.c_size_t)]
 
 
 class AdafacError(RuntimeError):
@@ -66,6 +87,14 @@ def lib():
         "adafac_kernel_time": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_int)]),
         "adafac_destroy": (None, [P]),
         "adafac_last_error": (C.c_char_p, [P]),
+        "adafac_server_default_cfg": (None, [C.POINTER(ServerCfg)]),
+        "adafac_server_create": (C.c_int, [C.POINTER(ServerCfg), P, C.c_size_t, P, C.POINTER(P)]),
+        "adafac_server_submit": (C.c_int, [P, C.POINTER(Request), C.POINTER(C.c_uint64)]),
+        "adafac_server_step": (C.c_int, [P, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+        "adafac_server_poll": (C.c_int, [P, C.c_uint64, C.POINTER(Result)]),
+        "adafac_server_fetch": (C.c_int, [P, C.c_uint64, C.POINTER(C.c_double), C.c_size_t]),
+        "adafac_server_destroy": (None, [P]),
+        "adafac_server_last_error": (C.c_char_p, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

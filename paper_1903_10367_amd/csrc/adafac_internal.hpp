@@ -96,6 +96,44 @@ struct SmallLevelsArgs {
   double* norm_out;        // nullptr: no norms in this launch
 };
 
+// ---------------------------------------------------------------------------
+// Requests solved inside the batched work-queue kernel (continuous batching)
+// ---------------------------------------------------------------------------
+// One precision's hierarchy of a request: level views (v[L] describes the finest level; its
+// iterate lives in ufine[cur], its right-hand side in bfine and its residual in rfine).
+template <typename T>
+struct BatchHier {
+  LevelView<T> v[kMaxLevel + 1];
+  T* ufine[2];
+  T* bfine;
+  T* rfine;
+  RtSep<T> rts;
+};
+
+struct BatchReq {
+  int dim, L, lmin, damping, precision, inner_k;
+  double omega, omega_t, omega_hat;
+  double tol;                // stop when ||r||_h / ||r^0||_h <= tol
+  int max_cycles;            // cycles (FP64) or outer steps (FP32_REFINED)
+  int pad;
+  BatchHier<double> h64;     // FP64 form: everything; FP32_REFINED: v[L], u (ufine[0]) and b
+  BatchHier<float> h32;      // FP32_REFINED: the inner hierarchy (ufine = e, bfine = r)
+  const float* ezero;        // FP32_REFINED: zero lattice, first inner iterate
+};
+
+// Progress of a request across launches (device memory, written by the kernel).
+struct BatchState {
+  int cycles;                // cycles or outer steps run
+  int status;                // 0 running, 1 converged, 2 diverged, 3 cycle cap reached
+  int cur;                   // FP64 form: index of ufine holding the current iterate
+  int pad;
+  double r0, l2h, linf;      // norms of iterate 0 and of the last measured iterate
+};
+
+// Internal hooks of the C ABI used by the request server (api.cpp).
+int batch_describe(void* ctx, BatchReq* out);        // device description of a bound context
+int batch_adopt(void* ctx, int cur, int converged);  // current iterate after batched cycles
+
 struct CycleParams {
   double omega, omega_t, omega_hat;
   int damping;               // ADAFAC_DAMP_*

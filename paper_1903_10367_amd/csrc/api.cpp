@@ -432,6 +432,56 @@ int upload_ops(adafac_ctx* c, Hier<T>& H, bool coarse) {
 
 }  // namespace
 
+namespace adafac {
+
+template <typename T>
+static void describe_hier(const adafac_ctx* c, const Hier<T>& H, BatchHier<T>& B) {
+  for (int l = 0; l <= kMaxLevel; ++l) B.v[l] = H.v[l];
+  B.ufine[0] = H.ufine[H.cur];
+  B.ufine[1] = H.ufine[1 - H.cur];
+  B.bfine = H.bfine;
+  B.rfine = H.rfine;
+  B.rts = H.rts;
+  (void)c;
+}
+
+// Device description of a bound context for the batched kernel.  Its iterate is taken as
+// ufine[0] (FP64 form) and nothing may be pending.
+int batch_describe(void* vc, BatchReq* out) {
+  adafac_ctx* c = static_cast<adafac_ctx*>(vc);
+  if (!c || !out || !c->bound) return ADAFAC_ESTATE;
+  if (c->h64.pending || c->h32.pending || c->e_pending) return ADAFAC_ESTATE;
+  *out = BatchReq{};
+  out->dim = c->dim;
+  out->L = c->L;
+  out->lmin = c->lmin;
+  out->damping = c->opts.damping;
+  out->precision = c->opts.precision;
+  out->inner_k = c->opts.inner_k;
+  out->omega = c->opts.omega;
+  out->omega_t = c->opts.omega_tilde;
+  out->omega_hat = c->opts.omega_hat;
+  describe_hier(c, c->h64, out->h64);
+  if (mixed(c)) {
+    describe_hier(c, c->h32, out->h32);
+    out->h32.ufine[0] = c->h32.ufine[0];
+    out->h32.ufine[1] = c->h32.ufine[1];
+    out->ezero = c->ezero;
+  }
+  return ADAFAC_OK;
+}
+
+// After batched cycles: ufine[cur] of the description holds the current FP64 iterate.
+int batch_adopt(void* vc, int cur, int /*converged*/) {
+  adafac_ctx* c = static_cast<adafac_ctx*>(vc);
+  if (!c || !c->bound) return ADAFAC_ESTATE;
+  if (!mixed(c) && cur == 1) c->h64.cur = 1 - c->h64.cur;
+  c->h64.pending = c->h32.pending = c->e_pending = false;
+  return ADAFAC_OK;
+}
+
+}  // namespace adafac
+
 extern "C" {
 
 void adafac_default_opts(adafac_opts* o) {

@@ -49,81 +49,6 @@ __global__ void __launch_bounds__(256) k_fine_residual(LevelView<T> F, const T* 
   block_norm_partials(ssum, smax, partials);
 }
 
-// FAS update of vertex i of coarse level C (next finer level F, next coarser level Cm).
-template <typename T, int D>
-__device__ __forceinline__ void level_update_vertex(const LevelView<T>& C, const LevelView<T>& F,
-                                                    const LevelView<T>& Cm, const RtSep<T>& rts, T omega,
-                                                    T omega_t, T cscale, int damping, int gather, size_t i) {
-  const int nv = C.nv, nvf = F.nv;
-  int x = int(i % nv), y = int((i / nv) % nv), z = D == 3 ? int(i / (size_t(nv) * nv)) : 0;
-  if (!is_interior<D>(x, y, z, nv)) return;
-  const bool jac = damping == ADAFAC_DAMP_JAC;
-  T uv, rr, bt;
-  T nb[27];
-  if (gather) {
-    const int X = 3 * x, Y = 3 * y, Z = 3 * z;
-    uv = F.u[lin<D>(X, Y, Z, nvf)];
-    rr = T(0);
-    bt = T(0);
-    // 5^d restriction gathers, one plane at a time with all its loads in flight
-#pragma unroll
-    for (int oz = (D == 3 ? -2 : 0); oz <= (D == 3 ? 2 : 0); ++oz) {
-      T pl[25];
-#pragma unroll
-      for (int t = 0; t < 25; ++t) pl[t] = F.r[lin<D>(X + t % 5 - 2, Y + t / 5 - 2, Z + oz, nvf)];
-      T W = T(0);
-      if (!F.pw) {
-#pragma unroll
-        for (int t = 0; t < 25; ++t) W += restrict_weight<T, D>(F, X + t % 5 - 2, Y + t / 5 - 2, Z + oz, x, y, z) * pl[t];
-      } else {
-        for (int t = 0; t < 25; ++t) W += restrict_weight<T, D>(F, X + t % 5 - 2, Y + t / 5 - 2, Z + oz, x, y, z) * pl[t];
-      }
-      rr += W;
-      if (jac) {
-        // R~ = scale sum_a delta(o_a) prod_{b != a} m(o_b)
-        T Xs = T(0), Ys = T(0), Qs = T(0);
-#pragma unroll
-        for (int o = 0; o < 5; ++o) {
-          Xs += rts.m[o] * pl[10 + o];
-          Ys += rts.m[o] * pl[5 * o + 2];
-          T row = T(0);
-#pragma unroll
-          for (int q = 0; q < 5; ++q) row += rts.m[q] * pl[5 * o + q];
-          Qs += rts.m[o] * row;
-        }
-        if (D == 2) bt += rts.scale * (Xs + Ys);
-        else bt += rts.scale * (rts.m[oz + 2] * (Xs + Ys) + (oz == 0 ? Qs : T(0)));
-      }
-    }
-    C.u[i] = uv;
-    C.rr[i] = rr;
-    C.bt[i] = bt;
-#pragma unroll
-    for (int t = 0; t < (D == 2 ? 9 : 27); ++t)
-      nb[t] = F.u[lin<D>(3 * (x + t % 3 - 1), 3 * (y + (t / 3) % 3 - 1), 3 * (z + t / 9 - (D == 3 ? 1 : 0)), nvf)];
-  } else {
-    uv = C.u[i];
-    rr = C.rr[i];
-    bt = C.bt[i];
-#pragma unroll
-    for (int t = 0; t < (D == 2 ? 9 : 27); ++t)
-      nb[t] = C.u[lin<D>(x + t % 3 - 1, y + (t / 3) % 3 - 1, z + t / 9 - (D == 3 ? 1 : 0), nv)];
-  }
-  T dg;
-  T au = apply_level_op_nb<T, D>(C, x, y, z, nb, dg);
-  // FAS right-hand side with the tau correction, then the FAS residual of this level
-  T bf = rr + au;
-  T res = bf - au;
-  T c = cscale * omega * res / dg;
-  T s = c;
-  if (jac) s = c - omega_t * bt / dg;
-  if (damping == ADAFAC_DAMP_PI && Cm.ic && x % 3 == 0 && y % 3 == 0 && (D == 2 || z % 3 == 0))
-    Cm.ic[lin<D>(x / 3, y / 3, z / 3, Cm.nv)] = c;
-  C.bf[i] = bf;
-  C.r[i] = res;
-  C.S[i] = s;
-}
-
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_level_update(LevelView<T> C, LevelView<T> F, LevelView<T> Cm,
                                                       RtSep<T> rts, T omega, T omega_t, T cscale,

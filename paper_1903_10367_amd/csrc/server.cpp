@@ -1,0 +1,461 @@
+// Request server of the C ABI (include/adafac.h): FIFO admission by device footprint into a
+// pool inside the caller's workspace, batched advance of small requests in one work-queue
+// launch, large requests on streams of their own, harvest of finished requests.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <new>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "adafac.h"
+#include "adafac_internal.hpp"
+
+namespace adafac {
+hipError_t launch_batch_serve(const BatchReq* reqs, BatchState* states, const int* work, int nwork, int* next,
+                              int budget, int max_groups, hipStream_t s);
+}  // namespace adafac
+
+using namespace adafac;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxGroups = 1024;   // workgroups of one batched launch (they share the work list)
+
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+// First-fit allocator of byte ranges [0, size).
+class Pool {
+ public:
+  void reset(size_t size) {
+    free_.clear();
+    size_ = size;
+    if (size) free_[0] = size;
+  }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = align_up(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      *off = it->first;
+      const size_t rest = it->second - bytes;
+      const size_t at = it->first + bytes;
+      free_.erase(it);
+      if (rest) free_[at] = rest;
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = align_up(bytes);
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t size() const { return size_; }
+
+ private:
+  std::map<size_t, size_t> free_;
+  size_t size_ = 0;
+};
+
+struct Req {
+  uint64_t ticket = 0;
+  int dim = 2, lmin = 1, L = 1, nb = 0;
+  std::vector<double> eps, f;
+  adafac_opts opts{};
+  double tol = 0;
+  int max_cycles = 1;
+  adafac_result res{};
+  adafac_ctx* ctx = nullptr;
+  size_t off = 0, bytes = 0;
+  int slot = -1;          // batched: row of the request table
+  int lane = -1;          // large: stream index
+  int cycles_seen = 0;    // large: cycles whose norms were examined
+  std::vector<double> u;  // solution once finished
+};
+
+size_t finest_vertices(int d, int L) {
+  size_t nv = size_t(ipow3(L) + 1);
+  return d == 2 ? nv * nv : nv * nv * nv;
+}
+
+}  // namespace
+
+struct adafac_server {
+  adafac_server_cfg cfg{};
+  char* ws = nullptr;
+  size_t bytes = 0;
+  hipStream_t stream = nullptr;
+  BatchReq* d_reqs = nullptr;
+  BatchState* d_states = nullptr;
+  int* d_work = nullptr;
+  int* d_next = nullptr;
+  char* pool_base = nullptr;
+  Pool pool;
+  std::vector<hipStream_t> lanes;
+  std::vector<int> lane_busy;
+  std::vector<int> free_slots;
+  std::vector<BatchReq> h_desc;        // host copies of the table rows (kept for async copies)
+  std::vector<BatchState> h_states;
+  std::vector<int> h_work;
+  std::deque<uint64_t> queue;
+  std::unordered_map<uint64_t, Req> reqs;
+  std::vector<uint64_t> active;
+  uint64_t next_ticket = 1;
+  bool in_flight = false;
+  std::chrono::steady_clock::time_point t0;
+  std::string err;
+};
+
+namespace {
+
+int sfail(adafac_server* s, int code, const std::string& m) {
+  if (s) s->err = m;
+  return code;
+}
+
+#define SHIP(srv, expr)                                                                     \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return sfail(srv, ADAFAC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+double now(const adafac_server* s) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - s->t0).count();
+}
+
+bool final_status(int st) { return st >= ADAFAC_REQ_CONVERGED; }
+
+// Build (once) the host side of a request's hierarchy.
+int build_ctx(Req& r) {
+  if (r.ctx) return ADAFAC_OK;
+  adafac_ctx* c = nullptr;
+  int rc = adafac_create(&c, r.dim, r.lmin, r.L);
+  if (rc) return rc;
+  if (r.nb > 0 && (rc = adafac_set_coefficient_blocks(c, r.nb, r.eps.data()))) {
+    adafac_destroy(c);
+    return rc;
+  }
+  if ((rc = adafac_set_rhs_lattice(c, r.f.data(), r.f.size())) || (rc = adafac_build_operators(c, &r.opts)) ||
+      (rc = adafac_workspace_bytes(c, &r.bytes))) {
+    adafac_destroy(c);
+    return rc;
+  }
+  r.ctx = c;
+  return ADAFAC_OK;
+}
+
+// Release a finished request's device resources, keeping its solution on the host.
+int finish(adafac_server* s, Req& r, int status, int cur) {
+  r.res.status = status;
+  r.res.t_done = now(s);
+  if (r.ctx) {
+    int rc = ADAFAC_OK;
+    if (r.res.batched) rc = batch_adopt(r.ctx, cur, status == ADAFAC_REQ_CONVERGED);
+    r.u.assign(finest_vertices(r.dim, r.L), 0.0);
+    if (!rc) rc = adafac_get_solution(r.ctx, r.u.data(), r.u.size());
+    adafac_destroy(r.ctx);
+    r.ctx = nullptr;
+    if (rc) {
+      r.res.status = ADAFAC_REQ_FAILED;
+      r.res.error = rc;
+    }
+  }
+  s->pool.release(r.off, r.bytes);
+  if (r.slot >= 0) s->free_slots.push_back(r.slot);
+  if (r.lane >= 0) s->lane_busy[r.lane] = 0;
+  r.slot = r.lane = -1;
+  r.f.clear();
+  r.f.shrink_to_fit();
+  return ADAFAC_OK;
+}
+
+int harvest(adafac_server* s) {
+  if (!s->in_flight) return ADAFAC_OK;
+  SHIP(s, hipStreamSynchronize(s->stream));
+  for (hipStream_t l : s->lanes) SHIP(s, hipStreamSynchronize(l));
+  s->in_flight = false;
+  bool any_batched = false;
+  for (uint64_t t : s->active) any_batched |= s->reqs[t].res.batched != 0;
+  if (any_batched)
+    SHIP(s, hipMemcpy(s->h_states.data(), s->d_states, sizeof(BatchState) * s->h_states.size(), hipMemcpyDeviceToHost));
+  std::vector<uint64_t> still;
+  for (uint64_t t : s->active) {
+    Req& r = s->reqs[t];
+    int status = ADAFAC_REQ_RUNNING, cur = 0;
+    if (r.res.batched) {
+      const BatchState& st = s->h_states[r.slot];
+      r.res.cycles = st.cycles;
+      r.res.l2h0 = st.r0;
+      r.res.l2h = st.l2h;
+      r.res.linf = st.linf;
+      cur = st.cur;
+      if (st.status == 1) status = ADAFAC_REQ_CONVERGED;
+      else if (st.status == 2) status = ADAFAC_REQ_DIVERGED;
+      else if (st.status == 3) status = ADAFAC_REQ_CAPPED;
+    } else {
+      const int n = adafac_cycles_run(r.ctx);
+      for (int k = r.cycles_seen; k < n && status == ADAFAC_REQ_RUNNING; ++k) {
+        double l2 = 0, li = 0;
+        int rc = adafac_residual(r.ctx, k, &l2, &li);
+        if (rc) return sfail(s, rc, adafac_last_error(r.ctx));
+        if (k == 0) r.res.l2h0 = l2;
+        r.res.l2h = l2;
+        r.res.linf = li;
+        if (!std::isfinite(l2) || l2 > 1e3 * r.res.l2h0) status = ADAFAC_REQ_DIVERGED;
+        else if (r.res.l2h0 == 0.0 || l2 / r.res.l2h0 <= r.tol) status = ADAFAC_REQ_CONVERGED;
+      }
+      r.cycles_seen = n;
+      r.res.cycles = n;
+      if (status == ADAFAC_REQ_RUNNING && n >= r.max_cycles) status = ADAFAC_REQ_CAPPED;
+    }
+    if (status == ADAFAC_REQ_RUNNING) {
+      still.push_back(t);
+    } else {
+      int rc = finish(s, r, status, cur);
+      if (rc) return rc;
+    }
+  }
+  s->active.swap(still);
+  return ADAFAC_OK;
+}
+
+int admit(adafac_server* s) {
+  for (auto it = s->queue.begin(); it != s->queue.end();) {
+    if (int(s->active.size()) >= s->cfg.max_active) break;
+    Req& r = s->reqs[*it];
+    int rc = build_ctx(r);
+    if (!rc && r.bytes > s->pool.size()) rc = ADAFAC_ENOMEM;
+    if (rc) {
+      r.res.status = ADAFAC_REQ_FAILED;
+      r.res.error = rc;
+      r.res.t_done = now(s);
+      it = s->queue.erase(it);
+      continue;
+    }
+    const bool batched = finest_vertices(r.dim, r.L) <= s->cfg.batch_max_vertices;
+    int lane = -1;
+    if (!batched) {
+      for (int k = 0; k < int(s->lanes.size()); ++k)
+        if (!s->lane_busy[k]) { lane = k; break; }
+      if (lane < 0) { ++it; continue; }
+    } else if (s->free_slots.empty()) {
+      ++it;
+      continue;
+    }
+    size_t off = 0;
+    if (!s->pool.alloc(r.bytes, &off)) { ++it; continue; }
+    hipStream_t st = batched ? s->stream : s->lanes[lane];
+    rc = adafac_bind(r.ctx, s->pool_base + off, align_up(r.bytes), st);
+    if (rc) {
+      s->pool.release(off, r.bytes);
+      r.res.status = ADAFAC_REQ_FAILED;
+      r.res.error = rc;
+      r.res.t_done = now(s);
+      adafac_destroy(r.ctx);
+      r.ctx = nullptr;
+      it = s->queue.erase(it);
+      continue;
+    }
+    r.off = off;
+    r.res.footprint = align_up(r.bytes);
+    r.res.batched = batched ? 1 : 0;
+    r.res.t_admit = now(s);
+    r.res.status = ADAFAC_REQ_RUNNING;
+    if (batched) {
+      r.slot = s->free_slots.back();
+      s->free_slots.pop_back();
+      BatchReq& d = s->h_desc[r.slot];
+      if ((rc = batch_describe(r.ctx, &d))) return sfail(s, rc, "batch_describe");
+      d.tol = r.tol;
+      d.max_cycles = r.max_cycles;
+      s->h_states[r.slot] = BatchState{};
+      SHIP(s, hipMemcpyAsync(&s->d_reqs[r.slot], &d, sizeof(BatchReq), hipMemcpyHostToDevice, s->stream));
+      SHIP(s, hipMemcpyAsync(&s->d_states[r.slot], &s->h_states[r.slot], sizeof(BatchState), hipMemcpyHostToDevice,
+                             s->stream));
+    } else {
+      r.lane = lane;
+      s->lane_busy[lane] = 1;
+    }
+    s->active.push_back(r.ticket);
+    it = s->queue.erase(it);
+  }
+  return ADAFAC_OK;
+}
+
+int launch(adafac_server* s) {
+  s->h_work.clear();
+  for (uint64_t t : s->active) {
+    Req& r = s->reqs[t];
+    if (r.res.batched) {
+      s->h_work.push_back(r.slot);
+    } else {
+      const int n = std::min(s->cfg.cycles_per_round, r.max_cycles - adafac_cycles_run(r.ctx));
+      if (n > 0) {
+        int rc = adafac_cycle(r.ctx, n);
+        if (rc) return sfail(s, rc, adafac_last_error(r.ctx));
+      }
+    }
+  }
+  if (!s->h_work.empty()) {
+    SHIP(s, hipMemcpyAsync(s->d_work, s->h_work.data(), sizeof(int) * s->h_work.size(), hipMemcpyHostToDevice,
+                           s->stream));
+    SHIP(s, hipMemsetAsync(s->d_next, 0, sizeof(int), s->stream));
+    SHIP(s, launch_batch_serve(s->d_reqs, s->d_states, s->d_work, int(s->h_work.size()), s->d_next,
+                               s->cfg.cycles_per_round, kMaxGroups, s->stream));
+  }
+  s->in_flight = !s->active.empty();
+  return ADAFAC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void adafac_server_default_cfg(adafac_server_cfg* c) {
+  if (!c) return;
+  c->max_active = 256;
+  c->max_queued = 4096;
+  c->cycles_per_round = 4;
+  c->max_streams = 4;
+  c->batch_max_vertices = 65536;
+}
+
+int adafac_server_create(const adafac_server_cfg* cfg, void* ws, size_t bytes, void* stream, adafac_server** out) {
+  if (!out) return ADAFAC_EINVAL;
+  *out = nullptr;
+  adafac_server_cfg c;
+  adafac_server_default_cfg(&c);
+  if (cfg) c = *cfg;
+  if (c.max_active < 1 || c.max_active > 4096 || c.max_queued < 1 || c.cycles_per_round < 1 || c.max_streams < 1 ||
+      c.max_streams > 16)
+    return ADAFAC_EINVAL;
+  if (!ws || reinterpret_cast<uintptr_t>(ws) % kAlign) return ADAFAC_EINVAL;
+  const size_t head = align_up(sizeof(BatchReq) * c.max_active) + align_up(sizeof(BatchState) * c.max_active) +
+                      align_up(sizeof(int) * c.max_active) + kAlign;
+  if (bytes < head) return ADAFAC_ENOMEM;
+  adafac_server* s = new (std::nothrow) adafac_server();
+  if (!s) return ADAFAC_ENOMEM;
+  s->cfg = c;
+  s->ws = static_cast<char*>(ws);
+  s->bytes = bytes;
+  s->stream = static_cast<hipStream_t>(stream);
+  char* p = s->ws;
+  s->d_reqs = reinterpret_cast<BatchReq*>(p);
+  p += align_up(sizeof(BatchReq) * c.max_active);
+  s->d_states = reinterpret_cast<BatchState*>(p);
+  p += align_up(sizeof(BatchState) * c.max_active);
+  s->d_work = reinterpret_cast<int*>(p);
+  p += align_up(sizeof(int) * c.max_active);
+  s->d_next = reinterpret_cast<int*>(p);
+  p += kAlign;
+  s->pool_base = p;
+  s->pool.reset((bytes - head) & ~(kAlign - 1));
+  s->h_desc.resize(c.max_active);
+  s->h_states.resize(c.max_active);
+  for (int k = c.max_active - 1; k >= 0; --k) s->free_slots.push_back(k);
+  s->lanes.resize(c.max_streams, nullptr);
+  s->lane_busy.assign(c.max_streams, 0);
+  for (auto& l : s->lanes) {
+    if (hipStreamCreateWithFlags(&l, hipStreamNonBlocking) != hipSuccess) {
+      adafac_server_destroy(s);
+      return ADAFAC_EDEVICE;
+    }
+  }
+  s->t0 = std::chrono::steady_clock::now();
+  *out = s;
+  return ADAFAC_OK;
+}
+
+int adafac_server_submit(adafac_server* s, const adafac_request* q, uint64_t* ticket) {
+  if (!s || !q || !ticket) return ADAFAC_EINVAL;
+  if (int(s->queue.size()) >= s->cfg.max_queued) return sfail(s, ADAFAC_EAGAIN, "queue full");
+  if ((q->dim != 2 && q->dim != 3) || q->l_min < 1 || q->l_min > q->l_max ||
+      (q->dim == 2 && q->l_max > 9) || (q->dim == 3 && q->l_max > 6))
+    return sfail(s, ADAFAC_EINVAL, "bad dimension or levels");
+  if (!q->f || q->max_cycles < 1 || !(q->rel_tol >= 0.0)) return sfail(s, ADAFAC_EINVAL, "bad f, tolerance or cycle cap");
+  if (q->blocks_per_axis < 0 || (q->blocks_per_axis > 0 && !q->eps)) return sfail(s, ADAFAC_EINVAL, "bad eps");
+  Req r;
+  r.ticket = s->next_ticket++;
+  r.dim = q->dim;
+  r.lmin = q->l_min;
+  r.L = q->l_max;
+  r.nb = q->blocks_per_axis;
+  if (r.nb > 0) {
+    const size_t ne = q->dim == 2 ? size_t(r.nb) * r.nb : size_t(r.nb) * r.nb * r.nb;
+    r.eps.assign(q->eps, q->eps + ne);
+  }
+  r.f.assign(q->f, q->f + finest_vertices(q->dim, q->l_max));
+  r.opts = q->opts;
+  r.tol = q->rel_tol;
+  r.max_cycles = q->max_cycles;
+  r.res.status = ADAFAC_REQ_QUEUED;
+  r.res.t_submit = now(s);
+  *ticket = r.ticket;
+  s->queue.push_back(r.ticket);
+  s->reqs.emplace(r.ticket, std::move(r));
+  return ADAFAC_OK;
+}
+
+int adafac_server_step(adafac_server* s, int* active, int* queued) {
+  if (!s) return ADAFAC_EINVAL;
+  int rc = harvest(s);
+  if (!rc) rc = admit(s);
+  if (!rc) rc = launch(s);
+  if (active) *active = int(s->active.size());
+  if (queued) *queued = int(s->queue.size());
+  return rc;
+}
+
+int adafac_server_poll(const adafac_server* s, uint64_t ticket, adafac_result* out) {
+  if (!s || !out) return ADAFAC_EINVAL;
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return ADAFAC_EINVAL;
+  *out = it->second.res;
+  return ADAFAC_OK;
+}
+
+int adafac_server_fetch(adafac_server* s, uint64_t ticket, double* u, size_t n) {
+  if (!s) return ADAFAC_EINVAL;
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return sfail(s, ADAFAC_EINVAL, "unknown ticket");
+  Req& r = it->second;
+  if (!final_status(r.res.status)) return sfail(s, ADAFAC_ESTATE, "request not finished");
+  if (r.res.status != ADAFAC_REQ_FAILED) {
+    if (!u || n != r.u.size()) return sfail(s, ADAFAC_EINVAL, "u: wrong size");
+    std::memcpy(u, r.u.data(), sizeof(double) * n);
+  }
+  s->reqs.erase(it);
+  return ADAFAC_OK;
+}
+
+void adafac_server_destroy(adafac_server* s) {
+  if (!s) return;
+  if (s->stream || s->in_flight) (void)hipStreamSynchronize(s->stream);
+  for (auto& kv : s->reqs)
+    if (kv.second.ctx) adafac_destroy(kv.second.ctx);
+  for (hipStream_t l : s->lanes)
+    if (l) (void)hipStreamDestroy(l);
+  delete s;
+}
+
+const char* adafac_server_last_error(const adafac_server* s) { return s ? s->err.c_str() : "null server"; }
+
+}  // extern "C"

@@ -1,0 +1,171 @@
+"""Request server (continuous batching) through the C ABI.
+
+Small hierarchies advance in the batched work-queue kernel (one workgroup per request), larger
+ones on streams of their own.  Checked here:
+
+- A served request gives the same iterate as the one-kernel-per-step solver.
+- Its cycle count and solution match the oracle.
+- Each result is bitwise the same served alone and in a mix, including a mix with staggered
+  arrivals.
+- Admission honours the device-memory budget, and later requests are admitted as memory frees.
+- The queue limit and impossible requests are reported.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import adafac_inputs as inp
+from oracle import cycle, hierarchy
+
+pytestmark = pytest.mark.gpu
+
+MB = 1 << 20
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def requests():
+    """A mix of dimensions, depths, coefficients and precisions (2D and 3D, batched and not)."""
+    return [
+        dict(dim=2, lmin=1, lmax=3, f=inp.rhs(2, 3, seed=40), eps_blocks=inp.eps_blocks(2, 2, 3.0, seed=41)),
+        dict(dim=3, lmin=1, lmax=3, f=inp.rhs(3, 3, seed=42), precision="fp32_refined", inner_k=4),
+        dict(dim=2, lmin=1, lmax=5, f=inp.rhs(2, 5, seed=43), eps_blocks=inp.eps_blocks(2, 2, 3.0, seed=44)),
+        dict(dim=3, lmin=1, lmax=4, f=inp.rhs(3, 4, seed=45, dist="normal")),
+        dict(dim=2, lmin=1, lmax=6, f=inp.rhs(2, 6, seed=46), precision="fp32_refined", inner_k=8),
+        dict(dim=2, lmin=2, lmax=4, f=inp.rhs(2, 4, seed=47), damping="pi"),
+    ]
+
+
+def serve(reqs, budget=2048 * MB, stagger=0, **cfg):
+    """Serve reqs; with stagger > 0 the second half arrives after that many rounds."""
+    from paper_1903_10367_amd import Server
+    srv = Server(budget, **cfg)
+    tickets = [None] * len(reqs)
+    first = reqs if not stagger else reqs[: len(reqs) // 2]
+    for i, r in enumerate(first):
+        tickets[i] = srv.submit(**r)
+    rounds = 0
+    while True:
+        a, q = srv.step()
+        rounds += 1
+        if stagger and rounds == stagger:
+            for i in range(len(reqs) // 2, len(reqs)):
+                tickets[i] = srv.submit(**reqs[i])
+            continue
+        if a == 0 and q == 0 and (not stagger or rounds >= stagger):
+            break
+        assert rounds < 10000
+    out = []
+    for t in tickets:
+        res = srv.poll(t)
+        out.append((res, srv.fetch(t)))
+    srv.close()
+    return out
+
+
+def test_batched_request_equals_one_kernel_per_step_solver():
+    from paper_1903_10367_amd import Solver
+    f = inp.rhs(2, 4, seed=48)
+    say("case server vs solver, 2D L=4")
+    [(res, u)] = serve([dict(dim=2, lmin=1, lmax=4, f=f, rel_tol=1e-8)])
+    assert res["state"] == "converged" and res["batched"] == 1
+    s = Solver(2, 1, 4, f, fused=False)
+    n = s.solve(1e-8, 200)
+    us = s.solution()
+    hs = s.residuals()
+    s.close()
+    say(f"served cycles {res['cycles']}, solver cycles {n}, identical {np.array_equal(u, us)}")
+    assert res["cycles"] == n
+    assert np.abs(u - us).max() <= 1e-14 * np.abs(us).max()
+    assert abs(res["l2h0"] - hs[0][0]) <= 1e-14 * hs[0][0]
+
+
+@pytest.mark.parametrize("k", [0, 1, 3, 5])
+def test_served_results_match_oracle(k):
+    r = requests()[k]
+    say("case server vs oracle", k, r["dim"], r["lmax"])
+    [(res, u)] = serve([dict(r, rel_tol=1e-8, max_cycles=600)])
+    assert res["state"] == "converged", res
+    H = hierarchy.Hierarchy(r["dim"], r["lmax"], r["lmin"], r.get("eps_blocks"))
+    b = H.rhs(r["f"])
+    if r.get("precision") == "fp32_refined":
+        uo, ho, _ = cycle.defect_correction(H, b, r["inner_k"], 1e-8, 600)
+        # the oracle's FP64 defect of the served iterate meets the tolerance, as the oracle's own
+        rel = cycle.norms(H, b - H.lev[H.L].A(u))[0] / ho[0][0]
+        say(f"outer steps {res['cycles']} (oracle {len(ho)}), final rel. residual {rel:.3e}")
+        assert rel <= 1e-8 * (1 + 1e-6) and abs(res["cycles"] - len(ho)) <= 1
+        return
+    uo, ho = cycle.solve(H, b, 600, tol=1e-8, damping=r.get("damping", "jac"))
+    if not res["batched"]:
+        # a request on its own stream stops at the end of the round in which it converged
+        assert len(ho) <= res["cycles"] < len(ho) + 4
+        uo, ho = cycle.solve(H, b, res["cycles"], damping=r.get("damping", "jac"))
+    err = np.linalg.norm(u - uo) / np.linalg.norm(uo)
+    say(f"cycles {res['cycles']} (oracle {len(ho)}), rel. error {err:.3e}")
+    assert res["cycles"] == len(ho)
+    assert abs(res["l2h0"] - ho[0][0]) <= 1e-12 * ho[0][0]
+    assert err <= 1e-10
+
+
+def test_alone_and_in_the_mix_are_identical():
+    reqs = [dict(r, rel_tol=1e-8, max_cycles=600) for r in requests()]
+    say("case alone vs mix")
+    alone = [serve([r])[0] for r in reqs]
+    mixed = serve(reqs)
+    staggered = serve(reqs, stagger=3)
+    for i, ((ra, ua), (rm, um), (rs, us)) in enumerate(zip(alone, mixed, staggered)):
+        say(f"request {i}: {ra['state']} batched={ra['batched']} cycles {ra['cycles']} / {rm['cycles']} / "
+            f"{rs['cycles']}")
+        assert ra["state"] == rm["state"] == rs["state"] == "converged"
+        assert ra["cycles"] == rm["cycles"] == rs["cycles"]
+        assert np.array_equal(ua, um) and np.array_equal(ua, us)
+    assert {r["batched"] for r, _ in alone} == {0, 1}
+
+
+def test_admission_waits_for_memory_and_slots():
+    # four equal 3D L=4 requests (not batched) and a pool that holds two of them
+    from paper_1903_10367_amd import Server
+    reqs = [dict(dim=3, lmin=1, lmax=4, f=inp.rhs(3, 4, seed=50 + i), rel_tol=1e-8) for i in range(4)]
+    probe = serve([reqs[0]])[0][0]
+    fp = probe["footprint"]
+    say("case admission, footprint", fp)
+    srv = Server(2 * fp + 8 * MB, max_streams=4)
+    tickets = [srv.submit(**r) for r in reqs]
+    peak = 0
+    while True:
+        a, q = srv.step()
+        states = [srv.poll(t) for t in tickets]
+        running = [s for s in states if s["state"] == "running"]
+        assert sum(s["footprint"] for s in running) <= 2 * fp + 8 * MB
+        peak = max(peak, len(running))
+        if a == 0 and q == 0:
+            break
+    states = [srv.poll(t) for t in tickets]
+    for t in tickets:
+        srv.fetch(t)
+    srv.close()
+    assert peak == 2
+    assert all(s["state"] == "converged" for s in states)
+    done = sorted(s["t_done"] for s in states[:2])
+    # the last two were admitted only after one of the first two had finished
+    assert min(s["t_admit"] for s in states[2:]) >= done[0]
+
+
+def test_queue_limit_and_impossible_request():
+    from paper_1903_10367_amd import Server
+    say("case queue limit")
+    srv = Server(64 * MB, max_queued=2)
+    f = inp.rhs(2, 3, seed=60)
+    t1 = srv.submit(2, 1, 3, f)
+    t2 = srv.submit(3, 1, 5, inp.rhs(3, 5, seed=61))   # far beyond a 64 MB pool
+    assert srv.submit(2, 1, 3, f) is None               # queue full
+    srv.run_until_idle()
+    assert srv.poll(t1)["state"] == "converged"
+    r2 = srv.poll(t2)
+    assert r2["state"] == "failed" and r2["error"] == 3   # ADAFAC_ENOMEM
+    srv.fetch(t1)
+    srv.fetch(t2)
+    srv.close()
