@@ -54,3 +54,30 @@ def workload_jump(d, L, seed=0):
     k, p = (2, 3.0) if d == 2 else (3, 4.0)
     k = min(k, L)
     return dict(d=d, L=L, lmin=1, eps=eps_blocks(d, k, p, seed), f=rhs(d, L, seed + 1, "uniform"))
+
+
+def request_stream(n, seed=0):
+    """The mixed request stream of the serving workload, in arrival order.
+
+    Half 2D with L ~ U{3..7} (eps on 9x9 blocks, log10 U(0, 3)), half 3D with L ~ U{3..5}
+    (eps on 27^3 blocks, log10 U(0, 4)); f ~ U(-1, 1); precision FP64 or FP32 inner cycles
+    with FP64 defect correction, half each.  Request i draws its coefficient with seed
+    seed + i; its right-hand side is one of two per (d, L) (``f_seed``) so that a long stream
+    does not hold thousands of large arrays.  Returns dicts with d, L, eps_seed, f_seed and
+    precision.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        d = 2 if rng.random() < 0.5 else 3
+        L = int(rng.integers(3, 8)) if d == 2 else int(rng.integers(3, 6))
+        prec = "fp64" if rng.random() < 0.5 else "fp32_refined"
+        out.append(dict(d=d, L=L, eps_seed=seed + i, f_seed=1000 * L + d * 10 + int(rng.integers(0, 2)),
+                        precision=prec))
+    return out
+
+
+def poisson_arrivals(n, rate, seed=0):
+    """Arrival times (s) of a Poisson process of the given rate (requests per second)."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, n))

@@ -97,6 +97,73 @@ def timed_solve(Solver, torch, d, L, f, **kw):
     return out
 
 
+def serving(Server, torch, n_req, loads, budget_gb, max_cycles, log=None, **server_kw):
+    """The request stream served with continuous batching: one pass with every request queued
+    at t = 0 (capacity), then Poisson arrivals at the given fractions of that capacity.
+    Latency = completion minus arrival, to ||r||_h / ||r^0||_h <= 1e-8."""
+    import numpy as np
+    import adafac_inputs as inp
+    stream = inp.request_stream(n_req, seed=7)
+    fcache = {}
+
+    def spec(r):
+        k, p = (2, 3.0) if r["d"] == 2 else (3, 4.0)
+        key = (r["d"], r["L"], r["f_seed"])
+        if key not in fcache:
+            fcache[key] = inp.rhs(r["d"], r["L"], r["f_seed"])
+        return dict(dim=r["d"], lmin=1, lmax=r["L"], f=fcache[key], eps_blocks=inp.eps_blocks(r["d"], k, p, r["eps_seed"]),
+                    precision=r["precision"], inner_k=8, rel_tol=1e-8, max_cycles=max_cycles)
+
+    specs = [spec(r) for r in stream]
+
+    def one_pass(arrivals):
+        kw = dict(max_active=256, max_streams=8, cycles_per_round=8)
+        kw.update(server_kw)
+        srv = Server(int(budget_gb * (1 << 30)), **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        open_, lat, status, i = {}, [], {}, 0
+        while len(lat) < len(specs):
+            now = time.perf_counter() - t0
+            while i < len(specs) and arrivals[i] <= now:
+                t = srv.submit(**specs[i])
+                if t is None:
+                    break
+                open_[t] = arrivals[i]
+                i += 1
+            srv.step()
+            for t in list(open_):
+                res = srv.poll(t)
+                if res["state"] in ("converged", "diverged", "capped", "failed"):
+                    # completion on the server clock, which starts at its creation (~t0)
+                    lat.append(res["t_done"] - open_.pop(t))
+                    status[res["state"]] = status.get(res["state"], 0) + 1
+                    srv.fetch(t)
+        makespan = time.perf_counter() - t0
+        srv.close()
+        lat = np.array(lat)
+        return {"solves_per_s": len(lat) / makespan, "makespan_s": makespan,
+                "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                "status": status}
+
+    out = {"requests": n_req, "budget_gb": budget_gb, "max_cycles": max_cycles,
+           "mix": "2D L~U{3..7} eps 9x9 blocks 10^U(0,3) / 3D L~U{3..5} eps 27^3 blocks 10^U(0,4), "
+                  "f~U(-1,1), FP64 / FP32 inner cycles (k=8) + FP64 defect correction half each, "
+                  "d-linear transfers, adAFAC-Jac, to 1e-8"}
+    cap = one_pass(np.zeros(len(specs)))
+    out["saturated"] = cap
+    if log:
+        log(f"serving: capacity {cap['solves_per_s']:.1f} solves/s")
+    for frac in loads:
+        rate = frac * cap["solves_per_s"]
+        res = one_pass(inp.poisson_arrivals(len(specs), rate, seed=11))
+        res["arrival_rate_per_s"] = rate
+        out[f"load_{int(round(frac * 100))}pct"] = res
+        if log:
+            log(f"serving at {frac:.0%}: p50 {res['p50_ms']:.1f} ms p99 {res['p99_ms']:.1f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +171,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=2)
+    ap.add_argument("--serve-requests", type=int, default=200, help="requests per serving pass (0: skip)")
+    ap.add_argument("--serve-loads", default="0.5,0.9", help="arrival rates as fractions of capacity")
+    ap.add_argument("--serve-budget-gb", type=float, default=4.0)
+    ap.add_argument("--serve-max-cycles", type=int, default=3000)
     ap.add_argument("--profile-pass", action="store_true",
                     help="counter runs: a 1 GiB device copy (byte-counter calibration), then a few cycles")
     args = ap.parse_args()
@@ -114,7 +185,10 @@ def main():
 
     import torch
     import adafac_inputs as inp
-    from paper_1903_10367_amd import Solver
+    from paper_1903_10367_amd import Server, Solver
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
 
     w = inp.workload_3d_poisson_l5(seed=0)
     d, L = w["d"], w["L"]
@@ -188,6 +262,10 @@ def main():
                      "algorithmic_bytes_per_launch": kbytes, "launches": nlaunch},
         "solve_to_1e-8": solves,
     }
+    if args.serve_requests > 0:
+        loads = [float(x) for x in args.serve_loads.split(",") if x]
+        out["serving"] = serving(Server, torch, args.serve_requests, loads, args.serve_budget_gb,
+                                 args.serve_max_cycles, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(d, L, w["f"], args.cpu_cycles, dofs)
     print(json.dumps(out), flush=True)

@@ -192,15 +192,17 @@ const char* adafac_last_error(const adafac_ctx* ctx);
  *
  * The caller hands over one device workspace.  A small header of it holds the
  * batched kernel's request table; the rest is a pool that holds the hierarchies
- * of the admitted requests.  Requests wait in a FIFO queue.  A request is
+ * of the admitted requests.  Requests wait in a FIFO queue while their host-side
+ * set-up (operators, load vector) runs on worker threads.  A set-up request is
  * admitted, in arrival order (a later request may pass one that does not fit
  * yet), when an active slot is free and its exact device footprint (the
  * adafac_workspace_bytes of its hierarchy) fits in the free pool.  Each
  * scheduling round (adafac_server_step) does three things:
  *  - harvests the previous round;
- *  - admits;
  *  - advances every active request by up to cycles_per_round cycles (outer
- *    steps for FP32_REFINED).
+ *    steps for FP32_REFINED);
+ *  - admits, uploading while that round runs; admitted requests join the next
+ *    round.
  * Requests whose finest level has at most batch_max_vertices vertices advance
  * together in ONE launch of a work-queue kernel: one workgroup per request, all
  * levels in sequence, stopping exactly at the first iterate that meets the

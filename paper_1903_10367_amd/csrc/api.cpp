@@ -597,16 +597,12 @@ int adafac_bind(adafac_ctx* c, void* ws, size_t bytes, void* stream) {
   const HostLevel& fl = c->ops.lev[c->L];
   std::vector<double> b(fl.nverts, 0.0);
   const double hd = std::pow(fl.h, d);
-  for (size_t i = 0; i < fl.nverts; ++i) {
-    size_t t = i;
-    bool in = true;
-    for (int a = 0; a < d; ++a) {
-      int x = int(t % fl.nv);
-      t /= fl.nv;
-      if (x == 0 || x == fl.nv - 1) in = false;
+  const int nv = fl.nv;
+  for (int z = (d == 3 ? 1 : 0); z < (d == 3 ? nv - 1 : 1); ++z)
+    for (int y = 1; y < nv - 1; ++y) {
+      const size_t row = (size_t(z) * nv + y) * nv;
+      for (int x = 1; x < nv - 1; ++x) b[row + x] = hd * c->f[row + x];
     }
-    if (in) b[i] = hd * c->f[i];
-  }
   HIPCHK(c, hipMemcpyAsync(c->h64.bfine, b.data(), sizeof(double) * b.size(), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->h64.cur = c->h32.cur = 0;
@@ -764,7 +760,16 @@ int adafac_host_operator(const adafac_ctx* cc, int level, int which, double* out
   }
   if (which == 1) {
     if (n != nv) return fail(c, ADAFAC_EINVAL, "out: wrong size");
-    std::memcpy(out, hl.dg.data(), sizeof(double) * n);
+    if (!hl.dg.empty()) {
+      std::memcpy(out, hl.dg.data(), sizeof(double) * n);
+      return ADAFAC_OK;
+    }
+    const int zero[3] = {0, 0, 0};
+    for (size_t i = 0; i < nv; ++i) {
+      int v[3] = {0, 0, 0};
+      coords(i, v);
+      out[i] = interior(v) ? fem_stencil_entry(c->ops, level, v, zero) : 0.0;
+    }
     return ADAFAC_OK;
   }
   if (which == 2) {

@@ -5,8 +5,12 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <future>
+#include <thread>
 #include <map>
 #include <new>
 #include <string>
@@ -27,6 +31,8 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxGroups = 1024;   // workgroups of one batched launch (they share the work list)
+constexpr int kPrepThreads = 4;    // host set-ups of queued requests running at once
+constexpr int kPrepAhead = 16;     // queued requests set up ahead of admission (host memory bound)
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
@@ -88,6 +94,10 @@ struct Req {
   int lane = -1;          // large: stream index
   int cycles_seen = 0;    // large: cycles whose norms were examined
   std::vector<double> u;  // solution once finished
+  std::future<int> prep;  // host-side set-up on a worker thread
+  bool prep_started = false;
+  bool prepared = false;  // prep finished; its status is prep_rc
+  int prep_rc = 0;
 };
 
 size_t finest_vertices(int d, int L) {
@@ -109,7 +119,12 @@ struct adafac_server {
   char* pool_base = nullptr;
   Pool pool;
   std::vector<hipStream_t> lanes;
-  std::vector<int> lane_busy;
+  hipStream_t setup = nullptr;         // uploads of newly admitted requests
+  std::vector<int> lane_busy;          // a request holds the lane
+  std::vector<int> lane_flight;        // its last chunk of cycles is enqueued and not harvested
+  std::vector<uint64_t> lane_req;
+  bool b_flight = false;               // a batched launch is enqueued and not harvested
+  std::vector<uint64_t> b_members;     // requests of that launch
   std::vector<int> free_slots;
   std::vector<BatchReq> h_desc;        // host copies of the table rows (kept for async copies)
   std::vector<BatchState> h_states;
@@ -118,9 +133,11 @@ struct adafac_server {
   std::unordered_map<uint64_t, Req> reqs;
   std::vector<uint64_t> active;
   uint64_t next_ticket = 1;
-  bool in_flight = false;
   std::chrono::steady_clock::time_point t0;
   std::string err;
+  // host time spent per phase of adafac_server_step (seconds) and rounds run
+  double t_harvest = 0, t_admit = 0, t_launch = 0;
+  long rounds = 0;
 };
 
 namespace {
@@ -144,8 +161,8 @@ double now(const adafac_server* s) {
 bool final_status(int st) { return st >= ADAFAC_REQ_CONVERGED; }
 
 // Build (once) the host side of a request's hierarchy.
-int build_ctx(Req& r) {
-  if (r.ctx) return ADAFAC_OK;
+int build_ctx(Req* rp) {
+  Req& r = *rp;
   adafac_ctx* c = nullptr;
   int rc = adafac_create(&c, r.dim, r.lmin, r.L);
   if (rc) return rc;
@@ -180,70 +197,174 @@ int finish(adafac_server* s, Req& r, int status, int cur) {
   }
   s->pool.release(r.off, r.bytes);
   if (r.slot >= 0) s->free_slots.push_back(r.slot);
-  if (r.lane >= 0) s->lane_busy[r.lane] = 0;
+  if (r.lane >= 0) {
+    s->lane_busy[r.lane] = 0;
+    s->lane_flight[r.lane] = 0;
+  }
   r.slot = r.lane = -1;
   r.f.clear();
   r.f.shrink_to_fit();
   return ADAFAC_OK;
 }
 
-int harvest(adafac_server* s) {
-  if (!s->in_flight) return ADAFAC_OK;
-  SHIP(s, hipStreamSynchronize(s->stream));
-  for (hipStream_t l : s->lanes) SHIP(s, hipStreamSynchronize(l));
-  s->in_flight = false;
-  bool any_batched = false;
-  for (uint64_t t : s->active) any_batched |= s->reqs[t].res.batched != 0;
-  if (any_batched)
-    SHIP(s, hipMemcpy(s->h_states.data(), s->d_states, sizeof(BatchState) * s->h_states.size(), hipMemcpyDeviceToHost));
-  std::vector<uint64_t> still;
-  for (uint64_t t : s->active) {
-    Req& r = s->reqs[t];
-    int status = ADAFAC_REQ_RUNNING, cur = 0;
-    if (r.res.batched) {
-      const BatchState& st = s->h_states[r.slot];
-      r.res.cycles = st.cycles;
-      r.res.l2h0 = st.r0;
-      r.res.l2h = st.l2h;
-      r.res.linf = st.linf;
-      cur = st.cur;
-      if (st.status == 1) status = ADAFAC_REQ_CONVERGED;
-      else if (st.status == 2) status = ADAFAC_REQ_DIVERGED;
-      else if (st.status == 3) status = ADAFAC_REQ_CAPPED;
-    } else {
-      const int n = adafac_cycles_run(r.ctx);
-      for (int k = r.cycles_seen; k < n && status == ADAFAC_REQ_RUNNING; ++k) {
-        double l2 = 0, li = 0;
-        int rc = adafac_residual(r.ctx, k, &l2, &li);
-        if (rc) return sfail(s, rc, adafac_last_error(r.ctx));
-        if (k == 0) r.res.l2h0 = l2;
-        r.res.l2h = l2;
-        r.res.linf = li;
-        if (!std::isfinite(l2) || l2 > 1e3 * r.res.l2h0) status = ADAFAC_REQ_DIVERGED;
-        else if (r.res.l2h0 == 0.0 || l2 / r.res.l2h0 <= r.tol) status = ADAFAC_REQ_CONVERGED;
-      }
-      r.cycles_seen = n;
-      r.res.cycles = n;
-      if (status == ADAFAC_REQ_RUNNING && n >= r.max_cycles) status = ADAFAC_REQ_CAPPED;
+// Whether the work enqueued on st has completed (any error counts as completed: the caller's
+// synchronisation then reports it).  A not-ready query is cleared from the last-error state so
+// that the next launch check does not see it.
+bool ready(hipStream_t st, bool wait) {
+  if (wait) return true;
+  const hipError_t e = hipStreamQuery(st);
+  if (e == hipErrorNotReady) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return true;
+}
+
+void drop_active(adafac_server* s, uint64_t t) {
+  for (size_t k = 0; k < s->active.size(); ++k)
+    if (s->active[k] == t) {
+      s->active.erase(s->active.begin() + long(k));
+      return;
     }
-    if (status == ADAFAC_REQ_RUNNING) {
-      still.push_back(t);
-    } else {
-      int rc = finish(s, r, status, cur);
+}
+
+// Batched group: when its launch has completed, finish the requests that stopped.
+int harvest_batched(adafac_server* s, bool wait, bool* done) {
+  *done = false;
+  if (!s->b_flight || !ready(s->stream, wait)) return ADAFAC_OK;
+  SHIP(s, hipStreamSynchronize(s->stream));
+  SHIP(s, hipMemcpy(s->h_states.data(), s->d_states, sizeof(BatchState) * s->h_states.size(), hipMemcpyDeviceToHost));
+  s->b_flight = false;
+  *done = true;
+  for (uint64_t t : s->b_members) {
+    Req& r = s->reqs[t];
+    const BatchState& st = s->h_states[r.slot];
+    r.res.cycles = st.cycles;
+    r.res.l2h0 = st.r0;
+    r.res.l2h = st.l2h;
+    r.res.linf = st.linf;
+    int status = ADAFAC_REQ_RUNNING;
+    if (st.status == 1) status = ADAFAC_REQ_CONVERGED;
+    else if (st.status == 2) status = ADAFAC_REQ_DIVERGED;
+    else if (st.status == 3) status = ADAFAC_REQ_CAPPED;
+    if (status != ADAFAC_REQ_RUNNING) {
+      int rc = finish(s, r, status, st.cur);
       if (rc) return rc;
+      drop_active(s, t);
     }
   }
-  s->active.swap(still);
+  s->b_members.clear();
   return ADAFAC_OK;
 }
 
+int launch_batched(adafac_server* s) {
+  if (s->b_flight) return ADAFAC_OK;
+  s->h_work.clear();
+  s->b_members.clear();
+  for (uint64_t t : s->active) {
+    Req& r = s->reqs[t];
+    if (r.res.batched) {
+      s->h_work.push_back(r.slot);
+      s->b_members.push_back(t);
+    }
+  }
+  if (s->h_work.empty()) return ADAFAC_OK;
+  SHIP(s, hipMemcpyAsync(s->d_work, s->h_work.data(), sizeof(int) * s->h_work.size(), hipMemcpyHostToDevice,
+                         s->stream));
+  SHIP(s, hipMemsetAsync(s->d_next, 0, sizeof(int), s->stream));
+  SHIP(s, launch_batch_serve(s->d_reqs, s->d_states, s->d_work, int(s->h_work.size()), s->d_next,
+                             s->cfg.cycles_per_round, kMaxGroups, s->stream));
+  s->b_flight = true;
+  return ADAFAC_OK;
+}
+
+// Lane k: when its chunk has completed, judge the new cycles and finish or enqueue the next chunk.
+int service_lane(adafac_server* s, int k, bool wait, bool* done) {
+  *done = false;
+  if (!s->lane_busy[k]) return ADAFAC_OK;
+  Req& r = s->reqs[s->lane_req[k]];
+  if (s->lane_flight[k]) {
+    if (!ready(s->lanes[k], wait)) return ADAFAC_OK;
+    s->lane_flight[k] = 0;
+    *done = true;
+    int status = ADAFAC_REQ_RUNNING;
+    const int n = adafac_cycles_run(r.ctx);
+    for (int c = r.cycles_seen; c < n && status == ADAFAC_REQ_RUNNING; ++c) {
+      double l2 = 0, li = 0;
+      int rc = adafac_residual(r.ctx, c, &l2, &li);
+      if (rc) return sfail(s, rc, adafac_last_error(r.ctx));
+      if (c == 0) r.res.l2h0 = l2;
+      r.res.l2h = l2;
+      r.res.linf = li;
+      if (!std::isfinite(l2) || l2 > 1e3 * r.res.l2h0) status = ADAFAC_REQ_DIVERGED;
+      else if (r.res.l2h0 == 0.0 || l2 / r.res.l2h0 <= r.tol) status = ADAFAC_REQ_CONVERGED;
+    }
+    r.cycles_seen = n;
+    r.res.cycles = n;
+    if (status == ADAFAC_REQ_RUNNING && n >= r.max_cycles) status = ADAFAC_REQ_CAPPED;
+    if (status != ADAFAC_REQ_RUNNING) {
+      const uint64_t t = r.ticket;
+      int rc = finish(s, r, status, 0);
+      if (rc) return rc;
+      drop_active(s, t);
+      return ADAFAC_OK;
+    }
+  }
+  // enqueue the next chunk of cycles
+  const int n = std::min(s->cfg.cycles_per_round, r.max_cycles - adafac_cycles_run(r.ctx));
+  if (n > 0) {
+    int rc = adafac_cycle(r.ctx, n);
+    if (rc) return sfail(s, rc, adafac_last_error(r.ctx));
+    s->lane_flight[k] = 1;
+  }
+  return ADAFAC_OK;
+}
+
+// Start the host-side set-up of queued requests, in arrival order, on worker threads: at most
+// kPrepThreads at once and kPrepAhead set up (or being set up) ahead of admission.
+void prepare(adafac_server* s) {
+  int running = 0, ahead = 0;
+  for (uint64_t t : s->queue) {
+    Req& r = s->reqs[t];
+    if (!r.prep_started) continue;
+    ++ahead;
+    if (!r.prepared && r.prep.wait_for(std::chrono::seconds(0)) != std::future_status::ready) ++running;
+  }
+  for (uint64_t t : s->queue) {
+    if (running >= kPrepThreads || ahead >= kPrepAhead) break;
+    Req& r = s->reqs[t];
+    if (r.prep_started) continue;
+    r.prep = std::async(std::launch::async, build_ctx, &r);
+    r.prep_started = true;
+    ++running;
+    ++ahead;
+  }
+}
+
+// Admit prepared requests in arrival order while slots and memory allow; their uploads go to
+// the setup stream and they join the next round's launch.
 int admit(adafac_server* s) {
+  bool any = false;
   for (auto it = s->queue.begin(); it != s->queue.end();) {
     if (int(s->active.size()) >= s->cfg.max_active) break;
     Req& r = s->reqs[*it];
-    int rc = build_ctx(r);
+    if (!r.prep_started) {
+      ++it;
+      continue;
+    }
+    if (!r.prepared) {
+      if (r.prep.wait_for(std::chrono::seconds(0)) != std::future_status::ready) {
+        ++it;
+        continue;
+      }
+      r.prep_rc = r.prep.get();
+      r.prepared = true;
+    }
+    int rc = r.prep_rc;
     if (!rc && r.bytes > s->pool.size()) rc = ADAFAC_ENOMEM;
     if (rc) {
+      if (r.ctx) adafac_destroy(r.ctx);
+      r.ctx = nullptr;
       r.res.status = ADAFAC_REQ_FAILED;
       r.res.error = rc;
       r.res.t_done = now(s);
@@ -262,7 +383,7 @@ int admit(adafac_server* s) {
     }
     size_t off = 0;
     if (!s->pool.alloc(r.bytes, &off)) { ++it; continue; }
-    hipStream_t st = batched ? s->stream : s->lanes[lane];
+    hipStream_t st = batched ? s->setup : s->lanes[lane];
     rc = adafac_bind(r.ctx, s->pool_base + off, align_up(r.bytes), st);
     if (rc) {
       s->pool.release(off, r.bytes);
@@ -287,41 +408,22 @@ int admit(adafac_server* s) {
       d.tol = r.tol;
       d.max_cycles = r.max_cycles;
       s->h_states[r.slot] = BatchState{};
-      SHIP(s, hipMemcpyAsync(&s->d_reqs[r.slot], &d, sizeof(BatchReq), hipMemcpyHostToDevice, s->stream));
+      SHIP(s, hipMemcpyAsync(&s->d_reqs[r.slot], &d, sizeof(BatchReq), hipMemcpyHostToDevice, s->setup));
       SHIP(s, hipMemcpyAsync(&s->d_states[r.slot], &s->h_states[r.slot], sizeof(BatchState), hipMemcpyHostToDevice,
-                             s->stream));
+                             s->setup));
+      any = true;
     } else {
       r.lane = lane;
       s->lane_busy[lane] = 1;
+      s->lane_flight[lane] = 0;
+      s->lane_req[lane] = r.ticket;
     }
     s->active.push_back(r.ticket);
     it = s->queue.erase(it);
   }
-  return ADAFAC_OK;
-}
-
-int launch(adafac_server* s) {
-  s->h_work.clear();
-  for (uint64_t t : s->active) {
-    Req& r = s->reqs[t];
-    if (r.res.batched) {
-      s->h_work.push_back(r.slot);
-    } else {
-      const int n = std::min(s->cfg.cycles_per_round, r.max_cycles - adafac_cycles_run(r.ctx));
-      if (n > 0) {
-        int rc = adafac_cycle(r.ctx, n);
-        if (rc) return sfail(s, rc, adafac_last_error(r.ctx));
-      }
-    }
-  }
-  if (!s->h_work.empty()) {
-    SHIP(s, hipMemcpyAsync(s->d_work, s->h_work.data(), sizeof(int) * s->h_work.size(), hipMemcpyHostToDevice,
-                           s->stream));
-    SHIP(s, hipMemsetAsync(s->d_next, 0, sizeof(int), s->stream));
-    SHIP(s, launch_batch_serve(s->d_reqs, s->d_states, s->d_work, int(s->h_work.size()), s->d_next,
-                               s->cfg.cycles_per_round, kMaxGroups, s->stream));
-  }
-  s->in_flight = !s->active.empty();
+  // the next batched launch reads the new table rows
+  if (any) SHIP(s, hipStreamSynchronize(s->setup));
+  prepare(s);
   return ADAFAC_OK;
 }
 
@@ -373,11 +475,17 @@ int adafac_server_create(const adafac_server_cfg* cfg, void* ws, size_t bytes, v
   for (int k = c.max_active - 1; k >= 0; --k) s->free_slots.push_back(k);
   s->lanes.resize(c.max_streams, nullptr);
   s->lane_busy.assign(c.max_streams, 0);
+  s->lane_flight.assign(c.max_streams, 0);
+  s->lane_req.assign(c.max_streams, 0);
   for (auto& l : s->lanes) {
     if (hipStreamCreateWithFlags(&l, hipStreamNonBlocking) != hipSuccess) {
       adafac_server_destroy(s);
       return ADAFAC_EDEVICE;
     }
+  }
+  if (hipStreamCreateWithFlags(&s->setup, hipStreamNonBlocking) != hipSuccess) {
+    adafac_server_destroy(s);
+    return ADAFAC_EDEVICE;
   }
   s->t0 = std::chrono::steady_clock::now();
   *out = s;
@@ -411,14 +519,44 @@ int adafac_server_submit(adafac_server* s, const adafac_request* q, uint64_t* ti
   *ticket = r.ticket;
   s->queue.push_back(r.ticket);
   s->reqs.emplace(r.ticket, std::move(r));
+  prepare(s);
   return ADAFAC_OK;
 }
 
 int adafac_server_step(adafac_server* s, int* active, int* queued) {
   if (!s) return ADAFAC_EINVAL;
-  int rc = harvest(s);
+  // Each group (the batched launch, every lane) is harvested and relaunched as soon as its own
+  // work completes; newly admitted requests start right away (lanes) or with the next batched
+  // launch.  When nothing has completed yet, wait a little for the first completion.
+  int rc = ADAFAC_OK;
+  const double t_a = now(s);
+  bool progress = false;
+  for (int spin = 0; spin < 200 && !rc; ++spin) {
+    bool done = false;
+    rc = harvest_batched(s, false, &done);
+    progress |= done;
+    for (int k = 0; k < int(s->lanes.size()) && !rc; ++k) {
+      rc = service_lane(s, k, false, &done);
+      progress |= done;
+    }
+    bool busy = s->b_flight;
+    for (int k = 0; k < int(s->lanes.size()); ++k) busy |= s->lane_flight[k] != 0;
+    if (progress || !busy) break;
+    std::this_thread::sleep_for(std::chrono::microseconds(25));
+  }
+  const double t_b = now(s);
   if (!rc) rc = admit(s);
-  if (!rc) rc = launch(s);
+  const double t_c = now(s);
+  // start newly admitted lanes and an idle batched group
+  bool done = false;
+  for (int k = 0; k < int(s->lanes.size()) && !rc; ++k)
+    if (s->lane_busy[k] && !s->lane_flight[k]) rc = service_lane(s, k, false, &done);
+  if (!rc) rc = launch_batched(s);
+  const double t_d = now(s);
+  s->t_harvest += t_b - t_a;
+  s->t_admit += t_c - t_b;
+  s->t_launch += t_d - t_c;
+  s->rounds += 1;
   if (active) *active = int(s->active.size());
   if (queued) *queued = int(s->queue.size());
   return rc;
@@ -448,11 +586,20 @@ int adafac_server_fetch(adafac_server* s, uint64_t ticket, double* u, size_t n) 
 
 void adafac_server_destroy(adafac_server* s) {
   if (!s) return;
-  if (s->stream || s->in_flight) (void)hipStreamSynchronize(s->stream);
-  for (auto& kv : s->reqs)
-    if (kv.second.ctx) adafac_destroy(kv.second.ctx);
+  if (std::getenv("ADAFAC_SERVER_STATS"))
+    std::fprintf(stderr, "adafac server: %ld rounds, host seconds harvest %.3f admit %.3f launch %.3f\n", s->rounds,
+                 s->t_harvest, s->t_admit, s->t_launch);
+  (void)hipStreamSynchronize(s->stream);
+  for (hipStream_t l : s->lanes)
+    if (l) (void)hipStreamSynchronize(l);
+  for (auto& kv : s->reqs) {
+    Req& r = kv.second;
+    if (r.prep_started && !r.prepared && r.prep.valid()) (void)r.prep.get();
+    if (r.ctx) adafac_destroy(r.ctx);
+  }
   for (hipStream_t l : s->lanes)
     if (l) (void)hipStreamDestroy(l);
+  if (s->setup) (void)hipStreamDestroy(s->setup);
   delete s;
 }
 

@@ -351,9 +351,11 @@ std::string build_host_ops(HostOps& ops, int transfer_boxmg, double omega) {
       ops.lev[l - 1].fem = false;
     }
   }
-  // diagonals
+  // diagonals of the stored levels (a Q1 level's diagonal is positive because eps is, and the
+  // kernels derive it from eps)
   for (int l = ops.lmin; l <= ops.L; ++l) {
     HostLevel& hl = ops.lev[l];
+    if (hl.fem) continue;
     hl.dg.assign(hl.nverts, 0.0);
     Grid g{d, hl.nv};
     int zero[3] = {0, 0, 0}, ns = st_size(d), ctr = st_index(d, zero);
