@@ -81,3 +81,24 @@ def poisson_arrivals(n, rate, seed=0):
     """Arrival times (s) of a Poisson process of the given rate (requests per second)."""
     rng = np.random.default_rng(seed)
     return np.cumsum(rng.exponential(1.0 / rate, n))
+
+
+def refine_ball(d, L, l_uniform, centre, radius):
+    """Refinement flags of a spacetree refined around a ball: a cell of level l (l_uniform <= l
+    < L) is refined when its closure meets the closed ball.  Returns {l: bool array over the
+    (3^l)^d cells} (C order, x on the last axis); the flags of cells that do not exist are
+    ignored by the tree."""
+    centre = np.asarray(centre, dtype=np.float64)
+    out = {}
+    for l in range(l_uniform, L):
+        n = 3 ** l
+        h = 1.0 / n
+        idx = np.indices((n,) * d).astype(np.float64)        # axis 0 is the slowest (z or y)
+        dist2 = np.zeros((n,) * d)
+        for a in range(d):
+            c = centre[d - 1 - a]                              # idx[a] runs along coordinate d-1-a
+            lo, hi = idx[a] * h, (idx[a] + 1) * h
+            gap = np.maximum(0.0, np.maximum(lo - c, c - hi))
+            dist2 += gap * gap
+        out[l] = dist2 <= radius * radius
+    return out

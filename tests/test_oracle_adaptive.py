@@ -1,0 +1,119 @@
+"""Pins of the adaptive-spacetree oracle (oracle/adaptive.py) to things other than itself.
+
+- A tree refined everywhere is the uniform hierarchy, and the cycle reduces to the uniform
+  oracle cycle.
+- The level-wise cycle (leaf residuals, bottom-up accumulation, corrections, top-down
+  prolongation) equals eq. (adaFACx) written over the generating system with dense matrices.
+  Those matrices are built from the hat functions of every level, evaluated at the composite
+  vertices.
+- The fixed point is the direct solve of the composite system C^T A^leaf C.
+- The level diagonals are a(phi, phi) of the level hats in the composite space.
+- Hanging values reproduce d-linear functions.
+"""
+import numpy as np
+import pytest
+
+import adafac_inputs as inp
+from oracle import adaptive, cycle, hierarchy
+
+
+def disk_tree(L=4, lu=2, eps=None, d=2, radius=0.2):
+    ref = inp.refine_ball(d, L, lu, (0.5,) * d if d == 2 else (0.45, 0.5, 0.55), radius)
+    return adaptive.AdaptiveTree(d, L, 1, lu, ref, eps)
+
+
+@pytest.mark.parametrize("d,L,k", [(2, 3, 0), (2, 3, 1), (3, 2, 1)])
+def test_uniform_tree_is_the_uniform_cycle(d, L, k):
+    eps = inp.eps_blocks(d, k, 2.0, seed=3) if k else None
+    T = adaptive.AdaptiveTree(d, L, 1, L, {}, eps)
+    f = inp.rhs(d, L, seed=4)
+    U, hist = adaptive.solve(T, f, 6)
+    H = hierarchy.Hierarchy(d, L, 1, eps)
+    u, ho = cycle.solve(H, H.rhs(f), 6)
+    assert np.abs(U[L].ravel() - u).max() <= 1e-14 * np.abs(u).max()
+    for a, b in zip(hist, ho):
+        assert abs(a[0] - b[0]) <= 1e-14 * ho[0][0]
+
+
+def test_tree_classes():
+    T = disk_tree()
+    for l in range(T.lmin, T.L + 1):
+        assert not np.any(T.dof[l] & T.hang[l])
+        assert np.all(T.comp[l] <= T.dof[l])
+    # uniform levels have no hanging vertices, refined ones do
+    assert T.hang[2].sum() == 0 and T.hang[3].sum() > 0 and T.hang[4].sum() > 0
+    # every composite dof appears once: positions are distinct
+    pos = set()
+    for l, i in T.composite_index():
+        v = np.array(np.unravel_index(i, T.shape(l))) * 3 ** (T.L - l)
+        pos.add(tuple(v))
+    assert len(pos) == len(T.composite_index())
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_hanging_values_reproduce_dlinear_functions(d):
+    T = disk_tree(L=4 if d == 2 else 3, d=d, radius=0.2 if d == 2 else 0.15)
+    coef = np.array([0.3, -1.2, 0.7][:d])
+
+    def g(l):
+        idx = np.indices(T.shape(l)).astype(float) * 3.0 ** -l        # axis a is coordinate d-1-a
+        return 1.0 + sum(coef[d - 1 - a] * idx[a] for a in range(d))
+
+    U = {l: np.where(T.comp[l], g(l), 0.0) for l in range(T.lmin, T.L + 1)}
+    U = T.spread(U)
+    for l in range(T.lmin, T.L + 1):
+        have = T.dof[l] | T.hang[l]
+        assert np.abs(U[l][have] - g(l)[have]).max() < 1e-13
+
+
+@pytest.mark.parametrize("damping", ["jac", "none"])
+@pytest.mark.parametrize("d", [2, 3])
+def test_cycle_equals_dense_generating_system_form(d, damping):
+    if d == 2:
+        eps = inp.eps_blocks(2, 2, 2.0, seed=5)
+        T = disk_tree(L=4, lu=2, eps=eps)
+    else:
+        T = disk_tree(L=3, lu=2, d=3, radius=0.15, eps=inp.eps_blocks(3, 1, 2.0, seed=6))
+    f = inp.rhs(d, T.L, seed=7)
+    A, b, pos, lev, Psi, C = adaptive.dense_system(T, f)
+    bleaf = T.load(f)
+    U = {l: np.zeros(T.shape(l)) for l in range(T.lmin, T.L + 1)}
+    u = np.zeros(len(b))
+    for it in range(4):
+        U, nr = adaptive.cycle(T, U, bleaf, damping=damping)
+        u, nd = adaptive.dense_cycle(T, A, b, lev, Psi, u, damping=damping)
+        uc = adaptive.to_composite(T, U)
+        assert np.abs(uc - u).max() <= 1e-12 * np.abs(u).max(), it
+        assert abs(nr[0] - nd[0]) <= 1e-12 * nd[0] and abs(nr[1] - nd[1]) <= 1e-12 * nd[1]
+
+
+def test_level_diagonals_are_hat_energies():
+    T = disk_tree(eps=inp.eps_blocks(2, 2, 2.0, seed=8))
+    A, b, pos, lev, Psi, C = adaptive.dense_system(T, inp.rhs(2, 4, seed=9))
+    for l in range(T.lmin, T.L + 1):
+        D = T.D[l].ravel()[np.flatnonzero(T.dof[l].ravel())]
+        E = np.einsum("ij,ij->j", Psi[l], A @ Psi[l])
+        assert np.abs(D - E).max() <= 1e-12 * D.max(), l
+
+
+def test_fixed_point_is_the_composite_direct_solve():
+    T = disk_tree(eps=inp.eps_blocks(2, 2, 1.0, seed=10))
+    f = inp.rhs(2, 4, seed=11)
+    A, b, pos, lev, Psi, C = adaptive.dense_system(T, f)
+    assert np.abs(A - A.T).max() <= 1e-14 * np.abs(A).max()
+    assert np.linalg.eigvalsh(A)[0] > 0
+    ustar = np.linalg.solve(A, b)
+    U, hist = adaptive.solve(T, f, 400, tol=1e-13)
+    u = adaptive.to_composite(T, U)
+    assert hist[-1][0] / hist[0][0] <= 1e-13
+    assert np.linalg.norm(u - ustar) <= 1e-9 * np.linalg.norm(ustar)
+
+
+def test_finest_values_are_the_composite_function():
+    T = disk_tree()
+    U, _ = adaptive.solve(T, inp.rhs(2, 4, seed=12), 3)
+    F = adaptive.finest_values(T, U)
+    # at every composite dof the finest-lattice value is the dof's value
+    for l, i in T.composite_index():
+        v = np.array(np.unravel_index(i, T.shape(l))) * 3 ** (T.L - l)
+        assert F[tuple(v)] == U[l].ravel()[i]
