@@ -96,6 +96,32 @@ int adafac_create(adafac_ctx** out, int dim, int l_min, int l_max);
  * never called: eps = 1 (Poisson).  EINVAL on bad sizes or values. */
 int adafac_set_coefficient_blocks(adafac_ctx* ctx, int blocks_per_axis, const double* eps);
 
+/* Adaptive spacetree (Sec. 2.1): refinement flags of the cells of one level
+ * l_min <= level < l_max, over the whole (3^level)^dim cell lattice (C order, x
+ * fastest; nonzero = refine).  Flags of cells that do not exist are ignored.
+ * Levels without flags refine every existing cell, unless adafac_refine_ball
+ * covers them.  With any flags (or a ball) set, the context solves on the
+ * adaptive tree: levels are ragged, vertices of a level that are not
+ * surrounded by 2^dim cells of that level hang (d-linear interpolation of the
+ * next coarser level), and the composite grid is formed by the finest dof of
+ * every position.  The cycle works over the hierarchical generating system
+ * (Sec. 2.3, eq. (adaFACx)).  Adaptive trees support d-linear transfers,
+ * adAFAC-Jac and plain additive damping, FP64.  The coefficient blocks must be
+ * no finer than the first refined level.  Call build_operators again afterwards.
+ * EINVAL on a bad level or size. */
+int adafac_set_refinement(adafac_ctx* ctx, int level, const uint8_t* flags, size_t ncells);
+
+/* Refine, on levels l_from .. l_max-1 without explicit flags, every existing cell
+ * whose closure meets the closed ball |x - centre| <= radius (centre: dim
+ * coordinates, x first).  Levels below l_from refine every cell.  radius 0
+ * clears the ball.  EINVAL on non-finite values or l_from outside
+ * l_min..l_max-1. */
+int adafac_refine_ball(adafac_ctx* ctx, const double* centre, double radius, int l_from);
+
+/* Number of composite degrees of freedom of the built tree (0 before
+ * build_operators). */
+int64_t adafac_composite_dofs(const adafac_ctx* ctx);
+
 /* Right-hand side f sampled at the vertices of the finest level: n must equal
  * (3^l_max + 1)^dim; boundary entries are ignored.  The load vector is
  * b_v = m_v f_v with the lumped mass m_v (h^d on a uniform level).  EINVAL on
@@ -156,7 +182,14 @@ int adafac_get_solution(adafac_ctx* ctx, double* u, size_t n);
  * ignored.  Residual history is cleared.  Synchronises. */
 int adafac_set_solution(adafac_ctx* ctx, const double* u, size_t n);
 
-/* Copy a level array of the last cycle to host memory (inspection and
+/* Adaptive trees: the finest-lattice values returned by adafac_get_solution are
+ * the composite FE function at every finest vertex, and adafac_set_solution takes
+ * the values at the dofs' positions from such a lattice.  adafac_get_level
+ * returns which = 0 (nodal values u_l, hanging ones interpolated), 1 (b_l, the
+ * level hats tested against the composite residual) or 4 (S_l) for levels
+ * l_min..l_max, on the full level lattice, zero outside the level's cells.
+ *
+ * Copy a level array of the last cycle to host memory (inspection and
  * per-step parity checks).  which: 0 = u_l (FAS solution, injected),
  * 1 = b_l (FAS right-hand side), 2 = b~_l (auxiliary right-hand side),
  * 3 = r_l (level residual), 4 = S_l (accumulated correction P^{..}(c - c~)).

@@ -36,7 +36,9 @@ class Solver:
 
     def __init__(self, dim, lmin, lmax, f, eps_blocks=None, transfer="dlinear", damping="jac",
                  precision="fp64", inner_k=4, fused=True, omega=0.6, omega_tilde=0.6, omega_hat=0.5,
-                 device=None, stream=None):
+                 device=None, stream=None, refine=None, ball=None):
+        """``refine``: {level: flags over the (3^level)^dim cells} of an adaptive tree;
+        ``ball``: (centre, radius, l_from) refinement around a ball (adaptive tree)."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("adafac needs a ROCm GPU (gfx950); none is visible")
@@ -52,6 +54,14 @@ class Solver:
             _check(self.L, ctx, self.L.adafac_set_coefficient_blocks(ctx, e.shape[0], _dptr(e)))
         fa = np.ascontiguousarray(f, dtype=np.float64).ravel()
         _check(self.L, ctx, self.L.adafac_set_rhs_lattice(ctx, _dptr(fa), fa.size))
+        for level, flags in (refine or {}).items():
+            fl = np.ascontiguousarray(flags, dtype=np.uint8).ravel()
+            _check(self.L, ctx, self.L.adafac_set_refinement(ctx, level, fl.ctypes.data_as(C.POINTER(C.c_uint8)),
+                                                             fl.size))
+        if ball is not None:
+            centre, radius, l_from = ball
+            cc = np.ascontiguousarray(centre, dtype=np.float64)
+            _check(self.L, ctx, self.L.adafac_refine_ball(ctx, _dptr(cc), radius, l_from))
         o = _abi.Opts()
         self.L.adafac_default_opts(C.byref(o))
         o.transfer, o.damping, o.precision = TRANSFER[transfer], DAMPING[damping], PRECISION[precision]
@@ -101,6 +111,9 @@ class Solver:
 
     def dofs_per_cycle(self):
         return int(self.L.adafac_dofs_per_cycle(self.ctx))
+
+    def composite_dofs(self):
+        return int(self.L.adafac_composite_dofs(self.ctx))
 
     def set_kernel_timing(self, on):
         _check(self.L, self.ctx, self.L.adafac_set_kernel_timing(self.ctx, int(on)))

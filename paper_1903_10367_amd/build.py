@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libadafac.so")
-SOURCES = ["setup.cpp", "api.cpp", "server.cpp", "kernels_generic.hip", "kernels_fused.hip", "kernels_batch.hip"]
+SOURCES = ["setup.cpp", "adaptive.cpp", "api.cpp", "server.cpp", "kernels_adaptive.hip", "kernels_generic.hip", "kernels_fused.hip", "kernels_batch.hip"]
 
 
 def hipcc():

@@ -11,6 +11,7 @@
 
 #include "adafac.h"
 #include "adafac_internal.hpp"
+#include "adaptive.hpp"
 
 namespace adafac {
 
@@ -98,6 +99,16 @@ struct adafac_ctx {
   double* norm0 = nullptr;  // (l2h, linf) of iterate 0, kept beyond the ring
   double r0 = -1.0;         // l2h of iterate 0 (host copy, set by solve)
   int ncyc = 0;
+  // adaptive spacetree (set_refinement / refine_ball)
+  std::vector<RefineSpec> refine;
+  double ball_c[3] = {0, 0, 0};
+  double ball_r = 0.0;
+  int ball_from = 0;
+  bool adaptive = false;
+  AdaptHost at;
+  RtSep<double> ad_rts{};
+  std::vector<AdaptLevel> ad;           // device views by level
+  double* ad_eps = nullptr;
   // kernel timing
   bool timing = false;
   std::vector<hipEvent_t> ev;
@@ -128,7 +139,10 @@ size_t nverts_of(int d, int l) {
 bool mixed(const adafac_ctx* c) { return c->opts.precision == ADAFAC_PREC_FP32_REFINED; }
 
 // Lay out every device array inside the workspace; with base == nullptr only sizes.
+size_t layout_adaptive(adafac_ctx* c, char* base);
+
 size_t layout(adafac_ctx* c, char* base) {
+  if (c->adaptive) return layout_adaptive(c, base);
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
     off = (off + 255) & ~size_t(255);
@@ -324,8 +338,11 @@ int run_cycle(adafac_ctx* c, Hier<T>& H, double* norm_out, const T* uin_zero) {
 
 // Add the pending prolongated coarse correction to the current FP64 iterate (FP64 form), or
 // the pending inner correction e + P S_{L-1} to the FP64 solution (FP32_REFINED).
+int adapt_hang(adafac_ctx* c);
+
 int flush(adafac_ctx* c) {
   const int L = c->L;
+  if (c->adaptive) return adapt_hang(c);
   if (mixed(c)) {
     if (!c->e_pending) return ADAFAC_OK;
     Hier<float>& H = c->h32;
@@ -345,12 +362,91 @@ int flush(adafac_ctx* c) {
   return ADAFAC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Adaptive spacetrees: per-level box arrays and the cycle over the ragged levels
+// ---------------------------------------------------------------------------
+size_t layout_adaptive(adafac_ctx* c, char* base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    off = (off + 255) & ~size_t(255);
+    char* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  };
+  const int d = c->dim;
+  c->ad.assign(c->L + 1, AdaptLevel{});
+  c->ad_eps = reinterpret_cast<double*>(take(sizeof(double) * c->ops.eps.size()));
+  const bool unit = c->ops.nb == 1 && c->ops.eps[0] == 1.0;
+  for (int l = c->lmin; l <= c->L; ++l) {
+    const AdaptHostLevel& H = c->at.lev[l];
+    AdaptLevel& A = c->ad[l];
+    A.ox = H.lo[0];
+    A.oy = H.lo[1];
+    A.oz = d == 3 ? H.lo[2] : 0;
+    A.mx = H.nc[0] + 1;
+    A.my = H.nc[1] + 1;
+    A.mz = d == 3 ? H.nc[2] + 1 : 1;
+    A.n = ipow3(l);
+    A.h = 1.0 / A.n;
+    A.hd = std::pow(A.h, d);
+    A.hdm2 = std::pow(A.h, d - 2);
+    A.fem = H.dg.empty() ? 1 : 0;
+    A.nb = c->ops.nb;
+    A.bs = A.fem ? ipow3(l - c->ops.k) : 1;
+    A.eps = unit ? nullptr : c->ad_eps;
+    const size_t nv = H.nverts(), ncell = H.ncells();
+    A.vcls = reinterpret_cast<uint8_t*>(take(nv));
+    A.leaf = reinterpret_cast<uint8_t*>(take(ncell));
+    if (!A.fem) A.dg = reinterpret_cast<double*>(take(sizeof(double) * nv));
+    A.bleaf = reinterpret_cast<double*>(take(sizeof(double) * nv));
+    A.u = reinterpret_cast<double*>(take(sizeof(double) * nv));
+    A.bb = reinterpret_cast<double*>(take(sizeof(double) * nv));
+    A.hh = reinterpret_cast<double*>(take(sizeof(double) * nv));
+    A.s = reinterpret_cast<double*>(take(sizeof(double) * nv));
+    A.S = reinterpret_cast<double*>(take(sizeof(double) * nv));
+  }
+  c->npartials = size_t(kAdaptNormBlocks) * (c->L - c->lmin + 1);
+  c->partials = reinterpret_cast<double*>(take(sizeof(double) * 2 * c->npartials));
+  c->norms = reinterpret_cast<double*>(take(sizeof(double) * 2 * kMaxHist));
+  c->scratch_norm = reinterpret_cast<double*>(take(sizeof(double) * 2));
+  c->norm0 = reinterpret_cast<double*>(take(sizeof(double) * 2));
+  return (off + 255) & ~size_t(255);
+}
+
+// hanging vertices interpolated top-down from the current nodal values
+int adapt_hang(adafac_ctx* c) {
+  for (int l = c->lmin + 1; l <= c->L; ++l) HIPCHK(c, launch_ad_hang(c->dim, c->ad[l], c->ad[l - 1], c->stream));
+  return ADAFAC_OK;
+}
+
+int run_adapt_cycle(adafac_ctx* c, double* norm_out) {
+  const int d = c->dim, L = c->L, lmin = c->lmin;
+  const adafac_opts& o = c->opts;
+  int rc = adapt_hang(c);
+  if (rc) return rc;
+  if ((rc = record_start(c))) return rc;
+  for (int l = lmin; l <= L; ++l) HIPCHK(c, launch_ad_leaf(d, c->ad[l], c->stream));
+  if ((rc = record_stop(c))) return rc;
+  for (int l = L; l >= lmin; --l)
+    HIPCHK(c, launch_ad_up(d, c->ad[l], l < L ? &c->ad[l + 1] : nullptr, c->ad_rts, o.omega, o.omega_tilde,
+                           o.damping, c->partials + 2 * size_t(kAdaptNormBlocks) * (l - lmin), c->stream));
+  HIPCHK(c, launch_norm_finalize(c->partials, int(c->npartials), norm_out, c->stream));
+  for (int l = lmin; l <= L; ++l)
+    HIPCHK(c, launch_ad_down(d, c->ad[l], l > lmin ? &c->ad[l - 1] : nullptr, c->stream));
+  for (int l = L; l >= lmin; --l)
+    HIPCHK(c, launch_ad_update(d, c->ad[l], l < L ? &c->ad[l + 1] : nullptr, c->stream));
+  return ADAFAC_OK;
+}
+
 // FP64 form: one cycle.  FP32_REFINED: the FP64 part of an outer step, i.e. the pending inner
 // correction added to u and the FP64 defect r = b - A u with its norms (the norms of the outer
 // iterate), stored in FP32 as the right-hand side of the next inner solve.
 int run_outer(adafac_ctx* c) {
   double* norm_out = c->norms + 2 * (c->ncyc % kMaxHist);
-  if (!mixed(c)) {
+  if (c->adaptive) {
+    int rc = run_adapt_cycle(c, norm_out);
+    if (rc) return rc;
+  } else if (!mixed(c)) {
     int rc = run_cycle<double>(c, c->h64, norm_out, nullptr);
     if (rc) return rc;
   } else if (c->dim == 3 && c->opts.fused && fused_ok(c)) {
@@ -428,6 +524,158 @@ int upload_ops(adafac_ctx* c, Hier<T>& H, bool coarse) {
   for (int i = 0; i < 5; ++i) H.rts.m[i] = T(c->ops.rt_m[i]);
   H.rts.scale = T(c->ops.rt_scale);
   return ADAFAC_OK;
+}
+
+// Host set-up of an adaptive context: the tree, the Galerkin diagonals of the uniform levels
+// below the coefficient blocks, and the factors of R~.
+int build_adaptive(adafac_ctx* c) {
+  const adafac_opts& o = c->opts;
+  if (o.transfer != ADAFAC_TRANSFER_DLINEAR) return fail(c, ADAFAC_EUNSUPPORTED, "adaptive trees use d-linear transfers");
+  if (o.damping != ADAFAC_DAMP_JAC && o.damping != ADAFAC_DAMP_NONE)
+    return fail(c, ADAFAC_EUNSUPPORTED, "adaptive trees support adAFAC-Jac and plain additive damping");
+  if (o.precision != ADAFAC_PREC_FP64) return fail(c, ADAFAC_EUNSUPPORTED, "adaptive trees run in FP64");
+  if (c->L <= c->lmin) return fail(c, ADAFAC_EINVAL, "an adaptive tree needs l_max > l_min");
+  int first = c->L;
+  for (const RefineSpec& r : c->refine) first = std::min(first, r.level);
+  if (c->ball_r > 0.0) first = std::min(first, std::max(c->ball_from, c->lmin));
+  if (c->ops.k > first)
+    return fail(c, ADAFAC_EINVAL, "coefficient blocks finer than the first refined level of the tree");
+  std::string m = build_adapt_tree(c->at, c->dim, c->lmin, c->L, c->refine, c->ball_c, c->ball_r, c->ball_from);
+  if (!m.empty()) return fail(c, ADAFAC_EINVAL, m);
+  // uniform hierarchy up to max(k, lmin + 1): R~ factors and Galerkin diagonals below level k
+  HostOps u;
+  u.dim = c->dim;
+  u.lmin = c->lmin;
+  u.L = std::max(c->ops.k, c->lmin + 1);
+  u.nb = c->nb;
+  u.k = c->ops.k;
+  u.eps = c->eps;
+  m = build_host_ops(u, 0, o.omega);
+  if (!m.empty()) return fail(c, ADAFAC_EINVAL, m);
+  for (int i = 0; i < 5; ++i) c->ad_rts.m[i] = u.rt_m[i];
+  c->ad_rts.scale = u.rt_scale;
+  for (int l = c->lmin; l < c->ops.k; ++l) c->at.lev[l].dg = u.lev[l].dg;   // uniform levels: full box
+  c->ops.lev = std::move(u.lev);     // kept for host_operator queries of the uniform part
+  c->ops.rtilde = u.rtilde;
+  c->ops.rt_scale = u.rt_scale;
+  for (int i = 0; i < 5; ++i) c->ops.rt_m[i] = u.rt_m[i];
+  return ADAFAC_OK;
+}
+
+// Uploads of an adaptive context: classes, leaf cells, stored diagonals, lumped loads.
+int bind_adaptive(adafac_ctx* c) {
+  const int d = c->dim, L = c->L;
+  HIPCHK(c, hipMemcpyAsync(c->ad_eps, c->ops.eps.data(), sizeof(double) * c->ops.eps.size(), hipMemcpyHostToDevice,
+                           c->stream));
+  const int nL = ipow3(L) + 1;
+  for (int l = c->lmin; l <= L; ++l) {
+    const AdaptHostLevel& H = c->at.lev[l];
+    const AdaptLevel& A = c->ad[l];
+    std::vector<uint8_t> leaf(H.ncells());
+    for (size_t i = 0; i < leaf.size(); ++i) leaf[i] = H.exists[i] && !H.refined[i];
+    // lumped load: m_v f_v, m_v = |leaf cells around v| h^d / 2^d, f sampled from the finest lattice
+    std::vector<double> bl(H.nverts(), 0.0);
+    const int s = ipow3(L - l);
+    const double share = A.hd / double(1 << d);
+    for (int z = 0; z < A.mz; ++z)
+      for (int y = 0; y < A.my; ++y)
+        for (int x = 0; x < A.mx; ++x) {
+          const size_t i = (size_t(z) * A.my + y) * A.mx + x;
+          if (!(H.vcls[i] & (kDof | kHang))) continue;
+          int nleaf = 0;
+          for (int e = 0; e < (1 << d); ++e) {
+            const int cx = x - 1 + (e & 1), cy = y - 1 + ((e >> 1) & 1), cz = d == 3 ? z - 1 + ((e >> 2) & 1) : 0;
+            if (cx < 0 || cy < 0 || cz < 0 || cx >= H.nc[0] || cy >= H.nc[1] || cz >= H.nc[2]) continue;
+            nleaf += leaf[(size_t(cz) * H.nc[1] + cy) * H.nc[0] + cx];
+          }
+          if (!nleaf) continue;
+          const size_t gx = size_t(A.ox + x) * s, gy = size_t(A.oy + y) * s, gz = d == 3 ? size_t(A.oz + z) * s : 0;
+          bl[i] = nleaf * share * c->f[(gz * nL + gy) * nL + gx];
+        }
+    HIPCHK(c, hipMemcpyAsync(const_cast<uint8_t*>(A.vcls), H.vcls.data(), H.vcls.size(), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(const_cast<uint8_t*>(A.leaf), leaf.data(), leaf.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(const_cast<double*>(A.bleaf), bl.data(), sizeof(double) * bl.size(), hipMemcpyHostToDevice,
+                             c->stream));
+    if (!A.fem)
+      HIPCHK(c, hipMemcpyAsync(const_cast<double*>(A.dg), H.dg.data(), sizeof(double) * H.dg.size(),
+                               hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));   // host vectors go out of scope
+  }
+  return ADAFAC_OK;
+}
+
+// Composite FE function at every vertex of the finest lattice (host, from the level boxes).
+int adaptive_finest(adafac_ctx* c, double* out) {
+  const int d = c->dim, L = c->L, lmin = c->lmin;
+  int rc = adapt_hang(c);
+  if (rc) return rc;
+  std::vector<double> cur, up;
+  int ncur = 0;
+  for (int l = lmin; l <= L; ++l) {
+    const AdaptHostLevel& H = c->at.lev[l];
+    const AdaptLevel& A = c->ad[l];
+    std::vector<double> box(H.nverts());
+    HIPCHK(c, hipMemcpyAsync(box.data(), A.u, sizeof(double) * box.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int n = ipow3(l), nv = n + 1;
+    const size_t full = d == 2 ? size_t(nv) * nv : size_t(nv) * nv * nv;
+    up.assign(full, 0.0);
+    if (l > lmin) {
+      // d-linear interpolation of the coarser level's composite function
+      for (size_t i = 0; i < full; ++i) {
+        const int x = int(i % nv), y = int((i / nv) % nv), z = d == 3 ? int(i / (size_t(nv) * nv)) : 0;
+        const int cx = std::min(x / 3, ncur - 1), cy = std::min(y / 3, ncur - 1), cz = d == 3 ? std::min(z / 3, ncur - 1) : 0;
+        const int sx = x - 3 * cx, sy = y - 3 * cy, sz = z - 3 * cz;
+        double acc = 0.0;
+        for (int e = 0; e < (1 << d); ++e) {
+          const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+          double w = (ex ? sx : 3 - sx) / 3.0 * (ey ? sy : 3 - sy) / 3.0;
+          if (d == 3) w *= (ez ? sz : 3 - sz) / 3.0;
+          if (w == 0.0) continue;
+          const size_t k = (size_t(cz + ez) * (ncur + 1) + (cy + ey)) * (ncur + 1) + (cx + ex);
+          acc += w * cur[d == 2 ? size_t(cy + ey) * (ncur + 1) + (cx + ex) : k];
+        }
+        up[i] = acc;
+      }
+    }
+    for (int z = 0; z < A.mz; ++z)
+      for (int y = 0; y < A.my; ++y)
+        for (int x = 0; x < A.mx; ++x) {
+          const size_t i = (size_t(z) * A.my + y) * A.mx + x;
+          if (!(H.vcls[i] & (kDof | kHang))) continue;
+          const size_t g = d == 2 ? size_t(A.oy + y) * nv + (A.ox + x)
+                                  : (size_t(A.oz + z) * nv + (A.oy + y)) * nv + (A.ox + x);
+          up[g] = box[i];
+        }
+    cur.swap(up);
+    ncur = n;
+  }
+  std::memcpy(out, cur.data(), sizeof(double) * cur.size());
+  return ADAFAC_OK;
+}
+
+// Nodal values at every dof of every level from values on the finest lattice.
+int adaptive_set(adafac_ctx* c, const double* u) {
+  const int d = c->dim, L = c->L;
+  const int nL = ipow3(L) + 1;
+  for (int l = c->lmin; l <= L; ++l) {
+    const AdaptHostLevel& H = c->at.lev[l];
+    const AdaptLevel& A = c->ad[l];
+    const int s = ipow3(L - l);
+    std::vector<double> box(H.nverts(), 0.0);
+    for (int z = 0; z < A.mz; ++z)
+      for (int y = 0; y < A.my; ++y)
+        for (int x = 0; x < A.mx; ++x) {
+          const size_t i = (size_t(z) * A.my + y) * A.mx + x;
+          if (!(H.vcls[i] & kDof)) continue;
+          const size_t gx = size_t(A.ox + x) * s, gy = size_t(A.oy + y) * s, gz = d == 3 ? size_t(A.oz + z) * s : 0;
+          box[i] = u[(gz * nL + gy) * nL + gx];
+        }
+    HIPCHK(c, hipMemcpyAsync(A.u, box.data(), sizeof(double) * box.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return adapt_hang(c);
 }
 
 }  // namespace
@@ -562,6 +810,15 @@ int adafac_build_operators(adafac_ctx* c, const adafac_opts* opts) {
   c->ops.k = 0;
   for (int b = 1; b < c->nb; b *= 3) c->ops.k++;
   c->ops.eps = c->eps;
+  c->adaptive = !c->refine.empty() || c->ball_r > 0.0;
+  if (c->adaptive) {
+    int rc = build_adaptive(c);
+    if (rc) return rc;
+    c->built = true;
+    c->bound = false;
+    c->ws_need = layout(c, nullptr);
+    return ADAFAC_OK;
+  }
   std::string m = build_host_ops(c->ops, o.transfer == ADAFAC_TRANSFER_BOXMG, o.omega);
   if (!m.empty()) return fail(c, ADAFAC_EINVAL, m);
   c->built = true;
@@ -590,6 +847,14 @@ int adafac_bind(adafac_ctx* c, void* ws, size_t bytes, void* stream) {
   layout(c, c->ws);
   const int d = c->dim;
   HIPCHK(c, hipMemsetAsync(c->ws, 0, need, c->stream));
+  if (c->adaptive) {
+    int rc = bind_adaptive(c);
+    if (rc) return rc;
+    c->ncyc = 0;
+    c->r0 = -1.0;
+    c->bound = true;
+    return ADAFAC_OK;
+  }
   int rc = upload_ops<double>(c, c->h64, !mixed(c));
   if (!rc && mixed(c)) rc = upload_ops<float>(c, c->h32, true);
   if (rc) return rc;
@@ -677,6 +942,7 @@ int adafac_get_solution(adafac_ctx* c, double* u, size_t n) {
   if (!c) return ADAFAC_EINVAL;
   if (!ready(c)) return fail(c, ADAFAC_ESTATE, "bind first");
   if (!u || n != nverts_of(c->dim, c->L)) return fail(c, ADAFAC_EINVAL, "u: wrong size");
+  if (c->adaptive) return adaptive_finest(c, u);
   int rc = flush(c);
   if (rc) return rc;
   HIPCHK(c, hipMemcpyAsync(u, c->h64.ufine[c->h64.cur], sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
@@ -688,18 +954,25 @@ int adafac_set_solution(adafac_ctx* c, const double* u, size_t n) {
   if (!c) return ADAFAC_EINVAL;
   if (!ready(c)) return fail(c, ADAFAC_ESTATE, "bind first");
   if (!u || n != nverts_of(c->dim, c->L)) return fail(c, ADAFAC_EINVAL, "u: wrong size");
-  const HostLevel& fl = c->ops.lev[c->L];
+  const int nv = ipow3(c->L) + 1;
   std::vector<double> v(u, u + n);
   for (size_t i = 0; i < n; ++i) {
     size_t t = i;
     for (int a = 0; a < c->dim; ++a) {
-      int x = int(t % fl.nv);
-      t /= fl.nv;
-      if (x == 0 || x == fl.nv - 1) v[i] = 0.0;
+      int x = int(t % nv);
+      t /= nv;
+      if (x == 0 || x == nv - 1) v[i] = 0.0;
     }
     if (!std::isfinite(v[i])) return fail(c, ADAFAC_EINVAL, "u: non-finite value");
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->adaptive) {
+    int rc = adaptive_set(c, v.data());
+    if (rc) return rc;
+    c->ncyc = 0;
+    c->r0 = -1.0;
+    return ADAFAC_OK;
+  }
   HIPCHK(c, hipMemcpyAsync(c->h64.ufine[c->h64.cur], v.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->h64.pending = c->h32.pending = c->e_pending = false;
@@ -711,6 +984,37 @@ int adafac_set_solution(adafac_ctx* c, const double* u, size_t n) {
 int adafac_get_level(adafac_ctx* c, int level, int which, double* out, size_t n) {
   if (!c) return ADAFAC_EINVAL;
   if (!ready(c)) return fail(c, ADAFAC_ESTATE, "bind first");
+  if (c->adaptive) {
+    // the level's box arrays on the full level lattice, zero outside the box
+    if (level < c->lmin || level > c->L) return fail(c, ADAFAC_EINVAL, "level out of range");
+    if (!out || n != nverts_of(c->dim, level)) return fail(c, ADAFAC_EINVAL, "out: wrong size");
+    const AdaptLevel& A = c->ad[level];
+    const double* src = nullptr;
+    switch (which) {
+      case 0: src = A.u; break;
+      case 1: src = A.bb; break;
+      case 4: src = A.S; break;
+      default: return fail(c, ADAFAC_EINVAL, "which: 0 (u), 1 (b), 4 (S) on adaptive trees");
+    }
+    if (which == 0) {
+      int rc = adapt_hang(c);
+      if (rc) return rc;
+    }
+    const AdaptHostLevel& H = c->at.lev[level];
+    std::vector<double> box(H.nverts());
+    HIPCHK(c, hipMemcpyAsync(box.data(), src, sizeof(double) * box.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int nv = ipow3(level) + 1;
+    std::fill(out, out + n, 0.0);
+    for (int z = 0; z < A.mz; ++z)
+      for (int y = 0; y < A.my; ++y)
+        for (int x = 0; x < A.mx; ++x) {
+          const size_t g = c->dim == 2 ? size_t(A.oy + y) * nv + (A.ox + x)
+                                       : (size_t(A.oz + z) * nv + (A.oy + y)) * nv + (A.ox + x);
+          out[g] = box[(size_t(z) * A.my + y) * A.mx + x];
+        }
+    return ADAFAC_OK;
+  }
   if (level < c->lmin || level >= c->L) return fail(c, ADAFAC_EINVAL, "level out of range");
   if (!out || n != nverts_of(c->dim, level)) return fail(c, ADAFAC_EINVAL, "out: wrong size");
   if (mixed(c)) return fail(c, ADAFAC_ESTATE, "level arrays are kept in the FP64 form only");
@@ -734,6 +1038,7 @@ int adafac_host_operator(const adafac_ctx* cc, int level, int which, double* out
   if (!c || !out) return ADAFAC_EINVAL;
   if (!c->built) return fail(c, ADAFAC_ESTATE, "build_operators first");
   const int d = c->dim, ns = d == 2 ? 9 : 27;
+  if (c->adaptive && which != 3) return fail(c, ADAFAC_EUNSUPPORTED, "host operators of uniform hierarchies only");
   if (which == 3) {
     if (n != c->ops.rtilde.size()) return fail(c, ADAFAC_EINVAL, "out: wrong size");
     std::memcpy(out, c->ops.rtilde.data(), sizeof(double) * n);
@@ -798,6 +1103,11 @@ int adafac_host_operator(const adafac_ctx* cc, int level, int which, double* out
 int64_t adafac_dofs_per_cycle(const adafac_ctx* c) {
   if (!c) return 0;
   int64_t s = 0;
+  if (c->adaptive && c->built) {
+    for (int l = c->lmin; l <= c->L; ++l)
+      for (uint8_t v : c->at.lev[l].vcls) s += (v & kDof) ? 1 : 0;
+    return s;
+  }
   for (int l = c->lmin; l <= c->L; ++l) {
     int64_t m = ipow3(l) - 1;
     s += c->dim == 2 ? m * m : m * m * m;
@@ -831,6 +1141,45 @@ int adafac_kernel_time(adafac_ctx* c, double* total_ms, int* launches) {
   if (total_ms) *total_ms = c->t_acc;
   if (launches) *launches = c->t_launches;
   return ADAFAC_OK;
+}
+
+int adafac_set_refinement(adafac_ctx* c, int level, const uint8_t* flags, size_t ncells) {
+  if (!c) return ADAFAC_EINVAL;
+  if (level < c->lmin || level >= c->L) return fail(c, ADAFAC_EINVAL, "level must lie in l_min..l_max-1");
+  const size_t n = size_t(ipow3(level));
+  if (!flags || ncells != (c->dim == 2 ? n * n : n * n * n)) return fail(c, ADAFAC_EINVAL, "flags: wrong size");
+  RefineSpec r;
+  r.level = level;
+  r.flags.assign(flags, flags + ncells);
+  for (auto it = c->refine.begin(); it != c->refine.end(); ++it)
+    if (it->level == level) {
+      c->refine.erase(it);
+      break;
+    }
+  c->refine.push_back(std::move(r));
+  c->built = c->bound = false;
+  return ADAFAC_OK;
+}
+
+int adafac_refine_ball(adafac_ctx* c, const double* centre, double radius, int l_from) {
+  if (!c) return ADAFAC_EINVAL;
+  if (!centre || !(radius >= 0.0) || !std::isfinite(radius)) return fail(c, ADAFAC_EINVAL, "bad ball");
+  if (l_from < c->lmin || l_from >= c->L) return fail(c, ADAFAC_EINVAL, "l_from must lie in l_min..l_max-1");
+  for (int a = 0; a < c->dim; ++a) {
+    if (!std::isfinite(centre[a])) return fail(c, ADAFAC_EINVAL, "bad ball centre");
+    c->ball_c[a] = centre[a];
+  }
+  c->ball_r = radius;
+  c->ball_from = l_from;
+  c->built = c->bound = false;
+  return ADAFAC_OK;
+}
+
+int64_t adafac_composite_dofs(const adafac_ctx* c) {
+  if (!c || !c->built) return 0;
+  if (c->adaptive) return int64_t(c->at.composite);
+  const int64_t m = ipow3(c->L) - 1;
+  return c->dim == 2 ? m * m : m * m * m;
 }
 
 void adafac_destroy(adafac_ctx* c) {

@@ -1,0 +1,280 @@
+// gfx950 kernels of the adAFAC cycle on adaptive spacetrees (ragged levels with hanging
+// vertices; Sec. 2.1, 2.3, 2.4; eq. (adaFACx) / Algorithm 1 over the generating system).
+// One thread per vertex of a level's box.  Per cycle:
+//   hang    hanging vertices take the d-linear interpolation of the next coarser level
+//   leaf    residual of the level's leaf cells (element-wise Q1, lumped load)
+//   up      finest to coarsest: b_l = r^leaf_l + R b_{l+1} (the level hats tested against the
+//           composite residual), the hanging-only part that forms the composite residual at
+//           the composite dofs (norm partials), and the corrections c - c~ at the dofs
+//   down    coarsest to finest: S_l = (c - c~)_l + P S_{l-1}
+//   update  finest to coarsest: composite dofs u += S, other dofs copy the finer dof
+#include <hip/hip_runtime.h>
+
+#include "adafac.h"
+#include "adafac_internal.hpp"
+#include "adaptive.hpp"
+#include "kernels_common.hpp"
+
+namespace adafac {
+namespace {
+
+constexpr int NTA = 256;
+
+template <int D>
+__device__ __forceinline__ long vidx(const AdaptLevel& A, int x, int y, int z) {
+  x -= A.ox;
+  y -= A.oy;
+  z -= A.oz;
+  if (x < 0 || x >= A.mx || y < 0 || y >= A.my) return -1;
+  if (D == 3 && (z < 0 || z >= A.mz)) return -1;
+  return (long(D == 3 ? z : 0) * A.my + y) * A.mx + x;
+}
+
+template <int D>
+__device__ __forceinline__ long cidx(const AdaptLevel& A, int cx, int cy, int cz) {
+  cx -= A.ox;
+  cy -= A.oy;
+  cz -= A.oz;
+  if (cx < 0 || cx >= A.mx - 1 || cy < 0 || cy >= A.my - 1) return -1;
+  if (D == 3 && (cz < 0 || cz >= A.mz - 1)) return -1;
+  return (long(D == 3 ? cz : 0) * (A.my - 1) + cy) * (A.mx - 1) + cx;
+}
+
+template <int D>
+__device__ __forceinline__ long nbox(const AdaptLevel& A) {
+  return long(A.mx) * A.my * (D == 3 ? A.mz : 1);
+}
+
+template <int D>
+__device__ __forceinline__ void coords(const AdaptLevel& A, long i, int& x, int& y, int& z) {
+  x = A.ox + int(i % A.mx);
+  y = A.oy + int((i / A.mx) % A.my);
+  z = D == 3 ? A.oz + int(i / (long(A.mx) * A.my)) : 0;
+}
+
+__device__ __forceinline__ double eps_of(const AdaptLevel& A, int cx, int cy, int cz, int d) {
+  if (!A.eps) return 1.0;
+  const int bx = cx / A.bs, by = cy / A.bs, bz = cz / A.bs;
+  return d == 2 ? A.eps[by * A.nb + bx] : A.eps[(bz * A.nb + by) * A.nb + bx];
+}
+
+// d-linear interpolation weight of coarse corner e at fine offset s (0..3 along each axis)
+__device__ __forceinline__ double lin3(int s, int e) { return e ? double(s) / 3.0 : double(3 - s) / 3.0; }
+
+template <int D>
+__device__ __forceinline__ double interp(const AdaptLevel& C, const double* v, int x, int y, int z) {
+  const int nc = C.n;
+  const int cx = min(x / 3, nc - 1), cy = min(y / 3, nc - 1), cz = D == 3 ? min(z / 3, nc - 1) : 0;
+  const int sx = x - 3 * cx, sy = y - 3 * cy, sz = z - 3 * cz;
+  double acc = 0.0;
+#pragma unroll
+  for (int e = 0; e < (1 << D); ++e) {
+    const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+    double w = lin3(sx, ex) * lin3(sy, ey);
+    if (D == 3) w *= lin3(sz, ez);
+    if (w == 0.0) continue;
+    const long k = vidx<D>(C, cx + ex, cy + ey, cz + ez);
+    if (k >= 0) acc += w * v[k];
+  }
+  return acc;
+}
+
+// Q1 diagonal at a dof (all 2^d cells exist): kref h^(d-2) sum of the cells' eps
+template <int D>
+__device__ __forceinline__ double diag_at(const AdaptLevel& A, long i, int x, int y, int z) {
+  if (!A.fem) return A.dg[i];
+  double es = 0.0;
+#pragma unroll
+  for (int e = 0; e < (1 << D); ++e) {
+    const int cx = x - 1 + (e & 1), cy = y - 1 + ((e >> 1) & 1), cz = D == 3 ? z - 1 + ((e >> 2) & 1) : 0;
+    es += eps_of(A, cx, cy, cz, D);
+  }
+  return (D == 2 ? 2.0 / 3.0 : 1.0 / 3.0) * A.hdm2 * es;
+}
+
+// Q1 reference element entry between corners i and j (bit a = offset along axis a)
+template <int D>
+__device__ __forceinline__ double kref(int i, int j) {
+  const int hd = __popc(unsigned(i ^ j));
+  if (D == 2) return hd == 0 ? 2.0 / 3.0 : (hd == 1 ? -1.0 / 6.0 : -1.0 / 3.0);
+  return hd == 0 ? 1.0 / 3.0 : (hd == 1 ? 0.0 : -1.0 / 12.0);
+}
+
+template <int D>
+__global__ void __launch_bounds__(NTA) k_ad_hang(AdaptLevel A, AdaptLevel C) {
+  const long nb = nbox<D>(A);
+  for (long i = long(blockIdx.x) * NTA + threadIdx.x; i < nb; i += long(gridDim.x) * NTA) {
+    if (!(A.vcls[i] & kHang)) continue;
+    int x, y, z;
+    coords<D>(A, i, x, y, z);
+    A.u[i] = interp<D>(C, C.u, x, y, z);
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(NTA) k_ad_leaf(AdaptLevel A) {
+  const long nb = nbox<D>(A);
+  const int n = A.n;
+  for (long i = long(blockIdx.x) * NTA + threadIdx.x; i < nb; i += long(gridDim.x) * NTA) {
+    int x, y, z;
+    coords<D>(A, i, x, y, z);
+    double r = 0.0;
+    const bool inter = x > 0 && x < n && y > 0 && y < n && (D == 2 || (z > 0 && z < n));
+    if (inter) {
+      r = A.bleaf[i];
+#pragma unroll
+      for (int e = 0; e < (1 << D); ++e) {
+        // cell with lower corner (cx, cy, cz); this vertex is its corner iw
+        const int ax = e & 1, ay = (e >> 1) & 1, az = (e >> 2) & 1;
+        const int cx = x - ax, cy = y - ay, cz = D == 3 ? z - az : 0;
+        const long c = cidx<D>(A, cx, cy, cz);
+        if (c < 0 || !A.leaf[c]) continue;
+        const int iw = ax | (ay << 1) | (az << 2);
+        double sum = 0.0;
+#pragma unroll
+        for (int j = 0; j < (1 << D); ++j) {
+          const long k = vidx<D>(A, cx + (j & 1), cy + ((j >> 1) & 1), cz + ((j >> 2) & 1));
+          sum += kref<D>(iw, j) * A.u[k];
+        }
+        r -= eps_of(A, cx, cy, cz, D) * A.hdm2 * sum;
+      }
+    }
+    A.bb[i] = r;
+  }
+}
+
+__device__ __forceinline__ double wl(int o) { return o == 0 ? 1.0 : (o == 1 || o == -1) ? 2.0 / 3.0 : 1.0 / 3.0; }
+
+template <int D>
+__global__ void __launch_bounds__(NTA) k_ad_up(AdaptLevel A, AdaptLevel F, int has_f, RtSep<double> rts,
+                                               double omega, double omega_t, int jac, double* partials) {
+  const long nb = nbox<D>(A);
+  double ssum = 0.0, smax = 0.0;
+  for (long i = long(blockIdx.x) * NTA + threadIdx.x; i < nb; i += long(gridDim.x) * NTA) {
+    const uint8_t cls = A.vcls[i];
+    const double rl = A.bb[i];
+    double Rb = 0.0, Rh = 0.0, Rt = 0.0;
+    int x, y, z;
+    coords<D>(A, i, x, y, z);
+    if (has_f && (cls & (kDof | kHang))) {
+      for (int oz = (D == 3 ? -2 : 0); oz <= (D == 3 ? 2 : 0); ++oz)
+        for (int oy = -2; oy <= 2; ++oy)
+          for (int ox = -2; ox <= 2; ++ox) {
+            const long k = vidx<D>(F, 3 * x + ox, 3 * y + oy, 3 * z + oz);
+            if (k < 0) continue;
+            const double w = wl(ox) * wl(oy) * (D == 3 ? wl(oz) : 1.0);
+            const double fb = F.bb[k];
+            Rb += w * fb;
+            Rh += w * F.hh[k];
+            if (jac && (cls & kDof) && (F.vcls[k] & kDof)) {
+              // R~ = scale sum_a delta(o_a) prod_{b != a} m(o_b)
+              double wt;
+              if (D == 2) {
+                wt = (ox == 0 ? rts.m[oy + 2] : 0.0) + (oy == 0 ? rts.m[ox + 2] : 0.0);
+              } else {
+                wt = (ox == 0 ? rts.m[oy + 2] * rts.m[oz + 2] : 0.0) + (oy == 0 ? rts.m[ox + 2] * rts.m[oz + 2] : 0.0) +
+                     (oz == 0 ? rts.m[ox + 2] * rts.m[oy + 2] : 0.0);
+              }
+              Rt += rts.scale * wt * fb;
+            }
+          }
+    }
+    const double acc = rl + Rb, acch = rl + Rh;
+    A.bb[i] = acc;
+    A.hh[i] = (cls & kHang) ? acch : 0.0;
+    if (cls & kComp) {
+      ssum += A.hd * acch * acch;
+      smax = fmax(smax, fabs(acch));
+    }
+    double sv = 0.0;
+    if (cls & kDof) {
+      const double dg = diag_at<D>(A, i, x, y, z);
+      sv = omega * acc / dg;
+      if (jac && has_f) sv -= omega_t * Rt / dg;
+    }
+    A.s[i] = sv;
+  }
+  block_norm_partials(ssum, smax, partials);
+}
+
+template <int D>
+__global__ void __launch_bounds__(NTA) k_ad_down(AdaptLevel A, AdaptLevel C, int has_c) {
+  const long nb = nbox<D>(A);
+  for (long i = long(blockIdx.x) * NTA + threadIdx.x; i < nb; i += long(gridDim.x) * NTA) {
+    const uint8_t cls = A.vcls[i];
+    double S = 0.0;
+    if (cls & (kDof | kHang)) {
+      S = A.s[i];
+      if (has_c) {
+        int x, y, z;
+        coords<D>(A, i, x, y, z);
+        S += interp<D>(C, C.S, x, y, z);
+      }
+    }
+    A.S[i] = S;
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(NTA) k_ad_update(AdaptLevel A, AdaptLevel F, int has_f) {
+  const long nb = nbox<D>(A);
+  for (long i = long(blockIdx.x) * NTA + threadIdx.x; i < nb; i += long(gridDim.x) * NTA) {
+    const uint8_t cls = A.vcls[i];
+    if (cls & kComp) {
+      A.u[i] += A.S[i];
+    } else if ((cls & kDof) && has_f) {
+      int x, y, z;
+      coords<D>(A, i, x, y, z);
+      const long k = vidx<D>(F, 3 * x, 3 * y, 3 * z);
+      if (k >= 0) A.u[i] = F.u[k];
+    }
+  }
+}
+
+unsigned grid_for(long nb) {
+  long g = (nb + NTA - 1) / NTA;
+  return unsigned(g < 8192 ? (g < 1 ? 1 : g) : 8192);
+}
+
+}  // namespace
+
+hipError_t launch_ad_hang(int d, const AdaptLevel& A, const AdaptLevel& C, hipStream_t s) {
+  const long nb = long(A.mx) * A.my * (d == 3 ? A.mz : 1);
+  if (d == 2) k_ad_hang<2><<<grid_for(nb), NTA, 0, s>>>(A, C);
+  else k_ad_hang<3><<<grid_for(nb), NTA, 0, s>>>(A, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_ad_leaf(int d, const AdaptLevel& A, hipStream_t s) {
+  const long nb = long(A.mx) * A.my * (d == 3 ? A.mz : 1);
+  if (d == 2) k_ad_leaf<2><<<grid_for(nb), NTA, 0, s>>>(A);
+  else k_ad_leaf<3><<<grid_for(nb), NTA, 0, s>>>(A);
+  return hipGetLastError();
+}
+
+hipError_t launch_ad_up(int d, const AdaptLevel& A, const AdaptLevel* F, const RtSep<double>& rts, double omega,
+                        double omega_t, int damping, double* partials, hipStream_t s) {
+  const AdaptLevel Fv = F ? *F : AdaptLevel{};
+  const int jac = damping == ADAFAC_DAMP_JAC;
+  if (d == 2) k_ad_up<2><<<kAdaptNormBlocks, NTA, 0, s>>>(A, Fv, F ? 1 : 0, rts, omega, omega_t, jac, partials);
+  else k_ad_up<3><<<kAdaptNormBlocks, NTA, 0, s>>>(A, Fv, F ? 1 : 0, rts, omega, omega_t, jac, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_ad_down(int d, const AdaptLevel& A, const AdaptLevel* C, hipStream_t s) {
+  const long nb = long(A.mx) * A.my * (d == 3 ? A.mz : 1);
+  const AdaptLevel Cv = C ? *C : AdaptLevel{};
+  if (d == 2) k_ad_down<2><<<grid_for(nb), NTA, 0, s>>>(A, Cv, C ? 1 : 0);
+  else k_ad_down<3><<<grid_for(nb), NTA, 0, s>>>(A, Cv, C ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_ad_update(int d, const AdaptLevel& A, const AdaptLevel* F, hipStream_t s) {
+  const long nb = long(A.mx) * A.my * (d == 3 ? A.mz : 1);
+  const AdaptLevel Fv = F ? *F : AdaptLevel{};
+  if (d == 2) k_ad_update<2><<<grid_for(nb), NTA, 0, s>>>(A, Fv, F ? 1 : 0);
+  else k_ad_update<3><<<grid_for(nb), NTA, 0, s>>>(A, Fv, F ? 1 : 0);
+  return hipGetLastError();
+}
+
+}  // namespace adafac

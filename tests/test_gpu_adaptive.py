@@ -1,0 +1,98 @@
+"""Adaptive spacetrees on the GPU against the adaptive oracle.
+
+The trees are uniform up to a level and refined around a disk or ball below it (or by
+explicit seeded flags), so their levels are ragged and hold hanging vertices.  Per cycle, the
+norms of the composite residual must agree within 1e-12 of the initial norm.  The nodal values
+of every level (dofs and hanging vertices) must agree within 1e-12 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import adafac_inputs as inp
+from oracle import adaptive
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_both(d, L, lu, f, eps=None, cycles=6, centre=None, radius=0.2, flags=None, damping="jac"):
+    from paper_1903_10367_amd import Solver
+    centre = centre if centre is not None else (0.5,) * d
+    refine = flags if flags is not None else inp.refine_ball(d, L, lu, centre, radius)
+    kw = dict(refine=flags) if flags is not None else dict(ball=(centre, radius, lu))
+    s = Solver(d, 1, L, f, eps_blocks=eps, damping=damping, **kw)
+    s.cycle(cycles)
+    hg = s.residuals()
+    levels = {l: s.level(l, "u") for l in range(1, L + 1)}
+    ufine = s.solution()
+    ncomp = s.composite_dofs()
+    s.close()
+    T = adaptive.AdaptiveTree(d, L, 1, lu, refine, eps)
+    U, ho = adaptive.solve(T, f, cycles, damping=damping)
+    assert ncomp == len(T.composite_index())
+    r0 = ho[0][0]
+    for n, (a, b) in enumerate(zip(hg, ho)):
+        assert abs(a[0] - b[0]) <= 1e-12 * r0, f"cycle {n}: {a[0]!r} vs {b[0]!r}"
+        assert abs(a[1] - b[1]) <= 1e-12 * ho[0][1], f"cycle {n} linf"
+    scale = max(np.abs(U[l]).max() for l in U)
+    for l in range(1, L + 1):
+        have = T.dof[l] | T.hang[l]
+        g = levels[l].reshape(T.shape(l))
+        err = np.abs(g[have] - U[l][have]).max()
+        assert err <= 1e-12 * scale, f"level {l}: {err:.3e}"
+    fo = adaptive.finest_values(T, U)
+    assert np.abs(ufine.reshape(fo.shape) - fo).max() <= 1e-12 * scale
+    return hg, ho
+
+
+@pytest.mark.parametrize("damping", ["jac", "none"])
+def test_2d_disk(damping):
+    say("case adaptive 2d disk L=4", damping)
+    eps = inp.eps_blocks(2, 2, 2.0, seed=70)
+    run_both(2, 4, 2, inp.rhs(2, 4, seed=71), eps, damping=damping)
+
+
+def test_3d_ball():
+    say("case adaptive 3d ball L=3")
+    eps = inp.eps_blocks(3, 1, 2.0, seed=72)
+    run_both(3, 3, 2, inp.rhs(3, 3, seed=73), eps, centre=(0.45, 0.5, 0.55), radius=0.15)
+
+
+def test_3d_ball_deeper():
+    say("case adaptive 3d ball L=4")
+    run_both(3, 4, 2, inp.rhs(3, 4, seed=74, dist="normal"), None, centre=(0.4, 0.55, 0.5), radius=0.12, cycles=4)
+
+
+def test_2d_explicit_flags():
+    say("case adaptive 2d seeded flags")
+    rng = np.random.default_rng(75)
+    flags = {l: rng.random((3 ** l,) * 2) < 0.35 for l in (2, 3, 4)}
+    run_both(2, 5, 2, inp.rhs(2, 5, seed=76), inp.eps_blocks(2, 1, 1.0, seed=77), flags=flags, cycles=5)
+
+
+def test_disk_workload_l6():
+    """The 2D jump-coefficient disk workload: 9x9 blocks, uniform to level 2, disk r = 0.25
+    refined to level 6 (729^2 finest cells there)."""
+    say("case adaptive 2d disk workload L=6")
+    eps = inp.eps_blocks(2, 2, 3.0, seed=78)
+    run_both(2, 6, 2, inp.rhs(2, 6, seed=79), eps, radius=0.25, cycles=3)
+
+
+def test_solve_to_tolerance():
+    from paper_1903_10367_amd import Solver
+    say("case adaptive solve 1e-8")
+    eps = inp.eps_blocks(2, 2, 1.0, seed=80)
+    f = inp.rhs(2, 4, seed=81)
+    s = Solver(2, 1, 4, f, eps_blocks=eps, ball=((0.5, 0.5), 0.2, 2))
+    n = s.solve(1e-8, 800)
+    hg = s.residuals()
+    s.close()
+    T = adaptive.AdaptiveTree(2, 4, 1, 2, inp.refine_ball(2, 4, 2, (0.5, 0.5), 0.2), eps)
+    _, ho = adaptive.solve(T, f, 800, tol=1e-8)
+    say(f"cycles {n} (oracle {len(ho)})")
+    assert n == len(ho) and hg[-1][0] / hg[0][0] <= 1e-8
