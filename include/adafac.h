@@ -118,6 +118,24 @@ int adafac_set_refinement(adafac_ctx* ctx, int level, const uint8_t* flags, size
  * l_min..l_max-1. */
 int adafac_refine_ball(adafac_ctx* ctx, const double* centre, double radius, int l_from);
 
+/* Regrid a bound adaptive context (the moving-source workload): prepare a tree
+ * refined around the ball (centre, radius, l_from) as adafac_refine_ball, with the
+ * right-hand side f (n = (3^l_max + 1)^dim), and report in *bytes the device
+ * workspace it needs.  The bound tree keeps cycling unchanged until
+ * adafac_regrid.  EINVAL on bad arguments, ESTATE on a context that is not a
+ * bound adaptive one. */
+int adafac_regrid_prepare(adafac_ctx* ctx, const double* centre, double radius, int l_from, const double* f,
+                          size_t n, size_t* bytes);
+
+/* Move onto the prepared tree.  Its operators and loads are uploaded into
+ * dev_workspace (>= the prepared size, 256-byte aligned).  Every dof of the new
+ * tree takes the old composite function at its position: kept vertices keep their
+ * value, new ones get the d-linear interpolation, and dropped ones vanish.  The
+ * residual history and the normalisation by the iterate-0 norm carry over.
+ * Afterwards the previous workspace is no longer referenced (the caller may free
+ * it).  Synchronises.  ENOMEM if the workspace is too small. */
+int adafac_regrid(adafac_ctx* ctx, void* dev_workspace, size_t bytes);
+
 /* Number of composite degrees of freedom of the built tree (0 before
  * build_operators). */
 int64_t adafac_composite_dofs(const adafac_ctx* ctx);

@@ -337,3 +337,17 @@ def dense_cycle(T, A, b, lev, Psi, u, omega=0.6, omega_t=0.6, damping="jac"):
 
 def to_composite(T, U):
     return np.array([U[l].ravel()[i] for l, i in T.composite_index()])
+
+
+def transfer(T_old, U_old, T_new):
+    """Storage of tree T_new holding the composite function of (T_old, U_old): every dof takes
+    its value at the dof's position (kept vertices keep theirs; new ones get the d-linear
+    interpolation of the finest old cell around them)."""
+    assert T_old.d == T_new.d and T_old.L == T_new.L and T_old.lmin == T_new.lmin
+    F = finest_values(T_old, U_old)
+    d, L = T_new.d, T_new.L
+    U = {}
+    for l in range(T_new.lmin, L + 1):
+        s = 3 ** (L - l)
+        U[l] = np.where(T_new.dof[l], F[tuple(slice(None, None, s) for _ in range(d))], 0.0)
+    return T_new.spread(U)

@@ -115,6 +115,19 @@ class Solver:
     def composite_dofs(self):
         return int(self.L.adafac_composite_dofs(self.ctx))
 
+    def regrid(self, centre, radius, l_from, f):
+        """Move an adaptive solve onto the tree refined around a new ball, with a new right-hand
+        side; the iterate is transferred and the residual history kept."""
+        import torch
+        cc = np.ascontiguousarray(centre, dtype=np.float64)
+        fa = np.ascontiguousarray(f, dtype=np.float64).ravel()
+        nbytes = C.c_size_t()
+        _check(self.L, self.ctx, self.L.adafac_regrid_prepare(self.ctx, _dptr(cc), radius, l_from, _dptr(fa), fa.size,
+                                                              C.byref(nbytes)))
+        ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
+        _check(self.L, self.ctx, self.L.adafac_regrid(self.ctx, C.c_void_p(ws.data_ptr()), ws.numel()))
+        self.workspace = ws
+
     def set_kernel_timing(self, on):
         _check(self.L, self.ctx, self.L.adafac_set_kernel_timing(self.ctx, int(on)))
 

@@ -29,13 +29,20 @@ struct AdaptLevel {
   const double* eps;        // nb^d blocks, nullptr: eps = 1
   const double* dg;         // stored diagonal over the box when !fem
   const uint8_t* vcls;      // per box vertex
-  const uint8_t* leaf;      // per box cell: 1 = leaf cell of this level
+  const uint8_t* leaf;      // per box cell: 0 = no cell, 1 = leaf cell, 2 = refined cell
   const double* bleaf;      // lumped load of the level's leaf cells at box vertices
   double* u;                // nodal values: composite dofs, copies of finer dofs, hanging interpolations
   double* bb;               // leaf residual, then the level hats tested against the composite residual
   double* hh;               // hanging-only accumulation (composite residual of coarser dofs)
   double* s;                // own correction c - c~ at dofs
   double* S;                // prolongated sum of corrections
+};
+
+// All levels of a tree (the old one of a regrid) and the finest-lattice spacing of each level.
+struct AdaptTreeView {
+  AdaptLevel lv[kMaxLevel + 1];
+  int scale[kMaxLevel + 1];    // 3^(L - l)
+  int lmin, L;
 };
 
 // Host description of the tree.
@@ -75,6 +82,7 @@ hipError_t launch_ad_up(int d, const AdaptLevel& L, const AdaptLevel* F, const R
                         double omega_t, int damping, double* partials, hipStream_t s);
 hipError_t launch_ad_down(int d, const AdaptLevel& L, const AdaptLevel* C, hipStream_t s);
 hipError_t launch_ad_update(int d, const AdaptLevel& L, const AdaptLevel* F, hipStream_t s);
+hipError_t launch_ad_transfer(int d, const AdaptLevel& A, int scale, const AdaptTreeView& O, hipStream_t s);
 constexpr int kAdaptNormBlocks = 256;   // norm partial blocks per level
 
 }  // namespace adafac

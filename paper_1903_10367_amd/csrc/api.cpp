@@ -109,6 +109,10 @@ struct adafac_ctx {
   RtSep<double> ad_rts{};
   std::vector<AdaptLevel> ad;           // device views by level
   double* ad_eps = nullptr;
+  AdaptHost at_next;                    // regrid: the prepared tree, its right-hand side and size
+  std::vector<double> f_next;
+  size_t next_need = 0;
+  bool next_ready = false;
   // kernel timing
   bool timing = false;
   std::vector<hipEvent_t> ev;
@@ -365,7 +369,7 @@ int flush(adafac_ctx* c) {
 // ---------------------------------------------------------------------------
 // Adaptive spacetrees: per-level box arrays and the cycle over the ragged levels
 // ---------------------------------------------------------------------------
-size_t layout_adaptive(adafac_ctx* c, char* base) {
+size_t layout_adaptive_tree(adafac_ctx* c, const AdaptHost& t, char* base) {
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
     off = (off + 255) & ~size_t(255);
@@ -374,12 +378,12 @@ size_t layout_adaptive(adafac_ctx* c, char* base) {
     return p;
   };
   const int d = c->dim;
-  c->ad.assign(c->L + 1, AdaptLevel{});
-  c->ad_eps = reinterpret_cast<double*>(take(sizeof(double) * c->ops.eps.size()));
+  std::vector<AdaptLevel> ad(c->L + 1, AdaptLevel{});
+  double* eps = reinterpret_cast<double*>(take(sizeof(double) * c->ops.eps.size()));
   const bool unit = c->ops.nb == 1 && c->ops.eps[0] == 1.0;
   for (int l = c->lmin; l <= c->L; ++l) {
-    const AdaptHostLevel& H = c->at.lev[l];
-    AdaptLevel& A = c->ad[l];
+    const AdaptHostLevel& H = t.lev[l];
+    AdaptLevel& A = ad[l];
     A.ox = H.lo[0];
     A.oy = H.lo[1];
     A.oz = d == 3 ? H.lo[2] : 0;
@@ -393,7 +397,7 @@ size_t layout_adaptive(adafac_ctx* c, char* base) {
     A.fem = H.dg.empty() ? 1 : 0;
     A.nb = c->ops.nb;
     A.bs = A.fem ? ipow3(l - c->ops.k) : 1;
-    A.eps = unit ? nullptr : c->ad_eps;
+    A.eps = unit ? nullptr : eps;
     const size_t nv = H.nverts(), ncell = H.ncells();
     A.vcls = reinterpret_cast<uint8_t*>(take(nv));
     A.leaf = reinterpret_cast<uint8_t*>(take(ncell));
@@ -405,13 +409,24 @@ size_t layout_adaptive(adafac_ctx* c, char* base) {
     A.s = reinterpret_cast<double*>(take(sizeof(double) * nv));
     A.S = reinterpret_cast<double*>(take(sizeof(double) * nv));
   }
-  c->npartials = size_t(kAdaptNormBlocks) * (c->L - c->lmin + 1);
-  c->partials = reinterpret_cast<double*>(take(sizeof(double) * 2 * c->npartials));
-  c->norms = reinterpret_cast<double*>(take(sizeof(double) * 2 * kMaxHist));
-  c->scratch_norm = reinterpret_cast<double*>(take(sizeof(double) * 2));
-  c->norm0 = reinterpret_cast<double*>(take(sizeof(double) * 2));
+  const size_t npart = size_t(kAdaptNormBlocks) * (c->L - c->lmin + 1);
+  double* partials = reinterpret_cast<double*>(take(sizeof(double) * 2 * npart));
+  double* norms = reinterpret_cast<double*>(take(sizeof(double) * 2 * kMaxHist));
+  double* scratch = reinterpret_cast<double*>(take(sizeof(double) * 2));
+  double* norm0 = reinterpret_cast<double*>(take(sizeof(double) * 2));
+  if (base) {
+    c->ad = std::move(ad);
+    c->ad_eps = eps;
+    c->npartials = npart;
+    c->partials = partials;
+    c->norms = norms;
+    c->scratch_norm = scratch;
+    c->norm0 = norm0;
+  }
   return (off + 255) & ~size_t(255);
 }
+
+size_t layout_adaptive(adafac_ctx* c, char* base) { return layout_adaptive_tree(c, c->at, base); }
 
 // hanging vertices interpolated top-down from the current nodal values
 int adapt_hang(adafac_ctx* c) {
@@ -571,8 +586,8 @@ int bind_adaptive(adafac_ctx* c) {
   for (int l = c->lmin; l <= L; ++l) {
     const AdaptHostLevel& H = c->at.lev[l];
     const AdaptLevel& A = c->ad[l];
-    std::vector<uint8_t> leaf(H.ncells());
-    for (size_t i = 0; i < leaf.size(); ++i) leaf[i] = H.exists[i] && !H.refined[i];
+    std::vector<uint8_t> leaf(H.ncells());   // cell classes: 0 none, 1 leaf, 2 refined
+    for (size_t i = 0; i < leaf.size(); ++i) leaf[i] = H.exists[i] ? (H.refined[i] ? 2 : 1) : 0;
     // lumped load: m_v f_v, m_v = |leaf cells around v| h^d / 2^d, f sampled from the finest lattice
     std::vector<double> bl(H.nverts(), 0.0);
     const int s = ipow3(L - l);
@@ -586,7 +601,7 @@ int bind_adaptive(adafac_ctx* c) {
           for (int e = 0; e < (1 << d); ++e) {
             const int cx = x - 1 + (e & 1), cy = y - 1 + ((e >> 1) & 1), cz = d == 3 ? z - 1 + ((e >> 2) & 1) : 0;
             if (cx < 0 || cy < 0 || cz < 0 || cx >= H.nc[0] || cy >= H.nc[1] || cz >= H.nc[2]) continue;
-            nleaf += leaf[(size_t(cz) * H.nc[1] + cy) * H.nc[0] + cx];
+            nleaf += leaf[(size_t(cz) * H.nc[1] + cy) * H.nc[0] + cx] == 1;
           }
           if (!nleaf) continue;
           const size_t gx = size_t(A.ox + x) * s, gy = size_t(A.oy + y) * s, gz = d == 3 ? size_t(A.oz + z) * s : 0;
@@ -1172,6 +1187,71 @@ int adafac_refine_ball(adafac_ctx* c, const double* centre, double radius, int l
   c->ball_r = radius;
   c->ball_from = l_from;
   c->built = c->bound = false;
+  return ADAFAC_OK;
+}
+
+int adafac_regrid_prepare(adafac_ctx* c, const double* centre, double radius, int l_from, const double* f, size_t n,
+                          size_t* bytes) {
+  if (!c) return ADAFAC_EINVAL;
+  if (!ready(c) || !c->adaptive) return fail(c, ADAFAC_ESTATE, "regrid needs a bound adaptive context");
+  if (!centre || !(radius > 0.0) || !std::isfinite(radius)) return fail(c, ADAFAC_EINVAL, "bad ball");
+  if (l_from < c->lmin || l_from >= c->L) return fail(c, ADAFAC_EINVAL, "l_from must lie in l_min..l_max-1");
+  if (c->ops.k > l_from) return fail(c, ADAFAC_EINVAL, "coefficient blocks finer than the first refined level");
+  if (!f || n != nverts_of(c->dim, c->L)) return fail(c, ADAFAC_EINVAL, "f: wrong size");
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(f[i])) return fail(c, ADAFAC_EINVAL, "f: non-finite value");
+  double cc[3] = {0, 0, 0};
+  for (int a = 0; a < c->dim; ++a) cc[a] = centre[a];
+  std::string m = build_adapt_tree(c->at_next, c->dim, c->lmin, c->L, {}, cc, radius, l_from);
+  if (!m.empty()) return fail(c, ADAFAC_EINVAL, m);
+  // the uniform levels below the coefficient blocks are those of the current tree
+  for (int l = c->lmin; l < c->ops.k; ++l) c->at_next.lev[l].dg = c->at.lev[l].dg;
+  c->f_next.assign(f, f + n);
+  c->next_need = layout_adaptive_tree(c, c->at_next, nullptr);
+  c->next_ready = true;
+  for (int a = 0; a < 3; ++a) c->ball_c[a] = cc[a];
+  c->ball_r = radius;
+  c->ball_from = l_from;
+  c->refine.clear();
+  if (bytes) *bytes = c->next_need;
+  return ADAFAC_OK;
+}
+
+int adafac_regrid(adafac_ctx* c, void* ws, size_t bytes) {
+  if (!c) return ADAFAC_EINVAL;
+  if (!ready(c) || !c->adaptive || !c->next_ready) return fail(c, ADAFAC_ESTATE, "adafac_regrid_prepare first");
+  if (!ws || bytes < c->next_need) return fail(c, ADAFAC_ENOMEM, "workspace too small: need " + std::to_string(c->next_need));
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(c, ADAFAC_EINVAL, "workspace not 256-byte aligned");
+  // the old tree: hanging values current, then a view of all its levels
+  int rc = adapt_hang(c);
+  if (rc) return rc;
+  AdaptTreeView O{};
+  O.lmin = c->lmin;
+  O.L = c->L;
+  for (int l = c->lmin; l <= c->L; ++l) {
+    O.lv[l] = c->ad[l];
+    O.scale[l] = ipow3(c->L - l);
+  }
+  double* old_norms = c->norms;
+  double* old_norm0 = c->norm0;
+  // switch to the new tree and its workspace
+  std::swap(c->at, c->at_next);
+  c->f.swap(c->f_next);
+  layout(c, static_cast<char*>(ws));
+  HIPCHK(c, hipMemsetAsync(ws, 0, c->next_need, c->stream));
+  if ((rc = bind_adaptive(c))) return rc;
+  for (int l = c->lmin; l <= c->L; ++l)
+    HIPCHK(c, launch_ad_transfer(c->dim, c->ad[l], ipow3(c->L - l), O, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->norms, old_norms, sizeof(double) * 2 * kMaxHist, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->norm0, old_norm0, sizeof(double) * 2, hipMemcpyDeviceToDevice, c->stream));
+  if ((rc = adapt_hang(c))) return rc;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->ws = static_cast<char*>(ws);
+  c->ws_bytes = bytes;
+  c->ws_need = c->next_need;
+  c->at_next = AdaptHost{};
+  c->f_next.clear();
+  c->next_ready = false;
   return ADAFAC_OK;
 }
 

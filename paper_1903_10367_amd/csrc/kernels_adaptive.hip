@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(NTA) k_ad_leaf(AdaptLevel A) {
         const int ax = e & 1, ay = (e >> 1) & 1, az = (e >> 2) & 1;
         const int cx = x - ax, cy = y - ay, cz = D == 3 ? z - az : 0;
         const long c = cidx<D>(A, cx, cy, cz);
-        if (c < 0 || !A.leaf[c]) continue;
+        if (c < 0 || A.leaf[c] != 1) continue;
         const int iw = ax | (ay << 1) | (az << 2);
         double sum = 0.0;
 #pragma unroll
@@ -231,6 +231,56 @@ __global__ void __launch_bounds__(NTA) k_ad_update(AdaptLevel A, AdaptLevel F, i
   }
 }
 
+// The composite FE function of tree O at finest-lattice point (X, Y, Z): d-linear interpolation
+// in the finest existing cell of O that contains the point (Sec. 2.1: continuous Q1 on the
+// leaves; refined cells are represented by their children).
+template <int D>
+__device__ double composite_at(const AdaptTreeView& O, int X, int Y, int Z) {
+  int best = -1;
+  long bc = -1;
+  int cx = 0, cy = 0, cz = 0;
+  for (int m = O.lmin; m <= O.L; ++m) {
+    const AdaptLevel& A = O.lv[m];
+    const int s = O.scale[m];
+    const int qx = min(X / s, A.n - 1), qy = min(Y / s, A.n - 1), qz = D == 3 ? min(Z / s, A.n - 1) : 0;
+    const long c = cidx<D>(A, qx, qy, qz);
+    if (c < 0 || A.leaf[c] == 0) break;
+    best = m;
+    bc = c;
+    cx = qx;
+    cy = qy;
+    cz = qz;
+    if (A.leaf[c] == 1) break;
+  }
+  if (best < 0 || bc < 0) return 0.0;
+  const AdaptLevel& A = O.lv[best];
+  const int s = O.scale[best];
+  const double fx = double(X - cx * s) / s, fy = double(Y - cy * s) / s, fz = D == 3 ? double(Z - cz * s) / s : 0.0;
+  double acc = 0.0;
+#pragma unroll
+  for (int e = 0; e < (1 << D); ++e) {
+    const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+    double w = (ex ? fx : 1.0 - fx) * (ey ? fy : 1.0 - fy);
+    if (D == 3) w *= ez ? fz : 1.0 - fz;
+    if (w == 0.0) continue;
+    const long k = vidx<D>(A, cx + ex, cy + ey, cz + ez);
+    if (k >= 0) acc += w * A.u[k];
+  }
+  return acc;
+}
+
+// New level A of a regridded tree: every dof takes the old tree's composite function.
+template <int D>
+__global__ void __launch_bounds__(NTA) k_ad_transfer(AdaptLevel A, int scale, AdaptTreeView O) {
+  const long nb = nbox<D>(A);
+  for (long i = long(blockIdx.x) * NTA + threadIdx.x; i < nb; i += long(gridDim.x) * NTA) {
+    if (!(A.vcls[i] & kDof)) continue;
+    int x, y, z;
+    coords<D>(A, i, x, y, z);
+    A.u[i] = composite_at<D>(O, x * scale, y * scale, z * scale);
+  }
+}
+
 unsigned grid_for(long nb) {
   long g = (nb + NTA - 1) / NTA;
   return unsigned(g < 8192 ? (g < 1 ? 1 : g) : 8192);
@@ -242,6 +292,13 @@ hipError_t launch_ad_hang(int d, const AdaptLevel& A, const AdaptLevel& C, hipSt
   const long nb = long(A.mx) * A.my * (d == 3 ? A.mz : 1);
   if (d == 2) k_ad_hang<2><<<grid_for(nb), NTA, 0, s>>>(A, C);
   else k_ad_hang<3><<<grid_for(nb), NTA, 0, s>>>(A, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_ad_transfer(int d, const AdaptLevel& A, int scale, const AdaptTreeView& O, hipStream_t s) {
+  const long nb = long(A.mx) * A.my * (d == 3 ? A.mz : 1);
+  if (d == 2) k_ad_transfer<2><<<grid_for(nb), NTA, 0, s>>>(A, scale, O);
+  else k_ad_transfer<3><<<grid_for(nb), NTA, 0, s>>>(A, scale, O);
   return hipGetLastError();
 }
 

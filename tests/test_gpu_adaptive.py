@@ -96,3 +96,41 @@ def test_solve_to_tolerance():
     _, ho = adaptive.solve(T, f, 800, tol=1e-8)
     say(f"cycles {n} (oracle {len(ho)})")
     assert n == len(ho) and hg[-1][0] / hg[0][0] <= 1e-8
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_regrid_moving_ball(d):
+    """Cycles on a tree refined around one ball, regrid to a moved ball with a new right-hand
+    side, more cycles: iterate transfer, residual history and normalisation against the oracle."""
+    from paper_1903_10367_amd import Solver
+    say("case adaptive regrid", d)
+    L, lu = (4, 2) if d == 2 else (3, 2)
+    rad = 0.2 if d == 2 else 0.15
+    c1 = (0.45, 0.5) if d == 2 else (0.45, 0.5, 0.5)
+    c2 = (0.55, 0.52) if d == 2 else (0.55, 0.45, 0.5)
+    eps = inp.eps_blocks(d, 1, 2.0, seed=82)
+    f1, f2 = inp.rhs(d, L, seed=83), inp.rhs(d, L, seed=84)
+    s = Solver(d, 1, L, f1, eps_blocks=eps, ball=(c1, rad, lu))
+    s.cycle(3)
+    s.regrid(c2, rad, lu, f2)
+    s.cycle(4)
+    hg = s.residuals()
+    levels = {l: s.level(l, "u") for l in range(1, L + 1)}
+    s.close()
+    T1 = adaptive.AdaptiveTree(d, L, 1, lu, inp.refine_ball(d, L, lu, c1, rad), eps)
+    T2 = adaptive.AdaptiveTree(d, L, 1, lu, inp.refine_ball(d, L, lu, c2, rad), eps)
+    U, h1 = adaptive.solve(T1, f1, 3)
+    U = adaptive.transfer(T1, U, T2)
+    b2 = T2.load(f2)
+    h2 = []
+    for _ in range(4):
+        U, nr = adaptive.cycle(T2, U, b2)
+        h2.append(nr)
+    ho = h1 + h2
+    assert len(hg) == len(ho)
+    for n, (a, b) in enumerate(zip(hg, ho)):
+        assert abs(a[0] - b[0]) <= 1e-12 * ho[0][0], f"cycle {n}"
+    scale = max(np.abs(U[l]).max() for l in U)
+    for l in range(1, L + 1):
+        have = T2.dof[l] | T2.hang[l]
+        assert np.abs(levels[l].reshape(T2.shape(l))[have] - U[l][have]).max() <= 1e-12 * scale

@@ -117,3 +117,20 @@ def test_finest_values_are_the_composite_function():
     for l, i in T.composite_index():
         v = np.array(np.unravel_index(i, T.shape(l))) * 3 ** (T.L - l)
         assert F[tuple(v)] == U[l].ravel()[i]
+
+
+def test_transfer_keeps_the_composite_function_where_both_trees_resolve_it():
+    T1 = disk_tree()
+    ref2 = inp.refine_ball(2, 4, 2, (0.6, 0.45), 0.2)
+    T2 = adaptive.AdaptiveTree(2, 4, 1, 2, ref2)
+    U1, _ = adaptive.solve(T1, inp.rhs(2, 4, seed=13), 3)
+    U2 = adaptive.transfer(T1, U1, T2)
+    F1, F2 = adaptive.finest_values(T1, U1), adaptive.finest_values(T2, U2)
+    # vertices that are composite dofs of both trees on the same level keep their value
+    for l in range(T2.lmin, T2.L + 1):
+        both = T1.comp[l] & T2.comp[l]
+        assert np.array_equal(U2[l][both], U1[l][both])
+    # the transferred function is the old one sampled at the new dofs and interpolated between
+    # them: wherever the new tree is at least as fine as the old one, the two agree
+    fine_both = T1.dof[4] & T2.dof[4]
+    assert np.abs(F1[fine_both] - F2[fine_both]).max() == 0.0
