@@ -102,3 +102,32 @@ def refine_ball(d, L, l_uniform, centre, radius):
             dist2 += gap * gap
         out[l] = dist2 <= radius * radius
     return out
+
+
+def gaussian(d, L, centre, sigma, amplitude=1.0):
+    """Samples of the source amplitude * exp(-|x - centre|^2 / (2 sigma^2)) on the finest
+    vertex lattice (C order, x on the last axis)."""
+    n = 3 ** L
+    x = np.arange(n + 1) / n
+    grids = np.meshgrid(*([x] * d), indexing="ij")            # axis a is coordinate d-1-a
+    r2 = sum((grids[a] - centre[d - 1 - a]) ** 2 for a in range(d))
+    return amplitude * np.exp(-r2 / (2.0 * sigma * sigma))
+
+
+def moving_source(seed=0, steps=4, d=3):
+    """Centres of the moving Gaussian source: x0 ~ U[0.3, 0.7]^d, then steps of 0.03 along a
+    seeded unit vector, reflected at the faces of [0.3, 0.7]^d."""
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0.3, 0.7, d)
+    v = rng.standard_normal(d)
+    v /= np.linalg.norm(v)
+    out = [x.copy()]
+    for _ in range(steps):
+        x = x + 0.03 * v
+        for a in range(d):
+            if x[a] > 0.7:
+                x[a], v[a] = 1.4 - x[a], -v[a]
+            elif x[a] < 0.3:
+                x[a], v[a] = 0.6 - x[a], -v[a]
+        out.append(x.copy())
+    return out

@@ -164,6 +164,68 @@ def serving(Server, torch, n_req, loads, budget_gb, max_cycles, log=None, **serv
     return out
 
 
+def adaptive_workloads(Solver, torch, log=None):
+    """The two adaptive-spacetree workloads (FP64, d-linear transfers, adAFAC-Jac):
+    2D disk: 9x9 eps blocks 10^U(0,3), uniform to level 2, disk r = 0.25 refined to level 6,
+    f ~ U(-1,1); timed cycles and a solve to 1e-8.
+    3D moving Gaussian: 27^3 eps blocks 10^U(0,4), uniform to level 3, source of width 0.05 at a
+    seeded centre, cells meeting the ball of radius 3 sigma refined to level 6, the tree
+    re-refined every 5 cycles as the centre moves by 0.03; cycle and regrid times."""
+    import numpy as np
+    import adafac_inputs as inp
+    out = {}
+    eps2 = inp.eps_blocks(2, 2, 3.0, seed=21)
+    s = Solver(2, 1, 6, inp.rhs(2, 6, seed=22), eps_blocks=eps2, ball=((0.5, 0.5), 0.25, 2))
+    dofs = s.dofs_per_cycle()
+    s.cycle(5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.cycle(50)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 50
+    s.set_solution(np.zeros(s.nvert))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    n = s.solve(1e-8, 5000)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t1
+    h = s.residuals()
+    out["disk_2d_l6"] = {"composite_dofs": s.composite_dofs(), "dofs_per_cycle": dofs, "us_per_cycle": dt * 1e6,
+                         "vertex_updates_per_s": dofs / dt, "solve_1e-8_cycles": n, "solve_1e-8_ms": ts * 1e3,
+                         "rel_residual": h[-1][0] / h[0][0]}
+    s.close()
+    if log:
+        log(f"adaptive 2D disk: {dt * 1e6:.1f} us/cycle, solve {n} cycles")
+    sigma = 0.05
+    centres = inp.moving_source(seed=23, steps=4, d=3)
+    eps3 = inp.eps_blocks(3, 3, 4.0, seed=24)
+    s = Solver(3, 1, 6, {"gaussian": (centres[0], sigma, 1.0)}, eps_blocks=eps3, ball=(centres[0], 3 * sigma, 3))
+    dofs0 = s.dofs_per_cycle()
+    cyc, reg = [], []
+    for k, c in enumerate(centres):
+        if k:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.regrid(c, 3 * sigma, 3)
+            torch.cuda.synchronize()
+            reg.append(time.perf_counter() - t0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.cycle(5)
+        torch.cuda.synchronize()
+        cyc.append((time.perf_counter() - t0) / 5)
+    h = s.residuals()
+    out["moving_gaussian_3d_l6"] = {
+        "dofs_per_cycle_first_tree": dofs0, "composite_dofs_last_tree": s.composite_dofs(),
+        "us_per_cycle": float(np.mean(cyc[1:])) * 1e6, "regrid_ms": float(np.mean(reg)) * 1e3,
+        "regrids": len(reg), "cycles": 5 * len(centres), "rel_residual_last": h[-1][0] / h[0][0],
+        "precision": "fp64 (FP32-inner cycles are not available on adaptive trees)"}
+    s.close()
+    if log:
+        log(f"adaptive 3D moving Gaussian: {np.mean(cyc[1:]) * 1e6:.1f} us/cycle, regrid {np.mean(reg) * 1e3:.1f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,6 +233,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=2)
+    ap.add_argument("--no-adaptive", action="store_true", help="skip the adaptive-tree workloads")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests per serving pass (0: skip)")
     ap.add_argument("--serve-loads", default="0.5,0.9", help="arrival rates as fractions of capacity")
     ap.add_argument("--serve-budget-gb", type=float, default=4.0)
@@ -262,6 +325,8 @@ def main():
                      "algorithmic_bytes_per_launch": kbytes, "launches": nlaunch},
         "solve_to_1e-8": solves,
     }
+    if not args.no_adaptive:
+        out["adaptive"] = adaptive_workloads(Solver, torch, log)
     if args.serve_requests > 0:
         loads = [float(x) for x in args.serve_loads.split(",") if x]
         out["serving"] = serving(Server, torch, args.serve_requests, loads, args.serve_budget_gb,

@@ -96,6 +96,12 @@ int adafac_create(adafac_ctx** out, int dim, int l_min, int l_max);
  * never called: eps = 1 (Poisson).  EINVAL on bad sizes or values. */
 int adafac_set_coefficient_blocks(adafac_ctx* ctx, int blocks_per_axis, const double* eps);
 
+/* Right-hand side f(x) = amplitude exp(-|x - centre|^2 / (2 sigma^2)), a Gaussian
+ * source (centre: dim coordinates, x first), evaluated at every vertex where the
+ * load is formed; replaces a lattice given with adafac_set_rhs_lattice.  EINVAL on
+ * sigma <= 0 or non-finite values. */
+int adafac_set_rhs_gaussian(adafac_ctx* ctx, const double* centre, double sigma, double amplitude);
+
 /* Adaptive spacetree (Sec. 2.1): refinement flags of the cells of one level
  * l_min <= level < l_max, over the whole (3^level)^dim cell lattice (C order, x
  * fastest; nonzero = refine).  Flags of cells that do not exist are ignored.
@@ -120,8 +126,9 @@ int adafac_refine_ball(adafac_ctx* ctx, const double* centre, double radius, int
 
 /* Regrid a bound adaptive context (the moving-source workload): prepare a tree
  * refined around the ball (centre, radius, l_from) as adafac_refine_ball, with the
- * right-hand side f (n = (3^l_max + 1)^dim), and report in *bytes the device
- * workspace it needs.  The bound tree keeps cycling unchanged until
+ * right-hand side f (n = (3^l_max + 1)^dim; NULL keeps a Gaussian source and
+ * moves its centre to the ball's), and report in *bytes the device workspace it
+ * needs.  The bound tree keeps cycling unchanged until
  * adafac_regrid.  EINVAL on bad arguments, ESTATE on a context that is not a
  * bound adaptive one. */
 int adafac_regrid_prepare(adafac_ctx* ctx, const double* centre, double radius, int l_from, const double* f,

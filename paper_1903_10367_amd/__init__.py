@@ -52,8 +52,14 @@ class Solver:
         if eps_blocks is not None:
             e = np.ascontiguousarray(eps_blocks, dtype=np.float64)
             _check(self.L, ctx, self.L.adafac_set_coefficient_blocks(ctx, e.shape[0], _dptr(e)))
-        fa = np.ascontiguousarray(f, dtype=np.float64).ravel()
-        _check(self.L, ctx, self.L.adafac_set_rhs_lattice(ctx, _dptr(fa), fa.size))
+        if isinstance(f, dict):
+            # {"gaussian": (centre, sigma, amplitude)}: a Gaussian source evaluated by the library
+            centre, sigma, amp = f["gaussian"]
+            cc = np.ascontiguousarray(centre, dtype=np.float64)
+            _check(self.L, ctx, self.L.adafac_set_rhs_gaussian(ctx, _dptr(cc), sigma, amp))
+        else:
+            fa = np.ascontiguousarray(f, dtype=np.float64).ravel()
+            _check(self.L, ctx, self.L.adafac_set_rhs_lattice(ctx, _dptr(fa), fa.size))
         for level, flags in (refine or {}).items():
             fl = np.ascontiguousarray(flags, dtype=np.uint8).ravel()
             _check(self.L, ctx, self.L.adafac_set_refinement(ctx, level, fl.ctypes.data_as(C.POINTER(C.c_uint8)),
@@ -115,15 +121,18 @@ class Solver:
     def composite_dofs(self):
         return int(self.L.adafac_composite_dofs(self.ctx))
 
-    def regrid(self, centre, radius, l_from, f):
+    def regrid(self, centre, radius, l_from, f=None):
         """Move an adaptive solve onto the tree refined around a new ball, with a new right-hand
         side; the iterate is transferred and the residual history kept."""
         import torch
         cc = np.ascontiguousarray(centre, dtype=np.float64)
-        fa = np.ascontiguousarray(f, dtype=np.float64).ravel()
         nbytes = C.c_size_t()
-        _check(self.L, self.ctx, self.L.adafac_regrid_prepare(self.ctx, _dptr(cc), radius, l_from, _dptr(fa), fa.size,
-                                                              C.byref(nbytes)))
+        if f is None:   # Gaussian source: it moves with the ball
+            rc = self.L.adafac_regrid_prepare(self.ctx, _dptr(cc), radius, l_from, None, 0, C.byref(nbytes))
+        else:
+            fa = np.ascontiguousarray(f, dtype=np.float64).ravel()
+            rc = self.L.adafac_regrid_prepare(self.ctx, _dptr(cc), radius, l_from, _dptr(fa), fa.size, C.byref(nbytes))
+        _check(self.L, self.ctx, rc)
         ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
         _check(self.L, self.ctx, self.L.adafac_regrid(self.ctx, C.c_void_p(ws.data_ptr()), ws.numel()))
         self.workspace = ws

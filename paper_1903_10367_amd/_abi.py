@@ -19,7 +19,7 @@ EXPORTS = [
     "adafac_residual", "adafac_cycles_run", "adafac_get_solution", "adafac_set_solution",
     "adafac_get_level", "adafac_host_operator", "adafac_dofs_per_cycle", "adafac_set_kernel_timing", "adafac_kernel_time",
     "adafac_destroy", "adafac_last_error", "adafac_set_refinement", "adafac_refine_ball", "adafac_composite_dofs",
-    "adafac_regrid_prepare", "adafac_regrid",
+    "adafac_regrid_prepare", "adafac_regrid", "adafac_set_rhs_gaussian",
     "adafac_server_default_cfg", "adafac_server_create", "adafac_server_submit", "adafac_server_step",
     "adafac_server_poll", "adafac_server_fetch", "adafac_server_destroy", "adafac_server_last_error",
 ]
@@ -93,6 +93,7 @@ def lib():
         "adafac_regrid_prepare": (C.c_int, [P, C.POINTER(C.c_double), C.c_double, C.c_int, C.POINTER(C.c_double),
                                             C.c_size_t, C.POINTER(C.c_size_t)]),
         "adafac_regrid": (C.c_int, [P, P, C.c_size_t]),
+        "adafac_set_rhs_gaussian": (C.c_int, [P, C.POINTER(C.c_double), C.c_double, C.c_double]),
         "adafac_last_error": (C.c_char_p, [P]),
         "adafac_server_default_cfg": (None, [C.POINTER(ServerCfg)]),
         "adafac_server_create": (C.c_int, [C.POINTER(ServerCfg), P, C.c_size_t, P, C.POINTER(P)]),

@@ -109,6 +109,10 @@ struct adafac_ctx {
   RtSep<double> ad_rts{};
   std::vector<AdaptLevel> ad;           // device views by level
   double* ad_eps = nullptr;
+  // right-hand side: a lattice (set_rhs_lattice) or a Gaussian source (set_rhs_gaussian)
+  int src_gauss = 0;
+  double src_c[3] = {0, 0, 0}, src_sigma = 1.0, src_amp = 1.0;
+  double next_src_c[3] = {0, 0, 0};
   AdaptHost at_next;                    // regrid: the prepared tree, its right-hand side and size
   std::vector<double> f_next;
   size_t next_need = 0;
@@ -141,6 +145,17 @@ size_t nverts_of(int d, int l) {
 }
 
 bool mixed(const adafac_ctx* c) { return c->opts.precision == ADAFAC_PREC_FP32_REFINED; }
+
+// f at the finest-lattice point (gx, gy, gz)
+double source_at(const adafac_ctx* c, size_t gx, size_t gy, size_t gz) {
+  const size_t nL = size_t(ipow3(c->L)) + 1;
+  if (!c->src_gauss) return c->f[(gz * nL + gy) * nL + gx];
+  const double h = 1.0 / double(nL - 1);
+  const double x[3] = {gx * h, gy * h, gz * h};
+  double r2 = 0.0;
+  for (int a = 0; a < c->dim; ++a) r2 += (x[a] - c->src_c[a]) * (x[a] - c->src_c[a]);
+  return c->src_amp * std::exp(-r2 / (2.0 * c->src_sigma * c->src_sigma));
+}
 
 // Lay out every device array inside the workspace; with base == nullptr only sizes.
 size_t layout_adaptive(adafac_ctx* c, char* base);
@@ -605,7 +620,7 @@ int bind_adaptive(adafac_ctx* c) {
           }
           if (!nleaf) continue;
           const size_t gx = size_t(A.ox + x) * s, gy = size_t(A.oy + y) * s, gz = d == 3 ? size_t(A.oz + z) * s : 0;
-          bl[i] = nleaf * share * c->f[(gz * nL + gy) * nL + gx];
+          bl[i] = nleaf * share * source_at(c, gx, gy, gz);
         }
     HIPCHK(c, hipMemcpyAsync(const_cast<uint8_t*>(A.vcls), H.vcls.data(), H.vcls.size(), hipMemcpyHostToDevice,
                              c->stream));
@@ -799,6 +814,23 @@ int adafac_set_rhs_lattice(adafac_ctx* c, const double* f, size_t n) {
   for (size_t i = 0; i < n; ++i)
     if (!std::isfinite(f[i])) return fail(c, ADAFAC_EINVAL, "f: non-finite value");
   c->f.assign(f, f + n);
+  c->src_gauss = 0;
+  c->bound = false;
+  return ADAFAC_OK;
+}
+
+int adafac_set_rhs_gaussian(adafac_ctx* c, const double* centre, double sigma, double amplitude) {
+  if (!c) return ADAFAC_EINVAL;
+  if (!centre || !(sigma > 0.0) || !std::isfinite(sigma) || !std::isfinite(amplitude))
+    return fail(c, ADAFAC_EINVAL, "bad Gaussian source");
+  for (int a = 0; a < c->dim; ++a) {
+    if (!std::isfinite(centre[a])) return fail(c, ADAFAC_EINVAL, "bad Gaussian centre");
+    c->src_c[a] = centre[a];
+  }
+  c->src_sigma = sigma;
+  c->src_amp = amplitude;
+  c->src_gauss = 1;
+  c->f.clear();
   c->bound = false;
   return ADAFAC_OK;
 }
@@ -852,7 +884,7 @@ int adafac_workspace_bytes(const adafac_ctx* c, size_t* bytes) {
 int adafac_bind(adafac_ctx* c, void* ws, size_t bytes, void* stream) {
   if (!c) return ADAFAC_EINVAL;
   if (!c->built) return fail(c, ADAFAC_ESTATE, "build_operators first");
-  if (c->f.empty()) return fail(c, ADAFAC_ESTATE, "set_rhs_lattice first");
+  if (c->f.empty() && !c->src_gauss) return fail(c, ADAFAC_ESTATE, "set the right-hand side first");
   size_t need = c->ws_need;
   if (!ws || bytes < need) return fail(c, ADAFAC_ENOMEM, "workspace too small: need " + std::to_string(need));
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(c, ADAFAC_EINVAL, "workspace not 256-byte aligned");
@@ -881,7 +913,7 @@ int adafac_bind(adafac_ctx* c, void* ws, size_t bytes, void* stream) {
   for (int z = (d == 3 ? 1 : 0); z < (d == 3 ? nv - 1 : 1); ++z)
     for (int y = 1; y < nv - 1; ++y) {
       const size_t row = (size_t(z) * nv + y) * nv;
-      for (int x = 1; x < nv - 1; ++x) b[row + x] = hd * c->f[row + x];
+      for (int x = 1; x < nv - 1; ++x) b[row + x] = hd * source_at(c, x, y, z);
     }
   HIPCHK(c, hipMemcpyAsync(c->h64.bfine, b.data(), sizeof(double) * b.size(), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1197,16 +1229,22 @@ int adafac_regrid_prepare(adafac_ctx* c, const double* centre, double radius, in
   if (!centre || !(radius > 0.0) || !std::isfinite(radius)) return fail(c, ADAFAC_EINVAL, "bad ball");
   if (l_from < c->lmin || l_from >= c->L) return fail(c, ADAFAC_EINVAL, "l_from must lie in l_min..l_max-1");
   if (c->ops.k > l_from) return fail(c, ADAFAC_EINVAL, "coefficient blocks finer than the first refined level");
-  if (!f || n != nverts_of(c->dim, c->L)) return fail(c, ADAFAC_EINVAL, "f: wrong size");
-  for (size_t i = 0; i < n; ++i)
-    if (!std::isfinite(f[i])) return fail(c, ADAFAC_EINVAL, "f: non-finite value");
+  if (f) {
+    if (n != nverts_of(c->dim, c->L)) return fail(c, ADAFAC_EINVAL, "f: wrong size");
+    for (size_t i = 0; i < n; ++i)
+      if (!std::isfinite(f[i])) return fail(c, ADAFAC_EINVAL, "f: non-finite value");
+  } else if (!c->src_gauss) {
+    return fail(c, ADAFAC_EINVAL, "f: a lattice is needed unless the right-hand side is a Gaussian source");
+  }
   double cc[3] = {0, 0, 0};
   for (int a = 0; a < c->dim; ++a) cc[a] = centre[a];
   std::string m = build_adapt_tree(c->at_next, c->dim, c->lmin, c->L, {}, cc, radius, l_from);
   if (!m.empty()) return fail(c, ADAFAC_EINVAL, m);
   // the uniform levels below the coefficient blocks are those of the current tree
   for (int l = c->lmin; l < c->ops.k; ++l) c->at_next.lev[l].dg = c->at.lev[l].dg;
-  c->f_next.assign(f, f + n);
+  if (f) c->f_next.assign(f, f + n);
+  else c->f_next.clear();
+  for (int a = 0; a < 3; ++a) c->next_src_c[a] = cc[a];
   c->next_need = layout_adaptive_tree(c, c->at_next, nullptr);
   c->next_ready = true;
   for (int a = 0; a < 3; ++a) c->ball_c[a] = cc[a];
@@ -1236,7 +1274,12 @@ int adafac_regrid(adafac_ctx* c, void* ws, size_t bytes) {
   double* old_norm0 = c->norm0;
   // switch to the new tree and its workspace
   std::swap(c->at, c->at_next);
-  c->f.swap(c->f_next);
+  if (c->src_gauss && c->f_next.empty()) {
+    for (int a = 0; a < 3; ++a) c->src_c[a] = c->next_src_c[a];   // the source moves with the ball
+  } else {
+    c->f.swap(c->f_next);
+    c->src_gauss = 0;
+  }
   layout(c, static_cast<char*>(ws));
   HIPCHK(c, hipMemsetAsync(ws, 0, c->next_need, c->stream));
   if ((rc = bind_adaptive(c))) return rc;

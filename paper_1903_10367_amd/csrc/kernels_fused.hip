@@ -54,6 +54,12 @@ constexpr int NR = RW * RW;
 #define ADAFAC_SWEEP3D_TZ 0      // 0: choose per level
 #endif
 constexpr int NT3 = ADAFAC_SWEEP3D_THREADS;
+#ifndef ADAFAC_SWEEP3D_RP
+#define ADAFAC_SWEEP3D_RP 31
+#endif
+constexpr int RP = ADAFAC_SWEEP3D_RP;        // LDS row pitch of the 3D residual ring (>= RW)
+constexpr int RB3 = RW * RP + (NT3 - NR);    // residual ring plus one slot per idle lane
+static_assert(RP >= RW, "row pitch below the ring width");
 constexpr int NUSLOT = (NU + 255) / 256;
 constexpr int NSLOT = (NR + 255) / 256;
 constexpr int NUSLOT3 = (NU + NT3 - 1) / NT3;
@@ -242,7 +248,7 @@ template <typename T, bool VAREPS, bool COARSE, bool PEND>
 __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_fine_sweep3d(Sweep3dArgs<T> a) {
   static_assert(NT3 >= NU, "one lane per ring column");
   __shared__ T Ub[3][NT3];               // u planes (padded: every lane writes its slot)
-  __shared__ T Rb[3][NT3];               // residual planes
+  __shared__ T Rb[3][RB3];               // residual planes, row pitch RP
   __shared__ T Xw[3][RW * NCO];          // x passes
   __shared__ T Xm[3][RW * NCO];
   __shared__ T Sb[PEND ? (MAXTZ / 3 + 3) * CW * CW : 1];
@@ -297,6 +303,8 @@ __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_fine_sweep3d(S
   const int roff = min(max(x, 0), n) + nv * min(max(y, 0), n);
   const unsigned roffb = unsigned(roff * sizeof(T));
   const int upos = (ry + 1) * UW + rx + 1;
+  // residual slot: row pitch RP (bank spread of the strided x-pass reads), idle lanes past it
+  const int rslot = ract ? ry * RP + rx : RW * RP + (tid - NR);
 
   ColumnOp<T, VAREPS> col;
   // prefetch ring: slot K holds u(p) and b(p-2) for the steps p of slot K
@@ -381,23 +389,24 @@ __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_fine_sweep3d(S
         // FAS injection u_{L-1} = I u: planes z = p-2 with z = 0 mod 3 are the steps K = 2
         if (K == 2 && own_pt && rinj) a.cu[lin<3>(x / 3, y / 3, z / 3, nvc)] = uz;
       }
-      Rb[K1][tid] = res;
+      Rb[K1][rslot] = res;
     }
     pb[K2] = CK ? bload(min(p + 1, ze)) : B.ld(roffb, unsigned(p + 1) * planeb);
     // (3) x pass of residual plane p-3 (slot K)
     if (!CK || (p - 3 >= zs + 1 && p - 3 <= ze - 1)) {
       const int xt = tid - XP0;
       if (xt >= 0 && xt < RW * NCO) {
-        const int yy = xt / NCO, ccx = xt % NCO;
-        const T* rp = &Rb[K][yy * RW + 3 * ccx + 2];
+        // consecutive lanes take consecutive rows of one coarse column (conflict-free reads)
+        const int yy = xt % RW, ccx = xt / RW;
+        const T* rp = &Rb[K][yy * RP + 3 * ccx + 2];
         T sw = T(0), sm = T(0);
 #pragma unroll
         for (int o = -2; o <= 2; ++o) {
           sw += wlin<T>(o) * rp[o];
           sm += a.rts.m[o + 2] * rp[o];
         }
-        Xw[K][xt] = sw;
-        Xm[K][xt] = sm;
+        Xw[K][yy * NCO + ccx] = sw;
+        Xm[K][yy * NCO + ccx] = sm;
       }
     }
     // (4) y pass of residual plane zr = p-4 (slot K2), accumulated into the coarse planes at
@@ -417,7 +426,7 @@ __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_fine_sweep3d(S
           const int row = 3 * ccy + 2 + o;
           W += wlin<T>(o) * xw[row * NCO + ccx];
           Q += a.rts.m[o + 2] * xm[row * NCO + ccx];
-          Y += a.rts.m[o + 2] * rz[row * RW + 3 * ccx + 2];
+          Y += a.rts.m[o + 2] * rz[row * RP + 3 * ccx + 2];
         }
         const T X = xm[(3 * ccy + 2) * NCO + ccx];
         // R~: planar tensor products; the plane through the coarse vertex also carries Q

@@ -134,3 +134,30 @@ def test_regrid_moving_ball(d):
     for l in range(1, L + 1):
         have = T2.dof[l] | T2.hang[l]
         assert np.abs(levels[l].reshape(T2.shape(l))[have] - U[l][have]).max() <= 1e-12 * scale
+
+
+def test_gaussian_source_moving_with_the_ball():
+    """The moving-source workload in miniature: a Gaussian source evaluated by the library,
+    the tree refined around it and regridded as it moves (no lattice handed over)."""
+    from paper_1903_10367_amd import Solver
+    say("case adaptive gaussian source regrid")
+    d, L, lu, sigma = 3, 3, 2, 0.05
+    centres = inp.moving_source(seed=85, steps=2, d=d)
+    rad = 3 * sigma
+    eps = inp.eps_blocks(d, 1, 2.0, seed=86)
+    s = Solver(d, 1, L, {"gaussian": (centres[0], sigma, 1.0)}, eps_blocks=eps, ball=(centres[0], rad, lu))
+    s.cycle(3)
+    s.regrid(centres[1], rad, lu)
+    s.cycle(3)
+    hg = s.residuals()
+    s.close()
+    T = adaptive.AdaptiveTree(d, L, 1, lu, inp.refine_ball(d, L, lu, centres[0], rad), eps)
+    U, ho = adaptive.solve(T, inp.gaussian(d, L, centres[0], sigma), 3)
+    T2 = adaptive.AdaptiveTree(d, L, 1, lu, inp.refine_ball(d, L, lu, centres[1], rad), eps)
+    U = adaptive.transfer(T, U, T2)
+    b2 = T2.load(inp.gaussian(d, L, centres[1], sigma))
+    for _ in range(3):
+        U, nr = adaptive.cycle(T2, U, b2)
+        ho.append(nr)
+    for n, (a, b) in enumerate(zip(hg, ho)):
+        assert abs(a[0] - b[0]) <= 1e-12 * ho[0][0], f"cycle {n}"
