@@ -112,7 +112,10 @@ int adafac_set_rhs_gaussian(adafac_ctx* ctx, const double* centre, double sigma,
  * next coarser level), and the composite grid is formed by the finest dof of
  * every position.  The cycle works over the hierarchical generating system
  * (Sec. 2.3, eq. (adaFACx)).  Adaptive trees support d-linear transfers,
- * adAFAC-Jac and plain additive damping, FP64.  The coefficient blocks must be
+ * adAFAC-Jac and plain additive damping, in FP64 or FP32_REFINED (the FP64
+ * defect of a step is the composite residual of the FP64 iterate; the inner
+ * FP32 cycles take it, at the composite dofs, as their leaf loads and start
+ * from zero values on every level).  The coefficient blocks must be
  * no finer than the first refined level.  Call build_operators again afterwards.
  * EINVAL on a bad level or size. */
 int adafac_set_refinement(adafac_ctx* ctx, int level, const uint8_t* flags, size_t ncells);
@@ -212,7 +215,8 @@ int adafac_set_solution(adafac_ctx* ctx, const double* u, size_t n);
  * the values at the dofs' positions from such a lattice.  adafac_get_level
  * returns which = 0 (nodal values u_l, hanging ones interpolated), 1 (b_l, the
  * level hats tested against the composite residual) or 4 (S_l) for levels
- * l_min..l_max, on the full level lattice, zero outside the level's cells.
+ * l_min..l_max, on the full level lattice, zero outside the level's cells;
+ * under FP32_REFINED only which = 0 (ESTATE otherwise).
  *
  * Copy a level array of the last cycle to host memory (inspection and
  * per-step parity checks).  which: 0 = u_l (FAS solution, injected),

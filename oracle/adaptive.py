@@ -197,15 +197,19 @@ def norms(T, rh):
     return np.sqrt(s), m
 
 
-def cycle(T, U, bleaf, omega=0.6, omega_t=0.6, damping="jac", trace=None):
+def cycle(T, U, bleaf, omega=0.6, omega_t=0.6, damping="jac", trace=None, dtype=np.float64):
     """One adAFAC cycle on the adaptive tree (correction form over the generating system).
 
     U: per-level storage of the iterate (see AdaptiveTree.spread).  Returns the new storage and
-    the norms of the composite residual of the input iterate.
+    the norms of the composite residual of the input iterate.  ``dtype`` float32 stores every
+    intermediate array in FP32 (the inner cycles of defect correction); the operators are
+    applied as FP64 factors and their results rounded, so this gives the size of FP32
+    rounding, not any particular rounding order.
     """
     assert damping in ("jac", "none")
     d, L, lmin = T.d, T.L, T.lmin
-    U = T.spread(U)
+    U = T.spread({l: U[l].astype(dtype) for l in U})
+    bleaf = {l: bleaf[l].astype(dtype) for l in bleaf}
     # leaf residuals, per level, at every vertex of a leaf cell
     rl = {l: bleaf[l] - T.leaf_apply(l, U[l]).reshape(T.shape(l)) for l in range(lmin, L + 1)}
     # the level-l hats tested against the composite residual: b_l = r^leaf_l + R b_{l+1}
@@ -221,9 +225,9 @@ def cycle(T, U, bleaf, omega=0.6, omega_t=0.6, damping="jac", trace=None):
         hh[l] = np.where(T.hang[l], acc, 0.0)
         rh[l] = np.where(T.comp[l], acc, 0.0)
     nr = norms(T, rh)
-    Dinv = {l: np.where(T.dof[l], 1.0 / np.where(T.dof[l], T.D[l], 1.0), 0.0) for l in T.D}
+    Dinv = {l: np.where(T.dof[l], 1.0 / np.where(T.dof[l], T.D[l], 1.0), 0.0).astype(dtype) for l in T.D}
     c = {l: omega * Dinv[l] * b[l] for l in b}
-    ct = {l: np.zeros(T.shape(l)) for l in b}
+    ct = {l: np.zeros(T.shape(l), dtype=dtype) for l in b}
     if damping == "jac":
         for l in range(lmin, L):
             ct[l] = omega_t * Dinv[l] * T.Rt[l + 1](b[l + 1].ravel()).reshape(T.shape(l))
@@ -247,6 +251,51 @@ def solve(T, f, max_cycles, tol=None, **kw):
         if tol is not None and hist[0][0] > 0 and hist[-1][0] / hist[0][0] <= tol:
             break
     return U, hist
+
+
+def composite_residual(T, U, bleaf):
+    """The composite residual of the iterate U at every composite dof (on the dof's level, zero
+    elsewhere) and its norms: the first steps of :func:`cycle`, in FP64."""
+    U = T.spread(U)
+    rl = {l: bleaf[l] - T.leaf_apply(l, U[l]).reshape(T.shape(l)) for l in range(T.lmin, T.L + 1)}
+    hh = np.where(T.hang[T.L], rl[T.L], 0.0)
+    rh = {T.L: np.where(T.comp[T.L], rl[T.L], 0.0)}
+    for l in range(T.L - 1, T.lmin - 1, -1):
+        acc = rl[l] + T.PT[l + 1](hh.ravel()).reshape(T.shape(l))
+        hh = np.where(T.hang[l], acc, 0.0)
+        rh[l] = np.where(T.comp[l], acc, 0.0)
+    return rh, norms(T, rh)
+
+
+def defect_correction(T, f, k_inner, tol, max_outer, inner_dtype=np.float32, iterates=None, U0=None, **kw):
+    """FP64 defect correction around k adAFAC cycles in ``inner_dtype`` on the tree.
+
+    Outer step: the composite residual r of u in FP64 and its norms; stop if
+    ||r||_h / ||r^0||_h <= tol; otherwise k cycles on the correction equation from e = 0, then
+    u <- u + e at every dof in FP64.  The inner leaf loads are r at the composite dofs and zero
+    elsewhere: the same functional as the leaf residuals of u (a composite-space function is
+    the sum of its composite-dof values times the composite hats), but without the large
+    per-level leaf parts that cancel at refinement boundaries and would be rounded to FP32
+    before they cancel.  The cycle is linear, so k inner cycles equal k cycles on u in exact
+    arithmetic.  Starts from U0 (per-level storage; default zero).  Returns (U, outer residual
+    history); ``iterates`` (a list) receives every outer iterate's per-level storage.
+    """
+    U = {l: np.zeros(T.shape(l)) for l in range(T.lmin, T.L + 1)} if U0 is None else U0
+    bleaf = T.load(f)
+    hist = []
+    for _ in range(max_outer + 1):
+        U = T.spread(U)
+        rh, nr = composite_residual(T, U, bleaf)
+        hist.append(nr)
+        if iterates is not None:
+            iterates.append({l: U[l].copy() for l in U})
+        if hist[0][0] == 0 or hist[-1][0] / hist[0][0] <= tol or len(hist) > max_outer:
+            break
+        E = {l: np.zeros(T.shape(l), dtype=inner_dtype) for l in U}
+        for _ in range(k_inner):
+            E, _ = cycle(T, E, rh, dtype=inner_dtype, **kw)
+        U = {l: np.where(T.dof[l], U[l] + E[l].astype(np.float64), U[l]) for l in U}
+    return T.spread(U), hist
 
 
 def finest_values(T, U):

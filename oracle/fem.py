@@ -124,7 +124,9 @@ def apply_matrix_free(u, eps_cells):
 
     Same element-wise accumulation: for each cell and each pair of its
     corners, eps_c h^(d-2) K_ref[i, j] u_j is added to vertex i.  The result is
-    zero on the boundary.  Used where the level is too large to assemble.
+    zero on the boundary.  Used where the level is too large to assemble.  The
+    arithmetic is that of u's dtype (FP32 inner cycles round every product and
+    sum in FP32).
     """
     eps_cells = np.asarray(eps_cells, dtype=np.float64)
     d = eps_cells.ndim
@@ -133,7 +135,7 @@ def apply_matrix_free(u, eps_cells):
     K = ref_stiffness(d)
     u = np.asarray(u)
     out = np.zeros_like(u)
-    scale = eps_cells * h ** (d - 2)
+    scale = (eps_cells * h ** (d - 2)).astype(out.dtype)
     for j in range(2 ** d):
         oj = corner_offset(j, d)
         uj = u[tuple(slice(oj[a], oj[a] + n) for a in range(d))]
@@ -142,7 +144,7 @@ def apply_matrix_free(u, eps_cells):
             if K[i, j] == 0.0:
                 continue
             oi = corner_offset(i, d)
-            out[tuple(slice(oi[a], oi[a] + n) for a in range(d))] += K[i, j] * su
+            out[tuple(slice(oi[a], oi[a] + n) for a in range(d))] += out.dtype.type(K[i, j]) * su
     out[~interior_mask(d, int(round(np.log(n) / np.log(3))))] = 0.0
     return out
 

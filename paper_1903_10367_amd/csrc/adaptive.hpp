@@ -18,25 +18,28 @@ constexpr uint8_t kDof = 1;        // all 2^d level cells around it exist, inter
 constexpr uint8_t kHang = 2;       // vertex of an existing cell, interior, not a dof
 constexpr uint8_t kComp = 4;       // dof whose finest dof level is this one (composite dof)
 
-// Device view of one ragged level: the box [o, o + m) of the level's vertex lattice (m = 1
-// along z in 2D); cells of the box are the (m - 1)^d cells between its vertices.
-struct AdaptLevel {
+// Device view of one ragged level in the arithmetic of T: the box [o, o + m) of the level's
+// vertex lattice (m = 1 along z in 2D); cells of the box are the (m - 1)^d cells between its
+// vertices.
+template <typename T>
+struct AdaptLevelT {
   int ox, oy, oz, mx, my, mz;
   int n;                    // cells per axis of the whole level
-  double h, hd, hdm2;       // h, h^d, h^(d-2)
+  T h, hd, hdm2;            // h, h^d, h^(d-2)
   int fem;                  // 1: Q1 operator from eps blocks; 0: stored diagonal (uniform Galerkin level)
   int nb, bs;               // eps blocks per axis, cells per block along an axis
-  const double* eps;        // nb^d blocks, nullptr: eps = 1
-  const double* dg;         // stored diagonal over the box when !fem
+  const T* eps;             // nb^d blocks, nullptr: eps = 1
+  const T* dg;              // stored diagonal over the box when !fem
   const uint8_t* vcls;      // per box vertex
   const uint8_t* leaf;      // per box cell: 0 = no cell, 1 = leaf cell, 2 = refined cell
-  const double* bleaf;      // lumped load of the level's leaf cells at box vertices
-  double* u;                // nodal values: composite dofs, copies of finer dofs, hanging interpolations
-  double* bb;               // leaf residual, then the level hats tested against the composite residual
-  double* hh;               // hanging-only accumulation (composite residual of coarser dofs)
-  double* s;                // own correction c - c~ at dofs
-  double* S;                // prolongated sum of corrections
+  T* bleaf;                 // lumped load of the level's leaf cells (inner form: the outer defect)
+  T* u;                     // nodal values: composite dofs, copies of finer dofs, hanging interpolations
+  T* bb;                    // leaf residual, then the level hats tested against the composite residual
+  T* hh;                    // hanging-only accumulation (composite residual of coarser dofs)
+  T* s;                     // own correction c - c~ at dofs
+  T* S;                     // prolongated sum of corrections
 };
+using AdaptLevel = AdaptLevelT<double>;
 
 // All levels of a tree (the old one of a regrid) and the finest-lattice spacing of each level.
 struct AdaptTreeView {
@@ -76,13 +79,25 @@ std::string build_adapt_tree(AdaptHost& t, int d, int lmin, int L, const std::ve
 
 // Device launchers (kernels_adaptive.hip).  Every level l is given with its next coarser
 // (C) or finer (F) neighbour level where the step needs it.
-hipError_t launch_ad_hang(int d, const AdaptLevel& L, const AdaptLevel& C, hipStream_t s);
-hipError_t launch_ad_leaf(int d, const AdaptLevel& L, hipStream_t s);
-hipError_t launch_ad_up(int d, const AdaptLevel& L, const AdaptLevel* F, const RtSep<double>& rts, double omega,
-                        double omega_t, int damping, double* partials, hipStream_t s);
-hipError_t launch_ad_down(int d, const AdaptLevel& L, const AdaptLevel* C, hipStream_t s);
-hipError_t launch_ad_update(int d, const AdaptLevel& L, const AdaptLevel* F, hipStream_t s);
+template <typename T>
+hipError_t launch_ad_hang(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>& C, hipStream_t s);
+template <typename T>
+hipError_t launch_ad_leaf(int d, const AdaptLevelT<T>& L, hipStream_t s);
+// norms_only: only the composite residual: norm partials, hh, and bb replaced by the composite
+// residual at composite dofs (zero elsewhere)
+template <typename T>
+hipError_t launch_ad_up(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>* F, const RtSep<T>& rts, T omega,
+                        T omega_t, int damping, int norms_only, double* partials, hipStream_t s);
+template <typename T>
+hipError_t launch_ad_down(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>* C, hipStream_t s);
+template <typename T>
+hipError_t launch_ad_update(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>* F, hipStream_t s);
 hipError_t launch_ad_transfer(int d, const AdaptLevel& A, int scale, const AdaptTreeView& O, hipStream_t s);
+// FP32 inner form: bleaf32 = float(bb), the composite residual of the FP64 iterate at its
+// composite dofs (the inner loads), inner iterate e = 0
+hipError_t launch_ad_to_inner(int d, const AdaptLevel& A, const AdaptLevelT<float>& E, hipStream_t s);
+// u += e at every dof (composite dofs and their coarse copies)
+hipError_t launch_ad_accumulate(int d, const AdaptLevel& A, const AdaptLevelT<float>& E, hipStream_t s);
 constexpr int kAdaptNormBlocks = 256;   // norm partial blocks per level
 
 }  // namespace adafac

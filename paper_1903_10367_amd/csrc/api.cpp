@@ -109,6 +109,9 @@ struct adafac_ctx {
   RtSep<double> ad_rts{};
   std::vector<AdaptLevel> ad;           // device views by level
   double* ad_eps = nullptr;
+  std::vector<AdaptLevelT<float>> ad32; // FP32_REFINED: inner cycles on the defect equation
+  RtSep<float> ad_rts32{};
+  float* ad_eps32 = nullptr;
   // right-hand side: a lattice (set_rhs_lattice) or a Gaussian source (set_rhs_gaussian)
   int src_gauss = 0;
   double src_c[3] = {0, 0, 0}, src_sigma = 1.0, src_amp = 1.0;
@@ -358,10 +361,14 @@ int run_cycle(adafac_ctx* c, Hier<T>& H, double* norm_out, const T* uin_zero) {
 // Add the pending prolongated coarse correction to the current FP64 iterate (FP64 form), or
 // the pending inner correction e + P S_{L-1} to the FP64 solution (FP32_REFINED).
 int adapt_hang(adafac_ctx* c);
+int adapt_accumulate(adafac_ctx* c);
 
 int flush(adafac_ctx* c) {
   const int L = c->L;
-  if (c->adaptive) return adapt_hang(c);
+  if (c->adaptive) {
+    int rc = adapt_accumulate(c);
+    return rc ? rc : adapt_hang(c);
+  }
   if (mixed(c)) {
     if (!c->e_pending) return ADAFAC_OK;
     Hier<float>& H = c->h32;
@@ -393,8 +400,11 @@ size_t layout_adaptive_tree(adafac_ctx* c, const AdaptHost& t, char* base) {
     return p;
   };
   const int d = c->dim;
+  const bool mp = mixed(c);
   std::vector<AdaptLevel> ad(c->L + 1, AdaptLevel{});
+  std::vector<AdaptLevelT<float>> ad32(mp ? c->L + 1 : 0, AdaptLevelT<float>{});
   double* eps = reinterpret_cast<double*>(take(sizeof(double) * c->ops.eps.size()));
+  float* eps32 = mp ? reinterpret_cast<float*>(take(sizeof(float) * c->ops.eps.size())) : nullptr;
   const bool unit = c->ops.nb == 1 && c->ops.eps[0] == 1.0;
   for (int l = c->lmin; l <= c->L; ++l) {
     const AdaptHostLevel& H = t.lev[l];
@@ -421,8 +431,31 @@ size_t layout_adaptive_tree(adafac_ctx* c, const AdaptHost& t, char* base) {
     A.u = reinterpret_cast<double*>(take(sizeof(double) * nv));
     A.bb = reinterpret_cast<double*>(take(sizeof(double) * nv));
     A.hh = reinterpret_cast<double*>(take(sizeof(double) * nv));
-    A.s = reinterpret_cast<double*>(take(sizeof(double) * nv));
-    A.S = reinterpret_cast<double*>(take(sizeof(double) * nv));
+    if (!mp) {
+      A.s = reinterpret_cast<double*>(take(sizeof(double) * nv));
+      A.S = reinterpret_cast<double*>(take(sizeof(double) * nv));
+      continue;
+    }
+    // FP32_REFINED: the FP64 levels only hold u and the outer defect; the cycles run on E
+    AdaptLevelT<float>& E = ad32[l];
+    E.ox = A.ox, E.oy = A.oy, E.oz = A.oz, E.mx = A.mx, E.my = A.my, E.mz = A.mz;
+    E.n = A.n;
+    E.h = float(A.h);
+    E.hd = float(A.hd);
+    E.hdm2 = float(A.hdm2);
+    E.fem = A.fem;
+    E.nb = A.nb;
+    E.bs = A.bs;
+    E.eps = unit ? nullptr : eps32;
+    E.vcls = A.vcls;
+    E.leaf = A.leaf;
+    if (!E.fem) E.dg = reinterpret_cast<float*>(take(sizeof(float) * nv));
+    E.bleaf = reinterpret_cast<float*>(take(sizeof(float) * nv));
+    E.u = reinterpret_cast<float*>(take(sizeof(float) * nv));
+    E.bb = reinterpret_cast<float*>(take(sizeof(float) * nv));
+    E.hh = reinterpret_cast<float*>(take(sizeof(float) * nv));
+    E.s = reinterpret_cast<float*>(take(sizeof(float) * nv));
+    E.S = reinterpret_cast<float*>(take(sizeof(float) * nv));
   }
   const size_t npart = size_t(kAdaptNormBlocks) * (c->L - c->lmin + 1);
   double* partials = reinterpret_cast<double*>(take(sizeof(double) * 2 * npart));
@@ -432,6 +465,8 @@ size_t layout_adaptive_tree(adafac_ctx* c, const AdaptHost& t, char* base) {
   if (base) {
     c->ad = std::move(ad);
     c->ad_eps = eps;
+    c->ad32 = std::move(ad32);
+    c->ad_eps32 = eps32;
     c->npartials = npart;
     c->partials = partials;
     c->norms = norms;
@@ -444,27 +479,64 @@ size_t layout_adaptive_tree(adafac_ctx* c, const AdaptHost& t, char* base) {
 size_t layout_adaptive(adafac_ctx* c, char* base) { return layout_adaptive_tree(c, c->at, base); }
 
 // hanging vertices interpolated top-down from the current nodal values
-int adapt_hang(adafac_ctx* c) {
-  for (int l = c->lmin + 1; l <= c->L; ++l) HIPCHK(c, launch_ad_hang(c->dim, c->ad[l], c->ad[l - 1], c->stream));
+template <typename T>
+int adapt_hang_views(adafac_ctx* c, const std::vector<AdaptLevelT<T>>& ad) {
+  for (int l = c->lmin + 1; l <= c->L; ++l) HIPCHK(c, launch_ad_hang<T>(c->dim, ad[l], ad[l - 1], c->stream));
   return ADAFAC_OK;
 }
 
-int run_adapt_cycle(adafac_ctx* c, double* norm_out) {
+int adapt_hang(adafac_ctx* c) { return adapt_hang_views(c, c->ad); }
+
+// FP32_REFINED: the pending inner correction added to the FP64 nodal values
+int adapt_accumulate(adafac_ctx* c) {
+  if (!mixed(c) || !c->e_pending) return ADAFAC_OK;
+  for (int l = c->lmin; l <= c->L; ++l) HIPCHK(c, launch_ad_accumulate(c->dim, c->ad[l], c->ad32[l], c->stream));
+  c->e_pending = false;
+  return ADAFAC_OK;
+}
+
+// One cycle on the levels ad (FP64 form, or an FP32 inner cycle whose leaf loads are the outer
+// defect); norms of the composite residual of the input iterate into norm_out.
+template <typename T>
+int run_adapt_cycle(adafac_ctx* c, const std::vector<AdaptLevelT<T>>& ad, const RtSep<T>& rts, double* norm_out) {
   const int d = c->dim, L = c->L, lmin = c->lmin;
   const adafac_opts& o = c->opts;
-  int rc = adapt_hang(c);
+  const T omega = T(o.omega), omega_t = T(o.omega_tilde);
+  int rc = adapt_hang_views(c, ad);
   if (rc) return rc;
   if ((rc = record_start(c))) return rc;
-  for (int l = lmin; l <= L; ++l) HIPCHK(c, launch_ad_leaf(d, c->ad[l], c->stream));
+  for (int l = lmin; l <= L; ++l) HIPCHK(c, launch_ad_leaf<T>(d, ad[l], c->stream));
   if ((rc = record_stop(c))) return rc;
   for (int l = L; l >= lmin; --l)
-    HIPCHK(c, launch_ad_up(d, c->ad[l], l < L ? &c->ad[l + 1] : nullptr, c->ad_rts, o.omega, o.omega_tilde,
-                           o.damping, c->partials + 2 * size_t(kAdaptNormBlocks) * (l - lmin), c->stream));
+    HIPCHK(c, launch_ad_up<T>(d, ad[l], l < L ? &ad[l + 1] : nullptr, rts, omega, omega_t, o.damping, 0,
+                              c->partials + 2 * size_t(kAdaptNormBlocks) * (l - lmin), c->stream));
   HIPCHK(c, launch_norm_finalize(c->partials, int(c->npartials), norm_out, c->stream));
   for (int l = lmin; l <= L; ++l)
-    HIPCHK(c, launch_ad_down(d, c->ad[l], l > lmin ? &c->ad[l - 1] : nullptr, c->stream));
+    HIPCHK(c, launch_ad_down<T>(d, ad[l], l > lmin ? &ad[l - 1] : nullptr, c->stream));
   for (int l = L; l >= lmin; --l)
-    HIPCHK(c, launch_ad_update(d, c->ad[l], l < L ? &c->ad[l + 1] : nullptr, c->stream));
+    HIPCHK(c, launch_ad_update<T>(d, ad[l], l < L ? &ad[l + 1] : nullptr, c->stream));
+  return ADAFAC_OK;
+}
+
+// FP32_REFINED on a tree: the pending correction added to u, then in FP64 the composite
+// residual of u and its norms; the residual at the composite dofs (zero elsewhere), rounded to
+// FP32, is the leaf load of the next inner solve, whose iterate restarts at zero.  It is the
+// same functional as the per-level leaf residuals, without their large parts that cancel
+// across refinement boundaries (rounded to FP32 first, they would leave an error of FP32 size
+// relative to b, a floor near 1e-8 for the outer iteration).
+int run_adapt_outer_mixed(adafac_ctx* c, double* norm_out) {
+  const int d = c->dim, L = c->L, lmin = c->lmin;
+  int rc = adapt_accumulate(c);
+  if (rc || (rc = adapt_hang(c))) return rc;
+  if ((rc = record_start(c))) return rc;
+  for (int l = lmin; l <= L; ++l) HIPCHK(c, launch_ad_leaf<double>(d, c->ad[l], c->stream));
+  if ((rc = record_stop(c))) return rc;
+  for (int l = L; l >= lmin; --l)
+    HIPCHK(c, launch_ad_up<double>(d, c->ad[l], l < L ? &c->ad[l + 1] : nullptr, c->ad_rts, 0.0, 0.0,
+                                   c->opts.damping, 1, c->partials + 2 * size_t(kAdaptNormBlocks) * (l - lmin),
+                                   c->stream));
+  HIPCHK(c, launch_norm_finalize(c->partials, int(c->npartials), norm_out, c->stream));
+  for (int l = lmin; l <= L; ++l) HIPCHK(c, launch_ad_to_inner(d, c->ad[l], c->ad32[l], c->stream));
   return ADAFAC_OK;
 }
 
@@ -474,7 +546,7 @@ int run_adapt_cycle(adafac_ctx* c, double* norm_out) {
 int run_outer(adafac_ctx* c) {
   double* norm_out = c->norms + 2 * (c->ncyc % kMaxHist);
   if (c->adaptive) {
-    int rc = run_adapt_cycle(c, norm_out);
+    int rc = mixed(c) ? run_adapt_outer_mixed(c, norm_out) : run_adapt_cycle<double>(c, c->ad, c->ad_rts, norm_out);
     if (rc) return rc;
   } else if (!mixed(c)) {
     int rc = run_cycle<double>(c, c->h64, norm_out, nullptr);
@@ -508,6 +580,14 @@ int run_outer(adafac_ctx* c) {
 
 // FP32_REFINED: inner_k FP32 cycles on A e = r from e = 0; the correction stays pending.
 int run_inner(adafac_ctx* c) {
+  if (c->adaptive) {
+    for (int j = 0; j < c->opts.inner_k; ++j) {
+      int rc = run_adapt_cycle<float>(c, c->ad32, c->ad_rts32, c->scratch_norm);
+      if (rc) return rc;
+    }
+    c->e_pending = true;
+    return ADAFAC_OK;
+  }
   Hier<float>& H = c->h32;
   H.pending = false;
   for (int j = 0; j < c->opts.inner_k; ++j) {
@@ -563,7 +643,6 @@ int build_adaptive(adafac_ctx* c) {
   if (o.transfer != ADAFAC_TRANSFER_DLINEAR) return fail(c, ADAFAC_EUNSUPPORTED, "adaptive trees use d-linear transfers");
   if (o.damping != ADAFAC_DAMP_JAC && o.damping != ADAFAC_DAMP_NONE)
     return fail(c, ADAFAC_EUNSUPPORTED, "adaptive trees support adAFAC-Jac and plain additive damping");
-  if (o.precision != ADAFAC_PREC_FP64) return fail(c, ADAFAC_EUNSUPPORTED, "adaptive trees run in FP64");
   if (c->L <= c->lmin) return fail(c, ADAFAC_EINVAL, "an adaptive tree needs l_max > l_min");
   int first = c->L;
   for (const RefineSpec& r : c->refine) first = std::min(first, r.level);
@@ -582,8 +661,12 @@ int build_adaptive(adafac_ctx* c) {
   u.eps = c->eps;
   m = build_host_ops(u, 0, o.omega);
   if (!m.empty()) return fail(c, ADAFAC_EINVAL, m);
-  for (int i = 0; i < 5; ++i) c->ad_rts.m[i] = u.rt_m[i];
+  for (int i = 0; i < 5; ++i) {
+    c->ad_rts.m[i] = u.rt_m[i];
+    c->ad_rts32.m[i] = float(u.rt_m[i]);
+  }
   c->ad_rts.scale = u.rt_scale;
+  c->ad_rts32.scale = float(u.rt_scale);
   for (int l = c->lmin; l < c->ops.k; ++l) c->at.lev[l].dg = u.lev[l].dg;   // uniform levels: full box
   c->ops.lev = std::move(u.lev);     // kept for host_operator queries of the uniform part
   c->ops.rtilde = u.rtilde;
@@ -597,6 +680,12 @@ int bind_adaptive(adafac_ctx* c) {
   const int d = c->dim, L = c->L;
   HIPCHK(c, hipMemcpyAsync(c->ad_eps, c->ops.eps.data(), sizeof(double) * c->ops.eps.size(), hipMemcpyHostToDevice,
                            c->stream));
+  const bool mp = mixed(c);
+  if (mp) {
+    std::vector<float> e32(c->ops.eps.begin(), c->ops.eps.end());
+    HIPCHK(c, hipMemcpyAsync(c->ad_eps32, e32.data(), sizeof(float) * e32.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
   const int nL = ipow3(L) + 1;
   for (int l = c->lmin; l <= L; ++l) {
     const AdaptHostLevel& H = c->at.lev[l];
@@ -630,6 +719,12 @@ int bind_adaptive(adafac_ctx* c) {
     if (!A.fem)
       HIPCHK(c, hipMemcpyAsync(const_cast<double*>(A.dg), H.dg.data(), sizeof(double) * H.dg.size(),
                                hipMemcpyHostToDevice, c->stream));
+    std::vector<float> dg32;
+    if (mp && !A.fem) {
+      dg32.assign(H.dg.begin(), H.dg.end());
+      HIPCHK(c, hipMemcpyAsync(const_cast<float*>(c->ad32[l].dg), dg32.data(), sizeof(float) * dg32.size(),
+                               hipMemcpyHostToDevice, c->stream));
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));   // host vectors go out of scope
   }
   return ADAFAC_OK;
@@ -638,7 +733,7 @@ int bind_adaptive(adafac_ctx* c) {
 // Composite FE function at every vertex of the finest lattice (host, from the level boxes).
 int adaptive_finest(adafac_ctx* c, double* out) {
   const int d = c->dim, L = c->L, lmin = c->lmin;
-  int rc = adapt_hang(c);
+  int rc = flush(c);
   if (rc) return rc;
   std::vector<double> cur, up;
   int ncur = 0;
@@ -705,6 +800,7 @@ int adaptive_set(adafac_ctx* c, const double* u) {
     HIPCHK(c, hipMemcpyAsync(A.u, box.data(), sizeof(double) * box.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
   }
+  c->e_pending = false;
   return adapt_hang(c);
 }
 
@@ -897,6 +993,7 @@ int adafac_bind(adafac_ctx* c, void* ws, size_t bytes, void* stream) {
   if (c->adaptive) {
     int rc = bind_adaptive(c);
     if (rc) return rc;
+    c->e_pending = false;
     c->ncyc = 0;
     c->r0 = -1.0;
     c->bound = true;
@@ -1043,8 +1140,9 @@ int adafac_get_level(adafac_ctx* c, int level, int which, double* out, size_t n)
       case 4: src = A.S; break;
       default: return fail(c, ADAFAC_EINVAL, "which: 0 (u), 1 (b), 4 (S) on adaptive trees");
     }
+    if (mixed(c) && which != 0) return fail(c, ADAFAC_ESTATE, "FP32_REFINED keeps only u in FP64 on a tree");
     if (which == 0) {
-      int rc = adapt_hang(c);
+      int rc = flush(c);
       if (rc) return rc;
     }
     const AdaptHostLevel& H = c->at.lev[level];
@@ -1260,8 +1358,8 @@ int adafac_regrid(adafac_ctx* c, void* ws, size_t bytes) {
   if (!ready(c) || !c->adaptive || !c->next_ready) return fail(c, ADAFAC_ESTATE, "adafac_regrid_prepare first");
   if (!ws || bytes < c->next_need) return fail(c, ADAFAC_ENOMEM, "workspace too small: need " + std::to_string(c->next_need));
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(c, ADAFAC_EINVAL, "workspace not 256-byte aligned");
-  // the old tree: hanging values current, then a view of all its levels
-  int rc = adapt_hang(c);
+  // the old tree: pending correction added, hanging values current, then a view of its levels
+  int rc = flush(c);
   if (rc) return rc;
   AdaptTreeView O{};
   O.lmin = c->lmin;

@@ -134,3 +134,37 @@ def test_transfer_keeps_the_composite_function_where_both_trees_resolve_it():
     # them: wherever the new tree is at least as fine as the old one, the two agree
     fine_both = T1.dof[4] & T2.dof[4]
     assert np.abs(F1[fine_both] - F2[fine_both]).max() == 0.0
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_defect_correction_with_fp64_inner_cycles_is_the_plain_iteration(d):
+    # the cycle is linear in (u, b): k cycles on A e = r from e = 0 added to u give the k-th
+    # iterate of the plain iteration started at u
+    T = disk_tree(eps=inp.eps_blocks(2, 2, 2.0, seed=14)) if d == 2 else \
+        disk_tree(L=3, lu=2, d=3, radius=0.15, eps=inp.eps_blocks(3, 1, 2.0, seed=15))
+    f = inp.rhs(d, T.L, seed=16)
+    k, steps = 3, 4
+    its = []
+    U, hist = adaptive.defect_correction(T, f, k, 0.0, steps, inner_dtype=np.float64, iterates=its)
+    Up, hp = adaptive.solve(T, f, k * steps + 1)
+    assert len(hist) == steps + 1
+    for n in range(steps + 1):
+        assert abs(hist[n][0] - hp[n * k][0]) <= 1e-11 * hp[0][0], n
+    Fd, Fp = adaptive.finest_values(T, U), adaptive.finest_values(T, adaptive.solve(T, f, k * steps)[0])
+    assert np.abs(Fd - Fp).max() <= 1e-11 * np.abs(Fp).max()
+
+
+def test_defect_correction_with_fp32_inner_cycles_reaches_fp64_accuracy():
+    T = disk_tree(eps=inp.eps_blocks(2, 2, 1.0, seed=17))
+    f = inp.rhs(2, 4, seed=18)
+    A, b, pos, lev, Psi, C = adaptive.dense_system(T, f)
+    ustar = np.linalg.solve(A, b)
+    U, hist = adaptive.defect_correction(T, f, 4, 1e-12, 100, inner_dtype=np.float32)
+    assert hist[-1][0] / hist[0][0] <= 1e-12          # far below FP32 resolution
+    u = adaptive.to_composite(T, U)
+    assert np.linalg.norm(u - ustar) <= 1e-9 * np.linalg.norm(ustar)
+    # the inner arrays really are FP32: a single outer step is off from FP64 by FP32 rounding
+    _, h32 = adaptive.defect_correction(T, f, 4, 0.0, 1, inner_dtype=np.float32)
+    _, h64 = adaptive.defect_correction(T, f, 4, 0.0, 1, inner_dtype=np.float64)
+    gap = abs(h32[1][0] - h64[1][0]) / h64[0][0]
+    assert 1e-10 < gap < 1e-4
