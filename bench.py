@@ -165,12 +165,14 @@ def serving(Server, torch, n_req, loads, budget_gb, max_cycles, log=None, **serv
 
 
 def adaptive_workloads(Solver, torch, log=None):
-    """The two adaptive-spacetree workloads (FP64, d-linear transfers, adAFAC-Jac):
+    """The two adaptive-spacetree workloads (d-linear transfers, adAFAC-Jac):
     2D disk: 9x9 eps blocks 10^U(0,3), uniform to level 2, disk r = 0.25 refined to level 6,
     f ~ U(-1,1); timed cycles and a solve to 1e-8.
     3D moving Gaussian: 27^3 eps blocks 10^U(0,4), uniform to level 3, source of width 0.05 at a
     seeded centre, cells meeting the ball of radius 3 sigma refined to level 6, the tree
-    re-refined every 5 cycles as the centre moves by 0.03; cycle and regrid times."""
+    re-refined as the centre moves by 0.03 (every 5 cycles in FP64, every 2 outer steps of 4
+    FP32 cycles in FP32_REFINED); cycle and regrid times, then a solve to 1e-8 from zero on the
+    last tree.  us_per_cycle of FP32_REFINED is per inner cycle, the outer FP64 step included."""
     import numpy as np
     import adafac_inputs as inp
     out = {}
@@ -199,30 +201,46 @@ def adaptive_workloads(Solver, torch, log=None):
     sigma = 0.05
     centres = inp.moving_source(seed=23, steps=4, d=3)
     eps3 = inp.eps_blocks(3, 3, 4.0, seed=24)
-    s = Solver(3, 1, 6, {"gaussian": (centres[0], sigma, 1.0)}, eps_blocks=eps3, ball=(centres[0], 3 * sigma, 3))
-    dofs0 = s.dofs_per_cycle()
-    cyc, reg = [], []
-    for k, c in enumerate(centres):
-        if k:
+    for prec, steps in (("fp64", 5), ("fp32_refined", 2)):
+        k = 4 if prec == "fp32_refined" else 1
+        s = Solver(3, 1, 6, {"gaussian": (centres[0], sigma, 1.0)}, eps_blocks=eps3, ball=(centres[0], 3 * sigma, 3),
+                   precision=prec, inner_k=4)
+        dofs0 = s.dofs_per_cycle()
+        cyc, reg = [], []
+        for j, c in enumerate(centres):
+            if j:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s.regrid(c, 3 * sigma, 3)
+                torch.cuda.synchronize()
+                reg.append(time.perf_counter() - t0)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            s.regrid(c, 3 * sigma, 3)
+            s.cycle(steps)
             torch.cuda.synchronize()
-            reg.append(time.perf_counter() - t0)
+            cyc.append((time.perf_counter() - t0) / (steps * k))
+        h = s.residuals()
+        rel_moving = h[-1][0] / h[0][0]
+        # time to solution on the last tree from zero
+        s.set_solution(np.zeros(s.nvert))
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s.cycle(5)
+        t1 = time.perf_counter()
+        n = s.solve(1e-8, 3000)
         torch.cuda.synchronize()
-        cyc.append((time.perf_counter() - t0) / 5)
-    h = s.residuals()
-    out["moving_gaussian_3d_l6"] = {
-        "dofs_per_cycle_first_tree": dofs0, "composite_dofs_last_tree": s.composite_dofs(),
-        "us_per_cycle": float(np.mean(cyc[1:])) * 1e6, "regrid_ms": float(np.mean(reg)) * 1e3,
-        "regrids": len(reg), "cycles": 5 * len(centres), "rel_residual_last": h[-1][0] / h[0][0],
-        "precision": "fp64 (FP32-inner cycles are not available on adaptive trees)"}
-    s.close()
-    if log:
-        log(f"adaptive 3D moving Gaussian: {np.mean(cyc[1:]) * 1e6:.1f} us/cycle, regrid {np.mean(reg) * 1e3:.1f} ms")
+        ts = time.perf_counter() - t1
+        hs = s.residuals()
+        key = "moving_gaussian_3d_l6" + ("" if prec == "fp64" else "_fp32_refined")
+        out[key] = {
+            "precision": prec, "inner_k": k if k > 1 else None,
+            "dofs_per_cycle_first_tree": dofs0, "composite_dofs_last_tree": s.composite_dofs(),
+            "us_per_cycle": float(np.mean(cyc[1:])) * 1e6, "regrid_ms": float(np.mean(reg)) * 1e3,
+            "regrids": len(reg), "cycles": steps * k * len(centres), "rel_residual_moving": rel_moving,
+            "solve_1e-8_steps": n, "solve_1e-8_cycles": n * k, "solve_1e-8_ms": ts * 1e3,
+            "solve_rel_residual": hs[-1][0] / hs[0][0]}
+        s.close()
+        if log:
+            log(f"adaptive 3D moving Gaussian {prec}: {np.mean(cyc[1:]) * 1e6:.1f} us/cycle, "
+                f"regrid {np.mean(reg) * 1e3:.1f} ms, solve {n} steps {ts * 1e3:.1f} ms")
     return out
 
 

@@ -29,7 +29,8 @@ struct AdaptLevelT {
   int fem;                  // 1: Q1 operator from eps blocks; 0: stored diagonal (uniform Galerkin level)
   int nb, bs;               // eps blocks per axis, cells per block along an axis
   const T* eps;             // nb^d blocks, nullptr: eps = 1
-  const T* dg;              // stored diagonal over the box when !fem
+  T* dg;                    // diagonal at the dofs (uploaded on Galerkin levels, set-up kernel otherwise)
+  T* wc;                    // per box cell: eps_c h^(d-2) on leaf cells, 0 elsewhere (set-up kernel)
   const uint8_t* vcls;      // per box vertex
   const uint8_t* leaf;      // per box cell: 0 = no cell, 1 = leaf cell, 2 = refined cell
   T* bleaf;                 // lumped load of the level's leaf cells (inner form: the outer defect)
@@ -92,12 +93,22 @@ template <typename T>
 hipError_t launch_ad_down(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>* C, hipStream_t s);
 template <typename T>
 hipError_t launch_ad_update(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>* F, hipStream_t s);
+// once per tree, after the classes, leaf flags and (Galerkin levels) diagonals are uploaded
+template <typename T>
+hipError_t launch_ad_setup(int d, const AdaptLevelT<T>& L, hipStream_t s);
 hipError_t launch_ad_transfer(int d, const AdaptLevel& A, int scale, const AdaptTreeView& O, hipStream_t s);
 // FP32 inner form: bleaf32 = float(bb), the composite residual of the FP64 iterate at its
 // composite dofs (the inner loads), inner iterate e = 0
 hipError_t launch_ad_to_inner(int d, const AdaptLevel& A, const AdaptLevelT<float>& E, hipStream_t s);
 // u += e at every dof (composite dofs and their coarse copies)
 hipError_t launch_ad_accumulate(int d, const AdaptLevel& A, const AdaptLevelT<float>& E, hipStream_t s);
-constexpr int kAdaptNormBlocks = 256;   // norm partial blocks per level
+#ifndef ADAFAC_AD_UP_MAX_BLOCKS
+#define ADAFAC_AD_UP_MAX_BLOCKS 4096
+#endif
+constexpr int kAdaptNormBlocks = ADAFAC_AD_UP_MAX_BLOCKS;   // most blocks (norm partial slots) of an up launch
+hipError_t launch_ad_norm_finalize(const double* partials, int n, double* out, hipStream_t s);
+unsigned adapt_up_blocks(long box_vertices);     // blocks of an up launch without a finer level
+unsigned adapt_up_blocks_f(long box_vertices);   // with one
+constexpr long kAdaptMaxBox = (1L << 31) - 1;   // vertices (and cells) of one level's box
 
 }  // namespace adafac

@@ -108,6 +108,7 @@ struct adafac_ctx {
   AdaptHost at;
   RtSep<double> ad_rts{};
   std::vector<AdaptLevel> ad;           // device views by level
+  std::vector<size_t> ad_part;          // first norm-partial slot of each level's up launch
   double* ad_eps = nullptr;
   std::vector<AdaptLevelT<float>> ad32; // FP32_REFINED: inner cycles on the defect equation
   RtSep<float> ad_rts32{};
@@ -426,7 +427,8 @@ size_t layout_adaptive_tree(adafac_ctx* c, const AdaptHost& t, char* base) {
     const size_t nv = H.nverts(), ncell = H.ncells();
     A.vcls = reinterpret_cast<uint8_t*>(take(nv));
     A.leaf = reinterpret_cast<uint8_t*>(take(ncell));
-    if (!A.fem) A.dg = reinterpret_cast<double*>(take(sizeof(double) * nv));
+    A.dg = reinterpret_cast<double*>(take(sizeof(double) * nv));
+    A.wc = reinterpret_cast<double*>(take(sizeof(double) * ncell));
     A.bleaf = reinterpret_cast<double*>(take(sizeof(double) * nv));
     A.u = reinterpret_cast<double*>(take(sizeof(double) * nv));
     A.bb = reinterpret_cast<double*>(take(sizeof(double) * nv));
@@ -449,7 +451,8 @@ size_t layout_adaptive_tree(adafac_ctx* c, const AdaptHost& t, char* base) {
     E.eps = unit ? nullptr : eps32;
     E.vcls = A.vcls;
     E.leaf = A.leaf;
-    if (!E.fem) E.dg = reinterpret_cast<float*>(take(sizeof(float) * nv));
+    E.dg = reinterpret_cast<float*>(take(sizeof(float) * nv));
+    E.wc = reinterpret_cast<float*>(take(sizeof(float) * ncell));
     E.bleaf = reinterpret_cast<float*>(take(sizeof(float) * nv));
     E.u = reinterpret_cast<float*>(take(sizeof(float) * nv));
     E.bb = reinterpret_cast<float*>(take(sizeof(float) * nv));
@@ -457,13 +460,21 @@ size_t layout_adaptive_tree(adafac_ctx* c, const AdaptHost& t, char* base) {
     E.s = reinterpret_cast<float*>(take(sizeof(float) * nv));
     E.S = reinterpret_cast<float*>(take(sizeof(float) * nv));
   }
-  const size_t npart = size_t(kAdaptNormBlocks) * (c->L - c->lmin + 1);
+  // norm partials: one slot per block of each level's up launch, levels packed
+  std::vector<size_t> part(c->L + 1, 0);
+  size_t npart = 0;
+  for (int l = c->lmin; l <= c->L; ++l) {
+    part[l] = npart;
+    const long nb = long(t.lev[l].nverts());
+    npart += l < c->L ? adapt_up_blocks_f(nb) : adapt_up_blocks(nb);
+  }
   double* partials = reinterpret_cast<double*>(take(sizeof(double) * 2 * npart));
   double* norms = reinterpret_cast<double*>(take(sizeof(double) * 2 * kMaxHist));
   double* scratch = reinterpret_cast<double*>(take(sizeof(double) * 2));
   double* norm0 = reinterpret_cast<double*>(take(sizeof(double) * 2));
   if (base) {
     c->ad = std::move(ad);
+    c->ad_part = std::move(part);
     c->ad_eps = eps;
     c->ad32 = std::move(ad32);
     c->ad_eps32 = eps32;
@@ -509,8 +520,8 @@ int run_adapt_cycle(adafac_ctx* c, const std::vector<AdaptLevelT<T>>& ad, const 
   if ((rc = record_stop(c))) return rc;
   for (int l = L; l >= lmin; --l)
     HIPCHK(c, launch_ad_up<T>(d, ad[l], l < L ? &ad[l + 1] : nullptr, rts, omega, omega_t, o.damping, 0,
-                              c->partials + 2 * size_t(kAdaptNormBlocks) * (l - lmin), c->stream));
-  HIPCHK(c, launch_norm_finalize(c->partials, int(c->npartials), norm_out, c->stream));
+                              c->partials + 2 * c->ad_part[l], c->stream));
+  HIPCHK(c, launch_ad_norm_finalize(c->partials, int(c->npartials), norm_out, c->stream));
   for (int l = lmin; l <= L; ++l)
     HIPCHK(c, launch_ad_down<T>(d, ad[l], l > lmin ? &ad[l - 1] : nullptr, c->stream));
   for (int l = L; l >= lmin; --l)
@@ -533,9 +544,8 @@ int run_adapt_outer_mixed(adafac_ctx* c, double* norm_out) {
   if ((rc = record_stop(c))) return rc;
   for (int l = L; l >= lmin; --l)
     HIPCHK(c, launch_ad_up<double>(d, c->ad[l], l < L ? &c->ad[l + 1] : nullptr, c->ad_rts, 0.0, 0.0,
-                                   c->opts.damping, 1, c->partials + 2 * size_t(kAdaptNormBlocks) * (l - lmin),
-                                   c->stream));
-  HIPCHK(c, launch_norm_finalize(c->partials, int(c->npartials), norm_out, c->stream));
+                                   c->opts.damping, 1, c->partials + 2 * c->ad_part[l], c->stream));
+  HIPCHK(c, launch_ad_norm_finalize(c->partials, int(c->npartials), norm_out, c->stream));
   for (int l = lmin; l <= L; ++l) HIPCHK(c, launch_ad_to_inner(d, c->ad[l], c->ad32[l], c->stream));
   return ADAFAC_OK;
 }
@@ -651,6 +661,9 @@ int build_adaptive(adafac_ctx* c) {
     return fail(c, ADAFAC_EINVAL, "coefficient blocks finer than the first refined level of the tree");
   std::string m = build_adapt_tree(c->at, c->dim, c->lmin, c->L, c->refine, c->ball_c, c->ball_r, c->ball_from);
   if (!m.empty()) return fail(c, ADAFAC_EINVAL, m);
+  for (int l = c->lmin; l <= c->L; ++l)
+    if (c->at.lev[l].nverts() > size_t(kAdaptMaxBox))
+      return fail(c, ADAFAC_EUNSUPPORTED, "a level's bounding box exceeds 2^31 - 1 vertices");
   // uniform hierarchy up to max(k, lmin + 1): R~ factors and Galerkin diagonals below level k
   HostOps u;
   u.dim = c->dim;
@@ -726,6 +739,10 @@ int bind_adaptive(adafac_ctx* c) {
                                hipMemcpyHostToDevice, c->stream));
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));   // host vectors go out of scope
+  }
+  for (int l = c->lmin; l <= L; ++l) {
+    HIPCHK(c, launch_ad_setup<double>(d, c->ad[l], c->stream));
+    if (mp) HIPCHK(c, launch_ad_setup<float>(d, c->ad32[l], c->stream));
   }
   return ADAFAC_OK;
 }
@@ -1338,6 +1355,9 @@ int adafac_regrid_prepare(adafac_ctx* c, const double* centre, double radius, in
   for (int a = 0; a < c->dim; ++a) cc[a] = centre[a];
   std::string m = build_adapt_tree(c->at_next, c->dim, c->lmin, c->L, {}, cc, radius, l_from);
   if (!m.empty()) return fail(c, ADAFAC_EINVAL, m);
+  for (int l = c->lmin; l <= c->L; ++l)
+    if (c->at_next.lev[l].nverts() > size_t(kAdaptMaxBox))
+      return fail(c, ADAFAC_EUNSUPPORTED, "a level's bounding box exceeds 2^31 - 1 vertices");
   // the uniform levels below the coefficient blocks are those of the current tree
   for (int l = c->lmin; l < c->ops.k; ++l) c->at_next.lev[l].dg = c->at.lev[l].dg;
   if (f) c->f_next.assign(f, f + n);

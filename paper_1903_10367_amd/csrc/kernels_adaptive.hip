@@ -1,6 +1,6 @@
 // gfx950 kernels of the adAFAC cycle on adaptive spacetrees (ragged levels with hanging
 // vertices; Sec. 2.1, 2.3, 2.4; eq. (adaFACx) / Algorithm 1 over the generating system).
-// One thread per vertex of a level's box.  Per cycle:
+// One thread per vertex of a level's box (grid-stride; box indices fit 31 bits).  Per cycle:
 //   hang    hanging vertices take the d-linear interpolation of the next coarser level
 //   leaf    residual of the level's leaf cells (element-wise Q1, lumped load)
 //   up      finest to coarsest: b_l = r^leaf_l + R b_{l+1} (the level hats tested against the
@@ -19,6 +19,11 @@ namespace adafac {
 namespace {
 
 constexpr int NTA = 256;
+
+// Grid-stride over the box: at any time the whole grid works on one contiguous window of it,
+// so the rows and planes a stencil reads are shared through the caches.  (One contiguous
+// eighth of the box per XCD, for L2 locality, measured slower for every kernel here.)
+#define AD_LOOP(i, nb) for (unsigned i = blockIdx.x * NTA + threadIdx.x; i < (nb); i += gridDim.x * NTA)
 
 template <int D, typename L>
 __device__ __forceinline__ long vidx(const L& A, int x, int y, int z) {
@@ -41,15 +46,31 @@ __device__ __forceinline__ long cidx(const L& A, int cx, int cy, int cz) {
 }
 
 template <int D, typename L>
-__device__ __forceinline__ long nbox(const L& A) {
-  return long(A.mx) * A.my * (D == 3 ? A.mz : 1);
+__device__ __forceinline__ unsigned nbox(const L& A) {
+  return unsigned(A.mx) * unsigned(A.my) * unsigned(D == 3 ? A.mz : 1);
+}
+
+// box-relative coordinates of box vertex i (32-bit division: the host keeps boxes below 2^31)
+template <int D, typename L>
+__device__ __forceinline__ void box_coords(const L& A, unsigned i, int& bx, int& by, int& bz) {
+  const unsigned mx = unsigned(A.mx), q = i / mx;
+  bx = int(i - q * mx);
+  if (D == 3) {
+    const unsigned my = unsigned(A.my), r = q / my;
+    by = int(q - r * my);
+    bz = int(r);
+  } else {
+    by = int(q);
+    bz = 0;
+  }
 }
 
 template <int D, typename L>
-__device__ __forceinline__ void coords(const L& A, long i, int& x, int& y, int& z) {
-  x = A.ox + int(i % A.mx);
-  y = A.oy + int((i / A.mx) % A.my);
-  z = D == 3 ? A.oz + int(i / (long(A.mx) * A.my)) : 0;
+__device__ __forceinline__ void coords(const L& A, unsigned i, int& x, int& y, int& z) {
+  box_coords<D>(A, i, x, y, z);
+  x += A.ox;
+  y += A.oy;
+  z += D == 3 ? A.oz : 0;
 }
 
 template <typename T>
@@ -83,8 +104,7 @@ __device__ __forceinline__ T interp(const AdaptLevelT<T>& C, const T* v, int x, 
 
 // Q1 diagonal at a dof (all 2^d cells exist): kref h^(d-2) sum of the cells' eps
 template <int D, typename T>
-__device__ __forceinline__ T diag_at(const AdaptLevelT<T>& A, long i, int x, int y, int z) {
-  if (!A.fem) return A.dg[i];
+__device__ __forceinline__ T fem_diag(const AdaptLevelT<T>& A, int x, int y, int z) {
   T es = T(0);
 #pragma unroll
   for (int e = 0; e < (1 << D); ++e) {
@@ -104,8 +124,8 @@ __device__ __forceinline__ T kref(int i, int j) {
 
 template <int D, typename T>
 __global__ void __launch_bounds__(NTA) k_ad_hang(AdaptLevelT<T> A, AdaptLevelT<T> C) {
-  const long nb = nbox<D>(A);
-  for (long i = long(blockIdx.x) * NTA + threadIdx.x; i < nb; i += long(gridDim.x) * NTA) {
+  const unsigned nb = nbox<D>(A);
+  AD_LOOP(i, nb) {
     if (!(A.vcls[i] & kHang)) continue;
     int x, y, z;
     coords<D>(A, i, x, y, z);
@@ -113,32 +133,95 @@ __global__ void __launch_bounds__(NTA) k_ad_hang(AdaptLevelT<T> A, AdaptLevelT<T
   }
 }
 
+// Set-up of a level (once per tree): the leaf-cell weights eps_c h^(d-2) (zero on cells that
+// are not leaves) and, on levels with the Q1 operator, the diagonal at the dofs.
 template <int D, typename T>
-__global__ void __launch_bounds__(NTA) k_ad_leaf(AdaptLevelT<T> A) {
-  const long nb = nbox<D>(A);
-  const int n = A.n;
-  for (long i = long(blockIdx.x) * NTA + threadIdx.x; i < nb; i += long(gridDim.x) * NTA) {
+__global__ void __launch_bounds__(NTA) k_ad_setup(AdaptLevelT<T> A) {
+  const unsigned cmx = unsigned(A.mx - 1), cmy = unsigned(A.my - 1);
+  const unsigned nc = cmx * cmy * unsigned(D == 3 ? A.mz - 1 : 1);
+  AD_LOOP(c, nc) {
+    const unsigned q = c / cmx;
+    const int cx = A.ox + int(c - q * cmx);
+    const int cy = A.oy + int(D == 3 ? q % cmy : q);
+    const int cz = D == 3 ? A.oz + int(q / cmy) : 0;
+    A.wc[c] = A.leaf[c] == 1 ? eps_of(A, cx, cy, cz, D) * A.hdm2 : T(0);
+  }
+  if (!A.fem) return;
+  const unsigned nb = nbox<D>(A);
+  AD_LOOP(i, nb) {
     int x, y, z;
     coords<D>(A, i, x, y, z);
+    A.dg[i] = (A.vcls[i] & kDof) ? fem_diag<D>(A, x, y, z) : T(0);
+  }
+}
+
+// Leaf residual at a vertex whose 3^d neighbours lie in the box: the 2^d cell weights folded
+// into the coefficients of the 3^d neighbours (the zero entries of the reference element drop
+// out at compile time).
+template <int D, typename T>
+__device__ __forceinline__ T leaf_inner(const AdaptLevelT<T>& A, unsigned i, int bx, int by, int bz, T r) {
+  const long cmx = A.mx - 1, cmy = A.my - 1;
+  const long c0 = (long(D == 3 ? bz - 1 : 0) * cmy + (by - 1)) * cmx + (bx - 1);
+  T w[1 << D];
+#pragma unroll
+  for (int e = 0; e < (1 << D); ++e)
+    w[e] = A.wc[c0 + (e & 1) + ((e >> 1) & 1) * cmx + (D == 3 ? ((e >> 2) & 1) * cmx * cmy : 0)];
+  const long sy = A.mx, sz = long(A.mx) * A.my;
+  constexpr int NO = D == 2 ? 9 : 27;
+#pragma unroll
+  for (int o = 0; o < NO; ++o) {
+    const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = D == 3 ? o / 9 - 1 : 0;
+    T cf = T(0);
+    bool any = false;
+#pragma unroll
+    for (int e = 0; e < (1 << D); ++e) {
+      // cell e has lower corner v - 1 + e; its corner j sits at offset e + j - 1 from v
+      const int jx = ox + 1 - (e & 1), jy = oy + 1 - ((e >> 1) & 1), jz = D == 3 ? oz + 1 - ((e >> 2) & 1) : 0;
+      if (jx < 0 || jx > 1 || jy < 0 || jy > 1 || jz < 0 || jz > 1) continue;
+      const T k = kref<D, T>(e ^ ((1 << D) - 1), jx | (jy << 1) | (jz << 2));
+      if (k == T(0)) continue;
+      cf += k * w[e];
+      any = true;
+    }
+    if (any) r -= cf * A.u[long(i) + ox + oy * sy + oz * sz];
+  }
+  return r;
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(NTA) k_ad_leaf(AdaptLevelT<T> A) {
+  const unsigned nb = nbox<D>(A);
+  const int n = A.n;
+  const int cmx = A.mx - 1, cmy = A.my - 1, cmz = D == 3 ? A.mz - 1 : 1;
+  AD_LOOP(i, nb) {
+    int bx, by, bz;
+    box_coords<D>(A, i, bx, by, bz);
+    const int x = A.ox + bx, y = A.oy + by, z = D == 3 ? A.oz + bz : 0;
     T r = T(0);
+    // vertices of no existing cell (class 0, interior) carry no leaf cell and no load
     const bool inter = x > 0 && x < n && y > 0 && y < n && (D == 2 || (z > 0 && z < n));
-    if (inter) {
+    if (inter && (A.vcls[i] & (kDof | kHang))) {
       r = A.bleaf[i];
+      if (bx >= 1 && bx < cmx && by >= 1 && by < cmy && (D == 2 || (bz >= 1 && bz < cmz))) {
+        r = leaf_inner<D>(A, i, bx, by, bz, r);
+      } else {
 #pragma unroll
-      for (int e = 0; e < (1 << D); ++e) {
-        // cell with lower corner (cx, cy, cz); this vertex is its corner iw
-        const int ax = e & 1, ay = (e >> 1) & 1, az = (e >> 2) & 1;
-        const int cx = x - ax, cy = y - ay, cz = D == 3 ? z - az : 0;
-        const long c = cidx<D>(A, cx, cy, cz);
-        if (c < 0 || A.leaf[c] != 1) continue;
-        const int iw = ax | (ay << 1) | (az << 2);
-        T sum = T(0);
+        for (int e = 0; e < (1 << D); ++e) {
+          // cell with lower corner v - 1 + e (box-relative); this vertex is its corner iw
+          const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+          const int cx = bx - 1 + ex, cy = by - 1 + ey, cz = D == 3 ? bz - 1 + ez : 0;
+          if (cx < 0 || cx >= cmx || cy < 0 || cy >= cmy || cz < 0 || cz >= cmz) continue;
+          const T wv = A.wc[(long(cz) * cmy + cy) * cmx + cx];
+          if (wv == T(0)) continue;
+          const int iw = e ^ ((1 << D) - 1);
+          T sum = T(0);
 #pragma unroll
-        for (int j = 0; j < (1 << D); ++j) {
-          const long k = vidx<D>(A, cx + (j & 1), cy + ((j >> 1) & 1), cz + ((j >> 2) & 1));
-          sum += kref<D, T>(iw, j) * A.u[k];
+          for (int j = 0; j < (1 << D); ++j) {
+            const long k = (long(cz + ((j >> 2) & 1)) * A.my + (cy + ((j >> 1) & 1))) * A.mx + (cx + (j & 1));
+            sum += kref<D, T>(iw, j) * A.u[k];
+          }
+          r -= wv * sum;
         }
-        r -= eps_of(A, cx, cy, cz, D) * A.hdm2 * sum;
       }
     }
     A.bb[i] = r;
@@ -148,70 +231,175 @@ __global__ void __launch_bounds__(NTA) k_ad_leaf(AdaptLevelT<T> A) {
 template <typename T>
 __device__ __forceinline__ T wl(int o) { return o == 0 ? T(1) : (o == 1 || o == -1) ? T(2.0 / 3.0) : T(1.0 / 3.0); }
 
+template <typename T>
+__device__ __forceinline__ T sel5(const RtSep<T>& r, int o) {
+  return o == -2 ? r.m[0] : o == -1 ? r.m[1] : o == 0 ? r.m[2] : o == 1 ? r.m[3] : r.m[4];
+}
+
+// R~ weight of fine offset o: scale sum_a delta(o_a) prod_{b != a} m(o_b) (selects, not an
+// indexed load: the factors stay in registers)
 template <int D, typename T>
-__global__ void __launch_bounds__(NTA) k_ad_up(AdaptLevelT<T> A, AdaptLevelT<T> F, int has_f, RtSep<T> rts,
-                                               T omega, T omega_t, int jac, int norms_only, double* partials) {
-  const long nb = nbox<D>(A);
+__device__ __forceinline__ T rt_weight(const RtSep<T>& rts, int ox, int oy, int oz) {
+  const T mx = sel5(rts, ox), my = sel5(rts, oy);
+  T wt;
+  if (D == 2) {
+    wt = (ox == 0 ? my : T(0)) + (oy == 0 ? mx : T(0));
+  } else {
+    const T mz = sel5(rts, oz);
+    wt = (ox == 0 ? my * mz : T(0)) + (oy == 0 ? mx * mz : T(0)) + (oz == 0 ? mx * my : T(0));
+  }
+  return rts.scale * wt;
+}
+
+// One plane (fixed oz) of the 5^d fine neighbourhood at fixed offsets from k: the d-linear
+// restriction weights wl(ox) wl(oy) of hh and bb, and the R~ terms.  pa collects the terms
+// with ox = 0 or oy = 0 (factor m(oz) applied by the caller), pc those with oz = 0 (CENTRE).
+template <typename T>
+__device__ __forceinline__ T wl_sel(int o) {
+  return o == 0 ? T(1) : (o == 1 || o == -1) ? T(2.0 / 3.0) : T(1.0 / 3.0);
+}
+
+// Per vertex, after the restrictions from the finer level: the hanging-only accumulation, the
+// composite residual (norms), b_l and the correction c - c~ at the dofs.
+template <typename T, int MODE>
+__device__ __forceinline__ void up_finish(const AdaptLevelT<T>& A, unsigned i, uint8_t cls, T rl, T Rh, T Rb, T Rt,
+                                          int has_f, T omega, T omega_t, double& ssum, double& smax) {
+  const T acch = rl + Rh;
+  A.hh[i] = (cls & kHang) ? acch : T(0);
+  if (cls & kComp) {
+    const double a = double(acch);
+    ssum += double(A.hd) * a * a;
+    smax = fmax(smax, fabs(a));
+  }
+  if (MODE == 0) {
+    // the composite residual in place of the leaf residual (same index, read before)
+    A.bb[i] = (cls & kComp) ? acch : T(0);
+    return;
+  }
+  const T acc = rl + Rb;
+  A.bb[i] = acc;
+  T sv = T(0);
+  if (cls & kDof) {
+    const T dg = A.dg[i];
+    sv = omega * acc / dg;
+    if (MODE == 2 && has_f) sv -= omega_t * Rt / dg;
+  }
+  A.s[i] = sv;
+}
+
+// MODE: 0 composite residual only (norms_only), 1 plain additive, 2 adAFAC-Jac.
+// The finest level (no finer level to restrict from): one thread per vertex.
+template <int D, typename T, int MODE>
+__global__ void __launch_bounds__(NTA) k_ad_up(AdaptLevelT<T> A, T omega, T omega_t, double* partials) {
+  const unsigned nb = nbox<D>(A);
   double ssum = 0.0, smax = 0.0;
-  for (long i = long(blockIdx.x) * NTA + threadIdx.x; i < nb; i += long(gridDim.x) * NTA) {
-    const uint8_t cls = A.vcls[i];
-    const T rl = A.bb[i];
-    T Rb = T(0), Rh = T(0), Rt = T(0);
-    int x, y, z;
-    coords<D>(A, i, x, y, z);
-    if (has_f && (cls & (kDof | kHang))) {
-      for (int oz = (D == 3 ? -2 : 0); oz <= (D == 3 ? 2 : 0); ++oz)
-        for (int oy = -2; oy <= 2; ++oy)
+  AD_LOOP(i, nb) {
+    up_finish<T, MODE>(A, i, A.vcls[i], A.bb[i], T(0), T(0), T(0), 0, omega, omega_t, ssum, smax);
+  }
+  block_norm_partials(ssum, smax, partials);
+}
+
+// Levels with a finer level: five waves per group of 64 coarse vertices, wave w gathering the
+// fine plane oz = w - 2 (3D) or row oy = w - 2 (2D) of every vertex's 5^d neighbourhood; wave
+// 0 adds the other waves' partial sums in a fixed order and finishes the vertices.  Five times
+// the lanes of one thread per vertex, for the small levels whose gathers are latency bound.
+constexpr int NTU = 320;
+
+template <int D, typename T, int MODE>
+__global__ void __launch_bounds__(NTU) k_ad_up_f(AdaptLevelT<T> A, AdaptLevelT<T> F, RtSep<T> rts, T omega,
+                                                 T omega_t, double* partials) {
+  __shared__ T sh[3][4][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int o2 = wave - 2;                 // oz in 3D, oy in 2D
+  const unsigned nb = nbox<D>(A);
+  const unsigned ngroups = (nb + 63) / 64;
+  double ssum = 0.0, smax = 0.0;
+  for (unsigned g = blockIdx.x; g < ngroups; g += gridDim.x) {
+    const unsigned i = g * 64 + lane;
+    const uint8_t cls = i < nb ? A.vcls[i] : uint8_t(0);
+    T Rh = T(0), Rb = T(0), Rt = T(0);
+    if (cls & (kDof | kHang)) {
+      int x, y, z;
+      coords<D>(A, i, x, y, z);
+      const int fx = 3 * x - F.ox, fy = 3 * y - F.oy, fz = D == 3 ? 3 * z - F.oz : 0;
+      const bool tdof = MODE == 2 && (cls & kDof);
+      const int oz = D == 3 ? o2 : 0;
+      const T wz = D == 3 ? wl_sel<T>(oz) : T(1);
+      const T mz = D == 3 ? sel5(rts, oz) : T(1);
+      if (fx >= 2 && fx + 2 < F.mx && fy >= 2 && fy + 2 < F.my && (D == 2 || (fz >= 2 && fz + 2 < F.mz))) {
+        const long k0 = (long(fz) * F.my + fy) * F.mx + fx, sy = F.mx, sz = long(F.mx) * F.my;
+        const int ylo = D == 3 ? -2 : o2, yhi = D == 3 ? 2 : o2;
+#pragma unroll 1
+        for (int oy = ylo; oy <= yhi; ++oy) {
+          const long kr = k0 + oz * sz + oy * sy;
+          const T* hh = F.hh + kr;
+          T hr = T(0);
+#pragma unroll
+          for (int ox = -2; ox <= 2; ++ox) hr += wl<T>(ox) * hh[ox];
+          const T wyz = wl_sel<T>(oy) * wz;
+          Rh += wyz * hr;
+          if (MODE == 0) continue;
+          const T* bb = F.bb + kr;
+          T fb[5], br = T(0);
+#pragma unroll
+          for (int ox = -2; ox <= 2; ++ox) {
+            fb[ox + 2] = bb[ox];
+            br += wl<T>(ox) * fb[ox + 2];
+          }
+          Rb += wyz * br;
+          if (MODE != 2 || !tdof) continue;
+          // R~ over fine dofs: rows through the centre line use the whole row, others one tap
+          const uint8_t* vc = F.vcls + kr;
+          const T my = sel5(rts, oy);
+          T rt = ((vc[0] & kDof) ? fb[2] : T(0)) * my * mz;
+          if (oy == 0 || (D == 3 && oz == 0)) {
+            T fm = T(0);
+#pragma unroll
+            for (int ox = -2; ox <= 2; ++ox) fm += rts.m[ox + 2] * ((vc[ox] & kDof) ? fb[ox + 2] : T(0));
+            if (oy == 0) rt += fm * mz;
+            if (D == 3 && oz == 0) rt += fm * my;
+          }
+          Rt += rts.scale * rt;
+        }
+      } else {
+        const int ylo = D == 3 ? -2 : o2, yhi = D == 3 ? 2 : o2;
+        for (int oy = ylo; oy <= yhi; ++oy)
           for (int ox = -2; ox <= 2; ++ox) {
             const long k = vidx<D>(F, 3 * x + ox, 3 * y + oy, 3 * z + oz);
             if (k < 0) continue;
-            const T w = wl<T>(ox) * wl<T>(oy) * (D == 3 ? wl<T>(oz) : T(1));
+            const T w = wl<T>(ox) * wl_sel<T>(oy) * wz;
             Rh += w * F.hh[k];
-            if (norms_only) continue;
+            if (MODE == 0) continue;
             const T fb = F.bb[k];
             Rb += w * fb;
-            if (jac && (cls & kDof) && (F.vcls[k] & kDof)) {
-              // R~ = scale sum_a delta(o_a) prod_{b != a} m(o_b)
-              T wt;
-              if (D == 2) {
-                wt = (ox == 0 ? rts.m[oy + 2] : T(0)) + (oy == 0 ? rts.m[ox + 2] : T(0));
-              } else {
-                wt = (ox == 0 ? rts.m[oy + 2] * rts.m[oz + 2] : T(0)) + (oy == 0 ? rts.m[ox + 2] * rts.m[oz + 2] : T(0)) +
-                     (oz == 0 ? rts.m[ox + 2] * rts.m[oy + 2] : T(0));
-              }
-              Rt += rts.scale * wt * fb;
-            }
+            if (MODE == 2) Rt += rt_weight<D>(rts, ox, oy, oz) * ((tdof && (F.vcls[k] & kDof)) ? fb : T(0));
           }
+      }
     }
-    const T acch = rl + Rh;
-    A.hh[i] = (cls & kHang) ? acch : T(0);
-    if (cls & kComp) {
-      const double a = double(acch);
-      ssum += double(A.hd) * a * a;
-      smax = fmax(smax, fabs(a));
+    if (wave > 0) {
+      sh[0][wave - 1][lane] = Rh;
+      sh[1][wave - 1][lane] = Rb;
+      sh[2][wave - 1][lane] = Rt;
     }
-    if (norms_only) {
-      // the composite residual in place of the leaf residual (same index, read above)
-      A.bb[i] = (cls & kComp) ? acch : T(0);
-      continue;
+    __syncthreads();
+    if (wave == 0 && i < nb) {
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        Rh += sh[0][w][lane];
+        Rb += sh[1][w][lane];
+        Rt += sh[2][w][lane];
+      }
+      up_finish<T, MODE>(A, i, cls, A.bb[i], Rh, Rb, Rt, 1, omega, omega_t, ssum, smax);
     }
-    const T acc = rl + Rb;
-    A.bb[i] = acc;
-    T sv = T(0);
-    if (cls & kDof) {
-      const T dg = diag_at<D>(A, i, x, y, z);
-      sv = omega * acc / dg;
-      if (jac && has_f) sv -= omega_t * Rt / dg;
-    }
-    A.s[i] = sv;
+    __syncthreads();
   }
   block_norm_partials(ssum, smax, partials);
 }
 
 template <int D, typename T>
 __global__ void __launch_bounds__(NTA) k_ad_down(AdaptLevelT<T> A, AdaptLevelT<T> C, int has_c) {
-  const long nb = nbox<D>(A);
-  for (long i = long(blockIdx.x) * NTA + threadIdx.x; i < nb; i += long(gridDim.x) * NTA) {
+  const unsigned nb = nbox<D>(A);
+  AD_LOOP(i, nb) {
     const uint8_t cls = A.vcls[i];
     T S = T(0);
     if (cls & (kDof | kHang)) {
@@ -228,8 +416,8 @@ __global__ void __launch_bounds__(NTA) k_ad_down(AdaptLevelT<T> A, AdaptLevelT<T
 
 template <int D, typename T>
 __global__ void __launch_bounds__(NTA) k_ad_update(AdaptLevelT<T> A, AdaptLevelT<T> F, int has_f) {
-  const long nb = nbox<D>(A);
-  for (long i = long(blockIdx.x) * NTA + threadIdx.x; i < nb; i += long(gridDim.x) * NTA) {
+  const unsigned nb = nbox<D>(A);
+  AD_LOOP(i, nb) {
     const uint8_t cls = A.vcls[i];
     if (cls & kComp) {
       A.u[i] += A.S[i];
@@ -283,8 +471,8 @@ __device__ double composite_at(const AdaptTreeView& O, int X, int Y, int Z) {
 // New level A of a regridded tree: every dof takes the old tree's composite function.
 template <int D>
 __global__ void __launch_bounds__(NTA) k_ad_transfer(AdaptLevel A, int scale, AdaptTreeView O) {
-  const long nb = nbox<D>(A);
-  for (long i = long(blockIdx.x) * NTA + threadIdx.x; i < nb; i += long(gridDim.x) * NTA) {
+  const unsigned nb = nbox<D>(A);
+  AD_LOOP(i, nb) {
     if (!(A.vcls[i] & kDof)) continue;
     int x, y, z;
     coords<D>(A, i, x, y, z);
@@ -296,8 +484,8 @@ __global__ void __launch_bounds__(NTA) k_ad_transfer(AdaptLevel A, int scale, Ad
 // iterate starts at zero.
 template <int D>
 __global__ void __launch_bounds__(NTA) k_ad_to_inner(AdaptLevel A, AdaptLevelT<float> E) {
-  const long nb = nbox<D>(A);
-  for (long i = long(blockIdx.x) * NTA + threadIdx.x; i < nb; i += long(gridDim.x) * NTA) {
+  const unsigned nb = nbox<D>(A);
+  AD_LOOP(i, nb) {
     E.bleaf[i] = float(A.bb[i]);
     E.u[i] = 0.f;
   }
@@ -305,17 +493,59 @@ __global__ void __launch_bounds__(NTA) k_ad_to_inner(AdaptLevel A, AdaptLevelT<f
 
 template <int D>
 __global__ void __launch_bounds__(NTA) k_ad_accumulate(AdaptLevel A, AdaptLevelT<float> E) {
-  const long nb = nbox<D>(A);
-  for (long i = long(blockIdx.x) * NTA + threadIdx.x; i < nb; i += long(gridDim.x) * NTA)
+  const unsigned nb = nbox<D>(A);
+  AD_LOOP(i, nb)
     if (A.vcls[i] & kDof) A.u[i] += double(E.u[i]);
 }
 
-unsigned grid_for(long nb) {
-  long g = (nb + NTA - 1) / NTA;
-  return unsigned(g < 8192 ? (g < 1 ? 1 : g) : 8192);
+unsigned blocks_of(long n, long per_block, long cap) {
+  long g = (n + per_block - 1) / per_block;
+  return unsigned(g < cap ? (g < 1 ? 1 : g) : cap);
 }
 
+unsigned grid_for(long nb) { return blocks_of(nb, NTA, 8192); }
+
 }  // namespace
+
+// Norms from the packed partials of all levels: one workgroup of 1024 lanes, fixed order.
+__global__ void __launch_bounds__(1024) k_ad_norm_finalize(const double* __restrict__ partials, int n,
+                                                            double* __restrict__ out) {
+  __shared__ double ss[16], sm[16];
+  double sv = 0.0, mv = 0.0;
+  for (int i = threadIdx.x; i < n; i += 1024) {
+    sv += partials[2 * i];
+    mv = fmax(mv, partials[2 * i + 1]);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    sv += __shfl_xor(sv, off);
+    mv = fmax(mv, __shfl_xor(mv, off));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    ss[threadIdx.x >> 6] = sv;
+    sm[threadIdx.x >> 6] = mv;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < 16; ++w) {
+      a += ss[w];
+      b = fmax(b, sm[w]);
+    }
+    out[0] = sqrt(a);
+    out[1] = b;
+  }
+}
+
+hipError_t launch_ad_norm_finalize(const double* partials, int n, double* out, hipStream_t s) {
+  k_ad_norm_finalize<<<1, 1024, 0, s>>>(partials, n, out);
+  return hipGetLastError();
+}
+
+unsigned adapt_up_blocks(long nb) { return blocks_of(nb, NTA, kAdaptNormBlocks); }
+
+// groups of 64 vertices per block of the five-wave up kernel
+unsigned adapt_up_blocks_f(long nb) { return blocks_of(nb, 64, kAdaptNormBlocks); }
 
 template <typename T>
 hipError_t launch_ad_hang(int d, const AdaptLevelT<T>& A, const AdaptLevelT<T>& C, hipStream_t s) {
@@ -337,11 +567,43 @@ template <typename T>
 hipError_t launch_ad_up(int d, const AdaptLevelT<T>& A, const AdaptLevelT<T>* F, const RtSep<T>& rts, T omega,
                         T omega_t, int damping, int norms_only, double* partials, hipStream_t s) {
   const AdaptLevelT<T> Fv = F ? *F : AdaptLevelT<T>{};
-  const int jac = damping == ADAFAC_DAMP_JAC;
-  if (d == 2)
-    k_ad_up<2, T><<<kAdaptNormBlocks, NTA, 0, s>>>(A, Fv, F ? 1 : 0, rts, omega, omega_t, jac, norms_only, partials);
-  else
-    k_ad_up<3, T><<<kAdaptNormBlocks, NTA, 0, s>>>(A, Fv, F ? 1 : 0, rts, omega, omega_t, jac, norms_only, partials);
+  const int mode = norms_only ? 0 : (damping == ADAFAC_DAMP_JAC ? 2 : 1);
+  const long nbv = long(A.mx) * A.my * (d == 3 ? A.mz : 1);
+  if (F) {
+    const unsigned gf = adapt_up_blocks_f(nbv);
+#define AD_UPF(DD, M) k_ad_up_f<DD, T, M><<<gf, NTU, 0, s>>>(A, Fv, rts, omega, omega_t, partials)
+    if (d == 2) {
+      if (mode == 0) AD_UPF(2, 0);
+      else if (mode == 1) AD_UPF(2, 1);
+      else AD_UPF(2, 2);
+    } else {
+      if (mode == 0) AD_UPF(3, 0);
+      else if (mode == 1) AD_UPF(3, 1);
+      else AD_UPF(3, 2);
+    }
+#undef AD_UPF
+    return hipGetLastError();
+  }
+  const unsigned g = adapt_up_blocks(nbv);
+#define AD_UP(DD, M) k_ad_up<DD, T, M><<<g, NTA, 0, s>>>(A, omega, omega_t, partials)
+  if (d == 2) {
+    if (mode == 0) AD_UP(2, 0);
+    else if (mode == 1) AD_UP(2, 1);
+    else AD_UP(2, 2);
+  } else {
+    if (mode == 0) AD_UP(3, 0);
+    else if (mode == 1) AD_UP(3, 1);
+    else AD_UP(3, 2);
+  }
+#undef AD_UP
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ad_setup(int d, const AdaptLevelT<T>& A, hipStream_t s) {
+  const long nb = long(A.mx) * A.my * (d == 3 ? A.mz : 1);
+  if (d == 2) k_ad_setup<2, T><<<grid_for(nb), NTA, 0, s>>>(A);
+  else k_ad_setup<3, T><<<grid_for(nb), NTA, 0, s>>>(A);
   return hipGetLastError();
 }
 
@@ -390,7 +652,8 @@ hipError_t launch_ad_accumulate(int d, const AdaptLevel& A, const AdaptLevelT<fl
   template hipError_t launch_ad_up<T>(int, const AdaptLevelT<T>&, const AdaptLevelT<T>*, const RtSep<T>&, T, T,  \
                                       int, int, double*, hipStream_t);                                            \
   template hipError_t launch_ad_down<T>(int, const AdaptLevelT<T>&, const AdaptLevelT<T>*, hipStream_t);          \
-  template hipError_t launch_ad_update<T>(int, const AdaptLevelT<T>&, const AdaptLevelT<T>*, hipStream_t);
+  template hipError_t launch_ad_update<T>(int, const AdaptLevelT<T>&, const AdaptLevelT<T>*, hipStream_t);      \
+  template hipError_t launch_ad_setup<T>(int, const AdaptLevelT<T>&, hipStream_t);
 ADAFAC_AD_INST(double)
 ADAFAC_AD_INST(float)
 
