@@ -1,5 +1,7 @@
 // Host set-up of adaptive spacetrees (Sec. 2.1): the ragged levels, their bounding boxes,
 // cell existence and refinement, and the vertex classes (dof, hanging, composite dof).
+// Every pass is linear in the box and split over host threads by z-planes (a regrid of a
+// level-6 3D tree touches about 10^7 cells and vertices per level).
 #include <algorithm>
 #include <cmath>
 #include <string>
@@ -39,7 +41,6 @@ std::string build_adapt_tree(AdaptHost& t, int d, int lmin, int L, const std::ve
     if (s.level < lmin || s.level >= L) return "refinement flags given for a level outside l_min..l_max-1";
     spec[s.level] = &s;
   }
-  auto vbox = [&](const AdaptHostLevel& A, int a) { return A.nc[a] + 1; };
   for (int l = lmin; l <= L; ++l) {
     AdaptHostLevel& A = t.lev[l];
     A.d = d;
@@ -76,83 +77,106 @@ std::string build_adapt_tree(AdaptHost& t, int d, int lmin, int L, const std::ve
         }
       }
       A.exists.assign(A.ncells(), 0);
-      for (int cz = 0; cz < A.nc[2]; ++cz)
-        for (int cy = 0; cy < A.nc[1]; ++cy)
-          for (int cx = 0; cx < A.nc[0]; ++cx) {
-            const int g[3] = {A.lo[0] + cx, A.lo[1] + cy, A.lo[2] + cz};
-            int pc[3];
-            for (int a = 0; a < 3; ++a) pc[a] = a < d ? g[a] / 3 - P.lo[a] : 0;
-            A.exists[(size_t(cz) * A.nc[1] + cy) * A.nc[0] + cx] =
-                P.refined[(size_t(pc[2]) * P.nc[1] + pc[1]) * P.nc[0] + pc[0]];
-          }
+      // every refined parent writes its 3^d children (parent planes own disjoint child planes)
+      const int zlo = d == 3 ? plo[2] : 0, zn = d == 3 ? phi[2] - plo[2] + 1 : 1;
+      parallel_ranges(size_t(zn), [&](size_t q0, size_t q1) {
+        for (size_t q = q0; q < q1; ++q) {
+          const int pz = zlo + int(q);
+          for (int py = plo[1]; py <= phi[1]; ++py)
+            for (int px = plo[0]; px <= phi[0]; ++px) {
+              if (!P.refined[(size_t(pz) * P.nc[1] + py) * P.nc[0] + px]) continue;
+              const int x0 = 3 * (P.lo[0] + px) - A.lo[0], y0 = 3 * (P.lo[1] + py) - A.lo[1];
+              const int z0 = d == 3 ? 3 * (P.lo[2] + pz) - A.lo[2] : 0;
+              for (int dz = 0; dz < (d == 3 ? 3 : 1); ++dz)
+                for (int dy = 0; dy < 3; ++dy)
+                  std::fill_n(&A.exists[(size_t(z0 + dz) * A.nc[1] + (y0 + dy)) * A.nc[0] + x0], 3, uint8_t(1));
+            }
+        }
+      });
     }
     A.refined.assign(A.ncells(), 0);
     if (l < L) {
       const double h = 1.0 / n;
-      for (int cz = 0; cz < A.nc[2]; ++cz)
-        for (int cy = 0; cy < A.nc[1]; ++cy)
-          for (int cx = 0; cx < A.nc[0]; ++cx) {
-            const size_t ci = (size_t(cz) * A.nc[1] + cy) * A.nc[0] + cx;
-            if (!A.exists[ci]) continue;
-            const int g[3] = {A.lo[0] + cx, A.lo[1] + cy, A.lo[2] + cz};
-            bool r = true;
-            if (spec[l]) {
-              size_t gi = size_t(g[0]) + size_t(n) * (size_t(g[1]) + (d == 3 ? size_t(n) * g[2] : 0));
-              r = spec[l]->flags[gi] != 0;
-            } else if (radius > 0.0 && l >= l_from) {
-              r = cell_meets_ball(d, g, h, centre, radius);
+      parallel_ranges(size_t(A.nc[2]), [&](size_t z0, size_t z1) {
+        for (int cz = int(z0); cz < int(z1); ++cz)
+          for (int cy = 0; cy < A.nc[1]; ++cy)
+            for (int cx = 0; cx < A.nc[0]; ++cx) {
+              const size_t ci = (size_t(cz) * A.nc[1] + cy) * A.nc[0] + cx;
+              if (!A.exists[ci]) continue;
+              const int g[3] = {A.lo[0] + cx, A.lo[1] + cy, A.lo[2] + cz};
+              bool r = true;
+              if (spec[l]) {
+                size_t gi = size_t(g[0]) + size_t(n) * (size_t(g[1]) + (d == 3 ? size_t(n) * g[2] : 0));
+                r = spec[l]->flags[gi] != 0;
+              } else if (radius > 0.0 && l >= l_from) {
+                r = cell_meets_ball(d, g, h, centre, radius);
+              }
+              A.refined[ci] = r ? 1 : 0;
             }
-            A.refined[ci] = r ? 1 : 0;
-          }
+      });
     }
   }
-  // vertex classes
-  for (int l = lmin; l <= L; ++l) {
+  // Vertex classes, finest level first: interior vertices with all 2^d cells of their level are
+  // dofs, with some of them hang; a dof is composite unless the next finer level has a dof at
+  // its position.
+  t.composite = 0;
+  const uint8_t full = uint8_t(1 << d);
+  for (int l = L; l >= lmin; --l) {
     AdaptHostLevel& A = t.lev[l];
     const int n = ipow3(l);
-    const int mx = vbox(A, 0), my = vbox(A, 1), mz = d == 3 ? vbox(A, 2) : 1;
-    A.vcls.assign(size_t(mx) * my * mz, 0);
-    for (int z = 0; z < mz; ++z)
-      for (int y = 0; y < my; ++y)
-        for (int x = 0; x < mx; ++x) {
-          const int g[3] = {A.lo[0] + x, A.lo[1] + y, d == 3 ? A.lo[2] + z : 0};
-          bool inter = true;
-          for (int a = 0; a < d; ++a) inter = inter && g[a] > 0 && g[a] < n;
-          int cnt = 0;
-          for (int e = 0; e < (1 << d); ++e) {
-            const int cx = x - 1 + (e & 1), cy = y - 1 + ((e >> 1) & 1), cz = d == 3 ? z - 1 + ((e >> 2) & 1) : 0;
-            if (cx < 0 || cy < 0 || cz < 0 || cx >= A.nc[0] || cy >= A.nc[1] || cz >= A.nc[2]) continue;
-            cnt += A.exists[(size_t(cz) * A.nc[1] + cy) * A.nc[0] + cx];
-          }
-          uint8_t c = 0;
-          if (inter && cnt == (1 << d)) c = kDof;
-          else if (inter && cnt > 0) c = kHang;
-          A.vcls[(size_t(z) * my + y) * mx + x] = c;
-        }
-  }
-  t.composite = 0;
-  for (int l = lmin; l <= L; ++l) {
-    AdaptHostLevel& A = t.lev[l];
-    const int mx = vbox(A, 0), my = vbox(A, 1), mz = d == 3 ? vbox(A, 2) : 1;
+    const int cx = A.nc[0], cy = A.nc[1], cz = A.nc[2];
+    const int mx = cx + 1, my = cy + 1, mz = d == 3 ? cz + 1 : 1;
     const AdaptHostLevel* F = l < L ? &t.lev[l + 1] : nullptr;
-    const int fx = F ? vbox(*F, 0) : 0, fy = F ? vbox(*F, 1) : 0, fz = F ? (d == 3 ? vbox(*F, 2) : 1) : 0;
-    for (int z = 0; z < mz; ++z)
-      for (int y = 0; y < my; ++y)
-        for (int x = 0; x < mx; ++x) {
-          uint8_t& c = A.vcls[(size_t(z) * my + y) * mx + x];
-          if (!(c & kDof)) continue;
-          bool finer = false;
-          if (F) {
-            const int X = 3 * (A.lo[0] + x) - F->lo[0], Y = 3 * (A.lo[1] + y) - F->lo[1];
-            const int Z = d == 3 ? 3 * (A.lo[2] + z) - F->lo[2] : 0;
-            if (X >= 0 && Y >= 0 && Z >= 0 && X < fx && Y < fy && Z < fz)
-              finer = (F->vcls[(size_t(Z) * fy + Y) * fx + X] & kDof) != 0;
-          }
-          if (!finer) {
-            c |= kComp;
-            ++t.composite;
+    const int fx = F ? F->nc[0] + 1 : 0, fy = F ? F->nc[1] + 1 : 0, fz = F ? (d == 3 ? F->nc[2] + 1 : 1) : 0;
+    const std::vector<uint8_t> zero(size_t(cx), 0);
+    A.vcls.assign(size_t(mx) * my * mz, 0);
+    std::vector<size_t> part(size_t(mz), 0);
+    parallel_ranges(size_t(mz), [&](size_t z0, size_t z1) {
+      for (int z = int(z0); z < int(z1); ++z) {
+        const int gz = d == 3 ? A.lo[2] + z : 1;
+        if (d == 3 && (gz <= 0 || gz >= n)) continue;
+        size_t k = 0;
+        for (int y = 0; y < my; ++y) {
+          const int gy = A.lo[1] + y;
+          if (gy <= 0 || gy >= n) continue;
+          // the (up to) 2^(d-1) cell rows around this vertex row; missing rows read as zero
+          const uint8_t* r[4];
+          int nr = 0;
+          for (int dz = (d == 3 ? -1 : 0); dz <= 0; ++dz)
+            for (int dy = -1; dy <= 0; ++dy) {
+              const int zz = z + dz, yy = y + dy;
+              const bool in = zz >= 0 && zz < cz && yy >= 0 && yy < cy;
+              r[nr++] = in ? &A.exists[(size_t(zz) * cy + yy) * cx] : zero.data();
+            }
+          uint8_t* out = &A.vcls[(size_t(z) * my + y) * mx];
+          for (int x = 0; x < mx; ++x) {
+            const int gx = A.lo[0] + x;
+            if (gx <= 0 || gx >= n) continue;
+            int cnt = 0;
+            for (int q = 0; q < nr; ++q) cnt += (x > 0 ? r[q][x - 1] : 0) + (x < cx ? r[q][x] : 0);
+            if (cnt == 0) continue;
+            if (cnt < full) {
+              out[x] = kHang;
+              continue;
+            }
+            uint8_t c = kDof;
+            bool finer = false;
+            if (F) {
+              const int X = 3 * gx - F->lo[0], Y = 3 * gy - F->lo[1], Z = d == 3 ? 3 * gz - F->lo[2] : 0;
+              if (X >= 0 && Y >= 0 && Z >= 0 && X < fx && Y < fy && Z < fz)
+                finer = (F->vcls[(size_t(Z) * fy + Y) * fx + X] & kDof) != 0;
+            }
+            if (!finer) {
+              c |= kComp;
+              ++k;
+            }
+            out[x] = c;
           }
         }
+        part[z] = k;
+      }
+    });
+    for (size_t k : part) t.composite += k;
   }
   return "";
 }

@@ -6,7 +6,9 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <algorithm>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "adafac_internal.hpp"
@@ -65,6 +67,22 @@ struct AdaptHost {
   std::vector<AdaptHostLevel> lev;             // indexed by level
   size_t composite = 0;                        // number of composite dofs
 };
+
+// f(lo, hi) over [0, n) on up to 16 host threads, one contiguous range each (host set-up of
+// boxes with 10^7 cells and vertices).
+template <class F>
+void parallel_ranges(size_t n, F&& f) {
+  unsigned nt = std::min(16u, std::max(1u, std::thread::hardware_concurrency()));
+  if (n < 2 || nt == 1) {
+    f(size_t(0), n);
+    return;
+  }
+  nt = unsigned(std::min<size_t>(nt, n));
+  std::vector<std::thread> th;
+  th.reserve(nt);
+  for (unsigned k = 0; k < nt; ++k) th.emplace_back([&f, n, nt, k] { f(n * k / nt, n * (k + 1) / nt); });
+  for (auto& t : th) t.join();
+}
 
 // Refinement flags of one level: over the full (3^l)^d cell lattice, C order (x fastest).
 struct RefineSpec {

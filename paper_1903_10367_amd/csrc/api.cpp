@@ -704,26 +704,30 @@ int bind_adaptive(adafac_ctx* c) {
     const AdaptHostLevel& H = c->at.lev[l];
     const AdaptLevel& A = c->ad[l];
     std::vector<uint8_t> leaf(H.ncells());   // cell classes: 0 none, 1 leaf, 2 refined
-    for (size_t i = 0; i < leaf.size(); ++i) leaf[i] = H.exists[i] ? (H.refined[i] ? 2 : 1) : 0;
+    parallel_ranges(leaf.size(), [&](size_t i0, size_t i1) {
+      for (size_t i = i0; i < i1; ++i) leaf[i] = H.exists[i] ? (H.refined[i] ? 2 : 1) : 0;
+    });
     // lumped load: m_v f_v, m_v = |leaf cells around v| h^d / 2^d, f sampled from the finest lattice
     std::vector<double> bl(H.nverts(), 0.0);
     const int s = ipow3(L - l);
     const double share = A.hd / double(1 << d);
-    for (int z = 0; z < A.mz; ++z)
-      for (int y = 0; y < A.my; ++y)
-        for (int x = 0; x < A.mx; ++x) {
-          const size_t i = (size_t(z) * A.my + y) * A.mx + x;
-          if (!(H.vcls[i] & (kDof | kHang))) continue;
-          int nleaf = 0;
-          for (int e = 0; e < (1 << d); ++e) {
-            const int cx = x - 1 + (e & 1), cy = y - 1 + ((e >> 1) & 1), cz = d == 3 ? z - 1 + ((e >> 2) & 1) : 0;
-            if (cx < 0 || cy < 0 || cz < 0 || cx >= H.nc[0] || cy >= H.nc[1] || cz >= H.nc[2]) continue;
-            nleaf += leaf[(size_t(cz) * H.nc[1] + cy) * H.nc[0] + cx] == 1;
+    parallel_ranges(size_t(A.mz), [&](size_t z0, size_t z1) {
+      for (int z = int(z0); z < int(z1); ++z)
+        for (int y = 0; y < A.my; ++y)
+          for (int x = 0; x < A.mx; ++x) {
+            const size_t i = (size_t(z) * A.my + y) * A.mx + x;
+            if (!(H.vcls[i] & (kDof | kHang))) continue;
+            int nleaf = 0;
+            for (int e = 0; e < (1 << d); ++e) {
+              const int cx = x - 1 + (e & 1), cy = y - 1 + ((e >> 1) & 1), cz = d == 3 ? z - 1 + ((e >> 2) & 1) : 0;
+              if (cx < 0 || cy < 0 || cz < 0 || cx >= H.nc[0] || cy >= H.nc[1] || cz >= H.nc[2]) continue;
+              nleaf += leaf[(size_t(cz) * H.nc[1] + cy) * H.nc[0] + cx] == 1;
+            }
+            if (!nleaf) continue;
+            const size_t gx = size_t(A.ox + x) * s, gy = size_t(A.oy + y) * s, gz = d == 3 ? size_t(A.oz + z) * s : 0;
+            bl[i] = nleaf * share * source_at(c, gx, gy, gz);
           }
-          if (!nleaf) continue;
-          const size_t gx = size_t(A.ox + x) * s, gy = size_t(A.oy + y) * s, gz = d == 3 ? size_t(A.oz + z) * s : 0;
-          bl[i] = nleaf * share * source_at(c, gx, gy, gz);
-        }
+    });
     HIPCHK(c, hipMemcpyAsync(const_cast<uint8_t*>(A.vcls), H.vcls.data(), H.vcls.size(), hipMemcpyHostToDevice,
                              c->stream));
     HIPCHK(c, hipMemcpyAsync(const_cast<uint8_t*>(A.leaf), leaf.data(), leaf.size(), hipMemcpyHostToDevice, c->stream));
@@ -1024,11 +1028,14 @@ int adafac_bind(adafac_ctx* c, void* ws, size_t bytes, void* stream) {
   std::vector<double> b(fl.nverts, 0.0);
   const double hd = std::pow(fl.h, d);
   const int nv = fl.nv;
-  for (int z = (d == 3 ? 1 : 0); z < (d == 3 ? nv - 1 : 1); ++z)
-    for (int y = 1; y < nv - 1; ++y) {
-      const size_t row = (size_t(z) * nv + y) * nv;
-      for (int x = 1; x < nv - 1; ++x) b[row + x] = hd * source_at(c, x, y, z);
-    }
+  const int z_lo = d == 3 ? 1 : 0, z_hi = d == 3 ? nv - 1 : 1;
+  parallel_ranges(size_t(z_hi - z_lo), [&](size_t q0, size_t q1) {
+    for (int z = z_lo + int(q0); z < z_lo + int(q1); ++z)
+      for (int y = 1; y < nv - 1; ++y) {
+        const size_t row = (size_t(z) * nv + y) * nv;
+        for (int x = 1; x < nv - 1; ++x) b[row + x] = hd * source_at(c, x, y, z);
+      }
+  });
   HIPCHK(c, hipMemcpyAsync(c->h64.bfine, b.data(), sizeof(double) * b.size(), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->h64.cur = c->h32.cur = 0;
