@@ -164,6 +164,34 @@ def serving(Server, torch, n_req, loads, budget_gb, max_cycles, log=None, **serv
     return out
 
 
+def copy_and_cold(s, torch, nbytes=2 << 30, reps=10, cold_cycles=20):
+    """Context for the roofline: (a) the rate of a plain device-to-device copy of 2 GiB on this
+    GPU (bytes read + written per second); (b) the finest-level sweep's average time when a
+    2 GiB copy runs before every cycle, which evicts u and b from the 256 MB Infinity Cache, so
+    that the sweep reads them from HBM."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    stream = s.stream
+    with torch.cuda.stream(stream):
+        dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record(stream)
+        e1.synchronize()
+        copy_gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+        s.set_kernel_timing(True)
+        for _ in range(cold_cycles):
+            dst.copy_(src)
+            s.cycle(1)
+        torch.cuda.synchronize()
+        ms, n = s.kernel_time()
+        s.set_kernel_timing(False)
+    del src, dst
+    return copy_gbs, ms / 1e3 / max(n, 1)
+
+
 def adaptive_workloads(Solver, torch, log=None):
     """The two adaptive-spacetree workloads (d-linear transfers, adAFAC-Jac):
     2D disk: 9x9 eps blocks 10^U(0,3), uniform to level 2, disk r = 0.25 refined to level 6,
@@ -298,6 +326,7 @@ def main():
     ksum_ms, nlaunch = s.kernel_time()
     s.set_kernel_timing(False)
     hist = s.residuals()
+    copy_gbs, cold = copy_and_cold(s, torch)
     s.close()
 
     value = dofs * args.steps / dt
@@ -340,7 +369,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_fine_sweep3d", "kernel_avg_us": kavg_s * 1e6,
-                     "algorithmic_bytes_per_launch": kbytes, "launches": nlaunch},
+                     "algorithmic_bytes_per_launch": kbytes, "launches": nlaunch,
+                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
+                     "kernel_avg_us_cold": cold * 1e6, "achieved_cold": kbytes / cold / 1e9,
+                     "frac_cold": kbytes / cold / 1e9 / HBM_PEAK_GBS},
         "solve_to_1e-8": solves,
     }
     if not args.no_adaptive:

@@ -102,11 +102,19 @@ template <typename T>
 hipError_t launch_ad_hang(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>& C, hipStream_t s);
 template <typename T>
 hipError_t launch_ad_leaf(int d, const AdaptLevelT<T>& L, hipStream_t s);
+// Levels with a finer level F (F must not be null; the finest level runs launch_ad_leaf_up).
 // norms_only: only the composite residual: norm partials, hh, and bb replaced by the composite
 // residual at composite dofs (zero elsewhere)
 template <typename T>
 hipError_t launch_ad_up(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>* F, const RtSep<T>& rts, T omega,
                         T omega_t, int damping, int norms_only, double* partials, hipStream_t s);
+// The finest level: leaf residual and up in one pass
+template <typename T>
+hipError_t launch_ad_leaf_up(int d, const AdaptLevelT<T>& L, T omega, T omega_t, int norms_only, double* partials,
+                             hipStream_t s);
+// The finest level: down and update in one pass (C: the next coarser level)
+template <typename T>
+hipError_t launch_ad_down_update(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>& C, hipStream_t s);
 template <typename T>
 hipError_t launch_ad_down(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>* C, hipStream_t s);
 template <typename T>

@@ -516,16 +516,17 @@ int run_adapt_cycle(adafac_ctx* c, const std::vector<AdaptLevelT<T>>& ad, const 
   int rc = adapt_hang_views(c, ad);
   if (rc) return rc;
   if ((rc = record_start(c))) return rc;
-  for (int l = lmin; l <= L; ++l) HIPCHK(c, launch_ad_leaf<T>(d, ad[l], c->stream));
+  for (int l = lmin; l < L; ++l) HIPCHK(c, launch_ad_leaf<T>(d, ad[l], c->stream));
+  HIPCHK(c, launch_ad_leaf_up<T>(d, ad[L], omega, omega_t, 0, c->partials + 2 * c->ad_part[L], c->stream));
   if ((rc = record_stop(c))) return rc;
-  for (int l = L; l >= lmin; --l)
-    HIPCHK(c, launch_ad_up<T>(d, ad[l], l < L ? &ad[l + 1] : nullptr, rts, omega, omega_t, o.damping, 0,
-                              c->partials + 2 * c->ad_part[l], c->stream));
+  for (int l = L - 1; l >= lmin; --l)
+    HIPCHK(c, launch_ad_up<T>(d, ad[l], &ad[l + 1], rts, omega, omega_t, o.damping, 0, c->partials + 2 * c->ad_part[l],
+                              c->stream));
   HIPCHK(c, launch_ad_norm_finalize(c->partials, int(c->npartials), norm_out, c->stream));
-  for (int l = lmin; l <= L; ++l)
+  for (int l = lmin; l < L; ++l)
     HIPCHK(c, launch_ad_down<T>(d, ad[l], l > lmin ? &ad[l - 1] : nullptr, c->stream));
-  for (int l = L; l >= lmin; --l)
-    HIPCHK(c, launch_ad_update<T>(d, ad[l], l < L ? &ad[l + 1] : nullptr, c->stream));
+  HIPCHK(c, launch_ad_down_update<T>(d, ad[L], ad[L - 1], c->stream));
+  for (int l = L - 1; l >= lmin; --l) HIPCHK(c, launch_ad_update<T>(d, ad[l], &ad[l + 1], c->stream));
   return ADAFAC_OK;
 }
 
@@ -540,11 +541,12 @@ int run_adapt_outer_mixed(adafac_ctx* c, double* norm_out) {
   int rc = adapt_accumulate(c);
   if (rc || (rc = adapt_hang(c))) return rc;
   if ((rc = record_start(c))) return rc;
-  for (int l = lmin; l <= L; ++l) HIPCHK(c, launch_ad_leaf<double>(d, c->ad[l], c->stream));
+  for (int l = lmin; l < L; ++l) HIPCHK(c, launch_ad_leaf<double>(d, c->ad[l], c->stream));
+  HIPCHK(c, launch_ad_leaf_up<double>(d, c->ad[L], 0.0, 0.0, 1, c->partials + 2 * c->ad_part[L], c->stream));
   if ((rc = record_stop(c))) return rc;
-  for (int l = L; l >= lmin; --l)
-    HIPCHK(c, launch_ad_up<double>(d, c->ad[l], l < L ? &c->ad[l + 1] : nullptr, c->ad_rts, 0.0, 0.0,
-                                   c->opts.damping, 1, c->partials + 2 * c->ad_part[l], c->stream));
+  for (int l = L - 1; l >= lmin; --l)
+    HIPCHK(c, launch_ad_up<double>(d, c->ad[l], &c->ad[l + 1], c->ad_rts, 0.0, 0.0, c->opts.damping, 1,
+                                   c->partials + 2 * c->ad_part[l], c->stream));
   HIPCHK(c, launch_ad_norm_finalize(c->partials, int(c->npartials), norm_out, c->stream));
   for (int l = lmin; l <= L; ++l) HIPCHK(c, launch_ad_to_inner(d, c->ad[l], c->ad32[l], c->stream));
   return ADAFAC_OK;

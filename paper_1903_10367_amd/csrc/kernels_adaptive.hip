@@ -188,46 +188,45 @@ __device__ __forceinline__ T leaf_inner(const AdaptLevelT<T>& A, unsigned i, int
   return r;
 }
 
+// Leaf residual at box vertex i of class dof or hanging (such vertices are interior).
+template <int D, typename T>
+__device__ __forceinline__ T leaf_residual(const AdaptLevelT<T>& A, unsigned i) {
+  const int cmx = A.mx - 1, cmy = A.my - 1, cmz = D == 3 ? A.mz - 1 : 1;
+  int bx, by, bz;
+  box_coords<D>(A, i, bx, by, bz);
+  T r = A.bleaf[i];
+  if (bx >= 1 && bx < cmx && by >= 1 && by < cmy && (D == 2 || (bz >= 1 && bz < cmz))) return leaf_inner<D>(A, i, bx, by, bz, r);
+#pragma unroll
+  for (int e = 0; e < (1 << D); ++e) {
+    // cell with lower corner v - 1 + e (box-relative); this vertex is its corner iw
+    const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+    const int cx = bx - 1 + ex, cy = by - 1 + ey, cz = D == 3 ? bz - 1 + ez : 0;
+    if (cx < 0 || cx >= cmx || cy < 0 || cy >= cmy || cz < 0 || cz >= cmz) continue;
+    const T wv = A.wc[(long(cz) * cmy + cy) * cmx + cx];
+    if (wv == T(0)) continue;
+    const int iw = e ^ ((1 << D) - 1);
+    T sum = T(0);
+#pragma unroll
+    for (int j = 0; j < (1 << D); ++j) {
+      const long k = (long(cz + ((j >> 2) & 1)) * A.my + (cy + ((j >> 1) & 1))) * A.mx + (cx + (j & 1));
+      sum += kref<D, T>(iw, j) * A.u[k];
+    }
+    r -= wv * sum;
+  }
+  return r;
+}
+
+// Vertices of class 0 (no existing cell, or the domain boundary) are never written: their
+// arrays hold the zeros of the workspace set-up, which is what every reader expects there.
 template <int D, typename T>
 __global__ void __launch_bounds__(NTA) k_ad_leaf(AdaptLevelT<T> A) {
   const unsigned nb = nbox<D>(A);
-  const int n = A.n;
-  const int cmx = A.mx - 1, cmy = A.my - 1, cmz = D == 3 ? A.mz - 1 : 1;
   AD_LOOP(i, nb) {
-    int bx, by, bz;
-    box_coords<D>(A, i, bx, by, bz);
-    const int x = A.ox + bx, y = A.oy + by, z = D == 3 ? A.oz + bz : 0;
-    T r = T(0);
-    // vertices of no existing cell (class 0, interior) carry no leaf cell and no load
-    const bool inter = x > 0 && x < n && y > 0 && y < n && (D == 2 || (z > 0 && z < n));
-    if (inter && (A.vcls[i] & (kDof | kHang))) {
-      r = A.bleaf[i];
-      if (bx >= 1 && bx < cmx && by >= 1 && by < cmy && (D == 2 || (bz >= 1 && bz < cmz))) {
-        r = leaf_inner<D>(A, i, bx, by, bz, r);
-      } else {
-#pragma unroll
-        for (int e = 0; e < (1 << D); ++e) {
-          // cell with lower corner v - 1 + e (box-relative); this vertex is its corner iw
-          const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
-          const int cx = bx - 1 + ex, cy = by - 1 + ey, cz = D == 3 ? bz - 1 + ez : 0;
-          if (cx < 0 || cx >= cmx || cy < 0 || cy >= cmy || cz < 0 || cz >= cmz) continue;
-          const T wv = A.wc[(long(cz) * cmy + cy) * cmx + cx];
-          if (wv == T(0)) continue;
-          const int iw = e ^ ((1 << D) - 1);
-          T sum = T(0);
-#pragma unroll
-          for (int j = 0; j < (1 << D); ++j) {
-            const long k = (long(cz + ((j >> 2) & 1)) * A.my + (cy + ((j >> 1) & 1))) * A.mx + (cx + (j & 1));
-            sum += kref<D, T>(iw, j) * A.u[k];
-          }
-          r -= wv * sum;
-        }
-      }
-    }
-    A.bb[i] = r;
+    if (A.vcls[i] & (kDof | kHang)) A.bb[i] = leaf_residual<D>(A, i);
   }
 }
 
+// d-linear restriction weight of fine offset o (|o| <= 2)
 template <typename T>
 __device__ __forceinline__ T wl(int o) { return o == 0 ? T(1) : (o == 1 || o == -1) ? T(2.0 / 3.0) : T(1.0 / 3.0); }
 
@@ -254,11 +253,6 @@ __device__ __forceinline__ T rt_weight(const RtSep<T>& rts, int ox, int oy, int 
 // One plane (fixed oz) of the 5^d fine neighbourhood at fixed offsets from k: the d-linear
 // restriction weights wl(ox) wl(oy) of hh and bb, and the R~ terms.  pa collects the terms
 // with ox = 0 or oy = 0 (factor m(oz) applied by the caller), pc those with oz = 0 (CENTRE).
-template <typename T>
-__device__ __forceinline__ T wl_sel(int o) {
-  return o == 0 ? T(1) : (o == 1 || o == -1) ? T(2.0 / 3.0) : T(1.0 / 3.0);
-}
-
 // Per vertex, after the restrictions from the finer level: the hanging-only accumulation, the
 // composite residual (norms), b_l and the correction c - c~ at the dofs.
 template <typename T, int MODE>
@@ -288,13 +282,16 @@ __device__ __forceinline__ void up_finish(const AdaptLevelT<T>& A, unsigned i, u
 }
 
 // MODE: 0 composite residual only (norms_only), 1 plain additive, 2 adAFAC-Jac.
-// The finest level (no finer level to restrict from): one thread per vertex.
+// The finest level (no finer level to restrict from): its leaf residual and the per-vertex tail
+// in one pass, one thread per vertex.
 template <int D, typename T, int MODE>
-__global__ void __launch_bounds__(NTA) k_ad_up(AdaptLevelT<T> A, T omega, T omega_t, double* partials) {
+__global__ void __launch_bounds__(NTA) k_ad_leaf_up(AdaptLevelT<T> A, T omega, T omega_t, double* partials) {
   const unsigned nb = nbox<D>(A);
   double ssum = 0.0, smax = 0.0;
   AD_LOOP(i, nb) {
-    up_finish<T, MODE>(A, i, A.vcls[i], A.bb[i], T(0), T(0), T(0), 0, omega, omega_t, ssum, smax);
+    const uint8_t cls = A.vcls[i];
+    if (!(cls & (kDof | kHang))) continue;
+    up_finish<T, MODE>(A, i, cls, leaf_residual<D>(A, i), T(0), T(0), T(0), 0, omega, omega_t, ssum, smax);
   }
   block_norm_partials(ssum, smax, partials);
 }
@@ -324,7 +321,7 @@ __global__ void __launch_bounds__(NTU) k_ad_up_f(AdaptLevelT<T> A, AdaptLevelT<T
       const int fx = 3 * x - F.ox, fy = 3 * y - F.oy, fz = D == 3 ? 3 * z - F.oz : 0;
       const bool tdof = MODE == 2 && (cls & kDof);
       const int oz = D == 3 ? o2 : 0;
-      const T wz = D == 3 ? wl_sel<T>(oz) : T(1);
+      const T wz = D == 3 ? wl<T>(oz) : T(1);
       const T mz = D == 3 ? sel5(rts, oz) : T(1);
       if (fx >= 2 && fx + 2 < F.mx && fy >= 2 && fy + 2 < F.my && (D == 2 || (fz >= 2 && fz + 2 < F.mz))) {
         const long k0 = (long(fz) * F.my + fy) * F.mx + fx, sy = F.mx, sz = long(F.mx) * F.my;
@@ -336,7 +333,7 @@ __global__ void __launch_bounds__(NTU) k_ad_up_f(AdaptLevelT<T> A, AdaptLevelT<T
           T hr = T(0);
 #pragma unroll
           for (int ox = -2; ox <= 2; ++ox) hr += wl<T>(ox) * hh[ox];
-          const T wyz = wl_sel<T>(oy) * wz;
+          const T wyz = wl<T>(oy) * wz;
           Rh += wyz * hr;
           if (MODE == 0) continue;
           const T* bb = F.bb + kr;
@@ -367,7 +364,7 @@ __global__ void __launch_bounds__(NTU) k_ad_up_f(AdaptLevelT<T> A, AdaptLevelT<T
           for (int ox = -2; ox <= 2; ++ox) {
             const long k = vidx<D>(F, 3 * x + ox, 3 * y + oy, 3 * z + oz);
             if (k < 0) continue;
-            const T w = wl<T>(ox) * wl_sel<T>(oy) * wz;
+            const T w = wl<T>(ox) * wl<T>(oy) * wz;
             Rh += w * F.hh[k];
             if (MODE == 0) continue;
             const T fb = F.bb[k];
@@ -382,7 +379,7 @@ __global__ void __launch_bounds__(NTU) k_ad_up_f(AdaptLevelT<T> A, AdaptLevelT<T
       sh[2][wave - 1][lane] = Rt;
     }
     __syncthreads();
-    if (wave == 0 && i < nb) {
+    if (wave == 0 && (cls & (kDof | kHang))) {
 #pragma unroll
       for (int w = 0; w < 4; ++w) {
         Rh += sh[0][w][lane];
@@ -400,17 +397,29 @@ template <int D, typename T>
 __global__ void __launch_bounds__(NTA) k_ad_down(AdaptLevelT<T> A, AdaptLevelT<T> C, int has_c) {
   const unsigned nb = nbox<D>(A);
   AD_LOOP(i, nb) {
-    const uint8_t cls = A.vcls[i];
-    T S = T(0);
-    if (cls & (kDof | kHang)) {
-      S = A.s[i];
-      if (has_c) {
-        int x, y, z;
-        coords<D>(A, i, x, y, z);
-        S += interp<D>(C, C.S, x, y, z);
-      }
+    if (!(A.vcls[i] & (kDof | kHang))) continue;
+    T S = A.s[i];
+    if (has_c) {
+      int x, y, z;
+      coords<D>(A, i, x, y, z);
+      S += interp<D>(C, C.S, x, y, z);
     }
     A.S[i] = S;
+  }
+}
+
+// The finest level: S_L = (c - c~)_L + P S_{L-1}, and at its dofs (all composite) u += S_L.
+template <int D, typename T>
+__global__ void __launch_bounds__(NTA) k_ad_down_update(AdaptLevelT<T> A, AdaptLevelT<T> C) {
+  const unsigned nb = nbox<D>(A);
+  AD_LOOP(i, nb) {
+    const uint8_t cls = A.vcls[i];
+    if (!(cls & (kDof | kHang))) continue;
+    int x, y, z;
+    coords<D>(A, i, x, y, z);
+    const T S = A.s[i] + interp<D>(C, C.S, x, y, z);
+    A.S[i] = S;
+    if (cls & kComp) A.u[i] += S;
   }
 }
 
@@ -486,6 +495,7 @@ template <int D>
 __global__ void __launch_bounds__(NTA) k_ad_to_inner(AdaptLevel A, AdaptLevelT<float> E) {
   const unsigned nb = nbox<D>(A);
   AD_LOOP(i, nb) {
+    if (!(A.vcls[i] & (kDof | kHang))) continue;
     E.bleaf[i] = float(A.bb[i]);
     E.u[i] = 0.f;
   }
@@ -584,18 +594,28 @@ hipError_t launch_ad_up(int d, const AdaptLevelT<T>& A, const AdaptLevelT<T>* F,
 #undef AD_UPF
     return hipGetLastError();
   }
-  const unsigned g = adapt_up_blocks(nbv);
-#define AD_UP(DD, M) k_ad_up<DD, T, M><<<g, NTA, 0, s>>>(A, omega, omega_t, partials)
+  return hipErrorInvalidValue;   // the finest level runs launch_ad_leaf_up
+}
+
+template <typename T>
+hipError_t launch_ad_leaf_up(int d, const AdaptLevelT<T>& A, T omega, T omega_t, int norms_only, double* partials,
+                             hipStream_t s) {
+  const unsigned g = adapt_up_blocks(long(A.mx) * A.my * (d == 3 ? A.mz : 1));
   if (d == 2) {
-    if (mode == 0) AD_UP(2, 0);
-    else if (mode == 1) AD_UP(2, 1);
-    else AD_UP(2, 2);
+    if (norms_only) k_ad_leaf_up<2, T, 0><<<g, NTA, 0, s>>>(A, omega, omega_t, partials);
+    else k_ad_leaf_up<2, T, 1><<<g, NTA, 0, s>>>(A, omega, omega_t, partials);
   } else {
-    if (mode == 0) AD_UP(3, 0);
-    else if (mode == 1) AD_UP(3, 1);
-    else AD_UP(3, 2);
+    if (norms_only) k_ad_leaf_up<3, T, 0><<<g, NTA, 0, s>>>(A, omega, omega_t, partials);
+    else k_ad_leaf_up<3, T, 1><<<g, NTA, 0, s>>>(A, omega, omega_t, partials);
   }
-#undef AD_UP
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ad_down_update(int d, const AdaptLevelT<T>& A, const AdaptLevelT<T>& C, hipStream_t s) {
+  const long nb = long(A.mx) * A.my * (d == 3 ? A.mz : 1);
+  if (d == 2) k_ad_down_update<2, T><<<grid_for(nb), NTA, 0, s>>>(A, C);
+  else k_ad_down_update<3, T><<<grid_for(nb), NTA, 0, s>>>(A, C);
   return hipGetLastError();
 }
 
@@ -653,7 +673,9 @@ hipError_t launch_ad_accumulate(int d, const AdaptLevel& A, const AdaptLevelT<fl
                                       int, int, double*, hipStream_t);                                            \
   template hipError_t launch_ad_down<T>(int, const AdaptLevelT<T>&, const AdaptLevelT<T>*, hipStream_t);          \
   template hipError_t launch_ad_update<T>(int, const AdaptLevelT<T>&, const AdaptLevelT<T>*, hipStream_t);      \
-  template hipError_t launch_ad_setup<T>(int, const AdaptLevelT<T>&, hipStream_t);
+  template hipError_t launch_ad_setup<T>(int, const AdaptLevelT<T>&, hipStream_t);                              \
+  template hipError_t launch_ad_leaf_up<T>(int, const AdaptLevelT<T>&, T, T, int, double*, hipStream_t);          \
+  template hipError_t launch_ad_down_update<T>(int, const AdaptLevelT<T>&, const AdaptLevelT<T>&, hipStream_t);
 ADAFAC_AD_INST(double)
 ADAFAC_AD_INST(float)
 
