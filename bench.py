@@ -166,21 +166,26 @@ def serving(Server, torch, n_req, loads, budget_gb, max_cycles, log=None, **serv
 
 def copy_and_cold(s, torch, nbytes=2 << 30, reps=10, cold_cycles=20):
     """Context for the roofline: (a) the rate of a plain device-to-device copy of 2 GiB on this
-    GPU (bytes read + written per second); (b) the finest-level sweep's average time when a
-    2 GiB copy runs before every cycle, which evicts u and b from the 256 MB Infinity Cache, so
-    that the sweep reads them from HBM."""
+    GPU (bytes read + written per second), with the library's streaming copy kernel and with
+    hipMemcpy; (b) the finest-level sweep's average time when a 2 GiB copy runs before every
+    cycle, which evicts u and b from the 256 MB Infinity Cache, so that the sweep reads them
+    from HBM."""
+    from paper_1903_10367_amd import stream_copy
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
     dst = torch.empty_like(src)
     stream = s.stream
+    rates = {}
     with torch.cuda.stream(stream):
-        dst.copy_(src)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            dst.copy_(src)
-        e1.record(stream)
-        e1.synchronize()
-        copy_gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+        for name, fn in (("kernel", lambda: stream_copy(src, dst, stream)), ("memcpy", lambda: dst.copy_(src))):
+            fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            e1.synchronize()
+            rates[name] = 2 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+        copy_gbs = rates
         s.set_kernel_timing(True)
         for _ in range(cold_cycles):
             dst.copy_(src)
@@ -370,7 +375,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_fine_sweep3d", "kernel_avg_us": kavg_s * 1e6,
                      "algorithmic_bytes_per_launch": kbytes, "launches": nlaunch,
-                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
+                     "copy_gbs": copy_gbs["kernel"], "memcpy_gbs": copy_gbs["memcpy"],
+                     "frac_of_copy": achieved / copy_gbs["kernel"],
                      "kernel_avg_us_cold": cold * 1e6, "achieved_cold": kbytes / cold / 1e9,
                      "frac_cold": kbytes / cold / 1e9 / HBM_PEAK_GBS},
         "solve_to_1e-8": solves,

@@ -248,6 +248,16 @@ int adafac_kernel_time(adafac_ctx* ctx, double* total_ms, int* launches);
 void adafac_destroy(adafac_ctx* ctx);
 const char* adafac_last_error(const adafac_ctx* ctx);
 
+/* Reference streaming copy for roofline context (not part of the method): copies
+ * `bytes` from device memory src to device memory dst on `stream` (a hipStream_t;
+ * NULL = default stream) with 16-byte non-temporal loads and stores, 1024
+ * workgroups of 256 lanes striding over the buffers.  Its rate is the memory
+ * rate a plain copy reaches on this GPU, reported beside the sweep's.  src and
+ * dst: 16-byte aligned, non-overlapping, owned by the caller; bytes: a multiple
+ * of 16.  Asynchronous.  ADAFAC_EINVAL on a null pointer, misalignment or a
+ * size that is not a multiple of 16; ADAFAC_EDEVICE if the launch fails. */
+int adafac_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
+
 /* ------------------------------------------------------------------------
  * Request server: continuous batching of independent solves (the cycle of
  * Sec. 3.1 run to the stopping criterion of Sec. 5, one hierarchy per request).

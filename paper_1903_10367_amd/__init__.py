@@ -12,7 +12,7 @@ import numpy as np
 from . import _abi
 from ._abi import AdafacError, DAMPING, LEVEL_ARRAY, PRECISION, TRANSFER
 
-__all__ = ["Solver", "Server", "AdafacError", "lib"]
+__all__ = ["Solver", "Server", "AdafacError", "lib", "stream_copy"]
 
 lib = _abi.lib
 
@@ -25,6 +25,22 @@ def _check(L, ctx, rc):
 
 def _dptr(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def stream_copy(src, dst, stream=None):
+    """Reference streaming copy of device tensor src into dst (same number of bytes, 16-byte
+    aligned; roofline context, see adafac_stream_copy).  Runs on `stream` (default: torch's
+    current stream of src's device)."""
+    import torch
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or not (src.is_cuda and dst.is_cuda):
+        raise AdafacError(1, "stream_copy: two device tensors of the same size")
+    st = stream or torch.cuda.current_stream(src.device)
+    L = lib()
+    rc = L.adafac_stream_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes,
+                              C.c_void_p(st.cuda_stream))
+    if rc:
+        raise AdafacError(rc, "adafac_stream_copy: null, misaligned or not a multiple of 16 bytes")
 
 
 class Solver:

@@ -22,6 +22,7 @@ EXPORTS = [
     "adafac_regrid_prepare", "adafac_regrid", "adafac_set_rhs_gaussian",
     "adafac_server_default_cfg", "adafac_server_create", "adafac_server_submit", "adafac_server_step",
     "adafac_server_poll", "adafac_server_fetch", "adafac_server_destroy", "adafac_server_last_error",
+    "adafac_stream_copy",
 ]
 
 
@@ -103,6 +104,7 @@ def lib():
         "adafac_server_fetch": (C.c_int, [P, C.c_uint64, C.POINTER(C.c_double), C.c_size_t]),
         "adafac_server_destroy": (None, [P]),
         "adafac_server_last_error": (C.c_char_p, [P]),
+        "adafac_stream_copy": (C.c_int, [P, P, C.c_size_t, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

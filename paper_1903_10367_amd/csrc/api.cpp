@@ -27,6 +27,7 @@ template <typename T>
 hipError_t launch_prolong_add(int d, const LevelView<T>& F, const LevelView<T>& C, T* dst, const T* src,
                               const T* sub, hipStream_t s);
 hipError_t launch_norm_finalize(const double* partials, int n, double* out, hipStream_t s);
+hipError_t launch_stream_copy(const void* src, void* dst, size_t n16, hipStream_t s);
 hipError_t launch_accumulate(int d, const LevelView<float>& F, const LevelView<float>& C, double* u,
                              const float* e, const float* S, hipStream_t s);
 hipError_t launch_defect(int d, const LevelView<double>& F, const double* u, const double* b, float* r32,
@@ -1440,5 +1441,13 @@ void adafac_destroy(adafac_ctx* c) {
 }
 
 const char* adafac_last_error(const adafac_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int adafac_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
+  if (!src || !dst || bytes % 16 || reinterpret_cast<uintptr_t>(src) % 16 || reinterpret_cast<uintptr_t>(dst) % 16)
+    return ADAFAC_EINVAL;
+  if (bytes == 0) return ADAFAC_OK;
+  return launch_stream_copy(src, dst, bytes / 16, static_cast<hipStream_t>(stream)) == hipSuccess ? ADAFAC_OK
+                                                                                                 : ADAFAC_EDEVICE;
+}
 
 }  // extern "C"

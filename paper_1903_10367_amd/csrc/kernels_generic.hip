@@ -275,6 +275,18 @@ __global__ void __launch_bounds__(256) k_norm_finalize(const double* __restrict_
   }
 }
 
+// Reference streaming copy (roofline context): 16-byte non-temporal vectors, grid-stride.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+__global__ void __launch_bounds__(256) k_stream_copy(const dvec2* __restrict__ a, dvec2* __restrict__ b, size_t n) {
+  for (size_t i = size_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += size_t(gridDim.x) * 256)
+    __builtin_nontemporal_store(__builtin_nontemporal_load(&a[i]), &b[i]);
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, size_t n16, hipStream_t s) {
+  k_stream_copy<<<1024, 256, 0, s>>>(static_cast<const dvec2*>(src), static_cast<dvec2*>(dst), n16);
+  return hipGetLastError();
+}
+
 hipError_t launch_norm_finalize(const double* partials, int n, double* out, hipStream_t s) {
   k_norm_finalize<<<1, 256, 0, s>>>(partials, n, out);
   return hipGetLastError();
