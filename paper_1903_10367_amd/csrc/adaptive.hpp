@@ -123,6 +123,13 @@ hipError_t launch_ad_update(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>
 template <typename T>
 hipError_t launch_ad_setup(int d, const AdaptLevelT<T>& L, hipStream_t s);
 hipError_t launch_ad_transfer(int d, const AdaptLevel& A, int scale, const AdaptTreeView& O, hipStream_t s);
+// Gaussian source amp exp(-|x - c|^2 / (2 sigma^2)) (x first in c)
+struct GaussSource {
+  double c[3];
+  double sigma, amp;
+};
+// lumped leaf loads of a Gaussian source on level A (classes and cell bytes uploaded)
+hipError_t launch_ad_gauss_load(int d, const AdaptLevel& A, const GaussSource& g, hipStream_t s);
 // FP32 inner form: bleaf32 = float(bb), the composite residual of the FP64 iterate at its
 // composite dofs (the inner loads), inner iterate e = 0
 hipError_t launch_ad_to_inner(int d, const AdaptLevel& A, const AdaptLevelT<float>& E, hipStream_t s);

@@ -711,10 +711,11 @@ int bind_adaptive(adafac_ctx* c) {
       for (size_t i = i0; i < i1; ++i) leaf[i] = H.exists[i] ? (H.refined[i] ? 2 : 1) : 0;
     });
     // lumped load: m_v f_v, m_v = |leaf cells around v| h^d / 2^d, f sampled from the finest lattice
-    std::vector<double> bl(H.nverts(), 0.0);
+    // (a Gaussian source is evaluated on the device after the uploads)
+    std::vector<double> bl(c->src_gauss ? 0 : H.nverts(), 0.0);
     const int s = ipow3(L - l);
     const double share = A.hd / double(1 << d);
-    parallel_ranges(size_t(A.mz), [&](size_t z0, size_t z1) {
+    if (!c->src_gauss) parallel_ranges(size_t(A.mz), [&](size_t z0, size_t z1) {
       for (int z = int(z0); z < int(z1); ++z)
         for (int y = 0; y < A.my; ++y)
           for (int x = 0; x < A.mx; ++x) {
@@ -734,8 +735,13 @@ int bind_adaptive(adafac_ctx* c) {
     HIPCHK(c, hipMemcpyAsync(const_cast<uint8_t*>(A.vcls), H.vcls.data(), H.vcls.size(), hipMemcpyHostToDevice,
                              c->stream));
     HIPCHK(c, hipMemcpyAsync(const_cast<uint8_t*>(A.leaf), leaf.data(), leaf.size(), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(const_cast<double*>(A.bleaf), bl.data(), sizeof(double) * bl.size(), hipMemcpyHostToDevice,
-                             c->stream));
+    if (c->src_gauss) {
+      GaussSource g{{c->src_c[0], c->src_c[1], c->src_c[2]}, c->src_sigma, c->src_amp};
+      HIPCHK(c, launch_ad_gauss_load(d, A, g, c->stream));
+    } else {
+      HIPCHK(c, hipMemcpyAsync(const_cast<double*>(A.bleaf), bl.data(), sizeof(double) * bl.size(),
+                               hipMemcpyHostToDevice, c->stream));
+    }
     if (!A.fem)
       HIPCHK(c, hipMemcpyAsync(const_cast<double*>(A.dg), H.dg.data(), sizeof(double) * H.dg.size(),
                                hipMemcpyHostToDevice, c->stream));

@@ -489,6 +489,35 @@ __global__ void __launch_bounds__(NTA) k_ad_transfer(AdaptLevel A, int scale, Ad
   }
 }
 
+// Lumped load of a Gaussian source on a level: m_v f(x_v) with m_v = |leaf cells around v| h^d / 2^d
+// at dofs and hanging vertices (the set-up of the loads on the device, for the moving source).
+template <int D>
+__global__ void __launch_bounds__(NTA) k_ad_gauss_load(AdaptLevel A, GaussSource g) {
+  const unsigned nb = nbox<D>(A);
+  const int cmx = A.mx - 1, cmy = A.my - 1, cmz = D == 3 ? A.mz - 1 : 1;
+  const double share = A.hd / double(1 << D);
+  AD_LOOP(i, nb) {
+    if (!(A.vcls[i] & (kDof | kHang))) continue;
+    int bx, by, bz;
+    box_coords<D>(A, i, bx, by, bz);
+    int nleaf = 0;
+#pragma unroll
+    for (int e = 0; e < (1 << D); ++e) {
+      const int cx = bx - 1 + (e & 1), cy = by - 1 + ((e >> 1) & 1), cz = D == 3 ? bz - 1 + ((e >> 2) & 1) : 0;
+      if (cx < 0 || cx >= cmx || cy < 0 || cy >= cmy || cz < 0 || cz >= cmz) continue;
+      nleaf += A.leaf[(long(cz) * cmy + cy) * cmx + cx] == 1;
+    }
+    double r2 = 0.0;
+    const double px = (A.ox + bx) * A.h - g.c[0], py = (A.oy + by) * A.h - g.c[1];
+    r2 = px * px + py * py;
+    if (D == 3) {
+      const double pz = (A.oz + bz) * A.h - g.c[2];
+      r2 += pz * pz;
+    }
+    A.bleaf[i] = nleaf ? nleaf * share * g.amp * exp(-r2 / (2.0 * g.sigma * g.sigma)) : 0.0;
+  }
+}
+
 // FP32 inner form of defect correction: the inner load is the FP64 leaf residual, the inner
 // iterate starts at zero.
 template <int D>
@@ -649,6 +678,13 @@ hipError_t launch_ad_transfer(int d, const AdaptLevel& A, int scale, const Adapt
   const long nb = long(A.mx) * A.my * (d == 3 ? A.mz : 1);
   if (d == 2) k_ad_transfer<2><<<grid_for(nb), NTA, 0, s>>>(A, scale, O);
   else k_ad_transfer<3><<<grid_for(nb), NTA, 0, s>>>(A, scale, O);
+  return hipGetLastError();
+}
+
+hipError_t launch_ad_gauss_load(int d, const AdaptLevel& A, const GaussSource& g, hipStream_t s) {
+  const long nb = long(A.mx) * A.my * (d == 3 ? A.mz : 1);
+  if (d == 2) k_ad_gauss_load<2><<<grid_for(nb), NTA, 0, s>>>(A, g);
+  else k_ad_gauss_load<3><<<grid_for(nb), NTA, 0, s>>>(A, g);
   return hipGetLastError();
 }
 
