@@ -105,9 +105,10 @@ hipError_t launch_ad_leaf(int d, const AdaptLevelT<T>& L, hipStream_t s);
 // Levels with a finer level F (F must not be null; the finest level runs launch_ad_leaf_up).
 // norms_only: only the composite residual: norm partials, hh, and bb replaced by the composite
 // residual at composite dofs (zero elsewhere)
+// tiled: the 3D tiled kernel (adapt_up_tiled), else the five-wave gathers
 template <typename T>
 hipError_t launch_ad_up(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>* F, const RtSep<T>& rts, T omega,
-                        T omega_t, int damping, int norms_only, double* partials, hipStream_t s);
+                        T omega_t, int damping, int norms_only, int tiled, double* partials, hipStream_t s);
 // The finest level: leaf residual and up in one pass
 template <typename T>
 hipError_t launch_ad_leaf_up(int d, const AdaptLevelT<T>& L, T omega, T omega_t, int norms_only, double* partials,
@@ -141,7 +142,14 @@ hipError_t launch_ad_accumulate(int d, const AdaptLevel& A, const AdaptLevelT<fl
 constexpr int kAdaptNormBlocks = ADAFAC_AD_UP_MAX_BLOCKS;   // most blocks (norm partial slots) of an up launch
 hipError_t launch_ad_norm_finalize(const double* partials, int n, double* out, hipStream_t s);
 unsigned adapt_up_blocks(long box_vertices);     // blocks of an up launch without a finer level
-unsigned adapt_up_blocks_f(long box_vertices);   // with one
+unsigned adapt_up_blocks_f(long box_vertices);   // with one (2D)
+unsigned adapt_up_blocks_tiled(int mx, int my, int mz);   // with one (3D, large levels)
+// does a level with a finer one run tiled (3D, at least min_tiles tiles)?  FP64 only: in FP32 the
+// per-vertex gathers move half the bytes and were measured faster than the tile march.
+bool adapt_up_tiled(int d, int mx, int my, int mz, int min_tiles);
+constexpr int kAdaptTiledMinTiles = 256;   // default: one tile per CU
+// norm partial slots of a level's up launch (box of mx x my x mz vertices)
+unsigned adapt_up_slots(int d, int mx, int my, int mz, bool has_finer, bool tiled);
 constexpr long kAdaptMaxBox = (1L << 31) - 1;   // vertices (and cells) of one level's box
 
 }  // namespace adafac

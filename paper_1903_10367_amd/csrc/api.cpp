@@ -4,9 +4,11 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "adafac.h"
@@ -95,6 +97,7 @@ struct adafac_ctx {
   bool e_pending = false;   // FP32_REFINED: inner correction not yet added to the FP64 solution
   double* partials = nullptr;
   size_t npartials = 0;
+  double* partials_inner = nullptr;   // adaptive FP32_REFINED: the inner cycles' norm partials
   double* norms = nullptr;  // (l2h, linf) per cycle or outer step, ring of kMaxHist
   double* scratch_norm = nullptr;
   double* norm0 = nullptr;  // (l2h, linf) of iterate 0, kept beyond the ring
@@ -110,6 +113,8 @@ struct adafac_ctx {
   RtSep<double> ad_rts{};
   std::vector<AdaptLevel> ad;           // device views by level
   std::vector<size_t> ad_part;          // first norm-partial slot of each level's up launch
+  std::vector<int> ad_tiled;            // level restricts from its finer level with the tiled kernel
+  int ad_tiled_min = kAdaptTiledMinTiles;   // tiles from which it does (fixed at build_operators)
   double* ad_eps = nullptr;
   std::vector<AdaptLevelT<float>> ad32; // FP32_REFINED: inner cycles on the defect equation
   RtSep<float> ad_rts32{};
@@ -463,24 +468,33 @@ size_t layout_adaptive_tree(adafac_ctx* c, const AdaptHost& t, char* base) {
   }
   // norm partials: one slot per block of each level's up launch, levels packed
   std::vector<size_t> part(c->L + 1, 0);
+  std::vector<int> tiled(c->L + 1, 0);
+  const int min_tiles = c->ad_tiled_min;
   size_t npart = 0;
   for (int l = c->lmin; l <= c->L; ++l) {
     part[l] = npart;
-    const long nb = long(t.lev[l].nverts());
-    npart += l < c->L ? adapt_up_blocks_f(nb) : adapt_up_blocks(nb);
+    const AdaptHostLevel& H = t.lev[l];
+    const int mx = H.nc[0] + 1, my = H.nc[1] + 1, mz = d == 3 ? H.nc[2] + 1 : 1;
+    tiled[l] = l < c->L && adapt_up_tiled(d, mx, my, mz, min_tiles);
+    npart += adapt_up_slots(d, mx, my, mz, l < c->L, tiled[l] != 0);
   }
   double* partials = reinterpret_cast<double*>(take(sizeof(double) * 2 * npart));
+  // the inner cycles run other kernels on some levels (so other slot counts): own partials, so
+  // that the outer step's norms never read the inner cycles' slots
+  double* partials_inner = mp ? reinterpret_cast<double*>(take(sizeof(double) * 2 * npart)) : nullptr;
   double* norms = reinterpret_cast<double*>(take(sizeof(double) * 2 * kMaxHist));
   double* scratch = reinterpret_cast<double*>(take(sizeof(double) * 2));
   double* norm0 = reinterpret_cast<double*>(take(sizeof(double) * 2));
   if (base) {
     c->ad = std::move(ad);
     c->ad_part = std::move(part);
+    c->ad_tiled = std::move(tiled);
     c->ad_eps = eps;
     c->ad32 = std::move(ad32);
     c->ad_eps32 = eps32;
     c->npartials = npart;
     c->partials = partials;
+    c->partials_inner = partials_inner;
     c->norms = norms;
     c->scratch_norm = scratch;
     c->norm0 = norm0;
@@ -518,12 +532,14 @@ int run_adapt_cycle(adafac_ctx* c, const std::vector<AdaptLevelT<T>>& ad, const 
   if (rc) return rc;
   if ((rc = record_start(c))) return rc;
   for (int l = lmin; l < L; ++l) HIPCHK(c, launch_ad_leaf<T>(d, ad[l], c->stream));
-  HIPCHK(c, launch_ad_leaf_up<T>(d, ad[L], omega, omega_t, 0, c->partials + 2 * c->ad_part[L], c->stream));
+  double* partials = std::is_same<T, double>::value ? c->partials : c->partials_inner;
+  HIPCHK(c, launch_ad_leaf_up<T>(d, ad[L], omega, omega_t, 0, partials + 2 * c->ad_part[L], c->stream));
   if ((rc = record_stop(c))) return rc;
   for (int l = L - 1; l >= lmin; --l)
-    HIPCHK(c, launch_ad_up<T>(d, ad[l], &ad[l + 1], rts, omega, omega_t, o.damping, 0, c->partials + 2 * c->ad_part[l],
+    HIPCHK(c, launch_ad_up<T>(d, ad[l], &ad[l + 1], rts, omega, omega_t, o.damping, 0,
+                              std::is_same<T, double>::value ? c->ad_tiled[l] : 0, partials + 2 * c->ad_part[l],
                               c->stream));
-  HIPCHK(c, launch_ad_norm_finalize(c->partials, int(c->npartials), norm_out, c->stream));
+  HIPCHK(c, launch_ad_norm_finalize(partials, int(c->npartials), norm_out, c->stream));
   for (int l = lmin; l < L; ++l)
     HIPCHK(c, launch_ad_down<T>(d, ad[l], l > lmin ? &ad[l - 1] : nullptr, c->stream));
   HIPCHK(c, launch_ad_down_update<T>(d, ad[L], ad[L - 1], c->stream));
@@ -547,7 +563,7 @@ int run_adapt_outer_mixed(adafac_ctx* c, double* norm_out) {
   if ((rc = record_stop(c))) return rc;
   for (int l = L - 1; l >= lmin; --l)
     HIPCHK(c, launch_ad_up<double>(d, c->ad[l], &c->ad[l + 1], c->ad_rts, 0.0, 0.0, c->opts.damping, 1,
-                                   c->partials + 2 * c->ad_part[l], c->stream));
+                                   c->ad_tiled[l], c->partials + 2 * c->ad_part[l], c->stream));
   HIPCHK(c, launch_ad_norm_finalize(c->partials, int(c->npartials), norm_out, c->stream));
   for (int l = lmin; l <= L; ++l) HIPCHK(c, launch_ad_to_inner(d, c->ad[l], c->ad32[l], c->stream));
   return ADAFAC_OK;
@@ -664,6 +680,10 @@ int build_adaptive(adafac_ctx* c) {
     return fail(c, ADAFAC_EINVAL, "coefficient blocks finer than the first refined level of the tree");
   std::string m = build_adapt_tree(c->at, c->dim, c->lmin, c->L, c->refine, c->ball_c, c->ball_r, c->ball_from);
   if (!m.empty()) return fail(c, ADAFAC_EINVAL, m);
+  // ADAFAC_AD_TILED_MIN_TILES overrides the tile count from which a 3D level restricts with the
+  // tiled kernel (0: every level; tests use it to run that kernel on small trees)
+  c->ad_tiled_min = kAdaptTiledMinTiles;
+  if (const char* e = std::getenv("ADAFAC_AD_TILED_MIN_TILES")) c->ad_tiled_min = std::max(0, std::atoi(e));
   for (int l = c->lmin; l <= c->L; ++l)
     if (c->at.lev[l].nverts() > size_t(kAdaptMaxBox))
       return fail(c, ADAFAC_EUNSUPPORTED, "a level's bounding box exceeds 2^31 - 1 vertices");

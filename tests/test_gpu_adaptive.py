@@ -161,3 +161,15 @@ def test_gaussian_source_moving_with_the_ball():
         ho.append(nr)
     for n, (a, b) in enumerate(zip(hg, ho)):
         assert abs(a[0] - b[0]) <= 1e-12 * ho[0][0], f"cycle {n}"
+
+
+@pytest.mark.parametrize("damping", ["jac", "none"])
+@pytest.mark.parametrize("L", [3, 4])
+def test_3d_tiled_restriction(L, damping, monkeypatch):
+    """The tiled 3D restriction (chosen from 256 tiles per level on large trees) on every level
+    of small trees, against the oracle; tile edges, box edges and z chunks all occur here."""
+    monkeypatch.setenv("ADAFAC_AD_TILED_MIN_TILES", "0")
+    say("case adaptive 3d tiled restriction", L, damping)
+    eps = inp.eps_blocks(3, 1, 2.0, seed=86)
+    run_both(3, L, 2, inp.rhs(3, L, seed=87, dist="normal"), eps, centre=(0.42, 0.55, 0.5),
+             radius=0.3 if L == 3 else 0.2, cycles=4, damping=damping)

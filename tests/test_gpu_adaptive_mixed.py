@@ -181,3 +181,19 @@ def test_regrid_between_outer_steps():
     adaptive.defect_correction(T1, f1, K, 0.0, 3, np.float64, i64)
     U0 = (adaptive.transfer(T1, i32[3], T2), adaptive.transfer(T1, i64[3], T2))
     check_steps(T2, f2, hg[3:], 3, U0=U0, label="after")
+
+
+def test_3d_tiled_restriction_outer_steps(monkeypatch):
+    """FP32_REFINED with the tiled 3D restriction on every level (the composite-residual-only
+    FP64 pass and the FP32 Jacobi cycles)."""
+    monkeypatch.setenv("ADAFAC_AD_TILED_MIN_TILES", "0")
+    say("case mixed adaptive 3d tiled restriction")
+    eps = inp.eps_blocks(3, 1, 2.0, seed=101)
+    f = inp.rhs(3, 4, seed=102)
+    c = (0.45, 0.5, 0.55)
+    s = solver(3, 4, 2, f, eps, c, 0.2)
+    s.cycle(3)
+    hg = s.residuals()
+    s.close()
+    T = adaptive.AdaptiveTree(3, 4, 1, 2, inp.refine_ball(3, 4, 2, c, 0.2), eps)
+    check_steps(T, f, hg, 3, label="3d tiled")
