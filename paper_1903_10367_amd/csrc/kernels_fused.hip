@@ -117,10 +117,28 @@ template <typename T, bool VAREPS>
 struct ColumnOp {
   T own = T(0), c1 = T(0), c2 = T(0), c3 = T(0), epsprev = T(0);
   T dq[4] = {T(0), T(0), T(0), T(0)}, eq[4] = {T(0), T(0), T(0), T(0)};
+  // variable eps: the blocks of the four cells around the column (fixed per column), the eps of
+  // the current block layer (reloaded only when z enters a new layer, the same step for every
+  // lane), and ceil(2^32 / bs) for the layer index
+  int off4[4] = {0, 0, 0, 0};
+  int bzc = -1;
+  T e4c[4] = {T(0), T(0), T(0), T(0)}, eslc = T(0);
+  unsigned long long bsm = 0;
+
+  __device__ __forceinline__ void init(int x, int y, int n, int nb, int bs) {
+    if constexpr (VAREPS) {
+      const int bx0 = min(max(x - 1, 0), n - 1) / bs, bx1 = min(max(x, 0), n - 1) / bs;
+      const int by0 = min(max(y - 1, 0), n - 1) / bs, by1 = min(max(y, 0), n - 1) / bs;
+      off4[0] = by0 * nb + bx0;
+      off4[1] = by0 * nb + bx1;
+      off4[2] = by1 * nb + bx0;
+      off4[3] = by1 * nb + bx1;
+      bsm = 0xFFFFFFFFull / unsigned(bs) + 1;   // exact floor(z / bs) = (z bsm) >> 32 for z < 2^20
+    }
+  }
 
   template <int W>
-  __device__ __forceinline__ T push(const T* up, T h, int x, int y, int z, int n, const T* eps, int nb, int bs,
-                                    T& diag, T& uz) {
+  __device__ __forceinline__ T push(const T* up, T h, int z, int n, const T* eps, int nb, T& diag, T& uz) {
     const T o_n = up[0];
     const T ax_m = up[-1], ax_p = up[1], ay_m = up[-W], ay_p = up[W];
     const T d_0 = up[-W - 1], d_1 = up[-W + 1], d_2 = up[W - 1], d_3 = up[W + 1];
@@ -139,18 +157,22 @@ struct ColumnOp {
       const T d_n[4] = {d_0, d_1, d_2, d_3};
       const T e_n[4] = {ax_m + ay_m + d_0, ax_p + ay_m + d_1, ax_m + ay_p + d_2, ax_p + ay_p + d_3};
       // eps of the four cells of layer z (between planes z and z+1) around the column
-      const int bx0 = min(max(x - 1, 0), n - 1) / bs, bx1 = min(max(x, 0), n - 1) / bs;
-      const int by0 = min(max(y - 1, 0), n - 1) / bs, by1 = min(max(y, 0), n - 1) / bs;
-      const int bz = min(max(z, 0), n - 1) / bs;
-      const T* eb = eps + size_t(bz) * nb * nb;
-      const T e4[4] = {eb[by0 * nb + bx0], eb[by0 * nb + bx1], eb[by1 * nb + bx0], eb[by1 * nb + bx1]};
+      const int bz = int((unsigned long long)unsigned(min(max(z, 0), n - 1)) * bsm >> 32);
+      if (bz != bzc) {
+        const T* eb = eps + size_t(bz) * nb * nb;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) e4c[q] = eb[off4[q]];
+        eslc = (e4c[0] + e4c[1]) + (e4c[2] + e4c[3]);
+        bzc = bz;
+      }
+      const T* e4 = e4c;
       T bc = T(0), tn = T(0);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         bc += e4[q] * (T(1.0 / 3.0) * uz - T(1.0 / 12.0) * (dq[q] + e_n[q]));
         tn += e4[q] * (T(1.0 / 3.0) * o_n - T(1.0 / 12.0) * (d_n[q] + eq[q]));
       }
-      const T esl = (e4[0] + e4[1]) + (e4[2] + e4[3]);
+      const T esl = eslc;
       au = h * (bc + c1);
       diag = h * T(1.0 / 3.0) * (esl + epsprev);
       c1 = tn;
@@ -307,6 +329,7 @@ __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_fine_sweep3d(S
   const int rslot = ract ? ry * RP + rx : RW * RP + (tid - NR);
 
   ColumnOp<T, VAREPS> col;
+  col.init(x, y, n, a.nb, a.bs);
   // prefetch ring: slot K holds u(p) and b(p-2) for the steps p of slot K
   T pu[3], pb[3];
   T accR[2] = {T(0), T(0)}, accT[2] = {T(0), T(0)};
@@ -360,7 +383,7 @@ __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_fine_sweep3d(S
     if (!CK || (p - 1 >= zs && p - 1 <= ze)) {
       const int z = p - 2;
       T diag, uz;
-      const T au = col.template push<UW>(&Ub[K2][upos], h, x, y, z, n, a.eps, a.nb, a.bs, diag, uz);
+      const T au = col.template push<UW>(&Ub[K2][upos], h, z, n, a.eps, a.nb, diag, uz);
       const T dinv = VAREPS ? a.omega / diag : wdiag;
       T res = T(0);
       const bool zin = !CK || (p - 1 >= zs + 2 && z > 0 && z < n);
@@ -568,6 +591,7 @@ __global__ void __launch_bounds__(NTD, VAREPS ? 4 : ADAFAC_DEFECT3D_MINWAVES) k_
   const int upos = (rj / TX + 1) * DW + rj % TX + 1;
 
   ColumnOp<double, VAREPS> col;
+  col.init(x, y, n, a.nb, a.bs);
   double pu[3], pb[3];
   float pe[3];
   double ssum = 0.0, smax = 0.0;
@@ -623,7 +647,7 @@ __global__ void __launch_bounds__(NTD, VAREPS ? 4 : ADAFAC_DEFECT3D_MINWAVES) k_
     if (!CK || (p - 1 >= zs && p - 1 <= ze)) {
       const int z = p - 2;
       double diag, uz;
-      const double au = col.template push<DW>(&Ub[K2][upos], h, x, y, z, n, a.eps, a.nb, a.bs, diag, uz);
+      const double au = col.template push<DW>(&Ub[K2][upos], h, z, n, a.eps, a.nb, diag, uz);
       if (rint && (!CK || (z >= z0 && z < z0 + tz && z > 0 && z < n))) {
         const double res = pb[K2] - au;
         R.st_stream(float(res), roffd * 4u, unsigned(z) * planef);
