@@ -116,10 +116,12 @@ __device__ __forceinline__ void restrict_x_pass(const T* Rb, T* Xw, T* Xm, const
 template <typename T, bool VAREPS>
 struct ColumnOp {
   T own = T(0), c1 = T(0), c2 = T(0), c3 = T(0), epsprev = T(0);
-  T dq[4] = {T(0), T(0), T(0), T(0)}, eq[4] = {T(0), T(0), T(0), T(0)};
-  // variable eps: the blocks of the four cells around the column (fixed per column), the eps of
-  // the current block layer (reloaded only when z enters a new layer, the same step for every
-  // lane), and ceil(2^32 / bs) for the layer index
+  // variable eps: the eps-weighted sums over the four quadrants of the diagonal neighbours and
+  // of the in-plane neighbour sums of the plane below (weighted with the next push's cell layer,
+  // so two values are carried instead of eight); the blocks of the four cells around the column
+  // (fixed per column); the eps of the current block layer (reloaded only when z enters a new
+  // layer, the same step for every lane); ceil(2^32 / bs) for the layer index
+  T acar = T(0), bcar = T(0);
   int off4[4] = {0, 0, 0, 0};
   int bzc = -1;
   T e4c[4] = {T(0), T(0), T(0), T(0)}, eslc = T(0);
@@ -157,30 +159,44 @@ struct ColumnOp {
       const T d_n[4] = {d_0, d_1, d_2, d_3};
       const T e_n[4] = {ax_m + ay_m + d_0, ax_p + ay_m + d_1, ax_m + ay_p + d_2, ax_p + ay_p + d_3};
       // eps of the four cells of layer z (between planes z and z+1) around the column
-      const int bz = int((unsigned long long)unsigned(min(max(z, 0), n - 1)) * bsm >> 32);
-      if (bz != bzc) {
+      auto layer = [&](int zz) { return int((unsigned long long)unsigned(min(max(zz, 0), n - 1)) * bsm >> 32); };
+      auto load = [&](int bz) {
         const T* eb = eps + size_t(bz) * nb * nb;
 #pragma unroll
         for (int q = 0; q < 4; ++q) e4c[q] = eb[off4[q]];
         eslc = (e4c[0] + e4c[1]) + (e4c[2] + e4c[3]);
         bzc = bz;
-      }
-      const T* e4 = e4c;
-      T bc = T(0), tn = T(0);
+      };
+      const int bz = layer(z);
+      if (bz != bzc) load(bz);
+      T se = T(0), sd = T(0);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        bc += e4[q] * (T(1.0 / 3.0) * uz - T(1.0 / 12.0) * (dq[q] + e_n[q]));
-        tn += e4[q] * (T(1.0 / 3.0) * o_n - T(1.0 / 12.0) * (d_n[q] + eq[q]));
+        se += e4c[q] * e_n[q];
+        sd += e4c[q] * d_n[q];
       }
       const T esl = eslc;
+      // layer z's contributions to A u(z) (with the plane below) and to A u(z+1) (carried)
+      const T bc = esl * (T(1.0 / 3.0) * uz) - T(1.0 / 12.0) * (acar + se);
+      const T tn = esl * (T(1.0 / 3.0) * o_n) - T(1.0 / 12.0) * (sd + bcar);
       au = h * (bc + c1);
       diag = h * T(1.0 / 3.0) * (esl + epsprev);
       c1 = tn;
       epsprev = esl;
+      // the next push (plane z+1) weights this plane's neighbours with layer z+1
+      const int bzn = layer(z + 1);
+      if (bzn != bz) {
+        load(bzn);
+        acar = T(0);
+        bcar = T(0);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        dq[q] = d_n[q];
-        eq[q] = e_n[q];
+        for (int q = 0; q < 4; ++q) {
+          acar += e4c[q] * d_n[q];
+          bcar += e4c[q] * e_n[q];
+        }
+      } else {
+        acar = sd;
+        bcar = se;
       }
     }
     own = o_n;
