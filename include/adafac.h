@@ -325,7 +325,7 @@ typedef struct {
 } adafac_result;
 
 /* Defaults: max_active 256, max_queued 4096, cycles_per_round 4, max_streams 4,
- * batch_max_vertices 65536. */
+ * batch_max_vertices 16384. */
 void adafac_server_default_cfg(adafac_server_cfg* cfg);
 
 /* Create a server over the device workspace [dev_workspace, +bytes) (256-byte

@@ -182,7 +182,7 @@ class Server:
     """
 
     def __init__(self, budget_bytes, max_active=256, max_queued=4096, cycles_per_round=4, max_streams=4,
-                 batch_max_vertices=65536, device=None, stream=None):
+                 batch_max_vertices=16384, device=None, stream=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("adafac needs a ROCm GPU (gfx950); none is visible")

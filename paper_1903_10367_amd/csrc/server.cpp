@@ -437,7 +437,7 @@ void adafac_server_default_cfg(adafac_server_cfg* c) {
   c->max_queued = 4096;
   c->cycles_per_round = 4;
   c->max_streams = 4;
-  c->batch_max_vertices = 65536;
+  c->batch_max_vertices = 16384;   // larger hierarchies run faster as multi-workgroup kernels on a lane
 }
 
 int adafac_server_create(const adafac_server_cfg* cfg, void* ws, size_t bytes, void* stream, adafac_server** out) {
