@@ -133,6 +133,7 @@ struct BatchState {
 // Internal hooks of the C ABI used by the request server (api.cpp).
 int batch_describe(void* ctx, BatchReq* out);        // device description of a bound context
 int batch_adopt(void* ctx, int cur, int converged);  // current iterate after batched cycles
+int residual_range(void* ctx, int c0, int n, double* out);   // norms of cycles c0.., 2 per cycle
 
 struct CycleParams {
   double omega, omega_t, omega_hat;

@@ -895,6 +895,22 @@ int batch_describe(void* vc, BatchReq* out) {
   return ADAFAC_OK;
 }
 
+// Norms (l2h, linf) of cycles c0 .. c0+n-1 into out[2n], in one or two copies and one
+// synchronisation (the server reads a lane's whole chunk at once).
+int residual_range(void* vc, int c0, int n, double* out) {
+  adafac_ctx* c = static_cast<adafac_ctx*>(vc);
+  if (!c || !c->bound) return ADAFAC_ESTATE;
+  if (n <= 0) return ADAFAC_OK;
+  if (c0 < 0 || c0 + n > c->ncyc || c->ncyc - c0 > kMaxHist || !out) return ADAFAC_EINVAL;
+  const int i0 = c0 % kMaxHist, first = std::min(n, kMaxHist - i0);
+  HIPCHK(c, hipMemcpyAsync(out, c->norms + 2 * i0, sizeof(double) * 2 * first, hipMemcpyDeviceToHost, c->stream));
+  if (first < n)
+    HIPCHK(c, hipMemcpyAsync(out + 2 * first, c->norms, sizeof(double) * 2 * (n - first), hipMemcpyDeviceToHost,
+                             c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return ADAFAC_OK;
+}
+
 // After batched cycles: ufine[cur] of the description holds the current FP64 iterate.
 int batch_adopt(void* vc, int cur, int /*converged*/) {
   adafac_ctx* c = static_cast<adafac_ctx*>(vc);

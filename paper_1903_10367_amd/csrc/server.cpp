@@ -3,6 +3,7 @@
 // launch, large requests on streams of their own, harvest of finished requests.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -137,6 +138,7 @@ struct adafac_server {
   std::string err;
   // host time spent per phase of adafac_server_step (seconds) and rounds run
   double t_harvest = 0, t_admit = 0, t_launch = 0;
+  std::vector<double> norm_buf;   // a lane chunk's norms
   long rounds = 0;
 };
 
@@ -289,10 +291,13 @@ int service_lane(adafac_server* s, int k, bool wait, bool* done) {
     *done = true;
     int status = ADAFAC_REQ_RUNNING;
     const int n = adafac_cycles_run(r.ctx);
-    for (int c = r.cycles_seen; c < n && status == ADAFAC_REQ_RUNNING; ++c) {
-      double l2 = 0, li = 0;
-      int rc = adafac_residual(r.ctx, c, &l2, &li);
+    s->norm_buf.resize(2 * size_t(std::max(n - r.cycles_seen, 0)));
+    if (n > r.cycles_seen) {
+      int rc = residual_range(r.ctx, r.cycles_seen, n - r.cycles_seen, s->norm_buf.data());
       if (rc) return sfail(s, rc, adafac_last_error(r.ctx));
+    }
+    for (int c = r.cycles_seen; c < n && status == ADAFAC_REQ_RUNNING; ++c) {
+      const double l2 = s->norm_buf[2 * size_t(c - r.cycles_seen)], li = s->norm_buf[2 * size_t(c - r.cycles_seen) + 1];
       if (c == 0) r.res.l2h0 = l2;
       r.res.l2h = l2;
       r.res.linf = li;
