@@ -173,3 +173,32 @@ def test_3d_tiled_restriction(L, damping, monkeypatch):
     eps = inp.eps_blocks(3, 1, 2.0, seed=86)
     run_both(3, L, 2, inp.rhs(3, L, seed=87, dist="normal"), eps, centre=(0.42, 0.55, 0.5),
              radius=0.3 if L == 3 else 0.2, cycles=4, damping=damping)
+
+
+def test_3d_gaussian_tree_l5_both_restrictions(monkeypatch):
+    """The moving-Gaussian configuration one level shallower (27^3 blocks 10^U(0,4), uniform to
+    level 3, the ball of radius 3 sigma refined to level 5, 249k composite dofs): two cycles
+    against the oracle with the per-vertex gathers and with the tiled restriction on every
+    level."""
+    from paper_1903_10367_amd import Solver
+    c = inp.moving_source(seed=23, steps=1, d=3)[0]
+    eps = inp.eps_blocks(3, 3, 4.0, seed=24)
+    f = inp.gaussian(3, 5, c, 0.05)
+    T = adaptive.AdaptiveTree(3, 5, 1, 3, inp.refine_ball(3, 5, 3, c, 0.15), eps)
+    U, ho = adaptive.solve(T, f, 2)
+    scale = max(np.abs(U[l]).max() for l in U)
+    for tiled in ("256", "0"):
+        monkeypatch.setenv("ADAFAC_AD_TILED_MIN_TILES", tiled)
+        say("case adaptive 3d gaussian tree L=5, tiled from", tiled, "tiles")
+        s = Solver(3, 1, 5, f, eps_blocks=eps, ball=(c, 0.15, 3))
+        s.cycle(2)
+        hg = s.residuals()
+        levels = {l: s.level(l, "u") for l in range(1, 6)}
+        assert s.composite_dofs() == int(sum(T.comp[l].sum() for l in T.comp))
+        s.close()
+        for n, (a, b) in enumerate(zip(hg, ho)):
+            assert abs(a[0] - b[0]) <= 1e-12 * ho[0][0], f"cycle {n}"
+        for l in range(1, 6):
+            have = T.dof[l] | T.hang[l]
+            err = np.abs(levels[l].reshape(T.shape(l))[have] - U[l][have]).max()
+            assert err <= 1e-12 * scale, f"level {l}: {err:.3e}"
