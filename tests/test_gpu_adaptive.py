@@ -202,3 +202,24 @@ def test_3d_gaussian_tree_l5_both_restrictions(monkeypatch):
             have = T.dof[l] | T.hang[l]
             err = np.abs(levels[l].reshape(T.shape(l))[have] - U[l][have]).max()
             assert err <= 1e-12 * scale, f"level {l}: {err:.3e}"
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_refinement_at_the_domain_corner(d, monkeypatch):
+    """A ball around a corner region: refined cells and their boxes touch the domain boundary
+    (box-edge and boundary paths of every kernel; 3D with the tiled restriction forced)."""
+    if d == 3:
+        monkeypatch.setenv("ADAFAC_AD_TILED_MIN_TILES", "0")
+    say("case adaptive refinement at the domain corner", d)
+    L = 4 if d == 2 else 3
+    centre = (0.08, 0.12) if d == 2 else (0.08, 0.12, 0.9)
+    eps = inp.eps_blocks(d, 1, 2.0, seed=88)
+    run_both(d, L, 1, inp.rhs(d, L, seed=89), eps, centre=centre, radius=0.3, cycles=4)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_two_level_tree(d):
+    """The shortest tree: level 1 uniform, part of it refined to level 2."""
+    say("case adaptive two-level tree", d)
+    centre = (0.4, 0.6) if d == 2 else (0.4, 0.6, 0.5)
+    run_both(d, 2, 1, inp.rhs(d, 2, seed=90), None, centre=centre, radius=0.2, cycles=5)
