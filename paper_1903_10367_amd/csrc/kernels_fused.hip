@@ -521,6 +521,288 @@ __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_fine_sweep3d(S
 }
 
 // ---------------------------------------------------------------------------
+// The constant-coefficient (eps = 1) 3D sweep on a 32-wide ring.  Lane (lx, ly) =
+// (tid mod 32, tid / 32) owns the ring column (x0-3+lx, y0-3+ly): it loads u and b there and,
+// where the column lies on the 29 x 29 residual ring (lx, ly in 1..29), evaluates the residual
+// too.  A ring row is half a wavefront, so the x neighbours of a column sit in the adjacent
+// lanes: each lane forms the x-neighbour sum of its newest u value with two whole-wavefront
+// lane shifts (DPP, no LDS traffic), and the stencil reads from LDS only the u values and x sums
+// of the rows above and below (four values instead of the nine of the 3 x 3 neighbourhood).  The
+// arithmetic is that of k_fine_sweep3d for eps = 1, term for term and in the same order.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int W2 = 32;                      // ring pitch in lanes
+constexpr int RQ = 33;                      // LDS row pitch of the residual planes (bank spread)
+static_assert(W2 * W2 == NT3, "one lane per ring column");
+
+typedef int i32x2_t __attribute__((ext_vector_type(2)));
+// v of lane i-1 (CTRL = wave_shr:1) or lane i+1 (CTRL = wave_shl:1) of the wavefront; the lane
+// without a source gets 0.  Must run with every lane of the wavefront active.
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double v) {
+  const i32x2_t p = __builtin_bit_cast(i32x2_t, v);
+  i32x2_t r;
+  r.x = __builtin_amdgcn_update_dpp(0, p.x, CTRL, 0xf, 0xf, false);
+  r.y = __builtin_amdgcn_update_dpp(0, p.y, CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, r);
+}
+template <int CTRL>
+__device__ __forceinline__ float lane_shift(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+constexpr int kDppWaveShr1 = 0x138;
+constexpr int kDppWaveShl1 = 0x130;
+}  // namespace
+
+template <typename T, bool COARSE, bool PEND>
+__global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_sweep3d_w32(Sweep3dArgs<T> a) {
+  // newest u planes and their x-neighbour sums, one padding row above and below so that every
+  // lane reads its y neighbours in bounds (the padding only feeds lanes without residual duty)
+  __shared__ T Ub[3][NT3 + 2 * W2];
+  __shared__ T Xb[3][NT3 + 2 * W2];
+  __shared__ T Rb[3][W2 * RQ];           // residual planes
+  __shared__ T Xw[3][RW * NCO];          // x passes
+  __shared__ T Xm[3][RW * NCO];
+  __shared__ T Sb[PEND ? (MAXTZ / 3 + 3) * CW * CW : 1];
+  __shared__ T Sz[3][CW * CW];           // S interpolated to a fine plane
+
+  const int n = a.n, nv = a.nv, nc = a.nc, nvc = a.nvc;
+  const int plane = nv * nv;
+  const unsigned planeb = unsigned(plane * sizeof(T));
+  const unsigned latb = unsigned(size_t(plane) * nv * sizeof(T));
+  const int nblk = a.ntx * a.ntx * a.ntz;
+  const int t = xcd_remap(blockIdx.x, nblk);
+  const int txi = t % a.ntx, tyi = (t / a.ntx) % a.ntx, tzi = t / (a.ntx * a.ntx);
+  const int tz = a.tz;
+  const int x0 = TX * txi, y0 = TX * tyi, z0 = tz * tzi;
+  const int cbx = x0 / 3 - 1, cby = y0 / 3 - 1, cbz = z0 / 3 - 1;
+  const int nsz = tz / 3 + 3;
+  const int tid = threadIdx.x;
+  const bool jac = a.damping == ADAFAC_DAMP_JAC;
+  const T h = a.h;
+  const Lattice<T> U(a.uin, latb), B(a.b, latb), UO(a.uout, latb);
+
+  if constexpr (PEND) {
+    for (int i = tid; i < nsz * CW * CW; i += NT3) {
+      const int lx = i % CW, ly = (i / CW) % CW, lz = i / (CW * CW);
+      const int cx = cbx + lx, cy = cby + ly, cz = cbz + lz;
+      T v = T(0);
+      if (cx >= 0 && cx <= nc && cy >= 0 && cy <= nc && cz >= 0 && cz <= nc) v = a.S[lin<3>(cx, cy, cz, nvc)];
+      Sb[i] = v;
+    }
+  }
+
+  // this lane's ring column (loads clamped into the lattice: values off the lattice only feed
+  // residuals of non-dof vertices, which are discarded)
+  const int lx = tid % W2, ly = tid / W2;
+  const int x = x0 - 3 + lx, y = y0 - 3 + ly;
+  const int xc = min(max(x, 0), n), yc = min(max(y, 0), n);
+  const int roff = xc + nv * yc;
+  const unsigned offb = unsigned(roff * sizeof(T));
+  const int ucx = xc / 3, ucy = yc / 3;
+  const int usi = (ucy - cby) * CW + ucx - cbx;
+  const int usx = xc - 3 * ucx, usy = yc - 3 * ucy;
+  const T wx0 = T(3 - usx) * T(1.0 / 3.0), wx1 = T(usx) * T(1.0 / 3.0);
+  const T wy0 = T(3 - usy) * T(1.0 / 3.0), wy1 = T(usy) * T(1.0 / 3.0);
+  // residual duty: the ring x0-2 .. x0+26 (lx, ly in 1..29)
+  const bool ract = lx >= 1 && lx <= RW && ly >= 1 && ly <= RW;
+  const bool rint = ract && x > 0 && x < n && y > 0 && y < n;
+  const bool rown = rint && lx >= 3 && ly >= 3 && x < x0 + TX && y < y0 + TX;
+  const bool rinj = rown && x % 3 == 0 && y % 3 == 0;
+  const int rslot = ly * RQ + lx;
+
+  // the column operator of k_fine_sweep3d (eps = 1): u(z), D4(z), F(z-1), F(z)
+  T own = T(0), c1 = T(0), c2 = T(0), c3 = T(0);
+  T vlast = T(0), xlast = T(0);          // this lane's newest u value and its x-neighbour sum
+  // prefetch ring: slot K holds u(p) and b(p-2) for the steps p of slot K
+  T pu[3], pb[3];
+  T accR[2] = {T(0), T(0)}, accT[2] = {T(0), T(0)};
+  double ssum = 0.0, smax = 0.0;
+  const T wdiag = a.omega / (h * T(8.0 / 3.0));     // omega / D for eps = 1
+
+  const int zs = z0 - 3, ze = z0 + tz;
+  auto uload = [&](int p) { return U.ld(offb, unsigned(min(max(p, 0), n)) * planeb); };
+  auto bload = [&](int p) { return B.ld(offb, unsigned(min(max(p, 0), n)) * planeb); };
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    pu[q] = uload(zs + q);
+    pb[q] = bload(zs + q - 1);
+  }
+
+  auto blend_s = [&](int p, auto ks) {
+    constexpr int KS = decltype(ks)::value;
+    if constexpr (PEND) {
+      const int bt = tid - BL0;
+      if (bt >= 0 && bt < CW * CW) {
+        T v = T(0);
+        if (p >= 0 && p <= n) {
+          const int cz = p / 3, sz = p - 3 * cz;
+          const T* s0 = &Sb[(cz - cbz) * CW * CW + bt];
+          v = T(3 - sz) * T(1.0 / 3.0) * s0[0] + T(sz) * T(1.0 / 3.0) * s0[CW * CW];
+        }
+        Sz[KS][bt] = v;
+      }
+    }
+  };
+  if constexpr (PEND) __syncthreads();  // Sb ready
+  blend_s(zs, IC<0>{});
+  __syncthreads();                       // Sz[0] ready
+
+  auto step = [&](int p, auto ck, auto kk) {
+    constexpr bool CK = decltype(ck)::value != 0;
+    constexpr int K = decltype(kk)::value;
+    constexpr int K1 = (K + 1) % 3, K2 = (K + 2) % 3;
+    // (1) u plane p (plus the pending correction) and its x-neighbour sums into slot K; the
+    // condition is uniform over the workgroup, so every lane takes part in the lane shifts
+    T vnew = T(0), xnew = T(0);
+    if (!CK || p <= ze) {
+      vnew = pu[K];
+      if constexpr (PEND) {
+        const T* s0 = &Sz[K][usi];
+        vnew += wy0 * (wx0 * s0[0] + wx1 * s0[1]) + wy1 * (wx0 * s0[CW] + wx1 * s0[CW + 1]);
+      }
+      xnew = lane_shift<kDppWaveShr1>(vnew) + lane_shift<kDppWaveShl1>(vnew);
+      Ub[K][W2 + tid] = vnew;
+      Xb[K][W2 + tid] = xnew;
+    }
+    pu[K] = CK ? uload(min(p + 3, ze)) : U.ld(offb, unsigned(p + 3) * planeb);
+    // (2) residual of plane z = p-2 from u planes p-3, p-2 (registers) and p-1 (slot K2 and the
+    // lane's own newest values)
+    if (!CK || (p - 1 >= zs && p - 1 <= ze)) {
+      const int z = p - 2;
+      const T ay = Ub[K2][tid] + Ub[K2][tid + 2 * W2];
+      const T d4 = Xb[K2][tid] + Xb[K2][tid + 2 * W2];
+      const T f = T(2) * (xlast + ay) + d4;
+      const T uz = own;
+      const T au = h * (T(8.0 / 3.0) * uz - T(1.0 / 12.0) * ((T(2) * c1 + c2) + f));
+      c1 = d4;
+      c2 = c3;
+      c3 = f;
+      own = vlast;
+      T res = T(0);
+      const bool zin = !CK || (p - 1 >= zs + 2 && z > 0 && z < n);
+      if (zin && rint) {
+        const bool own_pt = rown && (!CK || (z >= z0 && z < z0 + tz));
+        if constexpr (!COARSE) {
+          res = pb[K2] - au;
+          if (own_pt) {
+            UO.st_stream(uz + wdiag * res, offb, unsigned(z) * planeb);
+            const double rd = double(res);
+            ssum += rd * rd;
+            smax = fabs(rd) > smax ? fabs(rd) : smax;
+          }
+        } else {
+          const T bf = pb[K2] + au;       // FAS right-hand side with the tau correction
+          res = bf - au;
+          if (own_pt) {
+            const int gi = z * plane + roff;
+            T sv = a.cscale * wdiag * res;
+            if (jac) sv -= (a.omega_t / a.omega) * wdiag * a.bt_in[gi];
+            a.sout[gi] = sv;
+            a.bfout[gi] = bf;
+            a.rout[gi] = res;
+          }
+        }
+        // FAS injection u_{L-1} = I u: planes z = p-2 with z = 0 mod 3 are the steps K = 2
+        if (K == 2 && own_pt && rinj) a.cu[lin<3>(x / 3, y / 3, z / 3, nvc)] = uz;
+      }
+      Rb[K1][rslot] = res;
+    }
+    if (!CK || p <= ze) {
+      vlast = vnew;
+      xlast = xnew;
+    }
+    pb[K2] = CK ? bload(min(p + 1, ze)) : B.ld(offb, unsigned(p + 1) * planeb);
+    // (3) x pass of residual plane p-3 (slot K)
+    if (!CK || (p - 3 >= zs + 1 && p - 3 <= ze - 1)) {
+      const int xt = tid - XP0;
+      if (xt >= 0 && xt < RW * NCO) {
+        // consecutive lanes take consecutive rows of one coarse column (conflict-free reads)
+        const int yy = xt % RW, ccx = xt / RW;
+        const T* rp = &Rb[K][(yy + 1) * RQ + 3 * ccx + 3];
+        T sw = T(0), sm = T(0);
+#pragma unroll
+        for (int o = -2; o <= 2; ++o) {
+          sw += wlin<T>(o) * rp[o];
+          sm += a.rts.m[o + 2] * rp[o];
+        }
+        Xw[K][yy * NCO + ccx] = sw;
+        Xm[K][yy * NCO + ccx] = sm;
+      }
+    }
+    // (4) y pass of residual plane zr = p-4 (slot K2), accumulated into the coarse planes at
+    // or below and above it; m = zr - 3 floor(zr / 3) = K2 because zs = 0 mod 3
+    if (!CK || (p - 4 >= zs + 1 && p - 4 <= ze - 1)) {
+      const int yt = tid - YP0;
+      if (yt >= 0 && yt < NCO * NCO) {
+        constexpr int m = K2;
+        const int zr = p - 4;
+        const T* xw = Xw[K2];
+        const T* xm = Xm[K2];
+        const T* rz = Rb[K2];
+        const int ccx = yt % NCO, ccy = yt / NCO;
+        T W = T(0), Q = T(0), Y = T(0);
+#pragma unroll
+        for (int o = -2; o <= 2; ++o) {
+          const int row = 3 * ccy + 2 + o;
+          W += wlin<T>(o) * xw[row * NCO + ccx];
+          Q += a.rts.m[o + 2] * xm[row * NCO + ccx];
+          Y += a.rts.m[o + 2] * rz[(row + 1) * RQ + 3 * ccx + 3];
+        }
+        const T X = xm[(3 * ccy + 2) * NCO + ccx];
+        // R~: planar tensor products; the plane through the coarse vertex also carries Q
+        accR[0] += wlin<T>(m) * W;
+        if (jac) accT[0] += a.rts.scale * (a.rts.m[2 + m] * (X + Y) + (m == 0 ? Q : T(0)));
+        if constexpr (m != 0) {
+          accR[1] += wlin<T>(3 - m) * W;
+          if (jac) accT[1] += a.rts.scale * a.rts.m[2 + 3 - m] * (X + Y);
+        }
+        if constexpr (m == 2) {
+          const int cz = (zr - 2) / 3;        // coarse plane below zr (zr >= z0 - 1 >= -1)
+          const int cx = x0 / 3 + ccx, cy = y0 / 3 + ccy;
+          if (cz >= z0 / 3 && cz < (z0 + tz) / 3 && cx > 0 && cx < nc && cy > 0 && cy < nc &&
+              cz > 0 && cz < nc) {
+            const size_t ci = lin<3>(cx, cy, cz, nvc);
+            a.crr[ci] = accR[0];
+            a.cbt[ci] = accT[0];
+          }
+          accR[0] = accR[1];
+          accT[0] = accT[1];
+          accR[1] = accT[1] = T(0);
+        }
+      }
+    }
+    // (5) S interpolated to plane p+1 (slot K1)
+    if (!CK || p + 1 <= ze) blend_s(p + 1, IC<K1>{});
+    __syncthreads();
+  };
+
+  // steps zs .. ze+3 drain the pipeline (residuals end at plane ze-1, restriction two steps later)
+  const int nit = (tz + 7 + 2) / 3;
+  const int ihi = (tz - 2) / 3;          // iterations 2..ihi need no range checks
+  int it = 0;
+  for (; it < min(2, nit); ++it) {
+    const int p = zs + 3 * it;
+    step(p, IC<1>{}, IC<0>{});
+    step(p + 1, IC<1>{}, IC<1>{});
+    step(p + 2, IC<1>{}, IC<2>{});
+  }
+  for (; it <= ihi; ++it) {
+    const int p = zs + 3 * it;
+    step(p, IC<0>{}, IC<0>{});
+    step(p + 1, IC<0>{}, IC<1>{});
+    step(p + 2, IC<0>{}, IC<2>{});
+  }
+  for (; it < nit; ++it) {
+    const int p = zs + 3 * it;
+    step(p, IC<1>{}, IC<0>{});
+    step(p + 1, IC<1>{}, IC<1>{});
+    step(p + 2, IC<1>{}, IC<2>{});
+  }
+  if constexpr (!COARSE) block_norm_partials(double(a.hd) * ssum, smax, a.partials);
+}
+
+// ---------------------------------------------------------------------------
 // FP64 step of defect correction on a 3D level (FP32 cycles inside FP64 defect correction):
 //   u' = u + (e + P S_{L-1})     the FP32 inner correction with its pending prolongation
 //                                (MODE 2), the correction alone (MODE 1) or nothing (MODE 0)
@@ -827,6 +1109,12 @@ size_t fine_sweep_partials(int d, int n) {
   return size_t(ntx) * ntx * (n / 3);   // upper bound over the z-chunk choices
 }
 
+// Constant-coefficient 3D sweeps run on the 32-wide ring (k_sweep3d_w32) unless this is 0.
+#ifndef ADAFAC_SWEEP3D_W32
+#define ADAFAC_SWEEP3D_W32 1
+#endif
+constexpr bool kSweepW32 = ADAFAC_SWEEP3D_W32 != 0;
+
 static int pick_tz(int n) {
   // longest z chunk (multiple of 3 dividing n, <= MAXTZ) that still gives one workgroup per CU
   // of the 256 (fewer, longer chunks re-read fewer halo planes)
@@ -845,6 +1133,8 @@ static hipError_t launch_sweep3d(const Sweep3dArgs<T>& a, bool var, hipStream_t 
   if (a.coarse) {
     if (var)
       k_fine_sweep3d<T, true, true, false><<<nb, NT3, 0, s>>>(a);
+    else if (kSweepW32)
+      k_sweep3d_w32<T, true, false><<<nb, NT3, 0, s>>>(a);
     else
       k_fine_sweep3d<T, false, true, false><<<nb, NT3, 0, s>>>(a);
   } else if (var) {
@@ -852,6 +1142,11 @@ static hipError_t launch_sweep3d(const Sweep3dArgs<T>& a, bool var, hipStream_t 
       k_fine_sweep3d<T, true, false, true><<<nb, NT3, 0, s>>>(a);
     else
       k_fine_sweep3d<T, true, false, false><<<nb, NT3, 0, s>>>(a);
+  } else if (kSweepW32) {
+    if (pend)
+      k_sweep3d_w32<T, false, true><<<nb, NT3, 0, s>>>(a);
+    else
+      k_sweep3d_w32<T, false, false><<<nb, NT3, 0, s>>>(a);
   } else {
     if (pend)
       k_fine_sweep3d<T, false, false, true><<<nb, NT3, 0, s>>>(a);
@@ -899,7 +1194,8 @@ hipError_t launch_fine_sweep(int d, const LevelView<T>& F, const LevelView<T>& C
     Sweep3dArgs<T> a{uin, uout, b, C.S, C.u, C.rr, C.bt, F.eps, partials, F.h, omega, F.hd, rts,
                      n, F.nv, C.n, C.nv, F.nb, F.bs, tz, ntx, ntz, damping, apply_pending,
                      0, nullptr, nullptr, nullptr, nullptr, T(0), T(1)};
-    (void)launch_sweep3d<T>(a, var, s);
+    const hipError_t e = launch_sweep3d<T>(a, var, s);
+    if (e != hipSuccess) return e;
     *nparts = int(nb);
   }
   return hipGetLastError();
