@@ -373,7 +373,7 @@ def main():
                    "rhs": "N(0,1) seed 0"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_fine_sweep3d", "kernel_avg_us": kavg_s * 1e6,
+                     "kernel": "k_sweep3d_w32", "kernel_avg_us": kavg_s * 1e6,
                      "algorithmic_bytes_per_launch": kbytes, "launches": nlaunch,
                      "copy_gbs": copy_gbs["kernel"], "memcpy_gbs": copy_gbs["memcpy"],
                      "frac_of_copy": achieved / copy_gbs["kernel"],

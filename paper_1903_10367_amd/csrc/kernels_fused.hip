@@ -72,6 +72,30 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
   return x * q + min(x, rem) + k;
 }
 
+// The tile's block of a coarse-level array (CW x CW x nsz values from (cbx, cby, cbz), zero off
+// the lattice of nc + 1 vertices per axis) into LDS.  Every lane issues all its loads before the
+// first is needed (addresses clamped into the lattice), so the block costs one memory round
+// trip, not one per lane slot.
+template <typename T, int NTH>
+__device__ __forceinline__ void stage_coarse_block(T* Sb, const T* __restrict__ S, int cbx, int cby, int cbz,
+                                                   int nsz, int nc, int tid) {
+  constexpr int NSB = ((MAXTZ / 3 + 3) * CW * CW + NTH - 1) / NTH;
+  const int nsb = nsz * CW * CW, nvc = nc + 1;
+  T sv[NSB];
+#pragma unroll
+  for (int k = 0; k < NSB; ++k) {
+    const int i = tid + k * NTH;
+    const int lx = i % CW, ly = (i / CW) % CW, lz = i / (CW * CW);
+    const int cx = cbx + lx, cy = cby + ly, cz = cbz + lz;
+    const int cxc = min(max(cx, 0), nc), cyc = min(max(cy, 0), nc), czc = min(max(cz, 0), nc);
+    const T v = S[(size_t(czc) * nvc + cyc) * nvc + cxc];
+    sv[k] = (i < nsb && cx == cxc && cy == cyc && cz == czc) ? v : T(0);
+  }
+#pragma unroll
+  for (int k = 0; k < NSB; ++k)
+    if (tid + k * NTH < nsb) Sb[tid + k * NTH] = sv[k];
+}
+
 template <typename T>
 __device__ __forceinline__ T wlin(int o) {  // 1D d-linear restriction weight, |o| <= 2
   return o == 0 ? T(1) : (o == 1 || o == -1) ? T(2.0 / 3.0) : T(1.0 / 3.0);
@@ -309,15 +333,7 @@ __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_fine_sweep3d(S
   const T h = a.h;
   const Lattice<T> U(a.uin, latb), B(a.b, latb), UO(a.uout, latb);
 
-  if constexpr (PEND) {
-    for (int i = tid; i < nsz * CW * CW; i += NT3) {
-      const int lx = i % CW, ly = (i / CW) % CW, lz = i / (CW * CW);
-      const int cx = cbx + lx, cy = cby + ly, cz = cbz + lz;
-      T v = T(0);
-      if (cx >= 0 && cx <= nc && cy >= 0 && cy <= nc && cz >= 0 && cz <= nc) v = a.S[lin<3>(cx, cy, cz, nvc)];
-      Sb[i] = v;
-    }
-  }
+  if constexpr (PEND) stage_coarse_block<T, NT3>(Sb, a.S, cbx, cby, cbz, nsz, nc, tid);
 
   // this lane's u-ring column (loads are clamped into the lattice: values off the lattice only
   // feed residuals of non-dof vertices, which are discarded)
@@ -556,10 +572,11 @@ constexpr int kDppWaveShl1 = 0x130;
 
 template <typename T, bool COARSE, bool PEND>
 __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_sweep3d_w32(Sweep3dArgs<T> a) {
-  // newest u planes and their x-neighbour sums, one padding row above and below so that every
-  // lane reads its y neighbours in bounds (the padding only feeds lanes without residual duty)
-  __shared__ T Ub[3][NT3 + 2 * W2];
-  __shared__ T Xb[3][NT3 + 2 * W2];
+  // newest u planes with their x-neighbour sums as (u, sum) pairs (one 16-byte access each in
+  // FP64), one padding row above and below so that every lane reads its y neighbours in bounds
+  // (the padding only feeds lanes without residual duty)
+  typedef T T2 __attribute__((ext_vector_type(2)));
+  __shared__ T2 UX[3][NT3 + 2 * W2];
   __shared__ T Rb[3][W2 * RQ];           // residual planes
   __shared__ T Xw[3][RW * NCO];          // x passes
   __shared__ T Xm[3][RW * NCO];
@@ -582,15 +599,7 @@ __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_sweep3d_w32(Sw
   const T h = a.h;
   const Lattice<T> U(a.uin, latb), B(a.b, latb), UO(a.uout, latb);
 
-  if constexpr (PEND) {
-    for (int i = tid; i < nsz * CW * CW; i += NT3) {
-      const int lx = i % CW, ly = (i / CW) % CW, lz = i / (CW * CW);
-      const int cx = cbx + lx, cy = cby + ly, cz = cbz + lz;
-      T v = T(0);
-      if (cx >= 0 && cx <= nc && cy >= 0 && cy <= nc && cz >= 0 && cz <= nc) v = a.S[lin<3>(cx, cy, cz, nvc)];
-      Sb[i] = v;
-    }
-  }
+  if constexpr (PEND) stage_coarse_block<T, NT3>(Sb, a.S, cbx, cby, cbz, nsz, nc, tid);
 
   // this lane's ring column (loads clamped into the lattice: values off the lattice only feed
   // residuals of non-dof vertices, which are discarded)
@@ -662,16 +671,16 @@ __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_sweep3d_w32(Sw
         vnew += wy0 * (wx0 * s0[0] + wx1 * s0[1]) + wy1 * (wx0 * s0[CW] + wx1 * s0[CW + 1]);
       }
       xnew = lane_shift<kDppWaveShr1>(vnew) + lane_shift<kDppWaveShl1>(vnew);
-      Ub[K][W2 + tid] = vnew;
-      Xb[K][W2 + tid] = xnew;
+      UX[K][W2 + tid] = T2{vnew, xnew};
     }
     pu[K] = CK ? uload(min(p + 3, ze)) : U.ld(offb, unsigned(p + 3) * planeb);
     // (2) residual of plane z = p-2 from u planes p-3, p-2 (registers) and p-1 (slot K2 and the
     // lane's own newest values)
     if (!CK || (p - 1 >= zs && p - 1 <= ze)) {
       const int z = p - 2;
-      const T ay = Ub[K2][tid] + Ub[K2][tid + 2 * W2];
-      const T d4 = Xb[K2][tid] + Xb[K2][tid + 2 * W2];
+      const T2 ym = UX[K2][tid], yp = UX[K2][tid + 2 * W2];
+      const T ay = ym.x + yp.x;
+      const T d4 = ym.y + yp.y;
       const T f = T(2) * (xlast + ay) + d4;
       const T uz = own;
       const T au = h * (T(8.0 / 3.0) * uz - T(1.0 / 12.0) * ((T(2) * c1 + c2) + f));
@@ -858,15 +867,7 @@ __global__ void __launch_bounds__(NTD, VAREPS ? 4 : ADAFAC_DEFECT3D_MINWAVES) k_
   const Lattice<double> U(a.uin, latb), UO(a.uout, latb), B(a.b, latb);
   const Lattice<float> E(a.e, latf), R(a.r32, latf);
 
-  if constexpr (MODE == 2) {
-    for (int i = tid; i < nsz * CW * CW; i += NTD) {
-      const int lx = i % CW, ly = (i / CW) % CW, lz = i / (CW * CW);
-      const int cx = cbx + lx, cy = cby + ly, cz = cbz + lz;
-      float v = 0.f;
-      if (cx >= 0 && cx <= nc && cy >= 0 && cy <= nc && cz >= 0 && cz <= nc) v = a.S[lin<3>(cx, cy, cz, nvc)];
-      Sb[i] = v;
-    }
-  }
+  if constexpr (MODE == 2) stage_coarse_block<float, NTD>(Sb, a.S, cbx, cby, cbz, nsz, nc, tid);
   // u' ring column of this lane (clamped into the lattice)
   const int ui = tid < ND ? tid : 0;
   const int ux = x0 - 1 + ui % DW, uy = y0 - 1 + ui / DW;
