@@ -135,7 +135,7 @@ __device__ __attribute__((noinline)) void wg_defect(const BatchReq& R, const flo
 }
 
 // status after measuring iterate n with norms (s = sum h^d r^2, m = max |r|); lane 0 only
-__device__ __forceinline__ int judge(BatchState& S, double s, double m, double tol) {
+__device__ __forceinline__ int assess(BatchState& S, double s, double m, double tol) {
   const double l2 = sqrt(s);
   if (S.cycles == 0) S.r0 = l2;
   S.l2h = l2;
@@ -161,7 +161,7 @@ __device__ void serve(const BatchReq& R, BatchState& S, int budget, double* ws, 
       wg_reduce(s, m, ws, wm);
       if (tid == 0) {
         // the cycle that measured iterate n produced n+1: it is the result when n met the tolerance
-        const int st = judge(S, s, m, R.tol);
+        const int st = assess(S, s, m, R.tol);
         S.cur = 1 - cur;
         S.cycles += 1;
         S.status = st ? st : (S.cycles >= R.max_cycles ? 3 : 0);
@@ -170,7 +170,7 @@ __device__ void serve(const BatchReq& R, BatchState& S, int budget, double* ws, 
       wg_defect<D>(R, R.h32.ufine[S.cur], S.cycles > 0, s, m);
       wg_reduce(s, m, ws, wm);
       if (tid == 0) {
-        const int st = judge(S, s, m, R.tol);
+        const int st = assess(S, s, m, R.tol);
         S.cycles += 1;
         S.status = st ? st : (S.cycles >= R.max_cycles ? 3 : 0);
         *flag = S.status;

@@ -280,7 +280,7 @@ int launch_batched(adafac_server* s) {
   return ADAFAC_OK;
 }
 
-// Lane k: when its chunk has completed, judge the new cycles and finish or enqueue the next chunk.
+// Lane k: when its chunk has completed, assess the new cycles and finish or enqueue the next chunk.
 int service_lane(adafac_server* s, int k, bool wait, bool* done) {
   *done = false;
   if (!s->lane_busy[k]) return ADAFAC_OK;
