@@ -178,7 +178,9 @@ __device__ __forceinline__ void level_update_vertex(const LevelView<T>& C, const
                                                     const LevelView<T>& Cm, const RtSep<T>& rts, T omega,
                                                     T omega_t, T cscale, int damping, int gather, size_t i) {
   const int nv = C.nv, nvf = F.nv;
-  int x = int(i % nv), y = int((i / nv) % nv), z = D == 3 ? int(i / (size_t(nv) * nv)) : 0;
+  // coarse lattices stay far below 2^32 vertices: 32-bit index arithmetic
+  const unsigned iu = unsigned(i), nvu = unsigned(nv), q = iu / nvu;
+  const int x = int(iu - q * nvu), y = D == 3 ? int(q % nvu) : int(q), z = D == 3 ? int(q / nvu) : 0;
   if (!is_interior<D>(x, y, z, nv)) return;
   const bool jac = damping == ADAFAC_DAMP_JAC;
   T uv, rr, bt;

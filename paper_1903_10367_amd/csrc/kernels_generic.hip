@@ -131,12 +131,14 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_levels(SmallLevelsArgs<
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_prolong_add(LevelView<T> F, LevelView<T> C, T* __restrict__ dst,
                                                      const T* __restrict__ src, const T* __restrict__ sub) {
-  const int nv = F.nv;
-  const size_t nverts = D == 2 ? size_t(nv) * nv : size_t(nv) * nv * nv;
-  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  // lattices here stay below 2^32 vertices (the launcher checks): 32-bit index arithmetic
+  const unsigned nv = unsigned(F.nv);
+  const unsigned nverts = D == 2 ? nv * nv : nv * nv * nv;
+  const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nverts) return;
-  int x = int(i % nv), y = int((i / nv) % nv), z = D == 3 ? int(i / (size_t(nv) * nv)) : 0;
-  if (!is_interior<D>(x, y, z, nv)) return;
+  const unsigned q = i / nv;
+  const int x = int(i - q * nv), y = D == 3 ? int(q % nv) : int(q), z = D == 3 ? int(q / nv) : 0;
+  if (!is_interior<D>(x, y, z, int(nv))) return;
   dst[i] += prolong_value<T, D>(F, C, x, y, z, src, sub);
 }
 
@@ -220,6 +222,7 @@ hipError_t launch_level_update(int d, const LevelView<T>& C, const LevelView<T>&
                                const RtSep<T>& rt, T omega, T omega_t, T cscale, int damping, int gather,
                                hipStream_t s) {
   size_t nverts = d == 2 ? size_t(C.nv) * C.nv : size_t(C.nv) * C.nv * C.nv;
+  if (nverts >= (size_t(1) << 32)) return hipErrorInvalidValue;
   unsigned nb = unsigned((nverts + 255) / 256);
   if (d == 2)
     k_level_update<T, 2><<<nb, 256, 0, s>>>(C, F, Cm, rt, omega, omega_t, cscale, damping, gather);
@@ -232,6 +235,7 @@ template <typename T>
 hipError_t launch_prolong_add(int d, const LevelView<T>& F, const LevelView<T>& C, T* dst, const T* src,
                               const T* sub, hipStream_t s) {
   size_t nverts = d == 2 ? size_t(F.nv) * F.nv : size_t(F.nv) * F.nv * F.nv;
+  if (nverts >= (size_t(1) << 32)) return hipErrorInvalidValue;
   unsigned nb = unsigned((nverts + 255) / 256);
   if (d == 2)
     k_prolong_add<T, 2><<<nb, 256, 0, s>>>(F, C, dst, src, sub);
