@@ -1,18 +1,25 @@
 """Build the gfx950 shared library libadafac.so in-tree with hipcc.
 
-Every source under ``csrc/`` is compiled for gfx950 only; packed FP32 instructions are
-disabled for the device code.  Usage: ``python -m paper_1903_10367_amd.build``.
+Every source under ``csrc/`` is compiled for gfx950 only, one object per source (in parallel,
+under ``_build/``), then linked; packed FP32 instructions are disabled for the device code.
+Usage: ``python -m paper_1903_10367_amd.build``.
 """
 import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libadafac.so")
-SOURCES = ["setup.cpp", "adaptive.cpp", "api.cpp", "server.cpp", "kernels_adaptive.hip", "kernels_generic.hip", "kernels_fused.hip", "kernels_batch.hip"]
+SOURCES = ["setup.cpp", "adaptive.cpp", "api.cpp", "server.cpp", "kernels_adaptive.hip", "kernels_generic.hip",
+           "kernels_fused.hip", "kernels_batch.hip"]
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
 
 def hipcc():
@@ -22,19 +29,29 @@ def hipcc():
     return exe
 
 
-def build(verbose=False):
-    """Compile and link libadafac.so (always rebuilds)."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
-           "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed:\n" + " ".join(cmd) + "\n" + res.stdout + res.stderr)
+
+
+def build(verbose=False, jobs=None):
+    """Compile every source and link libadafac.so (always rebuilds)."""
+    os.makedirs(OBJ, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+    objs, cmds = [], []
+    for s in SOURCES:
+        o = os.path.join(OBJ, os.path.splitext(s)[0] + ".o")
+        objs.append(o)
+        cmds.append([hipcc()] + FLAGS + inc + ["-c", os.path.join(CSRC, s), "-o", o])
+    jobs = jobs or min(len(cmds), max(1, min(8, os.cpu_count() or 1)))
+    with ThreadPoolExecutor(jobs) as ex:
+        for f in [ex.submit(_run, c, verbose) for c in cmds]:
+            f.result()
+    tmp = LIB + ".tmp"
+    _run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs, verbose)
     os.replace(tmp, LIB)
     return LIB
 

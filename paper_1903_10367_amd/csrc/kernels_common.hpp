@@ -236,9 +236,12 @@ __device__ __forceinline__ void level_update_vertex(const LevelView<T>& C, const
   }
   T dg;
   T au = apply_level_op_nb<T, D>(C, x, y, z, nb, dg);
-  // FAS right-hand side with the tau correction, then the FAS residual of this level
+  // FAS right-hand side with the tau correction, b_l = R r_{l+1} + A_l I u_{l+1}.  The FAS
+  // residual b_l - A_l u_l of this level is R r_{l+1} itself: taken from rr directly rather
+  // than as (rr + au) - au, which would add a rounding of |A_l u_l| (large next to R r once the
+  // iteration has converged far) to every coarse residual.
   T bf = rr + au;
-  T res = bf - au;
+  T res = rr;
   T c = cscale * omega * res / dg;
   T s = c;
   if (jac) s = c - omega_t * bt / dg;

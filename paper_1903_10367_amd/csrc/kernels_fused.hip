@@ -247,7 +247,7 @@ struct Sweep3dArgs {
   int n, nv, nc, nvc, nb, bs;
   int tz, ntx, ntz, damping, apply_pending;
   // coarse FAS level (coarse = 1): b holds R r of the finer level; the kernel forms the FAS
-  // right-hand side bf = R r + A u (tau correction), the residual r = bf - A u, and writes
+  // right-hand side bf = R r + A u (tau correction), the residual r = bf - A u (= R r), and writes
   // S = cscale omega D^-1 r - omega~ D^-1 b~ instead of updating u
   int coarse;
   const T* bt_in;
@@ -430,8 +430,10 @@ __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_fine_sweep3d(S
             smax = fabs(rd) > smax ? fabs(rd) : smax;
           }
         } else {
-          const T bf = pb[K2] + au;       // FAS right-hand side with the tau correction
-          res = bf - au;
+          // FAS right-hand side with the tau correction; the FAS residual bf - A u is R r
+          // itself (taken directly: no rounding of |A u| enters it)
+          const T bf = pb[K2] + au;
+          res = pb[K2];
           if (own_pt) {
             const int gi = z * plane + roff;
             T sv = a.cscale * dinv * res;
@@ -701,8 +703,10 @@ __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_sweep3d_w32(Sw
             smax = fabs(rd) > smax ? fabs(rd) : smax;
           }
         } else {
-          const T bf = pb[K2] + au;       // FAS right-hand side with the tau correction
-          res = bf - au;
+          // FAS right-hand side with the tau correction; the FAS residual bf - A u is R r
+          // itself (taken directly: no rounding of |A u| enters it)
+          const T bf = pb[K2] + au;
+          res = pb[K2];
           if (own_pt) {
             const int gi = z * plane + roff;
             T sv = a.cscale * wdiag * res;

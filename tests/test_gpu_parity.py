@@ -50,8 +50,9 @@ def oracle_floor(H, b, cycles, **kw):
 
 def assert_parity(hg, ug, ho, uo, tol=TOL, floor=None):
     """Norms: |gpu - oracle| <= 1e-12 of the initial norm, every cycle.  Solution: relative
-    2-norm error <= 1e-12, or, where the oracle's own rounding spread (``floor()``) is of that
-    size (smooth error modes of badly conditioned levels), <= 10 x that spread."""
+    2-norm error <= max(1e-12, 2 x the oracle's own rounding spread) (the reading of the
+    "1e-12 relative" bar near convergence: r = b - A u cancels, and two exact evaluations of
+    the same cycles differ by about eps times the condition number)."""
     assert len(hg) == len(ho)
     r0, m0 = ho[0]
     for n, (a, b) in enumerate(zip(hg, ho)):
@@ -61,7 +62,7 @@ def assert_parity(hg, ug, ho, uo, tol=TOL, floor=None):
     if err > tol and floor is not None:
         fl = floor()
         say(f"solution rel. error {err:.3e} above {tol:g}; oracle spread {fl:.3e}")
-        assert err <= 10 * fl, f"solution rel. error {err:.3e} vs oracle spread {fl:.3e}"
+        assert err <= 2 * fl, f"solution rel. error {err:.3e} vs oracle spread {fl:.3e}"
         return
     assert err <= tol, f"solution rel. error {err:.3e}"
 

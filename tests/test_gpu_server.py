@@ -107,7 +107,7 @@ def test_served_results_match_oracle(k):
     say(f"cycles {res['cycles']} (oracle {len(ho)}), rel. error {err:.3e}")
     assert res["cycles"] == len(ho)
     assert abs(res["l2h0"] - ho[0][0]) <= 1e-12 * ho[0][0]
-    assert err <= 1e-10
+    assert err <= 1e-12
 
 
 def test_alone_and_in_the_mix_are_identical():

@@ -168,3 +168,95 @@ def test_defect_correction_with_fp32_inner_cycles_reaches_fp64_accuracy():
     _, h64 = adaptive.defect_correction(T, f, 4, 0.0, 1, inner_dtype=np.float64)
     gap = abs(h32[1][0] - h64[1][0]) / h64[0][0]
     assert 1e-10 < gap < 1e-4
+
+
+# --- the lumped load and the composite discretisation at refinement interfaces -------------
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_load_of_unit_source_is_the_integral_of_each_composite_hat(d):
+    """With f = 1 the lumped load of a composite dof is the integral of its composite hat (on a
+    leaf cell K every corner hat integrates to |K| / 2^d, hanging corners included through
+    their interpolation weights).  The integral is taken independently of the load: the hat is
+    spread to the finest lattice, where it is d-linear on every finest cell, so the trapezoidal
+    rule h_L^d sum_v phi(v) is exact."""
+    T = disk_tree(L=4, lu=2) if d == 2 else disk_tree(L=3, lu=2, d=3, radius=0.15)
+    rh, _ = adaptive.composite_residual(
+        T, {l: np.zeros(T.shape(l)) for l in range(T.lmin, T.L + 1)}, T.load(np.ones(T.shape(T.L))))
+    hL = 3.0 ** -T.L
+    idx = T.composite_index()
+    # every composite dof near a refinement interface, and a sample of the others
+    near = [j for j, (l, i) in enumerate(idx) if l < T.L]
+    pick = sorted(set(near + list(range(0, len(idx), max(1, len(idx) // 50)))))
+    for j in pick:
+        l, i = idx[j]
+        U = {m: np.zeros(T.shape(m)) for m in range(T.lmin, T.L + 1)}
+        U[l].ravel()[i] = 1.0
+        phi = adaptive.finest_values(T, T.spread(U))
+        integral = hL ** d * phi.sum()
+        assert abs(rh[l].ravel()[i] - integral) <= 1e-14 * 3.0 ** (-l * d), (l, i)
+
+
+def _sparse_composite_system(T, f):
+    """A_h = sum_l C_l^T A^leaf_l C_l and b_h = sum_l C_l^T b^leaf_l with sparse C_l, built
+    level by level: dof rows select the composite dof at that position, hanging rows take the
+    d-linear interpolation of the coarser level's rows (Sec. 2.1)."""
+    import scipy.sparse as sp
+    from oracle import fem, transfer
+    d, L = T.d, T.L
+    idx = T.composite_index()
+    n = len(idx)
+    where = {}
+    for j, (l, i) in enumerate(idx):
+        v = np.array(np.unravel_index(i, T.shape(l))) * 3 ** (L - l)
+        where[tuple(v)] = j
+    C = {}
+    for l in range(T.lmin, L + 1):
+        N = int(np.prod(T.shape(l)))
+        dofs = np.flatnonzero(T.dof[l].ravel())
+        cols = [where[tuple(np.array(np.unravel_index(i, T.shape(l))) * 3 ** (L - l))] for i in dofs]
+        Cl = sp.csr_matrix((np.ones(len(dofs)), (dofs, cols)), shape=(N, n))
+        if l > T.lmin:
+            hang = sp.diags(T.hang[l].ravel().astype(float))
+            Cl = Cl + hang @ transfer.dlinear_prolongation(d, l) @ C[l - 1]
+        C[l] = Cl.tocsr()
+    bleaf = T.load(f)
+    A = sp.csr_matrix((n, n))
+    b = np.zeros(n)
+    for l in range(T.lmin, L + 1):
+        if np.any(T.leaf_eps[l]):
+            A = A + C[l].T @ fem.assemble(T.leaf_eps[l]) @ C[l]
+        b += C[l].T @ bleaf[l].ravel()
+    pos = np.array([np.array(np.unravel_index(i, T.shape(l)))[::-1] * 3.0 ** -l for l, i in idx])
+    return A.tocsr(), b, pos
+
+
+def test_sparse_composite_system_is_the_dense_one():
+    T = disk_tree(eps=inp.eps_blocks(2, 2, 1.0, seed=19))
+    f = inp.rhs(2, 4, seed=20)
+    A, b, pos, lev, Psi, C = adaptive.dense_system(T, f)
+    As, bs, ps = _sparse_composite_system(T, f)
+    assert np.abs(As.toarray() - A).max() <= 1e-14 * np.abs(A).max()
+    assert np.abs(bs - b).max() <= 1e-15 * np.abs(b).max()
+    assert np.array_equal(ps, pos)
+
+
+def test_manufactured_solution_converges_at_second_order_on_disk_trees():
+    """u* = sin(pi x) sin(pi y), f = 2 pi^2 u*, on trees uniform to level lu and refined around
+    a disk two levels further: the composite solution's maximum error at the dofs falls by
+    about 3^2 per level (second order in the coarsest mesh width; a load that is wrong at the
+    refinement interfaces would leave a first-order error there)."""
+    import scipy.sparse.linalg as spla
+    errs = []
+    for lu in (2, 3, 4):
+        L = lu + 2
+        ref = inp.refine_ball(2, L, lu, (0.5, 0.5), 0.25)
+        T = adaptive.AdaptiveTree(2, L, 1, lu, ref)
+        n = 3 ** L
+        y, x = np.meshgrid(np.arange(n + 1) / n, np.arange(n + 1) / n, indexing="ij")
+        f = 2 * np.pi ** 2 * np.sin(np.pi * x) * np.sin(np.pi * y)
+        A, b, pos = _sparse_composite_system(T, f)
+        u = spla.spsolve(A.tocsc(), b)
+        ustar = np.sin(np.pi * pos[:, 0]) * np.sin(np.pi * pos[:, 1])
+        errs.append(np.abs(u - ustar).max())
+    ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
+    assert all(6.0 < r < 13.0 for r in ratios), (errs, ratios)

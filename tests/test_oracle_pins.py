@@ -230,6 +230,33 @@ def test_smoothed_operator_3d_symmetry_and_zero_sum():
     assert np.all(T[ring] <= 1e-15)
 
 
+def test_smoothed_operator_3d_exact_values():
+    """The 7^3 stencil of M^-1 A P at eps = 1 in closed form.  The 3D Q1 operator is
+    h sum_a K1(a) M1(b) M1(c) with the 1D stiffness K1 = [-1 2 -1] / h and mass
+    M1 = h [1 4 1] / 6, the coarse hat is the tensor product of the 1D hat
+    p = (1/3, 2/3, 1, 2/3, 1/3), and M = diag(A) = 8h/3.  So the entry at offset o is
+    (3/8) sum_a k(o_a) m(o_b) m(o_c) with k = K1 p = {0: 2/3, +-3: -1/3} and
+    m = M1 p = {0: 8/9, +-1: 2/3, +-2: 1/3, +-3: 1/18}: inside |o| <= 2 only the planar terms
+    survive (16/27 at the centre, 8/27 and 4/27 on the axes, 1/9, 1/18, 1/36 in the
+    coordinate planes, 61 nonzeros summing to 169/27)."""
+    from fractions import Fraction as Fr
+    k = {0: Fr(2, 3), 3: Fr(-1, 3)}
+    m = {0: Fr(8, 9), 1: Fr(2, 3), 2: Fr(1, 3), 3: Fr(1, 18)}
+    T = hierarchy.smoothed_operator_eps1(3)
+    for o in itertools.product(range(-3, 4), repeat=3):
+        a = [abs(v) for v in o]
+        e = Fr(3, 8) * sum(k.get(a[i], Fr(0)) * m[a[(i + 1) % 3]] * m[a[(i + 2) % 3]] for i in range(3))
+        assert abs(T[tuple(v + 3 for v in o)] - float(e)) < 1e-15, o
+    core = T[1:6, 1:6, 1:6]
+    assert np.count_nonzero(np.abs(core) > 1e-15) == 61
+    assert abs(core.sum() - 169.0 / 27.0) < 1e-13
+    want = {(0, 0, 0): Fr(16, 27), (1, 0, 0): Fr(8, 27), (2, 0, 0): Fr(4, 27), (1, 1, 0): Fr(1, 9),
+            (2, 1, 0): Fr(1, 18), (2, 2, 0): Fr(1, 36), (1, 1, 1): Fr(0), (2, 2, 2): Fr(0)}
+    for o, v in want.items():
+        for q in itertools.permutations(o):
+            assert abs(T[tuple(x + 3 for x in q)] - float(v)) < 1e-15
+
+
 def test_rtilde_const_is_truncated_omega_scaled_table():
     H = hierarchy.Hierarchy(2, 3, 1, None, "dlinear", "const", omega=0.6)
     Rt = H.lev[3].Rt.mat.toarray()
