@@ -59,6 +59,10 @@ extern "C" {
 #define ADAFAC_DAMP_EXP 3    /* exponential damping omega_hat^(L-l) */
 /* the smoothed restriction R~ = omega R A M^-1 truncated to P's support (Sec. 3.2) */
 #define ADAFAC_RTILDE_CONST_EPS1 0 /* from the eps = 1 operator, the same on every level */
+#define ADAFAC_RTILDE_OPERATOR 1   /* omega trunc(P^T A_l D_l^-1) of the level's own operator and
+                                      transfer, stored per coarse vertex (5^dim weights; the
+                                      storage the paper's Sec. 4.1 notes); uniform trees only, and
+                                      it runs the one-kernel-per-step form of the cycle */
 /* arithmetic of the cycle (spec precision form) */
 #define ADAFAC_PREC_FP64 0
 #define ADAFAC_PREC_FP32_REFINED 1 /* FP32 cycles inside FP64 defect correction */
@@ -232,7 +236,10 @@ int adafac_get_level(adafac_ctx* ctx, int level, int which, double* out, size_t 
  * 2 = prolongation weights from level l-1 into level l, 2^dim per fine vertex for the
  * corners of the coarse cell floor(x/3) clamped to the last cell (Sec. 2.5; d-linear or
  * BoxMG), n = 2^dim (3^l+1)^dim, l > l_min, 3 = the R~ weights times omega on the 5^dim
- * offsets (Sec. 3.2), n = 5^dim, level ignored.  ESTATE before build_operators. */
+ * offsets (Sec. 3.2), n = 5^dim, level ignored, 4 = the OPERATOR R~ restricting level l+1
+ * into level l (l_min <= l < l_max): 5^dim weights per level-l vertex, offset index
+ * (ox+2) + 5 (oy+2) + 25 (oz+2) of the fine vertex 3v + o, n = 5^dim (3^l+1)^dim (ESTATE
+ * unless built with ADAFAC_RTILDE_OPERATOR).  ESTATE before build_operators. */
 int adafac_host_operator(const adafac_ctx* ctx, int level, int which, double* out, size_t n);
 
 /* Sum over levels of the dofs (3^l - 1)^dim: the vertex updates of one cycle. */
@@ -247,6 +254,36 @@ int adafac_kernel_time(adafac_ctx* ctx, double* total_ms, int* launches);
 
 void adafac_destroy(adafac_ctx* ctx);
 const char* adafac_last_error(const adafac_ctx* ctx);
+
+/* Right-hand side given as a function (problem statement, Sec. 1): f(x, user) with x the
+ * dim coordinates of a point of the unit square/cube (x first).  It is evaluated, on the
+ * calling thread, at every vertex where the lumped load is formed, during adafac_bind (and
+ * adafac_regrid when the prepared tree keeps this source); f and user must stay valid until
+ * then.  Replaces a lattice or Gaussian source.  EINVAL on a null f. */
+int adafac_set_rhs_fn(adafac_ctx* ctx, double (*f)(const double* x, void* user), void* user);
+
+/* Residual norms of iterate `cycle` divided by those of iterate 0 (the iterate at bind or
+ * set_solution): the normalised residual of Sec. 5, ||r^(n)||_h / ||r^(0)||_h and
+ * max|r^(n)| / max|r^(0)| (0 when the initial norm is 0).  Synchronises.  EINVAL if the
+ * cycle has not run. */
+int adafac_residual_normalised(adafac_ctx* ctx, int cycle, double* l2h_rel, double* linf_rel);
+
+/* Positions of the composite degrees of freedom (Sec. 2.1: every position's finest dof) in
+ * the composite order used by adafac_get_composite / adafac_set_composite: uniform trees the
+ * interior vertices of the finest level in lattice order (x fastest); adaptive trees level by
+ * level from l_min, each level's composite dofs in lattice order.  xyz (may be NULL) receives
+ * dim coordinates per dof (x first), level (may be NULL) the dof's level.  n must equal
+ * adafac_composite_dofs.  No GPU involved.  ESTATE before build_operators. */
+int adafac_dof_coords(const adafac_ctx* ctx, double* xyz, int* level, size_t n);
+
+/* Current iterate at the composite dofs, in the order of adafac_dof_coords (n =
+ * adafac_composite_dofs).  Synchronises.  EINVAL on a wrong n. */
+int adafac_get_composite(adafac_ctx* ctx, double* u, size_t n);
+
+/* Replace the iterate by composite dof values in that order (warm start); clears the
+ * residual history as adafac_set_solution.  Synchronises.  EINVAL on a wrong n or
+ * non-finite values. */
+int adafac_set_composite(adafac_ctx* ctx, const double* u, size_t n);
 
 /* Reference streaming copy for roofline context (not part of the method): copies
  * `bytes` from device memory src to device memory dst on `stream` (a hipStream_t;

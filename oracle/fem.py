@@ -19,28 +19,30 @@ import scipy.sparse as sp
 def ref_stiffness(d):
     """Element stiffness of the d-linear element on the unit cell.
 
-    K[i, j] = integral over [0,1]^d of grad(phi_i) . grad(phi_j), evaluated
-    with 2-point Gauss-Legendre quadrature per axis, which is exact because
-    each factor is of degree <= 2 in every variable.  Corner ``i`` has shape
-    function prod_k (x_k if bit k of i else 1 - x_k).
+    K[i, j] = integral over [0,1]^d of grad(phi_i) . grad(phi_j), where corner ``i`` has shape
+    function prod_k (x_k if bit k of i else 1 - x_k).  The integrand is a sum over the
+    derivative axis k of products of one-variable factors, so the integral is
+    sum_k d_k(i) d_k(j) prod_{m != k} int_0^1 f_i^m f_j^m dx with d_k = +-1 the derivative of
+    the k-th factor and int x x = int (1-x)(1-x) = 1/3, int x (1-x) = 1/6.  It is evaluated in
+    exact rational arithmetic and rounded once per entry, so the entries are the correctly
+    rounded 2/3, -1/6, -1/3 (2D) and 1/3, 0, -1/12 (3D): the assembled interior rows then sum
+    to exactly zero, as the exact operator's do (a quadrature in floating point leaves a row
+    sum of a few ulp, an artificial zero-order term that the smoothest modes feel).
     """
-    g = np.array([0.5 - 0.5 / np.sqrt(3.0), 0.5 + 0.5 / np.sqrt(3.0)])
-    w = np.array([0.5, 0.5])
+    from fractions import Fraction
     nc = 2 ** d
     K = np.zeros((nc, nc))
-    for q in itertools.product(range(2), repeat=d):
-        x = [g[a] for a in q]
-        wq = np.prod([w[a] for a in q])
-        grads = np.zeros((nc, d))
-        for i in range(nc):
-            bits = [(i >> k) & 1 for k in range(d)]
+    for i in range(nc):
+        for j in range(nc):
+            s = Fraction(0)
             for k in range(d):
-                dv = 1.0 if bits[k] else -1.0
+                bi, bj = (i >> k) & 1, (j >> k) & 1
+                term = Fraction(1 if bi == bj else -1)
                 for m in range(d):
                     if m != k:
-                        dv *= x[m] if bits[m] else (1.0 - x[m])
-                grads[i, k] = dv
-        K += wq * grads @ grads.T
+                        term *= Fraction(1, 3) if ((i >> m) & 1) == ((j >> m) & 1) else Fraction(1, 6)
+                s += term
+            K[i, j] = float(s)
     return K
 
 

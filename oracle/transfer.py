@@ -26,7 +26,7 @@ def linear_1d(nc):
     rows, cols, vals = [], [], []
     for i in range(nf + 1):
         c, s = divmod(i, 3)
-        rows.append(i); cols.append(c); vals.append(1.0 - s / 3.0)
+        rows.append(i); cols.append(c); vals.append((3 - s) / 3.0)
         if s:
             rows.append(i); cols.append(c + 1); vals.append(s / 3.0)
     return sp.csr_matrix((vals, (rows, cols)), shape=(nf + 1, nc + 1))

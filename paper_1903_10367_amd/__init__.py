@@ -10,7 +10,7 @@ import ctypes as C
 import numpy as np
 
 from . import _abi
-from ._abi import AdafacError, DAMPING, LEVEL_ARRAY, PRECISION, TRANSFER
+from ._abi import AdafacError, DAMPING, LEVEL_ARRAY, PRECISION, RTILDE, TRANSFER
 
 __all__ = ["Solver", "Server", "AdafacError", "lib", "stream_copy"]
 
@@ -47,12 +47,15 @@ class Solver:
     """One adAFAC solve on a uniform 3:1 spacetree of dimension ``dim`` with levels lmin..lmax.
 
     ``eps_blocks``: coefficient on the (3^k)^dim cells of level k (None: Poisson);
-    ``f``: right-hand side samples on the (3^lmax + 1)^dim finest vertices.
+    ``f``: right-hand side samples on the (3^lmax + 1)^dim finest vertices, a callable
+    f(x) of the dim coordinates (x first), or {"gaussian": (centre, sigma, amplitude)};
+    ``rtilde``: "const" (the eps = 1 smoothed restriction) or "operator" (built per vertex from
+    the level's own operator).
     """
 
     def __init__(self, dim, lmin, lmax, f, eps_blocks=None, transfer="dlinear", damping="jac",
                  precision="fp64", inner_k=4, fused=True, omega=0.6, omega_tilde=0.6, omega_hat=0.5,
-                 device=None, stream=None, refine=None, ball=None):
+                 device=None, stream=None, refine=None, ball=None, rtilde="const"):
         """``refine``: {level: flags over the (3^level)^dim cells} of an adaptive tree;
         ``ball``: (centre, radius, l_from) refinement around a ball (adaptive tree)."""
         import torch
@@ -73,6 +76,10 @@ class Solver:
             centre, sigma, amp = f["gaussian"]
             cc = np.ascontiguousarray(centre, dtype=np.float64)
             _check(self.L, ctx, self.L.adafac_set_rhs_gaussian(ctx, _dptr(cc), sigma, amp))
+        elif callable(f):
+            fn = f
+            self._rhs_cb = _abi.RHS_FN(lambda x, user: float(fn(tuple(x[a] for a in range(dim)))))
+            _check(self.L, ctx, self.L.adafac_set_rhs_fn(ctx, self._rhs_cb, None))
         else:
             fa = np.ascontiguousarray(f, dtype=np.float64).ravel()
             _check(self.L, ctx, self.L.adafac_set_rhs_lattice(ctx, _dptr(fa), fa.size))
@@ -87,6 +94,7 @@ class Solver:
         o = _abi.Opts()
         self.L.adafac_default_opts(C.byref(o))
         o.transfer, o.damping, o.precision = TRANSFER[transfer], DAMPING[damping], PRECISION[precision]
+        o.rtilde = RTILDE[rtilde]
         o.inner_k, o.fused = inner_k, int(bool(fused))
         o.omega, o.omega_tilde, o.omega_hat = omega, omega_tilde, omega_hat
         _check(self.L, ctx, self.L.adafac_build_operators(ctx, C.byref(o)))
@@ -116,6 +124,29 @@ class Solver:
 
     def residuals(self):
         return [self.residual(i) for i in range(self.L.adafac_cycles_run(self.ctx))]
+
+    def residual_normalised(self, i):
+        a, b = C.c_double(), C.c_double()
+        _check(self.L, self.ctx, self.L.adafac_residual_normalised(self.ctx, i, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def dof_coords(self):
+        """(positions (n, dim), levels (n,)) of the composite dofs, in composite order."""
+        n = self.composite_dofs()
+        xyz = np.empty((n, self.dim))
+        lev = np.empty(n, dtype=np.int32)
+        _check(self.L, self.ctx, self.L.adafac_dof_coords(self.ctx, _dptr(xyz), lev.ctypes.data_as(C.POINTER(C.c_int)),
+                                                          n))
+        return xyz, lev
+
+    def composite(self):
+        u = np.empty(self.composite_dofs())
+        _check(self.L, self.ctx, self.L.adafac_get_composite(self.ctx, _dptr(u), u.size))
+        return u
+
+    def set_composite(self, u):
+        u = np.ascontiguousarray(u, dtype=np.float64).ravel()
+        _check(self.L, self.ctx, self.L.adafac_set_composite(self.ctx, _dptr(u), u.size))
 
     def solution(self):
         u = np.empty(self.nvert)

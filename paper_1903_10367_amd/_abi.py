@@ -8,6 +8,7 @@ LIB_PATH = os.path.join(HERE, "libadafac.so")
 OK, EINVAL, ESTATE, ENOMEM, EDEVICE, EDIVERGED, EAGAIN, EUNSUPPORTED = 0, 1, 2, 3, 4, 5, 6, 7
 REQ_STATUS = {0: "queued", 1: "running", 2: "converged", 3: "diverged", 4: "capped", 5: "failed"}
 TRANSFER = {"dlinear": 0, "boxmg": 1}
+RTILDE = {"const": 0, "operator": 1}
 DAMPING = {"jac": 0, "pi": 1, "none": 2, "exp": 3}
 PRECISION = {"fp64": 0, "fp32_refined": 1}
 LEVEL_ARRAY = {"u": 0, "b": 1, "btilde": 2, "r": 3, "S": 4}
@@ -22,8 +23,13 @@ EXPORTS = [
     "adafac_regrid_prepare", "adafac_regrid", "adafac_set_rhs_gaussian",
     "adafac_server_default_cfg", "adafac_server_create", "adafac_server_submit", "adafac_server_step",
     "adafac_server_poll", "adafac_server_fetch", "adafac_server_destroy", "adafac_server_last_error",
-    "adafac_stream_copy",
+    "adafac_stream_copy", "adafac_set_rhs_fn", "adafac_residual_normalised", "adafac_dof_coords",
+    "adafac_get_composite", "adafac_set_composite",
 ]
+
+
+# double f(const double* x, void* user)
+RHS_FN = C.CFUNCTYPE(C.c_double, C.POINTER(C.c_double), C.c_void_p)
 
 
 class Opts(C.Structure):
@@ -105,6 +111,11 @@ def lib():
         "adafac_server_destroy": (None, [P]),
         "adafac_server_last_error": (C.c_char_p, [P]),
         "adafac_stream_copy": (C.c_int, [P, P, C.c_size_t, P]),
+        "adafac_set_rhs_fn": (C.c_int, [P, RHS_FN, P]),
+        "adafac_residual_normalised": (C.c_int, [P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+        "adafac_dof_coords": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_size_t]),
+        "adafac_get_composite": (C.c_int, [P, C.POINTER(C.c_double), C.c_size_t]),
+        "adafac_set_composite": (C.c_int, [P, C.POINTER(C.c_double), C.c_size_t]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

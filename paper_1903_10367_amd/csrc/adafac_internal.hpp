@@ -23,6 +23,8 @@ struct HostLevel {
   std::vector<double> st;          // stored operator: 3^d entries per vertex (offset index o_x+3 o_y+9 o_z)
   std::vector<double> dg;          // diagonal of the operator (every level)
   std::vector<double> pw;          // transfer from level-1 to this level: 2^d weights per vertex, or empty = d-linear
+  std::vector<double> rtw;         // OPERATOR R~ restricting the next finer level into this one: 5^d
+                                   // weights per vertex (offset index (ox+2) + 5 (oy+2) + 25 (oz+2)), or empty
 };
 
 struct HostOps {
@@ -39,9 +41,10 @@ struct HostOps {
 };
 
 // Builds every operator of the hierarchy (FEM fine levels, BoxMG or d-linear
-// transfers, Galerkin coarse operators below the coefficient-block level, R~).
+// transfers, Galerkin coarse operators below the coefficient-block level, R~; with
+// rtilde_operator also the per-vertex R~ = omega trunc(P^T A D^-1) of every level below L).
 // Returns an empty string on success, else a message.
-std::string build_host_ops(HostOps& ops, int transfer_boxmg, double omega);
+std::string build_host_ops(HostOps& ops, int transfer_boxmg, double omega, int rtilde_operator = 0);
 
 // Q1 stencil entry of a FEM level for vertex v and neighbour offset o (used by tests of the setup).
 double fem_stencil_entry(const HostOps& ops, int level, const int* v, const int* o);
@@ -69,6 +72,7 @@ struct LevelView {
   T* r;                      // level residual
   T* S;                      // accumulated correction
   T* ic;                     // adAFAC-PI: injected correction of the next finer level
+  const T* rtw;              // OPERATOR R~ into this level: 5^d weights per vertex, or nullptr (eps = 1 stencil)
 };
 
 // Tensor-product factors of R~ handed to the kernels.

@@ -128,6 +128,8 @@ struct adafac_ctx {
   float* ad_eps32 = nullptr;
   // right-hand side: a lattice (set_rhs_lattice) or a Gaussian source (set_rhs_gaussian)
   int src_gauss = 0;
+  double (*src_fn)(const double*, void*) = nullptr;   // set_rhs_fn: f evaluated where the load is formed
+  void* src_user = nullptr;
   double src_c[3] = {0, 0, 0}, src_sigma = 1.0, src_amp = 1.0;
   double next_src_c[3] = {0, 0, 0};
   AdaptHost at_next;                    // regrid: the prepared tree, its right-hand side and size
@@ -166,8 +168,12 @@ bool mixed(const adafac_ctx* c) { return c->opts.precision == ADAFAC_PREC_FP32_R
 // f at the finest-lattice point (gx, gy, gz)
 double source_at(const adafac_ctx* c, size_t gx, size_t gy, size_t gz) {
   const size_t nL = size_t(ipow3(c->L)) + 1;
-  if (!c->src_gauss) return c->f[(gz * nL + gy) * nL + gx];
   const double h = 1.0 / double(nL - 1);
+  if (c->src_fn) {
+    const double x[3] = {gx * h, gy * h, gz * h};
+    return c->src_fn(x, c->src_user);
+  }
+  if (!c->src_gauss) return c->f[(gz * nL + gy) * nL + gx];
   const double x[3] = {gx * h, gy * h, gz * h};
   double r2 = 0.0;
   for (int a = 0; a < c->dim; ++a) r2 += (x[a] - c->src_c[a]) * (x[a] - c->src_c[a]);
@@ -221,6 +227,7 @@ size_t layout(adafac_ctx* c, char* base) {
         v.r = reinterpret_cast<T*>(take(sizeof(T) * nvx));
         v.S = reinterpret_cast<T*>(take(sizeof(T) * nvx));
         v.ic = reinterpret_cast<T*>(take(sizeof(T) * nvx));
+        if (!hl.rtw.empty()) v.rtw = reinterpret_cast<T*>(take(sizeof(T) * hl.rtw.size()));
       }
     }
     const size_t nvL = c->ops.lev[c->L].nverts;
@@ -301,8 +308,10 @@ int run_cycle(adafac_ctx* c, Hier<T>& H, double* norm_out, const T* uin_zero) {
   LevelView<T> Lm1 = L > lmin ? H.v[L - 1] : LevelView<T>{};
   int nparts = kNormBlocks;
   int rc;
-  // adAFAC-PI reads and writes the injected fine correction in the same sweep: one kernel per step
-  const bool fused = o.fused && L > lmin && !pi && fused_ok(c);
+  // adAFAC-PI reads and writes the injected fine correction in the same sweep, and the stored
+  // R~ of the OPERATOR form is a per-vertex gather: one kernel per step for both
+  const bool opr = o.rtilde == ADAFAC_RTILDE_OPERATOR;
+  const bool fused = o.fused && L > lmin && !pi && !opr && fused_ok(c);
   const bool pend = H.pending && !uin_zero;
   if ((rc = record_start(c))) return rc;
   if (fused) {
@@ -319,7 +328,7 @@ int run_cycle(adafac_ctx* c, Hier<T>& H, double* norm_out, const T* uin_zero) {
   for (int l = lmin; l < L && l - lmin < kMaxSmall && nverts_of(d, l) <= kSmallVerts; ++l) hi = l;
   bool fed = fused;               // level l's u, R r and R~ r already written by the finer level
   for (int l = L - 1; l > hi; --l) {
-    const bool sweep = !pi && fed && l > lmin && H.v[l].n >= kCoarseSweepMinN &&
+    const bool sweep = !pi && !opr && fed && l > lmin && H.v[l].n >= kCoarseSweepMinN &&
                        sweep_level_ok(d, H.v[l].n, H.v[l].fem, H.v[l].pw != nullptr);
     if (sweep) {
       HIPCHK(c, launch_coarse_sweep<T>(d, H.v[l], H.v[l - 1], H.rts, omega, omega_t, cscale_of(l), damping,
@@ -665,6 +674,7 @@ int upload_ops(adafac_ctx* c, Hier<T>& H, bool coarse) {
       if ((rc = put(const_cast<T*>(v.dg), hl.dg))) return rc;
     }
     if (!hl.pw.empty() && (rc = put(const_cast<T*>(v.pw), hl.pw))) return rc;
+    if (v.rtw && (rc = put(const_cast<T*>(v.rtw), hl.rtw))) return rc;
     (void)ns;
   }
   for (int i = 0; i < 5; ++i) H.rts.m[i] = T(c->ops.rt_m[i]);
@@ -677,6 +687,7 @@ int upload_ops(adafac_ctx* c, Hier<T>& H, bool coarse) {
 int build_adaptive(adafac_ctx* c) {
   const adafac_opts& o = c->opts;
   if (o.transfer != ADAFAC_TRANSFER_DLINEAR) return fail(c, ADAFAC_EUNSUPPORTED, "adaptive trees use d-linear transfers");
+  if (o.rtilde != ADAFAC_RTILDE_CONST_EPS1) return fail(c, ADAFAC_EUNSUPPORTED, "adaptive trees use the eps = 1 R~");
   if (o.damping != ADAFAC_DAMP_JAC && o.damping != ADAFAC_DAMP_NONE)
     return fail(c, ADAFAC_EUNSUPPORTED, "adaptive trees support adAFAC-Jac and plain additive damping");
   if (c->L <= c->lmin) return fail(c, ADAFAC_EINVAL, "an adaptive tree needs l_max > l_min");
@@ -742,7 +753,9 @@ int bind_adaptive(adafac_ctx* c) {
     std::vector<double> bl(c->src_gauss ? 0 : H.nverts(), 0.0);
     const int s = ipow3(L - l);
     const double share = A.hd / double(1 << d);
-    if (!c->src_gauss) parallel_ranges(size_t(A.mz), [&](size_t z0, size_t z1) {
+    // a user callback runs on the calling thread only
+    auto ranges = [&](size_t n, auto&& f) { if (c->src_fn) f(size_t(0), n); else parallel_ranges(n, f); };
+    if (!c->src_gauss) ranges(size_t(A.mz), [&](size_t z0, size_t z1) {
       for (int z = int(z0); z < int(z1); ++z)
         for (int y = 0; y < A.my; ++y)
           for (int x = 0; x < A.mx; ++x) {
@@ -984,6 +997,7 @@ int adafac_set_rhs_lattice(adafac_ctx* c, const double* f, size_t n) {
     if (!std::isfinite(f[i])) return fail(c, ADAFAC_EINVAL, "f: non-finite value");
   c->f.assign(f, f + n);
   c->src_gauss = 0;
+  c->src_fn = nullptr;
   c->bound = false;
   return ADAFAC_OK;
 }
@@ -999,6 +1013,7 @@ int adafac_set_rhs_gaussian(adafac_ctx* c, const double* centre, double sigma, d
   c->src_sigma = sigma;
   c->src_amp = amplitude;
   c->src_gauss = 1;
+  c->src_fn = nullptr;
   c->f.clear();
   c->bound = false;
   return ADAFAC_OK;
@@ -1012,7 +1027,8 @@ int adafac_build_operators(adafac_ctx* c, const adafac_opts* opts) {
   if (o.transfer != ADAFAC_TRANSFER_DLINEAR && o.transfer != ADAFAC_TRANSFER_BOXMG)
     return fail(c, ADAFAC_EINVAL, "unknown transfer");
   if (o.damping < ADAFAC_DAMP_JAC || o.damping > ADAFAC_DAMP_EXP) return fail(c, ADAFAC_EINVAL, "unknown damping");
-  if (o.rtilde != ADAFAC_RTILDE_CONST_EPS1) return fail(c, ADAFAC_EUNSUPPORTED, "only the eps = 1 R~ is implemented");
+  if (o.rtilde != ADAFAC_RTILDE_CONST_EPS1 && o.rtilde != ADAFAC_RTILDE_OPERATOR)
+    return fail(c, ADAFAC_EINVAL, "unknown R~ form");
   if (o.precision != ADAFAC_PREC_FP64 && o.precision != ADAFAC_PREC_FP32_REFINED)
     return fail(c, ADAFAC_EINVAL, "unknown precision form");
   if (!(o.omega > 0.0) || !(o.omega_tilde >= 0.0) || !(o.omega_hat > 0.0) || o.inner_k < 1)
@@ -1035,7 +1051,8 @@ int adafac_build_operators(adafac_ctx* c, const adafac_opts* opts) {
     c->ws_need = layout(c, nullptr);
     return ADAFAC_OK;
   }
-  std::string m = build_host_ops(c->ops, o.transfer == ADAFAC_TRANSFER_BOXMG, o.omega);
+  std::string m = build_host_ops(c->ops, o.transfer == ADAFAC_TRANSFER_BOXMG, o.omega,
+                                 o.rtilde == ADAFAC_RTILDE_OPERATOR && o.damping == ADAFAC_DAMP_JAC);
   if (!m.empty()) return fail(c, ADAFAC_EINVAL, m);
   c->built = true;
   c->bound = false;
@@ -1053,7 +1070,7 @@ int adafac_workspace_bytes(const adafac_ctx* c, size_t* bytes) {
 int adafac_bind(adafac_ctx* c, void* ws, size_t bytes, void* stream) {
   if (!c) return ADAFAC_EINVAL;
   if (!c->built) return fail(c, ADAFAC_ESTATE, "build_operators first");
-  if (c->f.empty() && !c->src_gauss) return fail(c, ADAFAC_ESTATE, "set the right-hand side first");
+  if (c->f.empty() && !c->src_gauss && !c->src_fn) return fail(c, ADAFAC_ESTATE, "set the right-hand side first");
   size_t need = c->ws_need;
   if (!ws || bytes < need) return fail(c, ADAFAC_ENOMEM, "workspace too small: need " + std::to_string(need));
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(c, ADAFAC_EINVAL, "workspace not 256-byte aligned");
@@ -1081,7 +1098,8 @@ int adafac_bind(adafac_ctx* c, void* ws, size_t bytes, void* stream) {
   const double hd = std::pow(fl.h, d);
   const int nv = fl.nv;
   const int z_lo = d == 3 ? 1 : 0, z_hi = d == 3 ? nv - 1 : 1;
-  parallel_ranges(size_t(z_hi - z_lo), [&](size_t q0, size_t q1) {
+  auto ranges = [&](size_t n, auto&& f) { if (c->src_fn) f(size_t(0), n); else parallel_ranges(n, f); };
+  ranges(size_t(z_hi - z_lo), [&](size_t q0, size_t q1) {
     for (int z = z_lo + int(q0); z < z_lo + int(q1); ++z)
       for (int y = 1; y < nv - 1; ++y) {
         const size_t row = (size_t(z) * nv + y) * nv;
@@ -1267,6 +1285,12 @@ int adafac_host_operator(const adafac_ctx* cc, int level, int which, double* out
   }
   if (level < c->lmin || level > c->L) return fail(c, ADAFAC_EINVAL, "level out of range");
   const HostLevel& hl = c->ops.lev[level];
+  if (which == 4) {
+    if (hl.rtw.empty()) return fail(c, ADAFAC_ESTATE, "no OPERATOR R~ on this level");
+    if (n != hl.rtw.size()) return fail(c, ADAFAC_EINVAL, "out: wrong size");
+    std::memcpy(out, hl.rtw.data(), sizeof(double) * n);
+    return ADAFAC_OK;
+  }
   const size_t nv = hl.nverts;
   auto coords = [&](size_t i, int* v) { for (int a = 0; a < d; ++a) { v[a] = int(i % hl.nv); i /= hl.nv; } };
   auto interior = [&](const int* v) { for (int a = 0; a < d; ++a) if (v[a] <= 0 || v[a] >= hl.nv - 1) return false; return true; };
@@ -1407,8 +1431,8 @@ int adafac_regrid_prepare(adafac_ctx* c, const double* centre, double radius, in
     if (n != nverts_of(c->dim, c->L)) return fail(c, ADAFAC_EINVAL, "f: wrong size");
     for (size_t i = 0; i < n; ++i)
       if (!std::isfinite(f[i])) return fail(c, ADAFAC_EINVAL, "f: non-finite value");
-  } else if (!c->src_gauss) {
-    return fail(c, ADAFAC_EINVAL, "f: a lattice is needed unless the right-hand side is a Gaussian source");
+  } else if (!c->src_gauss && !c->src_fn) {
+    return fail(c, ADAFAC_EINVAL, "f: a lattice is needed unless the right-hand side is a Gaussian source or a function");
   }
   double cc[3] = {0, 0, 0};
   for (int a = 0; a < c->dim; ++a) cc[a] = centre[a];
@@ -1451,11 +1475,14 @@ int adafac_regrid(adafac_ctx* c, void* ws, size_t bytes) {
   double* old_norm0 = c->norm0;
   // switch to the new tree and its workspace
   std::swap(c->at, c->at_next);
-  if (c->src_gauss && c->f_next.empty()) {
-    for (int a = 0; a < 3; ++a) c->src_c[a] = c->next_src_c[a];   // the source moves with the ball
+  if (c->f_next.empty()) {
+    // a Gaussian source moves with the ball; a function source stays as it is
+    if (c->src_gauss)
+      for (int a = 0; a < 3; ++a) c->src_c[a] = c->next_src_c[a];
   } else {
     c->f.swap(c->f_next);
     c->src_gauss = 0;
+    c->src_fn = nullptr;
   }
   layout(c, static_cast<char*>(ws));
   HIPCHK(c, hipMemsetAsync(ws, 0, c->next_need, c->stream));
@@ -1490,6 +1517,159 @@ void adafac_destroy(adafac_ctx* c) {
 }
 
 const char* adafac_last_error(const adafac_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int adafac_set_rhs_fn(adafac_ctx* c, double (*f)(const double* x, void* user), void* user) {
+  if (!c) return ADAFAC_EINVAL;
+  if (!f) return fail(c, ADAFAC_EINVAL, "f: null function");
+  c->src_fn = f;
+  c->src_user = user;
+  c->src_gauss = 0;
+  c->f.clear();
+  c->bound = false;
+  return ADAFAC_OK;
+}
+
+int adafac_residual_normalised(adafac_ctx* c, int cycle, double* l2h_rel, double* linf_rel) {
+  if (!c) return ADAFAC_EINVAL;
+  if (!ready(c)) return fail(c, ADAFAC_ESTATE, "bind first");
+  if (cycle < 0 || cycle >= c->ncyc || c->ncyc - cycle > kMaxHist)
+    return fail(c, ADAFAC_EINVAL, "cycle not run (or no longer kept)");
+  double nrm[2], n0[2];
+  HIPCHK(c, hipMemcpyAsync(nrm, c->norms + 2 * (cycle % kMaxHist), sizeof(nrm), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(n0, c->norm0, sizeof(n0), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (l2h_rel) *l2h_rel = n0[0] > 0.0 ? nrm[0] / n0[0] : 0.0;
+  if (linf_rel) *linf_rel = n0[1] > 0.0 ? nrm[1] / n0[1] : 0.0;
+  return ADAFAC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// f(level, box-or-lattice index, finest-lattice coordinates) for every composite dof, in the
+// composite order: uniform trees the interior finest vertices in lattice order; adaptive trees
+// level by level from l_min, each level's composite dofs in the order of its box (x fastest).
+template <class F>
+void for_composite(const adafac_ctx* c, F&& f) {
+  const int d = c->dim, L = c->L;
+  if (!c->adaptive) {
+    const int nv = ipow3(L) + 1;
+    const int zl = d == 3 ? 1 : 0, zh = d == 3 ? nv - 1 : 1;
+    for (int z = zl; z < zh; ++z)
+      for (int y = 1; y < nv - 1; ++y)
+        for (int x = 1; x < nv - 1; ++x) {
+          const int g[3] = {x, y, z};
+          f(L, (size_t(z) * nv + y) * nv + x, g);
+        }
+    return;
+  }
+  for (int l = c->lmin; l <= L; ++l) {
+    const AdaptHostLevel& H = c->at.lev[l];
+    const int s = ipow3(L - l);
+    const int mx = H.nc[0] + 1, my = H.nc[1] + 1, mz = d == 3 ? H.nc[2] + 1 : 1;
+    for (int z = 0; z < mz; ++z)
+      for (int y = 0; y < my; ++y)
+        for (int x = 0; x < mx; ++x) {
+          const size_t i = (size_t(z) * my + y) * mx + x;
+          if (!(H.vcls[i] & kComp)) continue;
+          const int g[3] = {(H.lo[0] + x) * s, (H.lo[1] + y) * s, d == 3 ? (H.lo[2] + z) * s : 0};
+          f(l, i, g);
+        }
+  }
+}
+}  // namespace
+
+extern "C" {
+
+int adafac_dof_coords(const adafac_ctx* cc, double* xyz, int* level, size_t n) {
+  adafac_ctx* c = const_cast<adafac_ctx*>(cc);
+  if (!c) return ADAFAC_EINVAL;
+  if (!c->built) return fail(c, ADAFAC_ESTATE, "build_operators first");
+  if (n != size_t(adafac_composite_dofs(c))) return fail(c, ADAFAC_EINVAL, "n must equal adafac_composite_dofs");
+  const double hL = 1.0 / ipow3(c->L);
+  const int d = c->dim;
+  size_t k = 0;
+  for_composite(c, [&](int l, size_t, const int* g) {
+    if (xyz)
+      for (int a = 0; a < d; ++a) xyz[k * d + a] = g[a] * hL;
+    if (level) level[k] = l;
+    ++k;
+  });
+  return ADAFAC_OK;
+}
+
+int adafac_get_composite(adafac_ctx* c, double* u, size_t n) {
+  if (!c) return ADAFAC_EINVAL;
+  if (!ready(c)) return fail(c, ADAFAC_ESTATE, "bind first");
+  if (!u || n != size_t(adafac_composite_dofs(c))) return fail(c, ADAFAC_EINVAL, "n must equal adafac_composite_dofs");
+  size_t k = 0;
+  if (c->adaptive) {
+    // the level boxes hold the composite dofs' values
+    int rc = flush(c);
+    if (rc) return rc;
+    std::vector<std::vector<double>> box(c->L + 1);
+    for (int l = c->lmin; l <= c->L; ++l) {
+      box[l].resize(c->at.lev[l].nverts());
+      HIPCHK(c, hipMemcpyAsync(box[l].data(), c->ad[l].u, sizeof(double) * box[l].size(), hipMemcpyDeviceToHost,
+                               c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for_composite(c, [&](int l, size_t i, const int*) { u[k++] = box[l][i]; });
+    return ADAFAC_OK;
+  }
+  std::vector<double> lat(nverts_of(c->dim, c->L));
+  int rc = adafac_get_solution(c, lat.data(), lat.size());
+  if (rc) return rc;
+  for_composite(c, [&](int, size_t i, const int*) { u[k++] = lat[i]; });
+  return ADAFAC_OK;
+}
+
+int adafac_set_composite(adafac_ctx* c, const double* u, size_t n) {
+  if (!c) return ADAFAC_EINVAL;
+  if (!ready(c)) return fail(c, ADAFAC_ESTATE, "bind first");
+  if (!u || n != size_t(adafac_composite_dofs(c))) return fail(c, ADAFAC_EINVAL, "n must equal adafac_composite_dofs");
+  for (size_t k = 0; k < n; ++k)
+    if (!std::isfinite(u[k])) return fail(c, ADAFAC_EINVAL, "u: non-finite value");
+  size_t k = 0;
+  if (c->adaptive) {
+    // composite dofs take their values; a dof that is not composite copies the dof at its
+    // position one level finer (filled first); hanging values are interpolated on the device
+    const int d = c->dim, L = c->L;
+    std::vector<std::vector<double>> box(L + 1);
+    for (int l = c->lmin; l <= L; ++l) box[l].assign(c->at.lev[l].nverts(), 0.0);
+    for_composite(c, [&](int l, size_t i, const int*) { box[l][i] = u[k++]; });
+    for (int l = L - 1; l >= c->lmin; --l) {
+      const AdaptHostLevel& H = c->at.lev[l];
+      const AdaptHostLevel& F = c->at.lev[l + 1];
+      const int mx = H.nc[0] + 1, my = H.nc[1] + 1, mz = d == 3 ? H.nc[2] + 1 : 1;
+      const int fmx = F.nc[0] + 1, fmy = F.nc[1] + 1;
+      for (int z = 0; z < mz; ++z)
+        for (int y = 0; y < my; ++y)
+          for (int x = 0; x < mx; ++x) {
+            const size_t i = (size_t(z) * my + y) * mx + x;
+            if ((H.vcls[i] & kDof) && !(H.vcls[i] & kComp)) {
+              const int fx = 3 * (H.lo[0] + x) - F.lo[0], fy = 3 * (H.lo[1] + y) - F.lo[1];
+              const int fz = d == 3 ? 3 * (H.lo[2] + z) - F.lo[2] : 0;
+              box[l][i] = box[l + 1][(size_t(fz) * fmy + fy) * fmx + fx];
+            }
+          }
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int l = c->lmin; l <= L; ++l)
+      HIPCHK(c, hipMemcpyAsync(c->ad[l].u, box[l].data(), sizeof(double) * box[l].size(), hipMemcpyHostToDevice,
+                               c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->e_pending = false;
+    int rc = adapt_hang(c);
+    if (rc) return rc;
+    c->ncyc = 0;
+    c->r0 = -1.0;
+    return ADAFAC_OK;
+  }
+  std::vector<double> lat(nverts_of(c->dim, c->L), 0.0);
+  for_composite(c, [&](int, size_t i, const int*) { lat[i] = u[k++]; });
+  return adafac_set_solution(c, lat.data(), lat.size());
+}
 
 int adafac_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
   if (!src || !dst || bytes % 16 || reinterpret_cast<uintptr_t>(src) % 16 || reinterpret_cast<uintptr_t>(dst) % 16)

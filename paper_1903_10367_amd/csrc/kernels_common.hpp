@@ -204,7 +204,14 @@ __device__ __forceinline__ void level_update_vertex(const LevelView<T>& C, const
         for (int t = 0; t < 25; ++t) W += restrict_weight<T, D>(F, X + t % 5 - 2, Y + t / 5 - 2, Z + oz, x, y, z) * pl[t];
       }
       rr += W;
-      if (jac) {
+      if (jac && C.rtw) {
+        // R~ built from the operator: this vertex's stored weights of the plane oz
+        const T* rw = C.rtw + i * (D == 2 ? 25 : 125) + (D == 3 ? 25 * (oz + 2) : 0);
+        T Bs = T(0);
+#pragma unroll
+        for (int t = 0; t < 25; ++t) Bs += rw[t] * pl[t];
+        bt += Bs;
+      } else if (jac) {
         // R~ = scale sum_a delta(o_a) prod_{b != a} m(o_b)
         T Xs = T(0), Ys = T(0), Qs = T(0);
 #pragma unroll

@@ -17,6 +17,7 @@
 #include <cstring>
 
 #include "adafac_internal.hpp"
+#include "adaptive.hpp"
 
 namespace adafac {
 namespace {
@@ -319,13 +320,101 @@ void fill_galerkin(HostOps& ops, int l) {
   }
 }
 
+// (A_l phi)(f) at an interior vertex f of level l for a function phi of the level's vertices
+// (zero on the boundary): the stored stencil row, or the Q1 elements of the cells around f.
+template <typename Phi>
+double apply_row(const HostOps& ops, int l, const int* f, Phi&& phi) {
+  const int d = ops.dim, ns = st_size(d);
+  const HostLevel& F = ops.lev[l];
+  Grid g{d, F.nv};
+  double s = 0.0;
+  if (!F.st.empty()) {
+    const double* row = &F.st[g.lin(f) * ns];
+    for (int t = 0; t < ns; ++t) {
+      if (row[t] == 0.0) continue;
+      int o[3], w[3] = {0, 0, 0};
+      st_offset(t, d, o);
+      for (int a = 0; a < d; ++a) w[a] = f[a] + o[a];
+      s += row[t] * phi(w);
+    }
+    return s;
+  }
+  const int n = F.n;
+  const double hd2 = std::pow(F.h, d - 2);
+  for (int cm = 0; cm < (1 << d); ++cm) {
+    int c[3] = {0, 0, 0}, i = 0;
+    bool ok = true;
+    for (int a = 0; a < d; ++a) {
+      c[a] = f[a] - ((cm >> a) & 1);
+      if (c[a] < 0 || c[a] >= n) { ok = false; break; }
+      i |= (f[a] - c[a]) << a;
+    }
+    if (!ok) continue;
+    double cs = 0.0;
+    for (int j = 0; j < (1 << d); ++j) {
+      int w[3] = {0, 0, 0};
+      for (int a = 0; a < d; ++a) w[a] = c[a] + ((j >> a) & 1);
+      const double k = ref_element(d, i, j);
+      if (k != 0.0 && g.interior(w)) cs += k * phi(w);
+    }
+    s += cell_eps(ops, l, c) * hd2 * cs;
+  }
+  return s;
+}
+
+// The smoothed restriction of Sec. 3.2 built from the operator itself (the second of the two
+// choices discussed there; the paper notes that R~ must then be stored): for every interior
+// vertex c of level l-1 and fine offset o with |o|_inf <= 2,
+//   R~(c, 3c + o) = omega sum_w P(w <- c) A_l(w, 3c + o) / D_l(3c + o),
+// i.e. omega P^T A D^-1 truncated to the support of P.  A is symmetric, so the sum is
+// (A_l (P e_c))(3c + o).  Stored on level l-1 as 5^d weights per vertex.
+void fill_rtilde_operator(HostOps& ops, int l, double omega) {
+  const int d = ops.dim, n5 = d == 2 ? 25 : 125;
+  const HostLevel& F = ops.lev[l];
+  HostLevel& C = ops.lev[l - 1];
+  Grid gf{d, F.nv}, gc{d, C.nv};
+  C.rtw.assign(C.nverts * n5, 0.0);
+  const int zero[3] = {0, 0, 0};
+  auto diag = [&](const int* f) { return F.dg.empty() ? fem_entry(ops, l, f, zero) : F.dg[gf.lin(f)]; };
+  parallel_ranges(C.nverts, [&](size_t c0, size_t c1) {
+    double pe[125];
+    for (size_t ci = c0; ci < c1; ++ci) {
+      int c[3] = {0, 0, 0};
+      gc.unlin(ci, c);
+      if (!gc.interior(c)) continue;
+      // P e_c on its support [3c - 2, 3c + 2]^d
+      for (int t = 0; t < n5; ++t) {
+        int w[3] = {0, 0, 0}, tt = t;
+        for (int a = 0; a < d; ++a) { w[a] = 3 * c[a] + tt % 5 - 2; tt /= 5; }
+        pe[t] = pweight(ops, l, w, c);
+      }
+      auto phi = [&](const int* w) {
+        int t = 0, mul = 1;
+        for (int a = 0; a < d; ++a) {
+          const int q = w[a] - 3 * c[a] + 2;
+          if (q < 0 || q > 4) return 0.0;
+          t += q * mul;
+          mul *= 5;
+        }
+        return pe[t];
+      };
+      for (int t = 0; t < n5; ++t) {
+        int f[3] = {0, 0, 0}, tt = t;
+        for (int a = 0; a < d; ++a) { f[a] = 3 * c[a] + tt % 5 - 2; tt /= 5; }
+        if (!gf.interior(f)) continue;
+        C.rtw[ci * n5 + t] = omega * apply_row(ops, l, f, phi) / diag(f);
+      }
+    }
+  });
+}
+
 }  // namespace
 
 double fem_stencil_entry(const HostOps& ops, int level, const int* v, const int* o) {
   return fem_entry(ops, level, v, o);
 }
 
-std::string build_host_ops(HostOps& ops, int transfer_boxmg, double omega) {
+std::string build_host_ops(HostOps& ops, int transfer_boxmg, double omega, int rtilde_operator) {
   int d = ops.dim;
   ops.lev.assign(ops.L + 1, HostLevel{});
   for (int l = 0; l <= ops.L; ++l) {
@@ -367,6 +456,8 @@ std::string build_host_ops(HostOps& ops, int transfer_boxmg, double omega) {
       if (!(hl.dg[i] > 0.0)) return "non-positive diagonal";
     }
   }
+  if (rtilde_operator)
+    for (int l = ops.lmin + 1; l <= ops.L; ++l) fill_rtilde_operator(ops, l, omega);
   // R~: omega times the eps = 1 smoothed operator M^-1 A P (d-linear hat, unit stencil),
   // truncated to offsets |o| <= 2 (the support of P).
   {

@@ -174,3 +174,85 @@ def test_precision_forms_are_accepted_and_sized():
     nv = 82 ** 3
     assert sizes[1] > 3 * 8 * nv + 4 * 4 * nv
     assert sizes[0] > 4 * 8 * nv
+
+
+@pytest.mark.parametrize("d,L,k,kind", [(2, 3, 2, "boxmg"), (2, 3, 1, "dlinear"), (3, 2, 1, "boxmg"),
+                                        (3, 3, 2, "boxmg")])
+def test_operator_rtilde_matches_oracle(d, L, k, kind):
+    """The per-vertex R~ = omega trunc(P^T A D^-1) of the OPERATOR form (Sec. 3.2), built on the
+    host, against the oracle's sparse product of the same hierarchy."""
+    eps = inp.eps_blocks(d, k, 3.0, seed=23)
+    lib = _abi.lib()
+    ctx = C.c_void_p()
+    assert lib.adafac_create(C.byref(ctx), d, 1, L) == 0
+    try:
+        e = np.ascontiguousarray(eps)
+        assert lib.adafac_set_coefficient_blocks(ctx, e.shape[0], _dp(e)) == 0
+        fa = np.zeros((3 ** L + 1) ** d)
+        assert lib.adafac_set_rhs_lattice(ctx, _dp(fa), fa.size) == 0
+        o = _abi.Opts()
+        lib.adafac_default_opts(C.byref(o))
+        o.transfer, o.rtilde = _abi.TRANSFER[kind], _abi.RTILDE["operator"]
+        assert lib.adafac_build_operators(ctx, C.byref(o)) == 0, lib.adafac_last_error(ctx)
+        H = hierarchy.Hierarchy(d, L, 1, eps, kind, rtilde="operator")
+        n5 = 5 ** d
+        for l in range(1, L):
+            nvc, nvf = 3 ** l + 1, 3 ** (l + 1) + 1
+            got = _host_op(lib, ctx, l, 4, nvc ** d * n5).reshape(nvc ** d, n5)
+            Rt = H.lev[l + 1].Rt.mat.toarray()
+            want = np.zeros_like(got)
+            cidx = np.array(np.unravel_index(np.arange(nvc ** d), (nvc,) * d))       # axis order z, y, x
+            for t in range(n5):
+                o_ = [(t // 5 ** a) % 5 - 2 for a in range(d)]                     # x, y, z offsets
+                f = 3 * cidx + np.array(o_[::-1])[:, None]
+                ok = np.all((f >= 0) & (f < nvf), axis=0)
+                fi = np.ravel_multi_index(tuple(np.where(ok, f, 0)), (nvf,) * d)
+                want[:, t] = np.where(ok, Rt[np.arange(nvc ** d), fi], 0.0)
+            assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max(), l
+            # every nonzero of the oracle's truncated R~ is one of the stored entries
+            assert np.count_nonzero(np.abs(Rt) > 0) == np.count_nonzero(np.abs(want) > 0)
+    finally:
+        lib.adafac_destroy(ctx)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_dof_coords_follow_the_composite_order(d):
+    """Positions and levels of the composite dofs: uniform trees the interior finest vertices,
+    adaptive trees the oracle's composite index (levels from l_min, lattice order)."""
+    from oracle import adaptive
+    lib = _abi.lib()
+    L, lu = (4, 2) if d == 2 else (3, 2)
+    centre = (0.5, 0.5) if d == 2 else (0.45, 0.5, 0.55)
+    ref = inp.refine_ball(d, L, lu, centre, 0.2 if d == 2 else 0.15)
+    T = adaptive.AdaptiveTree(d, L, 1, lu, ref)
+    ctx = C.c_void_p()
+    assert lib.adafac_create(C.byref(ctx), d, 1, L) == 0
+    try:
+        fa = np.zeros((3 ** L + 1) ** d)
+        assert lib.adafac_set_rhs_lattice(ctx, _dp(fa), fa.size) == 0
+        for l, flags in ref.items():
+            fl = np.ascontiguousarray(flags, dtype=np.uint8).ravel()
+            assert lib.adafac_set_refinement(ctx, l, fl.ctypes.data_as(C.POINTER(C.c_uint8)), fl.size) == 0
+        assert lib.adafac_build_operators(ctx, None) == 0, lib.adafac_last_error(ctx)
+        idx = T.composite_index()
+        n = lib.adafac_composite_dofs(ctx)
+        assert n == len(idx)
+        xyz = np.zeros((n, d))
+        lev = np.zeros(n, dtype=np.int32)
+        assert lib.adafac_dof_coords(ctx, _dp(xyz), lev.ctypes.data_as(C.POINTER(C.c_int)), n) == 0
+        assert lib.adafac_dof_coords(ctx, _dp(xyz), None, n + 1) == _abi.EINVAL
+        want = np.array([np.array(np.unravel_index(i, T.shape(l)))[::-1] * 3.0 ** -l for l, i in idx])
+        assert np.abs(xyz - want).max() < 1e-15
+        assert np.array_equal(lev, [l for l, _ in idx])
+    finally:
+        lib.adafac_destroy(ctx)
+    lib2, ctx2 = _ctx(d, 1, 2)
+    try:
+        n = lib2.adafac_composite_dofs(ctx2)
+        assert n == 8 ** d
+        xyz = np.zeros((n, d))
+        assert lib2.adafac_dof_coords(ctx2, _dp(xyz), None, n) == 0
+        grid = np.stack(np.meshgrid(*([np.arange(1, 9) / 9.0] * d), indexing="ij"), -1).reshape(-1, d)[:, ::-1]
+        assert np.abs(xyz - grid).max() < 1e-15
+    finally:
+        lib2.adafac_destroy(ctx2)

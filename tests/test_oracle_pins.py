@@ -64,6 +64,21 @@ def test_assembled_stencil_3d(level, eps):
         assert st[tuple(x + 1 for x in o)] == pytest.approx(want, abs=1e-15)
 
 
+@pytest.mark.parametrize("d,level", [(2, 3), (3, 2)])
+def test_assembled_interior_rows_sum_to_exactly_zero(d, level):
+    """A constant is in the kernel of the Q1 operator away from the boundary; with correctly
+    rounded element entries the assembled interior rows of the Poisson operator sum to zero in
+    exact arithmetic on the stored doubles (no artificial zero-order term)."""
+    import math
+    A = fem.assemble(np.ones((3 ** level,) * d)).tocsr()
+    m = fem.interior_mask(d, level)
+    far = np.zeros_like(m)
+    far[(slice(2, -2),) * d] = True
+    for i in np.flatnonzero(far.ravel()):
+        row = A.data[A.indptr[i]:A.indptr[i + 1]]
+        assert math.fsum(row) == 0.0, i
+
+
 @pytest.mark.parametrize("d,L,k", [(2, 3, 2), (3, 2, 1), (3, 2, 2)])
 def test_matrix_free_equals_assembled(d, L, k):
     eps = fem.cell_eps_from_blocks(inp.eps_blocks(d, k, 3.0, seed=3), L)
