@@ -55,12 +55,20 @@ class AdaptiveTree:
     ``refine[l]`` (l_uniform <= l < L): boolean array over the (3^l)^d cells of level l, the
     refinement flags; only flags of existing cells matter.  Levels below l_uniform are fully
     refined.  ``eps_blocks`` as in hierarchy.Hierarchy (blocks on a level k <= l_uniform).
+
+    ``transfer`` "boxmg": operator-dependent transfers (Sec. 2.5) into the levels l <= k, which
+    are uniform, so the level hats there are phi^l = sum_w P_wv phi^{l+1}_w with BoxMG's P of
+    the uniform hierarchy of levels lmin..k.  Above level k every cell lies inside one
+    coefficient block, where BoxMG's P is the d-linear one (pinned in the uniform tests), so
+    those levels keep d-linear transfers (and hanging vertices always interpolate d-linearly).
     """
 
-    def __init__(self, d, L, lmin, l_uniform, refine, eps_blocks=None, omega=0.6):
+    def __init__(self, d, L, lmin, l_uniform, refine, eps_blocks=None, omega=0.6, transfer="dlinear"):
         assert 1 <= lmin <= l_uniform <= L
+        assert transfer in ("dlinear", "boxmg")
         self.d, self.L, self.lmin, self.lu = d, L, lmin, l_uniform
         self.omega = omega
+        self.transfer = transfer
         eps_blocks = np.ones((1,) * d) if eps_blocks is None else np.asarray(eps_blocks, dtype=np.float64)
         self.eps_blocks = eps_blocks
         k = int(round(np.log(eps_blocks.shape[0]) / np.log(3)))
@@ -115,7 +123,8 @@ class AdaptiveTree:
         kref = fem.ref_stiffness(d)[0, 0]
         gal = None
         if self.k > self.lmin:
-            gal = hierarchy.Hierarchy(d, self.k, self.lmin, self.eps_blocks)
+            gal = hierarchy.Hierarchy(d, self.k, self.lmin, self.eps_blocks, self.transfer)
+        self.gal = gal
         for l in range(self.lmin, L + 1):
             n = 3 ** l
             if l >= self.k:
@@ -141,7 +150,12 @@ class AdaptiveTree:
         # R~ = omega trunc(M^-1 A P) from the eps = 1 stencil (Sec. 3.2), as on uniform grids
         rt = omega_rtilde(d, self.omega)
         for l in range(self.lmin + 1, L + 1):
-            self.P[l], self.PT[l] = hierarchy.dlinear_fns(d, l)
+            if gal is not None and self.transfer == "boxmg" and l <= self.k:
+                Pm = gal.lev[l].P.mat
+                self.P[l] = lambda x, M=Pm: M @ x
+                self.PT[l] = lambda x, M=Pm: M.T @ x
+            else:
+                self.P[l], self.PT[l] = hierarchy.dlinear_fns(d, l)
             self.Rt[l] = hierarchy.stencil_restriction_fn(rt, d, l)
 
     def shape(self, l):
@@ -359,6 +373,13 @@ def dense_system(T, f):
             v = np.array(np.unravel_index(i, T.shape(l)))[::-1]
             cols.append(hat(d, l, v, pos))
         Psi[l] = np.array(cols).T if cols else np.zeros((n, 0))
+    if T.transfer == "boxmg" and T.gal is not None:
+        # operator-dependent hats below level k: phi^l_v = sum_w P_wv phi^{l+1}_w (Sec. 2.5)
+        for l in range(T.k - 1, T.lmin - 1, -1):
+            Pm = T.gal.lev[l + 1].P.mat.toarray()
+            dof_f = np.flatnonzero(T.dof[l + 1].ravel())
+            dof_c = np.flatnonzero(T.dof[l].ravel())
+            Psi[l] = Psi[l + 1] @ Pm[np.ix_(dof_f, dof_c)]
     return A, b, pos, lev, Psi, C
 
 
@@ -370,7 +391,8 @@ def dense_cycle(T, A, b, lev, Psi, u, omega=0.6, omega_t=0.6, damping="jac"):
     du = np.zeros_like(u)
     Dl = {}
     for l in range(T.lmin, L + 1):
-        Dl[l] = T.D[l].ravel()[np.flatnonzero(T.dof[l].ravel())]
+        # D_l = a(phi^l_v, phi^l_v) of the level hats in the composite space
+        Dl[l] = np.einsum("iv,ij,jv->v", Psi[l], A, Psi[l])
         du += Psi[l] @ (omega * (Psi[l].T @ r) / Dl[l])
     if damping == "jac":
         rt = omega_rtilde(d, T.omega)

@@ -17,9 +17,9 @@ import adafac_inputs as inp
 from oracle import adaptive, cycle, hierarchy
 
 
-def disk_tree(L=4, lu=2, eps=None, d=2, radius=0.2):
+def disk_tree(L=4, lu=2, eps=None, d=2, radius=0.2, transfer="dlinear"):
     ref = inp.refine_ball(d, L, lu, (0.5,) * d if d == 2 else (0.45, 0.5, 0.55), radius)
-    return adaptive.AdaptiveTree(d, L, 1, lu, ref, eps)
+    return adaptive.AdaptiveTree(d, L, 1, lu, ref, eps, transfer=transfer)
 
 
 @pytest.mark.parametrize("d,L,k", [(2, 3, 0), (2, 3, 1), (3, 2, 1)])
@@ -33,6 +33,47 @@ def test_uniform_tree_is_the_uniform_cycle(d, L, k):
     assert np.abs(U[L].ravel() - u).max() <= 1e-14 * np.abs(u).max()
     for a, b in zip(hist, ho):
         assert abs(a[0] - b[0]) <= 1e-14 * ho[0][0]
+
+
+@pytest.mark.parametrize("d,L,k", [(2, 3, 1), (2, 3, 2), (3, 2, 1), (3, 2, 2)])
+def test_uniform_tree_with_boxmg_is_the_uniform_boxmg_cycle(d, L, k):
+    """A tree refined everywhere with operator-dependent transfers is the uniform BoxMG
+    hierarchy (Sec. 2.5), whose transfers and Galerkin operators are pinned on their own."""
+    eps = inp.eps_blocks(d, k, 3.0, seed=12 + k)
+    T = adaptive.AdaptiveTree(d, L, 1, L, {}, eps, transfer="boxmg")
+    f = inp.rhs(d, L, seed=14)
+    U, hist = adaptive.solve(T, f, 6)
+    H = hierarchy.Hierarchy(d, L, 1, eps, "boxmg")
+    u, ho = cycle.solve(H, H.rhs(f), 6)
+    assert np.abs(U[L].ravel() - u).max() <= 1e-12 * np.abs(u).max()
+    for a, b in zip(hist, ho):
+        assert abs(a[0] - b[0]) <= 1e-12 * ho[0][0]
+    # with blocks on level k = 2 the level-1 cells straddle blocks and the transfers differ from
+    # d-linear (the d-linear tree gives another iterate); with k = 1 (= l_min) they coincide
+    Td = adaptive.AdaptiveTree(d, L, 1, L, {}, eps)
+    Ud, _ = adaptive.solve(Td, f, 6)
+    gap = np.abs(Ud[L] - U[L]).max()
+    if k > 1:
+        assert gap > 1e-6 * np.abs(u).max()
+    else:
+        assert gap <= 1e-12 * np.abs(u).max()
+
+
+def test_boxmg_disk_tree_transfers_differ_from_dlinear_only_below_the_blocks():
+    """On the 2D disk tree with 9 x 9 coefficient blocks, the level-1 cells straddle blocks, so
+    the BoxMG prolongation into level 2 is not d-linear; above level 2 every coarse cell lies in
+    one block and the two coincide."""
+    eps = inp.eps_blocks(2, 2, 3.0, seed=15)
+    Tb = disk_tree(L=4, lu=2, eps=eps, transfer="boxmg")
+    Td = disk_tree(L=4, lu=2, eps=eps)
+    rng = np.random.default_rng(16)
+    for l in range(2, 5):
+        x = rng.standard_normal(Tb.shape(l - 1)).ravel()
+        diff = np.abs(Tb.P[l](x) - Td.P[l](x)).max()
+        if l == 2:
+            assert diff > 1e-3
+        else:
+            assert diff == 0.0
 
 
 def test_tree_classes():
@@ -66,14 +107,15 @@ def test_hanging_values_reproduce_dlinear_functions(d):
         assert np.abs(U[l][have] - g(l)[have]).max() < 1e-13
 
 
+@pytest.mark.parametrize("transfer", ["dlinear", "boxmg"])
 @pytest.mark.parametrize("damping", ["jac", "none"])
 @pytest.mark.parametrize("d", [2, 3])
-def test_cycle_equals_dense_generating_system_form(d, damping):
+def test_cycle_equals_dense_generating_system_form(d, damping, transfer):
     if d == 2:
         eps = inp.eps_blocks(2, 2, 2.0, seed=5)
-        T = disk_tree(L=4, lu=2, eps=eps)
+        T = disk_tree(L=4, lu=2, eps=eps, transfer=transfer)
     else:
-        T = disk_tree(L=3, lu=2, d=3, radius=0.15, eps=inp.eps_blocks(3, 1, 2.0, seed=6))
+        T = disk_tree(L=3, lu=2, d=3, radius=0.15, eps=inp.eps_blocks(3, 1, 2.0, seed=6), transfer=transfer)
     f = inp.rhs(d, T.L, seed=7)
     A, b, pos, lev, Psi, C = adaptive.dense_system(T, f)
     bleaf = T.load(f)
@@ -87,8 +129,9 @@ def test_cycle_equals_dense_generating_system_form(d, damping):
         assert abs(nr[0] - nd[0]) <= 1e-12 * nd[0] and abs(nr[1] - nd[1]) <= 1e-12 * nd[1]
 
 
-def test_level_diagonals_are_hat_energies():
-    T = disk_tree(eps=inp.eps_blocks(2, 2, 2.0, seed=8))
+@pytest.mark.parametrize("transfer", ["dlinear", "boxmg"])
+def test_level_diagonals_are_hat_energies(transfer):
+    T = disk_tree(eps=inp.eps_blocks(2, 2, 2.0, seed=8), transfer=transfer)
     A, b, pos, lev, Psi, C = adaptive.dense_system(T, inp.rhs(2, 4, seed=9))
     for l in range(T.lmin, T.L + 1):
         D = T.D[l].ravel()[np.flatnonzero(T.dof[l].ravel())]
