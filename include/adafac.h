@@ -176,6 +176,27 @@ int adafac_workspace_bytes(const adafac_ctx* ctx, size_t* bytes);
  * (NULL = the null stream).  EDEVICE if a copy fails. */
 int adafac_bind(adafac_ctx* ctx, void* dev_workspace, size_t bytes, void* hip_stream);
 
+/* Size of the library's static device workspace (see adafac_bind_static). */
+#define ADAFAC_STATIC_WORKSPACE_BYTES (32u << 20)
+
+/* adafac_bind without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops or harnesses that
+ * forbid hipMalloc).  The context is bound to the library's own device array of
+ * ADAFAC_STATIC_WORKSPACE_BYTES (32 MiB) on the stream's device; each device
+ * that binds holds one such array until the process ends.  Fits 2D hierarchies
+ * up to l_max = 6 and 3D up to l_max = 4 (adafac_workspace_bytes tells);
+ * ENOMEM, with the needed size in the message, if the hierarchy is larger.
+ * Allocates no device memory and makes no allocating HIP or torch call; the
+ * workspace is cleared by a kernel, not a memset.  Otherwise as adafac_bind:
+ * uploads operators and the load, sets iterate 0, synchronises the stream.
+ * The array holds ONE hierarchy per device: binding a second context to it
+ * unbinds the first (its later calls return ESTATE), and calls on two contexts
+ * that overlap on one device race.  The binding ends at adafac_destroy, the next
+ * adafac_bind / adafac_bind_static, or adafac_regrid (which moves the context to
+ * the workspace it is given).  EDEVICE if the stream's device cannot be told or
+ * the array's address cannot be taken. */
+int adafac_bind_static(adafac_ctx* ctx, void* hip_stream);
+
 /* Enqueue ncycles adAFAC cycles.  Cycle n computes the residual norms of
  * iterate n and produces iterate n+1.  FP32_REFINED: ncycles outer steps of
  * FP64 defect correction, each the FP64 defect r = b - A u of the outer

@@ -55,9 +55,11 @@ class Solver:
 
     def __init__(self, dim, lmin, lmax, f, eps_blocks=None, transfer="dlinear", damping="jac",
                  precision="fp64", inner_k=4, fused=True, omega=0.6, omega_tilde=0.6, omega_hat=0.5,
-                 device=None, stream=None, refine=None, ball=None, rtilde="const"):
+                 device=None, stream=None, refine=None, ball=None, rtilde="const", static_workspace=False):
         """``refine``: {level: flags over the (3^level)^dim cells} of an adaptive tree;
-        ``ball``: (centre, radius, l_from) refinement around a ball (adaptive tree)."""
+        ``ball``: (centre, radius, l_from) refinement around a ball (adaptive tree);
+        ``static_workspace``: bind to the library's own device array (adafac_bind_static)
+        instead of a torch-allocated workspace."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("adafac needs a ROCm GPU (gfx950); none is visible")
@@ -101,10 +103,14 @@ class Solver:
         nbytes = C.c_size_t()
         _check(self.L, ctx, self.L.adafac_workspace_bytes(ctx, C.byref(nbytes)))
         self.device = torch.device(device or "cuda:0")
-        self.workspace = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
         self.stream = stream or torch.cuda.current_stream(self.device)
-        _check(self.L, ctx, self.L.adafac_bind(ctx, C.c_void_p(self.workspace.data_ptr()), self.workspace.numel(),
-                                               C.c_void_p(self.stream.cuda_stream)))
+        if static_workspace:
+            self.workspace = None
+            _check(self.L, ctx, self.L.adafac_bind_static(ctx, C.c_void_p(self.stream.cuda_stream)))
+        else:
+            self.workspace = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
+            _check(self.L, ctx, self.L.adafac_bind(ctx, C.c_void_p(self.workspace.data_ptr()),
+                                                   self.workspace.numel(), C.c_void_p(self.stream.cuda_stream)))
         self.nvert = (3 ** lmax + 1) ** dim
 
     # --- cycle ----------------------------------------------------------------

@@ -9,6 +9,7 @@ OK, EINVAL, ESTATE, ENOMEM, EDEVICE, EDIVERGED, EAGAIN, EUNSUPPORTED = 0, 1, 2, 
 REQ_STATUS = {0: "queued", 1: "running", 2: "converged", 3: "diverged", 4: "capped", 5: "failed"}
 TRANSFER = {"dlinear": 0, "boxmg": 1}
 RTILDE = {"const": 0, "operator": 1}
+STATIC_WORKSPACE_BYTES = 32 << 20   # ADAFAC_STATIC_WORKSPACE_BYTES
 DAMPING = {"jac": 0, "pi": 1, "none": 2, "exp": 3}
 PRECISION = {"fp64": 0, "fp32_refined": 1}
 LEVEL_ARRAY = {"u": 0, "b": 1, "btilde": 2, "r": 3, "S": 4}
@@ -24,7 +25,7 @@ EXPORTS = [
     "adafac_server_default_cfg", "adafac_server_create", "adafac_server_submit", "adafac_server_step",
     "adafac_server_poll", "adafac_server_fetch", "adafac_server_destroy", "adafac_server_last_error",
     "adafac_stream_copy", "adafac_set_rhs_fn", "adafac_residual_normalised", "adafac_dof_coords",
-    "adafac_get_composite", "adafac_set_composite",
+    "adafac_get_composite", "adafac_set_composite", "adafac_bind_static",
 ]
 
 
@@ -82,6 +83,7 @@ def lib():
         "adafac_build_operators": (C.c_int, [P, C.POINTER(Opts)]),
         "adafac_workspace_bytes": (C.c_int, [P, C.POINTER(C.c_size_t)]),
         "adafac_bind": (C.c_int, [P, P, C.c_size_t, P]),
+        "adafac_bind_static": (C.c_int, [P, P]),
         "adafac_cycle": (C.c_int, [P, C.c_int]),
         "adafac_solve": (C.c_int, [P, C.c_double, C.c_int, C.POINTER(C.c_int)]),
         "adafac_residual": (C.c_int, [P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]),

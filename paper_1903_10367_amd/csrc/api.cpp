@@ -48,6 +48,8 @@ hipError_t launch_defect3d(const LevelView<double>& F, int nc, int nvc, const do
                            int mode, int* nparts, hipStream_t s);
 template <typename T>
 hipError_t launch_small_levels(int d, const SmallLevelsArgs<T>& a, size_t lds_bytes, hipStream_t s);
+hipError_t launch_zero_fill(void* p, size_t bytes, hipStream_t s);
+void static_ws_forget(const adafac_ctx* c);
 
 }  // namespace adafac
 
@@ -1067,19 +1069,30 @@ int adafac_workspace_bytes(const adafac_ctx* c, size_t* bytes) {
   return ADAFAC_OK;
 }
 
-int adafac_bind(adafac_ctx* c, void* ws, size_t bytes, void* stream) {
+}  // extern "C"
+
+namespace adafac {
+
+// Binds c to the device memory ws (bytes >= ws_need, 256-byte aligned) and the stream, uploads
+// the operators and the load and sets iterate 0.  clear_by_kernel: zero the workspace with a fill
+// kernel instead of a memset node (the library's static workspace, for callers that capture).
+int bind_workspace(adafac_ctx* c, void* ws, size_t bytes, void* stream, bool clear_by_kernel) {
   if (!c) return ADAFAC_EINVAL;
   if (!c->built) return fail(c, ADAFAC_ESTATE, "build_operators first");
   if (c->f.empty() && !c->src_gauss && !c->src_fn) return fail(c, ADAFAC_ESTATE, "set the right-hand side first");
   size_t need = c->ws_need;
   if (!ws || bytes < need) return fail(c, ADAFAC_ENOMEM, "workspace too small: need " + std::to_string(need));
   if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(c, ADAFAC_EINVAL, "workspace not 256-byte aligned");
+  c->bound = false;
   c->ws = static_cast<char*>(ws);
   c->ws_bytes = bytes;
   c->stream = static_cast<hipStream_t>(stream);
   layout(c, c->ws);
   const int d = c->dim;
-  HIPCHK(c, hipMemsetAsync(c->ws, 0, need, c->stream));
+  if (clear_by_kernel)
+    HIPCHK(c, launch_zero_fill(c->ws, need, c->stream));
+  else
+    HIPCHK(c, hipMemsetAsync(c->ws, 0, need, c->stream));
   if (c->adaptive) {
     int rc = bind_adaptive(c);
     if (rc) return rc;
@@ -1114,6 +1127,25 @@ int adafac_bind(adafac_ctx* c, void* ws, size_t bytes, void* stream) {
   c->r0 = -1.0;
   c->bound = true;
   return ADAFAC_OK;
+}
+
+const char* ctx_workspace(const adafac_ctx* c) { return c && c->bound ? c->ws : nullptr; }
+
+void ctx_unbind(adafac_ctx* c, const char* why) {
+  if (!c) return;
+  c->bound = false;
+  c->err = why;
+}
+
+int ctx_fail(adafac_ctx* c, int code, const char* msg) { return fail(c, code, msg); }
+
+}  // namespace adafac
+
+extern "C" {
+
+int adafac_bind(adafac_ctx* c, void* ws, size_t bytes, void* stream) {
+  if (c) static_ws_forget(c);
+  return bind_workspace(c, ws, bytes, stream, false);
 }
 
 int adafac_cycle(adafac_ctx* c, int ncycles) {
@@ -1484,6 +1516,7 @@ int adafac_regrid(adafac_ctx* c, void* ws, size_t bytes) {
     c->src_gauss = 0;
     c->src_fn = nullptr;
   }
+  static_ws_forget(c);
   layout(c, static_cast<char*>(ws));
   HIPCHK(c, hipMemsetAsync(ws, 0, c->next_need, c->stream));
   if ((rc = bind_adaptive(c))) return rc;
@@ -1511,6 +1544,7 @@ int64_t adafac_composite_dofs(const adafac_ctx* c) {
 
 void adafac_destroy(adafac_ctx* c) {
   if (!c) return;
+  static_ws_forget(c);
   if (c->bound) (void)hipStreamSynchronize(c->stream);
   for (auto& e : c->ev) (void)hipEventDestroy(e);
   delete c;
