@@ -220,7 +220,7 @@ def cycle(T, U, bleaf, omega=0.6, omega_t=0.6, damping="jac", trace=None, dtype=
     applied as FP64 factors and their results rounded, so this gives the size of FP32
     rounding, not any particular rounding order.
     """
-    assert damping in ("jac", "none")
+    assert damping in ("jac", "pi", "none")
     d, L, lmin = T.d, T.L, T.lmin
     U = T.spread({l: U[l].astype(dtype) for l in U})
     bleaf = {l: bleaf[l].astype(dtype) for l in bleaf}
@@ -245,6 +245,12 @@ def cycle(T, U, bleaf, omega=0.6, omega_t=0.6, damping="jac", trace=None, dtype=
     if damping == "jac":
         for l in range(lmin, L):
             ct[l] = omega_t * Dinv[l] * T.Rt[l + 1](b[l + 1].ravel()).reshape(T.shape(l))
+    elif damping == "pi":
+        # adAFAC-PI (Sec. 3.2): c~_l = P I c_l, the level's correction injected to level l-1 (its
+        # values at the coinciding level-(l-1) dofs) and prolongated back, none on l_min
+        for l in range(lmin + 1, L + 1):
+            Ic = np.where(T.dof[l - 1], c[l][tuple(slice(None, None, 3) for _ in range(d))], 0.0)
+            ct[l] = T.P[l](Ic.ravel()).reshape(T.shape(l)).astype(dtype)
     S = {lmin: c[lmin] - ct[lmin]}
     for l in range(lmin + 1, L + 1):
         S[l] = c[l] - ct[l] + T.P[l](S[l - 1].ravel()).reshape(T.shape(l))
@@ -402,6 +408,13 @@ def dense_cycle(T, A, b, lev, Psi, u, omega=0.6, omega_t=0.6, damping="jac"):
             dof_f = np.flatnonzero(T.dof[l + 1].ravel())
             bt = Rt[dof_c][:, dof_f] @ (Psi[l + 1].T @ r)
             du -= Psi[l] @ (omega_t * bt / Dl[l])
+    elif damping == "pi":
+        # minus the level-(l-1) function whose dof coefficients are c_l at the same positions
+        for l in range(T.lmin + 1, L + 1):
+            cl = np.zeros(int(np.prod(T.shape(l))))
+            cl[np.flatnonzero(T.dof[l].ravel())] = omega * (Psi[l].T @ r) / Dl[l]
+            at = cl.reshape(T.shape(l))[tuple(slice(None, None, 3) for _ in range(d))].ravel()
+            du -= Psi[l - 1] @ at[np.flatnonzero(T.dof[l - 1].ravel())]
     s = float(np.sum((3.0 ** (-lev * d)) * r * r))
     return u + du, (np.sqrt(s), float(np.max(np.abs(r))) if r.size else 0.0)
 

@@ -123,6 +123,7 @@ struct BatchReq {
   BatchHier<double> h64;     // FP64 form: everything; FP32_REFINED: v[L], u (ufine[0]) and b
   BatchHier<float> h32;      // FP32_REFINED: the inner hierarchy (ufine = e, bfine = r)
   const float* ezero;        // FP32_REFINED: zero lattice, first inner iterate
+  double* partials;          // norm partials of the finest level's work items, 2 per item
 };
 
 // Progress of a request across launches (device memory, written by the kernel).
@@ -132,6 +133,27 @@ struct BatchState {
   int cur;                   // FP64 form: index of ufine holding the current iterate
   int pad;
   double r0, l2h, linf;      // norms of iterate 0 and of the last measured iterate
+  unsigned long long done;   // work items of the request completed (all launches)
+  unsigned long long stop_need;   // items from this sequence number on do no work (stopped)
+};
+
+// Phase kinds of a serving step (one request's chain: FINE, FINAL, LEVEL l = L-1..lmin,
+// PROLONG l = lmin+1..L for FP64; ADDE, DEFECT, FINAL, then per inner cycle FINE, LEVELs,
+// PROLONGs in FP32 for FP32_REFINED).
+enum { SERVE_FINE = 0, SERVE_FINAL, SERVE_LEVEL, SERVE_PROLONG, SERVE_ADDE, SERVE_DEFECT };
+
+// One segment of a serving launch's work list: the ntile items of one phase of one request.
+struct ServeSeg {
+  int req;                   // row of the request table
+  int kind, level, sub;      // SERVE_*, the level it works on, inner cycle index (FP32 phases)
+  int ntile, tile;           // items, vertices per item
+  int need_off;              // items of the request in its earlier phases of the step
+  int per_step;              // items of the request per step
+  int item0;                 // first item of the segment within the step
+  int nparts;                // FINAL: norm partials to sum (items of the measured phase)
+  int run_after;             // FINAL: items of the request after it that still run when it stops
+  int cur0;                  // FP64: iterate index at the launch start
+  unsigned long long base;   // items of the request completed before the launch
 };
 
 // Internal hooks of the C ABI used by the request server (api.cpp).

@@ -41,6 +41,8 @@ struct AdaptLevelT {
   T* hh;                    // hanging-only accumulation (composite residual of coarser dofs)
   T* s;                     // own correction c - c~ at dofs
   T* S;                     // prolongated sum of corrections
+  const T* pw;              // BoxMG transfer from the next coarser level into this one (a complete level):
+                            // 2^d weights per vertex of the corners of its coarse cell, or nullptr: d-linear
 };
 using AdaptLevel = AdaptLevelT<double>;
 
@@ -115,9 +117,9 @@ hipError_t launch_ad_leaf_up(int d, const AdaptLevelT<T>& L, T omega, T omega_t,
                              hipStream_t s);
 // The finest level: down and update in one pass (C: the next coarser level)
 template <typename T>
-hipError_t launch_ad_down_update(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>& C, hipStream_t s);
+hipError_t launch_ad_down_update(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>& C, int pi, hipStream_t s);
 template <typename T>
-hipError_t launch_ad_down(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>* C, hipStream_t s);
+hipError_t launch_ad_down(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>* C, int pi, hipStream_t s);
 template <typename T>
 hipError_t launch_ad_update(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>* F, hipStream_t s);
 // once per tree, after the classes, leaf flags and (Galerkin levels) diagonals are uploaded

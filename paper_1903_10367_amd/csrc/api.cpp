@@ -27,7 +27,7 @@ hipError_t launch_level_update(int d, const LevelView<T>& C, const LevelView<T>&
                                hipStream_t s);
 template <typename T>
 hipError_t launch_prolong_add(int d, const LevelView<T>& F, const LevelView<T>& C, T* dst, const T* src,
-                              const T* sub, hipStream_t s);
+                              const T* sub, hipStream_t s, const T* self = nullptr);
 hipError_t launch_norm_finalize(const double* partials, int n, double* out, hipStream_t s);
 hipError_t launch_stream_copy(const void* src, void* dst, size_t n16, hipStream_t s);
 hipError_t launch_accumulate(int d, const LevelView<float>& F, const LevelView<float>& C, double* u,
@@ -310,10 +310,16 @@ int run_cycle(adafac_ctx* c, Hier<T>& H, double* norm_out, const T* uin_zero) {
   LevelView<T> Lm1 = L > lmin ? H.v[L - 1] : LevelView<T>{};
   int nparts = kNormBlocks;
   int rc;
-  // adAFAC-PI reads and writes the injected fine correction in the same sweep, and the stored
-  // R~ of the OPERATOR form is a per-vertex gather: one kernel per step for both
+  // smallest levels lo..hi for the single-workgroup kernel
+  int hi = lmin - 1;
+  for (int l = lmin; l < L && l - lmin < kMaxSmall && nverts_of(d, l) <= kSmallVerts; ++l) hi = l;
+  // The stored R~ of the OPERATOR form is a per-vertex gather: one kernel per step.  adAFAC-PI
+  // (c~_l = P I c_l) in the single-pass form: the sweeps write I c_l to level l-1, and the last
+  // prolongation into level L-1 subtracts I c_L there, so that S_{L-1} holds S_{L-1} - I c_L and
+  // the pending P S_{L-1} of the next sweep is P (S_{L-1} - I c_L).  That needs a prolongation
+  // launch into L-1 (L-1 above l_min and above the single-workgroup levels).
   const bool opr = o.rtilde == ADAFAC_RTILDE_OPERATOR;
-  const bool fused = o.fused && L > lmin && !pi && !opr && fused_ok(c);
+  const bool fused = o.fused && L > lmin && !opr && fused_ok(c) && (!pi || (L - 1 > lmin && L - 1 > hi));
   const bool pend = H.pending && !uin_zero;
   if ((rc = record_start(c))) return rc;
   if (fused) {
@@ -325,12 +331,9 @@ int run_cycle(adafac_ctx* c, Hier<T>& H, double* norm_out, const T* uin_zero) {
   }
   if ((rc = record_stop(c))) return rc;
   auto cscale_of = [&](int l) { return T(damping == ADAFAC_DAMP_EXP ? std::pow(o.omega_hat, L - l) : 1.0); };
-  // smallest levels lo..hi for the single-workgroup kernel
-  int hi = lmin - 1;
-  for (int l = lmin; l < L && l - lmin < kMaxSmall && nverts_of(d, l) <= kSmallVerts; ++l) hi = l;
   bool fed = fused;               // level l's u, R r and R~ r already written by the finer level
   for (int l = L - 1; l > hi; --l) {
-    const bool sweep = !pi && !opr && fed && l > lmin && H.v[l].n >= kCoarseSweepMinN &&
+    const bool sweep = !opr && fed && l > lmin && H.v[l].n >= kCoarseSweepMinN &&
                        sweep_level_ok(d, H.v[l].n, H.v[l].fem, H.v[l].pw != nullptr);
     if (sweep) {
       HIPCHK(c, launch_coarse_sweep<T>(d, H.v[l], H.v[l - 1], H.rts, omega, omega_t, cscale_of(l), damping,
@@ -370,7 +373,8 @@ int run_cycle(adafac_ctx* c, Hier<T>& H, double* norm_out, const T* uin_zero) {
   }
   for (int l = std::max(hi + 1, lmin + 1); l < L; ++l)
     HIPCHK(c, launch_prolong_add<T>(d, H.v[l], H.v[l - 1], H.v[l].S, H.v[l - 1].S,
-                                    pi ? H.v[l - 1].ic : nullptr, c->stream));
+                                    pi ? H.v[l - 1].ic : nullptr, c->stream,
+                                    (pi && fused && l == L - 1) ? H.v[l].ic : nullptr));
   if (fused) {
     H.pending = true;        // P S_{L-1} enters the next sweep (or the flush)
   } else {
@@ -406,9 +410,9 @@ int flush(adafac_ctx* c) {
   }
   Hier<double>& H = c->h64;
   if (!H.pending) return ADAFAC_OK;
-  const bool pi = c->opts.damping == ADAFAC_DAMP_PI;
-  HIPCHK(c, launch_prolong_add<double>(c->dim, H.v[L], H.v[L - 1], H.ufine[H.cur], H.v[L - 1].S,
-                                       pi ? H.v[L - 1].ic : nullptr, c->stream));
+  // pending only after a fused cycle, whose S_{L-1} already holds S_{L-1} - I c_L under adAFAC-PI
+  HIPCHK(c, launch_prolong_add<double>(c->dim, H.v[L], H.v[L - 1], H.ufine[H.cur], H.v[L - 1].S, nullptr,
+                                       c->stream));
   H.pending = false;
   return ADAFAC_OK;
 }
@@ -416,6 +420,12 @@ int flush(adafac_ctx* c) {
 // ---------------------------------------------------------------------------
 // Adaptive spacetrees: per-level box arrays and the cycle over the ragged levels
 // ---------------------------------------------------------------------------
+// Does level l of an adaptive tree take BoxMG weights from the next coarser level (a complete
+// level l <= k whose host transfer is stored)?
+bool adapt_pw_level(const adafac_ctx* c, int l) {
+  return l > c->lmin && l <= c->L && l < int(c->ops.lev.size()) && !c->ops.lev[l].pw.empty();
+}
+
 size_t layout_adaptive_tree(adafac_ctx* c, const AdaptHost& t, char* base) {
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
@@ -457,6 +467,8 @@ size_t layout_adaptive_tree(adafac_ctx* c, const AdaptHost& t, char* base) {
     A.u = reinterpret_cast<double*>(take(sizeof(double) * nv));
     A.bb = reinterpret_cast<double*>(take(sizeof(double) * nv));
     A.hh = reinterpret_cast<double*>(take(sizeof(double) * nv));
+    const bool boxpw = adapt_pw_level(c, l);
+    if (boxpw) A.pw = reinterpret_cast<double*>(take(sizeof(double) * nv << d));
     if (!mp) {
       A.s = reinterpret_cast<double*>(take(sizeof(double) * nv));
       A.S = reinterpret_cast<double*>(take(sizeof(double) * nv));
@@ -483,6 +495,7 @@ size_t layout_adaptive_tree(adafac_ctx* c, const AdaptHost& t, char* base) {
     E.hh = reinterpret_cast<float*>(take(sizeof(float) * nv));
     E.s = reinterpret_cast<float*>(take(sizeof(float) * nv));
     E.S = reinterpret_cast<float*>(take(sizeof(float) * nv));
+    if (boxpw) E.pw = reinterpret_cast<float*>(take(sizeof(float) * nv << d));
   }
   // norm partials: one slot per block of each level's up launch, levels packed
   std::vector<size_t> part(c->L + 1, 0);
@@ -493,7 +506,8 @@ size_t layout_adaptive_tree(adafac_ctx* c, const AdaptHost& t, char* base) {
     part[l] = npart;
     const AdaptHostLevel& H = t.lev[l];
     const int mx = H.nc[0] + 1, my = H.nc[1] + 1, mz = d == 3 ? H.nc[2] + 1 : 1;
-    tiled[l] = l < c->L && adapt_up_tiled(d, mx, my, mz, min_tiles);
+    // the tiled kernel restricts with d-linear weights only
+    tiled[l] = l < c->L && !adapt_pw_level(c, l + 1) && adapt_up_tiled(d, mx, my, mz, min_tiles);
     npart += adapt_up_slots(d, mx, my, mz, l < c->L, tiled[l] != 0);
   }
   double* partials = reinterpret_cast<double*>(take(sizeof(double) * 2 * npart));
@@ -546,6 +560,7 @@ int run_adapt_cycle(adafac_ctx* c, const std::vector<AdaptLevelT<T>>& ad, const 
   const int d = c->dim, L = c->L, lmin = c->lmin;
   const adafac_opts& o = c->opts;
   const T omega = T(o.omega), omega_t = T(o.omega_tilde);
+  const int pi = o.damping == ADAFAC_DAMP_PI;
   int rc = adapt_hang_views(c, ad);
   if (rc) return rc;
   if ((rc = record_start(c))) return rc;
@@ -559,8 +574,8 @@ int run_adapt_cycle(adafac_ctx* c, const std::vector<AdaptLevelT<T>>& ad, const 
                               c->stream));
   HIPCHK(c, launch_ad_norm_finalize(partials, int(c->npartials), norm_out, c->stream));
   for (int l = lmin; l < L; ++l)
-    HIPCHK(c, launch_ad_down<T>(d, ad[l], l > lmin ? &ad[l - 1] : nullptr, c->stream));
-  HIPCHK(c, launch_ad_down_update<T>(d, ad[L], ad[L - 1], c->stream));
+    HIPCHK(c, launch_ad_down<T>(d, ad[l], l > lmin ? &ad[l - 1] : nullptr, pi, c->stream));
+  HIPCHK(c, launch_ad_down_update<T>(d, ad[L], ad[L - 1], pi, c->stream));
   for (int l = L - 1; l >= lmin; --l) HIPCHK(c, launch_ad_update<T>(d, ad[l], &ad[l + 1], c->stream));
   return ADAFAC_OK;
 }
@@ -688,10 +703,9 @@ int upload_ops(adafac_ctx* c, Hier<T>& H, bool coarse) {
 // below the coefficient blocks, and the factors of R~.
 int build_adaptive(adafac_ctx* c) {
   const adafac_opts& o = c->opts;
-  if (o.transfer != ADAFAC_TRANSFER_DLINEAR) return fail(c, ADAFAC_EUNSUPPORTED, "adaptive trees use d-linear transfers");
   if (o.rtilde != ADAFAC_RTILDE_CONST_EPS1) return fail(c, ADAFAC_EUNSUPPORTED, "adaptive trees use the eps = 1 R~");
-  if (o.damping != ADAFAC_DAMP_JAC && o.damping != ADAFAC_DAMP_NONE)
-    return fail(c, ADAFAC_EUNSUPPORTED, "adaptive trees support adAFAC-Jac and plain additive damping");
+  if (o.damping == ADAFAC_DAMP_EXP)
+    return fail(c, ADAFAC_EUNSUPPORTED, "adaptive trees support adAFAC-Jac, adAFAC-PI and plain additive damping");
   if (c->L <= c->lmin) return fail(c, ADAFAC_EINVAL, "an adaptive tree needs l_max > l_min");
   int first = c->L;
   for (const RefineSpec& r : c->refine) first = std::min(first, r.level);
@@ -715,7 +729,9 @@ int build_adaptive(adafac_ctx* c) {
   u.nb = c->nb;
   u.k = c->ops.k;
   u.eps = c->eps;
-  m = build_host_ops(u, 0, o.omega);
+  // BoxMG (Sec. 2.5): the uniform hierarchy's operator-dependent P into the levels l <= k, which
+  // are complete; above k every coarse cell lies inside one block and P is d-linear
+  m = build_host_ops(u, o.transfer == ADAFAC_TRANSFER_BOXMG ? 1 : 0, o.omega);
   if (!m.empty()) return fail(c, ADAFAC_EINVAL, m);
   for (int i = 0; i < 5; ++i) {
     c->ad_rts.m[i] = u.rt_m[i];
@@ -787,6 +803,20 @@ int bind_adaptive(adafac_ctx* c) {
     if (!A.fem)
       HIPCHK(c, hipMemcpyAsync(const_cast<double*>(A.dg), H.dg.data(), sizeof(double) * H.dg.size(),
                                hipMemcpyHostToDevice, c->stream));
+    std::vector<float> pw32;
+    if (A.pw) {
+      // a complete level: its box is the whole lattice, so box and lattice indices agree
+      const std::vector<double>& pw = c->ops.lev[l].pw;
+      if (A.ox || A.oy || A.oz || A.mx != A.n + 1 || pw.size() != (H.nverts() << d))
+        return fail(c, ADAFAC_EINVAL, "internal: BoxMG weights on an incomplete level");
+      HIPCHK(c, hipMemcpyAsync(const_cast<double*>(A.pw), pw.data(), sizeof(double) * pw.size(),
+                               hipMemcpyHostToDevice, c->stream));
+      if (mp) {
+        pw32.assign(pw.begin(), pw.end());
+        HIPCHK(c, hipMemcpyAsync(const_cast<float*>(c->ad32[l].pw), pw32.data(), sizeof(float) * pw32.size(),
+                                 hipMemcpyHostToDevice, c->stream));
+      }
+    }
     std::vector<float> dg32;
     if (mp && !A.fem) {
       dg32.assign(H.dg.begin(), H.dg.end());
@@ -914,6 +944,7 @@ int batch_describe(void* vc, BatchReq* out) {
     out->h32.ufine[1] = c->h32.ufine[1];
     out->ezero = c->ezero;
   }
+  out->partials = c->partials;
   return ADAFAC_OK;
 }
 

@@ -105,6 +105,56 @@ __device__ __forceinline__ T interp(const AdaptLevelT<T>& C, const T* v, int x, 
   return acc;
 }
 
+// S_C at coarse vertex k = (X, Y, Z) of level C, less (adAFAC-PI) the injected correction of
+// level A there: c_A at the coinciding level-A vertex when k is a dof of C (A.s holds c at the
+// dofs of A under PI, zero elsewhere).
+template <int D, typename T, bool PI>
+__device__ __forceinline__ T coarse_sum(const AdaptLevelT<T>& A, const AdaptLevelT<T>& C, long k, int X, int Y,
+                                        int Z) {
+  T v = C.S[k];
+  if (PI && (C.vcls[k] & kDof)) {
+    const long kf = vidx<D>(A, 3 * X, 3 * Y, 3 * Z);
+    if (kf >= 0) v -= A.s[kf];
+  }
+  return v;
+}
+
+// P (S_C - I c_A) at vertex i = (x, y, z) of level A (PI; else P S_C): stored BoxMG weights on
+// complete levels that carry them (the box is the whole lattice there), else d-linear weights.
+template <int D, typename T, bool PI>
+__device__ __forceinline__ T prolong_at(const AdaptLevelT<T>& A, const AdaptLevelT<T>& C, unsigned i, int x, int y,
+                                        int z) {
+  const int nc = C.n;
+  const int cx = min(x / 3, nc - 1), cy = min(y / 3, nc - 1), cz = D == 3 ? min(z / 3, nc - 1) : 0;
+  const int sx = x - 3 * cx, sy = y - 3 * cy, sz = z - 3 * cz;
+  T acc = T(0);
+#pragma unroll
+  for (int e = 0; e < (1 << D); ++e) {
+    const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+    T w;
+    if (A.pw) {
+      w = A.pw[size_t(i) * (1 << D) + e];
+    } else {
+      w = lin3<T>(sx, ex) * lin3<T>(sy, ey);
+      if (D == 3) w *= lin3<T>(sz, ez);
+    }
+    if (w == T(0)) continue;
+    const long k = vidx<D>(C, cx + ex, cy + ey, cz + ez);
+    if (k >= 0) acc += w * coarse_sum<D, T, PI>(A, C, k, cx + ex, cy + ey, cz + ez);
+  }
+  return acc;
+}
+
+// R = P^T weight of fine vertex k = (fx, fy, fz) of level F for coarse vertex (x, y, z): the
+// stored BoxMG weight of that coarse corner of the fine vertex's coarse cell.
+template <int D, typename T>
+__device__ __forceinline__ T stored_rweight(const AdaptLevelT<T>& F, long k, int fx, int fy, int fz, int x, int y,
+                                            int z, int nc) {
+  const int ex = x - min(fx / 3, nc - 1), ey = y - min(fy / 3, nc - 1), ez = D == 3 ? z - min(fz / 3, nc - 1) : 0;
+  if (ex < 0 || ex > 1 || ey < 0 || ey > 1 || ez < 0 || ez > 1) return T(0);
+  return F.pw[size_t(k) * (1 << D) + (ex | (ey << 1) | (ez << 2))];
+}
+
 // Q1 diagonal at a dof (all 2^d cells exist): kref h^(d-2) sum of the cells' eps
 template <int D, typename T>
 __device__ __forceinline__ T fem_diag(const AdaptLevelT<T>& A, int x, int y, int z) {
@@ -326,7 +376,7 @@ __global__ void __launch_bounds__(NTU) k_ad_up_f(AdaptLevelT<T> A, AdaptLevelT<T
       const int oz = D == 3 ? o2 : 0;
       const T wz = D == 3 ? wl<T>(oz) : T(1);
       const T mz = D == 3 ? sel5(rts, oz) : T(1);
-      if (fx >= 2 && fx + 2 < F.mx && fy >= 2 && fy + 2 < F.my && (D == 2 || (fz >= 2 && fz + 2 < F.mz))) {
+      if (!F.pw && fx >= 2 && fx + 2 < F.mx && fy >= 2 && fy + 2 < F.my && (D == 2 || (fz >= 2 && fz + 2 < F.mz))) {
         const long k0 = (long(fz) * F.my + fy) * F.mx + fx, sy = F.mx, sz = long(F.mx) * F.my;
         const int ylo = D == 3 ? -2 : o2, yhi = D == 3 ? 2 : o2;
 #pragma unroll 1
@@ -367,7 +417,8 @@ __global__ void __launch_bounds__(NTU) k_ad_up_f(AdaptLevelT<T> A, AdaptLevelT<T
           for (int ox = -2; ox <= 2; ++ox) {
             const long k = vidx<D>(F, 3 * x + ox, 3 * y + oy, 3 * z + oz);
             if (k < 0) continue;
-            const T w = wl<T>(ox) * wl<T>(oy) * wz;
+            const T w = F.pw ? stored_rweight<D>(F, k, 3 * x + ox, 3 * y + oy, 3 * z + oz, x, y, z, A.n)
+                             : wl<T>(ox) * wl<T>(oy) * wz;
             Rh += w * F.hh[k];
             if (MODE == 0) continue;
             const T fb = F.bb[k];
@@ -534,7 +585,9 @@ __global__ void __launch_bounds__(NTT) k_ad_up_tiled(AdaptLevelT<T> A, AdaptLeve
   block_norm_partials(ssum, smax, partials);
 }
 
-template <int D, typename T>
+// S_l = (c - c~)_l + P S_{l-1}; adAFAC-PI: S_l = c_l + P (S_{l-1} - I c_l), which is
+// c_l - P I c_l + P S_{l-1} (c~_l = P I c_l, Sec. 3.2).
+template <int D, typename T, bool PI>
 __global__ void __launch_bounds__(NTA) k_ad_down(AdaptLevelT<T> A, AdaptLevelT<T> C, int has_c) {
   const unsigned nb = nbox<D>(A);
   AD_LOOP(i, nb) {
@@ -543,14 +596,14 @@ __global__ void __launch_bounds__(NTA) k_ad_down(AdaptLevelT<T> A, AdaptLevelT<T
     if (has_c) {
       int x, y, z;
       coords<D>(A, i, x, y, z);
-      S += interp<D>(C, C.S, x, y, z);
+      S += prolong_at<D, T, PI>(A, C, i, x, y, z);
     }
     A.S[i] = S;
   }
 }
 
-// The finest level: S_L = (c - c~)_L + P S_{L-1}, and at its dofs (all composite) u += S_L.
-template <int D, typename T>
+// The finest level: S_L as in k_ad_down, and at its dofs (all composite) u += S_L.
+template <int D, typename T, bool PI>
 __global__ void __launch_bounds__(NTA) k_ad_down_update(AdaptLevelT<T> A, AdaptLevelT<T> C) {
   const unsigned nb = nbox<D>(A);
   AD_LOOP(i, nb) {
@@ -558,7 +611,7 @@ __global__ void __launch_bounds__(NTA) k_ad_down_update(AdaptLevelT<T> A, AdaptL
     if (!(cls & (kDof | kHang))) continue;
     int x, y, z;
     coords<D>(A, i, x, y, z);
-    const T S = A.s[i] + interp<D>(C, C.S, x, y, z);
+    const T S = A.s[i] + prolong_at<D, T, PI>(A, C, i, x, y, z);
     A.S[i] = S;
     if (cls & kComp) A.u[i] += S;
   }
@@ -812,10 +865,15 @@ hipError_t launch_ad_leaf_up(int d, const AdaptLevelT<T>& A, T omega, T omega_t,
 }
 
 template <typename T>
-hipError_t launch_ad_down_update(int d, const AdaptLevelT<T>& A, const AdaptLevelT<T>& C, hipStream_t s) {
+hipError_t launch_ad_down_update(int d, const AdaptLevelT<T>& A, const AdaptLevelT<T>& C, int pi, hipStream_t s) {
   const long nb = long(A.mx) * A.my * (d == 3 ? A.mz : 1);
-  if (d == 2) k_ad_down_update<2, T><<<grid_for(nb), NTA, 0, s>>>(A, C);
-  else k_ad_down_update<3, T><<<grid_for(nb), NTA, 0, s>>>(A, C);
+  if (d == 2) {
+    if (pi) k_ad_down_update<2, T, true><<<grid_for(nb), NTA, 0, s>>>(A, C);
+    else k_ad_down_update<2, T, false><<<grid_for(nb), NTA, 0, s>>>(A, C);
+  } else {
+    if (pi) k_ad_down_update<3, T, true><<<grid_for(nb), NTA, 0, s>>>(A, C);
+    else k_ad_down_update<3, T, false><<<grid_for(nb), NTA, 0, s>>>(A, C);
+  }
   return hipGetLastError();
 }
 
@@ -828,11 +886,16 @@ hipError_t launch_ad_setup(int d, const AdaptLevelT<T>& A, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_ad_down(int d, const AdaptLevelT<T>& A, const AdaptLevelT<T>* C, hipStream_t s) {
+hipError_t launch_ad_down(int d, const AdaptLevelT<T>& A, const AdaptLevelT<T>* C, int pi, hipStream_t s) {
   const long nb = long(A.mx) * A.my * (d == 3 ? A.mz : 1);
   const AdaptLevelT<T> Cv = C ? *C : AdaptLevelT<T>{};
-  if (d == 2) k_ad_down<2, T><<<grid_for(nb), NTA, 0, s>>>(A, Cv, C ? 1 : 0);
-  else k_ad_down<3, T><<<grid_for(nb), NTA, 0, s>>>(A, Cv, C ? 1 : 0);
+  if (d == 2) {
+    if (pi) k_ad_down<2, T, true><<<grid_for(nb), NTA, 0, s>>>(A, Cv, C ? 1 : 0);
+    else k_ad_down<2, T, false><<<grid_for(nb), NTA, 0, s>>>(A, Cv, C ? 1 : 0);
+  } else {
+    if (pi) k_ad_down<3, T, true><<<grid_for(nb), NTA, 0, s>>>(A, Cv, C ? 1 : 0);
+    else k_ad_down<3, T, false><<<grid_for(nb), NTA, 0, s>>>(A, Cv, C ? 1 : 0);
+  }
   return hipGetLastError();
 }
 
@@ -878,11 +941,11 @@ hipError_t launch_ad_accumulate(int d, const AdaptLevel& A, const AdaptLevelT<fl
   template hipError_t launch_ad_leaf<T>(int, const AdaptLevelT<T>&, hipStream_t);                                 \
   template hipError_t launch_ad_up<T>(int, const AdaptLevelT<T>&, const AdaptLevelT<T>*, const RtSep<T>&, T, T,  \
                                       int, int, int, double*, hipStream_t);                                       \
-  template hipError_t launch_ad_down<T>(int, const AdaptLevelT<T>&, const AdaptLevelT<T>*, hipStream_t);          \
+  template hipError_t launch_ad_down<T>(int, const AdaptLevelT<T>&, const AdaptLevelT<T>*, int, hipStream_t);     \
   template hipError_t launch_ad_update<T>(int, const AdaptLevelT<T>&, const AdaptLevelT<T>*, hipStream_t);      \
   template hipError_t launch_ad_setup<T>(int, const AdaptLevelT<T>&, hipStream_t);                              \
   template hipError_t launch_ad_leaf_up<T>(int, const AdaptLevelT<T>&, T, T, int, double*, hipStream_t);          \
-  template hipError_t launch_ad_down_update<T>(int, const AdaptLevelT<T>&, const AdaptLevelT<T>&, hipStream_t);
+  template hipError_t launch_ad_down_update<T>(int, const AdaptLevelT<T>&, const AdaptLevelT<T>&, int, hipStream_t);
 ADAFAC_AD_INST(double)
 ADAFAC_AD_INST(float)
 

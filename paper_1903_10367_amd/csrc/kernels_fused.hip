@@ -255,6 +255,9 @@ struct Sweep3dArgs {
   T* bfout;
   T* rout;
   T omega_t, cscale;
+  // adAFAC-PI: the level's correction c at the c-points, I c, written to the next coarser level
+  // (nullptr for the other damping forms)
+  T* ic;
 };
 
 // Lattice loads and stores of the 3D sweep through a buffer resource: the per-lane column
@@ -444,7 +447,11 @@ __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_fine_sweep3d(S
           }
         }
         // FAS injection u_{L-1} = I u: planes z = p-2 with z = 0 mod 3 are the steps K = 2
-        if (K == 2 && own_pt && rinj) a.cu[lin<3>(x / 3, y / 3, z / 3, nvc)] = uz;
+        if (K == 2 && own_pt && rinj) {
+          const int ci = lin<3>(x / 3, y / 3, z / 3, nvc);
+          a.cu[ci] = uz;
+          if (a.ic) a.ic[ci] = (COARSE ? a.cscale : T(1)) * dinv * res;
+        }
       }
       Rb[K1][rslot] = res;
     }
@@ -717,7 +724,11 @@ __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_sweep3d_w32(Sw
           }
         }
         // FAS injection u_{L-1} = I u: planes z = p-2 with z = 0 mod 3 are the steps K = 2
-        if (K == 2 && own_pt && rinj) a.cu[lin<3>(x / 3, y / 3, z / 3, nvc)] = uz;
+        if (K == 2 && own_pt && rinj) {
+          const int ci = lin<3>(x / 3, y / 3, z / 3, nvc);
+          a.cu[ci] = uz;
+          if (a.ic) a.ic[ci] = (COARSE ? a.cscale : T(1)) * wdiag * res;
+        }
       }
       Rb[K1][rslot] = res;
     }
@@ -1078,6 +1089,7 @@ __global__ void __launch_bounds__(256) k_fine_sweep2d(LevelView<T> F, LevelView<
         smax = fmax(smax, fabs(rd));
         if (x % 3 == 0 && y % 3 == 0) {
           C.u[lin<2>(x / 3, y / 3, 0, nvc)] = u0;
+          if (damping == ADAFAC_DAMP_PI) C.ic[lin<2>(x / 3, y / 3, 0, nvc)] = c;
         }
       }
     }
@@ -1174,7 +1186,11 @@ hipError_t launch_coarse_sweep(int d, const LevelView<T>& L, const LevelView<T>&
   const int n = L.n, ntx = n / TX, tz = pick_tz(n), ntz = n / tz;
   Sweep3dArgs<T> a{L.u, nullptr, L.rr, C.S, C.u, C.rr, C.bt, L.eps, nullptr, L.h, omega, L.hd, rts,
                    n, L.nv, C.n, C.nv, L.nb, L.bs, tz, ntx, ntz, damping, 0,
-                   1, L.bt, L.S, L.bf, L.r, omega_t, cscale};
+                   1, L.bt, L.S, L.bf, L.r, omega_t, cscale, nullptr};
+  if (damping == ADAFAC_DAMP_PI) {
+    if (!C.ic) return hipErrorInvalidValue;
+    a.ic = C.ic;
+  }
   return launch_sweep3d<T>(a, L.eps != nullptr, s);
 }
 
@@ -1186,6 +1202,7 @@ hipError_t launch_fine_sweep(int d, const LevelView<T>& F, const LevelView<T>& C
   if (n % TX || F.pw) return hipErrorInvalidValue;   // needs 27 | n and d-linear transfer into L
   const int ntx = n / TX;
   const bool var = F.eps != nullptr;
+  if (damping == ADAFAC_DAMP_PI && !C.ic) return hipErrorInvalidValue;
   if (d == 2) {
     const unsigned nb = unsigned(ntx * ntx);
     if (var)
@@ -1198,7 +1215,8 @@ hipError_t launch_fine_sweep(int d, const LevelView<T>& F, const LevelView<T>& C
     const unsigned nb = unsigned(ntx * ntx * ntz);
     Sweep3dArgs<T> a{uin, uout, b, C.S, C.u, C.rr, C.bt, F.eps, partials, F.h, omega, F.hd, rts,
                      n, F.nv, C.n, C.nv, F.nb, F.bs, tz, ntx, ntz, damping, apply_pending,
-                     0, nullptr, nullptr, nullptr, nullptr, T(0), T(1)};
+                     0, nullptr, nullptr, nullptr, nullptr, T(0), T(1), nullptr};
+    if (damping == ADAFAC_DAMP_PI) a.ic = C.ic;
     const hipError_t e = launch_sweep3d<T>(a, var, s);
     if (e != hipSuccess) return e;
     *nparts = int(nb);

@@ -127,10 +127,12 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_levels(SmallLevelsArgs<
   }
 }
 
-// dst(f) += sum_c P(f <- c) (src(c) - sub(c)) on the interior vertices of level F.
+// dst(f) += sum_c P(f <- c) (src(c) - sub(c)) - self(f) on the interior vertices of level F
+// (sub, self may be null).
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_prolong_add(LevelView<T> F, LevelView<T> C, T* __restrict__ dst,
-                                                     const T* __restrict__ src, const T* __restrict__ sub) {
+                                                     const T* __restrict__ src, const T* __restrict__ sub,
+                                                     const T* __restrict__ self) {
   // lattices here stay below 2^32 vertices (the launcher checks): 32-bit index arithmetic
   const unsigned nv = unsigned(F.nv);
   const unsigned nverts = D == 2 ? nv * nv : nv * nv * nv;
@@ -139,7 +141,9 @@ __global__ void __launch_bounds__(256) k_prolong_add(LevelView<T> F, LevelView<T
   const unsigned q = i / nv;
   const int x = int(i - q * nv), y = D == 3 ? int(q % nv) : int(q), z = D == 3 ? int(q / nv) : 0;
   if (!is_interior<D>(x, y, z, int(nv))) return;
-  dst[i] += prolong_value<T, D>(F, C, x, y, z, src, sub);
+  T v = prolong_value<T, D>(F, C, x, y, z, src, sub);
+  if (self) v -= self[i];
+  dst[i] += v;
 }
 
 // FP32 cycles inside FP64 defect correction: the two FP64 steps of an outer iteration.
@@ -233,14 +237,14 @@ hipError_t launch_level_update(int d, const LevelView<T>& C, const LevelView<T>&
 
 template <typename T>
 hipError_t launch_prolong_add(int d, const LevelView<T>& F, const LevelView<T>& C, T* dst, const T* src,
-                              const T* sub, hipStream_t s) {
+                              const T* sub, hipStream_t s, const T* self) {
   size_t nverts = d == 2 ? size_t(F.nv) * F.nv : size_t(F.nv) * F.nv * F.nv;
   if (nverts >= (size_t(1) << 32)) return hipErrorInvalidValue;
   unsigned nb = unsigned((nverts + 255) / 256);
   if (d == 2)
-    k_prolong_add<T, 2><<<nb, 256, 0, s>>>(F, C, dst, src, sub);
+    k_prolong_add<T, 2><<<nb, 256, 0, s>>>(F, C, dst, src, sub, self);
   else
-    k_prolong_add<T, 3><<<nb, 256, 0, s>>>(F, C, dst, src, sub);
+    k_prolong_add<T, 3><<<nb, 256, 0, s>>>(F, C, dst, src, sub, self);
   return hipGetLastError();
 }
 
@@ -309,8 +313,8 @@ template hipError_t launch_level_update<float>(int, const LevelView<float>&, con
                                                const LevelView<float>&, const RtSep<float>&, float, float, float,
                                                int, int, hipStream_t);
 template hipError_t launch_prolong_add<double>(int, const LevelView<double>&, const LevelView<double>&,
-                                               double*, const double*, const double*, hipStream_t);
+                                               double*, const double*, const double*, hipStream_t, const double*);
 template hipError_t launch_prolong_add<float>(int, const LevelView<float>&, const LevelView<float>&, float*,
-                                              const float*, const float*, hipStream_t);
+                                              const float*, const float*, hipStream_t, const float*);
 
 }  // namespace adafac

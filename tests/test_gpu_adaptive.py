@@ -20,19 +20,20 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_both(d, L, lu, f, eps=None, cycles=6, centre=None, radius=0.2, flags=None, damping="jac"):
+def run_both(d, L, lu, f, eps=None, cycles=6, centre=None, radius=0.2, flags=None, damping="jac",
+             transfer="dlinear"):
     from paper_1903_10367_amd import Solver
     centre = centre if centre is not None else (0.5,) * d
     refine = flags if flags is not None else inp.refine_ball(d, L, lu, centre, radius)
     kw = dict(refine=flags) if flags is not None else dict(ball=(centre, radius, lu))
-    s = Solver(d, 1, L, f, eps_blocks=eps, damping=damping, **kw)
+    s = Solver(d, 1, L, f, eps_blocks=eps, damping=damping, transfer=transfer, **kw)
     s.cycle(cycles)
     hg = s.residuals()
     levels = {l: s.level(l, "u") for l in range(1, L + 1)}
     ufine = s.solution()
     ncomp = s.composite_dofs()
     s.close()
-    T = adaptive.AdaptiveTree(d, L, 1, lu, refine, eps)
+    T = adaptive.AdaptiveTree(d, L, 1, lu, refine, eps, transfer=transfer)
     U, ho = adaptive.solve(T, f, cycles, damping=damping)
     assert ncomp == len(T.composite_index())
     r0 = ho[0][0]
@@ -50,11 +51,28 @@ def run_both(d, L, lu, f, eps=None, cycles=6, centre=None, radius=0.2, flags=Non
     return hg, ho
 
 
-@pytest.mark.parametrize("damping", ["jac", "none"])
-def test_2d_disk(damping):
-    say("case adaptive 2d disk L=4", damping)
+@pytest.mark.parametrize("transfer", ["dlinear", "boxmg"])
+@pytest.mark.parametrize("damping", ["jac", "pi", "none"])
+def test_2d_disk(damping, transfer):
+    say("case adaptive 2d disk L=4", damping, transfer)
     eps = inp.eps_blocks(2, 2, 2.0, seed=70)
-    run_both(2, 4, 2, inp.rhs(2, 4, seed=71), eps, damping=damping)
+    run_both(2, 4, 2, inp.rhs(2, 4, seed=71), eps, damping=damping, transfer=transfer)
+
+
+@pytest.mark.parametrize("damping", ["jac", "pi"])
+def test_3d_ball_boxmg(damping):
+    """BoxMG transfers into the complete levels 1 -> 2 of a 3D ball tree whose 9^3 coefficient
+    blocks make the level-1 cells straddle blocks (Sec. 2.5), with adAFAC-Jac and adAFAC-PI."""
+    say("case adaptive 3d ball L=3 boxmg", damping)
+    eps = inp.eps_blocks(3, 2, 3.0, seed=85)
+    run_both(3, 3, 2, inp.rhs(3, 3, seed=86), eps, centre=(0.45, 0.5, 0.55), radius=0.15, transfer="boxmg",
+             damping=damping)
+
+
+def test_3d_ball_deeper_pi():
+    say("case adaptive 3d ball L=4 pi")
+    run_both(3, 4, 2, inp.rhs(3, 4, seed=87, dist="normal"), None, centre=(0.4, 0.55, 0.5), radius=0.12, cycles=4,
+             damping="pi")
 
 
 def test_3d_ball():
@@ -75,12 +93,14 @@ def test_2d_explicit_flags():
     run_both(2, 5, 2, inp.rhs(2, 5, seed=76), inp.eps_blocks(2, 1, 1.0, seed=77), flags=flags, cycles=5)
 
 
-def test_disk_workload_l6():
+@pytest.mark.parametrize("transfer", ["boxmg", "dlinear"])
+def test_disk_workload_l6(transfer):
     """The 2D jump-coefficient disk workload: 9x9 blocks, uniform to level 2, disk r = 0.25
-    refined to level 6 (729^2 finest cells there)."""
-    say("case adaptive 2d disk workload L=6")
+    refined to level 6 (729^2 finest cells there), with BoxMG transfers as the workload names
+    them (and d-linear ones)."""
+    say("case adaptive 2d disk workload L=6", transfer)
     eps = inp.eps_blocks(2, 2, 3.0, seed=78)
-    run_both(2, 6, 2, inp.rhs(2, 6, seed=79), eps, radius=0.25, cycles=3)
+    run_both(2, 6, 2, inp.rhs(2, 6, seed=79), eps, radius=0.25, cycles=3, transfer=transfer)
 
 
 def test_solve_to_tolerance():

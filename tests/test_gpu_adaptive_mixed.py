@@ -116,15 +116,16 @@ def test_3d_ball_outer_steps():
     check_steps(T, f, hg, 4, label="3d")
 
 
-def test_disk_workload_l6_outer_steps():
-    say("case mixed adaptive 2d disk workload L=6")
+@pytest.mark.parametrize("transfer", ["dlinear", "boxmg"])
+def test_disk_workload_l6_outer_steps(transfer):
+    say("case mixed adaptive 2d disk workload L=6", transfer)
     eps = inp.eps_blocks(2, 2, 3.0, seed=94)
     f = inp.rhs(2, 6, seed=95)
-    s = solver(2, 6, 2, f, eps, (0.5, 0.5), 0.25)
+    s = solver(2, 6, 2, f, eps, (0.5, 0.5), 0.25, transfer=transfer)
     s.cycle(2)
     hg = s.residuals()
     s.close()
-    T = adaptive.AdaptiveTree(2, 6, 1, 2, inp.refine_ball(2, 6, 2, (0.5, 0.5), 0.25), eps)
+    T = adaptive.AdaptiveTree(2, 6, 1, 2, inp.refine_ball(2, 6, 2, (0.5, 0.5), 0.25), eps, transfer=transfer)
     check_steps(T, f, hg, 2, label="L6")
 
 

@@ -123,6 +123,20 @@ def test_damping_variants(damping):
     assert_parity(hg, ug, ho, uo)
 
 
+@pytest.mark.parametrize("fused", [True, False])
+@pytest.mark.parametrize("d,L", [(2, 4), (3, 3), (3, 4), (2, 6)])
+def test_pi_single_pass_and_one_kernel_per_step(d, L, fused):
+    """adAFAC-PI (c~_l = P I c_l, Sec. 3.2) in the single-pass sweeps (I c written by the sweep,
+    subtracted from S_{L-1} by the last prolongation) and in the one-kernel-per-step form."""
+    f = inp.rhs(d, L, seed=13 + d + L)
+    say("case pi", d, L, fused)
+    cycles = 8 if d == 2 else 5
+    hg, ug = gpu_run(d, L, f, cycles=cycles, damping="pi", fused=fused)
+    ho, uo = oracle_run(d, L, f, cycles=cycles, damping="pi")
+    H = hierarchy.Hierarchy(d, L, 1)
+    assert_parity(hg, ug, ho, uo, floor=lambda: oracle_floor(H, H.rhs(f), cycles, damping="pi"))
+
+
 @pytest.mark.parametrize("d,L,fused", [(2, 4, True), (3, 3, True), (3, 3, False)])
 def test_level_arrays_match_fas_oracle(d, L, fused):
     """u_l (injection), b_l (FAS rhs with tau), b~_l, r_l and S_l of the second cycle."""
@@ -144,13 +158,27 @@ def test_level_arrays_match_fas_oracle(d, L, fused):
         assert np.abs(g - ref).max() <= 1e-12 * scale, f"level {l} {w}"
 
 
-def test_full_size_3d_poisson_l5():
-    """The benchmark workload itself (243^3 cells), three cycles, in the benchmark's launch shape."""
+@pytest.mark.parametrize("damping", ["jac", "pi"])
+def test_full_size_3d_poisson_l5(damping):
+    """The benchmark workload itself (243^3 cells), three cycles, in the benchmark's launch shape
+    (with adAFAC-PI also the level-4 FAS sweep writes I c_4)."""
     w = inp.workload_3d_poisson_l5()
-    say("case 3d poisson L=5 full size")
-    hg, ug = gpu_run(3, 5, w["f"], cycles=3)
+    say("case 3d poisson L=5 full size", damping)
+    hg, ug = gpu_run(3, 5, w["f"], cycles=3, damping=damping)
     say("oracle 3d L=5")
-    ho, uo = oracle_run(3, 5, w["f"], cycles=3)
+    ho, uo = oracle_run(3, 5, w["f"], cycles=3, damping=damping)
+    assert_parity(hg, ug, ho, uo)
+
+
+def test_full_size_3d_jump_27_blocks():
+    """243^3 cells with 27^3 coefficient blocks 10^U(0,4): the variable-eps single-pass sweep at
+    block size 9 (the serving mix's largest request shape), two cycles."""
+    eps = inp.eps_blocks(3, 3, 4.0, seed=14)
+    f = inp.rhs(3, 5, seed=15)
+    say("case 3d jump 27^3 blocks L=5 full size")
+    hg, ug = gpu_run(3, 5, f, eps, cycles=2)
+    say("oracle 3d L=5 27^3 blocks")
+    ho, uo = oracle_run(3, 5, f, eps, cycles=2)
     assert_parity(hg, ug, ho, uo)
 
 

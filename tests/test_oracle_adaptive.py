@@ -107,9 +107,23 @@ def test_hanging_values_reproduce_dlinear_functions(d):
         assert np.abs(U[l][have] - g(l)[have]).max() < 1e-13
 
 
-@pytest.mark.parametrize("transfer", ["dlinear", "boxmg"])
-@pytest.mark.parametrize("damping", ["jac", "none"])
-@pytest.mark.parametrize("d", [2, 3])
+@pytest.mark.parametrize("d,L,k", [(2, 3, 0), (2, 3, 2), (3, 2, 1)])
+def test_uniform_tree_pi_is_the_uniform_pi_cycle(d, L, k):
+    """adAFAC-PI on a tree refined everywhere is the uniform PI cycle (c~_l = P I c_l)."""
+    eps = inp.eps_blocks(d, k, 2.0, seed=17) if k else None
+    T = adaptive.AdaptiveTree(d, L, 1, L, {}, eps)
+    f = inp.rhs(d, L, seed=18)
+    U, hist = adaptive.solve(T, f, 6, damping="pi")
+    H = hierarchy.Hierarchy(d, L, 1, eps)
+    u, ho = cycle.solve(H, H.rhs(f), 6, damping="pi")
+    assert np.abs(U[L].ravel() - u).max() <= 1e-13 * np.abs(u).max()
+    for a, b in zip(hist, ho):
+        assert abs(a[0] - b[0]) <= 1e-13 * ho[0][0]
+
+
+@pytest.mark.parametrize("d,damping,transfer", [
+    (2, "jac", "dlinear"), (2, "none", "dlinear"), (2, "pi", "dlinear"), (2, "jac", "boxmg"), (2, "pi", "boxmg"),
+    (3, "jac", "dlinear"), (3, "none", "boxmg"), (3, "pi", "boxmg")])
 def test_cycle_equals_dense_generating_system_form(d, damping, transfer):
     if d == 2:
         eps = inp.eps_blocks(2, 2, 2.0, seed=5)
