@@ -131,3 +131,46 @@ def moving_source(seed=0, steps=4, d=3):
                 x[a], v[a] = 0.6 - x[a], -v[a]
         out.append(x.copy())
     return out
+
+
+# The paper's own set-ups (Sec. 5): f = 0, u = 1 on the boundary part x_2 = 0 and u = 0 on the
+# rest of the boundary, and four coefficient fields on the unit square with eps = 1 in one
+# region and eps = 10^-k in the other.  x_1 is the first coordinate (the last array axis),
+# x_2 the second.
+
+PAPER_FIELDS = ("homogeneous", "split", "needle", "checkerboard")
+
+
+def paper_eps_cells(L, kind, k):
+    """eps on the (3^L)^2 finest cells, evaluated at the cell centres (array [x_2, x_1]):
+    homogeneous: 1; split: 10^-k where x_1 > 1/2 (an axis-aligned split that no 3:1 level
+    resolves); needle: 10^-k on the strip |x_1 - 1/2| <= 0.01, x_2 <= 1/2 (width 0.02, from
+    the x_1 axis half-way into the domain); checkerboard: the lines x_2 = 5 x_1 - 2.5 and
+    x_2 = 0.2 x_1 + 0.5 cut the square into four regions, and eps = 10^-k in the two where
+    (x_2 - 5 x_1 + 2.5)(x_2 - 0.2 x_1 - 0.5) < 0."""
+    n = 3 ** L
+    c = (np.arange(n) + 0.5) / n
+    x1, x2 = np.meshgrid(c, c, indexing="xy")       # x1 varies along the last axis
+    low = 10.0 ** (-k)
+    if kind == "homogeneous":
+        inside = np.zeros((n, n), dtype=bool)
+    elif kind == "split":
+        inside = x1 > 0.5
+    elif kind == "needle":
+        inside = (np.abs(x1 - 0.5) <= 0.01) & (x2 <= 0.5)
+    elif kind == "checkerboard":
+        inside = (x2 - 5.0 * x1 + 2.5) * (x2 - 0.2 * x1 - 0.5) < 0.0
+    else:
+        raise ValueError(kind)
+    return np.where(inside, low, 1.0)
+
+
+def paper_boundary(d, L):
+    """Dirichlet data on the (3^L + 1)^d vertex lattice: 1 on x_2 = 0, 0 on the rest of the
+    boundary and in the interior (interior entries are ignored)."""
+    n = 3 ** L
+    g = np.zeros((n + 1,) * d)
+    idx = [slice(None)] * d
+    idx[d - 2] = 0                                   # the x_2 axis is the second-to-last
+    g[tuple(idx)] = 1.0
+    return g

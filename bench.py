@@ -23,6 +23,14 @@ SWEEP_SOURCE = os.path.join(ROOT, "paper_1903_10367_amd", "csrc", "kernels_fused
 COPY_BYTES = 1 << 30   # plain device copy used to calibrate the rocprofv3 byte counters
 
 
+def cycle_bytes(d, L, lmin=1):
+    """Algorithmic bytes of one whole cycle: per fine dof u read + u write + b read (24 B); per
+    coarse dof u, b, b~ and S each written once and read once (64 B)."""
+    nf = (3 ** L - 1) ** d
+    nc = sum((3 ** l - 1) ** d for l in range(lmin, L))
+    return 24 * nf + 64 * nc
+
+
 def fine_sweep_bytes(d, L):
     """Algorithmic bytes of one fused fine sweep: per fine dof u read + u write + b read
     (24 B); per dof of level L-1 S read and u, R r, R~ r written (32 B)."""
@@ -72,6 +80,32 @@ def cpu_baseline(d, L, f, cycles, dofs):
     return {"value": dofs * cycles / dt, "unit": "vertex-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{cycles} full cycles of the same 243^3 workload (operator setup excluded), "
                       f"{dt:.1f} s"}
+
+
+def oracle_reference(d, L, f, outdir):
+    """Part of the CPU-baseline leg, run in a child process started before the parent touches
+    the GPU, while the GPU legs run: the oracle's FP64 solve of the same workload to
+    ||r||_h / ||r^0||_h <= 1e-8 from u = 0; its solution goes to outdir/oracle.npy, its time and
+    cycle count are returned."""
+    import numpy as np
+    from oracle import cycle, hierarchy
+    H = hierarchy.Hierarchy(d, L, 1)
+    b = H.rhs(f)
+    t0 = time.perf_counter()
+    u, hist = cycle.solve(H, b, 400, tol=1e-8)
+    dt = time.perf_counter() - t0
+    np.save(os.path.join(outdir, "oracle.npy"), u)
+    return {"oracle_cycles": len(hist), "oracle_solve_s": dt, "oracle_rel_residual": hist[-1][0] / hist[0][0]}
+
+
+def _oracle_child(args):
+    d, L, seed, outdir = args
+    import adafac_inputs as inp
+    return oracle_reference(d, L, inp.workload_3d_poisson_l5(seed=seed)["f"], outdir)
+
+
+SOLVE_FORMS = (("fp64", {}), ("fp32_refined_k4", {"precision": "fp32_refined", "inner_k": 4}),
+               ("fp32_refined_k8", {"precision": "fp32_refined", "inner_k": 8}))
 
 
 def timed_solve(Solver, torch, d, L, f, **kw):
@@ -198,9 +232,9 @@ def copy_and_cold(s, torch, nbytes=2 << 30, reps=10, cold_cycles=20):
 
 
 def adaptive_workloads(Solver, torch, log=None):
-    """The two adaptive-spacetree workloads (d-linear transfers, adAFAC-Jac):
+    """The two adaptive-spacetree workloads (adAFAC-Jac):
     2D disk: 9x9 eps blocks 10^U(0,3), uniform to level 2, disk r = 0.25 refined to level 6,
-    f ~ U(-1,1); timed cycles and a solve to 1e-8.
+    f ~ U(-1,1), BoxMG transfers; timed cycles and a solve to 1e-8.
     3D moving Gaussian: 27^3 eps blocks 10^U(0,4), uniform to level 3, source of width 0.05 at a
     seeded centre, cells meeting the ball of radius 3 sigma refined to level 6, the tree
     re-refined as the centre moves by 0.03 (every 5 cycles in FP64, every 2 outer steps of 4
@@ -210,7 +244,7 @@ def adaptive_workloads(Solver, torch, log=None):
     import adafac_inputs as inp
     out = {}
     eps2 = inp.eps_blocks(2, 2, 3.0, seed=21)
-    s = Solver(2, 1, 6, inp.rhs(2, 6, seed=22), eps_blocks=eps2, ball=((0.5, 0.5), 0.25, 2))
+    s = Solver(2, 1, 6, inp.rhs(2, 6, seed=22), eps_blocks=eps2, ball=((0.5, 0.5), 0.25, 2), transfer="boxmg")
     dofs = s.dofs_per_cycle()
     s.cycle(5)
     torch.cuda.synchronize()
@@ -225,7 +259,8 @@ def adaptive_workloads(Solver, torch, log=None):
     torch.cuda.synchronize()
     ts = time.perf_counter() - t1
     h = s.residuals()
-    out["disk_2d_l6"] = {"composite_dofs": s.composite_dofs(), "dofs_per_cycle": dofs, "us_per_cycle": dt * 1e6,
+    out["disk_2d_l6"] = {"transfer": "boxmg", "composite_dofs": s.composite_dofs(), "dofs_per_cycle": dofs,
+                         "us_per_cycle": dt * 1e6,
                          "vertex_updates_per_s": dofs / dt, "solve_1e-8_cycles": n, "solve_1e-8_ms": ts * 1e3,
                          "rel_residual": h[-1][0] / h[0][0]}
     s.close()
@@ -277,18 +312,72 @@ def adaptive_workloads(Solver, torch, log=None):
     return out
 
 
+def paper_setups(Solver, torch, log=None, cycles=120):
+    """The set-ups of Sec. 5 on regular grids (f = 0, u = 1 on x_2 = 0): normalised residual
+    after `cycles` cycles (or the cycle at which the solve diverged) per damping variant, (a) for
+    the homogeneous field at L = 5..8 (the paper's claim: plain additive deteriorates at 7 levels
+    and diverges at 8, adAFAC-Jac and -PI stay stable, exponential damping slows down), (b) for
+    the split, needle and checkerboard fields at L = 6 with eps jumps 10^-1 and 10^-5, d-linear and
+    BoxMG transfers.  Timings are those of the run (set-up excluded)."""
+    import numpy as np
+    import adafac_inputs as inp
+    from paper_1903_10367_amd import AdafacError
+
+    def run(L, field, k, transfer, damping):
+        g = inp.paper_boundary(2, L)
+        eps = None if field == "homogeneous" else inp.paper_eps_cells(L, field, k)
+        s = Solver(2, 1, L, np.zeros_like(g), eps_blocks=eps, transfer=transfer, damping=damping,
+                   omega_hat=0.5, dirichlet=g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        status = "ran"
+        try:
+            n = s.solve(1e-8, cycles)
+            status = "converged" if n < cycles else "ran"
+        except AdafacError:
+            status = "diverged"
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        h = s.residuals()
+        s.close()
+        rel = h[-1][0] / h[0][0] if h and h[0][0] > 0 else float("nan")
+        return {"status": status, "cycles": len(h), "rel_residual": rel, "ms": dt * 1e3}
+
+    out = {"cycles_cap": cycles, "regular_poisson": {}, "fields": {}}
+    for L in (5, 6, 7, 8):
+        for damping in ("none", "exp", "pi", "jac"):
+            r = run(L, "homogeneous", 1, "dlinear", damping)
+            out["regular_poisson"][f"L{L}_{damping}"] = r
+            if log:
+                log(f"paper set-up Poisson L={L} {damping}: {r['status']} after {r['cycles']} cycles, "
+                    f"{r['rel_residual']:.2e}")
+    for field in ("split", "needle", "checkerboard"):
+        for k in (1, 5):
+            for transfer in ("dlinear", "boxmg"):
+                for damping in ("none", "pi", "jac"):
+                    r = run(6, field, k, transfer, damping)
+                    out["fields"][f"{field}_k{k}_{transfer}_{damping}"] = r
+                    if log:
+                        log(f"paper set-up {field} k={k} {transfer} {damping}: {r['status']} after "
+                            f"{r['cycles']} cycles, {r['rel_residual']:.2e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle timing and the oracle reference solve")
     ap.add_argument("--cpu-cycles", type=int, default=2)
     ap.add_argument("--no-adaptive", action="store_true", help="skip the adaptive-tree workloads")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests per serving pass (0: skip)")
     ap.add_argument("--serve-loads", default="0.5,0.9", help="arrival rates as fractions of capacity")
     ap.add_argument("--serve-budget-gb", type=float, default=4.0)
     ap.add_argument("--serve-max-cycles", type=int, default=3000)
+    ap.add_argument("--paper-setups", action="store_true",
+                    help="also run the set-ups of Sec. 5 on regular grids (stability of the damping variants)")
     ap.add_argument("--profile-pass", action="store_true",
                     help="counter runs: a 1 GiB device copy (byte-counter calibration), then a few cycles")
     args = ap.parse_args()
@@ -296,6 +385,16 @@ def main():
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is a design note, not a measured path.", file=sys.stderr)
         sys.exit(2)
+
+    import tempfile
+    refdir = tempfile.mkdtemp(prefix="adafac_bench_")
+    ref = pool = None
+    if not args.no_cpu_baseline and not args.profile_pass:
+        # the oracle reference solve runs in a child started before this process touches the GPU
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        pool = cf.ProcessPoolExecutor(1, mp_context=mp.get_context("spawn"))
+        ref = pool.submit(_oracle_child, (3, 5, 0, refdir))
 
     import torch
     import adafac_inputs as inp
@@ -334,6 +433,18 @@ def main():
     copy_gbs, cold = copy_and_cold(s, torch)
     s.close()
 
+    # the other damping forms of the cycle on the same workload (time per cycle)
+    forms = {"jac": {"us_per_cycle": dt / args.steps * 1e6}}
+    for name in ("pi", "none"):
+        sf = Solver(d, 1, L, w["f"], device="cuda:0", damping=name)
+        sf.cycle(5)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sf.cycle(50)
+        torch.cuda.synchronize()
+        forms[name] = {"us_per_cycle": (time.perf_counter() - t1) / 50 * 1e6}
+        sf.close()
+
     value = dofs * args.steps / dt
     kavg_s = ksum_ms / 1e3 / max(nlaunch, 1)
     kbytes = fine_sweep_bytes(d, L)
@@ -341,19 +452,20 @@ def main():
     traffic = measured_traffic()
 
     # solves to 1e-8: FP64 cycles, and FP32 cycles inside FP64 defect correction
+    import numpy as np
     solves = {}
     u64 = None
-    for name, kw in (("fp64", {}), ("fp32_refined_k4", {"precision": "fp32_refined", "inner_k": 4}),
-                     ("fp32_refined_k8", {"precision": "fp32_refined", "inner_k": 8})):
+    for name, kw in SOLVE_FORMS:
         res = timed_solve(Solver, torch, d, L, w["f"], **kw)
         u = res.pop("u")
+        np.save(os.path.join(refdir, name + ".npy"), u)
         if u64 is None:
             u64 = u
         else:
-            import numpy as np
             res["u_rel_diff_vs_fp64_solve"] = float(np.linalg.norm(u - u64) / np.linalg.norm(u64))
             res["speedup_vs_fp64"] = solves["fp64"]["ms"] / res["ms"]
         solves[name] = res
+    del u, u64
 
     out = {
         "metric": "vertex-updates/s & %HBM peak per cycle",
@@ -371,6 +483,10 @@ def main():
         "config": {"workload": "3d-poisson-243^3-adafac-jac-fp64", "levels": "1..5",
                    "dofs_per_cycle": dofs, "omega": 0.6, "omega_tilde": 0.6, "transfer": "d-linear",
                    "rhs": "N(0,1) seed 0"},
+        "cycle": {"algorithmic_bytes": cycle_bytes(d, L), "us": dt / args.steps * 1e6,
+                  "achieved": cycle_bytes(d, L) / (dt / args.steps) / 1e9,
+                  "frac": cycle_bytes(d, L) / (dt / args.steps) / 1e9 / HBM_PEAK_GBS},
+        "damping_forms": forms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_sweep3d_w32", "kernel_avg_us": kavg_s * 1e6,
@@ -383,12 +499,23 @@ def main():
     }
     if not args.no_adaptive:
         out["adaptive"] = adaptive_workloads(Solver, torch, log)
+    if args.paper_setups:
+        out["paper_setups"] = paper_setups(Solver, torch, log)
     if args.serve_requests > 0:
         loads = [float(x) for x in args.serve_loads.split(",") if x]
         out["serving"] = serving(Server, torch, args.serve_requests, loads, args.serve_budget_gb,
                                  args.serve_max_cycles, log)
-    if not args.no_cpu_baseline:
+    if ref is not None:
         out["cpu_baseline"] = cpu_baseline(d, L, w["f"], args.cpu_cycles, dofs)
+        out["cpu_baseline"]["oracle_solve_to_1e-8"] = ref.result()
+        pool.shutdown()
+        uo = np.load(os.path.join(refdir, "oracle.npy"))
+        nuo = np.linalg.norm(uo)
+        for name in solves:
+            ug = np.load(os.path.join(refdir, name + ".npy"))
+            solves[name]["u_rel_diff_vs_oracle"] = float(np.linalg.norm(ug - uo) / nuo)
+    import shutil
+    shutil.rmtree(refdir, ignore_errors=True)
     print(json.dumps(out), flush=True)
 
 

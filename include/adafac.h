@@ -176,6 +176,17 @@ int adafac_workspace_bytes(const adafac_ctx* ctx, size_t* bytes);
  * (NULL = the null stream).  EDEVICE if a copy fails. */
 int adafac_bind(adafac_ctx* ctx, void* dev_workspace, size_t bytes, void* hip_stream);
 
+/* Inhomogeneous Dirichlet data (the set-ups of Sec. 5: u = 1 on x_2 = 0, 0 on
+ * the rest of the boundary): g holds n = (3^l_max + 1)^dim values on the finest
+ * vertex lattice; its boundary entries are the values of u there, the interior
+ * entries are ignored.  The iterate then carries these values on its boundary
+ * vertices (adafac_set_solution keeps them, adafac_get_solution returns them),
+ * and every residual sees them, which is the load -A G of the lift u = u_0 + G.
+ * Takes effect at the next adafac_bind.  Uniform trees only: EUNSUPPORTED with
+ * refinement (here or at build_operators); EINVAL on a wrong n or a non-finite
+ * boundary value.  All-zero boundary values restore the homogeneous problem. */
+int adafac_set_dirichlet_lattice(adafac_ctx* ctx, const double* g, size_t n);
+
 /* Size of the library's static device workspace (see adafac_bind_static). */
 #define ADAFAC_STATIC_WORKSPACE_BYTES (32u << 20)
 
@@ -333,15 +344,20 @@ int adafac_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
  *    steps for FP32_REFINED);
  *  - admits, uploading while that round runs; admitted requests join the next
  *    round.
- * Requests whose finest level has at most batch_max_vertices vertices advance
- * together in ONE launch of a work-queue kernel: one workgroup per request, all
- * levels in sequence, stopping exactly at the first iterate that meets the
- * tolerance.  Larger requests advance on their own streams.  Their work
- * overlaps with the batched launch, and they stop at the end of the round in
- * which their residual met the tolerance, so up to cycles_per_round - 1 extra
- * cycles run.  A finished request's solution is copied to host memory and its
- * device memory and slot are freed.  A request's arithmetic does not depend on
- * the other requests, so results are the same served alone or in a mix.
+ * All active requests, of any depth and dimension, advance together in shared
+ * launches.  A request's cycle is a chain of phases (finest-level residual and
+ * Jacobi step, the residual norms and stopping rule, the FAS update of each
+ * coarser level, the prolongations back up), each cut into work items of a few
+ * thousand vertices; one launch runs the same phase slot of every request's
+ * chain, so requests of every size share each launch and the launch count per
+ * round (cycles_per_round x the longest chain) does not grow with the number
+ * of requests.  A request stops exactly at the first iterate that meets the
+ * tolerance.  Requests above batch_max_vertices finest vertices (default:
+ * none) advance on streams of their own instead and stop at the end of the
+ * round in which they converged.  A finished request's solution is copied to
+ * host memory and its device memory and slot are freed.  A request's
+ * arithmetic does not depend on the other requests, so results are the same
+ * served alone or in a mix.
  * A server is driven by one host thread.
  * ------------------------------------------------------------------------ */
 typedef struct adafac_server adafac_server;
@@ -350,7 +366,7 @@ typedef struct {
   int max_active;             /* requests on the device at once, 1..4096 */
   int max_queued;             /* requests waiting for admission (EAGAIN beyond), >= 1 */
   int cycles_per_round;       /* cycles a request advances per round, >= 1 */
-  int max_streams;            /* large requests advancing concurrently, 1..16 */
+  int max_streams;            /* requests on streams of their own advancing concurrently, 1..16 */
   size_t batch_max_vertices;  /* finest-level vertex count up to which a request is batched */
 } adafac_server_cfg;
 
@@ -383,13 +399,14 @@ typedef struct {
 } adafac_result;
 
 /* Defaults: max_active 256, max_queued 4096, cycles_per_round 4, max_streams 4,
- * batch_max_vertices 16384. */
+ * batch_max_vertices SIZE_MAX (every request batched). */
 void adafac_server_default_cfg(adafac_server_cfg* cfg);
 
 /* Create a server over the device workspace [dev_workspace, +bytes) (256-byte
  * aligned), with all work on hip_stream (and max_streams streams of its own for
- * large requests).  cfg may be NULL (defaults).  EINVAL on bad values, ENOMEM
- * when the workspace cannot hold the request table. */
+ * requests above batch_max_vertices).  cfg may be NULL (defaults).  EINVAL on
+ * bad values, ENOMEM when the workspace cannot hold the request table and work
+ * list. */
 int adafac_server_create(const adafac_server_cfg* cfg, void* dev_workspace, size_t bytes, void* hip_stream,
                          adafac_server** out);
 

@@ -171,3 +171,27 @@ def lumped_rhs(f, level):
     b = m * f
     b[~interior_mask(d, level)] = 0.0
     return b
+
+
+def dirichlet_lift(g, eps_cells):
+    """Load of inhomogeneous Dirichlet data (the u = 1 on x_2 = 0 set-ups of Sec. 5).
+
+    With u = u_0 + G, G the data on the boundary vertices and zero inside, the interior
+    equations of A u = b become A u_0 = b - A G: every element couples its boundary corners to
+    its interior ones.  Returns -A G at the interior vertices (zero on the boundary), from the
+    element-wise operator of :func:`apply_matrix_free`."""
+    g = np.asarray(g, dtype=np.float64)
+    d = g.ndim
+    n = g.shape[0] - 1
+    level = int(round(np.log(n) / np.log(3)))
+    G = np.where(interior_mask(d, level), 0.0, g)
+    return -apply_matrix_free(G, eps_cells)
+
+
+def with_boundary(u0, g):
+    """The full vertex lattice of u = u_0 + G: u_0 inside, the Dirichlet data on the boundary."""
+    g = np.asarray(g, dtype=np.float64)
+    d = g.ndim
+    level = int(round(np.log(g.shape[0] - 1) / np.log(3)))
+    m = interior_mask(d, level)
+    return np.where(m, np.asarray(u0).reshape(g.shape), g)

@@ -184,6 +184,7 @@ class Hierarchy:
         # finest operator
         fine = self.lev[L]
         eps_L = fem.cell_eps_from_blocks(eps_blocks, L)
+        self.eps_L = eps_L
         if big:
             fine.A = Op(fn=lambda x, e=eps_L: fem.apply_matrix_free(
                 x.reshape((e.shape[0] + 1,) * e.ndim), e).ravel())
@@ -262,9 +263,14 @@ class Hierarchy:
         keep = np.all(np.abs(fc - 3 * cr) <= 2, axis=0)
         return sp.csr_matrix((self.omega * M.data[keep], (M.row[keep], M.col[keep])), shape=M.shape)
 
-    def rhs(self, f):
-        """b_L from the vertex samples f of the right-hand side (lumped mass)."""
-        return fem.lumped_rhs(f, self.L).ravel()
+    def rhs(self, f, g=None):
+        """b_L from the vertex samples f of the right-hand side (lumped mass); with Dirichlet
+        data g (on the finest vertex lattice, boundary entries used) the load of its lift is
+        added, and the iterate is then u_0 = u - G (zero on the boundary)."""
+        b = fem.lumped_rhs(f, self.L).ravel()
+        if g is not None:
+            b = b + fem.dirichlet_lift(g, self.eps_L).ravel()
+        return b
 
     def astype(self, dtype):
         """A copy whose operators compute in ``dtype`` (FP32 inner cycles)."""

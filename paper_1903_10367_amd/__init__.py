@@ -55,11 +55,13 @@ class Solver:
 
     def __init__(self, dim, lmin, lmax, f, eps_blocks=None, transfer="dlinear", damping="jac",
                  precision="fp64", inner_k=4, fused=True, omega=0.6, omega_tilde=0.6, omega_hat=0.5,
-                 device=None, stream=None, refine=None, ball=None, rtilde="const", static_workspace=False):
+                 device=None, stream=None, refine=None, ball=None, rtilde="const", static_workspace=False,
+                 dirichlet=None):
         """``refine``: {level: flags over the (3^level)^dim cells} of an adaptive tree;
         ``ball``: (centre, radius, l_from) refinement around a ball (adaptive tree);
         ``static_workspace``: bind to the library's own device array (adafac_bind_static)
-        instead of a torch-allocated workspace."""
+        instead of a torch-allocated workspace; ``dirichlet``: values of u on the boundary, given
+        on the finest vertex lattice (interior entries ignored)."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("adafac needs a ROCm GPU (gfx950); none is visible")
@@ -85,6 +87,9 @@ class Solver:
         else:
             fa = np.ascontiguousarray(f, dtype=np.float64).ravel()
             _check(self.L, ctx, self.L.adafac_set_rhs_lattice(ctx, _dptr(fa), fa.size))
+        if dirichlet is not None:
+            g = np.ascontiguousarray(dirichlet, dtype=np.float64).ravel()
+            _check(self.L, ctx, self.L.adafac_set_dirichlet_lattice(ctx, _dptr(g), g.size))
         for level, flags in (refine or {}).items():
             fl = np.ascontiguousarray(flags, dtype=np.uint8).ravel()
             _check(self.L, ctx, self.L.adafac_set_refinement(ctx, level, fl.ctypes.data_as(C.POINTER(C.c_uint8)),
@@ -215,11 +220,13 @@ class Server:
 
     The pool for the request hierarchies is a torch uint8 tensor of ``budget_bytes`` on
     ``device``; all work runs on torch's current stream there (plus the server's own streams
-    for large requests).
+    for requests above ``batch_max_vertices``, when set).
     """
 
     def __init__(self, budget_bytes, max_active=256, max_queued=4096, cycles_per_round=4, max_streams=4,
-                 batch_max_vertices=16384, device=None, stream=None):
+                 batch_max_vertices=None, device=None, stream=None):
+        """``batch_max_vertices``: finest-level vertex count above which a request runs on a
+        stream of its own (None: every request joins the batched launch)."""
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("adafac needs a ROCm GPU (gfx950); none is visible")
@@ -227,7 +234,9 @@ class Server:
         cfg = _abi.ServerCfg()
         self.L.adafac_server_default_cfg(C.byref(cfg))
         cfg.max_active, cfg.max_queued, cfg.cycles_per_round = max_active, max_queued, cycles_per_round
-        cfg.max_streams, cfg.batch_max_vertices = max_streams, batch_max_vertices
+        cfg.max_streams = max_streams
+        if batch_max_vertices is not None:
+            cfg.batch_max_vertices = batch_max_vertices
         self.device = torch.device(device or "cuda:0")
         self.workspace = torch.empty(int(budget_bytes), dtype=torch.uint8, device=self.device)
         self.stream = stream or torch.cuda.current_stream(self.device)

@@ -25,7 +25,7 @@ EXPORTS = [
     "adafac_server_default_cfg", "adafac_server_create", "adafac_server_submit", "adafac_server_step",
     "adafac_server_poll", "adafac_server_fetch", "adafac_server_destroy", "adafac_server_last_error",
     "adafac_stream_copy", "adafac_set_rhs_fn", "adafac_residual_normalised", "adafac_dof_coords",
-    "adafac_get_composite", "adafac_set_composite", "adafac_bind_static",
+    "adafac_get_composite", "adafac_set_composite", "adafac_bind_static", "adafac_set_dirichlet_lattice",
 ]
 
 
@@ -84,6 +84,7 @@ def lib():
         "adafac_workspace_bytes": (C.c_int, [P, C.POINTER(C.c_size_t)]),
         "adafac_bind": (C.c_int, [P, P, C.c_size_t, P]),
         "adafac_bind_static": (C.c_int, [P, P]),
+        "adafac_set_dirichlet_lattice": (C.c_int, [P, C.POINTER(C.c_double), C.c_size_t]),
         "adafac_cycle": (C.c_int, [P, C.c_int]),
         "adafac_solve": (C.c_int, [P, C.c_double, C.c_int, C.POINTER(C.c_int)]),
         "adafac_residual": (C.c_int, [P, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]),

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libadafac.so")
 SOURCES = ["setup.cpp", "adaptive.cpp", "api.cpp", "server.cpp", "kernels_adaptive.hip", "kernels_generic.hip",
-           "kernels_fused.hip", "kernels_batch.hip", "static_ws.hip"]
+           "kernels_fused.hip", "kernels_serve.hip", "static_ws.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]

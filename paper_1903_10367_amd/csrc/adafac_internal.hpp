@@ -133,8 +133,7 @@ struct BatchState {
   int cur;                   // FP64 form: index of ufine holding the current iterate
   int pad;
   double r0, l2h, linf;      // norms of iterate 0 and of the last measured iterate
-  unsigned long long done;   // work items of the request completed (all launches)
-  unsigned long long stop_need;   // items from this sequence number on do no work (stopped)
+  unsigned long long stop_need;   // the request's items from this sequence number on do no work (stopped)
 };
 
 // Phase kinds of a serving step (one request's chain: FINE, FINAL, LEVEL l = L-1..lmin,
@@ -142,18 +141,18 @@ struct BatchState {
 // PROLONGs in FP32 for FP32_REFINED).
 enum { SERVE_FINE = 0, SERVE_FINAL, SERVE_LEVEL, SERVE_PROLONG, SERVE_ADDE, SERVE_DEFECT };
 
-// One segment of a serving launch's work list: the ntile items of one phase of one request.
+// One segment of a phase-slot launch's work list: the ntile items of one phase of one request.
 struct ServeSeg {
   int req;                   // row of the request table
   int kind, level, sub;      // SERVE_*, the level it works on, inner cycle index (FP32 phases)
   int ntile, tile;           // items, vertices per item
   int need_off;              // items of the request in its earlier phases of the step
   int per_step;              // items of the request per step
-  int item0;                 // first item of the segment within the step
+  int item0;                 // first item of the segment within its launch
   int nparts;                // FINAL: norm partials to sum (items of the measured phase)
   int run_after;             // FINAL: items of the request after it that still run when it stops
-  int cur0;                  // FP64: iterate index at the launch start
-  unsigned long long base;   // items of the request completed before the launch
+  int cur0;                  // FP64: iterate index at the round's start
+  unsigned long long base;   // items of the request in earlier rounds (its sequence numbers start there)
 };
 
 // Internal hooks of the C ABI used by the request server (api.cpp).

@@ -91,6 +91,7 @@ struct adafac_ctx {
   int nb = 1;
   std::vector<double> eps{1.0};
   std::vector<double> f;
+  std::vector<double> gdir;     // Dirichlet data on the finest lattice (boundary entries; empty: u = 0 there)
   adafac_opts opts{};
   HostOps ops;
   bool built = false, bound = false;
@@ -1076,6 +1077,8 @@ int adafac_build_operators(adafac_ctx* c, const adafac_opts* opts) {
   for (int b = 1; b < c->nb; b *= 3) c->ops.k++;
   c->ops.eps = c->eps;
   c->adaptive = !c->refine.empty() || c->ball_r > 0.0;
+  if (c->adaptive && !c->gdir.empty())
+    return fail(c, ADAFAC_EUNSUPPORTED, "Dirichlet data: uniform trees only");
   if (c->adaptive) {
     int rc = build_adaptive(c);
     if (rc) return rc;
@@ -1151,6 +1154,14 @@ int bind_workspace(adafac_ctx* c, void* ws, size_t bytes, void* stream, bool cle
       }
   });
   HIPCHK(c, hipMemcpyAsync(c->h64.bfine, b.data(), sizeof(double) * b.size(), hipMemcpyHostToDevice, c->stream));
+  if (!c->gdir.empty()) {
+    // Dirichlet data: the boundary entries of both FP64 iterate buffers (no kernel writes them;
+    // every residual reads them)
+    HIPCHK(c, hipMemcpyAsync(c->h64.ufine[0], c->gdir.data(), sizeof(double) * c->gdir.size(), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->h64.ufine[1], c->gdir.data(), sizeof(double) * c->gdir.size(), hipMemcpyHostToDevice,
+                             c->stream));
+  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->h64.cur = c->h32.cur = 0;
   c->h64.pending = c->h32.pending = c->e_pending = false;
@@ -1262,7 +1273,7 @@ int adafac_set_solution(adafac_ctx* c, const double* u, size_t n) {
     for (int a = 0; a < c->dim; ++a) {
       int x = int(t % nv);
       t /= nv;
-      if (x == 0 || x == nv - 1) v[i] = 0.0;
+      if (x == 0 || x == nv - 1) v[i] = c->gdir.empty() ? 0.0 : c->gdir[i];
     }
     if (!std::isfinite(v[i])) return fail(c, ADAFAC_EINVAL, "u: non-finite value");
   }
@@ -1591,6 +1602,32 @@ int adafac_set_rhs_fn(adafac_ctx* c, double (*f)(const double* x, void* user), v
   c->src_gauss = 0;
   c->f.clear();
   c->bound = false;
+  return ADAFAC_OK;
+}
+
+int adafac_set_dirichlet_lattice(adafac_ctx* c, const double* g, size_t n) {
+  if (!c) return ADAFAC_EINVAL;
+  if (c->adaptive || !c->refine.empty() || c->ball_r > 0.0)
+    return fail(c, ADAFAC_EUNSUPPORTED, "Dirichlet data: uniform trees only");
+  if (!g || n != nverts_of(c->dim, c->L)) return fail(c, ADAFAC_EINVAL, "g: wrong size");
+  const int nv = ipow3(c->L) + 1;
+  std::vector<double> gd(n, 0.0);
+  bool any = false;
+  for (size_t i = 0; i < n; ++i) {
+    size_t t = i;
+    bool bd = false;
+    for (int a = 0; a < c->dim; ++a) {
+      const int x = int(t % nv);
+      t /= nv;
+      bd = bd || x == 0 || x == nv - 1;
+    }
+    if (!bd) continue;
+    if (!std::isfinite(g[i])) return fail(c, ADAFAC_EINVAL, "g: non-finite boundary value");
+    gd[i] = g[i];
+    any = any || g[i] != 0.0;
+  }
+  if (any) c->gdir.swap(gd);
+  else c->gdir.clear();
   return ADAFAC_OK;
 }
 

@@ -22,8 +22,8 @@
 #include "adafac_internal.hpp"
 
 namespace adafac {
-hipError_t launch_batch_serve(const BatchReq* reqs, BatchState* states, const int* work, int nwork, int* next,
-                              int budget, int max_groups, hipStream_t s);
+hipError_t launch_serve_phase(const BatchReq* reqs, BatchState* states, const ServeSeg* segs, int nseg, int nitems,
+                              int j, hipStream_t s);
 }  // namespace adafac
 
 using namespace adafac;
@@ -31,7 +31,10 @@ using namespace adafac;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kMaxGroups = 1024;   // workgroups of one batched launch (they share the work list)
+constexpr int kSegsPerSlot = 48;   // work-list segments held per request slot (on average)
+// vertices per work item: finest-level phases (at most kNormBlocks items, one norm partial
+// each), coarse FAS updates (5^d gathers per vertex) and prolongations
+constexpr size_t kFineItem = 2048, kLevelItem = 1024, kProlongItem = 4096;
 constexpr int kPrepThreads = 4;    // host set-ups of queued requests running at once
 constexpr int kPrepAhead = 16;     // queued requests set up ahead of admission (host memory bound)
 
@@ -99,6 +102,7 @@ struct Req {
   bool prep_started = false;
   bool prepared = false;  // prep finished; its status is prep_rc
   int prep_rc = 0;
+  unsigned long long items_base = 0;   // batched: work items of the request in earlier rounds
 };
 
 size_t finest_vertices(int d, int L) {
@@ -115,8 +119,8 @@ struct adafac_server {
   hipStream_t stream = nullptr;
   BatchReq* d_reqs = nullptr;
   BatchState* d_states = nullptr;
-  int* d_work = nullptr;
-  int* d_next = nullptr;
+  ServeSeg* d_segs = nullptr;
+  int seg_cap = 0;
   char* pool_base = nullptr;
   Pool pool;
   std::vector<hipStream_t> lanes;
@@ -129,7 +133,7 @@ struct adafac_server {
   std::vector<int> free_slots;
   std::vector<BatchReq> h_desc;        // host copies of the table rows (kept for async copies)
   std::vector<BatchState> h_states;
-  std::vector<int> h_work;
+  std::vector<ServeSeg> h_segs;
   std::deque<uint64_t> queue;
   std::unordered_map<uint64_t, Req> reqs;
   std::vector<uint64_t> active;
@@ -259,23 +263,106 @@ int harvest_batched(adafac_server* s, bool wait, bool* done) {
   return ADAFAC_OK;
 }
 
-int launch_batched(adafac_server* s) {
-  if (s->b_flight) return ADAFAC_OK;
-  s->h_work.clear();
-  s->b_members.clear();
-  for (uint64_t t : s->active) {
-    Req& r = s->reqs[t];
-    if (r.res.batched) {
-      s->h_work.push_back(r.slot);
-      s->b_members.push_back(t);
+// The phases of one step of a request, in order (see ServeSeg).
+void step_program(const BatchReq& d, std::vector<ServeSeg>& prog) {
+  prog.clear();
+  auto nv_of = [&](int l) {
+    const size_t n = size_t(ipow3(l) + 1);
+    return d.dim == 2 ? n * n : n * n * n;
+  };
+  auto add = [&](int kind, int level, int sub, size_t nverts, size_t tile) {
+    ServeSeg g{};
+    g.kind = kind;
+    g.level = level;
+    g.sub = sub;
+    g.tile = int(tile);
+    g.ntile = int((nverts + tile - 1) / tile);
+    prog.push_back(g);
+  };
+  const size_t nvL = nv_of(d.L);
+  size_t tf = std::max(kFineItem, (nvL + size_t(kNormBlocks) - 1) / size_t(kNormBlocks));
+  tf = (tf + 255) / 256 * 256;
+  const int nf = int((nvL + tf - 1) / tf);
+  auto cycle_phases = [&](int sub) {
+    add(SERVE_FINE, d.L, sub, nvL, tf);
+    if (sub < 0) add(SERVE_FINAL, d.L, 0, 1, 1);
+    for (int l = d.L - 1; l >= d.lmin; --l) add(SERVE_LEVEL, l, sub < 0 ? 0 : sub, nv_of(l), kLevelItem);
+    for (int l = d.lmin + 1; l <= d.L; ++l) add(SERVE_PROLONG, l, sub < 0 ? 0 : sub, nv_of(l), kProlongItem);
+  };
+  if (d.precision == ADAFAC_PREC_FP64) {
+    cycle_phases(-1);
+    prog[0].sub = 0;
+  } else {
+    add(SERVE_ADDE, d.L, 0, nvL, tf);
+    add(SERVE_DEFECT, d.L, 0, nvL, tf);
+    add(SERVE_FINAL, d.L, 0, 1, 1);
+    for (int i = 0; i < d.inner_k; ++i) cycle_phases(i);
+  }
+  int off = 0;
+  for (ServeSeg& g : prog) {
+    g.need_off = off;
+    off += g.ntile;
+  }
+  for (size_t p = 0; p < prog.size(); ++p) {
+    ServeSeg& g = prog[p];
+    g.per_step = off;
+    if (g.kind == SERVE_FINAL) {
+      g.nparts = nf;
+      // FP64: the rest of the cycle still runs when it stops (it produces the result)
+      g.run_after = d.precision == ADAFAC_PREC_FP64 ? off - (g.need_off + 1) : 0;
     }
   }
-  if (s->h_work.empty()) return ADAFAC_OK;
-  SHIP(s, hipMemcpyAsync(s->d_work, s->h_work.data(), sizeof(int) * s->h_work.size(), hipMemcpyHostToDevice,
+}
+
+// One round advances every batched request by cycles_per_round steps.  Launch (j, p) runs the
+// p-th phase of step j of every request whose chain has one, so the launch count per round is
+// cycles_per_round x the longest chain, independent of the number of requests.
+int launch_batched(adafac_server* s) {
+  if (s->b_flight) return ADAFAC_OK;
+  s->b_members.clear();
+  std::vector<std::vector<ServeSeg>> progs;
+  std::vector<ServeSeg> prog;
+  size_t nseg = 0, maxp = 0;
+  const int steps = s->cfg.cycles_per_round;
+  for (uint64_t t : s->active) {
+    Req& r = s->reqs[t];
+    if (!r.res.batched) continue;
+    step_program(s->h_desc[r.slot], prog);
+    if (nseg + prog.size() > size_t(s->seg_cap)) break;   // the rest joins a later round
+    const BatchState& st = s->h_states[r.slot];
+    for (ServeSeg& g : prog) {
+      g.req = r.slot;
+      g.cur0 = st.cur;
+      g.base = r.items_base;
+    }
+    r.items_base += (unsigned long long)steps * (unsigned long long)prog[0].per_step;
+    nseg += prog.size();
+    maxp = std::max(maxp, prog.size());
+    progs.push_back(prog);
+    s->b_members.push_back(t);
+  }
+  if (s->b_members.empty()) return ADAFAC_OK;
+  s->h_segs.clear();
+  std::vector<int> slot_off(maxp + 1, 0), slot_items(maxp, 0);
+  for (size_t p = 0; p < maxp; ++p) {
+    slot_off[p] = int(s->h_segs.size());
+    int item = 0;
+    for (auto& pg : progs) {
+      if (p >= pg.size()) continue;
+      ServeSeg g = pg[p];
+      g.item0 = item;
+      item += g.ntile;
+      s->h_segs.push_back(g);
+    }
+    slot_items[p] = item;
+  }
+  slot_off[maxp] = int(s->h_segs.size());
+  SHIP(s, hipMemcpyAsync(s->d_segs, s->h_segs.data(), sizeof(ServeSeg) * s->h_segs.size(), hipMemcpyHostToDevice,
                          s->stream));
-  SHIP(s, hipMemsetAsync(s->d_next, 0, sizeof(int), s->stream));
-  SHIP(s, launch_batch_serve(s->d_reqs, s->d_states, s->d_work, int(s->h_work.size()), s->d_next,
-                             s->cfg.cycles_per_round, kMaxGroups, s->stream));
+  for (int j = 0; j < steps; ++j)
+    for (size_t p = 0; p < maxp; ++p)
+      SHIP(s, launch_serve_phase(s->d_reqs, s->d_states, s->d_segs + slot_off[p], slot_off[p + 1] - slot_off[p],
+                                 slot_items[p], j, s->stream));
   s->b_flight = true;
   return ADAFAC_OK;
 }
@@ -413,6 +500,7 @@ int admit(adafac_server* s) {
       d.tol = r.tol;
       d.max_cycles = r.max_cycles;
       s->h_states[r.slot] = BatchState{};
+      s->h_states[r.slot].stop_need = ~0ull;
       SHIP(s, hipMemcpyAsync(&s->d_reqs[r.slot], &d, sizeof(BatchReq), hipMemcpyHostToDevice, s->setup));
       SHIP(s, hipMemcpyAsync(&s->d_states[r.slot], &s->h_states[r.slot], sizeof(BatchState), hipMemcpyHostToDevice,
                              s->setup));
@@ -442,7 +530,7 @@ void adafac_server_default_cfg(adafac_server_cfg* c) {
   c->max_queued = 4096;
   c->cycles_per_round = 4;
   c->max_streams = 4;
-  c->batch_max_vertices = 16384;   // larger hierarchies run faster as multi-workgroup kernels on a lane
+  c->batch_max_vertices = SIZE_MAX;   // every request joins the batched launch
 }
 
 int adafac_server_create(const adafac_server_cfg* cfg, void* ws, size_t bytes, void* stream, adafac_server** out) {
@@ -456,7 +544,7 @@ int adafac_server_create(const adafac_server_cfg* cfg, void* ws, size_t bytes, v
     return ADAFAC_EINVAL;
   if (!ws || reinterpret_cast<uintptr_t>(ws) % kAlign) return ADAFAC_EINVAL;
   const size_t head = align_up(sizeof(BatchReq) * c.max_active) + align_up(sizeof(BatchState) * c.max_active) +
-                      align_up(sizeof(int) * c.max_active) + kAlign;
+                      align_up(sizeof(ServeSeg) * size_t(kSegsPerSlot) * c.max_active);
   if (bytes < head) return ADAFAC_ENOMEM;
   adafac_server* s = new (std::nothrow) adafac_server();
   if (!s) return ADAFAC_ENOMEM;
@@ -469,10 +557,9 @@ int adafac_server_create(const adafac_server_cfg* cfg, void* ws, size_t bytes, v
   p += align_up(sizeof(BatchReq) * c.max_active);
   s->d_states = reinterpret_cast<BatchState*>(p);
   p += align_up(sizeof(BatchState) * c.max_active);
-  s->d_work = reinterpret_cast<int*>(p);
-  p += align_up(sizeof(int) * c.max_active);
-  s->d_next = reinterpret_cast<int*>(p);
-  p += kAlign;
+  s->d_segs = reinterpret_cast<ServeSeg*>(p);
+  s->seg_cap = kSegsPerSlot * c.max_active;
+  p += align_up(sizeof(ServeSeg) * size_t(s->seg_cap));
   s->pool_base = p;
   s->pool.reset((bytes - head) & ~(kAlign - 1));
   s->h_desc.resize(c.max_active);
@@ -546,7 +633,19 @@ int adafac_server_step(adafac_server* s, int* active, int* queued) {
     }
     bool busy = s->b_flight;
     for (int k = 0; k < int(s->lanes.size()); ++k) busy |= s->lane_flight[k] != 0;
-    if (progress || !busy) break;
+    if (progress) break;
+    if (!busy) {
+      // nothing on the device: wait (a little) only for a queued request's host set-up
+      bool preparing = false;
+      for (uint64_t t : s->queue) {
+        Req& r = s->reqs[t];
+        if (r.prep_started && !r.prepared) {
+          preparing = r.prep.wait_for(std::chrono::seconds(0)) != std::future_status::ready;
+          break;   // admission is in arrival order: the first started set-up decides
+        }
+      }
+      if (!preparing) break;
+    }
     std::this_thread::sleep_for(std::chrono::microseconds(25));
   }
   const double t_b = now(s);

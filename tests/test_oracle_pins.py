@@ -480,3 +480,55 @@ def test_plain_additive_degrades_with_depth_while_adafac_does_not():
         rates[("jac", L)] = dense.spectral_radius(dense.iteration_matrix(H, damping="jac"))
     assert rates[("none", 3)] > rates[("none", 2)]
     assert rates[("jac", 3)] < 1 and rates[("jac", 2)] < 1
+
+
+# --- inhomogeneous Dirichlet data (the set-ups of Sec. 5) -------------------------------------
+
+def _lattice(d, L):
+    """Coordinates of the (3^L + 1)^d vertices, coordinate a on array axis d - 1 - a."""
+    n = 3 ** L
+    idx = np.indices((n + 1,) * d).astype(float) / n
+    return [idx[d - 1 - a] for a in range(d)]
+
+
+@pytest.mark.parametrize("d,L", [(2, 3), (3, 2)])
+def test_dirichlet_lift_reproduces_harmonic_multilinear_functions(d, L):
+    # a harmonic function in the d-linear space (x y + 2 x - y + 0.5; x y z + x - z in 3D) with
+    # f = 0 is its own discrete solution: the lift and a direct solve must give it back exactly
+    X = _lattice(d, L)
+    ue = X[0] * X[1] + 2 * X[0] - X[1] + 0.5 if d == 2 else X[0] * X[1] * X[2] + X[0] - X[2]
+    H = hierarchy.Hierarchy(d, L, 1)
+    b = H.rhs(np.zeros_like(ue), g=ue)
+    u0 = dense.direct_solve(H, b)
+    u = fem.with_boundary(u0, ue)
+    assert np.abs(u - ue).max() < 1e-13
+
+
+def test_dirichlet_lift_on_the_split_field_reproduces_a_flux_free_profile():
+    # eps depending on x_1 only (the split set-up with a 10^5 jump): u = x_2 carries the flux
+    # eps (0, 1), whose divergence vanishes, so u = x_2 is the exact and the discrete solution
+    L = 3
+    eps = inp.paper_eps_cells(L, "split", 5)
+    X = _lattice(2, L)
+    ue = X[1]
+    H = hierarchy.Hierarchy(2, L, 1, eps)
+    u0 = dense.direct_solve(H, H.rhs(np.zeros_like(ue), g=ue))
+    assert np.abs(fem.with_boundary(u0, ue) - ue).max() < 1e-12
+
+
+def test_paper_setup_fixed_point_is_the_lifted_direct_solve():
+    # f = 0, u = 1 on x_2 = 0: adAFAC-Jac converges to the direct solve of the lifted system,
+    # and the solution lies between the boundary values 0 and 1 (discrete maximum principle of
+    # the Q1 Laplacian with nonpositive off-diagonal entries)
+    L = 3
+    g = inp.paper_boundary(2, L)
+    H = hierarchy.Hierarchy(2, L, 1)
+    b = H.rhs(np.zeros_like(g), g=g)
+    us = dense.direct_solve(H, b)
+    u, hist = cycle.solve(H, b, 400, tol=1e-12)
+    assert hist[-1][0] / hist[0][0] <= 1e-12
+    assert np.abs(u - us).max() < 1e-10
+    full = fem.with_boundary(us, g)
+    assert full.min() >= -1e-14 and full.max() <= 1 + 1e-14
+    # symmetric in x_1 about 1/2
+    assert np.abs(full - full[:, ::-1]).max() < 1e-12
