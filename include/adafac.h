@@ -250,9 +250,11 @@ int adafac_set_solution(adafac_ctx* ctx, const double* u, size_t n);
  * the composite FE function at every finest vertex, and adafac_set_solution takes
  * the values at the dofs' positions from such a lattice.  adafac_get_level
  * returns which = 0 (nodal values u_l, hanging ones interpolated), 1 (b_l, the
- * level hats tested against the composite residual) or 4 (S_l) for levels
- * l_min..l_max, on the full level lattice, zero outside the level's cells;
- * under FP32_REFINED only which = 0 (ESTATE otherwise).
+ * level hats tested against the composite residual) or 4 (S_l, levels below
+ * l_max only) for levels l_min..l_max, on the full level lattice, zero outside
+ * the level's cells; under FP32_REFINED only which = 0 (ESTATE otherwise).
+ * Under adAFAC-PI with the single-pass sweeps, S_{l_max-1} of a uniform tree
+ * holds S_{l_max-1} - I c_{l_max} (the coarse part of the deferred correction).
  *
  * Copy a level array of the last cycle to host memory (inspection and
  * per-step parity checks).  which: 0 = u_l (FAS solution, injected),

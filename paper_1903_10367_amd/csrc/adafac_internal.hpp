@@ -61,6 +61,7 @@ struct LevelView {
   int fem;                   // 1: operator from eps blocks, 0: stored stencil
   int nb;                    // eps blocks per axis
   int bs;                    // cells per block along an axis (>= 1) when fem
+  unsigned bsm;              // ceil(2^32 / bs) when bs > 1 (cell / bs = umulhi(cell, bsm)), 0 when bs = 1
   const T* eps;              // nb^d block coefficients (nullptr: eps = 1)
   const T* st;               // stored stencil (3^d per vertex) when !fem
   const T* dg;               // stored diagonal when !fem
@@ -152,6 +153,7 @@ struct ServeSeg {
   int nparts;                // FINAL: norm partials to sum (items of the measured phase)
   int run_after;             // FINAL: items of the request after it that still run when it stops
   int cur0;                  // FP64: iterate index at the round's start
+  int cps;                   // FP64: cycles per step (sub numbers them); 1 otherwise
   unsigned long long base;   // items of the request in earlier rounds (its sequence numbers start there)
 };
 

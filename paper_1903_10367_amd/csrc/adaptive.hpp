@@ -53,6 +53,20 @@ struct AdaptTreeView {
   int lmin, L;
 };
 
+// Where the nodal values of a tree's levels live, for the copies of a level's updated dofs into
+// the coinciding dofs of the coarser levels (every level-l dof is a dof of level l-1 where the
+// position lies on the coarser lattice).
+template <typename T>
+struct AdaptCopyView {
+  struct Lv {
+    int ox, oy, oz, mx, my, mz;
+    const uint8_t* vcls;
+    T* u;
+  };
+  Lv lv[kMaxLevel + 1];
+  int lmin;
+};
+
 // Host description of the tree.
 struct AdaptHostLevel {
   int d = 2;
@@ -102,9 +116,8 @@ std::string build_adapt_tree(AdaptHost& t, int d, int lmin, int L, const std::ve
 // (C) or finer (F) neighbour level where the step needs it.
 template <typename T>
 hipError_t launch_ad_hang(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>& C, hipStream_t s);
-template <typename T>
-hipError_t launch_ad_leaf(int d, const AdaptLevelT<T>& L, hipStream_t s);
-// Levels with a finer level F (F must not be null; the finest level runs launch_ad_leaf_up).
+// Levels with a finer level F (F must not be null; the finest level runs launch_ad_leaf_up): the
+// level's own leaf residual (computed in place) plus the restrictions from F.
 // norms_only: only the composite residual: norm partials, hh, and bb replaced by the composite
 // residual at composite dofs (zero elsewhere)
 // tiled: the 3D tiled kernel (adapt_up_tiled), else the five-wave gathers
@@ -115,13 +128,13 @@ hipError_t launch_ad_up(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>* F,
 template <typename T>
 hipError_t launch_ad_leaf_up(int d, const AdaptLevelT<T>& L, T omega, T omega_t, int norms_only, double* partials,
                              hipStream_t s);
-// The finest level: down and update in one pass (C: the next coarser level)
+// Down and update of level `level` (L; C the next coarser level, null on the coarsest): the
+// prolongated sum S, u += S at the composite dofs, and those values copied into the coinciding
+// dofs of every coarser level (V).  Launched coarsest level first.  keep_s: store S (every level
+// but the finest, whose S feeds no finer level).
 template <typename T>
-hipError_t launch_ad_down_update(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>& C, int pi, hipStream_t s);
-template <typename T>
-hipError_t launch_ad_down(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>* C, int pi, hipStream_t s);
-template <typename T>
-hipError_t launch_ad_update(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>* F, hipStream_t s);
+hipError_t launch_ad_down_update(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>* C, const AdaptCopyView<T>& V,
+                                 int level, int pi, int keep_s, hipStream_t s);
 // once per tree, after the classes, leaf flags and (Galerkin levels) diagonals are uploaded
 template <typename T>
 hipError_t launch_ad_setup(int d, const AdaptLevelT<T>& L, hipStream_t s);

@@ -214,6 +214,7 @@ size_t layout(adafac_ctx* c, char* base) {
       v.fem = hl.fem ? 1 : 0;
       v.nb = c->ops.nb;
       v.bs = hl.fem ? ipow3(l - c->ops.k) : 1;
+      v.bsm = v.bs > 1 ? unsigned(((uint64_t(1) << 32) + uint64_t(v.bs) - 1) / uint64_t(v.bs)) : 0u;
       v.eps = unit ? nullptr : H.eps;
       if (!coarse_arrays && l < c->L) continue;
       const size_t nvx = hl.nverts;
@@ -565,7 +566,6 @@ int run_adapt_cycle(adafac_ctx* c, const std::vector<AdaptLevelT<T>>& ad, const 
   int rc = adapt_hang_views(c, ad);
   if (rc) return rc;
   if ((rc = record_start(c))) return rc;
-  for (int l = lmin; l < L; ++l) HIPCHK(c, launch_ad_leaf<T>(d, ad[l], c->stream));
   double* partials = std::is_same<T, double>::value ? c->partials : c->partials_inner;
   HIPCHK(c, launch_ad_leaf_up<T>(d, ad[L], omega, omega_t, 0, partials + 2 * c->ad_part[L], c->stream));
   if ((rc = record_stop(c))) return rc;
@@ -574,10 +574,14 @@ int run_adapt_cycle(adafac_ctx* c, const std::vector<AdaptLevelT<T>>& ad, const 
                               std::is_same<T, double>::value ? c->ad_tiled[l] : 0, partials + 2 * c->ad_part[l],
                               c->stream));
   HIPCHK(c, launch_ad_norm_finalize(partials, int(c->npartials), norm_out, c->stream));
-  for (int l = lmin; l < L; ++l)
-    HIPCHK(c, launch_ad_down<T>(d, ad[l], l > lmin ? &ad[l - 1] : nullptr, pi, c->stream));
-  HIPCHK(c, launch_ad_down_update<T>(d, ad[L], ad[L - 1], pi, c->stream));
-  for (int l = L - 1; l >= lmin; --l) HIPCHK(c, launch_ad_update<T>(d, ad[l], &ad[l + 1], c->stream));
+  // coarsest level first: S_l needs S_{l-1}; each level's updated composite dofs are copied into
+  // the coinciding coarser dofs
+  AdaptCopyView<T> V{};
+  V.lmin = lmin;
+  for (int l = lmin; l <= L; ++l)
+    V.lv[l] = {ad[l].ox, ad[l].oy, ad[l].oz, ad[l].mx, ad[l].my, ad[l].mz, ad[l].vcls, ad[l].u};
+  for (int l = lmin; l <= L; ++l)
+    HIPCHK(c, launch_ad_down_update<T>(d, ad[l], l > lmin ? &ad[l - 1] : nullptr, V, l, pi, l < L, c->stream));
   return ADAFAC_OK;
 }
 
@@ -592,7 +596,6 @@ int run_adapt_outer_mixed(adafac_ctx* c, double* norm_out) {
   int rc = adapt_accumulate(c);
   if (rc || (rc = adapt_hang(c))) return rc;
   if ((rc = record_start(c))) return rc;
-  for (int l = lmin; l < L; ++l) HIPCHK(c, launch_ad_leaf<double>(d, c->ad[l], c->stream));
   HIPCHK(c, launch_ad_leaf_up<double>(d, c->ad[L], 0.0, 0.0, 1, c->partials + 2 * c->ad_part[L], c->stream));
   if ((rc = record_stop(c))) return rc;
   for (int l = L - 1; l >= lmin; --l)
@@ -1308,6 +1311,8 @@ int adafac_get_level(adafac_ctx* c, int level, int which, double* out, size_t n)
       case 4: src = A.S; break;
       default: return fail(c, ADAFAC_EINVAL, "which: 0 (u), 1 (b), 4 (S) on adaptive trees");
     }
+    if (which == 4 && level == c->L)
+      return fail(c, ADAFAC_EINVAL, "S is not kept on the finest level of a tree (it feeds no finer level)");
     if (mixed(c) && which != 0) return fail(c, ADAFAC_ESTATE, "FP32_REFINED keeps only u in FP64 on a tree");
     if (which == 0) {
       int rc = flush(c);

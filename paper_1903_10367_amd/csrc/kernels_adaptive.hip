@@ -271,13 +271,6 @@ __device__ __forceinline__ T leaf_residual(const AdaptLevelT<T>& A, unsigned i) 
 
 // Vertices of class 0 (no existing cell, or the domain boundary) are never written: their
 // arrays hold the zeros of the workspace set-up, which is what every reader expects there.
-template <int D, typename T>
-__global__ void __launch_bounds__(NTA) k_ad_leaf(AdaptLevelT<T> A) {
-  const unsigned nb = nbox<D>(A);
-  AD_LOOP(i, nb) {
-    if (A.vcls[i] & (kDof | kHang)) A.bb[i] = leaf_residual<D>(A, i);
-  }
-}
 
 // d-linear restriction weight of fine offset o (|o| <= 2)
 template <typename T>
@@ -440,7 +433,7 @@ __global__ void __launch_bounds__(NTU) k_ad_up_f(AdaptLevelT<T> A, AdaptLevelT<T
         Rb += sh[1][w][lane];
         Rt += sh[2][w][lane];
       }
-      up_finish<T, MODE>(A, i, cls, A.bb[i], Rh, Rb, Rt, 1, omega, omega_t, ssum, smax);
+      up_finish<T, MODE>(A, i, cls, leaf_residual<D>(A, i), Rh, Rb, Rt, 1, omega, omega_t, ssum, smax);
     }
     __syncthreads();
   }
@@ -573,7 +566,7 @@ __global__ void __launch_bounds__(NTT) k_ad_up_tiled(AdaptLevelT<T> A, AdaptLeve
           const unsigned i = (unsigned(czb) * unsigned(A.my) + unsigned(cby)) * unsigned(A.mx) + unsigned(cbx);
           const uint8_t cls = A.vcls[i];
           if (cls & (kDof | kHang))
-            up_finish<T, MODE>(A, i, cls, A.bb[i], aH[0], aB[0], aT[0], 1, omega, omega_t, ssum, smax);
+            up_finish<T, MODE>(A, i, cls, leaf_residual<3>(A, i), aH[0], aB[0], aT[0], 1, omega, omega_t, ssum, smax);
         }
         aH[0] = aH[1];
         aB[0] = aB[1];
@@ -585,50 +578,43 @@ __global__ void __launch_bounds__(NTT) k_ad_up_tiled(AdaptLevelT<T> A, AdaptLeve
   block_norm_partials(ssum, smax, partials);
 }
 
-// S_l = (c - c~)_l + P S_{l-1}; adAFAC-PI: S_l = c_l + P (S_{l-1} - I c_l), which is
-// c_l - P I c_l + P S_{l-1} (c~_l = P I c_l, Sec. 3.2).
-template <int D, typename T, bool PI>
-__global__ void __launch_bounds__(NTA) k_ad_down(AdaptLevelT<T> A, AdaptLevelT<T> C, int has_c) {
-  const unsigned nb = nbox<D>(A);
-  AD_LOOP(i, nb) {
-    if (!(A.vcls[i] & (kDof | kHang))) continue;
-    T S = A.s[i];
-    if (has_c) {
-      int x, y, z;
-      coords<D>(A, i, x, y, z);
-      S += prolong_at<D, T, PI>(A, C, i, x, y, z);
-    }
-    A.S[i] = S;
+// The updated value of a composite dof at lattice point (x, y, z) of level l, copied into the dofs
+// of the coarser levels that sit at the same position (their nodal values copy the finer one).
+template <int D, typename T>
+__device__ __forceinline__ void copy_down(const AdaptCopyView<T>& V, int l, int x, int y, int z, T val) {
+  for (int m = l - 1; m >= V.lmin; --m) {
+    if (x % 3 || y % 3 || (D == 3 && z % 3)) return;
+    x /= 3;
+    y /= 3;
+    z /= 3;
+    const typename AdaptCopyView<T>::Lv& C = V.lv[m];
+    const int bx = x - C.ox, by = y - C.oy, bz = z - C.oz;
+    if (bx < 0 || bx >= C.mx || by < 0 || by >= C.my || (D == 3 && (bz < 0 || bz >= C.mz))) return;
+    const long k = (long(D == 3 ? bz : 0) * C.my + by) * C.mx + bx;
+    if (!(C.vcls[k] & kDof)) return;
+    C.u[k] = val;
   }
 }
 
-// The finest level: S_L as in k_ad_down, and at its dofs (all composite) u += S_L.
+// S_l = (c - c~)_l + P S_{l-1}; adAFAC-PI: S_l = c_l + P (S_{l-1} - I c_l), which is
+// c_l - P I c_l + P S_{l-1} (c~_l = P I c_l, Sec. 3.2).  Then u += S_l at the composite dofs,
+// copied into the coinciding coarser dofs.
 template <int D, typename T, bool PI>
-__global__ void __launch_bounds__(NTA) k_ad_down_update(AdaptLevelT<T> A, AdaptLevelT<T> C) {
+__global__ void __launch_bounds__(NTA) k_ad_down_update(AdaptLevelT<T> A, AdaptLevelT<T> C, int has_c,
+                                                        AdaptCopyView<T> V, int level, int keep_s) {
   const unsigned nb = nbox<D>(A);
   AD_LOOP(i, nb) {
     const uint8_t cls = A.vcls[i];
     if (!(cls & (kDof | kHang))) continue;
     int x, y, z;
     coords<D>(A, i, x, y, z);
-    const T S = A.s[i] + prolong_at<D, T, PI>(A, C, i, x, y, z);
-    A.S[i] = S;
-    if (cls & kComp) A.u[i] += S;
-  }
-}
-
-template <int D, typename T>
-__global__ void __launch_bounds__(NTA) k_ad_update(AdaptLevelT<T> A, AdaptLevelT<T> F, int has_f) {
-  const unsigned nb = nbox<D>(A);
-  AD_LOOP(i, nb) {
-    const uint8_t cls = A.vcls[i];
+    T S = A.s[i];
+    if (has_c) S += prolong_at<D, T, PI>(A, C, i, x, y, z);
+    if (keep_s) A.S[i] = S;   // the finest level's S feeds no finer level
     if (cls & kComp) {
-      A.u[i] += A.S[i];
-    } else if ((cls & kDof) && has_f) {
-      int x, y, z;
-      coords<D>(A, i, x, y, z);
-      const long k = vidx<D>(F, 3 * x, 3 * y, 3 * z);
-      if (k >= 0) A.u[i] = F.u[k];
+      const T nu = A.u[i] + S;
+      A.u[i] = nu;
+      copy_down<D>(V, level, x, y, z, nu);
     }
   }
 }
@@ -806,13 +792,6 @@ hipError_t launch_ad_hang(int d, const AdaptLevelT<T>& A, const AdaptLevelT<T>& 
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_ad_leaf(int d, const AdaptLevelT<T>& A, hipStream_t s) {
-  const long nb = long(A.mx) * A.my * (d == 3 ? A.mz : 1);
-  if (d == 2) k_ad_leaf<2, T><<<grid_for(nb), NTA, 0, s>>>(A);
-  else k_ad_leaf<3, T><<<grid_for(nb), NTA, 0, s>>>(A);
-  return hipGetLastError();
-}
 
 template <typename T>
 hipError_t launch_ad_up(int d, const AdaptLevelT<T>& A, const AdaptLevelT<T>* F, const RtSep<T>& rts, T omega,
@@ -865,14 +844,18 @@ hipError_t launch_ad_leaf_up(int d, const AdaptLevelT<T>& A, T omega, T omega_t,
 }
 
 template <typename T>
-hipError_t launch_ad_down_update(int d, const AdaptLevelT<T>& A, const AdaptLevelT<T>& C, int pi, hipStream_t s) {
+hipError_t launch_ad_down_update(int d, const AdaptLevelT<T>& A, const AdaptLevelT<T>* C, const AdaptCopyView<T>& V,
+                                 int level, int pi, int keep_s, hipStream_t s) {
   const long nb = long(A.mx) * A.my * (d == 3 ? A.mz : 1);
+  const AdaptLevelT<T> Cv = C ? *C : AdaptLevelT<T>{};
+  const int hc = C ? 1 : 0;
+  const int keep = keep_s ? 1 : 0;
   if (d == 2) {
-    if (pi) k_ad_down_update<2, T, true><<<grid_for(nb), NTA, 0, s>>>(A, C);
-    else k_ad_down_update<2, T, false><<<grid_for(nb), NTA, 0, s>>>(A, C);
+    if (pi) k_ad_down_update<2, T, true><<<grid_for(nb), NTA, 0, s>>>(A, Cv, hc, V, level, keep);
+    else k_ad_down_update<2, T, false><<<grid_for(nb), NTA, 0, s>>>(A, Cv, hc, V, level, keep);
   } else {
-    if (pi) k_ad_down_update<3, T, true><<<grid_for(nb), NTA, 0, s>>>(A, C);
-    else k_ad_down_update<3, T, false><<<grid_for(nb), NTA, 0, s>>>(A, C);
+    if (pi) k_ad_down_update<3, T, true><<<grid_for(nb), NTA, 0, s>>>(A, Cv, hc, V, level, keep);
+    else k_ad_down_update<3, T, false><<<grid_for(nb), NTA, 0, s>>>(A, Cv, hc, V, level, keep);
   }
   return hipGetLastError();
 }
@@ -882,29 +865,6 @@ hipError_t launch_ad_setup(int d, const AdaptLevelT<T>& A, hipStream_t s) {
   const long nb = long(A.mx) * A.my * (d == 3 ? A.mz : 1);
   if (d == 2) k_ad_setup<2, T><<<grid_for(nb), NTA, 0, s>>>(A);
   else k_ad_setup<3, T><<<grid_for(nb), NTA, 0, s>>>(A);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_ad_down(int d, const AdaptLevelT<T>& A, const AdaptLevelT<T>* C, int pi, hipStream_t s) {
-  const long nb = long(A.mx) * A.my * (d == 3 ? A.mz : 1);
-  const AdaptLevelT<T> Cv = C ? *C : AdaptLevelT<T>{};
-  if (d == 2) {
-    if (pi) k_ad_down<2, T, true><<<grid_for(nb), NTA, 0, s>>>(A, Cv, C ? 1 : 0);
-    else k_ad_down<2, T, false><<<grid_for(nb), NTA, 0, s>>>(A, Cv, C ? 1 : 0);
-  } else {
-    if (pi) k_ad_down<3, T, true><<<grid_for(nb), NTA, 0, s>>>(A, Cv, C ? 1 : 0);
-    else k_ad_down<3, T, false><<<grid_for(nb), NTA, 0, s>>>(A, Cv, C ? 1 : 0);
-  }
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_ad_update(int d, const AdaptLevelT<T>& A, const AdaptLevelT<T>* F, hipStream_t s) {
-  const long nb = long(A.mx) * A.my * (d == 3 ? A.mz : 1);
-  const AdaptLevelT<T> Fv = F ? *F : AdaptLevelT<T>{};
-  if (d == 2) k_ad_update<2, T><<<grid_for(nb), NTA, 0, s>>>(A, Fv, F ? 1 : 0);
-  else k_ad_update<3, T><<<grid_for(nb), NTA, 0, s>>>(A, Fv, F ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -938,14 +898,12 @@ hipError_t launch_ad_accumulate(int d, const AdaptLevel& A, const AdaptLevelT<fl
 
 #define ADAFAC_AD_INST(T)                                                                                         \
   template hipError_t launch_ad_hang<T>(int, const AdaptLevelT<T>&, const AdaptLevelT<T>&, hipStream_t);          \
-  template hipError_t launch_ad_leaf<T>(int, const AdaptLevelT<T>&, hipStream_t);                                 \
   template hipError_t launch_ad_up<T>(int, const AdaptLevelT<T>&, const AdaptLevelT<T>*, const RtSep<T>&, T, T,  \
                                       int, int, int, double*, hipStream_t);                                       \
-  template hipError_t launch_ad_down<T>(int, const AdaptLevelT<T>&, const AdaptLevelT<T>*, int, hipStream_t);     \
-  template hipError_t launch_ad_update<T>(int, const AdaptLevelT<T>&, const AdaptLevelT<T>*, hipStream_t);      \
   template hipError_t launch_ad_setup<T>(int, const AdaptLevelT<T>&, hipStream_t);                              \
   template hipError_t launch_ad_leaf_up<T>(int, const AdaptLevelT<T>&, T, T, int, double*, hipStream_t);          \
-  template hipError_t launch_ad_down_update<T>(int, const AdaptLevelT<T>&, const AdaptLevelT<T>&, int, hipStream_t);
+  template hipError_t launch_ad_down_update<T>(int, const AdaptLevelT<T>&, const AdaptLevelT<T>*,                 \
+                                               const AdaptCopyView<T>&, int, int, int, hipStream_t);
 ADAFAC_AD_INST(double)
 ADAFAC_AD_INST(float)
 

@@ -24,12 +24,19 @@ __device__ __forceinline__ int rt_index(int ox, int oy, int oz) {
   return D == 2 ? (ox + 2) + 5 * (oy + 2) : (ox + 2) + 5 * (oy + 2) + 25 * (oz + 2);
 }
 
+// cell / bs for a block size bs = 3^m: a multiply-high by ceil(2^32 / bs), exact for cell
+// indices below 2^16 (the error term cell * (bsm bs - 2^32) stays below 2^32 / bs)
+template <typename T>
+__device__ __forceinline__ int block_of(const LevelView<T>& L, int c) {
+  return L.bsm ? int(__umulhi(unsigned(c), L.bsm)) : c;
+}
+
 template <typename T, int D>
 __device__ __forceinline__ T eps_cell(const LevelView<T>& L, int cx, int cy, int cz) {
   if (!L.eps) return T(1);
-  int bx = cx / L.bs, by = cy / L.bs;
+  const int bx = block_of(L, cx), by = block_of(L, cy);
   if (D == 2) return L.eps[by * L.nb + bx];
-  int bz = cz / L.bs;
+  const int bz = block_of(L, cz);
   return L.eps[(bz * L.nb + by) * L.nb + bx];
 }
 

@@ -28,16 +28,34 @@ namespace {
 constexpr int NTS = 256;   // lanes per workgroup
 
 template <int D>
-__device__ __forceinline__ void xyz_of(size_t i, int nv, int& x, int& y, int& z) {
-  const size_t q = i / size_t(nv);
-  x = int(i - q * size_t(nv));
-  y = D == 3 ? int(q % size_t(nv)) : int(q);
-  z = D == 3 ? int(q / size_t(nv)) : 0;
+__device__ __forceinline__ size_t nverts_of(int nv) {
+  return D == 2 ? size_t(nv) * nv : size_t(nv) * nv * nv;
+}
+
+// Rows of a level's vertex lattice: row q holds the nv vertices (x, y, z) with y + nv z = q (2D:
+// y = q).  Row-based items give every lane a fixed x and no per-vertex index division.
+template <int D>
+__device__ __forceinline__ size_t nrows_of(int nv) {
+  return D == 2 ? size_t(nv) : size_t(nv) * nv;
+}
+
+// Lanes per lattice row: the smallest power of two covering the row's nv - 2 interior vertices
+// (at most NTS); NTS / tpr rows are worked on at once, so small levels keep every lane busy.
+__device__ __forceinline__ int row_lanes(int nv) {
+  int t = 1;
+  while (t < nv - 2 && t < NTS) t <<= 1;
+  return t;
 }
 
 template <int D>
-__device__ __forceinline__ size_t nverts_of(int nv) {
-  return D == 2 ? size_t(nv) * nv : size_t(nv) * nv * nv;
+__device__ __forceinline__ void row_yz(unsigned q, int nv, int& y, int& z) {
+  if (D == 2) {
+    y = int(q);
+    z = 0;
+  } else {
+    z = int(q / unsigned(nv));
+    y = int(q - unsigned(z) * unsigned(nv));
+  }
 }
 
 // (sum, max) over the workgroup into out[0], out[1] (thread 0), fixed order.
@@ -64,10 +82,10 @@ __device__ void wg_partials(double s, double m, double* out, double* ws, double*
   }
 }
 
-// Residual r = b - A u of iterate uin on vertices [v0, v1) of the finest level, its Jacobi step
-// into uout, the injected correction (adAFAC-PI), norm partials.
+// Residual r = b - A u of iterate uin on rows [q0, q1) of the finest level, its Jacobi step into
+// uout, the injected correction (adAFAC-PI), norm partials.
 template <typename T, int D>
-__device__ void fine_items(const BatchReq& R, const BatchHier<T>& H, const T* uin, T* uout, size_t v0, size_t v1,
+__device__ void fine_items(const BatchReq& R, const BatchHier<T>& H, const T* uin, T* uout, unsigned q0, unsigned q1,
                            double& s, double& m) {
   const int L = R.L;
   const bool pi = R.damping == ADAFAC_DAMP_PI && L > R.lmin;
@@ -75,22 +93,27 @@ __device__ void fine_items(const BatchReq& R, const BatchHier<T>& H, const T* ui
   const LevelView<T>& Lm1 = H.v[L > R.lmin ? L - 1 : L];
   const T omega = T(R.omega);
   const int nv = F.nv;
-  for (size_t i = v0 + threadIdx.x; i < v1; i += NTS) {
-    int x, y, z;
-    xyz_of<D>(i, nv, x, y, z);
-    if (!is_interior<D>(x, y, z, nv)) continue;
-    T dg;
-    const T au = apply_level_op<T, D>(F, x, y, z, dg, [&](int dx, int dy, int dz) {
-      return uin[lin<D>(x + dx, y + dy, z + dz, nv)];
-    });
-    const T res = H.bfine[i] - au;
-    const T c = omega * res / dg;
-    H.rfine[i] = res;
-    uout[i] = uin[i] + c;
-    if (pi && x % 3 == 0 && y % 3 == 0 && (D == 2 || z % 3 == 0)) Lm1.ic[lin<D>(x / 3, y / 3, z / 3, Lm1.nv)] = c;
-    const double rd = double(res);
-    s += double(F.hd) * rd * rd;
-    m = fmax(m, fabs(rd));
+  const int tpr = row_lanes(nv);
+  for (unsigned q = q0 + threadIdx.x / unsigned(tpr); q < q1; q += unsigned(NTS / tpr)) {
+    int y, z;
+    row_yz<D>(q, nv, y, z);
+    if (y == 0 || y == nv - 1 || (D == 3 && (z == 0 || z == nv - 1))) continue;
+    for (int x = 1 + int(threadIdx.x % unsigned(tpr)); x < nv - 1; x += tpr) {
+      const size_t i = lin<D>(x, y, z, nv);
+      T dg;
+      const T au = apply_level_op<T, D>(F, x, y, z, dg, [&](int dx, int dy, int dz) {
+        return uin[lin<D>(x + dx, y + dy, z + dz, nv)];
+      });
+      const T res = H.bfine[i] - au;
+      const T c = omega * res / dg;
+      H.rfine[i] = res;
+      uout[i] = uin[i] + c;
+      if (pi && x % 3 == 0 && y % 3 == 0 && (D == 2 || z % 3 == 0))
+        Lm1.ic[lin<D>(x / 3, y / 3, z / 3, Lm1.nv)] = c;
+      const double rd = double(res);
+      s += double(F.hd) * rd * rd;
+      m = fmax(m, fabs(rd));
+    }
   }
 }
 
@@ -109,53 +132,64 @@ __device__ void level_items(const BatchReq& R, const BatchHier<T>& H, const T* u
     level_update_vertex<T, D>(H.v[l], Fv, Cm, H.rts, T(R.omega), T(R.omega_t), cscale, R.damping, 1, i);
 }
 
-// S_l += P (S_{l-1} - I c_l) on vertices [v0, v1) of level l (the finest level: u_out).
+// S_l += P (S_{l-1} - I c_l) on rows [q0, q1) of level l (the finest level: u_out).
 template <typename T, int D>
-__device__ void prolong_items(const BatchReq& R, const BatchHier<T>& H, T* uout, int l, size_t v0, size_t v1) {
+__device__ void prolong_items(const BatchReq& R, const BatchHier<T>& H, T* uout, int l, unsigned q0, unsigned q1) {
   const bool pi = R.damping == ADAFAC_DAMP_PI;
   const LevelView<T>& F = H.v[l];
   const LevelView<T>& C = H.v[l - 1];
   T* dst = l == R.L ? uout : F.S;
   const int nv = F.nv;
-  for (size_t i = v0 + threadIdx.x; i < v1; i += NTS) {
-    int x, y, z;
-    xyz_of<D>(i, nv, x, y, z);
-    if (!is_interior<D>(x, y, z, nv)) continue;
-    dst[i] += prolong_value<T, D>(F, C, x, y, z, C.S, pi ? C.ic : nullptr);
+  const int tpr = row_lanes(nv);
+  for (unsigned q = q0 + threadIdx.x / unsigned(tpr); q < q1; q += unsigned(NTS / tpr)) {
+    int y, z;
+    row_yz<D>(q, nv, y, z);
+    if (y == 0 || y == nv - 1 || (D == 3 && (z == 0 || z == nv - 1))) continue;
+    for (int x = 1 + int(threadIdx.x % unsigned(tpr)); x < nv - 1; x += tpr)
+      dst[lin<D>(x, y, z, nv)] += prolong_value<T, D>(F, C, x, y, z, C.S, pi ? C.ic : nullptr);
   }
 }
 
-// FP32_REFINED: u += e on [v0, v1) of the finest level.
+// FP32_REFINED: u += e on rows [q0, q1) of the finest level.
 template <int D>
-__device__ void adde_items(const BatchReq& R, const float* e, size_t v0, size_t v1) {
+__device__ void adde_items(const BatchReq& R, const float* e, unsigned q0, unsigned q1) {
   double* u = R.h64.ufine[0];
   const int nv = R.h64.v[R.L].nv;
-  for (size_t i = v0 + threadIdx.x; i < v1; i += NTS) {
-    int x, y, z;
-    xyz_of<D>(i, nv, x, y, z);
-    if (is_interior<D>(x, y, z, nv)) u[i] += double(e[i]);
+  const int tpr = row_lanes(nv);
+  for (unsigned q = q0 + threadIdx.x / unsigned(tpr); q < q1; q += unsigned(NTS / tpr)) {
+    int y, z;
+    row_yz<D>(q, nv, y, z);
+    if (y == 0 || y == nv - 1 || (D == 3 && (z == 0 || z == nv - 1))) continue;
+    for (int x = 1 + int(threadIdx.x % unsigned(tpr)); x < nv - 1; x += tpr) {
+      const size_t i = lin<D>(x, y, z, nv);
+      u[i] += double(e[i]);
+    }
   }
 }
 
-// FP32_REFINED: r32 = float(b - A u) in FP64 on [v0, v1), norm partials.
+// FP32_REFINED: r32 = float(b - A u) in FP64 on rows [q0, q1), norm partials.
 template <int D>
-__device__ void defect_items(const BatchReq& R, size_t v0, size_t v1, double& s, double& m) {
+__device__ void defect_items(const BatchReq& R, unsigned q0, unsigned q1, double& s, double& m) {
   const BatchHier<double>& H = R.h64;
   const LevelView<double>& F = H.v[R.L];
   const double* u = H.ufine[0];
   const int nv = F.nv;
-  for (size_t i = v0 + threadIdx.x; i < v1; i += NTS) {
-    int x, y, z;
-    xyz_of<D>(i, nv, x, y, z);
-    if (!is_interior<D>(x, y, z, nv)) continue;
-    double dg;
-    const double au = apply_level_op<double, D>(F, x, y, z, dg, [&](int dx, int dy, int dz) {
-      return u[lin<D>(x + dx, y + dy, z + dz, nv)];
-    });
-    const double res = H.bfine[i] - au;
-    R.h32.bfine[i] = float(res);
-    s += F.hd * res * res;
-    m = fmax(m, fabs(res));
+  const int tpr = row_lanes(nv);
+  for (unsigned q = q0 + threadIdx.x / unsigned(tpr); q < q1; q += unsigned(NTS / tpr)) {
+    int y, z;
+    row_yz<D>(q, nv, y, z);
+    if (y == 0 || y == nv - 1 || (D == 3 && (z == 0 || z == nv - 1))) continue;
+    for (int x = 1 + int(threadIdx.x % unsigned(tpr)); x < nv - 1; x += tpr) {
+      const size_t i = lin<D>(x, y, z, nv);
+      double dg;
+      const double au = apply_level_op<double, D>(F, x, y, z, dg, [&](int dx, int dy, int dz) {
+        return u[lin<D>(x + dx, y + dy, z + dz, nv)];
+      });
+      const double res = H.bfine[i] - au;
+      R.h32.bfine[i] = float(res);
+      s += F.hd * res * res;
+      m = fmax(m, fabs(res));
+    }
   }
 }
 
@@ -181,7 +215,7 @@ __device__ void final_item(const BatchReq& R, BatchState& S, const ServeSeg& g, 
   S.cycles += 1;
   if (!st && S.cycles >= R.max_cycles) st = 3;
   S.status = st;
-  if (R.precision == ADAFAC_PREC_FP64) S.cur = g.cur0 ^ ((j + 1) & 1);   // the iterate this cycle produces
+  if (R.precision == ADAFAC_PREC_FP64) S.cur = g.cur0 ^ ((j * g.cps + g.sub + 1) & 1);   // the iterate it produces
   // FP64: the rest of this cycle still runs (it produces the result); FP32_REFINED: the outer
   // iterate just measured is the result
   if (st) S.stop_need = need + 1 + (unsigned long long)g.run_after;
@@ -190,59 +224,55 @@ __device__ void final_item(const BatchReq& R, BatchState& S, const ServeSeg& g, 
 template <int D>
 __device__ void run_item(const BatchReq& R, BatchState& S, const ServeSeg& g, int j, unsigned long long need, int t,
                          double* ws, double* wm, double* red) {
-  const size_t v0 = size_t(t) * size_t(g.tile);
   const int L = R.L;
   const bool fp64 = R.precision == ADAFAC_PREC_FP64;
-  // FP64 iterates ping-pong; FP32 inner cycle i reads e_i (e_0 = 0) and writes e_{i+1}
-  const int cur = g.cur0 ^ (j & 1);
+  // FP64 iterates ping-pong (cycle g.sub of the step's g.cps cycles); FP32 inner cycle i reads
+  // e_i (e_0 = 0) and writes e_{i+1}
+  const int cur = g.cur0 ^ ((j * g.cps + g.sub) & 1);
   const double* u64in = R.h64.ufine[cur];
   double* u64out = R.h64.ufine[1 - cur];
   const float* u32in = g.sub == 0 ? R.ezero : R.h32.ufine[g.sub & 1];
   float* u32out = R.h32.ufine[(g.sub + 1) & 1];
+  const int nvl = fp64 ? R.h64.v[g.level].nv : R.h32.v[g.level].nv;
+  // row-based phases: item t covers rows [q0, q1); the coarse FAS updates: vertices [v0, v1)
+  const unsigned q0 = unsigned(t) * unsigned(g.tile);
+  const unsigned q1 = unsigned(min(size_t(q0) + size_t(g.tile), nrows_of<D>(nvl)));
   double s = 0.0, m = 0.0;
   switch (g.kind) {
-    case SERVE_FINE: {
-      const size_t v1 = min(v0 + size_t(g.tile), nverts_of<D>(fp64 ? R.h64.v[L].nv : R.h32.v[L].nv));
+    case SERVE_FINE:
       if (fp64) {
-        fine_items<double, D>(R, R.h64, u64in, u64out, v0, v1, s, m);
+        fine_items<double, D>(R, R.h64, u64in, u64out, q0, q1, s, m);
         wg_partials(s, m, R.partials + 2 * t, ws, wm);
       } else {
-        fine_items<float, D>(R, R.h32, u32in, u32out, v0, v1, s, m);
+        fine_items<float, D>(R, R.h32, u32in, u32out, q0, q1, s, m);
       }
       break;
-    }
     case SERVE_LEVEL: {
-      const size_t v1 = min(v0 + size_t(g.tile), nverts_of<D>(fp64 ? R.h64.v[g.level].nv : R.h32.v[g.level].nv));
+      const size_t v0 = size_t(t) * size_t(g.tile);
+      const size_t v1 = min(v0 + size_t(g.tile), nverts_of<D>(nvl));
       if (fp64) level_items<double, D>(R, R.h64, u64in, g.level, v0, v1);
       else level_items<float, D>(R, R.h32, u32in, g.level, v0, v1);
       break;
     }
-    case SERVE_PROLONG: {
-      const size_t v1 = min(v0 + size_t(g.tile), nverts_of<D>(fp64 ? R.h64.v[g.level].nv : R.h32.v[g.level].nv));
-      if (fp64) prolong_items<double, D>(R, R.h64, u64out, g.level, v0, v1);
-      else prolong_items<float, D>(R, R.h32, u32out, g.level, v0, v1);
+    case SERVE_PROLONG:
+      if (fp64) prolong_items<double, D>(R, R.h64, u64out, g.level, q0, q1);
+      else prolong_items<float, D>(R, R.h32, u32out, g.level, q0, q1);
       break;
-    }
-    case SERVE_ADDE: {
+    case SERVE_ADDE:
       // the correction of the previous outer step (none before the first)
-      if (S.cycles > 0) {
-        const size_t v1 = min(v0 + size_t(g.tile), nverts_of<D>(R.h64.v[L].nv));
-        adde_items<D>(R, R.h32.ufine[R.inner_k & 1], v0, v1);
-      }
+      if (S.cycles > 0) adde_items<D>(R, R.h32.ufine[R.inner_k & 1], q0, q1);
       break;
-    }
-    case SERVE_DEFECT: {
-      const size_t v1 = min(v0 + size_t(g.tile), nverts_of<D>(R.h64.v[L].nv));
-      defect_items<D>(R, v0, v1, s, m);
+    case SERVE_DEFECT:
+      defect_items<D>(R, q0, q1, s, m);
       wg_partials(s, m, R.partials + 2 * t, ws, wm);
       break;
-    }
     case SERVE_FINAL:
       final_item(R, S, g, j, need, ws, wm, red);
       break;
     default:
       break;
   }
+  (void)L;
 }
 
 // One phase slot of one step of every batched request: workgroup b runs item b of the slot's

@@ -32,8 +32,9 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kSegsPerSlot = 48;   // work-list segments held per request slot (on average)
-// vertices per work item: finest-level phases (at most kNormBlocks items, one norm partial
-// each), coarse FAS updates (5^d gathers per vertex) and prolongations
+// vertices per work item (whole lattice rows for the row-based phases): finest-level phases (at
+// most kNormBlocks items, one norm partial each), coarse FAS updates (5^d gathers per vertex)
+// and prolongations
 constexpr size_t kFineItem = 2048, kLevelItem = 1024, kProlongItem = 4096;
 constexpr int kPrepThreads = 4;    // host set-ups of queued requests running at once
 constexpr int kPrepAhead = 16;     // queued requests set up ahead of admission (host memory bound)
@@ -264,52 +265,72 @@ int harvest_batched(adafac_server* s, bool wait, bool* done) {
 }
 
 // The phases of one step of a request, in order (see ServeSeg).
-void step_program(const BatchReq& d, std::vector<ServeSeg>& prog) {
+// slots[i]: the launch (phase slot) of phase i.  The stopping rule's item shares its slot with
+// the phase after it, which does not read its result (under FP64 that phase runs even when the
+// request stops; under FP32_REFINED it only writes the inner correction, which a stopped
+// request never adds).
+// An FP64 step is cps cycles (each with its own stopping rule), so that FP64 requests move on
+// as far per launch chain as FP32-refined ones whose steps hold inner_k cycles.
+void step_program(const BatchReq& d, int cps, std::vector<ServeSeg>& prog, std::vector<int>& slots) {
   prog.clear();
+  slots.clear();
   auto nv_of = [&](int l) {
     const size_t n = size_t(ipow3(l) + 1);
     return d.dim == 2 ? n * n : n * n * n;
   };
-  auto add = [&](int kind, int level, int sub, size_t nverts, size_t tile) {
+  // lattice rows (nv vertices each) of level l: the unit of the row-based phases
+  auto rows_of = [&](int l) {
+    const size_t n = size_t(ipow3(l) + 1);
+    return d.dim == 2 ? n : n * n;
+  };
+  auto add = [&](int kind, int level, int sub, size_t units, size_t tile) {
     ServeSeg g{};
     g.kind = kind;
     g.level = level;
     g.sub = sub;
     g.tile = int(tile);
-    g.ntile = int((nverts + tile - 1) / tile);
+    g.ntile = int((units + tile - 1) / tile);
     prog.push_back(g);
   };
-  const size_t nvL = nv_of(d.L);
-  size_t tf = std::max(kFineItem, (nvL + size_t(kNormBlocks) - 1) / size_t(kNormBlocks));
-  tf = (tf + 255) / 256 * 256;
-  const int nf = int((nvL + tf - 1) / tf);
-  auto cycle_phases = [&](int sub) {
-    add(SERVE_FINE, d.L, sub, nvL, tf);
-    if (sub < 0) add(SERVE_FINAL, d.L, 0, 1, 1);
-    for (int l = d.L - 1; l >= d.lmin; --l) add(SERVE_LEVEL, l, sub < 0 ? 0 : sub, nv_of(l), kLevelItem);
-    for (int l = d.lmin + 1; l <= d.L; ++l) add(SERVE_PROLONG, l, sub < 0 ? 0 : sub, nv_of(l), kProlongItem);
+  auto rows_per_item = [&](int l, size_t verts) {
+    const size_t nv = size_t(ipow3(l) + 1);
+    return std::max<size_t>(1, (verts + nv - 1) / nv);
   };
-  if (d.precision == ADAFAC_PREC_FP64) {
-    cycle_phases(-1);
-    prog[0].sub = 0;
+  // finest-level items: about kFineItem vertices, at most kNormBlocks of them (one norm partial each)
+  const size_t rL = rows_of(d.L);
+  const size_t tf = std::max(rows_per_item(d.L, kFineItem), (rL + size_t(kNormBlocks) - 1) / size_t(kNormBlocks));
+  const int nf = int((rL + tf - 1) / tf);
+  const bool fp64 = d.precision == ADAFAC_PREC_FP64;
+  auto cycle_phases = [&](int sub) {
+    add(SERVE_FINE, d.L, sub, rL, tf);
+    if (fp64) add(SERVE_FINAL, d.L, sub, 1, 1);
+    for (int l = d.L - 1; l >= d.lmin; --l) add(SERVE_LEVEL, l, sub, nv_of(l), kLevelItem);
+    for (int l = d.lmin + 1; l <= d.L; ++l) add(SERVE_PROLONG, l, sub, rows_of(l), rows_per_item(l, kProlongItem));
+  };
+  if (fp64) {
+    for (int c = 0; c < cps; ++c) cycle_phases(c);
   } else {
-    add(SERVE_ADDE, d.L, 0, nvL, tf);
-    add(SERVE_DEFECT, d.L, 0, nvL, tf);
+    add(SERVE_ADDE, d.L, 0, rL, tf);
+    add(SERVE_DEFECT, d.L, 0, rL, tf);
     add(SERVE_FINAL, d.L, 0, 1, 1);
     for (int i = 0; i < d.inner_k; ++i) cycle_phases(i);
   }
-  int off = 0;
+  int off = 0, slot = 0;
   for (ServeSeg& g : prog) {
     g.need_off = off;
     off += g.ntile;
+    slots.push_back(slot);
+    if (g.kind != SERVE_FINAL) ++slot;
   }
+  const int per_cycle = fp64 ? off / cps : 0;
   for (size_t p = 0; p < prog.size(); ++p) {
     ServeSeg& g = prog[p];
     g.per_step = off;
+    g.cps = fp64 ? cps : 1;
     if (g.kind == SERVE_FINAL) {
       g.nparts = nf;
-      // FP64: the rest of the cycle still runs when it stops (it produces the result)
-      g.run_after = d.precision == ADAFAC_PREC_FP64 ? off - (g.need_off + 1) : 0;
+      // FP64: the rest of its cycle still runs when it stops (that cycle produces the result)
+      g.run_after = fp64 ? (g.sub + 1) * per_cycle - (g.need_off + 1) : 0;
     }
   }
 }
@@ -321,13 +342,21 @@ int launch_batched(adafac_server* s) {
   if (s->b_flight) return ADAFAC_OK;
   s->b_members.clear();
   std::vector<std::vector<ServeSeg>> progs;
+  std::vector<std::vector<int>> pslots;
   std::vector<ServeSeg> prog;
+  std::vector<int> slots;
   size_t nseg = 0, maxp = 0;
   const int steps = s->cfg.cycles_per_round;
+  int cps = 1;
+  for (uint64_t t : s->active) {
+    const Req& r = s->reqs[t];
+    if (r.res.batched && s->h_desc[r.slot].precision != ADAFAC_PREC_FP64)
+      cps = std::max(cps, s->h_desc[r.slot].inner_k);
+  }
   for (uint64_t t : s->active) {
     Req& r = s->reqs[t];
     if (!r.res.batched) continue;
-    step_program(s->h_desc[r.slot], prog);
+    step_program(s->h_desc[r.slot], cps, prog, slots);
     if (nseg + prog.size() > size_t(s->seg_cap)) break;   // the rest joins a later round
     const BatchState& st = s->h_states[r.slot];
     for (ServeSeg& g : prog) {
@@ -337,23 +366,25 @@ int launch_batched(adafac_server* s) {
     }
     r.items_base += (unsigned long long)steps * (unsigned long long)prog[0].per_step;
     nseg += prog.size();
-    maxp = std::max(maxp, prog.size());
+    maxp = std::max(maxp, size_t(slots.back() + 1));
     progs.push_back(prog);
+    pslots.push_back(slots);
     s->b_members.push_back(t);
   }
   if (s->b_members.empty()) return ADAFAC_OK;
   s->h_segs.clear();
   std::vector<int> slot_off(maxp + 1, 0), slot_items(maxp, 0);
+  std::vector<size_t> at(progs.size(), 0);   // next phase of each request
   for (size_t p = 0; p < maxp; ++p) {
     slot_off[p] = int(s->h_segs.size());
     int item = 0;
-    for (auto& pg : progs) {
-      if (p >= pg.size()) continue;
-      ServeSeg g = pg[p];
-      g.item0 = item;
-      item += g.ntile;
-      s->h_segs.push_back(g);
-    }
+    for (size_t k = 0; k < progs.size(); ++k)
+      for (; at[k] < progs[k].size() && pslots[k][at[k]] == int(p); ++at[k]) {
+        ServeSeg g = progs[k][at[k]];
+        g.item0 = item;
+        item += g.ntile;
+        s->h_segs.push_back(g);
+      }
     slot_items[p] = item;
   }
   slot_off[maxp] = int(s->h_segs.size());
