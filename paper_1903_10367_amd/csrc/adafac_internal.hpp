@@ -120,7 +120,7 @@ struct BatchReq {
   double omega, omega_t, omega_hat;
   double tol;                // stop when ||r||_h / ||r^0||_h <= tol
   int max_cycles;            // cycles (FP64) or outer steps (FP32_REFINED)
-  int pad;
+  int fusable;               // the finest level can take the single-pass sweep (see run_cycle)
   BatchHier<double> h64;     // FP64 form: everything; FP32_REFINED: v[L], u (ufine[0]) and b
   BatchHier<float> h32;      // FP32_REFINED: the inner hierarchy (ufine = e, bfine = r)
   const float* ezero;        // FP32_REFINED: zero lattice, first inner iterate
@@ -139,8 +139,10 @@ struct BatchState {
 
 // Phase kinds of a serving step (one request's chain: FINE, FINAL, LEVEL l = L-1..lmin,
 // PROLONG l = lmin+1..L for FP64; ADDE, DEFECT, FINAL, then per inner cycle FINE, LEVELs,
-// PROLONGs in FP32 for FP32_REFINED).
-enum { SERVE_FINE = 0, SERVE_FINAL, SERVE_LEVEL, SERVE_PROLONG, SERVE_ADDE, SERVE_DEFECT };
+// PROLONGs in FP32 for FP32_REFINED).  Large requests replace FINE by SWEEP, the single-pass
+// finest-level sweep launched on its own (it restricts to level L-1 and adds the previous
+// cycle's pending prolongation), and leave the prolongation into level L pending.
+enum { SERVE_FINE = 0, SERVE_FINAL, SERVE_LEVEL, SERVE_PROLONG, SERVE_ADDE, SERVE_DEFECT, SERVE_SWEEP };
 
 // One segment of a phase-slot launch's work list: the ntile items of one phase of one request.
 struct ServeSeg {
@@ -154,12 +156,14 @@ struct ServeSeg {
   int run_after;             // FINAL: items of the request after it that still run when it stops
   int cur0;                  // FP64: iterate index at the round's start
   int cps;                   // FP64: cycles per step (sub numbers them); 1 otherwise
+  int gather;                // LEVEL: 1 gathers R r, R~ r and I u from level + 1; 0: the sweep wrote them
+  int pend;                  // ADDE: adds the pending P S_{L-1} with e; PROLONG into L-1: subtracts I c_L
   unsigned long long base;   // items of the request in earlier rounds (its sequence numbers start there)
 };
 
 // Internal hooks of the C ABI used by the request server (api.cpp).
 int batch_describe(void* ctx, BatchReq* out);        // device description of a bound context
-int batch_adopt(void* ctx, int cur, int converged);  // current iterate after batched cycles
+int batch_adopt(void* ctx, int cur, int pending);    // current iterate after batched cycles
 int residual_range(void* ctx, int c0, int n, double* out);   // norms of cycles c0.., 2 per cycle
 
 struct CycleParams {

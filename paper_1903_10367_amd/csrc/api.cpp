@@ -37,8 +37,10 @@ hipError_t launch_defect(int d, const LevelView<double>& F, const double* u, con
 template <typename T>
 hipError_t launch_fine_sweep(int d, const LevelView<T>& F, const LevelView<T>& C, const T* uin, T* uout,
                              const T* b, const RtSep<T>& rt, T omega, int damping, int apply_pending,
-                             double* partials, int* nparts, hipStream_t s);
+                             double* partials, int* nparts, hipStream_t s, const unsigned long long* stop = nullptr,
+                             unsigned long long need = 0);
 size_t fine_sweep_partials(int d, int n);
+int fine_sweep_nparts(int d, int n);
 template <typename T>
 hipError_t launch_coarse_sweep(int d, const LevelView<T>& L, const LevelView<T>& C, const RtSep<T>& rts,
                                T omega, T omega_t, T cscale, int damping, hipStream_t s);
@@ -949,6 +951,11 @@ int batch_describe(void* vc, BatchReq* out) {
     out->ezero = c->ezero;
   }
   out->partials = c->partials;
+  // the conditions of run_cycle's single-pass form, without the single-workgroup levels: under
+  // adAFAC-PI the prolongation into level L-1 is a phase of its own when L-1 > l_min
+  const int L = c->L;
+  out->fusable = c->opts.fused && L > c->lmin && c->opts.rtilde != ADAFAC_RTILDE_OPERATOR && fused_ok(c) &&
+                 (c->opts.damping != ADAFAC_DAMP_PI || L - 1 > c->lmin) && fine_sweep_nparts(c->dim, ipow3(L)) > 0;
   return ADAFAC_OK;
 }
 
@@ -968,12 +975,14 @@ int residual_range(void* vc, int c0, int n, double* out) {
   return ADAFAC_OK;
 }
 
-// After batched cycles: ufine[cur] of the description holds the current FP64 iterate.
-int batch_adopt(void* vc, int cur, int /*converged*/) {
+// After batched cycles: ufine[cur] of the description holds the current FP64 iterate; pending:
+// (FP64 form) the last cycle swept the finest level and left P S_{L-1} to be added.
+int batch_adopt(void* vc, int cur, int pending) {
   adafac_ctx* c = static_cast<adafac_ctx*>(vc);
   if (!c || !c->bound) return ADAFAC_ESTATE;
   if (!mixed(c) && cur == 1) c->h64.cur = 1 - c->h64.cur;
   c->h64.pending = c->h32.pending = c->e_pending = false;
+  if (!mixed(c) && pending) c->h64.pending = true;
   return ADAFAC_OK;
 }
 

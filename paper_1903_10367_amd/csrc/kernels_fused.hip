@@ -258,6 +258,9 @@ struct Sweep3dArgs {
   // adAFAC-PI: the level's correction c at the c-points, I c, written to the next coarser level
   // (nullptr for the other damping forms)
   T* ic;
+  // request server: the launch does nothing once *stop <= need (the request stopped)
+  const unsigned long long* stop;
+  unsigned long long need;
 };
 
 // Lattice loads and stores of the 3D sweep through a buffer resource: the per-lane column
@@ -319,6 +322,7 @@ __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_fine_sweep3d(S
   __shared__ T Sb[PEND ? (MAXTZ / 3 + 3) * CW * CW : 1];
   __shared__ T Sz[3][CW * CW];           // S interpolated to a fine plane
 
+  if (a.stop && a.need >= *a.stop) return;   // uniform over the launch
   const int n = a.n, nv = a.nv, nc = a.nc, nvc = a.nvc;
   const int plane = nv * nv;
   const unsigned planeb = unsigned(plane * sizeof(T));
@@ -592,6 +596,7 @@ __global__ void __launch_bounds__(NT3, ADAFAC_SWEEP3D_MINWAVES) k_sweep3d_w32(Sw
   __shared__ T Sb[PEND ? (MAXTZ / 3 + 3) * CW * CW : 1];
   __shared__ T Sz[3][CW * CW];           // S interpolated to a fine plane
 
+  if (a.stop && a.need >= *a.stop) return;   // uniform over the launch
   const int n = a.n, nv = a.nv, nc = a.nc, nvc = a.nvc;
   const int plane = nv * nv;
   const unsigned planeb = unsigned(plane * sizeof(T));
@@ -1004,7 +1009,9 @@ __global__ void __launch_bounds__(256) k_fine_sweep2d(LevelView<T> F, LevelView<
                                                       const T* __restrict__ uin, T* __restrict__ uout,
                                                       const T* __restrict__ b, RtSep<T> rts, T omega,
                                                       int damping, int apply_pending, int ntx,
-                                                      double* __restrict__ partials) {
+                                                      double* __restrict__ partials,
+                                                      const unsigned long long* stop, unsigned long long need) {
+  if (stop && need >= *stop) return;   // uniform over the launch (request server)
   __shared__ T Ub[NU];
   __shared__ T Rb[NR];
   __shared__ T Xw[RW * NCO];
@@ -1194,10 +1201,17 @@ hipError_t launch_coarse_sweep(int d, const LevelView<T>& L, const LevelView<T>&
   return launch_sweep3d<T>(a, L.eps != nullptr, s);
 }
 
+int fine_sweep_nparts(int d, int n) {
+  if (n % TX) return 0;
+  const int ntx = n / TX;
+  return d == 2 ? ntx * ntx : ntx * ntx * (n / pick_tz(n));
+}
+
 template <typename T>
 hipError_t launch_fine_sweep(int d, const LevelView<T>& F, const LevelView<T>& C, const T* uin, T* uout,
                              const T* b, const RtSep<T>& rts, T omega, int damping, int apply_pending,
-                             double* partials, int* nparts, hipStream_t s) {
+                             double* partials, int* nparts, hipStream_t s, const unsigned long long* stop,
+                             unsigned long long need) {
   const int n = F.n;
   if (n % TX || F.pw) return hipErrorInvalidValue;   // needs 27 | n and d-linear transfer into L
   const int ntx = n / TX;
@@ -1206,16 +1220,18 @@ hipError_t launch_fine_sweep(int d, const LevelView<T>& F, const LevelView<T>& C
   if (d == 2) {
     const unsigned nb = unsigned(ntx * ntx);
     if (var)
-      k_fine_sweep2d<T, true><<<nb, 256, 0, s>>>(F, C, uin, uout, b, rts, omega, damping, apply_pending, ntx, partials);
+      k_fine_sweep2d<T, true><<<nb, 256, 0, s>>>(F, C, uin, uout, b, rts, omega, damping, apply_pending, ntx, partials,
+                                                 stop, need);
     else
-      k_fine_sweep2d<T, false><<<nb, 256, 0, s>>>(F, C, uin, uout, b, rts, omega, damping, apply_pending, ntx, partials);
+      k_fine_sweep2d<T, false><<<nb, 256, 0, s>>>(F, C, uin, uout, b, rts, omega, damping, apply_pending, ntx, partials,
+                                                  stop, need);
     *nparts = int(nb);
   } else {
     const int tz = pick_tz(n), ntz = n / tz;
     const unsigned nb = unsigned(ntx * ntx * ntz);
     Sweep3dArgs<T> a{uin, uout, b, C.S, C.u, C.rr, C.bt, F.eps, partials, F.h, omega, F.hd, rts,
                      n, F.nv, C.n, C.nv, F.nb, F.bs, tz, ntx, ntz, damping, apply_pending,
-                     0, nullptr, nullptr, nullptr, nullptr, T(0), T(1), nullptr};
+                     0, nullptr, nullptr, nullptr, nullptr, T(0), T(1), nullptr, stop, need};
     if (damping == ADAFAC_DAMP_PI) a.ic = C.ic;
     const hipError_t e = launch_sweep3d<T>(a, var, s);
     if (e != hipSuccess) return e;
@@ -1255,9 +1271,11 @@ template hipError_t launch_coarse_sweep<float>(int, const LevelView<float>&, con
                                                const RtSep<float>&, float, float, float, int, hipStream_t);
 template hipError_t launch_fine_sweep<double>(int, const LevelView<double>&, const LevelView<double>&,
                                               const double*, double*, const double*, const RtSep<double>&,
-                                              double, int, int, double*, int*, hipStream_t);
+                                              double, int, int, double*, int*, hipStream_t,
+                                              const unsigned long long*, unsigned long long);
 template hipError_t launch_fine_sweep<float>(int, const LevelView<float>&, const LevelView<float>&,
                                              const float*, float*, const float*, const RtSep<float>&, float,
-                                             int, int, double*, int*, hipStream_t);
+                                             int, int, double*, int*, hipStream_t, const unsigned long long*,
+                                             unsigned long long);
 
 }  // namespace adafac

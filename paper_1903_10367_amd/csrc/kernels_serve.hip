@@ -117,9 +117,11 @@ __device__ void fine_items(const BatchReq& R, const BatchHier<T>& H, const T* ui
   }
 }
 
-// FAS update of level l on vertices [v0, v1) (gathering R r, R~ r and I u from level l + 1).
+// FAS update of level l on vertices [v0, v1) (gathering R r, R~ r and I u from level l + 1, or
+// with them already written by the finest-level sweep).
 template <typename T, int D>
-__device__ void level_items(const BatchReq& R, const BatchHier<T>& H, const T* uin, int l, size_t v0, size_t v1) {
+__device__ void level_items(const BatchReq& R, const BatchHier<T>& H, const T* uin, int l, int gather, size_t v0,
+                            size_t v1) {
   const int L = R.L;
   LevelView<T> Fv = H.v[l + 1];
   if (l + 1 == L) {
@@ -129,12 +131,15 @@ __device__ void level_items(const BatchReq& R, const BatchHier<T>& H, const T* u
   const LevelView<T> Cm = l > R.lmin ? H.v[l - 1] : LevelView<T>{};
   const T cscale = T(R.damping == ADAFAC_DAMP_EXP ? pow(R.omega_hat, double(L - l)) : 1.0);
   for (size_t i = v0 + threadIdx.x; i < v1; i += NTS)
-    level_update_vertex<T, D>(H.v[l], Fv, Cm, H.rts, T(R.omega), T(R.omega_t), cscale, R.damping, 1, i);
+    level_update_vertex<T, D>(H.v[l], Fv, Cm, H.rts, T(R.omega), T(R.omega_t), cscale, R.damping, gather, i);
 }
 
-// S_l += P (S_{l-1} - I c_l) on rows [q0, q1) of level l (the finest level: u_out).
+// S_l += P (S_{l-1} - I c_l) on rows [q0, q1) of level l (the finest level: u_out).  self: under
+// adAFAC-PI with the finest level swept, level L-1 also subtracts I c_L, which the sweep stored
+// there, so that the pending P S_{L-1} is P (S_{L-1} - I c_L).
 template <typename T, int D>
-__device__ void prolong_items(const BatchReq& R, const BatchHier<T>& H, T* uout, int l, unsigned q0, unsigned q1) {
+__device__ void prolong_items(const BatchReq& R, const BatchHier<T>& H, T* uout, int l, int self, unsigned q0,
+                              unsigned q1) {
   const bool pi = R.damping == ADAFAC_DAMP_PI;
   const LevelView<T>& F = H.v[l];
   const LevelView<T>& C = H.v[l - 1];
@@ -145,15 +150,22 @@ __device__ void prolong_items(const BatchReq& R, const BatchHier<T>& H, T* uout,
     int y, z;
     row_yz<D>(q, nv, y, z);
     if (y == 0 || y == nv - 1 || (D == 3 && (z == 0 || z == nv - 1))) continue;
-    for (int x = 1 + int(threadIdx.x % unsigned(tpr)); x < nv - 1; x += tpr)
-      dst[lin<D>(x, y, z, nv)] += prolong_value<T, D>(F, C, x, y, z, C.S, pi ? C.ic : nullptr);
+    for (int x = 1 + int(threadIdx.x % unsigned(tpr)); x < nv - 1; x += tpr) {
+      const size_t i = lin<D>(x, y, z, nv);
+      T v = prolong_value<T, D>(F, C, x, y, z, C.S, pi ? C.ic : nullptr);
+      if (self) v -= F.ic[i];
+      dst[i] += v;
+    }
   }
 }
 
-// FP32_REFINED: u += e on rows [q0, q1) of the finest level.
+// FP32_REFINED: u += e (pend: u += e + P S_{L-1}, the prolongation the last inner sweep left
+// pending, summed in FP32 as by the one-kernel-per-step path) on rows [q0, q1) of the finest level.
 template <int D>
-__device__ void adde_items(const BatchReq& R, const float* e, unsigned q0, unsigned q1) {
+__device__ void adde_items(const BatchReq& R, const float* e, int pend, unsigned q0, unsigned q1) {
   double* u = R.h64.ufine[0];
+  const LevelView<float>& F = R.h32.v[R.L];
+  const LevelView<float>& C = R.h32.v[R.L - 1];
   const int nv = R.h64.v[R.L].nv;
   const int tpr = row_lanes(nv);
   for (unsigned q = q0 + threadIdx.x / unsigned(tpr); q < q1; q += unsigned(NTS / tpr)) {
@@ -162,7 +174,9 @@ __device__ void adde_items(const BatchReq& R, const float* e, unsigned q0, unsig
     if (y == 0 || y == nv - 1 || (D == 3 && (z == 0 || z == nv - 1))) continue;
     for (int x = 1 + int(threadIdx.x % unsigned(tpr)); x < nv - 1; x += tpr) {
       const size_t i = lin<D>(x, y, z, nv);
-      u[i] += double(e[i]);
+      float c = e[i];
+      if (pend) c += prolong_value<float, D>(F, C, x, y, z, C.S, nullptr);
+      u[i] += double(c);
     }
   }
 }
@@ -250,17 +264,17 @@ __device__ void run_item(const BatchReq& R, BatchState& S, const ServeSeg& g, in
     case SERVE_LEVEL: {
       const size_t v0 = size_t(t) * size_t(g.tile);
       const size_t v1 = min(v0 + size_t(g.tile), nverts_of<D>(nvl));
-      if (fp64) level_items<double, D>(R, R.h64, u64in, g.level, v0, v1);
-      else level_items<float, D>(R, R.h32, u32in, g.level, v0, v1);
+      if (fp64) level_items<double, D>(R, R.h64, u64in, g.level, g.gather, v0, v1);
+      else level_items<float, D>(R, R.h32, u32in, g.level, g.gather, v0, v1);
       break;
     }
     case SERVE_PROLONG:
-      if (fp64) prolong_items<double, D>(R, R.h64, u64out, g.level, q0, q1);
-      else prolong_items<float, D>(R, R.h32, u32out, g.level, q0, q1);
+      if (fp64) prolong_items<double, D>(R, R.h64, u64out, g.level, g.pend, q0, q1);
+      else prolong_items<float, D>(R, R.h32, u32out, g.level, g.pend, q0, q1);
       break;
     case SERVE_ADDE:
       // the correction of the previous outer step (none before the first)
-      if (S.cycles > 0) adde_items<D>(R, R.h32.ufine[R.inner_k & 1], q0, q1);
+      if (S.cycles > 0) adde_items<D>(R, R.h32.ufine[R.inner_k & 1], g.pend, q0, q1);
       break;
     case SERVE_DEFECT:
       defect_items<D>(R, q0, q1, s, m);

@@ -24,6 +24,12 @@
 namespace adafac {
 hipError_t launch_serve_phase(const BatchReq* reqs, BatchState* states, const ServeSeg* segs, int nseg, int nitems,
                               int j, hipStream_t s);
+template <typename T>
+hipError_t launch_fine_sweep(int d, const LevelView<T>& F, const LevelView<T>& C, const T* uin, T* uout,
+                             const T* b, const RtSep<T>& rt, T omega, int damping, int apply_pending,
+                             double* partials, int* nparts, hipStream_t s, const unsigned long long* stop,
+                             unsigned long long need);
+int fine_sweep_nparts(int d, int n);
 }  // namespace adafac
 
 using namespace adafac;
@@ -36,6 +42,9 @@ constexpr int kSegsPerSlot = 48;   // work-list segments held per request slot (
 // most kNormBlocks items, one norm partial each), coarse FAS updates (5^d gathers per vertex)
 // and prolongations
 constexpr size_t kFineItem = 2048, kLevelItem = 1024, kProlongItem = 4096;
+// requests with at least this many finest-level vertices sweep that level in one pass (when
+// their options allow it): a launch of its own, which the smaller requests' phases do not share
+constexpr size_t kSweepMinVerts = size_t(1) << 18;
 constexpr int kPrepThreads = 4;    // host set-ups of queued requests running at once
 constexpr int kPrepAhead = 16;     // queued requests set up ahead of admission (host memory bound)
 
@@ -104,6 +113,7 @@ struct Req {
   bool prepared = false;  // prep finished; its status is prep_rc
   int prep_rc = 0;
   unsigned long long items_base = 0;   // batched: work items of the request in earlier rounds
+  bool sweep = false;     // batched: its finest level takes the single-pass sweep
 };
 
 size_t finest_vertices(int d, int L) {
@@ -192,7 +202,8 @@ int finish(adafac_server* s, Req& r, int status, int cur) {
   r.res.t_done = now(s);
   if (r.ctx) {
     int rc = ADAFAC_OK;
-    if (r.res.batched) rc = batch_adopt(r.ctx, cur, status == ADAFAC_REQ_CONVERGED);
+    // an FP64 request whose cycles swept the finest level has the last P S_{L-1} pending
+    if (r.res.batched) rc = batch_adopt(r.ctx, cur, r.sweep && s->h_desc[r.slot].precision == ADAFAC_PREC_FP64);
     r.u.assign(finest_vertices(r.dim, r.L), 0.0);
     if (!rc) rc = adafac_get_solution(r.ctx, r.u.data(), r.u.size());
     adafac_destroy(r.ctx);
@@ -271,7 +282,10 @@ int harvest_batched(adafac_server* s, bool wait, bool* done) {
 // request never adds).
 // An FP64 step is cps cycles (each with its own stopping rule), so that FP64 requests move on
 // as far per launch chain as FP32-refined ones whose steps hold inner_k cycles.
-void step_program(const BatchReq& d, int cps, std::vector<ServeSeg>& prog, std::vector<int>& slots) {
+// sweep: the finest level takes the single-pass sweep (SWEEP, one item in the request's sequence,
+// launched on its own), level L-1 is fed by it, and the prolongation into level L is left
+// pending for the next sweep (FP64) or the next outer step's ADDE (FP32_REFINED).
+void step_program(const BatchReq& d, int cps, bool sweep, std::vector<ServeSeg>& prog, std::vector<int>& slots) {
   prog.clear();
   slots.clear();
   auto nv_of = [&](int l) {
@@ -301,16 +315,25 @@ void step_program(const BatchReq& d, int cps, std::vector<ServeSeg>& prog, std::
   const size_t tf = std::max(rows_per_item(d.L, kFineItem), (rL + size_t(kNormBlocks) - 1) / size_t(kNormBlocks));
   const int nf = int((rL + tf - 1) / tf);
   const bool fp64 = d.precision == ADAFAC_PREC_FP64;
+  const bool pi = d.damping == ADAFAC_DAMP_PI;
   auto cycle_phases = [&](int sub) {
-    add(SERVE_FINE, d.L, sub, rL, tf);
+    if (sweep) add(SERVE_SWEEP, d.L, sub, 1, 1);
+    else add(SERVE_FINE, d.L, sub, rL, tf);
     if (fp64) add(SERVE_FINAL, d.L, sub, 1, 1);
-    for (int l = d.L - 1; l >= d.lmin; --l) add(SERVE_LEVEL, l, sub, nv_of(l), kLevelItem);
-    for (int l = d.lmin + 1; l <= d.L; ++l) add(SERVE_PROLONG, l, sub, rows_of(l), rows_per_item(l, kProlongItem));
+    for (int l = d.L - 1; l >= d.lmin; --l) {
+      add(SERVE_LEVEL, l, sub, nv_of(l), kLevelItem);
+      prog.back().gather = (sweep && l == d.L - 1) ? 0 : 1;
+    }
+    for (int l = d.lmin + 1; l <= (sweep ? d.L - 1 : d.L); ++l) {
+      add(SERVE_PROLONG, l, sub, rows_of(l), rows_per_item(l, kProlongItem));
+      prog.back().pend = (sweep && pi && l == d.L - 1) ? 1 : 0;
+    }
   };
   if (fp64) {
     for (int c = 0; c < cps; ++c) cycle_phases(c);
   } else {
     add(SERVE_ADDE, d.L, 0, rL, tf);
+    prog.back().pend = sweep ? 1 : 0;
     add(SERVE_DEFECT, d.L, 0, rL, tf);
     add(SERVE_FINAL, d.L, 0, 1, 1);
     for (int i = 0; i < d.inner_k; ++i) cycle_phases(i);
@@ -328,11 +351,40 @@ void step_program(const BatchReq& d, int cps, std::vector<ServeSeg>& prog, std::
     g.per_step = off;
     g.cps = fp64 ? cps : 1;
     if (g.kind == SERVE_FINAL) {
-      g.nparts = nf;
+      g.nparts = (fp64 && sweep) ? fine_sweep_nparts(d.dim, ipow3(d.L)) : nf;
       // FP64: the rest of its cycle still runs when it stops (that cycle produces the result)
       g.run_after = fp64 ? (g.sub + 1) * per_cycle - (g.need_off + 1) : 0;
     }
   }
+}
+
+// The single-pass finest-level sweep of segment g (kind SWEEP) in step j: it does nothing when the
+// request stopped before this item of its sequence.
+hipError_t launch_sweep(adafac_server* s, const ServeSeg& g, int j, bool first) {
+  const BatchReq& d = s->h_desc[g.req];
+  const int L = d.L;
+  const unsigned long long need =
+      g.base + (unsigned long long)j * (unsigned long long)g.per_step + (unsigned long long)g.need_off;
+  const unsigned long long* stop = &s->d_states[g.req].stop_need;
+  int np = 0;
+  if (d.precision == ADAFAC_PREC_FP64) {
+    const int cur = g.cur0 ^ ((j * g.cps + g.sub) & 1);
+    const double* uin = d.h64.ufine[cur];
+    LevelView<double> F = d.h64.v[L];
+    F.u = const_cast<double*>(uin);
+    F.r = d.h64.rfine;
+    const int pend = (first && j == 0 && g.sub == 0) ? 0 : 1;
+    return launch_fine_sweep<double>(d.dim, F, d.h64.v[L - 1], uin, d.h64.ufine[1 - cur], d.h64.bfine, d.h64.rts,
+                                     d.omega, d.damping, pend, d.partials, &np, s->stream, stop, need);
+  }
+  // inner cycle g.sub of an outer step: e_0 = 0, e_{i+1} from e_i plus the pending P S_{L-1}
+  const float* uin = g.sub == 0 ? d.ezero : d.h32.ufine[g.sub & 1];
+  LevelView<float> F = d.h32.v[L];
+  F.u = const_cast<float*>(uin);
+  F.r = d.h32.rfine;
+  return launch_fine_sweep<float>(d.dim, F, d.h32.v[L - 1], uin, d.h32.ufine[(g.sub + 1) & 1], d.h32.bfine,
+                                  d.h32.rts, float(d.omega), d.damping, g.sub > 0 ? 1 : 0, d.partials, &np, s->stream,
+                                  stop, need);
 }
 
 // One round advances every batched request by cycles_per_round steps.  Launch (j, p) runs the
@@ -353,10 +405,16 @@ int launch_batched(adafac_server* s) {
     if (r.res.batched && s->h_desc[r.slot].precision != ADAFAC_PREC_FP64)
       cps = std::max(cps, s->h_desc[r.slot].inner_k);
   }
+  struct SweepJob {
+    size_t p;       // phase slot
+    ServeSeg g;
+    bool first;     // the request's first cycle has no pending prolongation
+  };
+  std::vector<SweepJob> sweeps;
   for (uint64_t t : s->active) {
     Req& r = s->reqs[t];
     if (!r.res.batched) continue;
-    step_program(s->h_desc[r.slot], cps, prog, slots);
+    step_program(s->h_desc[r.slot], cps, r.sweep, prog, slots);
     if (nseg + prog.size() > size_t(s->seg_cap)) break;   // the rest joins a later round
     const BatchState& st = s->h_states[r.slot];
     for (ServeSeg& g : prog) {
@@ -364,6 +422,8 @@ int launch_batched(adafac_server* s) {
       g.cur0 = st.cur;
       g.base = r.items_base;
     }
+    for (size_t k = 0; k < prog.size(); ++k)
+      if (prog[k].kind == SERVE_SWEEP) sweeps.push_back(SweepJob{size_t(slots[k]), prog[k], r.items_base == 0});
     r.items_base += (unsigned long long)steps * (unsigned long long)prog[0].per_step;
     nseg += prog.size();
     maxp = std::max(maxp, size_t(slots.back() + 1));
@@ -381,6 +441,7 @@ int launch_batched(adafac_server* s) {
     for (size_t k = 0; k < progs.size(); ++k)
       for (; at[k] < progs[k].size() && pslots[k][at[k]] == int(p); ++at[k]) {
         ServeSeg g = progs[k][at[k]];
+        if (g.kind == SERVE_SWEEP) continue;   // a launch of its own
         g.item0 = item;
         item += g.ntile;
         s->h_segs.push_back(g);
@@ -390,10 +451,16 @@ int launch_batched(adafac_server* s) {
   slot_off[maxp] = int(s->h_segs.size());
   SHIP(s, hipMemcpyAsync(s->d_segs, s->h_segs.data(), sizeof(ServeSeg) * s->h_segs.size(), hipMemcpyHostToDevice,
                          s->stream));
+  // Within a slot the shared launch goes first: an FP32_REFINED request's stopping rule shares
+  // the slot with its first inner sweep, which then sees the decision and does not overwrite the
+  // norm partials before they are read.
   for (int j = 0; j < steps; ++j)
-    for (size_t p = 0; p < maxp; ++p)
+    for (size_t p = 0; p < maxp; ++p) {
       SHIP(s, launch_serve_phase(s->d_reqs, s->d_states, s->d_segs + slot_off[p], slot_off[p + 1] - slot_off[p],
                                  slot_items[p], j, s->stream));
+      for (const SweepJob& w : sweeps)
+        if (w.p == p) SHIP(s, launch_sweep(s, w.g, j, w.first));
+    }
   s->b_flight = true;
   return ADAFAC_OK;
 }
@@ -528,6 +595,7 @@ int admit(adafac_server* s) {
       s->free_slots.pop_back();
       BatchReq& d = s->h_desc[r.slot];
       if ((rc = batch_describe(r.ctx, &d))) return sfail(s, rc, "batch_describe");
+      r.sweep = d.fusable && finest_vertices(r.dim, r.L) >= kSweepMinVerts;
       d.tol = r.tol;
       d.max_cycles = r.max_cycles;
       s->h_states[r.slot] = BatchState{};

@@ -1,7 +1,8 @@
 """Request server (continuous batching) through the C ABI.
 
-Every request, of any depth and dimension, advances in one persistent launch per round whose
-work items are the phases of all requests' cycles.  Checked here:
+Every request, of any depth and dimension, advances in shared phase-slot launches whose work
+items are the phases of all requests' cycles (the largest ones sweep their finest level in a
+launch of their own).  Checked here:
 
 - A served request gives the same iterate as the one-kernel-per-step solver.
 - Its cycle count and solution match the oracle.
@@ -149,6 +150,58 @@ def test_served_large_requests_match_oracle():
         assert abs(res["l2h"] - ho[-1][0]) <= 1e-12 * ho[0][0]
         assert err <= 1e-12
     assert out[2][0]["state"] == "converged"
+
+
+def test_served_swept_requests_match_oracle():
+    """Requests large enough to sweep their finest level in one pass (a launch of their own, the
+    prolongation into it left pending): 2D L = 6 under adAFAC-PI (the prolongation into level
+    L-1 subtracts I c_L) in FP64, capped at 3 cycles, exact against the oracle; and 2D L = 6 in
+    FP32 cycles inside FP64 defect correction (the outer step adds e + P S_{L-1}), capped at 3
+    outer steps, within 4x the oracle's own FP32-vs-FP64 spread."""
+    f = inp.rhs(2, 6, seed=67)
+    eps = inp.eps_blocks(2, 2, 3.0, seed=68)
+    say("case served swept requests")
+    reqs = [dict(dim=2, lmin=1, lmax=6, f=f, eps_blocks=eps, damping="pi", rel_tol=1e-12, max_cycles=3),
+            dict(dim=2, lmin=1, lmax=6, f=f, eps_blocks=eps, precision="fp32_refined", inner_k=4, rel_tol=1e-12,
+                 max_cycles=3)]
+    out = serve(reqs)
+    H = hierarchy.Hierarchy(2, 6, 1, eps)
+    b = H.rhs(f)
+    (res, u) = out[0]
+    assert res["state"] == "capped" and res["cycles"] == 3, res
+    uo, ho = cycle.solve(H, b, 3, damping="pi")
+    err = np.linalg.norm(u - uo) / np.linalg.norm(uo)
+    say(f"PI: rel. error {err:.3e}, l2h {res['l2h']:.6e} vs {ho[-1][0]:.6e}")
+    assert abs(res["l2h0"] - ho[0][0]) <= 1e-12 * ho[0][0]
+    assert abs(res["l2h"] - ho[-1][0]) <= 1e-12 * ho[0][0]
+    assert err <= 1e-12
+    (res, u) = out[1]
+    assert res["state"] == "capped" and res["cycles"] == 3, res
+    i32, i64 = [], []
+    _, h32, _ = cycle.defect_correction(H, b, 4, 0.0, 2, inner_dtype=np.float32, iterates=i32)
+    cycle.defect_correction(H, b, 4, 0.0, 2, inner_dtype=np.float64, iterates=i64)
+    A = H.lev[H.L].A
+    spread = cycle.norms(H, A(i32[2]) - A(i64[2]))[0]
+    say(f"FP32: l2h {res['l2h']:.6e} vs {h32[2][0]:.6e}, spread {spread:.2e}")
+    assert abs(res["l2h0"] - h32[0][0]) <= 1e-12 * h32[0][0]
+    assert abs(res["l2h"] - h32[2][0]) <= 4 * spread + 1e-12 * h32[0][0]
+    # the iterate, in the norm of the stopping rule: the served and the oracle's FP32 iterates
+    # differ by no more than 4x the oracle's own FP32 rounding (the 2-norm of the difference is
+    # dominated by smooth components that the two FP32 evaluations round differently; printed)
+    dr = cycle.norms(H, A(u) - A(i32[2]))[0]
+    err, sp = np.linalg.norm(u - i32[2]), np.linalg.norm(i32[2] - i64[2])
+    say(f"FP32: ||A(gpu - oracle32)||_h {dr:.3e}; 2-norm |gpu - oracle32| {err:.3e}, |oracle32 - oracle64| {sp:.3e}")
+    assert dr <= 4 * spread + 1e-12 * h32[0][0]
+    # and the served iterate is the one-request solver's (same single-pass sweep; its coarse
+    # levels differ only in rounding order)
+    from paper_1903_10367_amd import Solver
+    sv = Solver(2, 1, 6, f, eps_blocks=eps, precision="fp32_refined", inner_k=4)
+    sv.cycle(2)
+    us = sv.solution()
+    sv.close()
+    ds = np.linalg.norm(u - us)
+    say(f"FP32: |served - solver| {ds:.3e}")
+    assert ds <= 0.1 * sp + 1e-12 * np.linalg.norm(us)
 
 
 def test_admission_waits_for_memory_and_slots():
