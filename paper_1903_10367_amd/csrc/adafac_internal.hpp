@@ -141,8 +141,20 @@ struct BatchState {
 // PROLONG l = lmin+1..L for FP64; ADDE, DEFECT, FINAL, then per inner cycle FINE, LEVELs,
 // PROLONGs in FP32 for FP32_REFINED).  Large requests replace FINE by SWEEP, the single-pass
 // finest-level sweep launched on its own (it restricts to level L-1 and adds the previous
-// cycle's pending prolongation), and leave the prolongation into level L pending.
-enum { SERVE_FINE = 0, SERVE_FINAL, SERVE_LEVEL, SERVE_PROLONG, SERVE_ADDE, SERVE_DEFECT, SERVE_SWEEP };
+// cycle's pending prolongation), and leave the prolongation into level L pending; large 3D
+// FP32_REFINED requests replace ADDE and DEFECT by DEFECT3, the one-pass u' = u + e + P S_{L-1}
+// and FP64 defect of u' into the other FP64 buffer (also a launch of its own).
+enum { SERVE_FINE = 0, SERVE_FINAL, SERVE_LEVEL, SERVE_PROLONG, SERVE_ADDE, SERVE_DEFECT, SERVE_SWEEP, SERVE_DEFECT3 };
+constexpr bool serve_own_launch(int kind) { return kind == SERVE_SWEEP || kind == SERVE_DEFECT3; }
+
+// Kernel classes of the shared phase launches: a slot launches one kernel per class present.
+// Light: prolongations, ADDE, the stopping rule; level: the coarse FAS updates (5^d gathers);
+// stencil: the finest-level residuals (FINE, DEFECT).
+enum { SERVE_CLS_LIGHT = 0, SERVE_CLS_LEVEL, SERVE_CLS_STENCIL, SERVE_NCLS };
+constexpr int serve_class(int kind) {
+  return kind == SERVE_LEVEL ? SERVE_CLS_LEVEL
+                             : (kind == SERVE_FINE || kind == SERVE_DEFECT) ? SERVE_CLS_STENCIL : SERVE_CLS_LIGHT;
+}
 
 // One segment of a phase-slot launch's work list: the ntile items of one phase of one request.
 struct ServeSeg {
@@ -157,7 +169,8 @@ struct ServeSeg {
   int cur0;                  // FP64: iterate index at the round's start
   int cps;                   // FP64: cycles per step (sub numbers them); 1 otherwise
   int gather;                // LEVEL: 1 gathers R r, R~ r and I u from level + 1; 0: the sweep wrote them
-  int pend;                  // ADDE: adds the pending P S_{L-1} with e; PROLONG into L-1: subtracts I c_L
+  int pend;                  // ADDE: adds the pending P S_{L-1} with e; PROLONG into L-1: subtracts I c_L;
+                             // FINAL: the measured FP64 iterate is the other buffer (after DEFECT3)
   unsigned long long base;   // items of the request in earlier rounds (its sequence numbers start there)
 };
 

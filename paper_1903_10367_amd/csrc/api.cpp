@@ -47,7 +47,8 @@ hipError_t launch_coarse_sweep(int d, const LevelView<T>& L, const LevelView<T>&
 bool sweep_level_ok(int d, int n, int fem, bool has_pw);
 hipError_t launch_defect3d(const LevelView<double>& F, int nc, int nvc, const double* uin, double* uout,
                            const float* e, const float* S, const double* b, float* r32, double* partials,
-                           int mode, int* nparts, hipStream_t s);
+                           int mode, int* nparts, hipStream_t s, const unsigned long long* stop = nullptr,
+                           unsigned long long need = 0);
 template <typename T>
 hipError_t launch_small_levels(int d, const SmallLevelsArgs<T>& a, size_t lds_bytes, hipStream_t s);
 hipError_t launch_zero_fill(void* p, size_t bytes, hipStream_t s);
@@ -975,12 +976,13 @@ int residual_range(void* vc, int c0, int n, double* out) {
   return ADAFAC_OK;
 }
 
-// After batched cycles: ufine[cur] of the description holds the current FP64 iterate; pending:
+// After batched cycles: ufine[cur] of the description holds the current FP64 iterate (also
+// under FP32_REFINED, whose one-pass 3D defect alternates the two buffers); pending:
 // (FP64 form) the last cycle swept the finest level and left P S_{L-1} to be added.
 int batch_adopt(void* vc, int cur, int pending) {
   adafac_ctx* c = static_cast<adafac_ctx*>(vc);
   if (!c || !c->bound) return ADAFAC_ESTATE;
-  if (!mixed(c) && cur == 1) c->h64.cur = 1 - c->h64.cur;
+  if (cur == 1) c->h64.cur = 1 - c->h64.cur;
   c->h64.pending = c->h32.pending = c->e_pending = false;
   if (!mixed(c) && pending) c->h64.pending = true;
   return ADAFAC_OK;

@@ -851,6 +851,9 @@ struct Defect3dArgs {
   double* partials;
   double h, hd;
   int n, nv, nc, nvc, nb, bs, tz, ntx, ntz;
+  // request server: the launch does nothing once *stop <= need (the request stopped)
+  const unsigned long long* stop;
+  unsigned long long need;
 };
 
 namespace {
@@ -870,6 +873,7 @@ __global__ void __launch_bounds__(NTD, VAREPS ? 4 : ADAFAC_DEFECT3D_MINWAVES) k_
   __shared__ float Sb[MODE == 2 ? (MAXTZ / 3 + 3) * CW * CW : 1];
   __shared__ float Sz[3][CW * CW];
 
+  if (a.stop && a.need >= *a.stop) return;   // uniform over the launch
   const int n = a.n, nv = a.nv, nc = a.nc, nvc = a.nvc;
   const int plane = nv * nv;
   const unsigned latb = unsigned(size_t(plane) * nv * sizeof(double));
@@ -1244,11 +1248,13 @@ hipError_t launch_fine_sweep(int d, const LevelView<T>& F, const LevelView<T>& C
 // 2 u' = u + e + P S (d-linear P into the level).  *nparts receives the partial count.
 hipError_t launch_defect3d(const LevelView<double>& F, int nc, int nvc, const double* uin, double* uout,
                            const float* e, const float* S, const double* b, float* r32, double* partials,
-                           int mode, int* nparts, hipStream_t s) {
+                           int mode, int* nparts, hipStream_t s, const unsigned long long* stop,
+                           unsigned long long need) {
   const int n = F.n;
   if (n % TX) return hipErrorInvalidValue;
   const int ntx = n / TX, tz = pick_tz(n), ntz = n / tz;
-  Defect3dArgs a{uin, uout, e, S, b, r32, F.eps, partials, F.h, F.hd, n, F.nv, nc, nvc, F.nb, F.bs, tz, ntx, ntz};
+  Defect3dArgs a{uin,  uout, e,  S,  b,    r32,  F.eps, partials, F.h, F.hd, n,   F.nv,
+                 nc,   nvc,  F.nb, F.bs, tz, ntx, ntz,   stop,     need};
   const unsigned nb = unsigned(ntx * ntx * ntz);
   const bool var = F.eps != nullptr;
   if (mode == 2) {

@@ -229,13 +229,16 @@ __device__ void final_item(const BatchReq& R, BatchState& S, const ServeSeg& g, 
   S.cycles += 1;
   if (!st && S.cycles >= R.max_cycles) st = 3;
   S.status = st;
-  if (R.precision == ADAFAC_PREC_FP64) S.cur = g.cur0 ^ ((j * g.cps + g.sub + 1) & 1);   // the iterate it produces
+  // the iterate it produces (FP64), or the one it measured (after the one-pass 3D defect)
+  if (R.precision == ADAFAC_PREC_FP64 || g.pend) S.cur = g.cur0 ^ ((j * g.cps + g.sub + 1) & 1);
   // FP64: the rest of this cycle still runs (it produces the result); FP32_REFINED: the outer
   // iterate just measured is the result
   if (st) S.stop_need = need + 1 + (unsigned long long)g.run_after;
 }
 
-template <int D>
+// CLS: the kernel class (serve_class) whose phase kinds this instance compiles; each class has
+// its own register budget, so that the light phases are not held to the heaviest one's occupancy.
+template <int D, int CLS>
 __device__ void run_item(const BatchReq& R, BatchState& S, const ServeSeg& g, int j, unsigned long long need, int t,
                          double* ws, double* wm, double* red) {
   const int L = R.L;
@@ -252,8 +255,10 @@ __device__ void run_item(const BatchReq& R, BatchState& S, const ServeSeg& g, in
   const unsigned q0 = unsigned(t) * unsigned(g.tile);
   const unsigned q1 = unsigned(min(size_t(q0) + size_t(g.tile), nrows_of<D>(nvl)));
   double s = 0.0, m = 0.0;
+  if (serve_class(g.kind) != CLS) return;
   switch (g.kind) {
     case SERVE_FINE:
+      if constexpr (CLS != SERVE_CLS_STENCIL) break;
       if (fp64) {
         fine_items<double, D>(R, R.h64, u64in, u64out, q0, q1, s, m);
         wg_partials(s, m, R.partials + 2 * t, ws, wm);
@@ -262,6 +267,7 @@ __device__ void run_item(const BatchReq& R, BatchState& S, const ServeSeg& g, in
       }
       break;
     case SERVE_LEVEL: {
+      if constexpr (CLS != SERVE_CLS_LEVEL) break;
       const size_t v0 = size_t(t) * size_t(g.tile);
       const size_t v1 = min(v0 + size_t(g.tile), nverts_of<D>(nvl));
       if (fp64) level_items<double, D>(R, R.h64, u64in, g.level, g.gather, v0, v1);
@@ -269,18 +275,22 @@ __device__ void run_item(const BatchReq& R, BatchState& S, const ServeSeg& g, in
       break;
     }
     case SERVE_PROLONG:
+      if constexpr (CLS != SERVE_CLS_LIGHT) break;
       if (fp64) prolong_items<double, D>(R, R.h64, u64out, g.level, g.pend, q0, q1);
       else prolong_items<float, D>(R, R.h32, u32out, g.level, g.pend, q0, q1);
       break;
     case SERVE_ADDE:
+      if constexpr (CLS != SERVE_CLS_LIGHT) break;
       // the correction of the previous outer step (none before the first)
       if (S.cycles > 0) adde_items<D>(R, R.h32.ufine[R.inner_k & 1], g.pend, q0, q1);
       break;
     case SERVE_DEFECT:
+      if constexpr (CLS != SERVE_CLS_STENCIL) break;
       defect_items<D>(R, q0, q1, s, m);
       wg_partials(s, m, R.partials + 2 * t, ws, wm);
       break;
     case SERVE_FINAL:
+      if constexpr (CLS != SERVE_CLS_LIGHT) break;
       final_item(R, S, g, j, need, ws, wm, red);
       break;
     default:
@@ -289,8 +299,10 @@ __device__ void run_item(const BatchReq& R, BatchState& S, const ServeSeg& g, in
   (void)L;
 }
 
-// One phase slot of one step of every batched request: workgroup b runs item b of the slot's
-// work list (segments ordered by request, items numbered within the slot).
+// One phase slot of one step of every batched request, the phases of one kernel class:
+// workgroup b runs item b of the class's work list (segments ordered by request, items numbered
+// within the list).
+template <int CLS>
 __global__ void __launch_bounds__(NTS) k_serve_phase(const BatchReq* __restrict__ reqs, BatchState* states,
                                                      const ServeSeg* __restrict__ segs, int nseg, int j) {
   __shared__ double ws[NTS / 64], wm[NTS / 64], red[2];
@@ -311,17 +323,25 @@ __global__ void __launch_bounds__(NTS) k_serve_phase(const BatchReq* __restrict_
   const unsigned long long need = g.base + (unsigned long long)j * (unsigned long long)g.per_step +
                                   (unsigned long long)g.need_off + (unsigned long long)t;
   if (need >= S.stop_need) return;
-  if (R.dim == 2) run_item<2>(R, S, g, j, need, t, ws, wm, red);
-  else run_item<3>(R, S, g, j, need, t, ws, wm, red);
+  if (R.dim == 2) run_item<2, CLS>(R, S, g, j, need, t, ws, wm, red);
+  else run_item<3, CLS>(R, S, g, j, need, t, ws, wm, red);
 }
 
 }  // namespace
 
-// Phase slot launch: nitems workgroups over the slot's nseg segments, step j of the round.
-hipError_t launch_serve_phase(const BatchReq* reqs, BatchState* states, const ServeSeg* segs, int nseg, int nitems,
-                              int j, hipStream_t s) {
+// Phase slot launch of kernel class cls: nitems workgroups over its nseg segments, step j of the
+// round.
+hipError_t launch_serve_phase(int cls, const BatchReq* reqs, BatchState* states, const ServeSeg* segs, int nseg,
+                              int nitems, int j, hipStream_t s) {
   if (nseg <= 0 || nitems <= 0) return hipSuccess;
-  k_serve_phase<<<nitems, NTS, 0, s>>>(reqs, states, segs, nseg, j);
+  switch (cls) {
+    case SERVE_CLS_LIGHT: k_serve_phase<SERVE_CLS_LIGHT><<<nitems, NTS, 0, s>>>(reqs, states, segs, nseg, j); break;
+    case SERVE_CLS_LEVEL: k_serve_phase<SERVE_CLS_LEVEL><<<nitems, NTS, 0, s>>>(reqs, states, segs, nseg, j); break;
+    case SERVE_CLS_STENCIL:
+      k_serve_phase<SERVE_CLS_STENCIL><<<nitems, NTS, 0, s>>>(reqs, states, segs, nseg, j);
+      break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

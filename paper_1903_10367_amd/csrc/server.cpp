@@ -22,14 +22,18 @@
 #include "adafac_internal.hpp"
 
 namespace adafac {
-hipError_t launch_serve_phase(const BatchReq* reqs, BatchState* states, const ServeSeg* segs, int nseg, int nitems,
-                              int j, hipStream_t s);
+hipError_t launch_serve_phase(int cls, const BatchReq* reqs, BatchState* states, const ServeSeg* segs, int nseg,
+                              int nitems, int j, hipStream_t s);
 template <typename T>
 hipError_t launch_fine_sweep(int d, const LevelView<T>& F, const LevelView<T>& C, const T* uin, T* uout,
                              const T* b, const RtSep<T>& rt, T omega, int damping, int apply_pending,
                              double* partials, int* nparts, hipStream_t s, const unsigned long long* stop,
                              unsigned long long need);
 int fine_sweep_nparts(int d, int n);
+hipError_t launch_defect3d(const LevelView<double>& F, int nc, int nvc, const double* uin, double* uout,
+                           const float* e, const float* S, const double* b, float* r32, double* partials,
+                           int mode, int* nparts, hipStream_t s, const unsigned long long* stop,
+                           unsigned long long need);
 }  // namespace adafac
 
 using namespace adafac;
@@ -41,7 +45,7 @@ constexpr int kSegsPerSlot = 48;   // work-list segments held per request slot (
 // vertices per work item (whole lattice rows for the row-based phases): finest-level phases (at
 // most kNormBlocks items, one norm partial each), coarse FAS updates (5^d gathers per vertex)
 // and prolongations
-constexpr size_t kFineItem = 2048, kLevelItem = 1024, kProlongItem = 4096;
+constexpr size_t kFineItem = 2048, kLevelItem = 256, kProlongItem = 2048;
 // requests with at least this many finest-level vertices sweep that level in one pass (when
 // their options allow it): a launch of its own, which the smaller requests' phases do not share
 constexpr size_t kSweepMinVerts = size_t(1) << 18;
@@ -331,6 +335,11 @@ void step_program(const BatchReq& d, int cps, bool sweep, std::vector<ServeSeg>&
   };
   if (fp64) {
     for (int c = 0; c < cps; ++c) cycle_phases(c);
+  } else if (sweep && d.dim == 3) {
+    add(SERVE_DEFECT3, d.L, 0, 1, 1);
+    add(SERVE_FINAL, d.L, 0, 1, 1);
+    prog.back().pend = 1;
+    for (int i = 0; i < d.inner_k; ++i) cycle_phases(i);
   } else {
     add(SERVE_ADDE, d.L, 0, rL, tf);
     prog.back().pend = sweep ? 1 : 0;
@@ -351,22 +360,33 @@ void step_program(const BatchReq& d, int cps, bool sweep, std::vector<ServeSeg>&
     g.per_step = off;
     g.cps = fp64 ? cps : 1;
     if (g.kind == SERVE_FINAL) {
-      g.nparts = (fp64 && sweep) ? fine_sweep_nparts(d.dim, ipow3(d.L)) : nf;
+      // the one-pass sweep and defect cut the finest level into the same tiles
+      g.nparts = (sweep && (fp64 || d.dim == 3)) ? fine_sweep_nparts(d.dim, ipow3(d.L)) : nf;
       // FP64: the rest of its cycle still runs when it stops (that cycle produces the result)
       g.run_after = fp64 ? (g.sub + 1) * per_cycle - (g.need_off + 1) : 0;
     }
   }
 }
 
-// The single-pass finest-level sweep of segment g (kind SWEEP) in step j: it does nothing when the
-// request stopped before this item of its sequence.
-hipError_t launch_sweep(adafac_server* s, const ServeSeg& g, int j, bool first) {
+// The phases with launches of their own (serve_own_launch), segment g in step j: each does
+// nothing when the request stopped before this item of its sequence.  SWEEP: the single-pass
+// finest-level sweep.  DEFECT3: u' = u + e + P S_{L-1} (nothing added before the first outer
+// step) and the FP64 defect of u', into the other FP64 buffer.
+hipError_t launch_own(adafac_server* s, const ServeSeg& g, int j, bool first) {
   const BatchReq& d = s->h_desc[g.req];
   const int L = d.L;
   const unsigned long long need =
       g.base + (unsigned long long)j * (unsigned long long)g.per_step + (unsigned long long)g.need_off;
   const unsigned long long* stop = &s->d_states[g.req].stop_need;
   int np = 0;
+  if (g.kind == SERVE_DEFECT3) {
+    const int cur = g.cur0 ^ (j & 1);
+    const int mode = (first && j == 0) ? 0 : 2;
+    const LevelView<float>& C = d.h32.v[L - 1];
+    return launch_defect3d(d.h64.v[L], C.n, C.nv, d.h64.ufine[cur], d.h64.ufine[1 - cur], d.h32.ufine[d.inner_k & 1],
+                           mode == 2 ? C.S : nullptr, d.h64.bfine, d.h32.bfine, d.partials, mode, &np, s->stream,
+                           stop, need);
+  }
   if (d.precision == ADAFAC_PREC_FP64) {
     const int cur = g.cur0 ^ ((j * g.cps + g.sub) & 1);
     const double* uin = d.h64.ufine[cur];
@@ -423,7 +443,7 @@ int launch_batched(adafac_server* s) {
       g.base = r.items_base;
     }
     for (size_t k = 0; k < prog.size(); ++k)
-      if (prog[k].kind == SERVE_SWEEP) sweeps.push_back(SweepJob{size_t(slots[k]), prog[k], r.items_base == 0});
+      if (serve_own_launch(prog[k].kind)) sweeps.push_back(SweepJob{size_t(slots[k]), prog[k], r.items_base == 0});
     r.items_base += (unsigned long long)steps * (unsigned long long)prog[0].per_step;
     nseg += prog.size();
     maxp = std::max(maxp, size_t(slots.back() + 1));
@@ -432,34 +452,48 @@ int launch_batched(adafac_server* s) {
     s->b_members.push_back(t);
   }
   if (s->b_members.empty()) return ADAFAC_OK;
+  // work lists: per slot, one per kernel class (list q = p * SERVE_NCLS + class)
   s->h_segs.clear();
-  std::vector<int> slot_off(maxp + 1, 0), slot_items(maxp, 0);
+  const size_t nlist = maxp * SERVE_NCLS;
+  std::vector<int> list_off(nlist + 1, 0), list_items(nlist, 0);
   std::vector<size_t> at(progs.size(), 0);   // next phase of each request
   for (size_t p = 0; p < maxp; ++p) {
-    slot_off[p] = int(s->h_segs.size());
-    int item = 0;
-    for (size_t k = 0; k < progs.size(); ++k)
-      for (; at[k] < progs[k].size() && pslots[k][at[k]] == int(p); ++at[k]) {
-        ServeSeg g = progs[k][at[k]];
-        if (g.kind == SERVE_SWEEP) continue;   // a launch of its own
-        g.item0 = item;
-        item += g.ntile;
-        s->h_segs.push_back(g);
+    const std::vector<size_t> at0 = at;
+    for (int cls = 0; cls < SERVE_NCLS; ++cls) {
+      const size_t q = p * SERVE_NCLS + size_t(cls);
+      list_off[q] = int(s->h_segs.size());
+      int item = 0;
+      for (size_t k = 0; k < progs.size(); ++k) {
+        size_t a = at0[k];
+        for (; a < progs[k].size() && pslots[k][a] == int(p); ++a) {
+          ServeSeg g = progs[k][a];
+          if (serve_own_launch(g.kind) || serve_class(g.kind) != cls) continue;   // a launch of its own
+          g.item0 = item;
+          item += g.ntile;
+          s->h_segs.push_back(g);
+        }
+        at[k] = a;
       }
-    slot_items[p] = item;
+      list_items[q] = item;
+    }
   }
-  slot_off[maxp] = int(s->h_segs.size());
+  list_off[nlist] = int(s->h_segs.size());
   SHIP(s, hipMemcpyAsync(s->d_segs, s->h_segs.data(), sizeof(ServeSeg) * s->h_segs.size(), hipMemcpyHostToDevice,
                          s->stream));
-  // Within a slot the shared launch goes first: an FP32_REFINED request's stopping rule shares
+  // Within a slot the shared launches go first: an FP32_REFINED request's stopping rule shares
   // the slot with its first inner sweep, which then sees the decision and does not overwrite the
-  // norm partials before they are read.
+  // norm partials before they are read.  The phases of a slot are independent of one another
+  // (different requests, or a request's stopping rule and the phase after it, which does not
+  // read its result), so the order of the class launches does not matter.
   for (int j = 0; j < steps; ++j)
     for (size_t p = 0; p < maxp; ++p) {
-      SHIP(s, launch_serve_phase(s->d_reqs, s->d_states, s->d_segs + slot_off[p], slot_off[p + 1] - slot_off[p],
-                                 slot_items[p], j, s->stream));
+      for (int cls = 0; cls < SERVE_NCLS; ++cls) {
+        const size_t q = p * SERVE_NCLS + size_t(cls);
+        SHIP(s, launch_serve_phase(cls, s->d_reqs, s->d_states, s->d_segs + list_off[q], list_off[q + 1] - list_off[q],
+                                   list_items[q], j, s->stream));
+      }
       for (const SweepJob& w : sweeps)
-        if (w.p == p) SHIP(s, launch_sweep(s, w.g, j, w.first));
+        if (w.p == p) SHIP(s, launch_own(s, w.g, j, w.first));
     }
   s->b_flight = true;
   return ADAFAC_OK;

@@ -152,17 +152,55 @@ def test_served_large_requests_match_oracle():
     assert out[2][0]["state"] == "converged"
 
 
+def _check_swept_fp32(res, u, d, L, f, eps, k):
+    """A served FP32_REFINED request capped at 3 outer steps against the oracle's iterate after 2
+    outer steps (FP32 inner cycles) and against the one-request solver."""
+    assert res["state"] == "capped" and res["cycles"] == 3, res
+    H = hierarchy.Hierarchy(d, L, 1, eps)
+    b = H.rhs(f)
+    i32, i64 = [], []
+    _, h32, _ = cycle.defect_correction(H, b, k, 0.0, 2, inner_dtype=np.float32, iterates=i32)
+    cycle.defect_correction(H, b, k, 0.0, 2, inner_dtype=np.float64, iterates=i64)
+    A = H.lev[H.L].A
+    spread = cycle.norms(H, A(i32[2]) - A(i64[2]))[0]
+    say(f"FP32 {d}D L={L}: l2h {res['l2h']:.6e} vs {h32[2][0]:.6e}, spread {spread:.2e}")
+    assert abs(res["l2h0"] - h32[0][0]) <= 1e-12 * h32[0][0]
+    assert abs(res["l2h"] - h32[2][0]) <= 4 * spread + 1e-12 * h32[0][0]
+    # the iterate, in the norm of the stopping rule: the served and the oracle's FP32 iterates
+    # differ by no more than 4x the oracle's own FP32 rounding (the 2-norm of the difference is
+    # dominated by smooth components that the two FP32 evaluations round differently; printed)
+    dr = cycle.norms(H, A(u) - A(i32[2]))[0]
+    err, sp = np.linalg.norm(u - i32[2]), np.linalg.norm(i32[2] - i64[2])
+    say(f"  ||A(gpu - oracle32)||_h {dr:.3e}; 2-norm |gpu - oracle32| {err:.3e}, |oracle32 - oracle64| {sp:.3e}")
+    assert dr <= 4 * spread + 1e-12 * h32[0][0]
+    # the served iterate is the one-request solver's (same one-pass kernels on the finest level;
+    # the coarse levels differ at most in rounding order)
+    from paper_1903_10367_amd import Solver
+    sv = Solver(d, 1, L, f, eps_blocks=eps, precision="fp32_refined", inner_k=k)
+    sv.cycle(2)
+    us = sv.solution()
+    sv.close()
+    ds = np.linalg.norm(u - us)
+    say(f"  |served - solver| {ds:.3e}")
+    assert ds <= 0.1 * sp + 1e-12 * np.linalg.norm(us)
+
+
 def test_served_swept_requests_match_oracle():
     """Requests large enough to sweep their finest level in one pass (a launch of their own, the
     prolongation into it left pending): 2D L = 6 under adAFAC-PI (the prolongation into level
-    L-1 subtracts I c_L) in FP64, capped at 3 cycles, exact against the oracle; and 2D L = 6 in
-    FP32 cycles inside FP64 defect correction (the outer step adds e + P S_{L-1}), capped at 3
-    outer steps, within 4x the oracle's own FP32-vs-FP64 spread."""
+    L-1 subtracts I c_L) in FP64, capped at 3 cycles, exact against the oracle; 2D L = 6 in FP32
+    cycles inside FP64 defect correction (the outer step adds e + P S_{L-1}) and 3D L = 4 in the
+    same precision (the outer step in one pass, u + e + P S_{L-1} and the FP64 defect, into the
+    other FP64 buffer), each capped at 3 outer steps."""
     f = inp.rhs(2, 6, seed=67)
     eps = inp.eps_blocks(2, 2, 3.0, seed=68)
+    f3 = inp.rhs(3, 4, seed=69)
+    eps3 = inp.eps_blocks(3, 3, 4.0, seed=70)
     say("case served swept requests")
     reqs = [dict(dim=2, lmin=1, lmax=6, f=f, eps_blocks=eps, damping="pi", rel_tol=1e-12, max_cycles=3),
             dict(dim=2, lmin=1, lmax=6, f=f, eps_blocks=eps, precision="fp32_refined", inner_k=4, rel_tol=1e-12,
+                 max_cycles=3),
+            dict(dim=3, lmin=1, lmax=4, f=f3, eps_blocks=eps3, precision="fp32_refined", inner_k=4, rel_tol=1e-12,
                  max_cycles=3)]
     out = serve(reqs)
     H = hierarchy.Hierarchy(2, 6, 1, eps)
@@ -175,33 +213,8 @@ def test_served_swept_requests_match_oracle():
     assert abs(res["l2h0"] - ho[0][0]) <= 1e-12 * ho[0][0]
     assert abs(res["l2h"] - ho[-1][0]) <= 1e-12 * ho[0][0]
     assert err <= 1e-12
-    (res, u) = out[1]
-    assert res["state"] == "capped" and res["cycles"] == 3, res
-    i32, i64 = [], []
-    _, h32, _ = cycle.defect_correction(H, b, 4, 0.0, 2, inner_dtype=np.float32, iterates=i32)
-    cycle.defect_correction(H, b, 4, 0.0, 2, inner_dtype=np.float64, iterates=i64)
-    A = H.lev[H.L].A
-    spread = cycle.norms(H, A(i32[2]) - A(i64[2]))[0]
-    say(f"FP32: l2h {res['l2h']:.6e} vs {h32[2][0]:.6e}, spread {spread:.2e}")
-    assert abs(res["l2h0"] - h32[0][0]) <= 1e-12 * h32[0][0]
-    assert abs(res["l2h"] - h32[2][0]) <= 4 * spread + 1e-12 * h32[0][0]
-    # the iterate, in the norm of the stopping rule: the served and the oracle's FP32 iterates
-    # differ by no more than 4x the oracle's own FP32 rounding (the 2-norm of the difference is
-    # dominated by smooth components that the two FP32 evaluations round differently; printed)
-    dr = cycle.norms(H, A(u) - A(i32[2]))[0]
-    err, sp = np.linalg.norm(u - i32[2]), np.linalg.norm(i32[2] - i64[2])
-    say(f"FP32: ||A(gpu - oracle32)||_h {dr:.3e}; 2-norm |gpu - oracle32| {err:.3e}, |oracle32 - oracle64| {sp:.3e}")
-    assert dr <= 4 * spread + 1e-12 * h32[0][0]
-    # and the served iterate is the one-request solver's (same single-pass sweep; its coarse
-    # levels differ only in rounding order)
-    from paper_1903_10367_amd import Solver
-    sv = Solver(2, 1, 6, f, eps_blocks=eps, precision="fp32_refined", inner_k=4)
-    sv.cycle(2)
-    us = sv.solution()
-    sv.close()
-    ds = np.linalg.norm(u - us)
-    say(f"FP32: |served - solver| {ds:.3e}")
-    assert ds <= 0.1 * sp + 1e-12 * np.linalg.norm(us)
+    _check_swept_fp32(*out[1], 2, 6, f, eps, 4)
+    _check_swept_fp32(*out[2], 3, 4, f3, eps3, 4)
 
 
 def test_admission_waits_for_memory_and_slots():
