@@ -341,20 +341,23 @@ int adafac_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
  * yet), when an active slot is free and its exact device footprint (the
  * adafac_workspace_bytes of its hierarchy) fits in the free pool.  Each
  * scheduling round (adafac_server_step) does three things:
- *  - harvests the previous round;
- *  - advances every active request by up to cycles_per_round cycles (outer
- *    steps for FP32_REFINED);
- *  - admits, uploading while that round runs; admitted requests join the next
- *    round.
+ *  - harvests the oldest round in flight once it has completed;
+ *  - admits, uploading while the device runs the other round in flight;
+ *  - enqueues rounds until two are in flight: each advances every active
+ *    request by up to cycles_per_round cycles (outer steps for FP32_REFINED).
+ *    A request admitted now joins the next round enqueued.
  * All active requests, of any depth and dimension, advance together in shared
  * launches.  A request's cycle is a chain of phases (finest-level residual and
  * Jacobi step, the residual norms and stopping rule, the FAS update of each
  * coarser level, the prolongations back up), each cut into work items of a few
  * thousand vertices; one launch runs the same phase slot of every request's
  * chain, so requests of every size share each launch and the launch count per
- * round (cycles_per_round x the longest chain) does not grow with the number
- * of requests.  A request stops exactly at the first iterate that meets the
- * tolerance.  Requests above batch_max_vertices finest vertices (default:
+ * round (cycles_per_round x the longest chain, times at most three kernel
+ * classes) does not grow with the number of requests.  Requests of at least
+ * 2^18 finest vertices sweep their finest level in one pass instead, in a
+ * launch of their own within the same slot.  A request stops exactly at the
+ * first iterate that meets the tolerance (the stopping rule runs on the
+ * device; the request's work in a round enqueued after that does nothing).  Requests above batch_max_vertices finest vertices (default:
  * none) advance on streams of their own instead and stop at the end of the
  * round in which they converged.  A finished request's solution is copied to
  * host memory and its device memory and slot are freed.  A request's
@@ -417,10 +420,10 @@ int adafac_server_create(const adafac_server_cfg* cfg, void* dev_workspace, size
  * ADAFAC_EAGAIN when max_queued requests wait already. */
 int adafac_server_submit(adafac_server* srv, const adafac_request* req, uint64_t* ticket);
 
-/* One scheduling round: wait for the previous round, harvest finished
- * requests, admit, launch.  *active (may be NULL) receives the number of
- * requests on the device after admission, *queued (may be NULL) the number
- * waiting.  Returns after enqueuing the round. */
+/* One scheduling round: wait (briefly) for the oldest round in flight, harvest
+ * finished requests, admit, enqueue rounds up to two in flight.  *active (may
+ * be NULL) receives the number of requests on the device after admission,
+ * *queued (may be NULL) the number waiting.  Returns after enqueuing. */
 int adafac_server_step(adafac_server* srv, int* active, int* queued);
 
 /* State of a ticket (no GPU synchronisation).  EINVAL for an unknown ticket. */

@@ -144,16 +144,25 @@ struct BatchState {
 // cycle's pending prolongation), and leave the prolongation into level L pending; large 3D
 // FP32_REFINED requests replace ADDE and DEFECT by DEFECT3, the one-pass u' = u + e + P S_{L-1}
 // and FP64 defect of u' into the other FP64 buffer (also a launch of its own).
-enum { SERVE_FINE = 0, SERVE_FINAL, SERVE_LEVEL, SERVE_PROLONG, SERVE_ADDE, SERVE_DEFECT, SERVE_SWEEP, SERVE_DEFECT3 };
+// A request's coarsest levels, up to `level` (each of at most kServeSmallVerts vertices), are one
+// SMALL item: one workgroup runs their FAS updates (coarsest last) and then their
+// prolongations, with a workgroup barrier between levels, as the per-level phases would.
+enum {
+  SERVE_FINE = 0, SERVE_FINAL, SERVE_LEVEL, SERVE_PROLONG, SERVE_ADDE, SERVE_DEFECT, SERVE_SWEEP, SERVE_DEFECT3,
+  SERVE_SMALL
+};
+constexpr size_t kServeSmallVerts = 1024;
 constexpr bool serve_own_launch(int kind) { return kind == SERVE_SWEEP || kind == SERVE_DEFECT3; }
 
 // Kernel classes of the shared phase launches: a slot launches one kernel per class present.
-// Light: prolongations, ADDE, the stopping rule; level: the coarse FAS updates (5^d gathers);
-// stencil: the finest-level residuals (FINE, DEFECT).
-enum { SERVE_CLS_LIGHT = 0, SERVE_CLS_LEVEL, SERVE_CLS_STENCIL, SERVE_NCLS };
+// Light: prolongations and ADDE; heavy: the finest-level residuals (FINE, DEFECT), the coarse
+// FAS updates (5^d gathers) and the stopping rule (which shares its slot with a heavy phase);
+// small: the SMALL items (in the last restriction slot; a class of their own, since the two
+// kernels together would spill).
+enum { SERVE_CLS_LIGHT = 0, SERVE_CLS_HEAVY, SERVE_CLS_SMALL, SERVE_NCLS };
 constexpr int serve_class(int kind) {
-  return kind == SERVE_LEVEL ? SERVE_CLS_LEVEL
-                             : (kind == SERVE_FINE || kind == SERVE_DEFECT) ? SERVE_CLS_STENCIL : SERVE_CLS_LIGHT;
+  return (kind == SERVE_PROLONG || kind == SERVE_ADDE) ? SERVE_CLS_LIGHT
+                                                       : kind == SERVE_SMALL ? SERVE_CLS_SMALL : SERVE_CLS_HEAVY;
 }
 
 // One segment of a phase-slot launch's work list: the ntile items of one phase of one request.
@@ -168,8 +177,10 @@ struct ServeSeg {
   int run_after;             // FINAL: items of the request after it that still run when it stops
   int cur0;                  // FP64: iterate index at the round's start
   int cps;                   // FP64: cycles per step (sub numbers them); 1 otherwise
-  int gather;                // LEVEL: 1 gathers R r, R~ r and I u from level + 1; 0: the sweep wrote them
-  int pend;                  // ADDE: adds the pending P S_{L-1} with e; PROLONG into L-1: subtracts I c_L;
+  int gather;                // LEVEL, SMALL (its top level): 1 gathers R r, R~ r and I u from level + 1;
+                             // 0: the sweep wrote them
+  int pend;                  // ADDE: adds the pending P S_{L-1} with e; PROLONG into L-1 (SMALL: when it
+                             // reaches L-1): subtracts I c_L;
                              // FINAL: the measured FP64 iterate is the other buffer (after DEFECT3)
   unsigned long long base;   // items of the request in earlier rounds (its sequence numbers start there)
 };

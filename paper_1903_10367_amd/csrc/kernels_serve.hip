@@ -120,7 +120,7 @@ __device__ void fine_items(const BatchReq& R, const BatchHier<T>& H, const T* ui
 // FAS update of level l on vertices [v0, v1) (gathering R r, R~ r and I u from level l + 1, or
 // with them already written by the finest-level sweep).
 template <typename T, int D>
-__device__ void level_items(const BatchReq& R, const BatchHier<T>& H, const T* uin, int l, int gather, size_t v0,
+__device__ __forceinline__ void level_items(const BatchReq& R, const BatchHier<T>& H, const T* uin, int l, int gather, size_t v0,
                             size_t v1) {
   const int L = R.L;
   LevelView<T> Fv = H.v[l + 1];
@@ -138,7 +138,7 @@ __device__ void level_items(const BatchReq& R, const BatchHier<T>& H, const T* u
 // adAFAC-PI with the finest level swept, level L-1 also subtracts I c_L, which the sweep stored
 // there, so that the pending P S_{L-1} is P (S_{L-1} - I c_L).
 template <typename T, int D>
-__device__ void prolong_items(const BatchReq& R, const BatchHier<T>& H, T* uout, int l, int self, unsigned q0,
+__device__ __forceinline__ void prolong_items(const BatchReq& R, const BatchHier<T>& H, T* uout, int l, int self, unsigned q0,
                               unsigned q1) {
   const bool pi = R.damping == ADAFAC_DAMP_PI;
   const LevelView<T>& F = H.v[l];
@@ -156,6 +156,23 @@ __device__ void prolong_items(const BatchReq& R, const BatchHier<T>& H, T* uout,
       if (self) v -= F.ic[i];
       dst[i] += v;
     }
+  }
+}
+
+// The FAS updates of levels hi .. l_min and the prolongations into levels l_min + 1 .. hi, in
+// that order, by one workgroup (a barrier after each level): the per-vertex arithmetic of
+// level_items and prolong_items.  gather_hi: level hi gathers from level hi + 1; self: the
+// prolongation into level L-1 subtracts I c_L.
+template <typename T, int D>
+__device__ void small_items(const BatchReq& R, const BatchHier<T>& H, const T* uin, T* uout, int hi, int gather_hi,
+                            int self) {
+  for (int l = hi; l >= R.lmin; --l) {
+    level_items<T, D>(R, H, uin, l, l == hi ? gather_hi : 1, 0, nverts_of<D>(H.v[l].nv));
+    __syncthreads();
+  }
+  for (int l = R.lmin + 1; l <= hi; ++l) {
+    prolong_items<T, D>(R, H, uout, l, (self && l == R.L - 1) ? 1 : 0, 0u, unsigned(nrows_of<D>(H.v[l].nv)));
+    __syncthreads();
   }
 }
 
@@ -258,7 +275,7 @@ __device__ void run_item(const BatchReq& R, BatchState& S, const ServeSeg& g, in
   if (serve_class(g.kind) != CLS) return;
   switch (g.kind) {
     case SERVE_FINE:
-      if constexpr (CLS != SERVE_CLS_STENCIL) break;
+      if constexpr (CLS != SERVE_CLS_HEAVY) break;
       if (fp64) {
         fine_items<double, D>(R, R.h64, u64in, u64out, q0, q1, s, m);
         wg_partials(s, m, R.partials + 2 * t, ws, wm);
@@ -267,13 +284,18 @@ __device__ void run_item(const BatchReq& R, BatchState& S, const ServeSeg& g, in
       }
       break;
     case SERVE_LEVEL: {
-      if constexpr (CLS != SERVE_CLS_LEVEL) break;
+      if constexpr (CLS != SERVE_CLS_HEAVY) break;
       const size_t v0 = size_t(t) * size_t(g.tile);
       const size_t v1 = min(v0 + size_t(g.tile), nverts_of<D>(nvl));
       if (fp64) level_items<double, D>(R, R.h64, u64in, g.level, g.gather, v0, v1);
       else level_items<float, D>(R, R.h32, u32in, g.level, g.gather, v0, v1);
       break;
     }
+    case SERVE_SMALL:
+      if constexpr (CLS != SERVE_CLS_SMALL) break;
+      if (fp64) small_items<double, D>(R, R.h64, u64in, u64out, g.level, g.gather, g.pend);
+      else small_items<float, D>(R, R.h32, u32in, u32out, g.level, g.gather, g.pend);
+      break;
     case SERVE_PROLONG:
       if constexpr (CLS != SERVE_CLS_LIGHT) break;
       if (fp64) prolong_items<double, D>(R, R.h64, u64out, g.level, g.pend, q0, q1);
@@ -285,12 +307,12 @@ __device__ void run_item(const BatchReq& R, BatchState& S, const ServeSeg& g, in
       if (S.cycles > 0) adde_items<D>(R, R.h32.ufine[R.inner_k & 1], g.pend, q0, q1);
       break;
     case SERVE_DEFECT:
-      if constexpr (CLS != SERVE_CLS_STENCIL) break;
+      if constexpr (CLS != SERVE_CLS_HEAVY) break;
       defect_items<D>(R, q0, q1, s, m);
       wg_partials(s, m, R.partials + 2 * t, ws, wm);
       break;
     case SERVE_FINAL:
-      if constexpr (CLS != SERVE_CLS_LIGHT) break;
+      if constexpr (CLS != SERVE_CLS_HEAVY) break;
       final_item(R, S, g, j, need, ws, wm, red);
       break;
     default:
@@ -336,10 +358,8 @@ hipError_t launch_serve_phase(int cls, const BatchReq* reqs, BatchState* states,
   if (nseg <= 0 || nitems <= 0) return hipSuccess;
   switch (cls) {
     case SERVE_CLS_LIGHT: k_serve_phase<SERVE_CLS_LIGHT><<<nitems, NTS, 0, s>>>(reqs, states, segs, nseg, j); break;
-    case SERVE_CLS_LEVEL: k_serve_phase<SERVE_CLS_LEVEL><<<nitems, NTS, 0, s>>>(reqs, states, segs, nseg, j); break;
-    case SERVE_CLS_STENCIL:
-      k_serve_phase<SERVE_CLS_STENCIL><<<nitems, NTS, 0, s>>>(reqs, states, segs, nseg, j);
-      break;
+    case SERVE_CLS_HEAVY: k_serve_phase<SERVE_CLS_HEAVY><<<nitems, NTS, 0, s>>>(reqs, states, segs, nseg, j); break;
+    case SERVE_CLS_SMALL: k_serve_phase<SERVE_CLS_SMALL><<<nitems, NTS, 0, s>>>(reqs, states, segs, nseg, j); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

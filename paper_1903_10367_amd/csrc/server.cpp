@@ -41,7 +41,7 @@ using namespace adafac;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kSegsPerSlot = 48;   // work-list segments held per request slot (on average)
+constexpr int kSegsPerSlot = 96;   // work-list segments held per request slot (on average)
 // vertices per work item (whole lattice rows for the row-based phases): finest-level phases (at
 // most kNormBlocks items, one norm partial each), coarse FAS updates (5^d gathers per vertex)
 // and prolongations
@@ -117,7 +117,17 @@ struct Req {
   bool prepared = false;  // prep finished; its status is prep_rc
   int prep_rc = 0;
   unsigned long long items_base = 0;   // batched: work items of the request in earlier rounds
+  int cur_next = 0;       // batched: iterate buffer at the start of its next round (see launch_batched)
   bool sweep = false;     // batched: its finest level takes the single-pass sweep
+};
+
+// A batched round in flight: its launches, then a copy of the state table to pinned host memory
+// and an event.  Two rounds may be in flight; each has its own work-list buffers.
+constexpr int kFlights = 3;
+struct Flight {
+  uint64_t id = 0;
+  int buf = 0;                         // buffers of this flight (work lists, state copy, event)
+  std::vector<uint64_t> members;       // requests of the round
 };
 
 size_t finest_vertices(int d, int L) {
@@ -134,8 +144,8 @@ struct adafac_server {
   hipStream_t stream = nullptr;
   BatchReq* d_reqs = nullptr;
   BatchState* d_states = nullptr;
-  ServeSeg* d_segs = nullptr;
-  int seg_cap = 0;
+  ServeSeg* d_segs[kFlights] = {};     // work lists, one buffer per flight
+  int seg_cap = 0;                     // segments per buffer
   char* pool_base = nullptr;
   Pool pool;
   std::vector<hipStream_t> lanes;
@@ -143,12 +153,18 @@ struct adafac_server {
   std::vector<int> lane_busy;          // a request holds the lane
   std::vector<int> lane_flight;        // its last chunk of cycles is enqueued and not harvested
   std::vector<uint64_t> lane_req;
-  bool b_flight = false;               // a batched launch is enqueued and not harvested
-  std::vector<uint64_t> b_members;     // requests of that launch
+  std::deque<Flight> flights;          // batched rounds enqueued and not harvested, oldest first
+  uint64_t next_flight = 1, launched = 0, harvested = 0;   // flight ids
+  BatchState* snap[kFlights] = {};     // pinned: the state table after each flight's round
+  hipEvent_t done_ev[kFlights] = {};
+  std::vector<ServeSeg> h_segs[kFlights];   // host sources of the work-list uploads
+  bool buf_busy[kFlights] = {};
   std::vector<int> free_slots;
+  // slots of finished requests, free again once every round launched before the finish (which
+  // may still hold the request's no-op items) has been harvested: (last such flight id, slot)
+  std::vector<std::pair<uint64_t, int>> quarantine;
   std::vector<BatchReq> h_desc;        // host copies of the table rows (kept for async copies)
   std::vector<BatchState> h_states;
-  std::vector<ServeSeg> h_segs;
   std::deque<uint64_t> queue;
   std::unordered_map<uint64_t, Req> reqs;
   std::vector<uint64_t> active;
@@ -159,6 +175,7 @@ struct adafac_server {
   double t_harvest = 0, t_admit = 0, t_launch = 0;
   std::vector<double> norm_buf;   // a lane chunk's norms
   long rounds = 0;
+  long launches = 0;              // kernel launches of batched rounds
 };
 
 namespace {
@@ -217,8 +234,11 @@ int finish(adafac_server* s, Req& r, int status, int cur) {
       r.res.error = rc;
     }
   }
+  // The pool range is free at once: the request's items in rounds still in flight find the
+  // request stopped and touch none of its memory.  Its table row is read by them, so the slot
+  // waits for those rounds.
   s->pool.release(r.off, r.bytes);
-  if (r.slot >= 0) s->free_slots.push_back(r.slot);
+  if (r.slot >= 0) s->quarantine.emplace_back(s->launched, r.slot);
   if (r.lane >= 0) {
     s->lane_busy[r.lane] = 0;
     s->lane_flight[r.lane] = 0;
@@ -250,17 +270,42 @@ void drop_active(adafac_server* s, uint64_t t) {
     }
 }
 
-// Batched group: when its launch has completed, finish the requests that stopped.
+// Batched group: when its oldest round in flight has completed, finish the requests that
+// stopped (in it, or in the one before).
 int harvest_batched(adafac_server* s, bool wait, bool* done) {
   *done = false;
-  if (!s->b_flight || !ready(s->stream, wait)) return ADAFAC_OK;
-  SHIP(s, hipStreamSynchronize(s->stream));
-  SHIP(s, hipMemcpy(s->h_states.data(), s->d_states, sizeof(BatchState) * s->h_states.size(), hipMemcpyDeviceToHost));
-  s->b_flight = false;
+  if (s->flights.empty()) return ADAFAC_OK;
+  const Flight f = s->flights.front();
+  if (wait) {
+    SHIP(s, hipEventSynchronize(s->done_ev[f.buf]));
+  } else {
+    const hipError_t e = hipEventQuery(s->done_ev[f.buf]);
+    if (e == hipErrorNotReady) {
+      (void)hipGetLastError();
+      return ADAFAC_OK;
+    }
+    SHIP(s, e);
+  }
+  s->flights.pop_front();
+  s->buf_busy[f.buf] = false;
+  s->harvested = f.id;
   *done = true;
-  for (uint64_t t : s->b_members) {
-    Req& r = s->reqs[t];
-    const BatchState& st = s->h_states[r.slot];
+  for (size_t k = 0; k < s->quarantine.size();) {
+    if (s->quarantine[k].first <= s->harvested) {
+      s->free_slots.push_back(s->quarantine[k].second);
+      s->quarantine[k] = s->quarantine.back();
+      s->quarantine.pop_back();
+    } else {
+      ++k;
+    }
+  }
+  const BatchState* snap = s->snap[f.buf];
+  for (uint64_t t : f.members) {
+    auto it = s->reqs.find(t);
+    if (it == s->reqs.end()) continue;
+    Req& r = it->second;
+    if (r.slot < 0 || final_status(r.res.status)) continue;   // finished at an earlier harvest
+    const BatchState& st = snap[r.slot];
     r.res.cycles = st.cycles;
     r.res.l2h0 = st.r0;
     r.res.l2h = st.l2h;
@@ -275,21 +320,53 @@ int harvest_batched(adafac_server* s, bool wait, bool* done) {
       drop_active(s, t);
     }
   }
-  s->b_members.clear();
   return ADAFAC_OK;
 }
 
-// The phases of one step of a request, in order (see ServeSeg).
-// slots[i]: the launch (phase slot) of phase i.  The stopping rule's item shares its slot with
-// the phase after it, which does not read its result (under FP64 that phase runs even when the
-// request stops; under FP32_REFINED it only writes the inner correction, which a stopped
-// request never adds).
-// An FP64 step is cps cycles (each with its own stopping rule), so that FP64 requests move on
-// as far per launch chain as FP32-refined ones whose steps hold inner_k cycles.
+// Slot template of a round, shared by all its requests so that phases of one kind line up: a
+// step is `prefix` slots (FP32_REFINED: ADDE, DEFECT, then the stopping rule, which shares the
+// next slot; empty for FP64 requests) and `cps` cycle blocks of T = Dr + Pm slots.  In a block a
+// request's restriction phases (the finest-level FINE or SWEEP, then LEVEL L-1 .. l_min) end at
+// slot Dr - 1 and its prolongations start at slot Dr, so restriction slots hold heavy phases
+// and prolongation slots light ones.  An FP64 step is cps cycles (each with its own stopping
+// rule), so that FP64 requests move on as far per launch chain as FP32-refined ones whose steps
+// hold inner_k cycles.
+struct StepTemplate {
+  int cps = 1, prefix = 0, Dr = 1, Pm = 0;
+};
+
+// The top level of a request's SMALL item: the largest l < L whose levels l_min .. l have at most
+// kServeSmallVerts vertices each, when that covers at least two levels; else l_min - 1 (none).
+int small_top(const BatchReq& d) {
+  int hi = d.lmin - 1;
+  for (int l = d.lmin; l < d.L; ++l) {
+    const size_t n = size_t(ipow3(l) + 1);
+    if ((d.dim == 2 ? n * n : n * n * n) > kServeSmallVerts) break;
+    hi = l;
+  }
+  return hi - d.lmin + 1 >= 2 ? hi : d.lmin - 1;
+}
+// restriction: FINE or SWEEP, LEVEL L-1 .. hi+1 (or .. l_min), SMALL; prolongation: into hi+1 .. L
+// (.. L-1 when the sweep leaves the finest one pending)
+int restriction_phases(const BatchReq& d) {
+  const int hi = small_top(d);
+  return hi >= d.lmin ? 1 + (d.L - 1 - hi) + 1 : 1 + d.L - d.lmin;
+}
+int prolong_phases(const BatchReq& d, bool sweep) {
+  const int top = (sweep && d.L > d.lmin) ? d.L - 1 : d.L;
+  return top - std::max(d.lmin, small_top(d));
+}
+
+// The phases of one step of a request, in order (see ServeSeg), and slots[i], the launch (phase
+// slot) of phase i.  The stopping rule's item shares its slot with the phase after it, which
+// does not read its result (under FP64 that phase runs even when the request stops; under
+// FP32_REFINED it only writes the inner correction, which a stopped request never adds).
 // sweep: the finest level takes the single-pass sweep (SWEEP, one item in the request's sequence,
 // launched on its own), level L-1 is fed by it, and the prolongation into level L is left
 // pending for the next sweep (FP64) or the next outer step's ADDE (FP32_REFINED).
-void step_program(const BatchReq& d, int cps, bool sweep, std::vector<ServeSeg>& prog, std::vector<int>& slots) {
+void step_program(const BatchReq& d, const StepTemplate& tp, bool sweep, std::vector<ServeSeg>& prog,
+                  std::vector<int>& slots) {
+  const int cps = tp.cps, T = tp.Dr + tp.Pm;
   prog.clear();
   slots.clear();
   auto nv_of = [&](int l) {
@@ -301,7 +378,8 @@ void step_program(const BatchReq& d, int cps, bool sweep, std::vector<ServeSeg>&
     const size_t n = size_t(ipow3(l) + 1);
     return d.dim == 2 ? n : n * n;
   };
-  auto add = [&](int kind, int level, int sub, size_t units, size_t tile) {
+  auto add = [&](int kind, int level, int sub, size_t units, size_t tile, int slot) {
+    slots.push_back(slot);
     ServeSeg g{};
     g.kind = kind;
     g.level = level;
@@ -320,39 +398,45 @@ void step_program(const BatchReq& d, int cps, bool sweep, std::vector<ServeSeg>&
   const int nf = int((rL + tf - 1) / tf);
   const bool fp64 = d.precision == ADAFAC_PREC_FP64;
   const bool pi = d.damping == ADAFAC_DAMP_PI;
-  auto cycle_phases = [&](int sub) {
-    if (sweep) add(SERVE_SWEEP, d.L, sub, 1, 1);
-    else add(SERVE_FINE, d.L, sub, rL, tf);
-    if (fp64) add(SERVE_FINAL, d.L, sub, 1, 1);
-    for (int l = d.L - 1; l >= d.lmin; --l) {
-      add(SERVE_LEVEL, l, sub, nv_of(l), kLevelItem);
+  const int hi = small_top(d);
+  auto cycle_phases = [&](int sub, int base) {
+    const int s0 = base + tp.Dr - restriction_phases(d);   // this request's first restriction slot
+    if (sweep) add(SERVE_SWEEP, d.L, sub, 1, 1, s0);
+    else add(SERVE_FINE, d.L, sub, rL, tf, s0);
+    if (fp64) add(SERVE_FINAL, d.L, sub, 1, 1, s0 + 1);
+    for (int l = d.L - 1; l > hi && l >= d.lmin; --l) {
+      add(SERVE_LEVEL, l, sub, nv_of(l), kLevelItem, s0 + d.L - l);
       prog.back().gather = (sweep && l == d.L - 1) ? 0 : 1;
     }
-    for (int l = d.lmin + 1; l <= (sweep ? d.L - 1 : d.L); ++l) {
-      add(SERVE_PROLONG, l, sub, rows_of(l), rows_per_item(l, kProlongItem));
+    if (hi >= d.lmin) {
+      add(SERVE_SMALL, hi, sub, 1, 1, s0 + d.L - hi);
+      prog.back().gather = (sweep && hi == d.L - 1) ? 0 : 1;
+      prog.back().pend = (sweep && pi) ? 1 : 0;
+    }
+    int i = 0;
+    for (int l = std::max(d.lmin, hi) + 1; l <= (sweep ? d.L - 1 : d.L); ++l, ++i) {
+      add(SERVE_PROLONG, l, sub, rows_of(l), rows_per_item(l, kProlongItem), base + tp.Dr + i);
       prog.back().pend = (sweep && pi && l == d.L - 1) ? 1 : 0;
     }
   };
   if (fp64) {
-    for (int c = 0; c < cps; ++c) cycle_phases(c);
+    for (int c = 0; c < cps; ++c) cycle_phases(c, tp.prefix + c * T);
   } else if (sweep && d.dim == 3) {
-    add(SERVE_DEFECT3, d.L, 0, 1, 1);
-    add(SERVE_FINAL, d.L, 0, 1, 1);
+    add(SERVE_DEFECT3, d.L, 0, 1, 1, 1);
+    add(SERVE_FINAL, d.L, 0, 1, 1, 2);
     prog.back().pend = 1;
-    for (int i = 0; i < d.inner_k; ++i) cycle_phases(i);
+    for (int i = 0; i < d.inner_k; ++i) cycle_phases(i, tp.prefix + i * T);
   } else {
-    add(SERVE_ADDE, d.L, 0, rL, tf);
+    add(SERVE_ADDE, d.L, 0, rL, tf, 0);
     prog.back().pend = sweep ? 1 : 0;
-    add(SERVE_DEFECT, d.L, 0, rL, tf);
-    add(SERVE_FINAL, d.L, 0, 1, 1);
-    for (int i = 0; i < d.inner_k; ++i) cycle_phases(i);
+    add(SERVE_DEFECT, d.L, 0, rL, tf, 1);
+    add(SERVE_FINAL, d.L, 0, 1, 1, 2);
+    for (int i = 0; i < d.inner_k; ++i) cycle_phases(i, tp.prefix + i * T);
   }
-  int off = 0, slot = 0;
+  int off = 0;
   for (ServeSeg& g : prog) {
     g.need_off = off;
     off += g.ntile;
-    slots.push_back(slot);
-    if (g.kind != SERVE_FINAL) ++slot;
   }
   const int per_cycle = fp64 ? off / cps : 0;
   for (size_t p = 0; p < prog.size(); ++p) {
@@ -411,19 +495,28 @@ hipError_t launch_own(adafac_server* s, const ServeSeg& g, int j, bool first) {
 // p-th phase of step j of every request whose chain has one, so the launch count per round is
 // cycles_per_round x the longest chain, independent of the number of requests.
 int launch_batched(adafac_server* s) {
-  if (s->b_flight) return ADAFAC_OK;
-  s->b_members.clear();
+  if (int(s->flights.size()) >= kFlights) return ADAFAC_OK;
+  int buf = 0;
+  while (s->buf_busy[buf]) ++buf;
+  Flight fl;
+  fl.buf = buf;
   std::vector<std::vector<ServeSeg>> progs;
   std::vector<std::vector<int>> pslots;
   std::vector<ServeSeg> prog;
   std::vector<int> slots;
   size_t nseg = 0, maxp = 0;
   const int steps = s->cfg.cycles_per_round;
-  int cps = 1;
+  StepTemplate tp;
   for (uint64_t t : s->active) {
     const Req& r = s->reqs[t];
-    if (r.res.batched && s->h_desc[r.slot].precision != ADAFAC_PREC_FP64)
-      cps = std::max(cps, s->h_desc[r.slot].inner_k);
+    if (!r.res.batched) continue;
+    const BatchReq& d = s->h_desc[r.slot];
+    if (d.precision != ADAFAC_PREC_FP64) {
+      tp.cps = std::max(tp.cps, d.inner_k);
+      tp.prefix = 2;
+    }
+    tp.Dr = std::max(tp.Dr, restriction_phases(d));
+    tp.Pm = std::max(tp.Pm, prolong_phases(d, r.sweep));
   }
   struct SweepJob {
     size_t p;       // phase slot
@@ -434,68 +527,84 @@ int launch_batched(adafac_server* s) {
   for (uint64_t t : s->active) {
     Req& r = s->reqs[t];
     if (!r.res.batched) continue;
-    step_program(s->h_desc[r.slot], cps, r.sweep, prog, slots);
+    step_program(s->h_desc[r.slot], tp, r.sweep, prog, slots);
     if (nseg + prog.size() > size_t(s->seg_cap)) break;   // the rest joins a later round
-    const BatchState& st = s->h_states[r.slot];
     for (ServeSeg& g : prog) {
       g.req = r.slot;
-      g.cur0 = st.cur;
+      g.cur0 = r.cur_next;
       g.base = r.items_base;
     }
     for (size_t k = 0; k < prog.size(); ++k)
       if (serve_own_launch(prog[k].kind)) sweeps.push_back(SweepJob{size_t(slots[k]), prog[k], r.items_base == 0});
     r.items_base += (unsigned long long)steps * (unsigned long long)prog[0].per_step;
+    // Where the round leaves the iterate if the request does not stop in it (when it stops, its
+    // later rounds do nothing and their start does not matter): an FP64 cycle, and an outer step
+    // with the one-pass 3D defect, swap the two FP64 buffers.
+    const BatchReq& d = s->h_desc[r.slot];
+    bool flips = d.precision == ADAFAC_PREC_FP64;
+    for (const ServeSeg& g : prog) flips |= g.kind == SERVE_DEFECT3;
+    if (flips) r.cur_next ^= (steps * prog[0].cps) & 1;
     nseg += prog.size();
     maxp = std::max(maxp, size_t(slots.back() + 1));
     progs.push_back(prog);
     pslots.push_back(slots);
-    s->b_members.push_back(t);
+    fl.members.push_back(t);
   }
-  if (s->b_members.empty()) return ADAFAC_OK;
-  // work lists: per slot, one per kernel class (list q = p * SERVE_NCLS + class)
-  s->h_segs.clear();
+  if (fl.members.empty()) return ADAFAC_OK;
+  std::vector<ServeSeg>& hsegs = s->h_segs[buf];
+  ServeSeg* dsegs = s->d_segs[buf];
+  // work lists: per slot, one per kernel class (list q = p * SERVE_NCLS + class), each in
+  // request order; a counting sort over all segments
   const size_t nlist = maxp * SERVE_NCLS;
   std::vector<int> list_off(nlist + 1, 0), list_items(nlist, 0);
-  std::vector<size_t> at(progs.size(), 0);   // next phase of each request
-  for (size_t p = 0; p < maxp; ++p) {
-    const std::vector<size_t> at0 = at;
-    for (int cls = 0; cls < SERVE_NCLS; ++cls) {
-      const size_t q = p * SERVE_NCLS + size_t(cls);
-      list_off[q] = int(s->h_segs.size());
-      int item = 0;
-      for (size_t k = 0; k < progs.size(); ++k) {
-        size_t a = at0[k];
-        for (; a < progs[k].size() && pslots[k][a] == int(p); ++a) {
-          ServeSeg g = progs[k][a];
-          if (serve_own_launch(g.kind) || serve_class(g.kind) != cls) continue;   // a launch of its own
-          g.item0 = item;
-          item += g.ntile;
-          s->h_segs.push_back(g);
-        }
-        at[k] = a;
-      }
-      list_items[q] = item;
+  auto list_of = [&](size_t k, size_t a) { return size_t(pslots[k][a]) * SERVE_NCLS + size_t(serve_class(progs[k][a].kind)); };
+  for (size_t k = 0; k < progs.size(); ++k)
+    for (size_t a = 0; a < progs[k].size(); ++a)
+      if (!serve_own_launch(progs[k][a].kind)) ++list_off[list_of(k, a) + 1];
+  for (size_t q = 0; q < nlist; ++q) list_off[q + 1] += list_off[q];
+  hsegs.resize(size_t(list_off[nlist]));
+  std::vector<int> fill(list_off.begin(), list_off.end() - 1);
+  for (size_t k = 0; k < progs.size(); ++k)
+    for (size_t a = 0; a < progs[k].size(); ++a) {
+      if (serve_own_launch(progs[k][a].kind)) continue;   // a launch of its own
+      const size_t q = list_of(k, a);
+      ServeSeg g = progs[k][a];
+      g.item0 = list_items[q];
+      list_items[q] += g.ntile;
+      hsegs[size_t(fill[q]++)] = g;
     }
-  }
-  list_off[nlist] = int(s->h_segs.size());
-  SHIP(s, hipMemcpyAsync(s->d_segs, s->h_segs.data(), sizeof(ServeSeg) * s->h_segs.size(), hipMemcpyHostToDevice,
+  // own launches by slot
+  std::stable_sort(sweeps.begin(), sweeps.end(), [](const SweepJob& x, const SweepJob& y) { return x.p < y.p; });
+  SHIP(s, hipMemcpyAsync(dsegs, hsegs.data(), sizeof(ServeSeg) * hsegs.size(), hipMemcpyHostToDevice,
                          s->stream));
   // Within a slot the shared launches go first: an FP32_REFINED request's stopping rule shares
   // the slot with its first inner sweep, which then sees the decision and does not overwrite the
   // norm partials before they are read.  The phases of a slot are independent of one another
   // (different requests, or a request's stopping rule and the phase after it, which does not
   // read its result), so the order of the class launches does not matter.
-  for (int j = 0; j < steps; ++j)
+  for (int j = 0; j < steps; ++j) {
+    size_t w = 0;
     for (size_t p = 0; p < maxp; ++p) {
       for (int cls = 0; cls < SERVE_NCLS; ++cls) {
         const size_t q = p * SERVE_NCLS + size_t(cls);
-        SHIP(s, launch_serve_phase(cls, s->d_reqs, s->d_states, s->d_segs + list_off[q], list_off[q + 1] - list_off[q],
+        if (list_items[q] == 0) continue;
+        SHIP(s, launch_serve_phase(cls, s->d_reqs, s->d_states, dsegs + list_off[q], list_off[q + 1] - list_off[q],
                                    list_items[q], j, s->stream));
+        ++s->launches;
       }
-      for (const SweepJob& w : sweeps)
-        if (w.p == p) SHIP(s, launch_own(s, w.g, j, w.first));
+      for (; w < sweeps.size() && sweeps[w].p == p; ++w) {
+        SHIP(s, launch_own(s, sweeps[w].g, j, sweeps[w].first));
+        ++s->launches;
+      }
     }
-  s->b_flight = true;
+  }
+  SHIP(s, hipMemcpyAsync(s->snap[buf], s->d_states, sizeof(BatchState) * size_t(s->cfg.max_active),
+                         hipMemcpyDeviceToHost, s->stream));
+  SHIP(s, hipEventRecord(s->done_ev[buf], s->stream));
+  fl.id = s->next_flight++;
+  s->launched = fl.id;
+  s->buf_busy[buf] = true;
+  s->flights.push_back(std::move(fl));
   return ADAFAC_OK;
 }
 
@@ -677,7 +786,7 @@ int adafac_server_create(const adafac_server_cfg* cfg, void* ws, size_t bytes, v
     return ADAFAC_EINVAL;
   if (!ws || reinterpret_cast<uintptr_t>(ws) % kAlign) return ADAFAC_EINVAL;
   const size_t head = align_up(sizeof(BatchReq) * c.max_active) + align_up(sizeof(BatchState) * c.max_active) +
-                      align_up(sizeof(ServeSeg) * size_t(kSegsPerSlot) * c.max_active);
+                      kFlights * align_up(sizeof(ServeSeg) * size_t(kSegsPerSlot) * c.max_active);
   if (bytes < head) return ADAFAC_ENOMEM;
   adafac_server* s = new (std::nothrow) adafac_server();
   if (!s) return ADAFAC_ENOMEM;
@@ -690,9 +799,11 @@ int adafac_server_create(const adafac_server_cfg* cfg, void* ws, size_t bytes, v
   p += align_up(sizeof(BatchReq) * c.max_active);
   s->d_states = reinterpret_cast<BatchState*>(p);
   p += align_up(sizeof(BatchState) * c.max_active);
-  s->d_segs = reinterpret_cast<ServeSeg*>(p);
   s->seg_cap = kSegsPerSlot * c.max_active;
-  p += align_up(sizeof(ServeSeg) * size_t(s->seg_cap));
+  for (int b = 0; b < kFlights; ++b) {
+    s->d_segs[b] = reinterpret_cast<ServeSeg*>(p);
+    p += align_up(sizeof(ServeSeg) * size_t(s->seg_cap));
+  }
   s->pool_base = p;
   s->pool.reset((bytes - head) & ~(kAlign - 1));
   s->h_desc.resize(c.max_active);
@@ -711,6 +822,16 @@ int adafac_server_create(const adafac_server_cfg* cfg, void* ws, size_t bytes, v
   if (hipStreamCreateWithFlags(&s->setup, hipStreamNonBlocking) != hipSuccess) {
     adafac_server_destroy(s);
     return ADAFAC_EDEVICE;
+  }
+  for (int b = 0; b < kFlights; ++b) {
+    void* h = nullptr;
+    if (hipHostMalloc(&h, sizeof(BatchState) * size_t(c.max_active), hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&s->done_ev[b], hipEventDisableTiming) != hipSuccess) {
+      if (h) (void)hipHostFree(h);
+      adafac_server_destroy(s);
+      return ADAFAC_EDEVICE;
+    }
+    s->snap[b] = static_cast<BatchState*>(h);
   }
   s->t0 = std::chrono::steady_clock::now();
   *out = s;
@@ -764,7 +885,7 @@ int adafac_server_step(adafac_server* s, int* active, int* queued) {
       rc = service_lane(s, k, false, &done);
       progress |= done;
     }
-    bool busy = s->b_flight;
+    bool busy = !s->flights.empty();
     for (int k = 0; k < int(s->lanes.size()); ++k) busy |= s->lane_flight[k] != 0;
     if (progress) break;
     if (!busy) {
@@ -788,7 +909,12 @@ int adafac_server_step(adafac_server* s, int* active, int* queued) {
   bool done = false;
   for (int k = 0; k < int(s->lanes.size()) && !rc; ++k)
     if (s->lane_busy[k] && !s->lane_flight[k]) rc = service_lane(s, k, false, &done);
-  if (!rc) rc = launch_batched(s);
+  // keep two batched rounds in flight: the host harvests one while the device runs the other
+  for (int k = 0; k < kFlights && !rc && int(s->flights.size()) < kFlights; ++k) {
+    const size_t before = s->flights.size();
+    rc = launch_batched(s);
+    if (s->flights.size() == before) break;
+  }
   const double t_d = now(s);
   s->t_harvest += t_b - t_a;
   s->t_admit += t_c - t_b;
@@ -824,8 +950,9 @@ int adafac_server_fetch(adafac_server* s, uint64_t ticket, double* u, size_t n) 
 void adafac_server_destroy(adafac_server* s) {
   if (!s) return;
   if (std::getenv("ADAFAC_SERVER_STATS"))
-    std::fprintf(stderr, "adafac server: %ld rounds, host seconds harvest %.3f admit %.3f launch %.3f\n", s->rounds,
-                 s->t_harvest, s->t_admit, s->t_launch);
+    std::fprintf(stderr, "adafac server: %ld steps, %lu rounds, %ld launches, host seconds harvest %.3f admit %.3f "
+                 "launch %.3f\n", s->rounds, (unsigned long)s->launched, s->launches, s->t_harvest, s->t_admit,
+                 s->t_launch);
   (void)hipStreamSynchronize(s->stream);
   for (hipStream_t l : s->lanes)
     if (l) (void)hipStreamSynchronize(l);
@@ -837,6 +964,10 @@ void adafac_server_destroy(adafac_server* s) {
   for (hipStream_t l : s->lanes)
     if (l) (void)hipStreamDestroy(l);
   if (s->setup) (void)hipStreamDestroy(s->setup);
+  for (int b = 0; b < kFlights; ++b) {
+    if (s->snap[b]) (void)hipHostFree(s->snap[b]);
+    if (s->done_ev[b]) (void)hipEventDestroy(s->done_ev[b]);
+  }
   delete s;
 }
 
