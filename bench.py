@@ -219,6 +219,49 @@ def serving(Server, torch, n_req, loads, budget_gb, max_cycles, log=None, **serv
     return out
 
 
+def _kname(n):
+    return n.replace("(anonymous namespace)::", "").replace("adafac::", "").replace("void ", "").split("(")[0]
+
+
+def trace_busy(path):
+    """GPU-busy fraction of the serving window in a rocprofv3 kernel trace (CSV): the union of
+    the kernel intervals between the first and the last phase launch of the request server,
+    over that window's length, and the kernel time per kernel (top 12)."""
+    import csv
+    ivs, names = [], {}
+    with open(path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            a, b = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+            n = r["Kernel_Name"]
+            ivs.append((a, b, "k_serve_phase" in n))
+            names.setdefault(_kname(n), [0, 0.0])
+    phase = [iv for iv in ivs if iv[2]]
+    if not phase:
+        return {"error": "no request-server launches in the trace"}
+    w0, w1 = min(a for a, _, _ in phase), max(b for _, b, _ in phase)
+    inside = sorted((max(a, w0), min(b, w1)) for a, b, _ in ivs if b > w0 and a < w1)
+    busy, cs, ce = 0, None, None
+    for a, b in inside:
+        if cs is None or a > ce:
+            if cs is not None:
+                busy += ce - cs
+            cs, ce = a, b
+        else:
+            ce = max(ce, b)
+    if cs is not None:
+        busy += ce - cs
+    with open(path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            a, b = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+            if b > w0 and a < w1:
+                k = _kname(r["Kernel_Name"])
+                names[k][0] += 1
+                names[k][1] += (b - a) / 1e6
+    top = sorted(((k, c, ms) for k, (c, ms) in names.items() if c), key=lambda x: -x[2])[:12]
+    return {"window_s": (w1 - w0) / 1e9, "busy_s": busy / 1e9, "busy_frac": busy / (w1 - w0),
+            "launches": sum(c for c, _ in names.values()), "kernels_ms": [[k, c, round(ms, 1)] for k, c, ms in top]}
+
+
 def copy_and_cold(s, torch, nbytes=2 << 30, reps=10, cold_cycles=20):
     """Context for the roofline: (a) the rate of a plain device-to-device copy of 2 GiB on this
     GPU (bytes read + written per second), with the library's streaming copy kernel and with
@@ -399,9 +442,14 @@ def main():
     ap.add_argument("--serve-max-cycles", type=int, default=3000)
     ap.add_argument("--paper-setups", action="store_true",
                     help="also run the set-ups of Sec. 5 on regular grids (stability of the damping variants)")
+    ap.add_argument("--trace-busy", metavar="CSV",
+                    help="print the GPU-busy fraction of the serving window of a rocprofv3 kernel trace and exit")
     ap.add_argument("--profile-pass", action="store_true",
                     help="counter runs: a 1 GiB device copy (byte-counter calibration), then a few cycles")
     args = ap.parse_args()
+    if args.trace_busy:
+        print(json.dumps(trace_busy(args.trace_busy)))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is a design note, not a measured path.", file=sys.stderr)

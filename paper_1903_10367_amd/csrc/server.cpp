@@ -119,6 +119,11 @@ struct Req {
   unsigned long long items_base = 0;   // batched: work items of the request in earlier rounds
   int cur_next = 0;       // batched: iterate buffer at the start of its next round (see launch_batched)
   bool sweep = false;     // batched: its finest level takes the single-pass sweep
+  // batched: binding (uploads and load vector) after admission, or finishing (solution to the
+  // host) after the stopping rule, on a worker thread; the request holds its pool range meanwhile
+  std::future<int> job;
+  int bg = 0;             // 0 none, 1 binding, 2 finishing
+  int fin_status = 0;     // finishing: the status it ends with
 };
 
 // A batched round in flight: its launches, then a copy of the state table to pinned host memory
@@ -168,11 +173,13 @@ struct adafac_server {
   std::deque<uint64_t> queue;
   std::unordered_map<uint64_t, Req> reqs;
   std::vector<uint64_t> active;
+  std::vector<uint64_t> background;    // batched requests binding or finishing on worker threads
   uint64_t next_ticket = 1;
   std::chrono::steady_clock::time_point t0;
   std::string err;
   // host time spent per phase of adafac_server_step (seconds) and rounds run
   double t_harvest = 0, t_admit = 0, t_launch = 0;
+  double t_issue = 0;             // part of t_launch spent issuing the round's copies and launches
   std::vector<double> norm_buf;   // a lane chunk's norms
   long rounds = 0;
   long launches = 0;              // kernel launches of batched rounds
@@ -217,8 +224,35 @@ int build_ctx(Req* rp) {
   return ADAFAC_OK;
 }
 
-// Release a finished request's device resources, keeping its solution on the host.
+// Batched request: its solution to the host (with the pending prolongation of a swept FP64
+// request added first) and its context released.  Runs on a worker thread.
+int finish_batched_job(Req* rp, int cur, int pending) {
+  Req& r = *rp;
+  int rc = batch_adopt(r.ctx, cur, pending);
+  r.u.assign(finest_vertices(r.dim, r.L), 0.0);
+  if (!rc) rc = adafac_get_solution(r.ctx, r.u.data(), r.u.size());
+  adafac_destroy(r.ctx);
+  r.ctx = nullptr;
+  return rc;
+}
+
+// Release a finished request's device resources, keeping its solution on the host.  A batched
+// request does so on a worker thread (complete_background ends it); its status stays RUNNING
+// until the solution is on the host.
 int finish(adafac_server* s, Req& r, int status, int cur) {
+  if (r.res.batched && r.ctx) {
+    // an FP64 request whose cycles swept the finest level has the last P S_{L-1} pending
+    const int pending = r.sweep && s->h_desc[r.slot].precision == ADAFAC_PREC_FP64;
+    r.fin_status = status;
+    r.bg = 2;
+    r.job = std::async(std::launch::async, finish_batched_job, &r, cur, pending);
+    s->background.push_back(r.ticket);
+    // Its table row is read by the rounds still in flight (where its items find it stopped), so
+    // the slot waits for those rounds.
+    s->quarantine.emplace_back(s->launched, r.slot);
+    r.slot = -1;
+    return ADAFAC_OK;
+  }
   r.res.status = status;
   r.res.t_done = now(s);
   if (r.ctx) {
@@ -234,11 +268,7 @@ int finish(adafac_server* s, Req& r, int status, int cur) {
       r.res.error = rc;
     }
   }
-  // The pool range is free at once: the request's items in rounds still in flight find the
-  // request stopped and touch none of its memory.  Its table row is read by them, so the slot
-  // waits for those rounds.
   s->pool.release(r.off, r.bytes);
-  if (r.slot >= 0) s->quarantine.emplace_back(s->launched, r.slot);
   if (r.lane >= 0) {
     s->lane_busy[r.lane] = 0;
     s->lane_flight[r.lane] = 0;
@@ -575,6 +605,7 @@ int launch_batched(adafac_server* s) {
     }
   // own launches by slot
   std::stable_sort(sweeps.begin(), sweeps.end(), [](const SweepJob& x, const SweepJob& y) { return x.p < y.p; });
+  const double t_i0 = now(s);
   SHIP(s, hipMemcpyAsync(dsegs, hsegs.data(), sizeof(ServeSeg) * hsegs.size(), hipMemcpyHostToDevice,
                          s->stream));
   // Within a slot the shared launches go first: an FP32_REFINED request's stopping rule shares
@@ -601,6 +632,7 @@ int launch_batched(adafac_server* s) {
   SHIP(s, hipMemcpyAsync(s->snap[buf], s->d_states, sizeof(BatchState) * size_t(s->cfg.max_active),
                          hipMemcpyDeviceToHost, s->stream));
   SHIP(s, hipEventRecord(s->done_ev[buf], s->stream));
+  s->t_issue += now(s) - t_i0;
   fl.id = s->next_flight++;
   s->launched = fl.id;
   s->buf_busy[buf] = true;
@@ -653,6 +685,61 @@ int service_lane(adafac_server* s, int k, bool wait, bool* done) {
   return ADAFAC_OK;
 }
 
+// Batched requests on worker threads: a finished binding joins the next round enqueued (its
+// table row uploaded here); a finished finishing releases the pool range (the request's items
+// in rounds still in flight find it stopped and touch none of its memory) and ends the request.
+int complete_background(adafac_server* s, bool wait) {
+  bool rows = false;
+  for (size_t k = 0; k < s->background.size();) {
+    Req& r = s->reqs[s->background[k]];
+    if (!wait && r.job.wait_for(std::chrono::seconds(0)) != std::future_status::ready) {
+      ++k;
+      continue;
+    }
+    int rc = r.job.get();
+    s->background[k] = s->background.back();
+    s->background.pop_back();
+    if (r.bg == 2) {
+      r.bg = 0;
+      r.res.status = rc ? ADAFAC_REQ_FAILED : r.fin_status;
+      if (rc) r.res.error = rc;
+      r.res.t_done = now(s);
+      s->pool.release(r.off, r.bytes);
+      r.f.clear();
+      r.f.shrink_to_fit();
+      continue;
+    }
+    r.bg = 0;
+    if (rc) {
+      // the slot never entered a round
+      s->pool.release(r.off, r.bytes);
+      s->free_slots.push_back(r.slot);
+      r.slot = -1;
+      r.res.status = ADAFAC_REQ_FAILED;
+      r.res.error = rc;
+      r.res.t_done = now(s);
+      adafac_destroy(r.ctx);
+      r.ctx = nullptr;
+      continue;
+    }
+    BatchReq& d = s->h_desc[r.slot];
+    if ((rc = batch_describe(r.ctx, &d))) return sfail(s, rc, "batch_describe");
+    r.sweep = d.fusable && finest_vertices(r.dim, r.L) >= kSweepMinVerts;
+    d.tol = r.tol;
+    d.max_cycles = r.max_cycles;
+    s->h_states[r.slot] = BatchState{};
+    s->h_states[r.slot].stop_need = ~0ull;
+    SHIP(s, hipMemcpyAsync(&s->d_reqs[r.slot], &d, sizeof(BatchReq), hipMemcpyHostToDevice, s->setup));
+    SHIP(s, hipMemcpyAsync(&s->d_states[r.slot], &s->h_states[r.slot], sizeof(BatchState), hipMemcpyHostToDevice,
+                           s->setup));
+    s->active.push_back(r.ticket);
+    rows = true;
+  }
+  // the next batched launch reads the new table rows
+  if (rows) SHIP(s, hipStreamSynchronize(s->setup));
+  return ADAFAC_OK;
+}
+
 // Start the host-side set-up of queued requests, in arrival order, on worker threads: at most
 // kPrepThreads at once and kPrepAhead set up (or being set up) ahead of admission.
 void prepare(adafac_server* s) {
@@ -677,9 +764,8 @@ void prepare(adafac_server* s) {
 // Admit prepared requests in arrival order while slots and memory allow; their uploads go to
 // the setup stream and they join the next round's launch.
 int admit(adafac_server* s) {
-  bool any = false;
   for (auto it = s->queue.begin(); it != s->queue.end();) {
-    if (int(s->active.size()) >= s->cfg.max_active) break;
+    if (int(s->active.size() + s->background.size()) >= s->cfg.max_active) break;
     Req& r = s->reqs[*it];
     if (!r.prep_started) {
       ++it;
@@ -716,7 +802,24 @@ int admit(adafac_server* s) {
     }
     size_t off = 0;
     if (!s->pool.alloc(r.bytes, &off)) { ++it; continue; }
-    hipStream_t st = batched ? s->setup : s->lanes[lane];
+    if (batched) {
+      // binding (the load vector and the uploads) on a worker thread; the request joins a round
+      // once it has finished (complete_background)
+      r.off = off;
+      r.res.footprint = align_up(r.bytes);
+      r.res.batched = 1;
+      r.res.t_admit = now(s);
+      r.res.status = ADAFAC_REQ_RUNNING;
+      r.slot = s->free_slots.back();
+      s->free_slots.pop_back();
+      r.bg = 1;
+      r.job = std::async(std::launch::async, adafac_bind, r.ctx, static_cast<void*>(s->pool_base + off),
+                         align_up(r.bytes), static_cast<void*>(s->setup));
+      s->background.push_back(r.ticket);
+      it = s->queue.erase(it);
+      continue;
+    }
+    hipStream_t st = s->lanes[lane];
     rc = adafac_bind(r.ctx, s->pool_base + off, align_up(r.bytes), st);
     if (rc) {
       s->pool.release(off, r.bytes);
@@ -730,36 +833,18 @@ int admit(adafac_server* s) {
     }
     r.off = off;
     r.res.footprint = align_up(r.bytes);
-    r.res.batched = batched ? 1 : 0;
+    r.res.batched = 0;
     r.res.t_admit = now(s);
     r.res.status = ADAFAC_REQ_RUNNING;
-    if (batched) {
-      r.slot = s->free_slots.back();
-      s->free_slots.pop_back();
-      BatchReq& d = s->h_desc[r.slot];
-      if ((rc = batch_describe(r.ctx, &d))) return sfail(s, rc, "batch_describe");
-      r.sweep = d.fusable && finest_vertices(r.dim, r.L) >= kSweepMinVerts;
-      d.tol = r.tol;
-      d.max_cycles = r.max_cycles;
-      s->h_states[r.slot] = BatchState{};
-      s->h_states[r.slot].stop_need = ~0ull;
-      SHIP(s, hipMemcpyAsync(&s->d_reqs[r.slot], &d, sizeof(BatchReq), hipMemcpyHostToDevice, s->setup));
-      SHIP(s, hipMemcpyAsync(&s->d_states[r.slot], &s->h_states[r.slot], sizeof(BatchState), hipMemcpyHostToDevice,
-                             s->setup));
-      any = true;
-    } else {
-      r.lane = lane;
-      s->lane_busy[lane] = 1;
-      s->lane_flight[lane] = 0;
-      s->lane_req[lane] = r.ticket;
-    }
+    r.lane = lane;
+    s->lane_busy[lane] = 1;
+    s->lane_flight[lane] = 0;
+    s->lane_req[lane] = r.ticket;
     s->active.push_back(r.ticket);
     it = s->queue.erase(it);
   }
-  // the next batched launch reads the new table rows
-  if (any) SHIP(s, hipStreamSynchronize(s->setup));
   prepare(s);
-  return ADAFAC_OK;
+  return complete_background(s, false);
 }
 
 }  // namespace
@@ -885,8 +970,10 @@ int adafac_server_step(adafac_server* s, int* active, int* queued) {
       rc = service_lane(s, k, false, &done);
       progress |= done;
     }
-    bool busy = !s->flights.empty();
+    bool busy = !s->flights.empty() || !s->background.empty();
     for (int k = 0; k < int(s->lanes.size()); ++k) busy |= s->lane_flight[k] != 0;
+    for (uint64_t t : s->background)
+      if (s->reqs[t].job.wait_for(std::chrono::seconds(0)) == std::future_status::ready) progress = true;
     if (progress) break;
     if (!busy) {
       // nothing on the device: wait (a little) only for a queued request's host set-up
@@ -920,7 +1007,7 @@ int adafac_server_step(adafac_server* s, int* active, int* queued) {
   s->t_admit += t_c - t_b;
   s->t_launch += t_d - t_c;
   s->rounds += 1;
-  if (active) *active = int(s->active.size());
+  if (active) *active = int(s->active.size() + s->background.size());
   if (queued) *queued = int(s->queue.size());
   return rc;
 }
@@ -951,14 +1038,15 @@ void adafac_server_destroy(adafac_server* s) {
   if (!s) return;
   if (std::getenv("ADAFAC_SERVER_STATS"))
     std::fprintf(stderr, "adafac server: %ld steps, %lu rounds, %ld launches, host seconds harvest %.3f admit %.3f "
-                 "launch %.3f\n", s->rounds, (unsigned long)s->launched, s->launches, s->t_harvest, s->t_admit,
-                 s->t_launch);
+                 "launch %.3f (issue %.3f)\n", s->rounds, (unsigned long)s->launched, s->launches, s->t_harvest,
+                 s->t_admit, s->t_launch, s->t_issue);
   (void)hipStreamSynchronize(s->stream);
   for (hipStream_t l : s->lanes)
     if (l) (void)hipStreamSynchronize(l);
   for (auto& kv : s->reqs) {
     Req& r = kv.second;
     if (r.prep_started && !r.prepared && r.prep.valid()) (void)r.prep.get();
+    if (r.bg && r.job.valid()) (void)r.job.get();   // a finishing job releases its context itself
     if (r.ctx) adafac_destroy(r.ctx);
   }
   for (hipStream_t l : s->lanes)
