@@ -436,7 +436,7 @@ def main():
                     help="skip the oracle timing and the oracle reference solve")
     ap.add_argument("--cpu-cycles", type=int, default=2)
     ap.add_argument("--no-adaptive", action="store_true", help="skip the adaptive-tree workloads")
-    ap.add_argument("--serve-requests", type=int, default=200, help="requests per serving pass (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=1000, help="requests per serving pass (0: skip)")
     ap.add_argument("--serve-loads", default="0.5,0.9", help="arrival rates as fractions of capacity")
     ap.add_argument("--serve-budget-gb", type=float, default=4.0)
     ap.add_argument("--serve-max-cycles", type=int, default=3000)

@@ -336,14 +336,15 @@ int adafac_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
  * The caller hands over one device workspace.  A small header of it holds the
  * batched kernel's request table; the rest is a pool that holds the hierarchies
  * of the admitted requests.  Requests wait in a FIFO queue while their host-side
- * set-up (operators, load vector) runs on worker threads.  A set-up request is
+ * set-up (operators) runs on worker threads.  A set-up request is
  * admitted, in arrival order (a later request may pass one that does not fit
  * yet), when an active slot is free and its exact device footprint (the
  * adafac_workspace_bytes of its hierarchy) fits in the free pool.  Each
  * scheduling round (adafac_server_step) does three things:
  *  - harvests the oldest round in flight once it has completed;
- *  - admits, uploading while the device runs the other round in flight;
- *  - enqueues rounds until two are in flight: each advances every active
+ *  - admits, binding on worker threads while the device runs the rounds in
+ *    flight;
+ *  - enqueues rounds until three are in flight: each advances every active
  *    request by up to cycles_per_round cycles (outer steps for FP32_REFINED).
  *    A request admitted now joins the next round enqueued.
  * All active requests, of any depth and dimension, advance together in shared
@@ -357,10 +358,12 @@ int adafac_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
  * 2^18 finest vertices sweep their finest level in one pass instead, in a
  * launch of their own within the same slot.  A request stops exactly at the
  * first iterate that meets the tolerance (the stopping rule runs on the
- * device; the request's work in a round enqueued after that does nothing).  Requests above batch_max_vertices finest vertices (default:
- * none) advance on streams of their own instead and stop at the end of the
- * round in which they converged.  A finished request's solution is copied to
- * host memory and its device memory and slot are freed.  A request's
+ * device; the request's work in a round enqueued after that does nothing).
+ * Requests above batch_max_vertices finest vertices (default: none) advance on
+ * streams of their own instead and stop at the end of the round in which they
+ * converged.  A finished request's solution is copied to host memory (on a
+ * worker thread; it reads as running until then) and its device memory and
+ * slot are freed (the slot once no round in flight can read it).  A request's
  * arithmetic does not depend on the other requests, so results are the same
  * served alone or in a mix.
  * A server is driven by one host thread.
@@ -421,7 +424,7 @@ int adafac_server_create(const adafac_server_cfg* cfg, void* dev_workspace, size
 int adafac_server_submit(adafac_server* srv, const adafac_request* req, uint64_t* ticket);
 
 /* One scheduling round: wait (briefly) for the oldest round in flight, harvest
- * finished requests, admit, enqueue rounds up to two in flight.  *active (may
+ * finished requests, admit, enqueue rounds up to three in flight.  *active (may
  * be NULL) receives the number of requests on the device after admission,
  * *queued (may be NULL) the number waiting.  Returns after enqueuing. */
 int adafac_server_step(adafac_server* srv, int* active, int* queued);

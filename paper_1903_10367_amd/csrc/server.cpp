@@ -127,7 +127,7 @@ struct Req {
 };
 
 // A batched round in flight: its launches, then a copy of the state table to pinned host memory
-// and an event.  Two rounds may be in flight; each has its own work-list buffers.
+// and an event.  kFlights rounds may be in flight; each has its own work-list buffers.
 constexpr int kFlights = 3;
 struct Flight {
   uint64_t id = 0;
@@ -996,7 +996,7 @@ int adafac_server_step(adafac_server* s, int* active, int* queued) {
   bool done = false;
   for (int k = 0; k < int(s->lanes.size()) && !rc; ++k)
     if (s->lane_busy[k] && !s->lane_flight[k]) rc = service_lane(s, k, false, &done);
-  // keep two batched rounds in flight: the host harvests one while the device runs the other
+  // keep kFlights batched rounds in flight: the host harvests one while the device runs the others
   for (int k = 0; k < kFlights && !rc && int(s->flights.size()) < kFlights; ++k) {
     const size_t before = s->flights.size();
     rc = launch_batched(s);
