@@ -182,9 +182,13 @@ int adafac_bind(adafac_ctx* ctx, void* dev_workspace, size_t bytes, void* hip_st
  * entries are ignored.  The iterate then carries these values on its boundary
  * vertices (adafac_set_solution keeps them, adafac_get_solution returns them),
  * and every residual sees them, which is the load -A G of the lift u = u_0 + G.
- * Takes effect at the next adafac_bind.  Uniform trees only: EUNSUPPORTED with
- * refinement (here or at build_operators); EINVAL on a wrong n or a non-finite
- * boundary value.  All-zero boundary values restore the homogeneous problem. */
+ * On adaptive trees every level's boundary vertices carry the data at their
+ * positions (hanging vertices next to the boundary interpolate it; a regrid keeps
+ * it), and the composite function's boundary traces are d-linear in the values at
+ * the corners of the leaf cells.  FP32_REFINED inner cycles solve for corrections
+ * with zero boundary values.  Takes effect at the next adafac_bind (or regrid).
+ * EINVAL on a wrong n or a non-finite boundary value.  All-zero boundary values
+ * restore the homogeneous problem. */
 int adafac_set_dirichlet_lattice(adafac_ctx* ctx, const double* g, size_t n);
 
 /* Size of the library's static device workspace (see adafac_bind_static). */

@@ -31,6 +31,12 @@ One cycle, in correction form over the generating system:
 The per-level arrays ("FAS storage") hold the composite value at every dof position and the
 interpolated value at hanging vertices.
 
+Inhomogeneous Dirichlet data (the set-ups of Sec. 5, u = 1 on x_2 = 0): the boundary vertices of
+existing cells carry the data g on every level, and the composite space is the continuous Q1
+functions on the leaf cells with those boundary values (hanging vertices still interpolate the
+next coarser level, boundary values included).  The residual of the interior dofs then contains
+the coupling to the boundary values; corrections stay zero on the boundary.
+
 Pinned by: the uniform tree reduces to cycle.cycle_correction, the cycle equals the dense
 generating-system form of eq. (adaFACx) built here independently from hat functions, and
 the fixed point is the direct solve of the composite system.  Border semantics beyond these
@@ -61,9 +67,12 @@ class AdaptiveTree:
     the uniform hierarchy of levels lmin..k.  Above level k every cell lies inside one
     coefficient block, where BoxMG's P is the d-linear one (pinned in the uniform tests), so
     those levels keep d-linear transfers (and hanging vertices always interpolate d-linearly).
+
+    ``g``: Dirichlet data on the finest vertex lattice (only its boundary entries are used);
+    None: u = 0 on the boundary.
     """
 
-    def __init__(self, d, L, lmin, l_uniform, refine, eps_blocks=None, omega=0.6, transfer="dlinear"):
+    def __init__(self, d, L, lmin, l_uniform, refine, eps_blocks=None, omega=0.6, transfer="dlinear", g=None):
         assert 1 <= lmin <= l_uniform <= L
         assert transfer in ("dlinear", "boxmg")
         self.d, self.L, self.lmin, self.lu = d, L, lmin, l_uniform
@@ -92,11 +101,16 @@ class AdaptiveTree:
             E = nxt
         self._classify()
         self._operators()
+        self.g = None
+        if g is not None:
+            g = np.asarray(g, dtype=np.float64).reshape(self.shape(L))
+            self.g = {l: g[tuple(slice(None, None, 3 ** (L - l)) for _ in range(d))].copy()
+                      for l in range(lmin, L + 1)}
 
     # --- vertex classes ---------------------------------------------------------
     def _classify(self):
         d = self.d
-        self.cnt, self.dof, self.hang, self.comp, self.exists_v = {}, {}, {}, {}, {}
+        self.cnt, self.dof, self.hang, self.comp, self.exists_v, self.bnd = {}, {}, {}, {}, {}, {}
         for l in range(self.lmin, self.L + 1):
             E = self.E[l].astype(np.int32)
             n = 3 ** l
@@ -108,6 +122,7 @@ class AdaptiveTree:
             self.exists_v[l] = cnt > 0
             self.dof[l] = inter & (cnt == 2 ** d)
             self.hang[l] = inter & (cnt > 0) & (cnt < 2 ** d)
+            self.bnd[l] = ~inter & (cnt > 0)
         for l in range(self.lmin, self.L + 1):
             if l == self.L:
                 self.comp[l] = self.dof[l].copy()
@@ -183,20 +198,33 @@ class AdaptiveTree:
                 out.append((l, int(i)))
         return out
 
-    def spread(self, U):
+    def spread(self, U, homogeneous=False):
         """Complete per-level storage from the composite values: coarse copies of finer dofs
-        (injection), then hanging vertices interpolated top-down."""
+        (injection), the Dirichlet data on the boundary vertices of existing cells (zero when
+        homogeneous: corrections, or no data), then hanging vertices interpolated top-down."""
         d, L = self.d, self.L
         U = {l: U[l].copy() for l in U}
         for l in range(L, self.lmin, -1):
             fine_at_coarse = U[l][tuple(slice(None, None, 3) for _ in range(d))]
             copy = self.dof[l - 1] & ~self.comp[l - 1]
             U[l - 1][copy] = fine_at_coarse[copy]
+        keep = {}
+        for l in range(self.lmin, L + 1):
+            keep[l] = self.dof[l] | self.hang[l]
+            if self.g is not None and not homogeneous:
+                U[l][self.bnd[l]] = self.g[l][self.bnd[l]].astype(U[l].dtype)
+                keep[l] = keep[l] | self.bnd[l]
+            else:
+                U[l][self.bnd[l]] = 0.0
         for l in range(self.lmin + 1, L + 1):
-            Pu = self.P[l](U[l - 1].ravel()).reshape(self.shape(l))
+            if self.g is not None and not homogeneous:
+                # hanging vertices next to the boundary interpolate its values too
+                Pu = _upsample(U[l - 1])
+            else:
+                Pu = self.P[l](U[l - 1].ravel()).reshape(self.shape(l))
             U[l][self.hang[l]] = Pu[self.hang[l]]
         for l in range(self.lmin, L + 1):
-            U[l][~(self.dof[l] | self.hang[l])] = 0.0
+            U[l][~keep[l]] = 0.0
         return U
 
 
@@ -211,18 +239,19 @@ def norms(T, rh):
     return np.sqrt(s), m
 
 
-def cycle(T, U, bleaf, omega=0.6, omega_t=0.6, damping="jac", trace=None, dtype=np.float64):
+def cycle(T, U, bleaf, omega=0.6, omega_t=0.6, damping="jac", trace=None, dtype=np.float64, homogeneous=False):
     """One adAFAC cycle on the adaptive tree (correction form over the generating system).
 
     U: per-level storage of the iterate (see AdaptiveTree.spread).  Returns the new storage and
     the norms of the composite residual of the input iterate.  ``dtype`` float32 stores every
     intermediate array in FP32 (the inner cycles of defect correction); the operators are
     applied as FP64 factors and their results rounded, so this gives the size of FP32
-    rounding, not any particular rounding order.
+    rounding, not any particular rounding order.  ``homogeneous``: zero boundary values (a
+    correction equation) whatever the tree's Dirichlet data.
     """
     assert damping in ("jac", "pi", "none")
     d, L, lmin = T.d, T.L, T.lmin
-    U = T.spread({l: U[l].astype(dtype) for l in U})
+    U = T.spread({l: U[l].astype(dtype) for l in U}, homogeneous)
     bleaf = {l: bleaf[l].astype(dtype) for l in bleaf}
     # leaf residuals, per level, at every vertex of a leaf cell
     rl = {l: bleaf[l] - T.leaf_apply(l, U[l]).reshape(T.shape(l)) for l in range(lmin, L + 1)}
@@ -257,7 +286,7 @@ def cycle(T, U, bleaf, omega=0.6, omega_t=0.6, damping="jac", trace=None, dtype=
     V = {l: np.where(T.comp[l], U[l] + S[l], U[l]) for l in U}
     if trace is not None:
         trace.update(rleaf=rl, b=b, rh=rh, c=c, ct=ct, S=S)
-    return T.spread(V), nr
+    return T.spread(V, homogeneous), nr
 
 
 def solve(T, f, max_cycles, tol=None, **kw):
@@ -313,19 +342,41 @@ def defect_correction(T, f, k_inner, tol, max_outer, inner_dtype=np.float32, ite
             break
         E = {l: np.zeros(T.shape(l), dtype=inner_dtype) for l in U}
         for _ in range(k_inner):
-            E, _ = cycle(T, E, rh, dtype=inner_dtype, **kw)
+            E, _ = cycle(T, E, rh, dtype=inner_dtype, homogeneous=True, **kw)
         U = {l: np.where(T.dof[l], U[l] + E[l].astype(np.float64), U[l]) for l in U}
     return T.spread(U), hist
 
 
+def _upsample(u):
+    """d-linear interpolation of a whole vertex lattice (boundary included) onto the lattice of
+    the next finer level: fine index 3c + s takes (1 - s/3) u[c] + (s/3) u[c + 1] per axis."""
+    for a in range(u.ndim):
+        n = u.shape[a] - 1
+        lo = np.take(u, np.arange(n), axis=a)
+        hi = np.take(u, np.arange(1, n + 1), axis=a)
+        parts = [lo, (2.0 * lo + hi) / 3.0, (lo + 2.0 * hi) / 3.0]
+        st = np.stack(parts, axis=a + 1)
+        shp = list(u.shape)
+        shp[a] = 3 * n
+        st = st.reshape(shp)
+        last = np.take(u, [n], axis=a)
+        u = np.concatenate([st, last], axis=a)
+    return u
+
+
 def finest_values(T, U):
     """The composite FE function at every vertex of the finest lattice (d-linear from the
-    coarsest level where the point is not covered by finer cells)."""
+    coarsest level where the point is not covered by finer cells; with Dirichlet data the
+    boundary traces of coarse leaf cells are d-linear in their corner values too)."""
     d, L = T.d, T.L
     out = U[T.lmin].copy()
     for l in range(T.lmin + 1, L + 1):
-        up = T.P[l](out.ravel()).reshape(T.shape(l))
-        have = T.dof[l] | T.hang[l]
+        if T.g is None:
+            up = T.P[l](out.ravel()).reshape(T.shape(l))
+            have = T.dof[l] | T.hang[l]
+        else:
+            up = _upsample(out)
+            have = T.dof[l] | T.hang[l] | T.bnd[l]
         out = np.where(have, U[l], up)
     return out
 
@@ -346,7 +397,9 @@ def dense_system(T, f):
 
     positions: (n, d) coordinates of the composite dofs (x on the last axis); Psi[l]: composite
     values of the level-l hats of the level-l dofs (columns in flat-index order of dof[l]).
+    Homogeneous Dirichlet data only.
     """
+    assert T.g is None
     d, L = T.d, T.L
     idx = T.composite_index()
     n = len(idx)

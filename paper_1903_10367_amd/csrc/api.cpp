@@ -755,6 +755,33 @@ int build_adaptive(adafac_ctx* c) {
 }
 
 // Uploads of an adaptive context: classes, leaf cells, stored diagonals, lumped loads.
+// Dirichlet data at the domain-boundary vertices of level l's box (the values the kernels read
+// there: no kernel writes a boundary vertex); other entries untouched.
+void fill_boundary(const adafac_ctx* c, int l, std::vector<double>& box) {
+  if (c->gdir.empty()) return;
+  const int d = c->dim, L = c->L, n = ipow3(l), nL = ipow3(L) + 1, s = ipow3(L - l);
+  const AdaptLevel& A = c->ad[l];
+  for (int z = 0; z < A.mz; ++z)
+    for (int y = 0; y < A.my; ++y)
+      for (int x = 0; x < A.mx; ++x) {
+        const int gx = A.ox + x, gy = A.oy + y, gz = d == 3 ? A.oz + z : 1;
+        const bool bd = gx == 0 || gx == n || gy == 0 || gy == n || (d == 3 && (gz == 0 || gz == n));
+        if (!bd) continue;
+        const size_t fx = size_t(gx) * s, fy = size_t(gy) * s, fz = d == 3 ? size_t(gz) * s : 0;
+        box[(size_t(z) * A.my + y) * A.mx + x] = c->gdir[(fz * nL + fy) * nL + fx];
+      }
+}
+
+// Whether box vertex (x, y, z) of level l is a corner of an existing cell of that level.
+bool vertex_of_cell(const AdaptHostLevel& H, int d, int x, int y, int z) {
+  for (int e = 0; e < (1 << d); ++e) {
+    const int cx = x - 1 + (e & 1), cy = y - 1 + ((e >> 1) & 1), cz = d == 3 ? z - 1 + ((e >> 2) & 1) : 0;
+    if (cx < 0 || cy < 0 || cz < 0 || cx >= H.nc[0] || cy >= H.nc[1] || cz >= H.nc[2]) continue;
+    if (H.exists[(size_t(cz) * H.nc[1] + cy) * H.nc[0] + cx]) return true;
+  }
+  return false;
+}
+
 int bind_adaptive(adafac_ctx* c) {
   const int d = c->dim, L = c->L;
   HIPCHK(c, hipMemcpyAsync(c->ad_eps, c->ops.eps.data(), sizeof(double) * c->ops.eps.size(), hipMemcpyHostToDevice,
@@ -810,6 +837,14 @@ int bind_adaptive(adafac_ctx* c) {
     if (!A.fem)
       HIPCHK(c, hipMemcpyAsync(const_cast<double*>(A.dg), H.dg.data(), sizeof(double) * H.dg.size(),
                                hipMemcpyHostToDevice, c->stream));
+    std::vector<double> ub;
+    if (!c->gdir.empty()) {
+      // the Dirichlet data on the level's boundary vertices, zero inside (the initial iterate,
+      // or the zeros a regrid's transfer writes over at the dofs)
+      ub.assign(H.nverts(), 0.0);
+      fill_boundary(c, l, ub);
+      HIPCHK(c, hipMemcpyAsync(A.u, ub.data(), sizeof(double) * ub.size(), hipMemcpyHostToDevice, c->stream));
+    }
     std::vector<float> pw32;
     if (A.pw) {
       // a complete level: its box is the whole lattice, so box and lattice indices agree
@@ -877,7 +912,13 @@ int adaptive_finest(adafac_ctx* c, double* out) {
       for (int y = 0; y < A.my; ++y)
         for (int x = 0; x < A.mx; ++x) {
           const size_t i = (size_t(z) * A.my + y) * A.mx + x;
-          if (!(H.vcls[i] & (kDof | kHang))) continue;
+          if (!(H.vcls[i] & (kDof | kHang))) {
+            // with Dirichlet data, the boundary vertices of existing cells hold it
+            if (c->gdir.empty()) continue;
+            const int gx = A.ox + x, gy = A.oy + y, gz = d == 3 ? A.oz + z : 1;
+            const bool bd = gx == 0 || gx == n || gy == 0 || gy == n || (d == 3 && (gz == 0 || gz == n));
+            if (!bd || !vertex_of_cell(H, d, x, y, z)) continue;
+          }
           const size_t g = d == 2 ? size_t(A.oy + y) * nv + (A.ox + x)
                                   : (size_t(A.oz + z) * nv + (A.oy + y)) * nv + (A.ox + x);
           up[g] = box[i];
@@ -906,6 +947,7 @@ int adaptive_set(adafac_ctx* c, const double* u) {
           const size_t gx = size_t(A.ox + x) * s, gy = size_t(A.oy + y) * s, gz = d == 3 ? size_t(A.oz + z) * s : 0;
           box[i] = u[(gz * nL + gy) * nL + gx];
         }
+    fill_boundary(c, l, box);
     HIPCHK(c, hipMemcpyAsync(A.u, box.data(), sizeof(double) * box.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
   }
@@ -1091,8 +1133,6 @@ int adafac_build_operators(adafac_ctx* c, const adafac_opts* opts) {
   for (int b = 1; b < c->nb; b *= 3) c->ops.k++;
   c->ops.eps = c->eps;
   c->adaptive = !c->refine.empty() || c->ball_r > 0.0;
-  if (c->adaptive && !c->gdir.empty())
-    return fail(c, ADAFAC_EUNSUPPORTED, "Dirichlet data: uniform trees only");
   if (c->adaptive) {
     int rc = build_adaptive(c);
     if (rc) return rc;
@@ -1623,8 +1663,6 @@ int adafac_set_rhs_fn(adafac_ctx* c, double (*f)(const double* x, void* user), v
 
 int adafac_set_dirichlet_lattice(adafac_ctx* c, const double* g, size_t n) {
   if (!c) return ADAFAC_EINVAL;
-  if (c->adaptive || !c->refine.empty() || c->ball_r > 0.0)
-    return fail(c, ADAFAC_EUNSUPPORTED, "Dirichlet data: uniform trees only");
   if (!g || n != nverts_of(c->dim, c->L)) return fail(c, ADAFAC_EINVAL, "g: wrong size");
   const int nv = ipow3(c->L) + 1;
   std::vector<double> gd(n, 0.0);
@@ -1773,9 +1811,11 @@ int adafac_set_composite(adafac_ctx* c, const double* u, size_t n) {
           }
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (int l = c->lmin; l <= L; ++l)
+    for (int l = c->lmin; l <= L; ++l) {
+      fill_boundary(c, l, box[l]);
       HIPCHK(c, hipMemcpyAsync(c->ad[l].u, box[l].data(), sizeof(double) * box[l].size(), hipMemcpyHostToDevice,
                                c->stream));
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->e_pending = false;
     int rc = adapt_hang(c);

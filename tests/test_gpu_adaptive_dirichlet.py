@@ -1,0 +1,159 @@
+"""Inhomogeneous Dirichlet data on adaptive spacetrees (the set-ups of Sec. 5), GPU against the
+adaptive oracle.
+
+The boundary vertices of every level carry the data; hanging vertices next to the boundary
+interpolate it; corrections stay zero there.  Per cycle the composite residual norms agree
+within 1e-12 of the initial norm, every level's values (dofs, hanging and boundary vertices)
+and the finest-lattice composite function within 1e-12 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import adafac_inputs as inp
+from oracle import adaptive
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bilinear(d, L):
+    x = np.linspace(0.0, 1.0, 3 ** L + 1)
+    if d == 2:
+        Y, X = np.meshgrid(x, x, indexing="ij")
+        return X * Y + 2 * X - Y + 0.5
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    return X * Y * Z + X - Z + 0.25
+
+
+def bottom_strip_flags(d, L, lu):
+    """Refine, on levels lu..L-1, every cell with a face on x_2 = 0 (the boundary that carries
+    u = 1), as the paper's runs do on the way to l_max."""
+    out = {}
+    for l in range(lu, L):
+        f = np.zeros((3 ** l,) * d, dtype=bool)
+        f[(0,) + (slice(None),) * (d - 1)] = True   # axis 0 is the last coordinate (x_2 in 2D)
+        out[l] = f
+    return out
+
+
+def run_both(d, L, lu, g, f=None, eps=None, cycles=6, ball=None, flags=None, damping="jac", transfer="dlinear",
+             tol_scale=1e-12):
+    from paper_1903_10367_amd import Solver
+    f = np.zeros_like(g) if f is None else f
+    if flags is not None:
+        refine, kw = flags, dict(refine=flags)
+    else:
+        centre, radius = ball
+        refine, kw = inp.refine_ball(d, L, lu, centre, radius), dict(ball=(centre, radius, lu))
+    s = Solver(d, 1, L, f, eps_blocks=eps, damping=damping, transfer=transfer, dirichlet=g, **kw)
+    s.cycle(cycles)
+    hg = s.residuals()
+    levels = {l: s.level(l, "u") for l in range(1, L + 1)}
+    ufine = s.solution()
+    s.close()
+    T = adaptive.AdaptiveTree(d, L, 1, lu, refine, eps, transfer=transfer, g=g)
+    U, ho = adaptive.solve(T, f, cycles, damping=damping)
+    r0 = ho[0][0]
+    for n, (a, b) in enumerate(zip(hg, ho)):
+        assert abs(a[0] - b[0]) <= 1e-12 * r0, f"cycle {n}: {a[0]!r} vs {b[0]!r}"
+        assert abs(a[1] - b[1]) <= 1e-12 * ho[0][1], f"cycle {n} linf"
+    scale = max(np.abs(U[l]).max() for l in U)
+    for l in range(1, L + 1):
+        have = T.dof[l] | T.hang[l]
+        lv = levels[l].reshape(T.shape(l))
+        err = np.abs(lv[have] - U[l][have]).max() if have.any() else 0.0
+        assert err <= tol_scale * scale, f"level {l}: {err:.3e}"
+    fo = adaptive.finest_values(T, U)
+    err = np.abs(ufine.reshape(fo.shape) - fo).max()
+    say(f"finest composite function: max error {err:.3e}")
+    assert err <= tol_scale * scale
+    return hg, ho, ufine
+
+
+@pytest.mark.parametrize("transfer", ["dlinear", "boxmg"])
+@pytest.mark.parametrize("damping", ["jac", "pi"])
+def test_2d_disk_paper_boundary(damping, transfer):
+    say("case adaptive Dirichlet 2d disk", damping, transfer)
+    g = inp.paper_boundary(2, 4)
+    eps = inp.eps_blocks(2, 2, 2.0, seed=80)
+    run_both(2, 4, 2, g, eps=eps, ball=((0.5, 0.5), 0.2), damping=damping, transfer=transfer)
+
+
+def test_2d_bottom_strip_tree():
+    """The tree of the paper's runs: refined along the data-carrying boundary, hanging
+    vertices next to it."""
+    say("case adaptive Dirichlet 2d bottom strip")
+    g = inp.paper_boundary(2, 5)
+    run_both(2, 5, 2, g, flags=bottom_strip_flags(2, 5, 2), cycles=8)
+
+
+def test_3d_ball_touching_the_boundary_reproduces_a_trilinear_function():
+    """A 3D tree whose refined cells reach the boundary, with the data of a harmonic trilinear
+    p: parity with the oracle per cycle, and a solve that reproduces p (it lies in the composite
+    space)."""
+    from paper_1903_10367_amd import Solver
+    say("case adaptive Dirichlet 3d ball, trilinear data")
+    d, L, lu = 3, 3, 1
+    p = bilinear(d, L)
+    ball = ((0.45, 0.5, 0.55), 0.2)
+    run_both(d, L, lu, p, ball=ball, cycles=5)
+    s = Solver(d, 1, L, np.zeros_like(p), ball=(ball[0], ball[1], lu), dirichlet=p)
+    n = s.solve(1e-12, 400)
+    u = s.solution().reshape(p.shape)
+    s.close()
+    say(f"solve: {n} cycles, max |u - p| {np.abs(u - p).max():.3e}")
+    assert np.abs(u - p).max() <= 1e-9
+
+
+def test_fp32_refined_solve_matches_the_fp64_oracle_solution():
+    from paper_1903_10367_amd import Solver
+    say("case adaptive Dirichlet fp32_refined solve")
+    d, L, lu = 2, 5, 2
+    g = inp.paper_boundary(d, L)
+    flags = bottom_strip_flags(d, L, lu)
+    s = Solver(d, 1, L, np.zeros_like(g), refine=flags, dirichlet=g, precision="fp32_refined", inner_k=4)
+    s.solve(1e-11, 200)
+    u = s.solution()
+    s.close()
+    T = adaptive.AdaptiveTree(d, L, 1, lu, flags, g=g)
+    U, ho = adaptive.solve(T, np.zeros_like(g), 2000, tol=1e-13)
+    fo = adaptive.finest_values(T, U)
+    err = np.abs(u.reshape(fo.shape) - fo).max()
+    say(f"fp32_refined vs oracle solution: {err:.3e}")
+    assert err <= 1e-9
+
+
+def test_regrid_keeps_the_boundary_values():
+    """Regrid of a Dirichlet problem onto a tree around a moved ball: the new dofs take the old
+    composite function (boundary traces included), and the continued cycles match the oracle."""
+    from paper_1903_10367_amd import Solver
+    say("case adaptive Dirichlet regrid")
+    d, L, lu = 2, 4, 2
+    g = inp.paper_boundary(d, L)
+    c0, c1, r = (0.3, 0.3), (0.6, 0.4), 0.15
+    s = Solver(d, 1, L, np.zeros_like(g), ball=(c0, r, lu), dirichlet=g)
+    s.cycle(3)
+    s.regrid(c1, r, lu, f=np.zeros_like(g))
+    s.cycle(3)
+    hg = s.residuals()
+    u = s.solution()
+    s.close()
+    T0 = adaptive.AdaptiveTree(d, L, 1, lu, inp.refine_ball(d, L, lu, c0, r), g=g)
+    U0, h0 = adaptive.solve(T0, np.zeros_like(g), 3)
+    T1 = adaptive.AdaptiveTree(d, L, 1, lu, inp.refine_ball(d, L, lu, c1, r), g=g)
+    U1 = adaptive.transfer(T0, U0, T1)
+    bleaf = T1.load(np.zeros_like(g))
+    h1 = []
+    for _ in range(3):
+        U1, nr = adaptive.cycle(T1, U1, bleaf)
+        h1.append(nr)
+    ho = h0 + h1
+    for n, (a, b) in enumerate(zip(hg, ho)):
+        assert abs(a[0] - b[0]) <= 1e-12 * ho[0][0], f"cycle {n}"
+    fo = adaptive.finest_values(T1, U1)
+    assert np.abs(u.reshape(fo.shape) - fo).max() <= 1e-12 * np.abs(fo).max()

@@ -317,3 +317,76 @@ def test_manufactured_solution_converges_at_second_order_on_disk_trees():
         errs.append(np.abs(u - ustar).max())
     ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
     assert all(6.0 < r < 13.0 for r in ratios), (errs, ratios)
+
+
+# --- inhomogeneous Dirichlet data on adaptive trees (the set-ups of Sec. 5) -------------------
+
+def _bilinear(d, L):
+    """A harmonic d-linear function on the finest lattice (x fastest): x y + 2x - y + 1/2 in 2D,
+    x y z + x - z + 1/4 in 3D."""
+    x = np.linspace(0.0, 1.0, 3 ** L + 1)
+    if d == 2:
+        Y, X = np.meshgrid(x, x, indexing="ij")
+        return X * Y + 2 * X - Y + 0.5
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    return X * Y * Z + X - Z + 0.25
+
+
+@pytest.mark.parametrize("d,L,lu", [(2, 4, 2), (3, 3, 1)])
+def test_dirichlet_bilinear_data_is_reproduced_on_refined_trees(d, L, lu):
+    """f = 0 with the boundary values of a harmonic d-linear p: p lies in the composite space
+    (continuous Q1 on the leaf cells; hanging vertices interpolate d-linearly), so the discrete
+    solution is p itself at every dof, whatever the tree."""
+    p = _bilinear(d, L)
+    ref = inp.refine_ball(d, L, lu, (0.5,) * d if d == 2 else (0.45, 0.5, 0.55), 0.2)
+    T = adaptive.AdaptiveTree(d, L, 1, lu, ref, g=p)
+    U, hist = adaptive.solve(T, np.zeros_like(p), 400, tol=1e-13)
+    assert hist[-1][0] / hist[0][0] <= 1e-13
+    for l in range(1, L + 1):
+        pl = p[tuple(slice(None, None, 3 ** (L - l)) for _ in range(d))]
+        m = T.dof[l] | T.hang[l] | T.bnd[l]
+        assert np.abs(U[l][m] - pl[m]).max() <= 1e-10, l
+    # the finest-lattice composite function is p wherever the tree has cells
+    F = adaptive.finest_values(T, U)
+    assert np.abs(F - p).max() <= 1e-10
+
+
+@pytest.mark.parametrize("d,L,field", [(2, 3, "split"), (2, 3, "homogeneous"), (3, 2, "homogeneous")])
+def test_dirichlet_uniform_tree_is_the_lifted_uniform_cycle(d, L, field):
+    """A tree refined everywhere with the Sec. 5 boundary data (u = 1 on x_2 = 0) runs the
+    uniform cycle on the lifted problem, A u_0 = b - A G, with u = u_0 + G."""
+    g = inp.paper_boundary(d, L)
+    eps = None if field == "homogeneous" else inp.eps_blocks(d, 1, 2.0, seed=9)
+    T = adaptive.AdaptiveTree(d, L, 1, L, {}, eps, g=g)
+    U, hist = adaptive.solve(T, np.zeros_like(g), 8)
+    H = hierarchy.Hierarchy(d, L, 1, eps)
+    u0, ho = cycle.solve(H, H.rhs(np.zeros_like(g), g=g), 8)
+    from oracle import fem
+    u = fem.with_boundary(u0, g)
+    assert np.abs(U[L] - u).max() <= 1e-13 * np.abs(u).max()
+    for a, b in zip(hist, ho):
+        assert abs(a[0] - b[0]) <= 1e-13 * ho[0][0]
+
+
+def test_dirichlet_defect_correction_with_fp64_inner_cycles_is_the_plain_iteration():
+    """The inner cycles solve the correction equation with zero boundary values: with FP64 inner
+    cycles, k inner cycles per outer step equal k plain cycles on u."""
+    d, L = 2, 4
+    g = inp.paper_boundary(d, L)
+    T = disk_tree(L=L)
+    T = adaptive.AdaptiveTree(d, L, 1, 2, inp.refine_ball(d, L, 2, (0.5, 0.5), 0.2), g=g)
+    its = []
+    U, h = adaptive.defect_correction(T, np.zeros_like(g), 3, 0.0, 2, inner_dtype=np.float64, iterates=its)
+    Up, hp = adaptive.solve(T, np.zeros_like(g), 6)
+    assert abs(h[0][0] - hp[0][0]) <= 1e-13 * hp[0][0]
+    for l in range(1, L + 1):
+        assert np.abs(U[l] - Up[l]).max() <= 1e-12 * max(1.0, np.abs(Up[l]).max())
+
+
+def test_upsample_reproduces_dlinear_functions():
+    """The whole-lattice d-linear interpolation used for boundary traces is exact on d-linear
+    functions, boundary included."""
+    for d, L in ((2, 2), (3, 2)):
+        p_c = _bilinear(d, L - 1)
+        p_f = _bilinear(d, L)
+        assert np.abs(adaptive._upsample(p_c) - p_f).max() <= 1e-14
