@@ -124,6 +124,32 @@ int adafac_set_rhs_gaussian(adafac_ctx* ctx, const double* centre, double sigma,
  * EINVAL on a bad level or size. */
 int adafac_set_refinement(adafac_ctx* ctx, int level, const uint8_t* flags, size_t ncells);
 
+/* Feature-based refinement of the Sec. 5 runs (dynamic AMR with a full-multigrid-like
+ * start): the refinement flags of the next tree, for levels l_uniform .. l_cap-1 (l_cap >=
+ * l_max), concatenated level by level, (3^l)^dim cells each in C order (x fastest); n must be
+ * their total.  A flag marks a cell that the next tree refines:
+ *  - every cell the current tree refines (levels below l_uniform must be complete and fully
+ *    refined: they carry no flags);
+ *  - while l_max < l_cap, every cell of level l_max with a face on which the Dirichlet data
+ *    are nonzero at every corner (the boundary carrying u = 1);
+ *  - the 2^dim cells around each composite dof of a level below l_cap that carries one of the
+ *    (approximately) `fraction` largest directional second derivatives of the current iterate
+ *    (max over the axes of |u(x + h e_i) - 2 u(x) + u(x - h e_i)| / h^2 on the dof's level):
+ *    the values are sorted into 1024 equal bins over [0, their maximum] and whole bins are
+ *    taken from the top until they hold at least that fraction of the dofs.
+ * *l_new receives the depth of the next tree (1 + its finest refined level, at least l_max).
+ * A uniform tree (no flags) needs l_uniform = l_max.  Synchronises.  EINVAL on bad
+ * arguments; ESTATE before bind. */
+int adafac_amr_mark(adafac_ctx* ctx, double fraction, int l_uniform, int l_cap, uint8_t* flags, size_t n,
+                    int* l_new);
+
+/* Start a deeper tree from a shallower one's solution (full-multigrid-like growth): u holds
+ * n = (3^l_src + 1)^dim values of the composite function on the finest lattice of a tree of
+ * depth l_src <= l_max (adafac_get_solution of that tree); they are interpolated d-linearly
+ * onto this tree's finest lattice and set as with adafac_set_solution (boundary entries take
+ * this context's Dirichlet data).  EINVAL on bad arguments; ESTATE before bind. */
+int adafac_set_solution_coarse(adafac_ctx* ctx, const double* u, size_t n, int l_src);
+
 /* Refine, on levels l_from .. l_max-1 without explicit flags, every existing cell
  * whose closure meets the closed ball |x - centre| <= radius (centre: dim
  * coordinates, x first).  Levels below l_from refine every cell.  radius 0

@@ -168,6 +168,26 @@ class Solver:
         u = np.ascontiguousarray(u, dtype=np.float64).ravel()
         _check(self.L, self.ctx, self.L.adafac_set_solution(self.ctx, _dptr(u), u.size))
 
+    def set_solution_coarse(self, u, l_src):
+        """Start from a shallower tree's finest-lattice solution (interpolated by the library)."""
+        u = np.ascontiguousarray(u, dtype=np.float64).ravel()
+        _check(self.L, self.ctx, self.L.adafac_set_solution_coarse(self.ctx, _dptr(u), u.size, int(l_src)))
+
+    def amr_mark(self, fraction, l_uniform, l_cap):
+        """Refinement flags of the next tree ({level: bool array}, levels l_uniform..l_cap-1) and
+        its depth, from adafac_amr_mark."""
+        sizes = [(3 ** l) ** self.dim for l in range(l_uniform, l_cap)]
+        flags = np.zeros(sum(sizes), dtype=np.uint8)
+        lnew = C.c_int()
+        _check(self.L, self.ctx, self.L.adafac_amr_mark(self.ctx, float(fraction), int(l_uniform), int(l_cap),
+                                                         flags.ctypes.data_as(C.POINTER(C.c_uint8)), flags.size,
+                                                         C.byref(lnew)))
+        out, k = {}, 0
+        for l, n in zip(range(l_uniform, l_cap), sizes):
+            out[l] = flags[k:k + n].reshape((3 ** l,) * self.dim).astype(bool)
+            k += n
+        return out, int(lnew.value)
+
     def level(self, level, which):
         out = np.empty((3 ** level + 1) ** self.dim)
         _check(self.L, self.ctx, self.L.adafac_get_level(self.ctx, level, LEVEL_ARRAY[which], _dptr(out), out.size))

@@ -26,6 +26,7 @@ EXPORTS = [
     "adafac_server_poll", "adafac_server_fetch", "adafac_server_destroy", "adafac_server_last_error",
     "adafac_stream_copy", "adafac_set_rhs_fn", "adafac_residual_normalised", "adafac_dof_coords",
     "adafac_get_composite", "adafac_set_composite", "adafac_bind_static", "adafac_set_dirichlet_lattice",
+    "adafac_amr_mark", "adafac_set_solution_coarse",
 ]
 
 
@@ -119,6 +120,9 @@ def lib():
         "adafac_dof_coords": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_size_t]),
         "adafac_get_composite": (C.c_int, [P, C.POINTER(C.c_double), C.c_size_t]),
         "adafac_set_composite": (C.c_int, [P, C.POINTER(C.c_double), C.c_size_t]),
+        "adafac_amr_mark": (C.c_int, [P, C.c_double, C.c_int, C.c_int, C.POINTER(C.c_uint8), C.c_size_t,
+                                      C.POINTER(C.c_int)]),
+        "adafac_set_solution_coarse": (C.c_int, [P, C.POINTER(C.c_double), C.c_size_t, C.c_int]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)

@@ -1518,6 +1518,199 @@ int adafac_kernel_time(adafac_ctx* c, double* total_ms, int* launches) {
   return ADAFAC_OK;
 }
 
+int adafac_set_solution_coarse(adafac_ctx* c, const double* u, size_t n, int l_src) {
+  if (!c) return ADAFAC_EINVAL;
+  if (!ready(c)) return fail(c, ADAFAC_ESTATE, "bind first");
+  if (l_src < 1 || l_src > c->L) return fail(c, ADAFAC_EINVAL, "l_src must lie in 1..l_max");
+  const int d = c->dim;
+  if (!u || n != nverts_of(d, l_src)) return fail(c, ADAFAC_EINVAL, "u: wrong size");
+  // d-linear interpolation, one level at a time: fine index 3 i + s takes (1 - s/3) u_i + (s/3) u_{i+1}
+  std::vector<double> cur(u, u + n), nxt;
+  for (int l = l_src; l < c->L; ++l) {
+    const int m = ipow3(l), M = 3 * m;   // cells per axis, coarse and fine
+    const size_t nc = size_t(m) + 1, nf = size_t(M) + 1;
+    nxt.assign(d == 2 ? nf * nf : nf * nf * nf, 0.0);
+    const int zf = d == 3 ? M : 0;
+    for (int z = 0; z <= zf; ++z)
+      for (int y = 0; y <= M; ++y)
+        for (int x = 0; x <= M; ++x) {
+          const int cx = std::min(x / 3, m - 1), cy = std::min(y / 3, m - 1), cz = d == 3 ? std::min(z / 3, m - 1) : 0;
+          const int sx = x - 3 * cx, sy = y - 3 * cy, sz = z - 3 * cz;
+          double acc = 0.0;
+          for (int e = 0; e < (1 << d); ++e) {
+            const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+            double w = (ex ? sx : 3 - sx) / 3.0 * ((ey ? sy : 3 - sy) / 3.0);
+            if (d == 3) w *= (ez ? sz : 3 - sz) / 3.0;
+            if (w == 0.0) continue;
+            acc += w * cur[(size_t(cz + ez) * nc + (cy + ey)) * nc + (cx + ex)];
+          }
+          nxt[(size_t(z) * nf + y) * nf + x] = acc;
+        }
+    cur.swap(nxt);
+  }
+  return adafac_set_solution(c, cur.data(), cur.size());
+}
+
+int adafac_amr_mark(adafac_ctx* c, double fraction, int l_uniform, int l_cap, uint8_t* flags, size_t n,
+                    int* l_new) {
+  if (!c) return ADAFAC_EINVAL;
+  if (!ready(c)) return fail(c, ADAFAC_ESTATE, "bind first");
+  const int d = c->dim, L = c->L;
+  if (!(fraction >= 0.0 && fraction <= 1.0) || l_uniform < c->lmin || l_uniform > L || l_cap < L || l_cap > kMaxLevel ||
+      (d == 3 && l_cap > 6))
+    return fail(c, ADAFAC_EINVAL, "bad fraction, l_uniform or l_cap");
+  if (!c->adaptive && l_uniform != L) return fail(c, ADAFAC_EINVAL, "a uniform tree has l_uniform = l_max");
+  if (c->adaptive) {
+    // the levels below l_uniform carry no flags: they must be complete and fully refined
+    for (int l = c->lmin; l < l_uniform; ++l) {
+      const AdaptHostLevel& H = c->at.lev[l];
+      const size_t m = size_t(ipow3(l)), full = d == 2 ? m * m : m * m * m;
+      bool ok = H.ncells() == full;
+      for (size_t i = 0; ok && i < H.refined.size(); ++i) ok = H.exists[i] && H.refined[i];
+      if (!ok) return fail(c, ADAFAC_EINVAL, "l_uniform above the current tree's complete levels");
+    }
+  }
+  std::vector<size_t> off(size_t(l_cap) + 1, 0);
+  size_t total = 0;
+  for (int l = l_uniform; l < l_cap; ++l) {
+    off[l] = total;
+    const size_t m = size_t(ipow3(l));
+    total += d == 2 ? m * m : m * m * m;
+  }
+  if (!flags || !l_new || n != total) return fail(c, ADAFAC_EINVAL, "flags: wrong size");
+  std::fill(flags, flags + n, uint8_t(0));
+  auto cell = [&](int l, int x, int y, int z) -> uint8_t& {
+    const size_t m = size_t(ipow3(l));
+    return flags[off[l] + (size_t(z) * m + y) * m + x];
+  };
+  int rc = flush(c);
+  if (rc) return rc;
+  // the current tree's refined cells, and every level's nodal values on the full lattice
+  // (dofs, hanging values, boundary data; zero outside the level's cells)
+  std::vector<std::vector<double>> u(L + 1);
+  std::vector<std::vector<uint8_t>> comp(L + 1), exists(L + 1);
+  for (int l = c->lmin; l <= L; ++l) {
+    const int m = ipow3(l), nv = m + 1;
+    const size_t nvert = d == 2 ? size_t(nv) * nv : size_t(nv) * nv * nv;
+    const size_t ncell = d == 2 ? size_t(m) * m : size_t(m) * m * m;
+    u[l].assign(nvert, 0.0);
+    comp[l].assign(nvert, 0);
+    exists[l].assign(ncell, 0);
+  }
+  if (c->adaptive) {
+    for (int l = c->lmin; l <= L; ++l) {
+      const AdaptHostLevel& H = c->at.lev[l];
+      const AdaptLevel& A = c->ad[l];
+      std::vector<double> box(H.nverts());
+      HIPCHK(c, hipMemcpyAsync(box.data(), A.u, sizeof(double) * box.size(), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      const int m = ipow3(l), nv = m + 1;
+      for (int z = 0; z < (d == 3 ? H.nc[2] + 1 : 1); ++z)
+        for (int y = 0; y <= H.nc[1]; ++y)
+          for (int x = 0; x <= H.nc[0]; ++x) {
+            const size_t i = (size_t(z) * (H.nc[1] + 1) + y) * (H.nc[0] + 1) + x;
+            const size_t g = (size_t(d == 3 ? H.lo[2] + z : 0) * nv + (H.lo[1] + y)) * nv + (H.lo[0] + x);
+            u[l][g] = box[i];
+            comp[l][g] = (H.vcls[i] & kComp) ? 1 : 0;
+          }
+      for (int z = 0; z < H.nc[2]; ++z)
+        for (int y = 0; y < H.nc[1]; ++y)
+          for (int x = 0; x < H.nc[0]; ++x) {
+            const size_t i = (size_t(z) * H.nc[1] + y) * H.nc[0] + x;
+            const size_t g = (size_t(d == 3 ? H.lo[2] + z : 0) * m + (H.lo[1] + y)) * m + (H.lo[0] + x);
+            exists[l][g] = H.exists[i];
+            if (l >= l_uniform && l < L && H.exists[i] && H.refined[i])
+              cell(l, H.lo[0] + x, H.lo[1] + y, d == 3 ? H.lo[2] + z : 0) = 1;
+          }
+    }
+  } else {
+    std::vector<double> lat(nverts_of(d, L));
+    if ((rc = adafac_get_solution(c, lat.data(), lat.size()))) return rc;
+    u[L] = lat;
+    const int m = ipow3(L), nv = m + 1;
+    std::fill(exists[L].begin(), exists[L].end(), uint8_t(1));
+    for (size_t i = 0; i < comp[L].size(); ++i) {
+      const int x = int(i % nv), y = int((i / nv) % nv), z = d == 3 ? int(i / (size_t(nv) * nv)) : 1;
+      comp[L][i] = x > 0 && x < m && y > 0 && y < m && (d == 2 || (z > 0 && z < m));
+    }
+  }
+  // (i) the finest level's cells with a face on which the Dirichlet data are nonzero at every
+  // vertex (the bottom boundary of the Sec. 5 set-ups), while the tree is below l_cap
+  if (L < l_cap && !c->gdir.empty()) {
+    const int m = ipow3(L), nv = m + 1;
+    auto gv = [&](int x, int y, int z) { return c->gdir[(size_t(z) * nv + y) * nv + x]; };
+    for (int z = 0; z < (d == 3 ? m : 1); ++z)
+      for (int y = 0; y < m; ++y)
+        for (int x = 0; x < m; ++x) {
+          if (!exists[L][(size_t(z) * m + y) * m + x]) continue;
+          const int q[3] = {x, y, z};
+          bool mark = false;
+          for (int a = 0; a < d && !mark; ++a)
+            for (int side = 0; side < 2 && !mark; ++side) {
+              // the cell's face at coordinate f along axis a lies on the boundary
+              const int f = side ? m : 0;
+              if (q[a] + side != f) continue;
+              bool all = true;   // the data at the face's 2^(d-1) corners
+              for (int e = 0; e < (1 << d) && all; ++e) {
+                const int v[3] = {x + (e & 1), y + ((e >> 1) & 1), z + (d == 3 ? (e >> 2) & 1 : 0)};
+                if (v[a] == f) all = gv(v[0], v[1], v[2]) != 0.0;
+              }
+              mark = all;
+            }
+          if (mark) cell(L, x, y, z) = 1;
+        }
+  }
+  // (ii) the composite dofs carrying the (approximately) `fraction` largest directional second
+  // derivatives |d^2 u / dx_i^2| (second differences on the dof's level), found by sorting the
+  // values into 1024 equal bins over [0, max] and taking whole bins from the top until they
+  // hold that fraction; their 2^d cells are refined unless the level is l_cap
+  struct Dof { int l; int x, y, z; double v; };
+  std::vector<Dof> dofs;
+  for (int l = c->lmin; l <= L; ++l) {
+    const int m = ipow3(l), nv = m + 1;
+    const double h2 = 1.0 / (double(m) * m);
+    for (size_t i = 0; i < comp[l].size(); ++i) {
+      if (!comp[l][i]) continue;
+      const int x = int(i % nv), y = int((i / nv) % nv), z = d == 3 ? int(i / (size_t(nv) * nv)) : 0;
+      const size_t st[3] = {1, size_t(nv), size_t(nv) * nv};
+      double v = 0.0;
+      for (int a = 0; a < d; ++a)
+        v = std::max(v, std::fabs(u[l][i + st[a]] - 2.0 * u[l][i] + u[l][i - st[a]]) / h2);
+      dofs.push_back(Dof{l, x, y, z, v});
+    }
+  }
+  if (!dofs.empty() && fraction > 0.0) {
+    double vmax = 0.0;
+    for (const Dof& q : dofs) vmax = std::max(vmax, q.v);
+    constexpr int kBins = 1024;
+    std::vector<size_t> cnt(kBins, 0);
+    auto bin = [&](double v) { return vmax > 0.0 ? std::min(kBins - 1, int(v / vmax * kBins)) : 0; };
+    for (const Dof& q : dofs) ++cnt[bin(q.v)];
+    const double want = fraction * double(dofs.size());
+    int cut = kBins;
+    size_t have = 0;
+    while (cut > 0 && double(have) < want) have += cnt[--cut];
+    for (const Dof& q : dofs) {
+      if (bin(q.v) < cut || q.l >= l_cap) continue;
+      for (int e = 0; e < (1 << d); ++e) {
+        const int cx = q.x - 1 + (e & 1), cy = q.y - 1 + ((e >> 1) & 1), cz = d == 3 ? q.z - 1 + ((e >> 2) & 1) : 0;
+        if (q.l >= l_uniform) cell(q.l, cx, cy, cz) = 1;
+      }
+    }
+  }
+  int top = L;
+  for (int l = l_uniform; l < l_cap; ++l) {
+    const size_t m = size_t(ipow3(l)), nc = d == 2 ? m * m : m * m * m;
+    for (size_t i = 0; i < nc; ++i)
+      if (flags[off[l] + i]) {
+        top = std::max(top, l + 1);
+        break;
+      }
+  }
+  *l_new = top;
+  return ADAFAC_OK;
+}
+
 int adafac_set_refinement(adafac_ctx* c, int level, const uint8_t* flags, size_t ncells) {
   if (!c) return ADAFAC_EINVAL;
   if (level < c->lmin || level >= c->L) return fail(c, ADAFAC_EINVAL, "level must lie in l_min..l_max-1");
