@@ -427,6 +427,72 @@ def paper_setups(Solver, torch, log=None, cycles=120):
     return out
 
 
+def paper_amr(Solver, torch, log=None, l_cap=8, max_cycles=300, fraction=0.1, every=2):
+    """The homogeneous set-up of Sec. 5 (f = 0, u = 1 on x_2 = 0) with the paper's dynamic
+    refinement: from l_max = 2, after every other cycle the next tree from adafac_amr_mark
+    (bottom-boundary cells until l_cap, cells around the ~10% largest second derivatives) with
+    the solution interpolated onto it, until a move no longer changes the tree; then cycles to
+    ||r||_h <= 1e-8 ||r^(0)||_h (r^(0): the first residual on the settled tree) or the cap.  Per
+    damping variant: cycles, depth, composite dofs, dof updates, and the normalised residual."""
+    import numpy as np
+    import adafac_inputs as inp
+    from paper_1903_10367_amd import AdafacError
+
+    def g_of(L):
+        return inp.paper_boundary(2, L)
+
+    # (exponential damping is not built for adaptive trees)
+    out = {"l_cap": l_cap, "fraction": fraction, "every": every, "max_cycles": max_cycles}
+    for damping in ("none", "pi", "jac"):
+        s = Solver(2, 1, 2, np.zeros_like(g_of(2)), dirichlet=g_of(2), damping=damping, omega_hat=0.5)
+        lu, prev, settled_at, r_settled = 2, None, None, None
+        updates, moves, status, n = 0, 0, "capped", 0
+        rel = float("nan")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            for n in range(max_cycles):
+                s.cycle(1)
+                updates += s.dofs_per_cycle()
+                l2 = s.residuals()[-1][0]
+                if settled_at is not None:
+                    if r_settled is None:
+                        r_settled = l2
+                    rel = l2 / r_settled if r_settled > 0 else 0.0
+                    if not np.isfinite(rel) or rel > 1e3:
+                        status = "diverged"
+                        break
+                    if rel <= 1e-8:
+                        status = "converged"
+                        break
+                elif (n + 1) % every == 0:
+                    flags, top = s.amr_mark(fraction, lu, l_cap)
+                    key = (top, tuple(np.packbits(flags[l]).tobytes() for l in sorted(flags)))
+                    if key == prev:
+                        settled_at = n + 1
+                        continue
+                    prev = key
+                    u, lold = s.solution(), s.lmax
+                    s2 = Solver(2, 1, top, np.zeros_like(g_of(top)), refine={l: flags[l] for l in range(lu, top)},
+                                dirichlet=g_of(top), damping=damping, omega_hat=0.5)
+                    s2.set_solution_coarse(u, lold)
+                    s.close()
+                    s, moves = s2, moves + 1
+        except AdafacError:
+            status = "diverged"
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res = {"status": status, "cycles": n + 1, "settled_after_cycles": settled_at, "moves": moves,
+               "depth": s.lmax, "composite_dofs": s.composite_dofs(), "dof_updates": int(updates),
+               "rel_residual_after_settling": rel, "seconds": dt}
+        s.close()
+        out[damping] = res
+        if log:
+            log(f"paper AMR {damping}: {status} after {res['cycles']} cycles (settled after {settled_at}), "
+                f"depth {res['depth']}, {res['composite_dofs']} dofs, rel. residual {rel:.2e}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -579,6 +645,7 @@ def main():
         out["adaptive"] = adaptive_workloads(Solver, torch, log)
     if args.paper_setups:
         out["paper_setups"] = paper_setups(Solver, torch, log)
+        out["paper_setups"]["amr"] = paper_amr(Solver, torch, log)
     if args.serve_requests > 0:
         loads = [float(x) for x in args.serve_loads.split(",") if x]
         out["serving"] = serving(Server, torch, args.serve_requests, loads, args.serve_budget_gb,
