@@ -101,6 +101,23 @@ struct SmallLevelsArgs {
   double* norm_out;        // nullptr: no norms in this launch
 };
 
+// A chain of prolongations S_k <- S_k + P (S_{k-1} - sub_{k-1}) for k = 1 .. nt in one launch
+// (see k_prolong_chain).  lv[0] is the source level (its S final), lv[k] the k-th target, lv[nt]
+// the top one; sub[k] (may be null) is subtracted from lv[k]'s values where they feed the next
+// prolongation, self (may be null) from the prolonged value at the top target's vertices.  The
+// top target is updated in place; an intermediate target k reads lv[k].S and writes its new
+// values to out[k] (other workgroups still read lv[k].S), whose boundary entries must hold
+// those of lv[k].S.
+constexpr int kMaxChain = 6;
+template <typename T>
+struct ProlongChainArgs {
+  LevelView<T> lv[kMaxChain + 1];
+  const T* sub[kMaxChain];
+  T* out[kMaxChain];
+  const T* self;
+  int nt;
+};
+
 // ---------------------------------------------------------------------------
 // Requests solved inside the batched work-queue kernel (continuous batching)
 // ---------------------------------------------------------------------------

@@ -51,6 +51,8 @@ hipError_t launch_defect3d(const LevelView<double>& F, int nc, int nvc, const do
                            unsigned long long need = 0);
 template <typename T>
 hipError_t launch_small_levels(int d, const SmallLevelsArgs<T>& a, size_t lds_bytes, hipStream_t s);
+template <typename T>
+hipError_t launch_prolong_chain(int d, const ProlongChainArgs<T>& a, hipStream_t s);
 hipError_t launch_zero_fill(void* p, size_t bytes, hipStream_t s);
 void static_ws_forget(const adafac_ctx* c);
 
@@ -83,6 +85,7 @@ struct Hier {
   T* bfine = nullptr;
   T* rfine = nullptr;
   T* eps = nullptr;
+  T* Salt[kMaxLevel + 1]{};  // second S of the levels below L-1: a prolongation chain's output
   RtSep<T> rts{};
   int cur = 0;
   bool pending = false;     // fused path: P S_{L-1} of the last cycle not yet added to the iterate
@@ -235,6 +238,7 @@ size_t layout(adafac_ctx* c, char* base) {
         v.S = reinterpret_cast<T*>(take(sizeof(T) * nvx));
         v.ic = reinterpret_cast<T*>(take(sizeof(T) * nvx));
         if (!hl.rtw.empty()) v.rtw = reinterpret_cast<T*>(take(sizeof(T) * hl.rtw.size()));
+        H.Salt[l] = l < c->L - 1 ? reinterpret_cast<T*>(take(sizeof(T) * nvx)) : nullptr;
       }
     }
     const size_t nvL = c->ops.lev[c->L].nverts;
@@ -376,10 +380,26 @@ int run_cycle(adafac_ctx* c, Hier<T>& H, double* norm_out, const T* uin_zero) {
   } else {
     HIPCHK(c, launch_norm_finalize(c->partials, nparts, norm_out, c->stream));
   }
-  for (int l = std::max(hi + 1, lmin + 1); l < L; ++l)
-    HIPCHK(c, launch_prolong_add<T>(d, H.v[l], H.v[l - 1], H.v[l].S, H.v[l - 1].S,
-                                    pi ? H.v[l - 1].ic : nullptr, c->stream,
-                                    (pi && fused && l == L - 1) ? H.v[l].ic : nullptr));
+  const int l0 = std::max(hi + 1, lmin + 1), nt = L - l0;
+  if (nt >= 2 && nt <= kMaxChain) {
+    // S_l += P S_{l-1} for l = l0 .. L-1 in one launch; the levels below L-1 get their new S in
+    // their second buffer, which then becomes their S
+    ProlongChainArgs<T> a{};
+    a.nt = nt;
+    for (int k = 0; k <= nt; ++k) a.lv[k] = H.v[l0 - 1 + k];
+    for (int k = 0; k < nt; ++k) {
+      a.sub[k] = pi ? H.v[l0 - 1 + k].ic : nullptr;
+      a.out[k] = k > 0 ? H.Salt[l0 - 1 + k] : nullptr;
+    }
+    a.self = (pi && fused) ? H.v[L - 1].ic : nullptr;
+    HIPCHK(c, launch_prolong_chain<T>(d, a, c->stream));
+    for (int l = l0; l < L - 1; ++l) std::swap(H.v[l].S, H.Salt[l]);
+  } else {
+    for (int l = l0; l < L; ++l)
+      HIPCHK(c, launch_prolong_add<T>(d, H.v[l], H.v[l - 1], H.v[l].S, H.v[l - 1].S,
+                                      pi ? H.v[l - 1].ic : nullptr, c->stream,
+                                      (pi && fused && l == L - 1) ? H.v[l].ic : nullptr));
+  }
   if (fused) {
     H.pending = true;        // P S_{L-1} enters the next sweep (or the flush)
   } else {

@@ -150,11 +150,13 @@ __device__ __forceinline__ T restrict_weight(const LevelView<T>& F, int fx, int 
   return F.pw[lin<D>(fx, fy, fz, F.nv) * (1 << D) + (ex | (ey << 1) | (ez << 2))];
 }
 
-// sum_c P(f <- c) (src(c) - sub(c)) at fine vertex f of level F from level C.
-template <typename T, int D>
-__device__ __forceinline__ T prolong_value(const LevelView<T>& F, const LevelView<T>& C, int x, int y, int z,
-                                           const T* __restrict__ src, const T* __restrict__ sub) {
-  const int nc = C.nv - 1;
+// sum_c P(f <- c) v(c) at fine vertex f (lattice of nvf vertices per axis, transfer weights pw
+// into it or nullptr: d-linear) from the coarse lattice of nvc vertices per axis, with
+// v(c) = fetch(cx, cy, cz).
+template <typename T, int D, typename Fetch>
+__device__ __forceinline__ T prolong_gather(const T* __restrict__ pw, int nvf, int nvc, int x, int y, int z,
+                                            Fetch&& fetch) {
+  const int nc = nvc - 1;
   const int cx = min(x / 3, nc - 1), cy = min(y / 3, nc - 1), cz = D == 3 ? min(z / 3, nc - 1) : 0;
   const int sx = x - 3 * cx, sy = y - 3 * cy, sz = z - 3 * cz;
   T acc = T(0);
@@ -162,21 +164,28 @@ __device__ __forceinline__ T prolong_value(const LevelView<T>& F, const LevelVie
   for (int e = 0; e < (1 << D); ++e) {
     const int ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
     T w;
-    if (!F.pw) {
+    if (!pw) {
       w = (ex ? T(sx) : T(3 - sx)) * T(1.0 / 3.0);
       w *= (ey ? T(sy) : T(3 - sy)) * T(1.0 / 3.0);
       if (D == 3) w *= (ez ? T(sz) : T(3 - sz)) * T(1.0 / 3.0);
     } else {
-      w = F.pw[lin<D>(x, y, z, F.nv) * (1 << D) + e];
+      w = pw[lin<D>(x, y, z, nvf) * (1 << D) + e];
     }
-    if (w != T(0)) {
-      size_t ci = lin<D>(cx + ex, cy + ey, cz + ez, C.nv);
-      T v = src[ci];
-      if (sub) v -= sub[ci];
-      acc += w * v;
-    }
+    if (w != T(0)) acc += w * fetch(cx + ex, cy + ey, cz + ez);
   }
   return acc;
+}
+
+// sum_c P(f <- c) (src(c) - sub(c)) at fine vertex f of level F from level C.
+template <typename T, int D>
+__device__ __forceinline__ T prolong_value(const LevelView<T>& F, const LevelView<T>& C, int x, int y, int z,
+                                           const T* __restrict__ src, const T* __restrict__ sub) {
+  return prolong_gather<T, D>(F.pw, F.nv, C.nv, x, y, z, [&](int X, int Y, int Z) {
+    const size_t ci = lin<D>(X, Y, Z, C.nv);
+    T v = src[ci];
+    if (sub) v -= sub[ci];
+    return v;
+  });
 }
 
 // FAS update of vertex i of coarse level C (next finer level F, next coarser level Cm).

@@ -146,6 +146,190 @@ __global__ void __launch_bounds__(256) k_prolong_add(LevelView<T> F, LevelView<T
   dst[i] += v;
 }
 
+// The prolongations of one cycle, S_k += P (S_{k-1} - sub_{k-1}) for k = 1 .. NT (Sec. 3.1: the
+// corrections of all levels summed down to the finest), in one launch instead of NT dependent
+// ones.  A workgroup owns a tile of the top target and first gathers, for every level below,
+// the region its tile's prolongations read (a level's region: the coarse vertices under the
+// finer region, plus one); all global loads of the chain are issued before the first barrier.
+// It then forms the levels' new S bottom-up in LDS (recomputing the few vertices its regions
+// share with the neighbouring tiles) and writes, to out[k], the intermediate levels' interior
+// vertices whose top-level image 3^(NT-k) x lies in its tile, so that each is written once.  The arithmetic per
+// vertex is prolong_add's, so the result is bitwise that of the NT single launches.
+template <int D>
+struct ChainTile {
+  static constexpr int X = D == 3 ? 27 : 81, Y = 9, Z = D == 3 ? 3 : 1;
+};
+// width of the coarse region under a finer region of width w (any offset, clamps included)
+constexpr int chain_grow(int w) { return (w - 1) / 3 + 3; }
+
+// What the chain reads of each level, packed small: every wave loads it at entry in one batch
+// of scalar loads (a kernel-argument block of full level views costs several dependent
+// scalar-cache round trips before the first vector load).
+template <typename T>
+struct ChainLevel {
+  T* S;
+  const T* sub;
+  T* out;
+  const T* pw;
+  int nv, pad;
+};
+template <typename T, int NT>
+struct ChainDev {
+  ChainLevel<T> lv[NT + 1];
+  const T* self;
+  int tiles0, tiles1;
+};
+
+template <typename T, int D, int NT>
+__global__ void __launch_bounds__(256) k_prolong_chain(ChainDev<T, NT> a) {
+  constexpr int TX = ChainTile<D>::X, TY = ChainTile<D>::Y, TZ = ChainTile<D>::Z;
+  constexpr int TILE = TX * TY * TZ;
+  constexpr int TOP = (TILE + 255) / 256;
+  // the widest region below the top: level NT-1 (regions shrink further down, 3 stays 3)
+  constexpr int CAP = chain_grow(TX) * chain_grow(TY) * (D == 3 ? chain_grow(TZ) : 1);
+  static_assert(CAP <= 256, "one region vertex per lane");
+  __shared__ T reg[NT][CAP];
+  const int tid = threadIdx.x;
+  int nv[NT + 1];
+  const T *sub[NT + 1], *pw[NT + 1];
+  T *S[NT + 1], *out[NT + 1];
+#pragma unroll
+  for (int k = 0; k <= NT; ++k) {
+    nv[k] = a.lv[k].nv;
+    S[k] = a.lv[k].S;
+    sub[k] = a.lv[k].sub;
+    pw[k] = a.lv[k].pw;
+    out[k] = a.lv[k].out;
+  }
+  const T* self = a.self;
+  int lo[NT + 1][3], w[NT + 1][3];
+  {
+    const int b = blockIdx.x, t0 = a.tiles0, t1 = a.tiles1;
+    lo[NT][0] = (b % t0) * TX;
+    lo[NT][1] = ((b / t0) % t1) * TY;
+    lo[NT][2] = D == 3 ? (b / (t0 * t1)) * TZ : 0;
+    w[NT][0] = min(TX, nv[NT] - lo[NT][0]);
+    w[NT][1] = min(TY, nv[NT] - lo[NT][1]);
+    w[NT][2] = D == 3 ? min(TZ, nv[NT] - lo[NT][2]) : 1;
+  }
+#pragma unroll
+  for (int k = NT - 1; k >= 0; --k) {
+    const int nc = nv[k] - 1;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      if (ax < D) {
+        const int c0 = min(lo[k + 1][ax] / 3, nc - 1);
+        const int c1 = min((lo[k + 1][ax] + w[k + 1][ax] - 1) / 3, nc - 1) + 1;
+        lo[k][ax] = c0;
+        w[k][ax] = c1 - c0 + 1;
+      } else {
+        lo[k][ax] = 0;
+        w[k][ax] = 1;
+      }
+    }
+  }
+  // this lane's vertex of each region below the top (global coordinates), if any
+  int rx[NT], ry[NT], rz[NT];
+  bool rin[NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) {
+    const int e = tid, w0 = w[k][0], w01 = w[k][0] * w[k][1];
+    rin[k] = e < w01 * w[k][2];
+    const int q = e / w0;
+    rx[k] = lo[k][0] + (e - q * w0);
+    ry[k] = lo[k][1] + q % w[k][1];
+    rz[k] = lo[k][2] + e / w01;
+  }
+  // all global loads first: the source values, the targets' S and sub, the top's S and self
+  T src0 = T(0), srcSub0 = T(0), rawS[NT], rawSub[NT], topS[TOP], topSelf[TOP];
+  if (rin[0]) {
+    const size_t gi = lin<D>(rx[0], ry[0], rz[0], nv[0]);
+    src0 = S[0][gi];
+    if (sub[0]) srcSub0 = sub[0][gi];
+  }
+#pragma unroll
+  for (int k = 1; k < NT; ++k) {
+    rawS[k] = T(0);
+    rawSub[k] = T(0);
+    if (rin[k]) {
+      const size_t gi = lin<D>(rx[k], ry[k], rz[k], nv[k]);
+      rawS[k] = S[k][gi];
+      if (sub[k]) rawSub[k] = sub[k][gi];
+    }
+  }
+  const int nvt = nv[NT];
+#pragma unroll
+  for (int j = 0; j < TOP; ++j) {
+    const int e = tid + 256 * j;
+    topS[j] = T(0);
+    topSelf[j] = T(0);
+    if (e < TILE) {
+      const int x = lo[NT][0] + e % TX, y = lo[NT][1] + (e / TX) % TY, z = lo[NT][2] + e / (TX * TY);
+      if (x < nvt && y < nvt && (D == 2 || z < nvt) && is_interior<D>(x, y, z, nvt)) {
+        const size_t gi = lin<D>(x, y, z, nvt);
+        topS[j] = S[NT][gi];
+        if (self) topSelf[j] = self[gi];
+      }
+    }
+  }
+  if (rin[0]) {
+    T v = src0;
+    if (sub[0]) v -= srcSub0;
+    reg[0][tid] = v;
+  }
+  __syncthreads();
+  // the intermediate targets, bottom-up; their global stores wait until after the last barrier
+  // (the memory counter that a later load waits on also counts stores)
+  T outv[NT];
+  size_t outi[NT];
+#pragma unroll
+  for (int k = 1; k < NT; ++k) {
+    outi[k] = ~size_t(0);
+    outv[k] = T(0);
+    if (rin[k]) {
+      const int x = rx[k], y = ry[k], z = rz[k];
+      T v = rawS[k];
+      if (is_interior<D>(x, y, z, nv[k])) {
+        v += prolong_gather<T, D>(pw[k], nv[k], nv[k - 1], x, y, z, [&](int X, int Y, int Z) {
+          return reg[k - 1][(X - lo[k - 1][0]) + w[k - 1][0] * ((Y - lo[k - 1][1]) + w[k - 1][1] * (Z - lo[k - 1][2]))];
+        });
+        // written by the tile that holds this vertex's image on the top level
+        int s = 1;
+#pragma unroll
+        for (int j = k; j < NT; ++j) s *= 3;
+        const bool own = s * x >= lo[NT][0] && s * x < lo[NT][0] + TX && s * y >= lo[NT][1] &&
+                         s * y < lo[NT][1] + TY && (D == 2 || (s * z >= lo[NT][2] && s * z < lo[NT][2] + TZ));
+        if (own) {
+          outi[k] = lin<D>(x, y, z, nv[k]);
+          outv[k] = v;
+        }
+      }
+      if (sub[k]) v -= rawSub[k];
+      reg[k][tid] = v;
+    }
+    __syncthreads();
+  }
+  // the top target
+#pragma unroll
+  for (int j = 0; j < TOP; ++j) {
+    const int e = tid + 256 * j;
+    if (e < TILE) {
+      const int x = lo[NT][0] + e % TX, y = lo[NT][1] + (e / TX) % TY, z = lo[NT][2] + e / (TX * TY);
+      if (x < nvt && y < nvt && (D == 2 || z < nvt) && is_interior<D>(x, y, z, nvt)) {
+        T v = prolong_gather<T, D>(pw[NT], nvt, nv[NT - 1], x, y, z, [&](int X, int Y, int Z) {
+          return reg[NT - 1][(X - lo[NT - 1][0]) +
+                             w[NT - 1][0] * ((Y - lo[NT - 1][1]) + w[NT - 1][1] * (Z - lo[NT - 1][2]))];
+        });
+        if (self) v -= topSelf[j];
+        S[NT][lin<D>(x, y, z, nvt)] = topS[j] + v;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 1; k < NT; ++k)
+    if (outi[k] != ~size_t(0)) out[k][outi[k]] = outv[k];
+}
+
 // FP32 cycles inside FP64 defect correction: the two FP64 steps of an outer iteration.
 //   accumulate  u <- u + (e + P S_{L-1}): the FP32 correction of the inner cycles (with the
 //               prolongation the fused sweep leaves pending) added to the FP64 solution
@@ -247,6 +431,50 @@ hipError_t launch_prolong_add(int d, const LevelView<T>& F, const LevelView<T>& 
     k_prolong_add<T, 3><<<nb, 256, 0, s>>>(F, C, dst, src, sub, self);
   return hipGetLastError();
 }
+
+template <typename T, int D, int NT>
+static hipError_t launch_chain_nt(const ProlongChainArgs<T>& a, hipStream_t s) {
+  ChainDev<T, NT> dv{};
+  for (int k = 0; k <= NT; ++k) {
+    dv.lv[k].S = a.lv[k].S;
+    dv.lv[k].sub = k < NT ? a.sub[k] : nullptr;
+    dv.lv[k].out = (k > 0 && k < NT) ? a.out[k] : nullptr;
+    dv.lv[k].pw = a.lv[k].pw;
+    dv.lv[k].nv = a.lv[k].nv;
+  }
+  dv.self = a.self;
+  const int n = a.lv[NT].nv - 1;   // cells of the top target: tiles cover vertices 0 .. n-1
+  dv.tiles0 = (n + ChainTile<D>::X - 1) / ChainTile<D>::X;
+  dv.tiles1 = (n + ChainTile<D>::Y - 1) / ChainTile<D>::Y;
+  const size_t nb = size_t(dv.tiles0) * dv.tiles1 * (D == 3 ? (n + ChainTile<D>::Z - 1) / ChainTile<D>::Z : 1);
+  if (nb >= (size_t(1) << 31)) return hipErrorInvalidValue;
+  k_prolong_chain<T, D, NT><<<unsigned(nb), 256, 0, s>>>(dv);
+  return hipGetLastError();
+}
+
+template <typename T, int D>
+static hipError_t launch_chain_d(const ProlongChainArgs<T>& a, hipStream_t s) {
+  switch (a.nt) {
+    case 2: return launch_chain_nt<T, D, 2>(a, s);
+    case 3: return launch_chain_nt<T, D, 3>(a, s);
+    case 4: return launch_chain_nt<T, D, 4>(a, s);
+    case 5: return launch_chain_nt<T, D, 5>(a, s);
+    case 6: return launch_chain_nt<T, D, 6>(a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+hipError_t launch_prolong_chain(int d, const ProlongChainArgs<T>& a, hipStream_t s) {
+  if (a.nt < 2 || a.nt > kMaxChain) return hipErrorInvalidValue;
+  for (int k = 0; k < a.nt; ++k)
+    if (a.lv[k + 1].nv - 1 != 3 * (a.lv[k].nv - 1) || !a.lv[k].S || (k > 0 && !a.out[k]))
+      return hipErrorInvalidValue;
+  if (!a.lv[a.nt].S) return hipErrorInvalidValue;
+  return d == 2 ? launch_chain_d<T, 2>(a, s) : launch_chain_d<T, 3>(a, s);
+}
+template hipError_t launch_prolong_chain<double>(int, const ProlongChainArgs<double>&, hipStream_t);
+template hipError_t launch_prolong_chain<float>(int, const ProlongChainArgs<float>&, hipStream_t);
 
 template <typename T>
 hipError_t launch_small_levels(int d, const SmallLevelsArgs<T>& a, size_t lds_bytes, hipStream_t s) {

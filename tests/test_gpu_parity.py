@@ -137,9 +137,11 @@ def test_pi_single_pass_and_one_kernel_per_step(d, L, fused):
     assert_parity(hg, ug, ho, uo, floor=lambda: oracle_floor(H, H.rhs(f), cycles, damping="pi"))
 
 
-@pytest.mark.parametrize("d,L,fused", [(2, 4, True), (3, 3, True), (3, 3, False)])
+@pytest.mark.parametrize("d,L,fused", [(2, 4, True), (3, 3, True), (3, 3, False), (3, 4, True), (2, 6, True),
+                                        (2, 6, False)])
 def test_level_arrays_match_fas_oracle(d, L, fused):
-    """u_l (injection), b_l (FAS rhs with tau), b~_l, r_l and S_l of the second cycle."""
+    """u_l (injection), b_l (FAS rhs with tau), b~_l, r_l and S_l of the second cycle (3D L=4
+    and 2D L=6 prolongate two and three levels in one chained launch)."""
     from paper_1903_10367_amd import Solver
     f = inp.rhs(d, L, seed=10)
     say("case level arrays", d, L, fused)
