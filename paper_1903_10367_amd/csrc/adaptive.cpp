@@ -4,6 +4,7 @@
 // level-6 3D tree touches about 10^7 cells and vertices per level).
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -28,6 +29,37 @@ bool cell_meets_ball(int d, const int* c, double h, const double* centre, double
 }
 
 }  // namespace
+
+// Runs over the vertices whose class has a bit of mask: disjoint windows of at most 64 box
+// vertices, each starting at the first such vertex rounded down to a multiple of 16 (not below
+// the previous run's end), in box order.  Unselected vertices inside a window are skipped by the
+// kernels' own class tests.  Eight class bytes at a time are skipped where none is selected.
+static void make_runs(const std::vector<uint8_t>& cls, uint8_t mask, std::vector<uint32_t>& out) {
+  out.clear();
+  const size_t n = cls.size();
+  uint64_t rep = 0;
+  for (int b = 0; b < 8; ++b) rep |= uint64_t(mask) << (8 * b);
+  size_t i = 0, prev = 0;
+  while (i < n) {
+    if (i + 8 <= n) {
+      uint64_t w;
+      std::memcpy(&w, &cls[i], 8);
+      if (!(w & rep)) {
+        i += 8;
+        continue;
+      }
+    }
+    if (!(cls[i] & mask)) {
+      ++i;
+      continue;
+    }
+    const size_t s = std::max(i & ~size_t(15), prev);
+    const size_t e = std::min(n, s + 64);
+    out.push_back(uint32_t(s));
+    out.push_back(uint32_t(e - s));
+    prev = i = e;
+  }
+}
 
 std::string build_adapt_tree(AdaptHost& t, int d, int lmin, int L, const std::vector<RefineSpec>& specs,
                              const double* centre, double radius, int l_from) {
@@ -177,6 +209,11 @@ std::string build_adapt_tree(AdaptHost& t, int d, int lmin, int L, const std::ve
       }
     });
     for (size_t k : part) t.composite += k;
+  }
+  for (int l = lmin; l <= L; ++l) {
+    AdaptHostLevel& A = t.lev[l];
+    make_runs(A.vcls, uint8_t(kDof | kHang), A.run);
+    make_runs(A.vcls, kHang, A.hrun);
   }
   return "";
 }

@@ -43,6 +43,9 @@ struct AdaptLevelT {
   T* S;                     // prolongated sum of corrections
   const T* pw;              // BoxMG transfer from the next coarser level into this one (a complete level):
                             // 2^d weights per vertex of the corners of its coarse cell, or nullptr: d-linear
+  const uint2* run;         // runs (first box vertex, count <= 64) covering every dof and hanging vertex
+  const uint2* hrun;        // the same for the hanging vertices alone
+  unsigned nrun, nhrun;
 };
 using AdaptLevel = AdaptLevelT<double>;
 
@@ -74,6 +77,10 @@ struct AdaptHostLevel {
   std::vector<uint8_t> exists, refined;        // over the cell box
   std::vector<uint8_t> vcls;                   // over the vertex box (nc + 1 per axis)
   std::vector<double> dg;                      // stored diagonal (Galerkin levels), vertex box
+  // runs of the vertex box, (first index, count) pairs in box order, disjoint, each at most 64
+  // vertices from a multiple of 16 on: every dof or hanging vertex (run), every hanging vertex
+  // (hrun).  The per-vertex kernels walk these instead of the whole box.
+  std::vector<uint32_t> run, hrun;
   size_t nverts() const;
   size_t ncells() const;
 };

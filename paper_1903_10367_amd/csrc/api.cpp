@@ -492,6 +492,10 @@ size_t layout_adaptive_tree(adafac_ctx* c, const AdaptHost& t, char* base) {
     A.u = reinterpret_cast<double*>(take(sizeof(double) * nv));
     A.bb = reinterpret_cast<double*>(take(sizeof(double) * nv));
     A.hh = reinterpret_cast<double*>(take(sizeof(double) * nv));
+    A.nrun = unsigned(H.run.size() / 2);
+    A.nhrun = unsigned(H.hrun.size() / 2);
+    A.run = reinterpret_cast<const uint2*>(take(sizeof(uint2) * A.nrun));
+    A.hrun = reinterpret_cast<const uint2*>(take(sizeof(uint2) * A.nhrun));
     const bool boxpw = adapt_pw_level(c, l);
     if (boxpw) A.pw = reinterpret_cast<double*>(take(sizeof(double) * nv << d));
     if (!mp) {
@@ -512,6 +516,10 @@ size_t layout_adaptive_tree(adafac_ctx* c, const AdaptHost& t, char* base) {
     E.eps = unit ? nullptr : eps32;
     E.vcls = A.vcls;
     E.leaf = A.leaf;
+    E.run = A.run;
+    E.hrun = A.hrun;
+    E.nrun = A.nrun;
+    E.nhrun = A.nhrun;
     E.dg = reinterpret_cast<float*>(take(sizeof(float) * nv));
     E.wc = reinterpret_cast<float*>(take(sizeof(float) * ncell));
     E.bleaf = reinterpret_cast<float*>(take(sizeof(float) * nv));
@@ -847,6 +855,12 @@ int bind_adaptive(adafac_ctx* c) {
     HIPCHK(c, hipMemcpyAsync(const_cast<uint8_t*>(A.vcls), H.vcls.data(), H.vcls.size(), hipMemcpyHostToDevice,
                              c->stream));
     HIPCHK(c, hipMemcpyAsync(const_cast<uint8_t*>(A.leaf), leaf.data(), leaf.size(), hipMemcpyHostToDevice, c->stream));
+    if (A.nrun)
+      HIPCHK(c, hipMemcpyAsync(const_cast<uint2*>(A.run), H.run.data(), sizeof(uint32_t) * H.run.size(),
+                               hipMemcpyHostToDevice, c->stream));
+    if (A.nhrun)
+      HIPCHK(c, hipMemcpyAsync(const_cast<uint2*>(A.hrun), H.hrun.data(), sizeof(uint32_t) * H.hrun.size(),
+                               hipMemcpyHostToDevice, c->stream));
     if (c->src_gauss) {
       GaussSource g{{c->src_c[0], c->src_c[1], c->src_c[2]}, c->src_sigma, c->src_amp};
       HIPCHK(c, launch_ad_gauss_load(d, A, g, c->stream));

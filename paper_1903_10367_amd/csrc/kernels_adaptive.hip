@@ -28,6 +28,15 @@ constexpr int NTA = 256;
 // eighth of the box per XCD, for L2 locality, measured slower for every kernel here.)
 #define AD_LOOP(i, nb) for (unsigned i = blockIdx.x * NTA + threadIdx.x; i < (nb); i += gridDim.x * NTA)
 
+// One wavefront per run of the level's run list (box vertices run.x .. run.x + run.y - 1, at
+// most 64), runs taken in box order by the grid as a whole (the same cache sharing of rows and
+// planes as above), empty corners of the box never read.  The body sees box vertex i and may
+// `continue` to the next run.
+#define AD_RUNS(i, RUNS, NRUN)                                                                  \
+  for (unsigned q_ = blockIdx.x * (NTA / 64) + (threadIdx.x >> 6); q_ < (NRUN);                 \
+       q_ += gridDim.x * (NTA / 64))                                                            \
+    for (unsigned i = (RUNS)[q_].x + (threadIdx.x & 63), e_ = (RUNS)[q_].x + (RUNS)[q_].y; i < e_; i = e_)
+
 template <int D, typename L>
 __device__ __forceinline__ long vidx(const L& A, int x, int y, int z) {
   x -= A.ox;
@@ -177,8 +186,7 @@ __device__ __forceinline__ T kref(int i, int j) {
 
 template <int D, typename T>
 __global__ void __launch_bounds__(NTA) k_ad_hang(AdaptLevelT<T> A, AdaptLevelT<T> C) {
-  const unsigned nb = nbox<D>(A);
-  AD_LOOP(i, nb) {
+  AD_RUNS(i, A.hrun, A.nhrun) {
     if (!(A.vcls[i] & kHang)) continue;
     int x, y, z;
     coords<D>(A, i, x, y, z);
@@ -332,9 +340,8 @@ __device__ __forceinline__ void up_finish(const AdaptLevelT<T>& A, unsigned i, u
 // in one pass, one thread per vertex.
 template <int D, typename T, int MODE>
 __global__ void __launch_bounds__(NTA) k_ad_leaf_up(AdaptLevelT<T> A, T omega, T omega_t, double* partials) {
-  const unsigned nb = nbox<D>(A);
   double ssum = 0.0, smax = 0.0;
-  AD_LOOP(i, nb) {
+  AD_RUNS(i, A.run, A.nrun) {
     const uint8_t cls = A.vcls[i];
     if (!(cls & (kDof | kHang))) continue;
     up_finish<T, MODE>(A, i, cls, leaf_residual<D>(A, i), T(0), T(0), T(0), 0, omega, omega_t, ssum, smax);
@@ -354,12 +361,12 @@ __global__ void __launch_bounds__(NTU) k_ad_up_f(AdaptLevelT<T> A, AdaptLevelT<T
   __shared__ T sh[3][4][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int o2 = wave - 2;                 // oz in 3D, oy in 2D
-  const unsigned nb = nbox<D>(A);
-  const unsigned ngroups = (nb + 63) / 64;
   double ssum = 0.0, smax = 0.0;
-  for (unsigned g = blockIdx.x; g < ngroups; g += gridDim.x) {
-    const unsigned i = g * 64 + lane;
-    const uint8_t cls = i < nb ? A.vcls[i] : uint8_t(0);
+  // one group of (at most) 64 vertices per run of the level's run list
+  for (unsigned g = blockIdx.x; g < A.nrun; g += gridDim.x) {
+    const uint2 run = A.run[g];
+    const unsigned i = run.x + lane;
+    const uint8_t cls = unsigned(lane) < run.y ? A.vcls[i] : uint8_t(0);
     T Rh = T(0), Rb = T(0), Rt = T(0);
     if (cls & (kDof | kHang)) {
       int x, y, z;
@@ -469,6 +476,21 @@ __global__ void __launch_bounds__(NTT) k_ad_up_tiled(AdaptLevelT<T> A, AdaptLeve
   const int bx0 = tx * TCX, by0 = ty * TCY, bz0 = tzc * TZC, bz1 = min(bz0 + TZC, A.mz);
   // finer-box coordinates of the tile's fine region (3 c - 2 .. 3 c + 2 around its columns)
   const int fx0 = 3 * (A.ox + bx0) - 2 - F.ox, fy0 = 3 * (A.oy + by0) - 2 - F.oy;
+  // a tile whose coarse block holds no dof or hanging vertex writes nothing: only its (zero) norm
+  // partials
+  {
+    int any = 0;
+    for (int k = tid; k < TCX * TCY * TZC; k += NTT) {
+      const int cx = bx0 + k % TCX, cy = by0 + (k / TCX) % TCY, cz = bz0 + k / (TCX * TCY);
+      if (cx < A.mx && cy < A.my && cz < bz1 &&
+          (A.vcls[(unsigned(cz) * unsigned(A.my) + unsigned(cy)) * unsigned(A.mx) + unsigned(cx)] & (kDof | kHang)))
+        any = 1;
+    }
+    if (!__syncthreads_or(any)) {
+      block_norm_partials(0.0, 0.0, partials);
+      return;
+    }
+  }
   const bool item = tid < TCX * TCY;
   const int icx = tid % TCX, icy = tid / TCX;
   const int cbx = bx0 + icx, cby = by0 + icy;
@@ -602,8 +624,7 @@ __device__ __forceinline__ void copy_down(const AdaptCopyView<T>& V, int l, int 
 template <int D, typename T, bool PI>
 __global__ void __launch_bounds__(NTA) k_ad_down_update(AdaptLevelT<T> A, AdaptLevelT<T> C, int has_c,
                                                         AdaptCopyView<T> V, int level, int keep_s) {
-  const unsigned nb = nbox<D>(A);
-  AD_LOOP(i, nb) {
+  AD_RUNS(i, A.run, A.nrun) {
     const uint8_t cls = A.vcls[i];
     if (!(cls & (kDof | kHang))) continue;
     int x, y, z;
@@ -702,8 +723,7 @@ __global__ void __launch_bounds__(NTA) k_ad_gauss_load(AdaptLevel A, GaussSource
 // iterate starts at zero.
 template <int D>
 __global__ void __launch_bounds__(NTA) k_ad_to_inner(AdaptLevel A, AdaptLevelT<float> E) {
-  const unsigned nb = nbox<D>(A);
-  AD_LOOP(i, nb) {
+  AD_RUNS(i, A.run, A.nrun) {
     if (!(A.vcls[i] & (kDof | kHang))) continue;
     E.bleaf[i] = float(A.bb[i]);
     E.u[i] = 0.f;
@@ -712,8 +732,7 @@ __global__ void __launch_bounds__(NTA) k_ad_to_inner(AdaptLevel A, AdaptLevelT<f
 
 template <int D>
 __global__ void __launch_bounds__(NTA) k_ad_accumulate(AdaptLevel A, AdaptLevelT<float> E) {
-  const unsigned nb = nbox<D>(A);
-  AD_LOOP(i, nb)
+  AD_RUNS(i, A.run, A.nrun)
     if (A.vcls[i] & kDof) A.u[i] += double(E.u[i]);
 }
 
@@ -723,6 +742,8 @@ unsigned blocks_of(long n, long per_block, long cap) {
 }
 
 unsigned grid_for(long nb) { return blocks_of(nb, NTA, 8192); }
+// one wavefront per run
+unsigned grid_runs(unsigned nrun) { return blocks_of(long(nrun), NTA / 64, 8192); }
 
 }  // namespace
 
@@ -786,9 +807,8 @@ unsigned adapt_up_blocks_f(long nb) { return blocks_of(nb, 64, kAdaptNormBlocks)
 
 template <typename T>
 hipError_t launch_ad_hang(int d, const AdaptLevelT<T>& A, const AdaptLevelT<T>& C, hipStream_t s) {
-  const long nb = long(A.mx) * A.my * (d == 3 ? A.mz : 1);
-  if (d == 2) k_ad_hang<2, T><<<grid_for(nb), NTA, 0, s>>>(A, C);
-  else k_ad_hang<3, T><<<grid_for(nb), NTA, 0, s>>>(A, C);
+  if (d == 2) k_ad_hang<2, T><<<grid_runs(A.nhrun), NTA, 0, s>>>(A, C);
+  else k_ad_hang<3, T><<<grid_runs(A.nhrun), NTA, 0, s>>>(A, C);
   return hipGetLastError();
 }
 
@@ -846,16 +866,15 @@ hipError_t launch_ad_leaf_up(int d, const AdaptLevelT<T>& A, T omega, T omega_t,
 template <typename T>
 hipError_t launch_ad_down_update(int d, const AdaptLevelT<T>& A, const AdaptLevelT<T>* C, const AdaptCopyView<T>& V,
                                  int level, int pi, int keep_s, hipStream_t s) {
-  const long nb = long(A.mx) * A.my * (d == 3 ? A.mz : 1);
   const AdaptLevelT<T> Cv = C ? *C : AdaptLevelT<T>{};
   const int hc = C ? 1 : 0;
   const int keep = keep_s ? 1 : 0;
   if (d == 2) {
-    if (pi) k_ad_down_update<2, T, true><<<grid_for(nb), NTA, 0, s>>>(A, Cv, hc, V, level, keep);
-    else k_ad_down_update<2, T, false><<<grid_for(nb), NTA, 0, s>>>(A, Cv, hc, V, level, keep);
+    if (pi) k_ad_down_update<2, T, true><<<grid_runs(A.nrun), NTA, 0, s>>>(A, Cv, hc, V, level, keep);
+    else k_ad_down_update<2, T, false><<<grid_runs(A.nrun), NTA, 0, s>>>(A, Cv, hc, V, level, keep);
   } else {
-    if (pi) k_ad_down_update<3, T, true><<<grid_for(nb), NTA, 0, s>>>(A, Cv, hc, V, level, keep);
-    else k_ad_down_update<3, T, false><<<grid_for(nb), NTA, 0, s>>>(A, Cv, hc, V, level, keep);
+    if (pi) k_ad_down_update<3, T, true><<<grid_runs(A.nrun), NTA, 0, s>>>(A, Cv, hc, V, level, keep);
+    else k_ad_down_update<3, T, false><<<grid_runs(A.nrun), NTA, 0, s>>>(A, Cv, hc, V, level, keep);
   }
   return hipGetLastError();
 }
@@ -883,16 +902,14 @@ hipError_t launch_ad_gauss_load(int d, const AdaptLevel& A, const GaussSource& g
 }
 
 hipError_t launch_ad_to_inner(int d, const AdaptLevel& A, const AdaptLevelT<float>& E, hipStream_t s) {
-  const long nb = long(A.mx) * A.my * (d == 3 ? A.mz : 1);
-  if (d == 2) k_ad_to_inner<2><<<grid_for(nb), NTA, 0, s>>>(A, E);
-  else k_ad_to_inner<3><<<grid_for(nb), NTA, 0, s>>>(A, E);
+  if (d == 2) k_ad_to_inner<2><<<grid_runs(A.nrun), NTA, 0, s>>>(A, E);
+  else k_ad_to_inner<3><<<grid_runs(A.nrun), NTA, 0, s>>>(A, E);
   return hipGetLastError();
 }
 
 hipError_t launch_ad_accumulate(int d, const AdaptLevel& A, const AdaptLevelT<float>& E, hipStream_t s) {
-  const long nb = long(A.mx) * A.my * (d == 3 ? A.mz : 1);
-  if (d == 2) k_ad_accumulate<2><<<grid_for(nb), NTA, 0, s>>>(A, E);
-  else k_ad_accumulate<3><<<grid_for(nb), NTA, 0, s>>>(A, E);
+  if (d == 2) k_ad_accumulate<2><<<grid_runs(A.nrun), NTA, 0, s>>>(A, E);
+  else k_ad_accumulate<3><<<grid_runs(A.nrun), NTA, 0, s>>>(A, E);
   return hipGetLastError();
 }
 
