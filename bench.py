@@ -338,7 +338,9 @@ def adaptive_workloads(Solver, torch, log=None):
         s = Solver(3, 1, 6, {"gaussian": (centres[0], sigma, 1.0)}, eps_blocks=eps3, ball=(centres[0], 3 * sigma, 3),
                    precision=prec, inner_k=4)
         dofs0 = s.dofs_per_cycle()
-        cyc, reg = [], []
+        # FP64: 32 B per finest dof and 64 B per coarser dof; FP32 inner cycles half of that
+        fine_b, coarse_b = (32, 64) if prec == "fp64" else (16, 32)
+        cyc, reg, rate = [], [], []
         for j, c in enumerate(centres):
             if j:
                 torch.cuda.synchronize()
@@ -346,11 +348,13 @@ def adaptive_workloads(Solver, torch, log=None):
                 s.regrid(c, 3 * sigma, 3)
                 torch.cuda.synchronize()
                 reg.append(time.perf_counter() - t0)
+            nbytes, _ = adaptive_bytes(s, fine_b, coarse_b)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             s.cycle(steps)
             torch.cuda.synchronize()
             cyc.append((time.perf_counter() - t0) / (steps * k))
+            rate.append(nbytes / cyc[-1])
         h = s.residuals()
         rel_moving = h[-1][0] / h[0][0]
         # time to solution on the last tree from zero
@@ -368,12 +372,24 @@ def adaptive_workloads(Solver, torch, log=None):
             "us_per_cycle": float(np.mean(cyc[1:])) * 1e6, "regrid_ms": float(np.mean(reg)) * 1e3,
             "regrids": len(reg), "cycles": steps * k * len(centres), "rel_residual_moving": rel_moving,
             "solve_1e-8_steps": n, "solve_1e-8_cycles": n * k, "solve_1e-8_ms": ts * 1e3,
-            "solve_rel_residual": hs[-1][0] / hs[0][0]}
+            "solve_rel_residual": hs[-1][0] / hs[0][0],
+            "roofline": {"bound": "hbm", "bytes_per_cycle_model": f"{fine_b} B per finest dof + {coarse_b} B per coarser dof",
+                         "achieved": float(np.mean(rate[1:])) / 1e9, "peak": 8000.0, "unit": "GB/s",
+                         "frac": float(np.mean(rate[1:])) / 8e12}}
         s.close()
         if log:
             log(f"adaptive 3D moving Gaussian {prec}: {np.mean(cyc[1:]) * 1e6:.1f} us/cycle, "
                 f"regrid {np.mean(reg) * 1e3:.1f} ms, solve {n} steps {ts * 1e3:.1f} ms")
     return out
+
+
+def adaptive_bytes(s, fine_b, coarse_b):
+    """Algorithmic bytes of one cycle on an adaptive tree: fine_b per dof of the finest level
+    (u read and written, the load, eps) and coarse_b per dof of every coarser level (u, b, b~ and S,
+    each written once and read once)."""
+    _, lev = s.dof_coords()
+    n_fine = int((lev == s.lmax).sum())
+    return fine_b * n_fine + coarse_b * (s.dofs_per_cycle() - n_fine), n_fine
 
 
 def paper_setups(Solver, torch, log=None, cycles=120):
@@ -512,6 +528,8 @@ def main():
                     help="print the GPU-busy fraction of the serving window of a rocprofv3 kernel trace and exit")
     ap.add_argument("--profile-pass", action="store_true",
                     help="counter runs: a 1 GiB device copy (byte-counter calibration), then a few cycles")
+    ap.add_argument("--profile-adaptive", action="store_true",
+                    help="counter runs: the 1 GiB copy, then a few FP64 cycles on the first 3D moving-Gaussian tree")
     args = ap.parse_args()
     if args.trace_busy:
         print(json.dumps(trace_busy(args.trace_busy)))
@@ -524,7 +542,7 @@ def main():
     import tempfile
     refdir = tempfile.mkdtemp(prefix="adafac_bench_")
     ref = pool = None
-    if not args.no_cpu_baseline and not args.profile_pass:
+    if not args.no_cpu_baseline and not args.profile_pass and not args.profile_adaptive:
         # the oracle reference solve runs in a child started before this process touches the GPU
         import concurrent.futures as cf
         import multiprocessing as mp
@@ -540,6 +558,23 @@ def main():
 
     w = inp.workload_3d_poisson_l5(seed=0)
     d, L = w["d"], w["L"]
+    if args.profile_adaptive:
+        src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        centres = inp.moving_source(seed=23, steps=4, d=3)
+        s = Solver(3, 1, 6, {"gaussian": (centres[0], 0.05, 1.0)}, eps_blocks=inp.eps_blocks(3, 3, 4.0, seed=24),
+                   ball=(centres[0], 0.15, 3))
+        nbytes, n_fine = adaptive_bytes(s, 32, 64)
+        s.cycle(args.steps)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_adaptive": True, "copy_bytes": COPY_BYTES, "cycles": args.steps,
+                          "dofs_per_cycle": s.dofs_per_cycle(), "finest_dofs": n_fine,
+                          "algorithmic_bytes_per_cycle": nbytes}), flush=True)
+        s.close()
+        return
     if args.profile_pass:
         src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)

@@ -183,7 +183,7 @@ def test_gaussian_source_moving_with_the_ball():
         assert abs(a[0] - b[0]) <= 1e-12 * ho[0][0], f"cycle {n}"
 
 
-@pytest.mark.parametrize("damping", ["jac", "none"])
+@pytest.mark.parametrize("damping", ["jac", "none", "pi"])
 @pytest.mark.parametrize("L", [3, 4])
 def test_3d_tiled_restriction(L, damping, monkeypatch):
     """The tiled 3D restriction (chosen from 256 tiles per level on large trees) on every level

@@ -92,12 +92,14 @@ def test_2d_bottom_strip_tree():
     run_both(2, 5, 2, g, flags=bottom_strip_flags(2, 5, 2), cycles=8)
 
 
-def test_3d_ball_touching_the_boundary_reproduces_a_trilinear_function():
+@pytest.mark.parametrize("tiled", ["256", "0"])
+def test_3d_ball_touching_the_boundary_reproduces_a_trilinear_function(tiled, monkeypatch):
     """A 3D tree whose refined cells reach the boundary, with the data of a harmonic trilinear
     p: parity with the oracle per cycle, and a solve that reproduces p (it lies in the composite
-    space)."""
+    space); also with the tiled restriction on every level."""
     from paper_1903_10367_amd import Solver
-    say("case adaptive Dirichlet 3d ball, trilinear data")
+    monkeypatch.setenv("ADAFAC_AD_TILED_MIN_TILES", tiled)
+    say("case adaptive Dirichlet 3d ball, trilinear data, tiled from", tiled)
     d, L, lu = 3, 3, 1
     p = bilinear(d, L)
     ball = ((0.45, 0.5, 0.55), 0.2)
