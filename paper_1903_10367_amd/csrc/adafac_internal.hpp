@@ -83,6 +83,25 @@ struct RtSep {
   T scale;
 };
 
+// Pipelined solve: the cycles of a batch are launched without a host wait.  The launch of cycle
+// `need` does nothing once *stop <= need; the kernel that forms a cycle's residual norms applies
+// the stopping rule and, when it holds, writes *stop = that cycle's index + 1, so the cycle that
+// met it still completes and every later one is skipped.  stop = nullptr: no gating.
+struct Gate {
+  const unsigned long long* stop;
+  unsigned long long need;
+};
+// The stopping rule of a solve, applied on the device to the norms of cycle `need`: stop once
+// ||r||_h <= tol ||r^0||_h (or ||r^0||_h = 0), or when ||r||_h is not finite or above 1e3 ||r^0||_h
+// (the host then reports divergence).  r0 = nullptr with first = 1: this cycle's own norm is r^0.
+struct StopRule {
+  unsigned long long* stop;
+  unsigned long long need;
+  double tol;
+  const double* r0;
+  int first;
+};
+
 // The smallest levels lo..hi handled by one workgroup (see k_small_levels).  lv[j] is the
 // view of level lo-1+j (lv[0]: level lo-1, empty when lo is the coarsest; lv[hi-lo+2]: the
 // next finer level hi+1).
@@ -99,6 +118,8 @@ struct SmallLevelsArgs {
   const double* partials;
   int nparts;
   double* norm_out;        // nullptr: no norms in this launch
+  Gate gate;
+  StopRule rule;           // rule.stop = nullptr: no stopping rule
 };
 
 // A chain of prolongations S_k <- S_k + P (S_{k-1} - sub_{k-1}) for k = 1 .. nt in one launch
@@ -116,6 +137,7 @@ struct ProlongChainArgs {
   T* out[kMaxChain];
   const T* self;
   int nt;
+  Gate gate;
 };
 
 // ---------------------------------------------------------------------------

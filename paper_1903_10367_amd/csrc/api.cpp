@@ -20,15 +20,16 @@ namespace adafac {
 template <typename T>
 hipError_t launch_fine_residual(int d, const LevelView<T>& F, const T* uin, T* uout, const T* b, T* r,
                                 T* ic_coarse, int nvc, T omega, int pi, double* partials, int nblocks,
-                                hipStream_t s);
+                                hipStream_t s, Gate g = Gate{});
 template <typename T>
 hipError_t launch_level_update(int d, const LevelView<T>& C, const LevelView<T>& F, const LevelView<T>& Cm,
                                const RtSep<T>& rt, T omega, T omega_t, T cscale, int damping, int gather,
-                               hipStream_t s);
+                               hipStream_t s, Gate g = Gate{});
 template <typename T>
 hipError_t launch_prolong_add(int d, const LevelView<T>& F, const LevelView<T>& C, T* dst, const T* src,
-                              const T* sub, hipStream_t s, const T* self = nullptr);
-hipError_t launch_norm_finalize(const double* partials, int n, double* out, hipStream_t s);
+                              const T* sub, hipStream_t s, const T* self = nullptr, Gate g = Gate{});
+hipError_t launch_norm_finalize(const double* partials, int n, double* out, hipStream_t s, Gate g = Gate{},
+                                StopRule rule = StopRule{});
 hipError_t launch_stream_copy(const void* src, void* dst, size_t n16, hipStream_t s);
 hipError_t launch_accumulate(int d, const LevelView<float>& F, const LevelView<float>& C, double* u,
                              const float* e, const float* S, hipStream_t s);
@@ -43,7 +44,8 @@ size_t fine_sweep_partials(int d, int n);
 int fine_sweep_nparts(int d, int n);
 template <typename T>
 hipError_t launch_coarse_sweep(int d, const LevelView<T>& L, const LevelView<T>& C, const RtSep<T>& rts,
-                               T omega, T omega_t, T cscale, int damping, hipStream_t s);
+                               T omega, T omega_t, T cscale, int damping, hipStream_t s,
+                               const unsigned long long* stop = nullptr, unsigned long long need = 0);
 bool sweep_level_ok(int d, int n, int fem, bool has_pw);
 hipError_t launch_defect3d(const LevelView<double>& F, int nc, int nvc, const double* uin, double* uout,
                            const float* e, const float* S, const double* b, float* r32, double* partials,
@@ -86,6 +88,7 @@ struct Hier {
   T* rfine = nullptr;
   T* eps = nullptr;
   T* Salt[kMaxLevel + 1]{};  // second S of the levels below L-1: a prolongation chain's output
+  int swap_lo = 0, swap_hi = 0;   // levels whose S and Salt the last cycle swapped
   RtSep<T> rts{};
   int cur = 0;
   bool pending = false;     // fused path: P S_{L-1} of the last cycle not yet added to the iterate
@@ -117,6 +120,7 @@ struct adafac_ctx {
   double* norms = nullptr;  // (l2h, linf) per cycle or outer step, ring of kMaxHist
   double* scratch_norm = nullptr;
   double* norm0 = nullptr;  // (l2h, linf) of iterate 0, kept beyond the ring
+  unsigned long long* stopseq = nullptr;   // pipelined solve: first cycle index whose launches do nothing
   double r0 = -1.0;         // l2h of iterate 0 (host copy, set by solve)
   int ncyc = 0;
   // adaptive spacetree (set_refinement / refine_ball)
@@ -261,6 +265,7 @@ size_t layout(adafac_ctx* c, char* base) {
   c->norms = reinterpret_cast<double*>(take(sizeof(double) * 2 * kMaxHist));
   c->scratch_norm = reinterpret_cast<double*>(take(sizeof(double) * 2));
   c->norm0 = reinterpret_cast<double*>(take(sizeof(double) * 2));
+  c->stopseq = reinterpret_cast<unsigned long long*>(take(sizeof(unsigned long long)));
   return (off + 255) & ~size_t(255);
 }
 
@@ -303,9 +308,11 @@ constexpr int kCoarseSweepMinN = ADAFAC_COARSE_SWEEP_MIN_N;
 // One adAFAC cycle in the arithmetic of T on hierarchy H: residual (and norms into norm_out)
 // of the current finest iterate, FAS restriction cascade, coarse corrections, prolongation; the
 // next iterate lands in H.ufine[1 - H.cur].  uin_zero (may be nullptr) replaces the current
-// iterate by a zero lattice (first inner cycle of a defect-correction step).
+// iterate by a zero lattice (first inner cycle of a defect-correction step).  rule (may be
+// nullptr): a pipelined solve's cycle rule->need, every launch gated on rule->stop, the stopping
+// rule applied where the norms are formed.
 template <typename T>
-int run_cycle(adafac_ctx* c, Hier<T>& H, double* norm_out, const T* uin_zero) {
+int run_cycle(adafac_ctx* c, Hier<T>& H, double* norm_out, const T* uin_zero, const StopRule* rule = nullptr) {
   const int d = c->dim, L = c->L, lmin = c->lmin;
   const adafac_opts& o = c->opts;
   const int damping = o.damping;
@@ -330,13 +337,15 @@ int run_cycle(adafac_ctx* c, Hier<T>& H, double* norm_out, const T* uin_zero) {
   const bool opr = o.rtilde == ADAFAC_RTILDE_OPERATOR;
   const bool fused = o.fused && L > lmin && !opr && fused_ok(c) && (!pi || (L - 1 > lmin && L - 1 > hi));
   const bool pend = H.pending && !uin_zero;
+  const Gate gate = rule ? Gate{rule->stop, rule->need} : Gate{};
+  const StopRule norm_rule = rule ? *rule : StopRule{};
   if ((rc = record_start(c))) return rc;
   if (fused) {
     HIPCHK(c, launch_fine_sweep<T>(d, F, Lm1, uin, uout, H.bfine, H.rts, omega, damping, pend ? 1 : 0,
-                                   c->partials, &nparts, c->stream));
+                                   c->partials, &nparts, c->stream, gate.stop, gate.need));
   } else {
     HIPCHK(c, launch_fine_residual<T>(d, F, uin, uout, H.bfine, H.rfine, pi ? Lm1.ic : nullptr, Lm1.nv, omega,
-                                      pi, c->partials, kNormBlocks, c->stream));
+                                      pi, c->partials, kNormBlocks, c->stream, gate));
   }
   if ((rc = record_stop(c))) return rc;
   auto cscale_of = [&](int l) { return T(damping == ADAFAC_DAMP_EXP ? std::pow(o.omega_hat, L - l) : 1.0); };
@@ -346,13 +355,13 @@ int run_cycle(adafac_ctx* c, Hier<T>& H, double* norm_out, const T* uin_zero) {
                        sweep_level_ok(d, H.v[l].n, H.v[l].fem, H.v[l].pw != nullptr);
     if (sweep) {
       HIPCHK(c, launch_coarse_sweep<T>(d, H.v[l], H.v[l - 1], H.rts, omega, omega_t, cscale_of(l), damping,
-                                       c->stream));
+                                       c->stream, gate.stop, gate.need));
     } else {
       LevelView<T> Fv = H.v[l + 1];
       if (l + 1 == L) { Fv.u = const_cast<T*>(uin); Fv.r = H.rfine; }
       LevelView<T> Cm = l > lmin ? H.v[l - 1] : LevelView<T>{};
       HIPCHK(c, launch_level_update<T>(d, H.v[l], Fv, Cm, H.rts, omega, omega_t, cscale_of(l), damping,
-                                       fed ? 0 : 1, c->stream));
+                                       fed ? 0 : 1, c->stream, gate));
     }
     fed = sweep;
   }
@@ -376,9 +385,11 @@ int run_cycle(adafac_ctx* c, Hier<T>& H, double* norm_out, const T* uin_zero) {
     a.partials = c->partials;
     a.nparts = nparts;
     a.norm_out = norm_out;
+    a.gate = gate;
+    a.rule = norm_rule;
     HIPCHK(c, launch_small_levels<T>(d, a, 0, c->stream));
   } else {
-    HIPCHK(c, launch_norm_finalize(c->partials, nparts, norm_out, c->stream));
+    HIPCHK(c, launch_norm_finalize(c->partials, nparts, norm_out, c->stream, gate, norm_rule));
   }
   const int l0 = std::max(hi + 1, lmin + 1), nt = L - l0;
   if (nt >= 2 && nt <= kMaxChain) {
@@ -392,13 +403,16 @@ int run_cycle(adafac_ctx* c, Hier<T>& H, double* norm_out, const T* uin_zero) {
       a.out[k] = k > 0 ? H.Salt[l0 - 1 + k] : nullptr;
     }
     a.self = (pi && fused) ? H.v[L - 1].ic : nullptr;
+    a.gate = gate;
     HIPCHK(c, launch_prolong_chain<T>(d, a, c->stream));
     for (int l = l0; l < L - 1; ++l) std::swap(H.v[l].S, H.Salt[l]);
+    H.swap_lo = l0;
+    H.swap_hi = L - 1;
   } else {
     for (int l = l0; l < L; ++l)
       HIPCHK(c, launch_prolong_add<T>(d, H.v[l], H.v[l - 1], H.v[l].S, H.v[l - 1].S,
                                       pi ? H.v[l - 1].ic : nullptr, c->stream,
-                                      (pi && fused && l == L - 1) ? H.v[l].ic : nullptr));
+                                      (pi && fused && l == L - 1) ? H.v[l].ic : nullptr, gate));
   }
   if (fused) {
     H.pending = true;        // P S_{L-1} enters the next sweep (or the flush)
@@ -406,7 +420,7 @@ int run_cycle(adafac_ctx* c, Hier<T>& H, double* norm_out, const T* uin_zero) {
     H.pending = false;
     if (L > lmin)
       HIPCHK(c, launch_prolong_add<T>(d, H.v[L], H.v[L - 1], uout, H.v[L - 1].S,
-                                      pi ? H.v[L - 1].ic : nullptr, c->stream));
+                                      pi ? H.v[L - 1].ic : nullptr, c->stream, nullptr, gate));
   }
   H.cur = 1 - H.cur;
   return ADAFAC_OK;
@@ -1304,11 +1318,92 @@ int adafac_residual(adafac_ctx* c, int cycle, double* l2h, double* linf) {
   return ADAFAC_OK;
 }
 
+// FP64 cycles on a uniform hierarchy, launched in batches without a host wait: the stopping rule
+// is applied on the device where each cycle's norms are formed, and the launches of the cycles
+// after the one that met it do nothing (Gate).  After each batch the host reads how many cycles
+// ran and takes back its per-cycle bookkeeping of the skipped ones (iterate buffer, swapped S
+// buffers).  The iterates are those of one cycle per host check.  The first batch has
+// kSolveBatch cycles; the next ones as many as the contraction of the last cycles predicts until
+// the tolerance (at most kSolveBatchMax), so that few batches end and few launches are skipped.
+constexpr int kSolveBatch = 8, kSolveBatchMax = 64;
+
+// cycles still needed after the last one of the history (norms of cycles n - k .. n - 1 in the ring)
+int predict_cycles(const adafac_ctx* c, const double* nrm, int k, double rel_tol) {
+  if (k < 2 || !(c->r0 > 0.0)) return kSolveBatch;
+  const int j = std::min(k - 1, 4);
+  const double last = nrm[2 * (k - 1)], prev = nrm[2 * (k - 1 - j)];
+  if (!(last > 0.0) || !(prev > last)) return kSolveBatch;
+  const double rho = std::pow(last / prev, 1.0 / j);
+  const double need = std::log(rel_tol * c->r0 / last) / std::log(rho);
+  if (!std::isfinite(need)) return kSolveBatch;
+  return std::max(1, std::min(kSolveBatchMax, int(std::ceil(need))));
+}
+
+int solve_pipelined(adafac_ctx* c, double rel_tol, int max_cycles, int* done_out) {
+  Hier<double>& H = c->h64;
+  static const unsigned long long never = ~0ull;
+  int done = 0, rc = ADAFAC_OK, next = kSolveBatch;
+  HIPCHK(c, hipMemcpyAsync(c->stopseq, &never, sizeof(never), hipMemcpyHostToDevice, c->stream));
+  while (done < max_cycles) {
+    const int n0 = c->ncyc, batch = std::min({next, max_cycles - done, kMaxHist});
+    for (int b = 0; b < batch; ++b) {
+      double* norm_out = c->norms + 2 * (c->ncyc % kMaxHist);
+      const StopRule rule{c->stopseq, static_cast<unsigned long long>(c->ncyc), rel_tol, c->norm0, c->ncyc == 0};
+      if ((rc = run_cycle<double>(c, H, norm_out, nullptr, &rule))) break;
+      if (c->ncyc == 0)
+        HIPCHK(c, hipMemcpyAsync(c->norm0, norm_out, 2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      c->ncyc += 1;
+    }
+    if (rc) break;
+    unsigned long long stop = never;
+    HIPCHK(c, hipMemcpyAsync(&stop, c->stopseq, sizeof(stop), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int ran = stop == never ? batch : int(stop - static_cast<unsigned long long>(n0));
+    if (ran < 1 || ran > batch) return fail(c, ADAFAC_EINVAL, "internal: stop counter out of the batch");
+    if ((batch - ran) & 1) {
+      H.cur = 1 - H.cur;
+      for (int l = H.swap_lo; l < H.swap_hi; ++l) std::swap(H.v[l].S, H.Salt[l]);
+    }
+    c->ncyc = n0 + ran;
+    done += ran;
+    if (c->r0 < 0) {
+      HIPCHK(c, hipMemcpyAsync(&c->r0, c->norm0, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    if (stop != never) {
+      double l2 = 0, li = 0;
+      if ((rc = adafac_residual(c, c->ncyc - 1, &l2, &li))) break;
+      if (!std::isfinite(l2) || l2 > 1e3 * c->r0) rc = fail(c, ADAFAC_EDIVERGED, "residual diverged");
+      break;
+    }
+    // the norms of the batch's cycles (consecutive slots of the ring, or two pieces)
+    std::vector<double> nrm(2 * size_t(ran));
+    const int s0 = n0 % kMaxHist, k1 = std::min(ran, kMaxHist - s0);
+    HIPCHK(c, hipMemcpyAsync(nrm.data(), c->norms + 2 * s0, 2 * sizeof(double) * k1, hipMemcpyDeviceToHost,
+                             c->stream));
+    if (k1 < ran)
+      HIPCHK(c, hipMemcpyAsync(&nrm[2 * size_t(k1)], c->norms, 2 * sizeof(double) * (ran - k1),
+                               hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    next = predict_cycles(c, nrm.data(), ran, rel_tol);
+  }
+  *done_out = done;
+  return rc;
+}
+
 int adafac_solve(adafac_ctx* c, double rel_tol, int max_cycles, int* cycles_done) {
   if (!c) return ADAFAC_EINVAL;
   if (!ready(c)) return fail(c, ADAFAC_ESTATE, "bind first");
   if (!(rel_tol >= 0.0) || max_cycles < 0) return fail(c, ADAFAC_EINVAL, "bad tolerance or cycle cap");
   int done = 0, rc = ADAFAC_OK;
+  if (!c->adaptive && !mixed(c)) {
+    rc = solve_pipelined(c, rel_tol, max_cycles, &done);
+    if (cycles_done) *cycles_done = done;
+    int frc = flush(c);
+    if (!rc) rc = frc;
+    if (!rc) HIPCHK(c, hipStreamSynchronize(c->stream));
+    return rc;
+  }
   for (; done < max_cycles; ++done) {
     // norms of iterate ncyc (FP64 cycle or FP64 defect of the outer iterate)
     if ((rc = run_outer(c))) break;

@@ -275,6 +275,21 @@ __device__ __forceinline__ void level_update_vertex(const LevelView<T>& C, const
   C.S[i] = s;
 }
 
+// A launch of a pipelined solve's cycle after the one that met the stopping rule does nothing
+// (uniform over the launch).
+__device__ __forceinline__ bool gated(const Gate& g) { return g.stop && g.need >= *g.stop; }
+
+// The stopping rule on the norms (l2h, linf) a cycle has just formed (one thread); it is applied
+// once (a later cycle, were its launch not gated, would leave *stop alone).
+__device__ __forceinline__ void apply_stop_rule(const StopRule& r, const double* norm) {
+  if (!r.stop || r.need >= *r.stop) return;
+  const double l2 = norm[0];
+  const double r0 = r.first ? l2 : r.r0[0];
+  const bool diverged = !isfinite(l2) || l2 > 1e3 * r0;
+  const bool met = r0 == 0.0 || l2 / r0 <= r.tol;
+  if (diverged || met) *r.stop = r.need + 1;
+}
+
 // Block-wide (up to 1024 threads) sum and max; thread 0 writes (sum, max) to partials[2*blockIdx.x].
 __device__ __forceinline__ void block_norm_partials(double ssum, double smax, double* partials) {
   __shared__ double ws[16], wm[16];

@@ -1192,12 +1192,13 @@ bool sweep_level_ok(int d, int n, int fem, bool has_pw) {
 // into it) in one tiled pass that also restricts into the next coarser level C.
 template <typename T>
 hipError_t launch_coarse_sweep(int d, const LevelView<T>& L, const LevelView<T>& C, const RtSep<T>& rts,
-                               T omega, T omega_t, T cscale, int damping, hipStream_t s) {
+                               T omega, T omega_t, T cscale, int damping, hipStream_t s,
+                               const unsigned long long* stop, unsigned long long need) {
   if (d != 3 || L.n % TX || L.pw || !L.fem) return hipErrorInvalidValue;
   const int n = L.n, ntx = n / TX, tz = pick_tz(n), ntz = n / tz;
   Sweep3dArgs<T> a{L.u, nullptr, L.rr, C.S, C.u, C.rr, C.bt, L.eps, nullptr, L.h, omega, L.hd, rts,
                    n, L.nv, C.n, C.nv, L.nb, L.bs, tz, ntx, ntz, damping, 0,
-                   1, L.bt, L.S, L.bf, L.r, omega_t, cscale, nullptr};
+                   1, L.bt, L.S, L.bf, L.r, omega_t, cscale, nullptr, stop, need};
   if (damping == ADAFAC_DAMP_PI) {
     if (!C.ic) return hipErrorInvalidValue;
     a.ic = C.ic;
@@ -1272,9 +1273,11 @@ hipError_t launch_defect3d(const LevelView<double>& F, int nc, int nvc, const do
 }
 
 template hipError_t launch_coarse_sweep<double>(int, const LevelView<double>&, const LevelView<double>&,
-                                                const RtSep<double>&, double, double, double, int, hipStream_t);
+                                                const RtSep<double>&, double, double, double, int, hipStream_t,
+                                                const unsigned long long*, unsigned long long);
 template hipError_t launch_coarse_sweep<float>(int, const LevelView<float>&, const LevelView<float>&,
-                                               const RtSep<float>&, float, float, float, int, hipStream_t);
+                                               const RtSep<float>&, float, float, float, int, hipStream_t,
+                                               const unsigned long long*, unsigned long long);
 template hipError_t launch_fine_sweep<double>(int, const LevelView<double>&, const LevelView<double>&,
                                               const double*, double*, const double*, const RtSep<double>&,
                                               double, int, int, double*, int*, hipStream_t,

@@ -24,7 +24,8 @@ __global__ void __launch_bounds__(256) k_fine_residual(LevelView<T> F, const T* 
                                                        T* __restrict__ uout, const T* __restrict__ b,
                                                        T* __restrict__ r, T* __restrict__ ic_coarse,
                                                        int nvc, T omega, int pi,
-                                                       double* __restrict__ partials) {
+                                                       double* __restrict__ partials, Gate g) {
+  if (gated(g)) return;
   const int nv = F.nv;
   const size_t nverts = D == 2 ? size_t(nv) * nv : size_t(nv) * nv * nv;
   double ssum = 0.0, smax = 0.0;
@@ -52,7 +53,8 @@ __global__ void __launch_bounds__(256) k_fine_residual(LevelView<T> F, const T* 
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_level_update(LevelView<T> C, LevelView<T> F, LevelView<T> Cm,
                                                       RtSep<T> rts, T omega, T omega_t, T cscale,
-                                                      int damping, int gather) {
+                                                      int damping, int gather, Gate g) {
+  if (gated(g)) return;
   const size_t nverts = D == 2 ? size_t(C.nv) * C.nv : size_t(C.nv) * C.nv * C.nv;
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= nverts) return;
@@ -71,6 +73,7 @@ static_assert(kSmallThreads % 64 == 0 && kSmallThreads <= 1024, "whole wavefront
 
 template <typename T, int D>
 __global__ void __launch_bounds__(kSmallThreads) k_small_levels(SmallLevelsArgs<T> a) {
+  if (gated(a.gate)) return;
   const int tid = threadIdx.x;
   const int lo = a.lo, hi = a.hi;
   auto nverts_of = [](const LevelView<T>& v) {
@@ -102,6 +105,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_levels(SmallLevelsArgs<
       }
       a.norm_out[0] = sqrt(st);
       a.norm_out[1] = mt;
+      apply_stop_rule(a.rule, a.norm_out);
     }
   }
   for (int l = hi; l >= lo; --l) {
@@ -132,7 +136,8 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_levels(SmallLevelsArgs<
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_prolong_add(LevelView<T> F, LevelView<T> C, T* __restrict__ dst,
                                                      const T* __restrict__ src, const T* __restrict__ sub,
-                                                     const T* __restrict__ self) {
+                                                     const T* __restrict__ self, Gate g) {
+  if (gated(g)) return;
   // lattices here stay below 2^32 vertices (the launcher checks): 32-bit index arithmetic
   const unsigned nv = unsigned(F.nv);
   const unsigned nverts = D == 2 ? nv * nv : nv * nv * nv;
@@ -178,10 +183,12 @@ struct ChainDev {
   ChainLevel<T> lv[NT + 1];
   const T* self;
   int tiles0, tiles1;
+  Gate gate;
 };
 
 template <typename T, int D, int NT>
 __global__ void __launch_bounds__(256) k_prolong_chain(ChainDev<T, NT> a) {
+  if (gated(a.gate)) return;
   constexpr int TX = ChainTile<D>::X, TY = ChainTile<D>::Y, TZ = ChainTile<D>::Z;
   constexpr int TILE = TX * TY * TZ;
   constexpr int TOP = (TILE + 255) / 256;
@@ -397,38 +404,38 @@ hipError_t launch_defect(int d, const LevelView<double>& F, const double* u, con
 template <typename T>
 hipError_t launch_fine_residual(int d, const LevelView<T>& F, const T* uin, T* uout, const T* b, T* r,
                                 T* ic_coarse, int nvc, T omega, int pi, double* partials, int nblocks,
-                                hipStream_t s) {
+                                hipStream_t s, Gate g) {
   if (d == 2)
-    k_fine_residual<T, 2><<<nblocks, 256, 0, s>>>(F, uin, uout, b, r, ic_coarse, nvc, omega, pi, partials);
+    k_fine_residual<T, 2><<<nblocks, 256, 0, s>>>(F, uin, uout, b, r, ic_coarse, nvc, omega, pi, partials, g);
   else
-    k_fine_residual<T, 3><<<nblocks, 256, 0, s>>>(F, uin, uout, b, r, ic_coarse, nvc, omega, pi, partials);
+    k_fine_residual<T, 3><<<nblocks, 256, 0, s>>>(F, uin, uout, b, r, ic_coarse, nvc, omega, pi, partials, g);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_level_update(int d, const LevelView<T>& C, const LevelView<T>& F, const LevelView<T>& Cm,
                                const RtSep<T>& rt, T omega, T omega_t, T cscale, int damping, int gather,
-                               hipStream_t s) {
+                               hipStream_t s, Gate g) {
   size_t nverts = d == 2 ? size_t(C.nv) * C.nv : size_t(C.nv) * C.nv * C.nv;
   if (nverts >= (size_t(1) << 32)) return hipErrorInvalidValue;
   unsigned nb = unsigned((nverts + 255) / 256);
   if (d == 2)
-    k_level_update<T, 2><<<nb, 256, 0, s>>>(C, F, Cm, rt, omega, omega_t, cscale, damping, gather);
+    k_level_update<T, 2><<<nb, 256, 0, s>>>(C, F, Cm, rt, omega, omega_t, cscale, damping, gather, g);
   else
-    k_level_update<T, 3><<<nb, 256, 0, s>>>(C, F, Cm, rt, omega, omega_t, cscale, damping, gather);
+    k_level_update<T, 3><<<nb, 256, 0, s>>>(C, F, Cm, rt, omega, omega_t, cscale, damping, gather, g);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_prolong_add(int d, const LevelView<T>& F, const LevelView<T>& C, T* dst, const T* src,
-                              const T* sub, hipStream_t s, const T* self) {
+                              const T* sub, hipStream_t s, const T* self, Gate g) {
   size_t nverts = d == 2 ? size_t(F.nv) * F.nv : size_t(F.nv) * F.nv * F.nv;
   if (nverts >= (size_t(1) << 32)) return hipErrorInvalidValue;
   unsigned nb = unsigned((nverts + 255) / 256);
   if (d == 2)
-    k_prolong_add<T, 2><<<nb, 256, 0, s>>>(F, C, dst, src, sub, self);
+    k_prolong_add<T, 2><<<nb, 256, 0, s>>>(F, C, dst, src, sub, self, g);
   else
-    k_prolong_add<T, 3><<<nb, 256, 0, s>>>(F, C, dst, src, sub, self);
+    k_prolong_add<T, 3><<<nb, 256, 0, s>>>(F, C, dst, src, sub, self, g);
   return hipGetLastError();
 }
 
@@ -443,6 +450,7 @@ static hipError_t launch_chain_nt(const ProlongChainArgs<T>& a, hipStream_t s) {
     dv.lv[k].nv = a.lv[k].nv;
   }
   dv.self = a.self;
+  dv.gate = a.gate;
   const int n = a.lv[NT].nv - 1;   // cells of the top target: tiles cover vertices 0 .. n-1
   dv.tiles0 = (n + ChainTile<D>::X - 1) / ChainTile<D>::X;
   dv.tiles1 = (n + ChainTile<D>::Y - 1) / ChainTile<D>::Y;
@@ -488,7 +496,8 @@ template hipError_t launch_small_levels<double>(int, const SmallLevelsArgs<doubl
 template hipError_t launch_small_levels<float>(int, const SmallLevelsArgs<float>&, size_t, hipStream_t);
 
 __global__ void __launch_bounds__(256) k_norm_finalize(const double* __restrict__ partials, int n,
-                                                       double* __restrict__ out) {
+                                                       double* __restrict__ out, Gate g, StopRule rule) {
+  if (gated(g)) return;
   __shared__ double ss[256], sm[256];
   double s = 0.0, m = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) {
@@ -508,6 +517,7 @@ __global__ void __launch_bounds__(256) k_norm_finalize(const double* __restrict_
   if (threadIdx.x == 0) {
     out[0] = sqrt(ss[0]);
     out[1] = sm[0];
+    apply_stop_rule(rule, out);
   }
 }
 
@@ -523,26 +533,27 @@ hipError_t launch_stream_copy(const void* src, void* dst, size_t n16, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_norm_finalize(const double* partials, int n, double* out, hipStream_t s) {
-  k_norm_finalize<<<1, 256, 0, s>>>(partials, n, out);
+hipError_t launch_norm_finalize(const double* partials, int n, double* out, hipStream_t s, Gate g, StopRule rule) {
+  k_norm_finalize<<<1, 256, 0, s>>>(partials, n, out, g, rule);
   return hipGetLastError();
 }
 
 template hipError_t launch_fine_residual<double>(int, const LevelView<double>&, const double*, double*,
                                                  const double*, double*, double*, int, double, int, double*,
-                                                 int, hipStream_t);
+                                                 int, hipStream_t, Gate);
 template hipError_t launch_fine_residual<float>(int, const LevelView<float>&, const float*, float*,
                                                 const float*, float*, float*, int, float, int, double*, int,
-                                                hipStream_t);
+                                                hipStream_t, Gate);
 template hipError_t launch_level_update<double>(int, const LevelView<double>&, const LevelView<double>&,
                                                 const LevelView<double>&, const RtSep<double>&, double, double,
-                                                double, int, int, hipStream_t);
+                                                double, int, int, hipStream_t, Gate);
 template hipError_t launch_level_update<float>(int, const LevelView<float>&, const LevelView<float>&,
                                                const LevelView<float>&, const RtSep<float>&, float, float, float,
-                                               int, int, hipStream_t);
+                                               int, int, hipStream_t, Gate);
 template hipError_t launch_prolong_add<double>(int, const LevelView<double>&, const LevelView<double>&,
-                                               double*, const double*, const double*, hipStream_t, const double*);
+                                               double*, const double*, const double*, hipStream_t, const double*,
+                                               Gate);
 template hipError_t launch_prolong_add<float>(int, const LevelView<float>&, const LevelView<float>&, float*,
-                                              const float*, const float*, hipStream_t, const float*);
+                                              const float*, const float*, hipStream_t, const float*, Gate);
 
 }  // namespace adafac

@@ -233,3 +233,41 @@ def test_divergence_is_reported():
         s.solve(1e-8, 200)
     assert e.value.code == 5
     s.close()
+
+
+@pytest.mark.parametrize("d,L,damping,fused,cap", [(3, 4, "jac", True, 100), (2, 5, "jac", True, 13),
+                                                   (2, 5, "pi", True, 100), (3, 3, "jac", False, 100),
+                                                   (2, 6, "jac", False, 100)])
+def test_pipelined_solve_matches_a_check_after_every_cycle(d, L, damping, fused, cap):
+    """adafac_solve launches FP64 cycles in batches and stops them on the device: the cycle count,
+    every norm and the solution are bitwise those of running one cycle at a time and checking the
+    relative residual after each (also when the cap ends a batch early, and for a second solve
+    that continues the first)."""
+    from paper_1903_10367_amd import Solver
+    f = inp.rhs(d, L, seed=40 + d + L)
+    say("case pipelined solve", d, L, damping, fused, cap)
+    s1 = Solver(d, 1, L, f, damping=damping, fused=fused)
+    n1a = s1.solve(1e-4, cap)
+    n1b = s1.solve(1e-9, cap)
+    h1 = s1.residuals()
+    u1 = s1.solution()
+    s1.close()
+    s2 = Solver(d, 1, L, f, damping=damping, fused=fused)
+    counts = []
+    for tol in (1e-4, 1e-9):
+        n = 0
+        while n < cap:
+            s2.cycle(1)
+            n += 1
+            k = len(s2.residuals()) - 1
+            if s2.residual(k)[0] / s2.residual(0)[0] <= tol:
+                break
+        counts.append(n)
+        s2.solution()   # a solve ends by adding the pending coarse correction; so does this read
+    h2 = s2.residuals()
+    u2 = s2.solution()
+    s2.close()
+    say(f"cycles {n1a} + {n1b} / {counts}")
+    assert [n1a, n1b] == counts
+    assert h1 == h2
+    assert np.array_equal(u1, u2)
