@@ -19,13 +19,13 @@
 
 namespace adafac {
 
-template <typename T, int D>
+template <typename T, int D, bool G>
 __global__ void __launch_bounds__(256) k_fine_residual(LevelView<T> F, const T* __restrict__ uin,
                                                        T* __restrict__ uout, const T* __restrict__ b,
                                                        T* __restrict__ r, T* __restrict__ ic_coarse,
                                                        int nvc, T omega, int pi,
                                                        double* __restrict__ partials, Gate g) {
-  if (gated(g)) return;
+  if (G && gated(g)) return;
   const int nv = F.nv;
   const size_t nverts = D == 2 ? size_t(nv) * nv : size_t(nv) * nv * nv;
   double ssum = 0.0, smax = 0.0;
@@ -50,11 +50,11 @@ __global__ void __launch_bounds__(256) k_fine_residual(LevelView<T> F, const T* 
   block_norm_partials(ssum, smax, partials);
 }
 
-template <typename T, int D>
+template <typename T, int D, bool G>
 __global__ void __launch_bounds__(256) k_level_update(LevelView<T> C, LevelView<T> F, LevelView<T> Cm,
                                                       RtSep<T> rts, T omega, T omega_t, T cscale,
                                                       int damping, int gather, Gate g) {
-  if (gated(g)) return;
+  if (G && gated(g)) return;
   const size_t nverts = D == 2 ? size_t(C.nv) * C.nv : size_t(C.nv) * C.nv * C.nv;
   size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= nverts) return;
@@ -71,9 +71,9 @@ __global__ void __launch_bounds__(256) k_level_update(LevelView<T> C, LevelView<
 constexpr int kSmallThreads = ADAFAC_SMALL_THREADS;
 static_assert(kSmallThreads % 64 == 0 && kSmallThreads <= 1024, "whole wavefronts, at most 16");
 
-template <typename T, int D>
+template <typename T, int D, bool G>
 __global__ void __launch_bounds__(kSmallThreads) k_small_levels(SmallLevelsArgs<T> a) {
-  if (gated(a.gate)) return;
+  if (G && gated(a.gate)) return;
   const int tid = threadIdx.x;
   const int lo = a.lo, hi = a.hi;
   auto nverts_of = [](const LevelView<T>& v) {
@@ -105,7 +105,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_levels(SmallLevelsArgs<
       }
       a.norm_out[0] = sqrt(st);
       a.norm_out[1] = mt;
-      apply_stop_rule(a.rule, a.norm_out);
+      if (G) apply_stop_rule(a.rule, a.norm_out);
     }
   }
   for (int l = hi; l >= lo; --l) {
@@ -133,11 +133,11 @@ __global__ void __launch_bounds__(kSmallThreads) k_small_levels(SmallLevelsArgs<
 
 // dst(f) += sum_c P(f <- c) (src(c) - sub(c)) - self(f) on the interior vertices of level F
 // (sub, self may be null).
-template <typename T, int D>
+template <typename T, int D, bool G>
 __global__ void __launch_bounds__(256) k_prolong_add(LevelView<T> F, LevelView<T> C, T* __restrict__ dst,
                                                      const T* __restrict__ src, const T* __restrict__ sub,
                                                      const T* __restrict__ self, Gate g) {
-  if (gated(g)) return;
+  if (G && gated(g)) return;
   // lattices here stay below 2^32 vertices (the launcher checks): 32-bit index arithmetic
   const unsigned nv = unsigned(F.nv);
   const unsigned nverts = D == 2 ? nv * nv : nv * nv * nv;
@@ -186,9 +186,9 @@ struct ChainDev {
   Gate gate;
 };
 
-template <typename T, int D, int NT>
+template <typename T, int D, int NT, bool G>
 __global__ void __launch_bounds__(256) k_prolong_chain(ChainDev<T, NT> a) {
-  if (gated(a.gate)) return;
+  if (G && gated(a.gate)) return;
   constexpr int TX = ChainTile<D>::X, TY = ChainTile<D>::Y, TZ = ChainTile<D>::Z;
   constexpr int TILE = TX * TY * TZ;
   constexpr int TOP = (TILE + 255) / 256;
@@ -405,10 +405,13 @@ template <typename T>
 hipError_t launch_fine_residual(int d, const LevelView<T>& F, const T* uin, T* uout, const T* b, T* r,
                                 T* ic_coarse, int nvc, T omega, int pi, double* partials, int nblocks,
                                 hipStream_t s, Gate g) {
-  if (d == 2)
-    k_fine_residual<T, 2><<<nblocks, 256, 0, s>>>(F, uin, uout, b, r, ic_coarse, nvc, omega, pi, partials, g);
-  else
-    k_fine_residual<T, 3><<<nblocks, 256, 0, s>>>(F, uin, uout, b, r, ic_coarse, nvc, omega, pi, partials, g);
+#define AD_FR(DD, GG) k_fine_residual<T, DD, GG><<<nblocks, 256, 0, s>>>(F, uin, uout, b, r, ic_coarse, nvc, omega, pi, partials, g)
+  if (d == 2) {
+    if (g.stop) AD_FR(2, true); else AD_FR(2, false);
+  } else {
+    if (g.stop) AD_FR(3, true); else AD_FR(3, false);
+  }
+#undef AD_FR
   return hipGetLastError();
 }
 
@@ -419,10 +422,13 @@ hipError_t launch_level_update(int d, const LevelView<T>& C, const LevelView<T>&
   size_t nverts = d == 2 ? size_t(C.nv) * C.nv : size_t(C.nv) * C.nv * C.nv;
   if (nverts >= (size_t(1) << 32)) return hipErrorInvalidValue;
   unsigned nb = unsigned((nverts + 255) / 256);
-  if (d == 2)
-    k_level_update<T, 2><<<nb, 256, 0, s>>>(C, F, Cm, rt, omega, omega_t, cscale, damping, gather, g);
-  else
-    k_level_update<T, 3><<<nb, 256, 0, s>>>(C, F, Cm, rt, omega, omega_t, cscale, damping, gather, g);
+#define AD_LU(DD, GG) k_level_update<T, DD, GG><<<nb, 256, 0, s>>>(C, F, Cm, rt, omega, omega_t, cscale, damping, gather, g)
+  if (d == 2) {
+    if (g.stop) AD_LU(2, true); else AD_LU(2, false);
+  } else {
+    if (g.stop) AD_LU(3, true); else AD_LU(3, false);
+  }
+#undef AD_LU
   return hipGetLastError();
 }
 
@@ -432,10 +438,13 @@ hipError_t launch_prolong_add(int d, const LevelView<T>& F, const LevelView<T>& 
   size_t nverts = d == 2 ? size_t(F.nv) * F.nv : size_t(F.nv) * F.nv * F.nv;
   if (nverts >= (size_t(1) << 32)) return hipErrorInvalidValue;
   unsigned nb = unsigned((nverts + 255) / 256);
-  if (d == 2)
-    k_prolong_add<T, 2><<<nb, 256, 0, s>>>(F, C, dst, src, sub, self, g);
-  else
-    k_prolong_add<T, 3><<<nb, 256, 0, s>>>(F, C, dst, src, sub, self, g);
+#define AD_PA(DD, GG) k_prolong_add<T, DD, GG><<<nb, 256, 0, s>>>(F, C, dst, src, sub, self, g)
+  if (d == 2) {
+    if (g.stop) AD_PA(2, true); else AD_PA(2, false);
+  } else {
+    if (g.stop) AD_PA(3, true); else AD_PA(3, false);
+  }
+#undef AD_PA
   return hipGetLastError();
 }
 
@@ -456,7 +465,10 @@ static hipError_t launch_chain_nt(const ProlongChainArgs<T>& a, hipStream_t s) {
   dv.tiles1 = (n + ChainTile<D>::Y - 1) / ChainTile<D>::Y;
   const size_t nb = size_t(dv.tiles0) * dv.tiles1 * (D == 3 ? (n + ChainTile<D>::Z - 1) / ChainTile<D>::Z : 1);
   if (nb >= (size_t(1) << 31)) return hipErrorInvalidValue;
-  k_prolong_chain<T, D, NT><<<unsigned(nb), 256, 0, s>>>(dv);
+  if (a.gate.stop)
+    k_prolong_chain<T, D, NT, true><<<unsigned(nb), 256, 0, s>>>(dv);
+  else
+    k_prolong_chain<T, D, NT, false><<<unsigned(nb), 256, 0, s>>>(dv);
   return hipGetLastError();
 }
 
@@ -486,18 +498,23 @@ template hipError_t launch_prolong_chain<float>(int, const ProlongChainArgs<floa
 
 template <typename T>
 hipError_t launch_small_levels(int d, const SmallLevelsArgs<T>& a, size_t lds_bytes, hipStream_t s) {
-  if (d == 2)
-    k_small_levels<T, 2><<<1, kSmallThreads, lds_bytes, s>>>(a);
-  else
-    k_small_levels<T, 3><<<1, kSmallThreads, lds_bytes, s>>>(a);
+  const bool g = a.gate.stop || a.rule.stop;
+  if (d == 2) {
+    if (g) k_small_levels<T, 2, true><<<1, kSmallThreads, lds_bytes, s>>>(a);
+    else k_small_levels<T, 2, false><<<1, kSmallThreads, lds_bytes, s>>>(a);
+  } else {
+    if (g) k_small_levels<T, 3, true><<<1, kSmallThreads, lds_bytes, s>>>(a);
+    else k_small_levels<T, 3, false><<<1, kSmallThreads, lds_bytes, s>>>(a);
+  }
   return hipGetLastError();
 }
 template hipError_t launch_small_levels<double>(int, const SmallLevelsArgs<double>&, size_t, hipStream_t);
 template hipError_t launch_small_levels<float>(int, const SmallLevelsArgs<float>&, size_t, hipStream_t);
 
+template <bool G>
 __global__ void __launch_bounds__(256) k_norm_finalize(const double* __restrict__ partials, int n,
                                                        double* __restrict__ out, Gate g, StopRule rule) {
-  if (gated(g)) return;
+  if (G && gated(g)) return;
   __shared__ double ss[256], sm[256];
   double s = 0.0, m = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) {
@@ -517,7 +534,7 @@ __global__ void __launch_bounds__(256) k_norm_finalize(const double* __restrict_
   if (threadIdx.x == 0) {
     out[0] = sqrt(ss[0]);
     out[1] = sm[0];
-    apply_stop_rule(rule, out);
+    if (G) apply_stop_rule(rule, out);
   }
 }
 
@@ -534,7 +551,10 @@ hipError_t launch_stream_copy(const void* src, void* dst, size_t n16, hipStream_
 }
 
 hipError_t launch_norm_finalize(const double* partials, int n, double* out, hipStream_t s, Gate g, StopRule rule) {
-  k_norm_finalize<<<1, 256, 0, s>>>(partials, n, out, g, rule);
+  if (g.stop || rule.stop)
+    k_norm_finalize<true><<<1, 256, 0, s>>>(partials, n, out, g, rule);
+  else
+    k_norm_finalize<false><<<1, 256, 0, s>>>(partials, n, out, g, rule);
   return hipGetLastError();
 }
 
