@@ -100,6 +100,7 @@ struct StopRule {
   double tol;
   const double* r0;
   int first;
+  int apply;               // 0: the launches are gated only (the inner cycles of FP32_REFINED)
 };
 
 // The smallest levels lo..hi handled by one workgroup (see k_small_levels).  lv[j] is the

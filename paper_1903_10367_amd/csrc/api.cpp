@@ -654,13 +654,17 @@ int run_adapt_outer_mixed(adafac_ctx* c, double* norm_out) {
 // FP64 form: one cycle.  FP32_REFINED: the FP64 part of an outer step, i.e. the pending inner
 // correction added to u and the FP64 defect r = b - A u with its norms (the norms of the outer
 // iterate), stored in FP32 as the right-hand side of the next inner solve.
-int run_outer(adafac_ctx* c) {
+// rule (may be nullptr): a pipelined solve's step (uniform FP64, or the one-pass 3D
+// FP32_REFINED outer step), gated and applying the stopping rule.
+int run_outer(adafac_ctx* c, const StopRule* rule = nullptr) {
   double* norm_out = c->norms + 2 * (c->ncyc % kMaxHist);
+  const Gate gate = rule ? Gate{rule->stop, rule->need} : Gate{};
+  const StopRule norm_rule = rule ? *rule : StopRule{};
   if (c->adaptive) {
     int rc = mixed(c) ? run_adapt_outer_mixed(c, norm_out) : run_adapt_cycle<double>(c, c->ad, c->ad_rts, norm_out);
     if (rc) return rc;
   } else if (!mixed(c)) {
-    int rc = run_cycle<double>(c, c->h64, norm_out, nullptr);
+    int rc = run_cycle<double>(c, c->h64, norm_out, nullptr, rule);
     if (rc) return rc;
   } else if (c->dim == 3 && c->opts.fused && fused_ok(c)) {
     // one pass: u' = u + e + P S into the other FP64 buffer, and the FP64 defect of u'
@@ -671,12 +675,14 @@ int run_outer(adafac_ctx* c) {
     const LevelView<float> C = L > c->lmin ? H.v[L - 1] : LevelView<float>{};
     int nparts = 0;
     HIPCHK(c, launch_defect3d(D.v[L], C.n, C.nv, D.ufine[D.cur], D.ufine[1 - D.cur], H.ufine[H.cur],
-                              mode == 2 ? C.S : nullptr, D.bfine, H.bfine, c->partials, mode, &nparts, c->stream));
-    HIPCHK(c, launch_norm_finalize(c->partials, nparts, norm_out, c->stream));
+                              mode == 2 ? C.S : nullptr, D.bfine, H.bfine, c->partials, mode, &nparts, c->stream,
+                              gate.stop, gate.need));
+    HIPCHK(c, launch_norm_finalize(c->partials, nparts, norm_out, c->stream, gate, norm_rule));
     D.cur = 1 - D.cur;
     H.pending = false;
     c->e_pending = false;
   } else {
+    if (rule) return fail(c, ADAFAC_EINVAL, "internal: this outer step is not pipelined");
     int rc = flush(c);
     if (rc) return rc;
     HIPCHK(c, launch_defect(c->dim, c->h64.v[c->L], c->h64.ufine[c->h64.cur], c->h64.bfine, c->h32.bfine,
@@ -690,7 +696,8 @@ int run_outer(adafac_ctx* c) {
 }
 
 // FP32_REFINED: inner_k FP32 cycles on A e = r from e = 0; the correction stays pending.
-int run_inner(adafac_ctx* c) {
+// gate (may be nullptr): a pipelined solve's gate for these cycles (no stopping rule).
+int run_inner(adafac_ctx* c, const StopRule* gate = nullptr) {
   if (c->adaptive) {
     for (int j = 0; j < c->opts.inner_k; ++j) {
       int rc = run_adapt_cycle<float>(c, c->ad32, c->ad_rts32, c->scratch_norm);
@@ -702,7 +709,7 @@ int run_inner(adafac_ctx* c) {
   Hier<float>& H = c->h32;
   H.pending = false;
   for (int j = 0; j < c->opts.inner_k; ++j) {
-    int rc = run_cycle<float>(c, H, c->scratch_norm, j == 0 ? c->ezero : nullptr);
+    int rc = run_cycle<float>(c, H, c->scratch_norm, j == 0 ? c->ezero : nullptr, gate);
     if (rc) return rc;
   }
   c->e_pending = true;
@@ -1339,30 +1346,56 @@ int predict_cycles(const adafac_ctx* c, const double* nrm, int k, double rel_tol
   return std::max(1, std::min(kSolveBatchMax, int(std::ceil(need))));
 }
 
+// Can adafac_solve pipeline this context?  Uniform FP64, and the one-pass 3D FP32_REFINED form
+// (an outer step and its inner cycles per batch entry); ADAFAC_SOLVE_HOST_CHECK=1 forces the check
+// on the host after every step (the tests compare both).
+bool solve_pipelines(const adafac_ctx* c) {
+  if (c->adaptive) return false;
+  if (const char* e = std::getenv("ADAFAC_SOLVE_HOST_CHECK"))
+    if (std::atoi(e) != 0) return false;
+  return !mixed(c) || (c->dim == 3 && c->opts.fused && fused_ok(c));
+}
+
 int solve_pipelined(adafac_ctx* c, double rel_tol, int max_cycles, int* done_out) {
-  Hier<double>& H = c->h64;
+  Hier<double>& D = c->h64;
+  Hier<float>& H = c->h32;
+  const bool mp = mixed(c);
+  const int k = c->opts.inner_k;
   static const unsigned long long never = ~0ull;
   int done = 0, rc = ADAFAC_OK, next = kSolveBatch;
   HIPCHK(c, hipMemcpyAsync(c->stopseq, &never, sizeof(never), hipMemcpyHostToDevice, c->stream));
   while (done < max_cycles) {
     const int n0 = c->ncyc, batch = std::min({next, max_cycles - done, kMaxHist});
     for (int b = 0; b < batch; ++b) {
-      double* norm_out = c->norms + 2 * (c->ncyc % kMaxHist);
-      const StopRule rule{c->stopseq, static_cast<unsigned long long>(c->ncyc), rel_tol, c->norm0, c->ncyc == 0};
-      if ((rc = run_cycle<double>(c, H, norm_out, nullptr, &rule))) break;
-      if (c->ncyc == 0)
-        HIPCHK(c, hipMemcpyAsync(c->norm0, norm_out, 2 * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-      c->ncyc += 1;
+      const StopRule rule{c->stopseq, static_cast<unsigned long long>(c->ncyc), rel_tol, c->norm0, c->ncyc == 0, 1};
+      if ((rc = run_outer(c, &rule))) break;
+      if (mp) {
+        // the inner solve of step n runs unless step n met the rule: gated as step n + 1
+        const StopRule g{c->stopseq, static_cast<unsigned long long>(c->ncyc), 0.0, nullptr, 0, 0};
+        if ((rc = run_inner(c, &g))) break;
+      }
     }
     if (rc) break;
     unsigned long long stop = never;
     HIPCHK(c, hipMemcpyAsync(&stop, c->stopseq, sizeof(stop), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    const int ran = stop == never ? batch : int(stop - static_cast<unsigned long long>(n0));
+    const bool stopped = stop != never;
+    const int ran = stopped ? int(stop - static_cast<unsigned long long>(n0)) : batch;
     if (ran < 1 || ran > batch) return fail(c, ADAFAC_EINVAL, "internal: stop counter out of the batch");
-    if ((batch - ran) & 1) {
-      H.cur = 1 - H.cur;
-      for (int l = H.swap_lo; l < H.swap_hi; ++l) std::swap(H.v[l].S, H.Salt[l]);
+    // take back the host bookkeeping of what the device skipped
+    if (!mp) {
+      if ((batch - ran) & 1) {
+        D.cur = 1 - D.cur;
+        for (int l = D.swap_lo; l < D.swap_hi; ++l) std::swap(D.v[l].S, D.Salt[l]);
+      }
+    } else if (stopped) {
+      if ((batch - ran) & 1) D.cur = 1 - D.cur;                 // outer steps: one buffer flip each
+      if (((batch - (ran - 1)) * k) & 1) {                      // inner cycles: one flip and swap each
+        H.cur = 1 - H.cur;
+        for (int l = H.swap_lo; l < H.swap_hi; ++l) std::swap(H.v[l].S, H.Salt[l]);
+      }
+      H.pending = false;                                        // the last step ran its outer part only
+      c->e_pending = false;
     }
     c->ncyc = n0 + ran;
     done += ran;
@@ -1370,13 +1403,13 @@ int solve_pipelined(adafac_ctx* c, double rel_tol, int max_cycles, int* done_out
       HIPCHK(c, hipMemcpyAsync(&c->r0, c->norm0, sizeof(double), hipMemcpyDeviceToHost, c->stream));
       HIPCHK(c, hipStreamSynchronize(c->stream));
     }
-    if (stop != never) {
+    if (stopped) {
       double l2 = 0, li = 0;
       if ((rc = adafac_residual(c, c->ncyc - 1, &l2, &li))) break;
       if (!std::isfinite(l2) || l2 > 1e3 * c->r0) rc = fail(c, ADAFAC_EDIVERGED, "residual diverged");
       break;
     }
-    // the norms of the batch's cycles (consecutive slots of the ring, or two pieces)
+    // the norms of the batch's steps (consecutive slots of the ring, or two pieces)
     std::vector<double> nrm(2 * size_t(ran));
     const int s0 = n0 % kMaxHist, k1 = std::min(ran, kMaxHist - s0);
     HIPCHK(c, hipMemcpyAsync(nrm.data(), c->norms + 2 * s0, 2 * sizeof(double) * k1, hipMemcpyDeviceToHost,
@@ -1396,7 +1429,7 @@ int adafac_solve(adafac_ctx* c, double rel_tol, int max_cycles, int* cycles_done
   if (!ready(c)) return fail(c, ADAFAC_ESTATE, "bind first");
   if (!(rel_tol >= 0.0) || max_cycles < 0) return fail(c, ADAFAC_EINVAL, "bad tolerance or cycle cap");
   int done = 0, rc = ADAFAC_OK;
-  if (!c->adaptive && !mixed(c)) {
+  if (solve_pipelines(c)) {
     rc = solve_pipelined(c, rel_tol, max_cycles, &done);
     if (cycles_done) *cycles_done = done;
     int frc = flush(c);

@@ -282,7 +282,7 @@ __device__ __forceinline__ bool gated(const Gate& g) { return g.stop && g.need >
 // The stopping rule on the norms (l2h, linf) a cycle has just formed (one thread); it is applied
 // once (a later cycle, were its launch not gated, would leave *stop alone).
 __device__ __forceinline__ void apply_stop_rule(const StopRule& r, const double* norm) {
-  if (!r.stop || r.need >= *r.stop) return;
+  if (!r.stop || !r.apply || r.need >= *r.stop) return;
   const double l2 = norm[0];
   const double r0 = r.first ? l2 : r.r0[0];
   const bool diverged = !isfinite(l2) || l2 > 1e3 * r0;

@@ -271,3 +271,26 @@ def test_pipelined_solve_matches_a_check_after_every_cycle(d, L, damping, fused,
     assert [n1a, n1b] == counts
     assert h1 == h2
     assert np.array_equal(u1, u2)
+
+
+@pytest.mark.parametrize("k,cap,tols", [(4, 100, (1e-5, 1e-9)), (3, 100, (1e-9,)), (4, 3, (1e-9,))])
+def test_pipelined_fp32_refined_solve_matches_the_host_checked_one(k, cap, tols, monkeypatch):
+    """The one-pass 3D FP32_REFINED solve in batches (outer step and inner cycles gated, the inner
+    solve of the step that met the rule skipped): outer-step counts, norms and the solution bitwise
+    those of the solve that checks on the host after every outer step (ADAFAC_SOLVE_HOST_CHECK=1),
+    with an odd inner cycle count, a cap inside the first batch and a continued second solve."""
+    from paper_1903_10367_amd import Solver
+    d, L = 3, 4
+    f = inp.rhs(d, L, seed=61)
+    say("case pipelined fp32_refined solve, k", k, "cap", cap, "tols", tols)
+    out = []
+    for host_check in ("0", "1"):
+        monkeypatch.setenv("ADAFAC_SOLVE_HOST_CHECK", host_check)
+        s = Solver(d, 1, L, f, precision="fp32_refined", inner_k=k)
+        n = [s.solve(t, cap) for t in tols]
+        out.append((n, s.residuals(), s.solution()))
+        s.close()
+    say(f"steps {out[0][0]} / {out[1][0]}")
+    assert out[0][0] == out[1][0]
+    assert out[0][1] == out[1][1]
+    assert np.array_equal(out[0][2], out[1][2])
