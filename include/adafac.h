@@ -255,11 +255,14 @@ int adafac_cycle(adafac_ctx* ctx, int ncycles);
  * defect of its iterate and, unless it met the tolerance, runs inner_k FP32
  * cycles on A e = r; the solution afterwards is the last outer iterate (the one
  * whose FP64 residual met the tolerance when the solve converged).
- * FP64 form on a uniform hierarchy: the cycles are launched in batches of 8
- * without a host wait; the stopping rule is applied on the device where each
- * cycle's norms are formed, and the launches of the cycles after the one that met
- * it do nothing, so the cycle count, the norms and the solution are those of a
- * check after every cycle.
+ * Uniform hierarchies, FP64 and the one-pass 3D FP32_REFINED form: the cycles
+ * (outer steps with their inner cycles) are launched in batches without a host
+ * wait (8 first, then as many as the observed contraction predicts, at most 64);
+ * the stopping rule is applied on the device where each step's norms are formed,
+ * and the launches after the step that met it do nothing, so the step count, the
+ * norms and the solution are those of a check after every step.  The environment
+ * variable ADAFAC_SOLVE_HOST_CHECK=1 (read at each call) makes the host check
+ * after every step instead.
  * Synchronises.  EDIVERGED on NaN/Inf or growth beyond 1e3 x the initial norm. */
 int adafac_solve(adafac_ctx* ctx, double rel_tol, int max_cycles, int* cycles_done);
 
