@@ -160,9 +160,16 @@ __global__ void __launch_bounds__(256) k_prolong_add(LevelView<T> F, LevelView<T
 // share with the neighbouring tiles) and writes, to out[k], the intermediate levels' interior
 // vertices whose top-level image 3^(NT-k) x lies in its tile, so that each is written once.  The arithmetic per
 // vertex is prolong_add's, so the result is bitwise that of the NT single launches.
+#ifndef ADAFAC_CHAIN_TZ
+#define ADAFAC_CHAIN_TZ 3
+#endif
+#ifndef ADAFAC_CHAIN_THREADS
+#define ADAFAC_CHAIN_THREADS 512
+#endif
+constexpr int kChainThreads = ADAFAC_CHAIN_THREADS;
 template <int D>
 struct ChainTile {
-  static constexpr int X = D == 3 ? 27 : 81, Y = 9, Z = D == 3 ? 3 : 1;
+  static constexpr int X = D == 3 ? 27 : 81, Y = 9, Z = D == 3 ? ADAFAC_CHAIN_TZ : 1;
 };
 // width of the coarse region under a finer region of width w (any offset, clamps included)
 constexpr int chain_grow(int w) { return (w - 1) / 3 + 3; }
@@ -187,14 +194,15 @@ struct ChainDev {
 };
 
 template <typename T, int D, int NT, bool G>
-__global__ void __launch_bounds__(256) k_prolong_chain(ChainDev<T, NT> a) {
+__global__ void __launch_bounds__(kChainThreads) k_prolong_chain(ChainDev<T, NT> a) {
   if (G && gated(a.gate)) return;
+  constexpr int NTH = kChainThreads;
   constexpr int TX = ChainTile<D>::X, TY = ChainTile<D>::Y, TZ = ChainTile<D>::Z;
   constexpr int TILE = TX * TY * TZ;
-  constexpr int TOP = (TILE + 255) / 256;
+  constexpr int TOP = (TILE + NTH - 1) / NTH;
   // the widest region below the top: level NT-1 (regions shrink further down, 3 stays 3)
   constexpr int CAP = chain_grow(TX) * chain_grow(TY) * (D == 3 ? chain_grow(TZ) : 1);
-  static_assert(CAP <= 256, "one region vertex per lane");
+  static_assert(CAP <= NTH, "one region vertex per lane");
   __shared__ T reg[NT][CAP];
   const int tid = threadIdx.x;
   int nv[NT + 1];
@@ -267,7 +275,7 @@ __global__ void __launch_bounds__(256) k_prolong_chain(ChainDev<T, NT> a) {
   const int nvt = nv[NT];
 #pragma unroll
   for (int j = 0; j < TOP; ++j) {
-    const int e = tid + 256 * j;
+    const int e = tid + NTH * j;
     topS[j] = T(0);
     topSelf[j] = T(0);
     if (e < TILE) {
@@ -319,7 +327,7 @@ __global__ void __launch_bounds__(256) k_prolong_chain(ChainDev<T, NT> a) {
   // the top target
 #pragma unroll
   for (int j = 0; j < TOP; ++j) {
-    const int e = tid + 256 * j;
+    const int e = tid + NTH * j;
     if (e < TILE) {
       const int x = lo[NT][0] + e % TX, y = lo[NT][1] + (e / TX) % TY, z = lo[NT][2] + e / (TX * TY);
       if (x < nvt && y < nvt && (D == 2 || z < nvt) && is_interior<D>(x, y, z, nvt)) {
@@ -466,9 +474,9 @@ static hipError_t launch_chain_nt(const ProlongChainArgs<T>& a, hipStream_t s) {
   const size_t nb = size_t(dv.tiles0) * dv.tiles1 * (D == 3 ? (n + ChainTile<D>::Z - 1) / ChainTile<D>::Z : 1);
   if (nb >= (size_t(1) << 31)) return hipErrorInvalidValue;
   if (a.gate.stop)
-    k_prolong_chain<T, D, NT, true><<<unsigned(nb), 256, 0, s>>>(dv);
+    k_prolong_chain<T, D, NT, true><<<unsigned(nb), kChainThreads, 0, s>>>(dv);
   else
-    k_prolong_chain<T, D, NT, false><<<unsigned(nb), 256, 0, s>>>(dv);
+    k_prolong_chain<T, D, NT, false><<<unsigned(nb), kChainThreads, 0, s>>>(dv);
   return hipGetLastError();
 }
 
