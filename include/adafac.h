@@ -255,8 +255,8 @@ int adafac_cycle(adafac_ctx* ctx, int ncycles);
  * defect of its iterate and, unless it met the tolerance, runs inner_k FP32
  * cycles on A e = r; the solution afterwards is the last outer iterate (the one
  * whose FP64 residual met the tolerance when the solve converged).
- * Uniform hierarchies, FP64 and the one-pass 3D FP32_REFINED form: the cycles
- * (outer steps with their inner cycles) are launched in batches without a host
+ * FP64 (uniform hierarchies and adaptive trees) and the one-pass 3D FP32_REFINED
+ * form: the cycles (outer steps with their inner cycles) are launched in batches without a host
  * wait (8 first, then as many as the observed contraction predicts, at most 64);
  * the stopping rule is applied on the device where each step's norms are formed,
  * and the launches after the step that met it do nothing, so the step count, the

@@ -122,7 +122,7 @@ std::string build_adapt_tree(AdaptHost& t, int d, int lmin, int L, const std::ve
 // Device launchers (kernels_adaptive.hip).  Every level l is given with its next coarser
 // (C) or finer (F) neighbour level where the step needs it.
 template <typename T>
-hipError_t launch_ad_hang(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>& C, hipStream_t s);
+hipError_t launch_ad_hang(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>& C, hipStream_t s, Gate g = Gate{});
 // Levels with a finer level F (F must not be null; the finest level runs launch_ad_leaf_up): the
 // level's own leaf residual (computed in place) plus the restrictions from F.
 // norms_only: only the composite residual: norm partials, hh, and bb replaced by the composite
@@ -130,18 +130,19 @@ hipError_t launch_ad_hang(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>& 
 // tiled: the 3D tiled kernel (adapt_up_tiled), else the five-wave gathers
 template <typename T>
 hipError_t launch_ad_up(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>* F, const RtSep<T>& rts, T omega,
-                        T omega_t, int damping, int norms_only, int tiled, double* partials, hipStream_t s);
+                        T omega_t, int damping, int norms_only, int tiled, double* partials, hipStream_t s,
+                        Gate g = Gate{});
 // The finest level: leaf residual and up in one pass
 template <typename T>
 hipError_t launch_ad_leaf_up(int d, const AdaptLevelT<T>& L, T omega, T omega_t, int norms_only, double* partials,
-                             hipStream_t s);
+                             hipStream_t s, Gate g = Gate{});
 // Down and update of level `level` (L; C the next coarser level, null on the coarsest): the
 // prolongated sum S, u += S at the composite dofs, and those values copied into the coinciding
 // dofs of every coarser level (V).  Launched coarsest level first.  keep_s: store S (every level
 // but the finest, whose S feeds no finer level).
 template <typename T>
 hipError_t launch_ad_down_update(int d, const AdaptLevelT<T>& L, const AdaptLevelT<T>* C, const AdaptCopyView<T>& V,
-                                 int level, int pi, int keep_s, hipStream_t s);
+                                 int level, int pi, int keep_s, hipStream_t s, Gate g = Gate{});
 // once per tree, after the classes, leaf flags and (Galerkin levels) diagonals are uploaded
 template <typename T>
 hipError_t launch_ad_setup(int d, const AdaptLevelT<T>& L, hipStream_t s);
@@ -162,7 +163,9 @@ hipError_t launch_ad_accumulate(int d, const AdaptLevel& A, const AdaptLevelT<fl
 #define ADAFAC_AD_UP_MAX_BLOCKS 4096
 #endif
 constexpr int kAdaptNormBlocks = ADAFAC_AD_UP_MAX_BLOCKS;   // most blocks (norm partial slots) of an up launch
-hipError_t launch_ad_norm_finalize(const double* partials, int n, double* out, hipStream_t s);
+// g, rule: a pipelined solve's gate and stopping rule (see run_cycle)
+hipError_t launch_ad_norm_finalize(const double* partials, int n, double* out, hipStream_t s, Gate g = Gate{},
+                                   StopRule rule = StopRule{});
 unsigned adapt_up_blocks(long box_vertices);     // blocks of an up launch without a finer level
 unsigned adapt_up_blocks_f(long box_vertices);   // with one (2D)
 unsigned adapt_up_blocks_tiled(int mx, int my, int mz);   // with one (3D, large levels)

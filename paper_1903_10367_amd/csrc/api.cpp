@@ -564,6 +564,7 @@ size_t layout_adaptive_tree(adafac_ctx* c, const AdaptHost& t, char* base) {
   double* norms = reinterpret_cast<double*>(take(sizeof(double) * 2 * kMaxHist));
   double* scratch = reinterpret_cast<double*>(take(sizeof(double) * 2));
   double* norm0 = reinterpret_cast<double*>(take(sizeof(double) * 2));
+  auto* stopseq = reinterpret_cast<unsigned long long*>(take(sizeof(unsigned long long)));
   if (base) {
     c->ad = std::move(ad);
     c->ad_part = std::move(part);
@@ -577,6 +578,7 @@ size_t layout_adaptive_tree(adafac_ctx* c, const AdaptHost& t, char* base) {
     c->norms = norms;
     c->scratch_norm = scratch;
     c->norm0 = norm0;
+    c->stopseq = stopseq;
   }
   return (off + 255) & ~size_t(255);
 }
@@ -585,8 +587,8 @@ size_t layout_adaptive(adafac_ctx* c, char* base) { return layout_adaptive_tree(
 
 // hanging vertices interpolated top-down from the current nodal values
 template <typename T>
-int adapt_hang_views(adafac_ctx* c, const std::vector<AdaptLevelT<T>>& ad) {
-  for (int l = c->lmin + 1; l <= c->L; ++l) HIPCHK(c, launch_ad_hang<T>(c->dim, ad[l], ad[l - 1], c->stream));
+int adapt_hang_views(adafac_ctx* c, const std::vector<AdaptLevelT<T>>& ad, Gate g = Gate{}) {
+  for (int l = c->lmin + 1; l <= c->L; ++l) HIPCHK(c, launch_ad_hang<T>(c->dim, ad[l], ad[l - 1], c->stream, g));
   return ADAFAC_OK;
 }
 
@@ -602,23 +604,27 @@ int adapt_accumulate(adafac_ctx* c) {
 
 // One cycle on the levels ad (FP64 form, or an FP32 inner cycle whose leaf loads are the outer
 // defect); norms of the composite residual of the input iterate into norm_out.
+// rule (may be nullptr): a pipelined solve's cycle, every launch gated (see run_cycle).
 template <typename T>
-int run_adapt_cycle(adafac_ctx* c, const std::vector<AdaptLevelT<T>>& ad, const RtSep<T>& rts, double* norm_out) {
+int run_adapt_cycle(adafac_ctx* c, const std::vector<AdaptLevelT<T>>& ad, const RtSep<T>& rts, double* norm_out,
+                    const StopRule* rule = nullptr) {
+  const Gate gate = rule ? Gate{rule->stop, rule->need} : Gate{};
+  const StopRule norm_rule = rule ? *rule : StopRule{};
   const int d = c->dim, L = c->L, lmin = c->lmin;
   const adafac_opts& o = c->opts;
   const T omega = T(o.omega), omega_t = T(o.omega_tilde);
   const int pi = o.damping == ADAFAC_DAMP_PI;
-  int rc = adapt_hang_views(c, ad);
+  int rc = adapt_hang_views(c, ad, gate);
   if (rc) return rc;
   if ((rc = record_start(c))) return rc;
   double* partials = std::is_same<T, double>::value ? c->partials : c->partials_inner;
-  HIPCHK(c, launch_ad_leaf_up<T>(d, ad[L], omega, omega_t, 0, partials + 2 * c->ad_part[L], c->stream));
+  HIPCHK(c, launch_ad_leaf_up<T>(d, ad[L], omega, omega_t, 0, partials + 2 * c->ad_part[L], c->stream, gate));
   if ((rc = record_stop(c))) return rc;
   for (int l = L - 1; l >= lmin; --l)
     HIPCHK(c, launch_ad_up<T>(d, ad[l], &ad[l + 1], rts, omega, omega_t, o.damping, 0,
                               std::is_same<T, double>::value ? c->ad_tiled[l] : 0, partials + 2 * c->ad_part[l],
-                              c->stream));
-  HIPCHK(c, launch_ad_norm_finalize(partials, int(c->npartials), norm_out, c->stream));
+                              c->stream, gate));
+  HIPCHK(c, launch_ad_norm_finalize(partials, int(c->npartials), norm_out, c->stream, gate, norm_rule));
   // coarsest level first: S_l needs S_{l-1}; each level's updated composite dofs are copied into
   // the coinciding coarser dofs
   AdaptCopyView<T> V{};
@@ -626,7 +632,8 @@ int run_adapt_cycle(adafac_ctx* c, const std::vector<AdaptLevelT<T>>& ad, const 
   for (int l = lmin; l <= L; ++l)
     V.lv[l] = {ad[l].ox, ad[l].oy, ad[l].oz, ad[l].mx, ad[l].my, ad[l].mz, ad[l].vcls, ad[l].u};
   for (int l = lmin; l <= L; ++l)
-    HIPCHK(c, launch_ad_down_update<T>(d, ad[l], l > lmin ? &ad[l - 1] : nullptr, V, l, pi, l < L, c->stream));
+    HIPCHK(c, launch_ad_down_update<T>(d, ad[l], l > lmin ? &ad[l - 1] : nullptr, V, l, pi, l < L, c->stream,
+                                       gate));
   return ADAFAC_OK;
 }
 
@@ -661,7 +668,9 @@ int run_outer(adafac_ctx* c, const StopRule* rule = nullptr) {
   const Gate gate = rule ? Gate{rule->stop, rule->need} : Gate{};
   const StopRule norm_rule = rule ? *rule : StopRule{};
   if (c->adaptive) {
-    int rc = mixed(c) ? run_adapt_outer_mixed(c, norm_out) : run_adapt_cycle<double>(c, c->ad, c->ad_rts, norm_out);
+    if (rule && mixed(c)) return fail(c, ADAFAC_EINVAL, "internal: this outer step is not pipelined");
+    int rc = mixed(c) ? run_adapt_outer_mixed(c, norm_out)
+                      : run_adapt_cycle<double>(c, c->ad, c->ad_rts, norm_out, rule);
     if (rc) return rc;
   } else if (!mixed(c)) {
     int rc = run_cycle<double>(c, c->h64, norm_out, nullptr, rule);
@@ -1346,13 +1355,13 @@ int predict_cycles(const adafac_ctx* c, const double* nrm, int k, double rel_tol
   return std::max(1, std::min(kSolveBatchMax, int(std::ceil(need))));
 }
 
-// Can adafac_solve pipeline this context?  Uniform FP64, and the one-pass 3D FP32_REFINED form
-// (an outer step and its inner cycles per batch entry); ADAFAC_SOLVE_HOST_CHECK=1 forces the check
-// on the host after every step (the tests compare both).
+// Can adafac_solve pipeline this context?  FP64 on uniform hierarchies and on adaptive trees, and
+// the one-pass 3D FP32_REFINED form (an outer step and its inner cycles per batch entry);
+// ADAFAC_SOLVE_HOST_CHECK=1 forces the check on the host after every step (the tests compare both).
 bool solve_pipelines(const adafac_ctx* c) {
-  if (c->adaptive) return false;
   if (const char* e = std::getenv("ADAFAC_SOLVE_HOST_CHECK"))
     if (std::atoi(e) != 0) return false;
+  if (c->adaptive) return !mixed(c);
   return !mixed(c) || (c->dim == 3 && c->opts.fused && fused_ok(c));
 }
 
@@ -1363,6 +1372,7 @@ int solve_pipelined(adafac_ctx* c, double rel_tol, int max_cycles, int* done_out
   const int k = c->opts.inner_k;
   static const unsigned long long never = ~0ull;
   int done = 0, rc = ADAFAC_OK, next = kSolveBatch;
+  if (!c->stopseq) return fail(c, ADAFAC_EINVAL, "internal: no stop counter in the workspace layout");
   HIPCHK(c, hipMemcpyAsync(c->stopseq, &never, sizeof(never), hipMemcpyHostToDevice, c->stream));
   while (done < max_cycles) {
     const int n0 = c->ncyc, batch = std::min({next, max_cycles - done, kMaxHist});
@@ -1382,13 +1392,13 @@ int solve_pipelined(adafac_ctx* c, double rel_tol, int max_cycles, int* done_out
     const bool stopped = stop != never;
     const int ran = stopped ? int(stop - static_cast<unsigned long long>(n0)) : batch;
     if (ran < 1 || ran > batch) return fail(c, ADAFAC_EINVAL, "internal: stop counter out of the batch");
-    // take back the host bookkeeping of what the device skipped
-    if (!mp) {
+    // take back the host bookkeeping of what the device skipped (an adaptive cycle keeps none)
+    if (!c->adaptive && !mp) {
       if ((batch - ran) & 1) {
         D.cur = 1 - D.cur;
         for (int l = D.swap_lo; l < D.swap_hi; ++l) std::swap(D.v[l].S, D.Salt[l]);
       }
-    } else if (stopped) {
+    } else if (!c->adaptive && stopped) {
       if ((batch - ran) & 1) D.cur = 1 - D.cur;                 // outer steps: one buffer flip each
       if (((batch - (ran - 1)) * k) & 1) {                      // inner cycles: one flip and swap each
         H.cur = 1 - H.cur;

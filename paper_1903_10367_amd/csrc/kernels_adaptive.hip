@@ -184,8 +184,9 @@ __device__ __forceinline__ T kref(int i, int j) {
   return hd == 0 ? T(1.0 / 3.0) : (hd == 1 ? T(0) : T(-1.0 / 12.0));
 }
 
-template <int D, typename T>
-__global__ void __launch_bounds__(NTA) k_ad_hang(AdaptLevelT<T> A, AdaptLevelT<T> C) {
+template <int D, typename T, bool G>
+__global__ void __launch_bounds__(NTA) k_ad_hang(AdaptLevelT<T> A, AdaptLevelT<T> C, Gate g) {
+  if (G && gated(g)) return;
   AD_RUNS(i, A.hrun, A.nhrun) {
     if (!(A.vcls[i] & kHang)) continue;
     int x, y, z;
@@ -338,8 +339,9 @@ __device__ __forceinline__ void up_finish(const AdaptLevelT<T>& A, unsigned i, u
 // MODE: 0 composite residual only (norms_only), 1 plain additive, 2 adAFAC-Jac.
 // The finest level (no finer level to restrict from): its leaf residual and the per-vertex tail
 // in one pass, one thread per vertex.
-template <int D, typename T, int MODE>
-__global__ void __launch_bounds__(NTA) k_ad_leaf_up(AdaptLevelT<T> A, T omega, T omega_t, double* partials) {
+template <int D, typename T, int MODE, bool G>
+__global__ void __launch_bounds__(NTA) k_ad_leaf_up(AdaptLevelT<T> A, T omega, T omega_t, double* partials, Gate g) {
+  if (G && gated(g)) return;
   double ssum = 0.0, smax = 0.0;
   AD_RUNS(i, A.run, A.nrun) {
     const uint8_t cls = A.vcls[i];
@@ -355,9 +357,10 @@ __global__ void __launch_bounds__(NTA) k_ad_leaf_up(AdaptLevelT<T> A, T omega, T
 // the lanes of one thread per vertex, for the small levels whose gathers are latency bound.
 constexpr int NTU = 320;
 
-template <int D, typename T, int MODE>
+template <int D, typename T, int MODE, bool G>
 __global__ void __launch_bounds__(NTU) k_ad_up_f(AdaptLevelT<T> A, AdaptLevelT<T> F, RtSep<T> rts, T omega,
-                                                 T omega_t, double* partials) {
+                                                 T omega_t, double* partials, Gate g) {
+  if (G && gated(g)) return;
   __shared__ T sh[3][4][64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int o2 = wave - 2;                 // oz in 3D, oy in 2D
@@ -460,9 +463,10 @@ __global__ void __launch_bounds__(NTU) k_ad_up_f(AdaptLevelT<T> A, AdaptLevelT<T
 constexpr int TCX = 16, TCY = 8, TZC = ADAFAC_AD_TILE_ZC, NTT = 256;
 constexpr int FXW = 3 * TCX + 2, FYW = 3 * TCY + 2, NFT = FXW * FYW;
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool G>
 __global__ void __launch_bounds__(NTT) k_ad_up_tiled(AdaptLevelT<T> A, AdaptLevelT<T> F, RtSep<T> rts, T omega,
-                                                     T omega_t, double* partials) {
+                                                     T omega_t, double* partials, Gate g) {
+  if (G && gated(g)) return;
   __shared__ T Lh[NFT];
   __shared__ T Lb[MODE ? NFT : 1];
   __shared__ T Ld[MODE == 2 ? NFT : 1];
@@ -621,9 +625,10 @@ __device__ __forceinline__ void copy_down(const AdaptCopyView<T>& V, int l, int 
 // S_l = (c - c~)_l + P S_{l-1}; adAFAC-PI: S_l = c_l + P (S_{l-1} - I c_l), which is
 // c_l - P I c_l + P S_{l-1} (c~_l = P I c_l, Sec. 3.2).  Then u += S_l at the composite dofs,
 // copied into the coinciding coarser dofs.
-template <int D, typename T, bool PI>
+template <int D, typename T, bool PI, bool G>
 __global__ void __launch_bounds__(NTA) k_ad_down_update(AdaptLevelT<T> A, AdaptLevelT<T> C, int has_c,
-                                                        AdaptCopyView<T> V, int level, int keep_s) {
+                                                        AdaptCopyView<T> V, int level, int keep_s, Gate g) {
+  if (G && gated(g)) return;
   AD_RUNS(i, A.run, A.nrun) {
     const uint8_t cls = A.vcls[i];
     if (!(cls & (kDof | kHang))) continue;
@@ -748,8 +753,10 @@ unsigned grid_runs(unsigned nrun) { return blocks_of(long(nrun), NTA / 64, 8192)
 }  // namespace
 
 // Norms from the packed partials of all levels: one workgroup of 1024 lanes, fixed order.
+template <bool G>
 __global__ void __launch_bounds__(1024) k_ad_norm_finalize(const double* __restrict__ partials, int n,
-                                                            double* __restrict__ out) {
+                                                            double* __restrict__ out, Gate g, StopRule rule) {
+  if (G && gated(g)) return;
   __shared__ double ss[16], sm[16];
   double sv = 0.0, mv = 0.0;
   for (int i = threadIdx.x; i < n; i += 1024) {
@@ -774,11 +781,15 @@ __global__ void __launch_bounds__(1024) k_ad_norm_finalize(const double* __restr
     }
     out[0] = sqrt(a);
     out[1] = b;
+    if (G) apply_stop_rule(rule, out);
   }
 }
 
-hipError_t launch_ad_norm_finalize(const double* partials, int n, double* out, hipStream_t s) {
-  k_ad_norm_finalize<<<1, 1024, 0, s>>>(partials, n, out);
+hipError_t launch_ad_norm_finalize(const double* partials, int n, double* out, hipStream_t s, Gate g, StopRule rule) {
+  if (g.stop || rule.stop)
+    k_ad_norm_finalize<true><<<1, 1024, 0, s>>>(partials, n, out, g, rule);
+  else
+    k_ad_norm_finalize<false><<<1, 1024, 0, s>>>(partials, n, out, g, rule);
   return hipGetLastError();
 }
 
@@ -806,16 +817,23 @@ unsigned adapt_up_slots(int d, int mx, int my, int mz, bool has_finer, bool tile
 unsigned adapt_up_blocks_f(long nb) { return blocks_of(nb, 64, kAdaptNormBlocks); }
 
 template <typename T>
-hipError_t launch_ad_hang(int d, const AdaptLevelT<T>& A, const AdaptLevelT<T>& C, hipStream_t s) {
-  if (d == 2) k_ad_hang<2, T><<<grid_runs(A.nhrun), NTA, 0, s>>>(A, C);
-  else k_ad_hang<3, T><<<grid_runs(A.nhrun), NTA, 0, s>>>(A, C);
+hipError_t launch_ad_hang(int d, const AdaptLevelT<T>& A, const AdaptLevelT<T>& C, hipStream_t s, Gate g) {
+#define AD_H(DD, GG) k_ad_hang<DD, T, GG><<<grid_runs(A.nhrun), NTA, 0, s>>>(A, C, g)
+  if (d == 2) {
+    if (g.stop) AD_H(2, true); else AD_H(2, false);
+  } else {
+    if (g.stop) AD_H(3, true); else AD_H(3, false);
+  }
+#undef AD_H
   return hipGetLastError();
 }
 
 
 template <typename T>
 hipError_t launch_ad_up(int d, const AdaptLevelT<T>& A, const AdaptLevelT<T>* F, const RtSep<T>& rts, T omega,
-                        T omega_t, int damping, int norms_only, int tiled, double* partials, hipStream_t s) {
+                        T omega_t, int damping, int norms_only, int tiled, double* partials, hipStream_t s,
+                        Gate g) {
+  const bool gg = g.stop != nullptr;
   const AdaptLevelT<T> Fv = F ? *F : AdaptLevelT<T>{};
   const int mode = norms_only ? 0 : (damping == ADAFAC_DAMP_JAC ? 2 : 1);
   const long nbv = long(A.mx) * A.my * (d == 3 ? A.mz : 1);
@@ -823,9 +841,11 @@ hipError_t launch_ad_up(int d, const AdaptLevelT<T>& A, const AdaptLevelT<T>* F,
     if constexpr (std::is_same<T, double>::value) {
       if (d != 3) return hipErrorInvalidValue;
       const unsigned gt = adapt_up_blocks_tiled(A.mx, A.my, A.mz);
-      if (mode == 0) k_ad_up_tiled<T, 0><<<gt, NTT, 0, s>>>(A, Fv, rts, omega, omega_t, partials);
-      else if (mode == 1) k_ad_up_tiled<T, 1><<<gt, NTT, 0, s>>>(A, Fv, rts, omega, omega_t, partials);
-      else k_ad_up_tiled<T, 2><<<gt, NTT, 0, s>>>(A, Fv, rts, omega, omega_t, partials);
+#define AD_UT(M, GG) k_ad_up_tiled<T, M, GG><<<gt, NTT, 0, s>>>(A, Fv, rts, omega, omega_t, partials, g)
+      if (mode == 0) { if (gg) AD_UT(0, true); else AD_UT(0, false); }
+      else if (mode == 1) { if (gg) AD_UT(1, true); else AD_UT(1, false); }
+      else { if (gg) AD_UT(2, true); else AD_UT(2, false); }
+#undef AD_UT
       return hipGetLastError();
     } else {
       return hipErrorInvalidValue;   // FP64 levels only
@@ -833,7 +853,11 @@ hipError_t launch_ad_up(int d, const AdaptLevelT<T>& A, const AdaptLevelT<T>* F,
   }
   if (F) {
     const unsigned gf = adapt_up_blocks_f(nbv);
-#define AD_UPF(DD, M) k_ad_up_f<DD, T, M><<<gf, NTU, 0, s>>>(A, Fv, rts, omega, omega_t, partials)
+#define AD_UPF(DD, M)                                                                          \
+  do {                                                                                         \
+    if (gg) k_ad_up_f<DD, T, M, true><<<gf, NTU, 0, s>>>(A, Fv, rts, omega, omega_t, partials, g);  \
+    else k_ad_up_f<DD, T, M, false><<<gf, NTU, 0, s>>>(A, Fv, rts, omega, omega_t, partials, g);    \
+  } while (0)
     if (d == 2) {
       if (mode == 0) AD_UPF(2, 0);
       else if (mode == 1) AD_UPF(2, 1);
@@ -851,31 +875,43 @@ hipError_t launch_ad_up(int d, const AdaptLevelT<T>& A, const AdaptLevelT<T>* F,
 
 template <typename T>
 hipError_t launch_ad_leaf_up(int d, const AdaptLevelT<T>& A, T omega, T omega_t, int norms_only, double* partials,
-                             hipStream_t s) {
-  const unsigned g = adapt_up_blocks(long(A.mx) * A.my * (d == 3 ? A.mz : 1));
+                             hipStream_t s, Gate g) {
+  const unsigned nbk = adapt_up_blocks(long(A.mx) * A.my * (d == 3 ? A.mz : 1));
+#define AD_LF(DD, M)                                                                    \
+  do {                                                                                  \
+    if (g.stop) k_ad_leaf_up<DD, T, M, true><<<nbk, NTA, 0, s>>>(A, omega, omega_t, partials, g);  \
+    else k_ad_leaf_up<DD, T, M, false><<<nbk, NTA, 0, s>>>(A, omega, omega_t, partials, g);        \
+  } while (0)
   if (d == 2) {
-    if (norms_only) k_ad_leaf_up<2, T, 0><<<g, NTA, 0, s>>>(A, omega, omega_t, partials);
-    else k_ad_leaf_up<2, T, 1><<<g, NTA, 0, s>>>(A, omega, omega_t, partials);
+    if (norms_only) AD_LF(2, 0);
+    else AD_LF(2, 1);
   } else {
-    if (norms_only) k_ad_leaf_up<3, T, 0><<<g, NTA, 0, s>>>(A, omega, omega_t, partials);
-    else k_ad_leaf_up<3, T, 1><<<g, NTA, 0, s>>>(A, omega, omega_t, partials);
+    if (norms_only) AD_LF(3, 0);
+    else AD_LF(3, 1);
   }
+#undef AD_LF
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_ad_down_update(int d, const AdaptLevelT<T>& A, const AdaptLevelT<T>* C, const AdaptCopyView<T>& V,
-                                 int level, int pi, int keep_s, hipStream_t s) {
+                                 int level, int pi, int keep_s, hipStream_t s, Gate g) {
   const AdaptLevelT<T> Cv = C ? *C : AdaptLevelT<T>{};
   const int hc = C ? 1 : 0;
   const int keep = keep_s ? 1 : 0;
+#define AD_DU(DD, P)                                                                                          \
+  do {                                                                                                        \
+    if (g.stop) k_ad_down_update<DD, T, P, true><<<grid_runs(A.nrun), NTA, 0, s>>>(A, Cv, hc, V, level, keep, g); \
+    else k_ad_down_update<DD, T, P, false><<<grid_runs(A.nrun), NTA, 0, s>>>(A, Cv, hc, V, level, keep, g);       \
+  } while (0)
   if (d == 2) {
-    if (pi) k_ad_down_update<2, T, true><<<grid_runs(A.nrun), NTA, 0, s>>>(A, Cv, hc, V, level, keep);
-    else k_ad_down_update<2, T, false><<<grid_runs(A.nrun), NTA, 0, s>>>(A, Cv, hc, V, level, keep);
+    if (pi) AD_DU(2, true);
+    else AD_DU(2, false);
   } else {
-    if (pi) k_ad_down_update<3, T, true><<<grid_runs(A.nrun), NTA, 0, s>>>(A, Cv, hc, V, level, keep);
-    else k_ad_down_update<3, T, false><<<grid_runs(A.nrun), NTA, 0, s>>>(A, Cv, hc, V, level, keep);
+    if (pi) AD_DU(3, true);
+    else AD_DU(3, false);
   }
+#undef AD_DU
   return hipGetLastError();
 }
 
@@ -914,13 +950,13 @@ hipError_t launch_ad_accumulate(int d, const AdaptLevel& A, const AdaptLevelT<fl
 }
 
 #define ADAFAC_AD_INST(T)                                                                                         \
-  template hipError_t launch_ad_hang<T>(int, const AdaptLevelT<T>&, const AdaptLevelT<T>&, hipStream_t);          \
+  template hipError_t launch_ad_hang<T>(int, const AdaptLevelT<T>&, const AdaptLevelT<T>&, hipStream_t, Gate);    \
   template hipError_t launch_ad_up<T>(int, const AdaptLevelT<T>&, const AdaptLevelT<T>*, const RtSep<T>&, T, T,  \
-                                      int, int, int, double*, hipStream_t);                                       \
+                                      int, int, int, double*, hipStream_t, Gate);                                 \
   template hipError_t launch_ad_setup<T>(int, const AdaptLevelT<T>&, hipStream_t);                              \
-  template hipError_t launch_ad_leaf_up<T>(int, const AdaptLevelT<T>&, T, T, int, double*, hipStream_t);          \
+  template hipError_t launch_ad_leaf_up<T>(int, const AdaptLevelT<T>&, T, T, int, double*, hipStream_t, Gate);    \
   template hipError_t launch_ad_down_update<T>(int, const AdaptLevelT<T>&, const AdaptLevelT<T>*,                 \
-                                               const AdaptCopyView<T>&, int, int, int, hipStream_t);
+                                               const AdaptCopyView<T>&, int, int, int, hipStream_t, Gate);
 ADAFAC_AD_INST(double)
 ADAFAC_AD_INST(float)
 

@@ -243,3 +243,26 @@ def test_two_level_tree(d):
     say("case adaptive two-level tree", d)
     centre = (0.4, 0.6) if d == 2 else (0.4, 0.6, 0.5)
     run_both(d, 2, 1, inp.rhs(d, 2, seed=90), None, centre=centre, radius=0.2, cycles=5)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_pipelined_solve_on_a_tree_matches_the_host_checked_one(d, monkeypatch):
+    """FP64 solves on adaptive trees in batches, every launch gated on the device's stop counter:
+    cycle counts, norms and the solution bitwise those of the check on the host after every cycle
+    (ADAFAC_SOLVE_HOST_CHECK=1), for two consecutive solves."""
+    from paper_1903_10367_amd import Solver
+    L = 4 if d == 2 else 3
+    centre = (0.4, 0.55) if d == 2 else (0.42, 0.55, 0.5)
+    f = inp.rhs(d, L, seed=95)
+    say("case adaptive pipelined solve", d)
+    out = []
+    for host_check in ("0", "1"):
+        monkeypatch.setenv("ADAFAC_SOLVE_HOST_CHECK", host_check)
+        s = Solver(d, 1, L, f, ball=(centre, 0.25, 1))
+        n = [s.solve(1e-5, 300), s.solve(1e-10, 300)]
+        out.append((n, s.residuals(), s.solution()))
+        s.close()
+    say(f"cycles {out[0][0]} / {out[1][0]}")
+    assert out[0][0] == out[1][0]
+    assert out[0][1] == out[1][1]
+    assert np.array_equal(out[0][2], out[1][2])
